@@ -1,0 +1,268 @@
+"""Pins for the CPU oracle (no GPU).
+
+The oracle is checked against things other than itself:
+  * the paper's worked example for dictionary sizing (Sec. 4.1);
+  * the published SplitMix64 test vector for the checksum mixer;
+  * a dense-bitset brute-force model (tests/bruteforce.py) over random
+    operation sequences on tiny graphs, after every operation;
+  * closed forms and invariants of set semantics on larger graphs.
+"""
+import numpy as np
+import pytest
+
+from conftest import golden_rows
+from oracle import pyoracle as O
+from paper_2306_08252_amd import inputs as I
+from bruteforce import BruteGraph, py_mix64, ceil_div
+
+GAMMA = 0x9E3779B97F4A7C15
+
+
+# ---------------------------------------------------------------- examples
+def test_dictionary_pow2_worked_example():
+    for n, size in golden_rows("dictionary_pow2.txt"):
+        assert O.next_pow2(n) == size
+        g = O.OracleGraph(n, [], [], block_slots=8)
+        assert g.capacity == size
+
+
+@pytest.mark.parametrize("x,want", [(0, 1), (1, 1), (2, 2), (3, 4), (512, 512),
+                                    (513, 1024), ((1 << 31) - 1, 1 << 31)])
+def test_next_pow2_closed_form(x, want):
+    assert O.next_pow2(x) == want
+
+
+def test_mix64_published_vector():
+    rows = golden_rows("splitmix64_seed1234567.txt")
+    for i, want in rows:
+        state = (1234567 + (i + 1) * GAMMA) % (1 << 64)
+        assert O.mix64(state) == want
+        assert py_mix64(state) == want
+    got = I.splitmix64(1234567, len(rows))
+    assert [int(x) for x in got] == [w for _, w in rows]
+
+
+@pytest.mark.parametrize("edges,nonzero,want", [
+    (0, 0, 8), (10, 10, 8), (80, 10, 8), (81, 10, 16), (160, 10, 16),
+    (161, 10, 32), (100, 1, 64), (10**6, 3, 64)])
+def test_paper_block_rule(edges, nonzero, want):
+    # Sec. 4.3: average degree of non-zero-degree vertices, read as
+    # ceil(edges / nonzero) rounded up to a power of two within [8, 64].
+    assert O.paper_block_slots(edges, nonzero) == want
+
+
+def test_paper_block_rule_from_graph():
+    # 3 sources with 20, 20 and 5 distinct out-edges: avg ceil(45/3) = 15 -> 16.
+    src = [0] * 20 + [1] * 20 + [2] * 5 + [0] * 3  # three repeats of vertex 0
+    dst = list(range(1, 21)) + list(range(2, 22)) + list(range(3, 8)) + [1, 2, 3]
+    g = O.OracleGraph(64, src, dst, block_slots=0)
+    assert g.num_edges == 45
+    assert g.block_slots == 16
+
+
+# ---------------------------------------------------------------- errors
+def test_init_errors():
+    with pytest.raises(O.OracleError) as e:
+        O.OracleGraph(10, [1, 10], [2, 3])
+    assert e.value.code == O.ERANGE
+    with pytest.raises(O.OracleError) as e:
+        O.OracleGraph(10, [1], [2], block_slots=12)
+    assert e.value.code == O.EINVAL
+    with pytest.raises(O.OracleError) as e:
+        O.OracleGraph(10, [0xFFFFFFFF], [2])
+    assert e.value.code == O.ERANGE
+
+
+def test_get_adjacency_ranges():
+    g = O.OracleGraph(8, [1, 1, 1], [5, 2, 7], block_slots=8)
+    assert list(g.get_adjacency(1)) == [2, 5, 7]
+    assert list(g.get_adjacency(3)) == []
+    with pytest.raises(O.OracleError):
+        g.get_adjacency(8)
+
+
+# ---------------------------------------------------------------- brute force
+def _random_ops(rng, n, steps):
+    """Random mixed operations with duplicates, bad ids and vertex churn."""
+    ops = []
+    for _ in range(steps):
+        kind = rng.choice(["ins", "del", "vins", "vdel", "q"], p=[.35, .3, .1, .1, .15])
+        k = int(rng.integers(0, 3 * n))
+        hi = 2 * n  # ids beyond the dictionary are exercised too
+        if kind in ("ins", "del", "q"):
+            s = rng.integers(0, hi, k)
+            d = rng.integers(0, hi, k)
+            if k and kind != "q":  # add explicit in-batch repeats
+                rep = rng.integers(0, k, k // 4)
+                s = np.concatenate([s, s[rep]])
+                d = np.concatenate([d, d[rep]])
+            if k and rng.random() < 0.2:
+                s[0] = 0xFFFFFFFF
+            ops.append((kind, s.astype(np.uint32), d.astype(np.uint32)))
+        else:
+            m = int(rng.integers(0, max(2, n // 4)))
+            ids = rng.integers(0, hi + n, m).astype(np.uint32)
+            if m and rng.random() < 0.2:
+                ids[0] = 0xFFFFFFFF
+            ops.append((kind, ids, None))
+    return ops
+
+
+def _compare(o, b):
+    offs, dst, ck = o.dump()
+    boffs, bdst, bck = b.dump()
+    assert o.capacity == b.cap
+    np.testing.assert_array_equal(offs, boffs)
+    np.testing.assert_array_equal(dst, bdst)
+    assert ck == bck
+    assert o.blocks_in_use == b.blocks_in_use()
+    assert o.num_edges == int(b.A.sum())
+    for v in range(o.capacity):
+        assert o.is_active(v) == bool(b.active[v])
+
+
+@pytest.mark.parametrize("n,B,seed", [(16, 1, 1), (16, 4, 2), (64, 8, 3),
+                                      (100, 16, 4), (256, 32, 5)])
+def test_oracle_matches_bitset_bruteforce(n, B, seed):
+    rng = np.random.default_rng(seed)
+    m = 4 * n
+    s = rng.integers(0, n, m).astype(np.uint32)
+    d = rng.integers(0, n, m).astype(np.uint32)
+    o = O.OracleGraph(n, s, d, block_slots=B)
+    b = BruteGraph(n, s, d, block_slots=B)
+    _compare(o, b)
+    for kind, x, y in _random_ops(rng, n, 40):
+        if kind == "ins":
+            assert o.insert_edges(x, y) == b.insert_edges(x, y)
+        elif kind == "del":
+            assert o.delete_edges(x, y) == b.delete_edges(x, y)
+        elif kind == "vins":
+            assert o.insert_vertices(x) == b.insert_vertices(x)
+        elif kind == "vdel":
+            assert o.delete_vertices(x) == b.delete_vertices(x)
+        else:
+            np.testing.assert_array_equal(o.edge_exists(x, y), b.edge_exists(x, y))
+        _compare(o, b)
+    for v in range(0, o.capacity, max(1, o.capacity // 16)):
+        np.testing.assert_array_equal(o.get_adjacency(v), b.get_adjacency(v))
+
+
+def test_oracle_pool_exhaustion_matches_bruteforce():
+    rng = np.random.default_rng(11)
+    n, B = 32, 4
+    s = rng.integers(0, n, 40).astype(np.uint32)
+    d = rng.integers(0, n, 40).astype(np.uint32)
+    pool = 4 * B * 30  # 30 blocks
+    o = O.OracleGraph(n, s, d, block_slots=B, pool_bytes=pool)
+    b = BruteGraph(n, s, d, block_slots=B, pool_bytes=pool)
+    assert o.pool_blocks == 30
+    hits = 0
+    for _ in range(30):
+        x = rng.integers(0, n, 24).astype(np.uint32)
+        y = rng.integers(0, n, 24).astype(np.uint32)
+        r1, r2 = o.insert_edges(x, y), b.insert_edges(x, y)
+        assert r1 == r2
+        hits += r1[0] == O.ENOMEM
+        _compare(o, b)
+        if rng.random() < 0.5:
+            assert o.delete_edges(y, x) == b.delete_edges(y, x)
+    assert hits > 0
+    assert o.blocks_in_use <= 30
+
+
+def test_init_pool_exhaustion():
+    with pytest.raises(O.OracleError) as e:
+        O.OracleGraph(8, [0, 0, 0], [1, 2, 3], block_slots=2, pool_bytes=4 * 2 * 1)
+    assert e.value.code == O.ENOMEM
+
+
+# ---------------------------------------------------------------- invariants
+@pytest.fixture(scope="module")
+def rmat_small():
+    return I.rmat_graph(I.stream_seed("oracle-invariants"), 12, 1 << 15)
+
+
+def _checked_edges(g):
+    offs, dst, _ = g.dump()
+    for v in range(g.capacity):
+        seg = dst[offs[v]:offs[v + 1]]
+        assert np.all(np.diff(seg.astype(np.int64)) > 0)  # sorted, no duplicates
+    return offs, dst
+
+
+def test_invariants_counts_and_idempotence(rmat_small):
+    s, d = rmat_small
+    g = O.OracleGraph(1 << 12, s, d, block_slots=8)
+    assert g.num_edges == len(s)
+    _checked_edges(g)
+    bs, bd = I.rmat_pairs(I.stream_seed("inv-batch"), 5000, 12)
+    e0 = g.num_edges
+    rc, (applied, rej, dup) = g.insert_edges(bs, bd)
+    assert rc == 0 and rej == 0
+    assert g.num_edges == e0 + applied
+    keys = np.unique(I.pair_keys(bs, bd))
+    assert dup == len(bs) - len(keys)
+    present = np.isin(keys, I.pair_keys(s, d))
+    assert applied == int((~present).sum())
+    assert g.insert_edges(bs, bd)[1][0] == 0  # idempotent
+    rc, (removed, _, _) = g.delete_edges(bs, bd)
+    assert g.num_edges == e0 + applied - removed
+    assert removed == len(keys)
+    _checked_edges(g)
+    offs, _ = _checked_edges(g)
+    deg = np.diff(offs.astype(np.int64))
+    assert g.blocks_in_use == int(sum(ceil_div(int(x), 8) for x in deg))
+
+
+def test_invariants_insert_delete_restore_and_commute(rmat_small):
+    s, d = rmat_small
+    keys = I.pair_keys(s, d)
+    g = O.OracleGraph(1 << 12, s, d, block_slots=16)
+    ck0 = g.checksum()
+    # a batch disjoint from the graph: insert then delete restores the state
+    bs, bd = I.uniform_pairs(I.stream_seed("inv-disjoint"), 3000, 1 << 12)
+    fresh = ~np.isin(I.pair_keys(bs, bd), keys)
+    bs, bd = bs[fresh], bd[fresh]
+    g.insert_edges(bs, bd)
+    assert g.checksum() != ck0
+    g.delete_edges(bs, bd)
+    assert g.checksum() == ck0
+    # two insert batches commute
+    a = I.rmat_pairs(I.stream_seed("inv-a"), 2000, 12)
+    b = I.rmat_pairs(I.stream_seed("inv-b"), 2000, 12)
+    g1 = O.OracleGraph(1 << 12, s, d, block_slots=16)
+    g2 = O.OracleGraph(1 << 12, s, d, block_slots=16)
+    g1.insert_edges(*a)
+    g1.insert_edges(*b)
+    g2.insert_edges(*b)
+    g2.insert_edges(*a)
+    assert g1.checksum() == g2.checksum()
+    np.testing.assert_array_equal(g1.dump()[1], g2.dump()[1])
+
+
+def test_invariants_symmetry_lattice():
+    s, d = I.lattice_graph(I.stream_seed("inv-lattice"), 32)
+    g = O.OracleGraph(32 * 32, s, d, block_slots=4)
+    offs, dst = _checked_edges(g)
+
+    def symmetric():
+        o, t, _ = g.dump()
+        u = np.repeat(np.arange(g.capacity, dtype=np.uint64), np.diff(o.astype(np.int64)))
+        fwd = np.sort(I.pair_keys(u, t))
+        rev = np.sort(I.pair_keys(t, u))
+        return np.array_equal(fwd, rev)
+
+    assert symmetric()
+    # apply symmetric edge updates (each pair in both directions)
+    a, b = I.uniform_pairs(I.stream_seed("inv-sym"), 200, 32 * 32)
+    g.insert_edges(np.concatenate([a, b]), np.concatenate([b, a]))
+    assert symmetric()
+    g.delete_edges(np.concatenate([a[:100], b[:100]]), np.concatenate([b[:100], a[:100]]))
+    assert symmetric()
+    # a vertex delete removes in- and out-edges, keeping symmetry
+    g.delete_vertices(np.array([5, 77, 500], np.uint32))
+    assert symmetric()
+    for x in (5, 77, 500):
+        assert g.degree(x) == 0 and not g.is_active(x)
+    o, t, _ = g.dump()
+    assert not np.isin(t, [5, 77, 500]).any()
