@@ -1,0 +1,209 @@
+/*
+ * graphvine.h -- C ABI of the MI355X (gfx950) GraphVine dynamic-graph library.
+ *
+ * The library keeps a directed graph resident in GPU memory and updates it in
+ * batches.  It follows the problem statement of GraphVine (Krishnan S, Tavva,
+ * Nasre, arXiv 2306.08252): an initial graph, then batched vertex and edge
+ * inserts and deletes (Sec. 4.3), edge queries (Sec. 4.6, Alg. 3) and the
+ * memory footprint (Sec. 5.4).
+ *
+ * Structure.  Each vertex's adjacency lives in fixed-size edge blocks of B
+ * uint32 destination slots (Sec. 4.1).  Blocks come from one pre-allocated
+ * device pool (the "edge queue" of Sec. 4.2) managed as a free-list stack plus
+ * a bump pointer.  A per-vertex block directory replaces the paper's complete
+ * binary tree of blocks and gives block j of a vertex in O(1).  The vertex
+ * dictionary capacity is a power of two (Sec. 4.1, Sec. 4.4).
+ *
+ * Semantics.  Adjacencies are sets: inserting an existing edge and deleting an
+ * absent edge are no-ops, and duplicates inside a batch collapse.  Deletes
+ * compact the adjacency and return emptied blocks to the pool, so a vertex of
+ * degree d always holds exactly ceil(d / B) blocks.  Edges are never created
+ * for inactive vertices: a pair whose source or destination is inactive or
+ * outside the dictionary is rejected and counted, not an error.
+ *
+ * Memory and streams.  Every array argument named d_* is a DEVICE pointer on
+ * the graph's current device, owned by the caller and read (or written) in
+ * stream order on the graph's stream; the caller keeps it alive until that
+ * stream has passed the call.  The library never frees caller memory.  The
+ * graph owns all of its internal memory; gv_graph_destroy releases it.
+ * A gv_graph must be used by one host thread at a time.
+ *
+ * Errors.  Every int-returning function returns a GV_* code; no C++ exception
+ * crosses this boundary.  Batch calls with a NULL stats pointer are
+ * asynchronous: their errors are kept and reported by the next gv_sync or
+ * synchronising call.  With a non-NULL stats pointer the call waits for its
+ * own completion and reports its own result.
+ *
+ * Ids are uint32.  The largest dictionary capacity is 2^31 vertices, so the
+ * largest vertex id is 2^31 - 1; 0xFFFFFFFF is never a valid id.
+ */
+#ifndef GRAPHVINE_H
+#define GRAPHVINE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    GV_OK = 0,
+    GV_EINVAL = 1,  /* NULL pointer where data is required, or bad config     */
+    GV_ERANGE = 2,  /* id outside the dictionary, or an output buffer too small */
+    GV_ENOMEM = 3,  /* pool, directory or device memory exhausted; the batch is
+                       not applied and the graph is unchanged                  */
+    GV_EDEVICE = 4  /* a HIP runtime failure; the graph must be destroyed      */
+};
+
+#define GV_MAX_CAPACITY (1ull << 31)
+
+typedef struct gv_graph gv_graph;
+
+typedef struct {
+    /* Slots per edge block, a power of two in [1, 1024]; 0 selects the rule of
+     * Sec. 4.3: the average degree of the non-zero-degree vertices of the
+     * initial graph, rounded up to a power of two within [8, 64]. */
+    uint32_t block_slots;
+    uint32_t flags;            /* reserved, must be 0                            */
+    /* Edge-block pool size in bytes (holds floor(pool_bytes / (4 B)) blocks);
+     * 0 = twice the initial graph's blocks plus 2^20 blocks. */
+    uint64_t pool_bytes;
+    /* Minimum dictionary capacity; the capacity is the next power of two of
+     * max(num_vertices, vertex_capacity, 1). */
+    uint64_t vertex_capacity;
+    /* Directory arena size in uint32 entries; 0 = default (4 entries per pool
+     * block plus 2^20). */
+    uint64_t directory_entries;
+} gv_config;
+
+typedef struct {
+    uint64_t applied;          /* edges (vertices) actually inserted / removed   */
+    uint64_t rejected;         /* pairs (ids) with an inactive or invalid end    */
+    uint64_t batch_duplicates; /* valid entries minus distinct valid entries     */
+} gv_batch_stats;
+
+typedef struct {
+    uint64_t block_bytes;          /* 4 * B                                     */
+    uint64_t pool_capacity_blocks; /* blocks the pool can hold                  */
+    uint64_t blocks_in_use;        /* = sum over vertices of ceil(deg / B)      */
+    uint64_t free_list_blocks;     /* blocks on the free-list stack             */
+    uint64_t bump_blocks;          /* blocks ever carved by the bump pointer    */
+    uint64_t vertex_capacity;      /* dictionary capacity (power of two)        */
+    uint64_t vertex_table_bytes;   /* dictionary + activity bitmap bytes        */
+    uint64_t directory_entries_in_use; /* directory entries held by vertices    */
+    uint64_t directory_bytes;      /* directory arena bytes reserved            */
+    uint64_t live_bytes;           /* blocks_in_use * block_bytes + vertex table
+                                      + 4 * directory_entries_in_use            */
+    uint64_t num_edges;            /* edges stored                              */
+    uint64_t reserved_bytes;       /* all device memory held by the graph       */
+} gv_mem;
+
+typedef struct {
+    uint64_t vertex_capacity; /* dictionary capacity (power of two)            */
+    uint32_t block_slots;     /* B                                             */
+    uint32_t device;          /* HIP device ordinal                            */
+} gv_info;
+
+/* Cumulative work counters (since init) used by the benchmark's bytes model.
+ * Batch counters count every entry handed to insert/delete/query calls. */
+typedef struct {
+    uint64_t batches;          /* edge batches (insert + delete + query)        */
+    uint64_t pairs;            /* pairs handed in                               */
+    uint64_t touched_vertices; /* distinct valid sources over all batches       */
+    uint64_t scanned_slots;    /* block-granular slots of touched adjacencies   */
+    uint64_t new_blocks;       /* blocks taken from the pool                    */
+    uint64_t freed_blocks;     /* blocks returned to the pool                   */
+    uint64_t written_slots;    /* slots written by appends and compaction moves */
+} gv_counters;
+
+/* Build a graph from a COO edge list (Sec. 4.3 "initialization", Sec. 5.2
+ * "bulk build"): vertices 0..num_vertices-1 become active and the distinct
+ * pairs (d_src[i], d_dst[i]), i < num_edges, become edges.  d_src/d_dst may be
+ * NULL when num_edges is 0.  cfg may be NULL (all defaults).  hip_stream is a
+ * hipStream_t (NULL = the null stream) used for this and later calls.
+ * Synchronous.  Returns GV_ERANGE (and no graph) if any id >= num_vertices,
+ * GV_EINVAL for a bad config or num_vertices > 2^31, GV_ENOMEM if the pool or
+ * device memory is too small. */
+int gv_graph_init(gv_graph** out, uint64_t num_vertices, const uint32_t* d_src,
+                  const uint32_t* d_dst, uint64_t num_edges, const gv_config* cfg,
+                  void* hip_stream);
+
+/* Batched edge insertion (Sec. 4.5.1, Alg. 1) with set semantics: pairs
+ * already present and repeated pairs are skipped.  All-or-nothing: if the pool
+ * or directory cannot hold the result, nothing is applied (GV_ENOMEM). */
+int gv_insert_edges(gv_graph* g, const uint32_t* d_src, const uint32_t* d_dst,
+                    uint64_t n, gv_batch_stats* stats_or_null);
+
+/* Batched edge deletion (Sec. 4.5.2, Alg. 2): matching edges are removed, the
+ * adjacency is compacted and emptied blocks return to the pool. */
+int gv_delete_edges(gv_graph* g, const uint32_t* d_src, const uint32_t* d_dst,
+                    uint64_t n, gv_batch_stats* stats_or_null);
+
+/* Vertex insertion (Sec. 4.4): inactive ids become active with no edges; the
+ * dictionary grows to the next power of two above the largest id when needed.
+ * Ids > 2^31 - 1 are rejected.  Synchronous. */
+int gv_insert_vertices(gv_graph* g, const uint32_t* d_ids, uint64_t n,
+                       gv_batch_stats* stats_or_null);
+
+/* Vertex deletion (Sec. 4.4): each active id loses its out- and in-edges and
+ * becomes inactive; its blocks return to the pool.  Ids >= capacity are
+ * rejected; inactive ids are no-ops.  Synchronous. */
+int gv_delete_vertices(gv_graph* g, const uint32_t* d_ids, uint64_t n,
+                       gv_batch_stats* stats_or_null);
+
+/* Edge query (Sec. 4.6, Alg. 3), batched: d_out[i] = 1 if edge
+ * (d_src[i], d_dst[i]) exists, else 0, in input order.  Asynchronous. */
+int gv_edge_exists(gv_graph* g, const uint32_t* d_src, const uint32_t* d_dst,
+                   uint64_t n, uint8_t* d_out);
+
+/* Adjacency of v in ascending order into d_out (device, out_capacity
+ * entries).  *degree is always set when v < capacity.  v >= capacity gives
+ * GV_ERANGE with *degree = 0; out_capacity < degree gives GV_ERANGE with
+ * *degree set and nothing written.  An inactive v has degree 0.  Synchronous. */
+int gv_get_adjacency(gv_graph* g, uint32_t v, uint32_t* d_out,
+                     uint64_t out_capacity, uint64_t* degree);
+
+/* Memory footprint by exact block accounting (Sec. 5.4).  Synchronous. */
+int gv_memory_used(gv_graph* g, gv_mem* out);
+
+/* Canonical CSR dump for verification: d_offsets has capacity + 1 uint64
+ * entries, d_dst receives each vertex's destinations in ascending order.
+ * *checksum = sum over edges (u, v) of mix64((u << 32) | v) modulo 2^64 where
+ * mix64 is the SplitMix64 output function.  d_offsets and d_dst may both be
+ * NULL to compute only *num_edges and *checksum.  dst_capacity < edges gives
+ * GV_ERANGE with *num_edges set.  Synchronous. */
+int gv_dump_canonical(gv_graph* g, uint64_t* d_offsets, uint32_t* d_dst,
+                      uint64_t dst_capacity, uint64_t* checksum,
+                      uint64_t* num_edges);
+
+/* Structural audit for tests: counts violations of the pool invariants
+ * (every block id below the bump pointer is owned by exactly one adjacency or
+ * sits on the free list exactly once; every vertex of degree d holds
+ * ceil(d / B) blocks; no slot below a degree holds 0xFFFFFFFF or an inactive
+ * id; inactive vertices have degree 0).  *violations = 0 means consistent.
+ * Synchronous. */
+int gv_audit(gv_graph* g, uint64_t* violations);
+
+int gv_graph_info(gv_graph* g, gv_info* out);
+int gv_get_counters(gv_graph* g, gv_counters* out); /* synchronous */
+
+/* Per-kernel timing with HIP events on the graph's stream.  While enabled,
+ * every kernel launch is bracketed by events; gv_kernel_times returns, for
+ * the kernel named `name`, the number of launches and their summed duration
+ * in milliseconds since the last reset (synchronous). */
+int gv_profile_enable(gv_graph* g, int enable);
+int gv_profile_reset(gv_graph* g);
+int gv_kernel_times(gv_graph* g, const char* name, uint64_t* launches,
+                    double* total_ms);
+
+int gv_set_stream(gv_graph* g, void* hip_stream);
+/* Wait for all queued work; returns and clears the first error of earlier
+ * asynchronous calls. */
+int gv_sync(gv_graph* g);
+const char* gv_strerror(int code);
+void gv_graph_destroy(gv_graph* g);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GRAPHVINE_H */

@@ -1,0 +1,328 @@
+// gv_api.hip -- the C ABI declared in include/graphvine.h.
+//
+// Validates arguments, keeps the graph's device current for the duration of
+// a call, and turns internal failures into GV_* codes: no exception crosses
+// this boundary.
+#include <algorithm>
+#include <cstring>
+#include <new>
+
+#include "gv_graph.h"
+
+using namespace gv;
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    int want;
+    explicit DeviceGuard(int dev) : want(dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != want) hip_check(hipSetDevice(want), "hipSetDevice");
+    }
+    ~DeviceGuard() {
+        if (prev >= 0 && prev != want) hipSetDevice(prev);
+    }
+};
+
+template <typename F>
+int guarded(gv_graph* g, F&& f) {
+    if (!g) return GV_EINVAL;
+    if (g->dead) return GV_EDEVICE;
+    try {
+        DeviceGuard dg(g->device);
+        f();
+        return GV_OK;
+    } catch (const Error& e) {
+        if (e.code == GV_EDEVICE) g->dead = true;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        return GV_ENOMEM;
+    } catch (...) {
+        g->dead = true;
+        return GV_EDEVICE;
+    }
+}
+
+void free_graph(gv_graph* g) {
+    if (!g) return;
+    hipStreamSynchronize(g->ctx.stream);
+    g->ctx.release();
+    g->scratch.release();
+    void* mem[] = {g->mem_pool, g->mem_free, g->mem_dir, g->mem_dfree,
+                   g->mem_vt,   g->mem_active, g->mem_ctr};
+    for (void* p : mem)
+        if (p) hipFree(p);
+    if (g->hctr) hipHostFree(g->hctr);
+    delete g;
+}
+
+bool pow2(uint64_t x) { return x && !(x & (x - 1)); }
+
+void fill_stats(gv_graph* g, gv_batch_stats* st) {
+    st->applied = g->hctr->st_applied;
+    st->rejected = g->hctr->st_rejected;
+    st->batch_duplicates = g->hctr->st_dups;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gv_strerror(int code) {
+    switch (code) {
+        case GV_OK: return "ok";
+        case GV_EINVAL: return "invalid argument";
+        case GV_ERANGE: return "id or size out of range";
+        case GV_ENOMEM: return "out of memory (pool, directory or device)";
+        case GV_EDEVICE: return "HIP device failure";
+        default: return "unknown error";
+    }
+}
+
+int gv_graph_init(gv_graph** out, uint64_t num_vertices, const uint32_t* d_src,
+                  const uint32_t* d_dst, uint64_t num_edges, const gv_config* cfg,
+                  void* hip_stream) {
+    if (!out) return GV_EINVAL;
+    *out = nullptr;
+    gv_config c{};
+    if (cfg) c = *cfg;
+    if (num_vertices > GV_MAX_CAPACITY || c.vertex_capacity > GV_MAX_CAPACITY) return GV_EINVAL;
+    if (c.block_slots != 0 && (c.block_slots > 1024 || !pow2(c.block_slots))) return GV_EINVAL;
+    if (c.flags != 0) return GV_EINVAL;
+    if (num_edges && (!d_src || !d_dst)) return GV_EINVAL;
+    gv_graph* g = new (std::nothrow) gv_graph();
+    if (!g) return GV_ENOMEM;
+    try {
+        hip_check(hipGetDevice(&g->device), "hipGetDevice");
+        g->ctx.stream = (hipStream_t)hip_stream;
+        uint64_t want = std::max<uint64_t>(std::max<uint64_t>(num_vertices, c.vertex_capacity), 1);
+        uint64_t cap = 1;
+        while (cap < want) cap <<= 1;
+        GraphView& v = g->v;
+        v.n_cap = cap;
+        v.L = log2_exact(cap);
+        hip_check(hipMalloc(&g->mem_vt, cap * sizeof(VRec)), "hipMalloc vertex table");
+        hip_check(hipMalloc(&g->mem_active, ((cap + 31) / 32) * 4), "hipMalloc active");
+        hip_check(hipMalloc(&g->mem_ctr, sizeof(DevCounters)), "hipMalloc counters");
+        hip_check(hipHostMalloc((void**)&g->hctr, sizeof(DevCounters), hipHostMallocDefault),
+                  "hipHostMalloc");
+        hip_check(hipMemsetAsync(g->mem_ctr, 0, sizeof(DevCounters), g->ctx.stream),
+                  "hipMemsetAsync");
+        v.vt = (VRec*)g->mem_vt;
+        v.active = (uint32_t*)g->mem_active;
+        v.ctr = (DevCounters*)g->mem_ctr;
+        bulk_build(g, num_vertices, d_src, d_dst, num_edges, c);
+    } catch (const Error& e) {
+        free_graph(g);
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        free_graph(g);
+        return GV_ENOMEM;
+    } catch (...) {
+        free_graph(g);
+        return GV_EDEVICE;
+    }
+    *out = g;
+    return GV_OK;
+}
+
+void gv_graph_destroy(gv_graph* g) {
+    if (!g) return;
+    const int dev = g->device;
+    int prev = -1;
+    hipGetDevice(&prev);
+    if (prev != dev) hipSetDevice(dev);
+    free_graph(g);
+    if (prev >= 0 && prev != dev) hipSetDevice(prev);
+}
+
+static int edge_update(gv_graph* g, EdgeMode mode, const uint32_t* s, const uint32_t* d,
+                       uint64_t n, gv_batch_stats* st) {
+    if (st) std::memset(st, 0, sizeof(*st));
+    if (!g) return GV_EINVAL;
+    if (n && (!s || !d)) return GV_EINVAL;
+    if (n == 0) return GV_OK;
+    int rc = guarded(g, [&] {
+        edge_batch(g, mode, s, d, n, nullptr, st == nullptr);
+        if (st) {
+            read_counters(g);
+            if (g->hctr->err_batch) fail((int)g->hctr->err_batch, "batch failed");
+            fill_stats(g, st);
+        }
+    });
+    if (rc != GV_OK && st) std::memset(st, 0, sizeof(*st));
+    return rc;
+}
+
+int gv_insert_edges(gv_graph* g, const uint32_t* d_src, const uint32_t* d_dst, uint64_t n,
+                    gv_batch_stats* st) {
+    return edge_update(g, kInsert, d_src, d_dst, n, st);
+}
+
+int gv_delete_edges(gv_graph* g, const uint32_t* d_src, const uint32_t* d_dst, uint64_t n,
+                    gv_batch_stats* st) {
+    return edge_update(g, kDelete, d_src, d_dst, n, st);
+}
+
+int gv_insert_vertices(gv_graph* g, const uint32_t* d_ids, uint64_t n, gv_batch_stats* st) {
+    if (st) std::memset(st, 0, sizeof(*st));
+    if (!g || (n && !d_ids)) return GV_EINVAL;
+    if (n == 0) return GV_OK;
+    gv_batch_stats tmp{};
+    int rc = guarded(g, [&] { vertex_insert(g, d_ids, n, &tmp); });
+    if (rc == GV_OK && st) *st = tmp;
+    return rc;
+}
+
+int gv_delete_vertices(gv_graph* g, const uint32_t* d_ids, uint64_t n, gv_batch_stats* st) {
+    if (st) std::memset(st, 0, sizeof(*st));
+    if (!g || (n && !d_ids)) return GV_EINVAL;
+    if (n == 0) return GV_OK;
+    gv_batch_stats tmp{};
+    int rc = guarded(g, [&] { vertex_delete(g, d_ids, n, &tmp); });
+    if (rc == GV_OK && st) *st = tmp;
+    return rc;
+}
+
+int gv_edge_exists(gv_graph* g, const uint32_t* d_src, const uint32_t* d_dst, uint64_t n,
+                   uint8_t* d_out) {
+    if (!g) return GV_EINVAL;
+    if (n && (!d_src || !d_dst || !d_out)) return GV_EINVAL;
+    if (n == 0) return GV_OK;
+    return guarded(g, [&] { edge_batch(g, kQuery, d_src, d_dst, n, d_out, true); });
+}
+
+int gv_get_adjacency(gv_graph* g, uint32_t v, uint32_t* d_out, uint64_t out_capacity,
+                     uint64_t* degree) {
+    if (!g || !degree) return GV_EINVAL;
+    *degree = 0;
+    uint64_t deg = 0;
+    int rc = guarded(g, [&] { adjacency(g, v, d_out, out_capacity, &deg); });
+    *degree = deg;
+    return rc;
+}
+
+int gv_memory_used(gv_graph* g, gv_mem* out) {
+    if (!g || !out) return GV_EINVAL;
+    return guarded(g, [&] {
+        read_counters(g);
+        const GraphView& v = g->v;
+        const DevCounters& c = *g->hctr;
+        gv_mem m{};
+        m.block_bytes = 4ull * v.B;
+        m.pool_capacity_blocks = v.cap_blocks;
+        m.free_list_blocks = c.free_cnt;
+        m.bump_blocks = c.bump;
+        m.blocks_in_use = c.bump - c.free_cnt;
+        m.vertex_capacity = v.n_cap;
+        m.vertex_table_bytes = v.n_cap * sizeof(VRec) + ((v.n_cap + 31) / 32) * 4;
+        m.directory_entries_in_use = c.dir_live;
+        uint64_t dfree_total = 0;
+        for (int k = 1; k < kMaxClass; ++k) dfree_total += v.dir_cap >> k;
+        m.directory_bytes = 4ull * (v.dir_cap + dfree_total);
+        m.live_bytes = m.blocks_in_use * m.block_bytes + m.vertex_table_bytes + 4ull * c.dir_live;
+        m.num_edges = c.live_edges;
+        m.reserved_bytes = v.cap_blocks * m.block_bytes + 4ull * v.cap_blocks +
+                           m.directory_bytes + m.vertex_table_bytes + sizeof(DevCounters) +
+                           g->scratch.cap;
+        *out = m;
+    });
+}
+
+int gv_dump_canonical(gv_graph* g, uint64_t* d_offsets, uint32_t* d_dst, uint64_t dst_capacity,
+                      uint64_t* checksum, uint64_t* num_edges) {
+    if (!g || !checksum || !num_edges) return GV_EINVAL;
+    if ((d_offsets == nullptr) != (d_dst == nullptr)) return GV_EINVAL;
+    uint64_t ck = 0, e = 0;
+    int rc = guarded(g, [&] { dump(g, d_offsets, d_dst, dst_capacity, &ck, &e); });
+    *checksum = ck;
+    *num_edges = e;
+    return rc;
+}
+
+int gv_audit(gv_graph* g, uint64_t* violations) {
+    if (!g || !violations) return GV_EINVAL;
+    uint64_t bad = 0;
+    int rc = guarded(g, [&] { bad = audit(g); });
+    *violations = bad;
+    return rc;
+}
+
+int gv_graph_info(gv_graph* g, gv_info* out) {
+    if (!g || !out) return GV_EINVAL;
+    out->vertex_capacity = g->v.n_cap;
+    out->block_slots = g->v.B;
+    out->device = (uint32_t)g->device;
+    return GV_OK;
+}
+
+int gv_get_counters(gv_graph* g, gv_counters* out) {
+    if (!g || !out) return GV_EINVAL;
+    return guarded(g, [&] {
+        read_counters(g);
+        const DevCounters& c = *g->hctr;
+        out->batches = c.c_batches;
+        out->pairs = c.c_pairs;
+        out->touched_vertices = c.c_touched;
+        out->scanned_slots = c.c_scanned;
+        out->new_blocks = c.c_new_blocks;
+        out->freed_blocks = c.c_freed_blocks;
+        out->written_slots = c.c_written;
+    });
+}
+
+int gv_profile_enable(gv_graph* g, int enable) {
+    if (!g) return GV_EINVAL;
+    return guarded(g, [&] {
+        g->ctx.collect();
+        g->ctx.prof = enable != 0;
+    });
+}
+
+int gv_profile_reset(gv_graph* g) {
+    if (!g) return GV_EINVAL;
+    return guarded(g, [&] {
+        g->ctx.collect();
+        g->ctx.sums.clear();
+    });
+}
+
+int gv_kernel_times(gv_graph* g, const char* name, uint64_t* launches, double* total_ms) {
+    if (!g || !name || !launches || !total_ms) return GV_EINVAL;
+    *launches = 0;
+    *total_ms = 0;
+    return guarded(g, [&] {
+        g->ctx.collect();
+        for (auto& s : g->ctx.sums)
+            if (s.name == name) {
+                *launches = s.launches;
+                *total_ms = s.ms;
+            }
+    });
+}
+
+int gv_set_stream(gv_graph* g, void* hip_stream) {
+    if (!g) return GV_EINVAL;
+    return guarded(g, [&] {
+        g->ctx.collect();
+        hip_check(hipStreamSynchronize(g->ctx.stream), "hipStreamSynchronize");
+        g->ctx.stream = (hipStream_t)hip_stream;
+    });
+}
+
+int gv_sync(gv_graph* g) {
+    if (!g) return GV_EINVAL;
+    int code = GV_OK;
+    int rc = guarded(g, [&] {
+        read_counters(g);
+        code = (int)g->hctr->err_sticky;
+        if (code) {
+            set_u32(g, &g->v.ctr->err_sticky, 0);
+            hip_check(hipStreamSynchronize(g->ctx.stream), "hipStreamSynchronize");
+        }
+    });
+    return rc != GV_OK ? rc : code;
+}
+
+}  // extern "C"

@@ -1,0 +1,59 @@
+// gv_graph.h -- the host object behind gv_graph* and the internal entry
+// points implemented by the kernel files.
+#pragma once
+
+#include "gv_device.h"
+#include "gv_host.h"
+
+struct gv_graph {
+    int device = 0;
+    gv::Ctx ctx;
+    gv::GraphView v{};            // device pointers and sizes
+    gv::DevCounters* hctr = nullptr;  // pinned host copy for read-back
+    gv::Scratch scratch;          // per-call temporaries
+    uint64_t item_slots = 0;      // bound on live adjacency slots (pool slots)
+    // device allocations owned by the graph
+    void* mem_pool = nullptr;
+    void* mem_free = nullptr;
+    void* mem_dir = nullptr;
+    void* mem_dfree = nullptr;
+    void* mem_vt = nullptr;
+    void* mem_active = nullptr;
+    void* mem_ctr = nullptr;
+    bool dead = false;            // set after a device failure
+};
+
+namespace gv {
+
+enum EdgeMode { kInsert = 0, kDelete = 1, kQuery = 2 };
+
+// queue one batched edge operation on the graph's stream (no host sync);
+// `sticky` makes an allocation failure visible to later gv_sync calls
+void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t* dst,
+                uint64_t n, uint8_t* out, bool sticky);
+
+// bulk build into a graph whose vertex table is allocated (synchronous)
+void bulk_build(gv_graph* g, uint64_t num_vertices, const uint32_t* src, const uint32_t* dst,
+                uint64_t m, const gv_config& cfg);
+
+void vertex_insert(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats* st);
+void vertex_delete(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats* st);
+
+void adjacency(gv_graph* g, uint32_t v, uint32_t* out, uint64_t cap, uint64_t* degree);
+void dump(gv_graph* g, uint64_t* offsets, uint32_t* dst, uint64_t cap, uint64_t* checksum,
+          uint64_t* edges);
+uint64_t audit(gv_graph* g);
+
+// copy the device counters into g->hctr (synchronous)
+void read_counters(gv_graph* g);
+// set one 32-bit or 64-bit device word from a kernel (stream ordered)
+void set_u32(gv_graph* g, uint32_t* p, uint32_t value);
+void set_u64(gv_graph* g, unsigned long long* p, unsigned long long value);
+
+inline uint32_t log2_exact(uint64_t x) {
+    uint32_t c = 0;
+    while ((1ull << c) < x) ++c;
+    return c;
+}
+
+}  // namespace gv

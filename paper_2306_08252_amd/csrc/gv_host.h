@@ -1,0 +1,151 @@
+// gv_host.h -- host-side launch context, error handling and scratch carving.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/graphvine.h"
+
+namespace gv {
+
+// Internal failures carry a GV_* code; they are caught at the C ABI.
+struct Error {
+    int code;
+    const char* what;
+};
+
+[[noreturn]] inline void fail(int code, const char* what) { throw Error{code, what}; }
+
+inline void hip_check(hipError_t e, const char* what) {
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) fail(GV_ENOMEM, what);
+    if (e != hipSuccess) fail(GV_EDEVICE, what);
+}
+
+// Kernel launches go through Ctx so that they can be timed with HIP events on
+// the graph's stream when profiling is enabled.
+struct Ctx {
+    hipStream_t stream = nullptr;
+    bool prof = false;
+    struct Rec {
+        const char* name;
+        hipEvent_t e0, e1;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> spare;
+    struct Sum {
+        std::string name;
+        uint64_t launches;
+        double ms;
+    };
+    std::vector<Sum> sums;
+
+    hipEvent_t event() {
+        if (!spare.empty()) {
+            hipEvent_t e = spare.back();
+            spare.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        hip_check(hipEventCreate(&e), "hipEventCreate");
+        return e;
+    }
+
+    // Fold finished records into per-name sums (synchronises the stream).
+    void collect() {
+        if (recs.empty()) return;
+        hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
+        for (auto& r : recs) {
+            float ms = 0.f;
+            hip_check(hipEventElapsedTime(&ms, r.e0, r.e1), "hipEventElapsedTime");
+            bool found = false;
+            for (auto& s : sums)
+                if (s.name == r.name) {
+                    s.launches++;
+                    s.ms += ms;
+                    found = true;
+                    break;
+                }
+            if (!found) sums.push_back({r.name, 1, (double)ms});
+            spare.push_back(r.e0);
+            spare.push_back(r.e1);
+        }
+        recs.clear();
+    }
+
+    void release() {
+        for (auto& r : recs) {
+            hipEventDestroy(r.e0);
+            hipEventDestroy(r.e1);
+        }
+        recs.clear();
+        for (auto e : spare) hipEventDestroy(e);
+        spare.clear();
+    }
+
+    template <typename... KArgs, typename... Args>
+    void launch(const char* name, void (*kernel)(KArgs...), uint64_t grid, uint32_t block,
+                Args... args) {
+        if (grid == 0) return;
+        if (grid > 0x7fffffffull) fail(GV_EINVAL, "grid too large");
+        hipEvent_t e0 = nullptr;
+        if (prof) {
+            e0 = event();
+            hip_check(hipEventRecord(e0, stream), "hipEventRecord");
+        }
+        hipLaunchKernelGGL(kernel, dim3((uint32_t)grid), dim3(block), 0, stream, args...);
+        hip_check(hipGetLastError(), name);
+        if (prof) {
+            hipEvent_t e1 = event();
+            hip_check(hipEventRecord(e1, stream), "hipEventRecord");
+            recs.push_back({name, e0, e1});
+            if (recs.size() > 4096) collect();
+        }
+    }
+};
+
+// Carves typed arrays out of one device buffer.  With base == nullptr it only
+// measures, so a caller can size the buffer first and carve second.
+struct Carver {
+    char* base;
+    size_t used = 0;
+    explicit Carver(void* b) : base((char*)b) {}
+    template <typename T>
+    T* take(uint64_t n) {
+        used = (used + 255) & ~size_t(255);
+        T* p = base ? (T*)(base + used) : nullptr;
+        used += (size_t)n * sizeof(T);
+        return p;
+    }
+};
+
+// Growable device scratch buffer owned by a graph.
+struct Scratch {
+    void* ptr = nullptr;
+    size_t cap = 0;
+    void ensure(size_t bytes, hipStream_t s) {
+        if (bytes <= cap) return;
+        if (ptr) {
+            hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+            hip_check(hipFree(ptr), "hipFree");
+            ptr = nullptr;
+            cap = 0;
+        }
+        size_t want = bytes + bytes / 4 + (1 << 20);
+        hip_check(hipMalloc(&ptr, want), "hipMalloc scratch");
+        cap = want;
+    }
+    void release() {
+        if (ptr) hipFree(ptr);
+        ptr = nullptr;
+        cap = 0;
+    }
+};
+
+inline uint64_t div_up(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+}  // namespace gv

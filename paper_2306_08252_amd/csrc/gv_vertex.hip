@@ -1,0 +1,313 @@
+// gv_vertex.hip -- batched vertex insertion and deletion (Sec. 4.4).
+//
+// Insert: ids are sorted and deduplicated; when the largest id does not fit,
+// the dictionary is replaced by one of the next power-of-two capacity (copy
+// kernel, then the old one is freed); inactive ids are switched on.
+//
+// Delete: the deleted set is marked in a bitmap; one sweep over every
+// adjacency emits the out-edges of deleted vertices and the in-edges that
+// point at them; those pairs go through the batched edge-delete pipeline
+// (which compacts and frees blocks); finally the vertices are switched off
+// and their directory segments returned.
+#include <algorithm>
+
+#include "gv_graph.h"
+#include "gv_prim.h"
+
+namespace gv {
+
+__device__ __forceinline__ uint64_t vt_tidx() {
+    return (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+}
+
+constexpr uint32_t kMaxId = 0x7fffffffu;
+
+__device__ __forceinline__ bool bit_of(const uint32_t* bm, uint32_t x) {
+    return (bm[x >> 5] >> (x & 31)) & 1u;
+}
+
+__global__ __launch_bounds__(kThreads) void k_vmax(const uint32_t* ids, uint64_t n,
+                                                   DevCounters* ctr) {
+    const uint64_t i = vt_tidx();
+    uint32_t m = 0, any = 0;
+    if (i < n && ids[i] <= kMaxId) {
+        m = ids[i];
+        any = 1;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        m = max(m, (uint32_t)__shfl_xor((int)m, o, 64));
+        any |= (uint32_t)__shfl_xor((int)any, o, 64);
+    }
+    if (lane_id() == 0 && any) {
+        atomicMax(&ctr->vmax, m);
+        ctr->vany = 1;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_vcopy_ids(const uint32_t* ids, uint64_t n,
+                                                        uint32_t* out) {
+    const uint64_t i = vt_tidx();
+    if (i < n) out[i] = ids[i];
+}
+
+__global__ __launch_bounds__(kThreads) void k_vzero(uint32_t* a, uint64_t n) {
+    const uint64_t i = vt_tidx();
+    if (i < n) a[i] = 0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_grow_table(const VRec* vt, const uint32_t* act,
+                                                         uint64_t old_cap, VRec* vt2,
+                                                         uint32_t* act2, uint64_t new_cap) {
+    const uint64_t v = vt_tidx();
+    if (v < new_cap) vt2[v] = v < old_cap ? vt[v] : VRec{0u, 0u, kNoDir, 0u};
+    const uint64_t ow = (old_cap + 31) / 32, nw = (new_cap + 31) / 32;
+    if (v < nw) {
+        uint32_t w = v < ow ? act[v] : 0u;
+        if (v == ow - 1 && (old_cap & 31)) w &= (1u << (old_cap & 31)) - 1u;
+        act2[v] = w;
+    }
+}
+
+__global__ void k_vreset(DevCounters* c) {
+    c->st_applied = c->st_rejected = c->st_dups = 0;
+    c->n_uniq = 0;
+    c->vmax = 0;
+    c->vany = 0;
+    c->edges = 0;
+    c->checksum = 0;
+}
+
+// sorted ids: count rejected and distinct, activate the inactive ones
+__global__ __launch_bounds__(kThreads) void k_vins(GraphView g, const uint32_t* keys, uint64_t n) {
+    __shared__ unsigned long long lds[kWaves];
+    const uint64_t i = vt_tidx();
+    unsigned long long rej = 0, uniq = 0, app = 0;
+    if (i < n) {
+        const uint32_t id = keys[i];
+        const bool valid = id <= kMaxId && (uint64_t)id < g.n_cap;
+        rej = !valid;
+        if (valid && (i == 0 || keys[i - 1] != id)) {
+            uniq = 1;
+            const uint32_t bit = 1u << (id & 31);
+            const uint32_t old = atomicOr(&g.active[id >> 5], bit);
+            if (!(old & bit)) {
+                app = 1;
+                g.vt[id] = VRec{0u, 0u, kNoDir, 0u};
+            }
+        }
+    }
+    rej = block_sum(rej, lds);
+    uniq = block_sum(uniq, lds);
+    app = block_sum(app, lds);
+    if (threadIdx.x == 0) {
+        if (rej) atomicAdd(&g.ctr->st_rejected, rej);
+        if (uniq) atomicAdd(&g.ctr->n_uniq, uniq);
+        if (app) atomicAdd(&g.ctr->st_applied, app);
+    }
+}
+
+// sorted ids: mark the active distinct ones in the `gone` bitmap
+__global__ __launch_bounds__(kThreads) void k_vdel_mark(GraphView g, const uint32_t* keys,
+                                                        uint64_t n, uint32_t* gone) {
+    __shared__ unsigned long long lds[kWaves];
+    const uint64_t i = vt_tidx();
+    unsigned long long rej = 0, uniq = 0, app = 0;
+    if (i < n) {
+        const uint32_t id = keys[i];
+        const bool valid = (uint64_t)id < g.n_cap;
+        rej = !valid;
+        if (valid && (i == 0 || keys[i - 1] != id)) {
+            uniq = 1;
+            if (is_active(g, id)) {
+                atomicOr(&gone[id >> 5], 1u << (id & 31));
+                app = 1;
+            }
+        }
+    }
+    rej = block_sum(rej, lds);
+    uniq = block_sum(uniq, lds);
+    app = block_sum(app, lds);
+    if (threadIdx.x == 0) {
+        if (rej) atomicAdd(&g.ctr->st_rejected, rej);
+        if (uniq) atomicAdd(&g.ctr->n_uniq, uniq);
+        if (app) atomicAdd(&g.ctr->st_applied, app);
+    }
+}
+
+// one wave per vertex: count (EMIT = false) or emit (EMIT = true) the edges
+// that touch a deleted vertex
+template <bool EMIT>
+__global__ __launch_bounds__(kThreads) void k_vdel_sweep(GraphView g, const uint32_t* gone,
+                                                         uint32_t* psrc, uint32_t* pdst,
+                                                         uint64_t cap) {
+    const uint32_t lane = lane_id();
+    const uint64_t nw = (uint64_t)gridDim.x * kWaves;
+    const uint64_t wave = ((uint64_t)blockIdx.x * kThreads + threadIdx.x) >> 6;
+    unsigned long long cnt = 0;
+    for (uint64_t u = wave; u < g.n_cap; u += nw) {
+        const VRec r = g.vt[u];
+        if (r.deg == 0 || !is_active(g, u)) continue;
+        const bool src_gone = bit_of(gone, (uint32_t)u);
+        for (uint32_t s0 = 0; s0 < r.deg; s0 += 64) {
+            const uint32_t s = s0 + lane;
+            bool hit = false;
+            uint32_t x = 0;
+            if (s < r.deg) {
+                x = g.pool[slot_addr(g, r, s)];
+                hit = src_gone || bit_of(gone, x);
+            }
+            const uint64_t m = ballot(hit);
+            if (EMIT) {
+                unsigned long long base = 0;
+                if (m && lane == 0) base = atomicAdd(&g.ctr->checksum, (unsigned long long)popc64(m));
+                base = __shfl(base, 0, 64);
+                const uint64_t pos = base + rank_below(m);
+                if (hit && pos < cap) {
+                    psrc[pos] = (uint32_t)u;
+                    pdst[pos] = x;
+                }
+            } else {
+                cnt += popc64(m);
+            }
+        }
+    }
+    if (!EMIT && lane == 0 && cnt) atomicAdd(&g.ctr->edges, cnt);
+}
+
+__global__ __launch_bounds__(kThreads) void k_vdel_finish(GraphView g, const uint32_t* keys,
+                                                          uint64_t n, const uint32_t* gone) {
+    const uint64_t i = vt_tidx();
+    if (i >= n) return;
+    const uint32_t id = keys[i];
+    if ((uint64_t)id >= g.n_cap || (i > 0 && keys[i - 1] == id) || !bit_of(gone, id)) return;
+    atomicAnd(&g.active[id >> 5], ~(1u << (id & 31)));
+    const VRec r = g.vt[id];
+    if (r.dcls != kNoDir) {
+        const uint32_t pos = atomicAdd(&g.ctr->dfree_cnt[r.dcls], 1u);
+        g.dfree[g.dfree_base[r.dcls] + pos] = r.dir;
+        atomicAdd(&g.ctr->dir_live, (unsigned long long)(-(long long)(1ull << r.dcls)));
+    }
+    g.vt[id] = VRec{0u, 0u, kNoDir, 0u};
+}
+
+// sort a copy of the ids into `keys` (ascending); returns the sorted array
+static uint32_t* sorted_ids(gv_graph* g, const uint32_t* ids, uint64_t n, uint32_t* k0,
+                            uint32_t* k1) {
+    Ctx& c = g->ctx;
+    c.launch("vcopy", k_vcopy_ids, div_up(n, kThreads), kThreads, ids, n, k0);
+    SortScratch ss{};
+    {
+        Carver mz(nullptr);
+        carve_sort<uint32_t>(mz, ss, n);
+        g->scratch.ensure(mz.used, c.stream);
+        Carver cv(g->scratch.ptr);
+        carve_sort<uint32_t>(cv, ss, n);
+    }
+    return radix_sort<uint32_t, false>(c, k0, k1, nullptr, nullptr, n, 32, ss) ? k1 : k0;
+}
+
+struct DevBuf {
+    void* p = nullptr;
+    explicit DevBuf(size_t bytes) { hip_check(hipMalloc(&p, std::max<size_t>(bytes, 4)), "hipMalloc"); }
+    ~DevBuf() {
+        if (p) hipFree(p);
+    }
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+};
+
+static void grow_table(gv_graph* g, uint64_t new_cap) {
+    Ctx& c = g->ctx;
+    GraphView& v = g->v;
+    void *vt2 = nullptr, *act2 = nullptr;
+    hip_check(hipMalloc(&vt2, new_cap * sizeof(VRec)), "hipMalloc vertex table");
+    const uint64_t words = (new_cap + 31) / 32;
+    if (hipMalloc(&act2, words * 4) != hipSuccess) {
+        hipFree(vt2);
+        fail(GV_ENOMEM, "hipMalloc active bitmap");
+    }
+    c.launch("grow_table", k_grow_table, div_up(new_cap, kThreads), kThreads, (const VRec*)v.vt,
+             (const uint32_t*)v.active, (uint64_t)v.n_cap, (VRec*)vt2, (uint32_t*)act2, new_cap);
+    hip_check(hipStreamSynchronize(c.stream), "hipStreamSynchronize");
+    hipFree(g->mem_vt);
+    hipFree(g->mem_active);
+    g->mem_vt = vt2;
+    g->mem_active = act2;
+    v.vt = (VRec*)vt2;
+    v.active = (uint32_t*)act2;
+    v.n_cap = new_cap;
+    v.L = log2_exact(new_cap);
+}
+
+void vertex_insert(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats* st) {
+    Ctx& c = g->ctx;
+    if (n >= 0xffffffffull) fail(GV_EINVAL, "batch too large");
+    c.launch("vreset", k_vreset, 1, 1, g->v.ctr);
+    c.launch("vmax", k_vmax, div_up(n, kThreads), kThreads, ids, n, g->v.ctr);
+    read_counters(g);
+    if (g->hctr->vany && (uint64_t)g->hctr->vmax >= g->v.n_cap) {
+        uint64_t cap = g->v.n_cap;
+        while (cap <= (uint64_t)g->hctr->vmax) cap <<= 1;
+        grow_table(g, cap);
+    }
+    DevBuf keys(2 * n * sizeof(uint32_t));
+    uint32_t* k0 = (uint32_t*)keys.p;
+    uint32_t* sorted = sorted_ids(g, ids, n, k0, k0 + n);
+    c.launch("vinsert", k_vins, div_up(n, kThreads), kThreads, g->v, (const uint32_t*)sorted, n);
+    read_counters(g);
+    if (st) {
+        st->applied = g->hctr->st_applied;
+        st->rejected = g->hctr->st_rejected;
+        st->batch_duplicates = n - g->hctr->st_rejected - g->hctr->n_uniq;
+    }
+}
+
+void vertex_delete(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats* st) {
+    Ctx& c = g->ctx;
+    const GraphView& v = g->v;
+    if (n >= 0xffffffffull) fail(GV_EINVAL, "batch too large");
+    const uint64_t words = (v.n_cap + 31) / 32;
+    DevBuf tmp((2 * n + words) * sizeof(uint32_t));
+    uint32_t* k0 = (uint32_t*)tmp.p;
+    uint32_t* gone = k0 + 2 * n;
+    c.launch("vreset", k_vreset, 1, 1, v.ctr);
+    c.launch("vzero", k_vzero, div_up(words, kThreads), kThreads, gone, words);
+    uint32_t* sorted = sorted_ids(g, ids, n, k0, k0 + n);
+    c.launch("vdel_mark", k_vdel_mark, div_up(n, kThreads), kThreads, v, (const uint32_t*)sorted,
+             n, gone);
+    read_counters(g);
+    const uint64_t applied = g->hctr->st_applied;
+    const uint64_t rejected = g->hctr->st_rejected;
+    const uint64_t uniq = g->hctr->n_uniq;
+    if (applied) {
+        const uint64_t wgrid = std::min<uint64_t>(div_up(v.n_cap, kWaves), 4096);
+        c.launch("vdel_count", k_vdel_sweep<false>, wgrid, kThreads, v, (const uint32_t*)gone,
+                 (uint32_t*)nullptr, (uint32_t*)nullptr, (uint64_t)0);
+        read_counters(g);
+        const uint64_t pairs = g->hctr->edges;
+        if (pairs) {
+            DevBuf pb(2 * pairs * sizeof(uint32_t));
+            uint32_t* psrc = (uint32_t*)pb.p;
+            uint32_t* pdst = psrc + pairs;
+            set_u64(g, &v.ctr->checksum, 0);
+            c.launch("vdel_emit", k_vdel_sweep<true>, wgrid, kThreads, v, (const uint32_t*)gone,
+                     psrc, pdst, pairs);
+            edge_batch(g, kDelete, psrc, pdst, pairs, nullptr, false);
+            c.launch("vdel_finish", k_vdel_finish, div_up(n, kThreads), kThreads, g->v,
+                     (const uint32_t*)sorted, n, (const uint32_t*)gone);
+            hip_check(hipStreamSynchronize(c.stream), "hipStreamSynchronize");
+        } else {
+            c.launch("vdel_finish", k_vdel_finish, div_up(n, kThreads), kThreads, g->v,
+                     (const uint32_t*)sorted, n, (const uint32_t*)gone);
+            hip_check(hipStreamSynchronize(c.stream), "hipStreamSynchronize");
+        }
+    }
+    if (st) {
+        st->applied = applied;
+        st->rejected = rejected;
+        st->batch_duplicates = n - rejected - uniq;
+    }
+}
+
+}  // namespace gv

@@ -1,0 +1,347 @@
+"""Python binding of libgraphvine.so (include/graphvine.h).
+
+Argument marshalling only: every function below forwards to the C function of
+the same name, passing device pointers of torch tensors and the current HIP
+stream.  All work runs in the library's HIP kernels.  There is no fallback:
+if the library has not been built, importing a function raises.
+
+Id arrays are 32-bit tensors (torch.int32 or torch.uint32, holding the
+uint32 bit patterns) on the graph's GPU; numpy arrays are copied to the GPU
+first.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgraphvine.so")
+
+GV_OK, GV_EINVAL, GV_ERANGE, GV_ENOMEM, GV_EDEVICE = 0, 1, 2, 3, 4
+
+
+class gv_config(C.Structure):
+    _fields_ = [("block_slots", C.c_uint32), ("flags", C.c_uint32),
+                ("pool_bytes", C.c_uint64), ("vertex_capacity", C.c_uint64),
+                ("directory_entries", C.c_uint64)]
+
+
+class gv_batch_stats(C.Structure):
+    _fields_ = [("applied", C.c_uint64), ("rejected", C.c_uint64),
+                ("batch_duplicates", C.c_uint64)]
+
+    def as_tuple(self):
+        return (self.applied, self.rejected, self.batch_duplicates)
+
+
+class gv_mem(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in (
+        "block_bytes", "pool_capacity_blocks", "blocks_in_use", "free_list_blocks",
+        "bump_blocks", "vertex_capacity", "vertex_table_bytes", "directory_entries_in_use",
+        "directory_bytes", "live_bytes", "num_edges", "reserved_bytes")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class gv_info(C.Structure):
+    _fields_ = [("vertex_capacity", C.c_uint64), ("block_slots", C.c_uint32),
+                ("device", C.c_uint32)]
+
+
+class gv_counters(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in (
+        "batches", "pairs", "touched_vertices", "scanned_slots", "new_blocks",
+        "freed_blocks", "written_slots")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with "
+                "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = C.CDLL(LIB_PATH)
+        vp, u32p, u64p = C.c_void_p, C.c_void_p, C.POINTER(C.c_uint64)
+        sig = {
+            "gv_graph_init": [C.POINTER(C.c_void_p), C.c_uint64, u32p, u32p, C.c_uint64,
+                              C.POINTER(gv_config), vp],
+            "gv_insert_edges": [vp, u32p, u32p, C.c_uint64, C.POINTER(gv_batch_stats)],
+            "gv_delete_edges": [vp, u32p, u32p, C.c_uint64, C.POINTER(gv_batch_stats)],
+            "gv_insert_vertices": [vp, u32p, C.c_uint64, C.POINTER(gv_batch_stats)],
+            "gv_delete_vertices": [vp, u32p, C.c_uint64, C.POINTER(gv_batch_stats)],
+            "gv_edge_exists": [vp, u32p, u32p, C.c_uint64, vp],
+            "gv_get_adjacency": [vp, C.c_uint32, u32p, C.c_uint64, u64p],
+            "gv_memory_used": [vp, C.POINTER(gv_mem)],
+            "gv_dump_canonical": [vp, vp, u32p, C.c_uint64, u64p, u64p],
+            "gv_audit": [vp, u64p],
+            "gv_graph_info": [vp, C.POINTER(gv_info)],
+            "gv_get_counters": [vp, C.POINTER(gv_counters)],
+            "gv_profile_enable": [vp, C.c_int],
+            "gv_profile_reset": [vp],
+            "gv_kernel_times": [vp, C.c_char_p, u64p, C.POINTER(C.c_double)],
+            "gv_set_stream": [vp, vp],
+            "gv_sync": [vp],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.gv_strerror.argtypes = [C.c_int]
+        L.gv_strerror.restype = C.c_char_p
+        L.gv_graph_destroy.argtypes = [vp]
+        L.gv_graph_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+class GraphVineError(RuntimeError):
+    def __init__(self, code, fn):
+        super().__init__(f"{fn}: {gv_strerror(code)} (code {code})")
+        self.code = code
+
+
+def gv_strerror(code: int) -> str:
+    return lib().gv_strerror(int(code)).decode()
+
+
+def _check(rc, fn):
+    if rc != GV_OK:
+        raise GraphVineError(rc, fn)
+
+
+def _stream_ptr(device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def as_device_u32(x, device) -> torch.Tensor:
+    """A contiguous 32-bit tensor holding the uint32 ids of x on `device`."""
+    if isinstance(x, torch.Tensor):
+        if x.dtype not in (torch.int32, torch.uint32):
+            raise TypeError("id tensors must be int32 or uint32")
+        if x.device != torch.device(device):
+            raise ValueError(f"tensor on {x.device}, graph on {device}")
+        return x.contiguous()
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.uint32)).view(np.int32)
+    return torch.from_numpy(a).to(device)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None and t.numel() else C.c_void_p(0)
+
+
+# ------------------------------------------------------------------ C names
+def gv_graph_init(num_vertices, src, dst, block_slots=0, pool_bytes=0, vertex_capacity=0,
+                  directory_entries=0, device="cuda:0"):
+    """Returns an opaque graph handle (int).  See gv_graph_init in graphvine.h."""
+    s = as_device_u32(src, device)
+    d = as_device_u32(dst, device)
+    if s.numel() != d.numel():
+        raise ValueError("src/dst length mismatch")
+    cfg = gv_config(int(block_slots), 0, int(pool_bytes), int(vertex_capacity),
+                    int(directory_entries))
+    h = C.c_void_p()
+    with torch.cuda.device(torch.device(device)):
+        rc = lib().gv_graph_init(C.byref(h), int(num_vertices), _ptr(s), _ptr(d), s.numel(),
+                                 C.byref(cfg), _stream_ptr(device))
+    _check(rc, "gv_graph_init")
+    return h.value
+
+
+def _edges(fn, name, g, src, dst, device, stats):
+    s = as_device_u32(src, device)
+    d = as_device_u32(dst, device)
+    if s.numel() != d.numel():
+        raise ValueError("src/dst length mismatch")
+    st = gv_batch_stats()
+    rc = fn(C.c_void_p(g), _ptr(s), _ptr(d), s.numel(), C.byref(st) if stats else None)
+    _check(rc, name)
+    return st.as_tuple() if stats else None
+
+
+def gv_insert_edges(g, src, dst, device="cuda:0", stats=True):
+    return _edges(lib().gv_insert_edges, "gv_insert_edges", g, src, dst, device, stats)
+
+
+def gv_delete_edges(g, src, dst, device="cuda:0", stats=True):
+    return _edges(lib().gv_delete_edges, "gv_delete_edges", g, src, dst, device, stats)
+
+
+def _verts(fn, name, g, ids, device):
+    a = as_device_u32(ids, device)
+    st = gv_batch_stats()
+    _check(fn(C.c_void_p(g), _ptr(a), a.numel(), C.byref(st)), name)
+    return st.as_tuple()
+
+
+def gv_insert_vertices(g, ids, device="cuda:0"):
+    return _verts(lib().gv_insert_vertices, "gv_insert_vertices", g, ids, device)
+
+
+def gv_delete_vertices(g, ids, device="cuda:0"):
+    return _verts(lib().gv_delete_vertices, "gv_delete_vertices", g, ids, device)
+
+
+def gv_edge_exists(g, src, dst, device="cuda:0", out=None):
+    s = as_device_u32(src, device)
+    d = as_device_u32(dst, device)
+    if s.numel() != d.numel():
+        raise ValueError("src/dst length mismatch")
+    if out is None:
+        out = torch.empty(s.numel(), dtype=torch.uint8, device=device)
+    _check(lib().gv_edge_exists(C.c_void_p(g), _ptr(s), _ptr(d), s.numel(), _ptr(out)),
+           "gv_edge_exists")
+    return out
+
+
+def gv_get_adjacency(g, v, device="cuda:0", out=None):
+    deg = C.c_uint64()
+    if out is None:
+        rc = lib().gv_get_adjacency(C.c_void_p(g), int(v), C.c_void_p(0), 0, C.byref(deg))
+        if rc not in (GV_OK, GV_ERANGE) or (rc == GV_ERANGE and deg.value == 0
+                                            and int(v) >= gv_graph_info(g)["vertex_capacity"]):
+            _check(rc, "gv_get_adjacency")
+        out = torch.empty(max(deg.value, 1), dtype=torch.int32, device=device)
+    rc = lib().gv_get_adjacency(C.c_void_p(g), int(v), _ptr(out), out.numel(), C.byref(deg))
+    _check(rc, "gv_get_adjacency")
+    return out[: deg.value]
+
+
+def gv_memory_used(g):
+    m = gv_mem()
+    _check(lib().gv_memory_used(C.c_void_p(g), C.byref(m)), "gv_memory_used")
+    return m.as_dict()
+
+
+def gv_dump_canonical(g, device="cuda:0", checksum_only=False):
+    """(offsets int64[capacity+1], dst int32[E], checksum, E); arrays are None
+    when checksum_only."""
+    ck, e = C.c_uint64(), C.c_uint64()
+    L = lib()
+    if checksum_only:
+        _check(L.gv_dump_canonical(C.c_void_p(g), None, None, 0, C.byref(ck), C.byref(e)),
+               "gv_dump_canonical")
+        return None, None, ck.value, e.value
+    cap = gv_graph_info(g)["vertex_capacity"]
+    _check(L.gv_dump_canonical(C.c_void_p(g), None, None, 0, C.byref(ck), C.byref(e)),
+           "gv_dump_canonical")
+    offs = torch.empty(cap + 1, dtype=torch.int64, device=device)
+    dst = torch.empty(max(e.value, 1), dtype=torch.int32, device=device)
+    _check(L.gv_dump_canonical(C.c_void_p(g), _ptr(offs), _ptr(dst), dst.numel(), C.byref(ck),
+                               C.byref(e)), "gv_dump_canonical")
+    return offs, dst[: e.value], ck.value, e.value
+
+
+def gv_audit(g):
+    bad = C.c_uint64()
+    _check(lib().gv_audit(C.c_void_p(g), C.byref(bad)), "gv_audit")
+    return bad.value
+
+
+def gv_graph_info(g):
+    i = gv_info()
+    _check(lib().gv_graph_info(C.c_void_p(g), C.byref(i)), "gv_graph_info")
+    return {"vertex_capacity": i.vertex_capacity, "block_slots": i.block_slots,
+            "device": i.device}
+
+
+def gv_get_counters(g):
+    c = gv_counters()
+    _check(lib().gv_get_counters(C.c_void_p(g), C.byref(c)), "gv_get_counters")
+    return c.as_dict()
+
+
+def gv_profile_enable(g, enable=True):
+    _check(lib().gv_profile_enable(C.c_void_p(g), int(bool(enable))), "gv_profile_enable")
+
+
+def gv_profile_reset(g):
+    _check(lib().gv_profile_reset(C.c_void_p(g)), "gv_profile_reset")
+
+
+def gv_kernel_times(g, name):
+    n, ms = C.c_uint64(), C.c_double()
+    _check(lib().gv_kernel_times(C.c_void_p(g), name.encode(), C.byref(n), C.byref(ms)),
+           "gv_kernel_times")
+    return n.value, ms.value
+
+
+def gv_set_stream(g, stream_ptr):
+    _check(lib().gv_set_stream(C.c_void_p(g), C.c_void_p(stream_ptr)), "gv_set_stream")
+
+
+def gv_sync(g):
+    return lib().gv_sync(C.c_void_p(g))
+
+
+def gv_graph_destroy(g):
+    lib().gv_graph_destroy(C.c_void_p(g))
+
+
+# ------------------------------------------------------------------ wrapper
+class Graph:
+    """Owning wrapper over a gv_graph handle on one GPU."""
+
+    def __init__(self, num_vertices, src=(), dst=(), block_slots=16, pool_bytes=0,
+                 vertex_capacity=0, directory_entries=0, device="cuda:0"):
+        self.device = torch.device(device)
+        self.h = gv_graph_init(num_vertices, src, dst, block_slots, pool_bytes, vertex_capacity,
+                               directory_entries, self.device)
+
+    def close(self):
+        if getattr(self, "h", None):
+            gv_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def insert_edges(self, src, dst, stats=True):
+        return gv_insert_edges(self.h, src, dst, self.device, stats)
+
+    def delete_edges(self, src, dst, stats=True):
+        return gv_delete_edges(self.h, src, dst, self.device, stats)
+
+    def insert_vertices(self, ids):
+        return gv_insert_vertices(self.h, ids, self.device)
+
+    def delete_vertices(self, ids):
+        return gv_delete_vertices(self.h, ids, self.device)
+
+    def edge_exists(self, src, dst, out=None):
+        return gv_edge_exists(self.h, src, dst, self.device, out)
+
+    def get_adjacency(self, v):
+        return gv_get_adjacency(self.h, v, self.device)
+
+    def memory_used(self):
+        return gv_memory_used(self.h)
+
+    def dump(self, checksum_only=False):
+        return gv_dump_canonical(self.h, self.device, checksum_only)
+
+    def audit(self):
+        return gv_audit(self.h)
+
+    def info(self):
+        return gv_graph_info(self.h)
+
+    def counters(self):
+        return gv_get_counters(self.h)
+
+    def sync(self):
+        return gv_sync(self.h)

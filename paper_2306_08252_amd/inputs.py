@@ -75,6 +75,8 @@ def uniform_pairs(seed: int, n: int, num_vertices: int, self_loops: bool = False
     Draw i gives src from its high 32 bits and dst from its low 32 bits.
     Without self_loops, draws with src == dst are skipped."""
     out_s, out_d, have, start = [], [], 0, 0
+    out_s.append(np.zeros(0, np.uint64))
+    out_d.append(np.zeros(0, np.uint64))
     while have < n:
         want = (n - have) + (n - have) // 8 + 64
         r = splitmix64(seed, want, start)
@@ -103,33 +105,34 @@ def rmat_pairs_raw(seed: int, n: int, scale: int, start: int = 0,
 
     Pair i uses ceil(scale / 2) draws; level l (0 = most significant bit)
     reads the high half of draw l // 2 for even l and the low half for odd l.
-    Quadrant (src bit, dst bit): u < t1 -> (0,0); u < t2 -> (0,1);
-    u < t3 -> (1,0); otherwise (1,1)."""
-    t1, t2, t3 = (np.uint64(t) for t in rmat_thresholds(*abc))
+    Quadrant q = [u >= t1] + [u >= t2] + [u >= t3] in 0..3, i.e.
+    u < t1 -> (0,0); u < t2 -> (0,1); u < t3 -> (1,0); otherwise (1,1);
+    the source bit is q >> 1 and the destination bit q & 1."""
+    t1, t2, t3 = (np.uint32(t) for t in rmat_thresholds(*abc))
     w = (scale + 1) // 2
-    src = np.zeros(n, dtype=np.uint64)
-    dst = np.zeros(n, dtype=np.uint64)
-    chunk = 1 << 22
+    src = np.zeros(n, dtype=np.uint32)
+    dst = np.zeros(n, dtype=np.uint32)
+    weights = (np.uint32(1) << np.arange(scale - 1, -1, -1, dtype=np.uint32))
+    chunk = 1 << 21
     for c0 in range(0, n, chunk):
         m = min(chunk, n - c0)
         r = splitmix64(seed, m * w, (start + c0) * w).reshape(m, w)
-        s = np.zeros(m, dtype=np.uint64)
-        d = np.zeros(m, dtype=np.uint64)
-        for lvl in range(scale):
-            word = r[:, lvl // 2]
-            u = (word >> np.uint64(32)) if lvl % 2 == 0 else (word & _MASK32)
-            sbit = (u >= t2).astype(np.uint64)
-            dbit = (((u >= t1) & (u < t2)) | (u >= t3)).astype(np.uint64)
-            s = (s << np.uint64(1)) | sbit
-            d = (d << np.uint64(1)) | dbit
-        src[c0:c0 + m] = s
-        dst[c0:c0 + m] = d
-    return src.astype(np.uint32), dst.astype(np.uint32)
+        u = np.empty((m, 2 * w), dtype=np.uint32)
+        u[:, 0::2] = (r >> np.uint64(32)).astype(np.uint32)
+        u[:, 1::2] = (r & _MASK32).astype(np.uint32)
+        u = u[:, :scale]
+        q = ((u >= t1).astype(np.uint8) + (u >= t2).astype(np.uint8)
+             + (u >= t3).astype(np.uint8))
+        src[c0:c0 + m] = ((q >> 1).astype(np.uint32) * weights).sum(axis=1, dtype=np.uint32)
+        dst[c0:c0 + m] = ((q & 1).astype(np.uint32) * weights).sum(axis=1, dtype=np.uint32)
+    return src, dst
 
 
 def rmat_pairs(seed: int, n: int, scale: int, abc=RMAT_ABC):
     """The first n R-MAT pairs of the stream that are not self-loops."""
     out_s, out_d, have, start = [], [], 0, 0
+    out_s.append(np.zeros(0, np.uint32))
+    out_d.append(np.zeros(0, np.uint32))
     while have < n:
         want = (n - have) + (n - have) // 16 + 64
         s, d = rmat_pairs_raw(seed, want, scale, start, abc)

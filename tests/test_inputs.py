@@ -91,3 +91,47 @@ def test_tiny_workload_shape():
         hit = np.isin(I.pair_keys(bs, bd), known)
         assert int(hit.sum()) == 512
     assert len(w["query"][0]) == 1024
+
+
+def test_torch_streams_match_numpy():
+    import torch
+    from paper_2306_08252_amd import inputs_torch as T
+    seed = I.stream_seed("torch-eq")
+    assert np.array_equal(T.splitmix64(seed, 1000, 17).numpy().view(np.uint64),
+                          I.splitmix64(seed, 1000, 17))
+    a = I.uniform_pairs(seed, 5000, 1000)
+    b = T.uniform_pairs(seed, 5000, 1000)
+    assert np.array_equal(a[0], b[0].numpy().view(np.uint32))
+    assert np.array_equal(a[1], b[1].numpy().view(np.uint32))
+    a = I.rmat_pairs(seed, 7000, 13)
+    b = T.rmat_pairs(seed, 7000, 13)
+    assert np.array_equal(a[0], b[0].numpy().view(np.uint32))
+    assert np.array_equal(a[1], b[1].numpy().view(np.uint32))
+    a = I.rmat_graph(seed, 11, 9000)
+    b = T.rmat_graph(seed, 11, 9000)
+    assert np.array_equal(a[0], b[0].numpy().view(np.uint32))
+    assert np.array_equal(a[1], b[1].numpy().view(np.uint32))
+    assert np.array_equal(I.permutation(seed, 3000), T.permutation(seed, 3000).numpy())
+    wn = I.RmatWorkload(12, 20000, name="eq")
+    wt = T.RmatWorkload(12, 20000, name="eq")
+    for fn in ("insert_batch", "delete_batch", "query_batch"):
+        for j in range(2):
+            x = getattr(wn, fn)(3000, j)
+            y = getattr(wt, fn)(3000, j)
+            assert np.array_equal(x[0], y[0].numpy().view(np.uint32)), fn
+            assert np.array_equal(x[1], y[1].numpy().view(np.uint32)), fn
+
+
+def test_zero_length_draws():
+    from paper_2306_08252_amd import inputs_torch as T
+    for f in (lambda: I.uniform_pairs(1, 0, 10), lambda: I.rmat_pairs(1, 0, 10)):
+        s, d = f()
+        assert len(s) == 0 and s.dtype == np.uint32 and d.dtype == np.uint32
+    for f in (lambda: T.uniform_pairs(1, 0, 10), lambda: T.rmat_pairs(1, 0, 10)):
+        s, d = f()
+        assert len(s) == 0 and str(s.dtype) == "torch.int32"
+    w = I.RmatWorkload(10, 3000, name="z")
+    s, d = w.delete_batch(1, 0)
+    assert len(s) == 1
+    s, d = T.RmatWorkload(10, 3000, name="z").delete_batch(1, 0)
+    assert len(s) == 1 and str(s.dtype) == "torch.int32"
