@@ -1,0 +1,295 @@
+#!/usr/bin/env python3
+"""Benchmark of the GraphVine hot path on one MI355X.
+
+Workload: directed R-MAT graph (a, b, c, d) = (0.57, 0.19, 0.19, 0.05) with
+2^20 vertices and 2^24 distinct edges, block size B = 16, drawn on the GPU
+from the seeded streams of paper_2306_08252_amd.inputs.  A step is one
+batched edge insert of 10^6 R-MAT pairs followed by one batched edge delete
+of 10^6 pairs (80 % existing edges, 20 % uniform pairs), both applied to the
+resident graph through the C ABI with inputs already in HBM.
+
+value = (insert pairs + delete pairs) per second over the timed steps.  The
+same run also times, each in its own loop: bulk build from COO (init
+edges/s), batched edge queries, vertex insert/delete batches, an adjacency
+read of the largest hub and the memory report.
+
+roofline: the kernel with the largest share of the step's GPU time, its
+algorithmic bytes per launch (model below) over its average launch time,
+measured with HIP events on the graph's stream inside the timed region.
+
+cpu_baseline: the CPU oracle (ordered sets, one thread) applying the same
+batches restricted to a quarter of the sources (those whose SplitMix64 hash
+is 0 mod 4) to the same graph restricted the same way.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def bytes_model(name, per_launch):
+    """Algorithmic bytes of one launch of `name` (counted once, at any cache
+    level).  per_launch holds the averages of the batch quantities:
+    k (pairs), T (touched sources), S (block-granular slots of the touched
+    adjacencies), NB (blocks per touched adjacency, S / B), W (slots written),
+    M (slots moved), NEW / FREED (blocks)."""
+    k, T, S, NBLK = per_launch["k"], per_launch["T"], per_launch["S"], per_launch["NB"]
+    if name in ("probe_insert", "probe_delete", "probe_query"):
+        # adjacency slots + their directory entries + vertex records + the
+        # sorted batch keys (each read once) + one mark byte per pair
+        return 4 * S + 4 * NBLK + 16 * T + 8 * k + k
+    if name == "sort_scatter":
+        return 16 * k  # read and write every key once
+    if name == "sort_hist":
+        return 8 * k
+    if name == "pack":
+        return 8 * k + 8 * k + k  # pairs in, keys out, mark bytes
+    if name == "flags":
+        return 8 * k + k
+    if name == "append":
+        return k + k + 4 * k + 4 * per_launch["W"] + 16 * T
+    if name == "compact":
+        return 8 * per_launch["M"] + 16 * T + 4 * per_launch["FREED"]
+    return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=10**6)
+    ap.add_argument("--block-slots", type=int, default=16)
+    ap.add_argument("--scale", type=int, default=20)
+    ap.add_argument("--edges", type=int, default=1 << 24)
+    ap.add_argument("--queries", type=int, default=5, help="timed query batches")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (HBM counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    if args.copy_calibration:
+        x = torch.ones(1 << 28, dtype=torch.int32, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4,
+                          "launches": 3}))
+        return
+
+    from paper_2306_08252_amd import graphvine as gv
+    from paper_2306_08252_amd import inputs as I
+    from paper_2306_08252_amd import inputs_torch as T
+
+    dev = torch.device("cuda:0")
+    k, B = args.batch, args.block_slots
+    log(f"generating R-MAT 2^{args.scale} / {args.edges} edges on the GPU")
+    w = T.RmatWorkload(args.scale, args.edges, device=dev)
+    n = w.num_vertices
+    nsteps = args.warmup + 1 + args.steps
+    ins = [w.insert_batch(k, j) for j in range(nsteps)]
+    dels = [w.delete_batch(k, j) for j in range(nsteps)]
+    qry = [w.query_batch(k, j) for j in range(args.queries + 1)]
+    torch.cuda.synchronize()
+
+    # ---- bulk build (init edges/s): one warm-up build, then the timed one
+    g0 = gv.Graph(n, w.src, w.dst, block_slots=B, device=dev)
+    g0.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = gv.Graph(n, w.src, w.dst, block_slots=B, device=dev)
+    torch.cuda.synchronize()
+    init_s = time.perf_counter() - t0
+    log(f"init {init_s * 1e3:.2f} ms")
+
+    h = g.h
+    for j in range(args.warmup):
+        gv.gv_insert_edges(h, *ins[j], dev, stats=False)
+        gv.gv_delete_edges(h, *dels[j], dev, stats=False)
+    torch.cuda.synchronize()
+
+    # ---- pilot step (untimed): every kernel timed, to find the dominant one
+    gv.gv_profile_enable(h, True)
+    gv.gv_profile_only(h, None)
+    gv.gv_profile_reset(h)
+    j = args.warmup
+    gv.gv_insert_edges(h, *ins[j], dev, stats=False)
+    gv.gv_delete_edges(h, *dels[j], dev, stats=False)
+    torch.cuda.synchronize()
+    names = ["pack", "sort_hist", "sort_scatter", "scan_reduce", "scan_partials", "scan_down",
+             "flags", "segments", "expand", "probe_insert", "probe_delete", "plan_insert",
+             "plan", "grow", "append", "final_insert", "compact", "final_delete"]
+    pilot = {}
+    for nm in names:
+        cnt, ms = gv.gv_kernel_times(h, nm)
+        if cnt:
+            pilot[nm] = {"launches": cnt, "ms": round(ms, 4)}
+    dominant = max(pilot, key=lambda x: pilot[x]["ms"])
+    log("pilot step kernels:", json.dumps(pilot))
+
+    # ---- timed region: steps of insert + delete; events around the dominant
+    # kernel only
+    gv.gv_profile_only(h, dominant)
+    gv.gv_profile_reset(h)
+    c0 = g.counters()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(args.warmup + 1, nsteps):
+        gv.gv_insert_edges(h, *ins[j], dev, stats=False)
+        gv.gv_delete_edges(h, *dels[j], dev, stats=False)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    dom_launches, dom_ms = gv.gv_kernel_times(h, dominant)
+    gv.gv_profile_enable(h, False)
+    c1 = g.counters()
+    rc = g.sync()
+    if rc != 0:
+        raise RuntimeError(f"batch error during timed steps: {gv.gv_strerror(rc)}")
+    K = args.steps
+    value = 2 * k * K / elapsed
+
+    d = {key: (np.array(c1[key]) - np.array(c0[key])) for key in c1}
+    ins_T, del_T = d["touched"][0], d["touched"][1]
+    ins_S, del_S = d["scanned_slots"][0], d["scanned_slots"][1]
+    # bytes model M1 of the whole batch path (pairs read, one grouping pass,
+    # touched adjacency scan, slot writes, vertex records, block bookkeeping)
+    m1 = (2 * K * k) * (8 + 16) + 4 * (ins_S + del_S) + 4 * d["written_slots"] \
+        + 16 * (ins_T + del_T) + 8 * d["new_blocks"] + 8 * d["moved_slots"] \
+        + 4 * d["freed_blocks"]
+    pct_m1 = m1 / elapsed / (HBM_PEAK_GBS * 1e9)
+
+    # per-launch quantities of the dominant kernel's batch type
+    if dominant.endswith("delete") or dominant == "compact":
+        per = {"k": k, "T": del_T / K, "S": del_S / K, "NB": del_S / K / B,
+               "W": 0, "M": d["moved_slots"] / K, "FREED": d["freed_blocks"] / K}
+    else:
+        per = {"k": k, "T": ins_T / K, "S": ins_S / K, "NB": ins_S / K / B,
+               "W": d["written_slots"] / K, "M": 0, "FREED": 0}
+    if dominant.startswith("sort_"):
+        per["k"] = k
+    bpl = bytes_model(dominant, per)
+    avg_s = dom_ms / 1e3 / dom_launches if dom_launches else None
+    roof = None
+    if bpl is not None and avg_s:
+        ach = bpl / avg_s / 1e9
+        roof = {"bound": "hbm", "kernel": dominant, "achieved": round(ach, 2),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5),
+                "traffic": None, "bytes_per_launch": int(bpl),
+                "avg_launch_us": round(avg_s * 1e6, 3), "launches": dom_launches}
+
+    # ---- queries, in their own loop
+    gv.gv_edge_exists(h, *qry[0], dev)
+    torch.cuda.synchronize()
+    out = torch.empty(k, dtype=torch.uint8, device=dev)
+    t0 = time.perf_counter()
+    for j in range(1, args.queries + 1):
+        gv.gv_edge_exists(h, *qry[j], dev, out=out)
+    torch.cuda.synchronize()
+    q_rate = k * args.queries / (time.perf_counter() - t0)
+
+    # ---- adjacency of the largest hub, memory report
+    deg = torch.bincount(w.src.to(torch.int64), minlength=n)
+    hub = int(torch.argmax(deg))
+    gv.gv_get_adjacency(h, hub, dev)
+    t0 = time.perf_counter()
+    adj = gv.gv_get_adjacency(h, hub, dev)
+    adj_ms = (time.perf_counter() - t0) * 1e3
+    mem = g.memory_used()
+
+    # ---- vertex batches of 10^4: delete then re-insert the same ids
+    vids = torch.from_numpy(
+        (I.splitmix64(I.stream_seed("bench-vertices"), 10**4) % np.uint64(n))
+        .astype(np.uint32).view(np.int32)).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    vdel = g.delete_vertices(vids)
+    vdel_ms = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    vins = g.insert_vertices(vids)
+    vins_ms = (time.perf_counter() - t0) * 1e3
+    g.close()
+
+    # ---- CPU oracle baseline on a quarter of the sources
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import pyoracle as O
+        src_np = w.src.cpu().numpy().view(np.uint32)
+        dst_np = w.dst.cpu().numpy().view(np.uint32)
+        keep_v = (I.mix64(np.arange(n, dtype=np.uint64)) & np.uint64(3)) == 0
+        sel = keep_v[src_np]
+        o = O.OracleGraph(n, src_np[sel], dst_np[sel], block_slots=B)
+        pairs = 0
+        t0 = time.perf_counter()
+        for j in range(min(2, args.steps)):
+            jj = args.warmup + 1 + j
+            for batch, fn in ((ins[jj], o.insert_edges), (dels[jj], o.delete_edges)):
+                bs = batch[0].cpu().numpy().view(np.uint32)
+                bd = batch[1].cpu().numpy().view(np.uint32)
+                m = keep_v[bs]
+                fn(bs[m], bd[m])
+                pairs += int(m.sum())
+        cpu_s = time.perf_counter() - t0
+        o.close()
+        cpu = {"value": round(pairs / cpu_s, 1), "unit": "edges/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"{min(2, args.steps)} insert + delete batch pairs whose source "
+                         f"hashes to 0 mod 4 ({pairs} pairs) against the graph restricted "
+                         f"to those sources ({int(sel.sum())} edges)"}
+
+    out = {
+        "metric": "batch insert/delete edges/s + % HBM peak; init edges/s; served p50/p99 latency",
+        "value": round(value, 1),
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / K * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic (seeded R-MAT, drawn on the GPU)",
+        "config": {"workload": f"rmat{args.scale} {args.edges} edges, B={B}, insert+delete "
+                               f"batches of {k}", "vertices": n, "edges": args.edges,
+                   "batch": k, "block_slots": B},
+        "pct_hbm_m1": round(pct_m1, 5),
+        "m1_bytes_per_step": int(m1 / K),
+        "init_edges_per_s": round(args.edges / init_s, 1),
+        "init_ms": round(init_s * 1e3, 3),
+        "query_edges_per_s": round(q_rate, 1),
+        "adjacency_hub": {"vertex": hub, "degree": int(adj.numel()), "ms": round(adj_ms, 3)},
+        "vertex_delete_1e4": {"ms": round(vdel_ms, 3), "stats": vdel},
+        "vertex_insert_1e4": {"ms": round(vins_ms, 3), "stats": vins},
+        "memory": {"live_bytes": mem["live_bytes"], "blocks_in_use": mem["blocks_in_use"],
+                   "num_edges": mem["num_edges"]},
+        "served_p50_p99": None,
+        "pilot_kernels_ms": pilot,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

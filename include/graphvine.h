@@ -105,15 +105,16 @@ typedef struct {
 } gv_info;
 
 /* Cumulative work counters (since init) used by the benchmark's bytes model.
- * Batch counters count every entry handed to insert/delete/query calls. */
+ * Index 0 = insert, 1 = delete, 2 = query batches. */
 typedef struct {
-    uint64_t batches;          /* edge batches (insert + delete + query)        */
-    uint64_t pairs;            /* pairs handed in                               */
-    uint64_t touched_vertices; /* distinct valid sources over all batches       */
-    uint64_t scanned_slots;    /* block-granular slots of touched adjacencies   */
+    uint64_t batches[3];       /* edge batches handed in                        */
+    uint64_t pairs[3];         /* pairs handed in                               */
+    uint64_t touched[3];       /* distinct valid sources, summed over batches   */
+    uint64_t scanned_slots[3]; /* block-granular slots of touched adjacencies   */
     uint64_t new_blocks;       /* blocks taken from the pool                    */
     uint64_t freed_blocks;     /* blocks returned to the pool                   */
-    uint64_t written_slots;    /* slots written by appends and compaction moves */
+    uint64_t written_slots;    /* slots written by appends                      */
+    uint64_t moved_slots;      /* slots moved by delete compaction              */
 } gv_counters;
 
 /* Build a graph from a COO edge list (Sec. 4.3 "initialization", Sec. 5.2
@@ -192,6 +193,9 @@ int gv_get_counters(gv_graph* g, gv_counters* out); /* synchronous */
  * the kernel named `name`, the number of launches and their summed duration
  * in milliseconds since the last reset (synchronous). */
 int gv_profile_enable(gv_graph* g, int enable);
+/* Restrict timing to launches of one kernel name (NULL or "" = all), so that a
+ * timed region carries events around that kernel only. */
+int gv_profile_only(gv_graph* g, const char* name);
 int gv_profile_reset(gv_graph* g);
 int gv_kernel_times(gv_graph* g, const char* name, uint64_t* launches,
                     double* total_ms);

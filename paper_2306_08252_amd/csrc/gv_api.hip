@@ -262,13 +262,16 @@ int gv_get_counters(gv_graph* g, gv_counters* out) {
     return guarded(g, [&] {
         read_counters(g);
         const DevCounters& c = *g->hctr;
-        out->batches = c.c_batches;
-        out->pairs = c.c_pairs;
-        out->touched_vertices = c.c_touched;
-        out->scanned_slots = c.c_scanned;
+        for (int k = 0; k < 3; ++k) {
+            out->batches[k] = c.c_batches[k];
+            out->pairs[k] = c.c_pairs[k];
+            out->touched[k] = c.c_touched[k];
+            out->scanned_slots[k] = c.c_scanned[k];
+        }
         out->new_blocks = c.c_new_blocks;
         out->freed_blocks = c.c_freed_blocks;
         out->written_slots = c.c_written;
+        out->moved_slots = c.c_moved;
     });
 }
 
@@ -277,6 +280,14 @@ int gv_profile_enable(gv_graph* g, int enable) {
     return guarded(g, [&] {
         g->ctx.collect();
         g->ctx.prof = enable != 0;
+    });
+}
+
+int gv_profile_only(gv_graph* g, const char* name) {
+    if (!g) return GV_EINVAL;
+    return guarded(g, [&] {
+        g->ctx.collect();
+        g->ctx.only = name ? name : "";
     });
 }
 

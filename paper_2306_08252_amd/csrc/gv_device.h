@@ -59,8 +59,8 @@ struct DevCounters {
     // statistics of the last batch
     unsigned long long st_applied, st_rejected, st_dups;
     // cumulative work counters
-    unsigned long long c_batches, c_pairs, c_touched, c_scanned, c_new_blocks,
-        c_freed_blocks, c_written;
+    unsigned long long c_batches[3], c_pairs[3], c_touched[3], c_scanned[3];
+    unsigned long long c_new_blocks, c_freed_blocks, c_written, c_moved;
     // verification
     unsigned long long live_edges;     // edges stored
     unsigned long long checksum, edges, violations;

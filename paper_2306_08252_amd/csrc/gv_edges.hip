@@ -170,7 +170,7 @@ struct ItemIn {
 
 __global__ __launch_bounds__(kThreads) void k_expand(GraphView g, const uint32_t* t_vtx,
                                                      const uint32_t* t_items, uint64_t n,
-                                                     uint2* items) {
+                                                     uint2* items, int mode) {
     __shared__ unsigned long long lds[kWaves];
     const uint64_t t = thread_index();
     const uint32_t nT = g.ctr->n_T;
@@ -183,8 +183,12 @@ __global__ __launch_bounds__(kThreads) void k_expand(GraphView g, const uint32_t
         slots = (unsigned long long)nblocks(g, d) << g.log2B;
     }
     slots = block_sum(slots, lds);
-    if (threadIdx.x == 0 && slots) atomicAdd(&g.ctr->c_scanned, slots);
-    if (t == 0) g.ctr->c_touched += nT;
+    if (threadIdx.x == 0 && slots) atomicAdd(&g.ctr->c_scanned[mode], slots);
+    if (t == 0) {
+        g.ctr->c_touched[mode] += nT;
+        g.ctr->c_batches[mode] += 1;
+        g.ctr->c_pairs[mode] += n;
+    }
 }
 
 // One wave per work item: lanes stream consecutive slots of one adjacency and
@@ -316,8 +320,6 @@ __global__ void k_plan(GraphView g, uint64_t n, int sticky) {
     c->st_applied = c->sum_a;
     c->st_rejected = n - c->n_valid;
     c->st_dups = c->n_valid - c->n_uniq;
-    c->c_batches += 1;
-    c->c_pairs += n;
     c->c_new_blocks += N;
     c->c_written += c->sum_a;
     c->live_edges += c->sum_a;
@@ -446,6 +448,7 @@ __global__ __launch_bounds__(kThreads) void k_compact(GraphView g, const uint8_t
     const uint32_t lane = lane_id();
     const uint32_t nw = gridDim.x * kWaves;
     const unsigned long long fbase = c->free_cnt;
+    unsigned long long moved = 0;
     for (uint32_t t = global_wave(); t < nT; t += nw) {
         const uint32_t lo = t_start[t], hi = t_start[t + 1];
         const uint32_t r = b[hi] - b[lo];
@@ -485,6 +488,7 @@ __global__ __launch_bounds__(kThreads) void k_compact(GraphView g, const uint8_t
             }
             ns += popc64(m);
         }
+        moved += ns;
         const uint32_t nb0 = nblocks(g, d), nb1 = nblocks(g, dn);
         const unsigned long long pb = fbase + t_need[t];
         for (uint32_t j = nb1 + lane; j < nb0; j += 64)
@@ -496,6 +500,7 @@ __global__ __launch_bounds__(kThreads) void k_compact(GraphView g, const uint8_t
             g.vt[v] = nr;
         }
     }
+    if (lane == 0 && moved) atomicAdd(&g.ctr->c_moved, moved);
 }
 
 __global__ void k_final_del(GraphView g, uint64_t n) {
@@ -504,8 +509,6 @@ __global__ void k_final_del(GraphView g, uint64_t n) {
     c->st_applied = c->sum_a;
     c->st_rejected = n - c->n_valid;
     c->st_dups = c->n_valid - c->n_uniq;
-    c->c_batches += 1;
-    c->c_pairs += n;
     c->c_freed_blocks += c->sum_b;
     c->live_edges -= c->sum_a;
 }
@@ -515,10 +518,6 @@ __global__ __launch_bounds__(kThreads) void k_answer(GraphView g, const uint32_t
                                                      const uint8_t* mark, uint64_t n,
                                                      uint8_t* out) {
     const uint64_t i = thread_index();
-    if (i == 0) {
-        g.ctr->c_batches += 1;
-        g.ctr->c_pairs += n;
-    }
     if (i >= n) return;
     out[vals[i]] = i < g.ctr->n_valid ? mark[i] : (uint8_t)0;
 }
@@ -570,7 +569,7 @@ void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t*
     scan_excl<uint32_t>(c, ItemIn{v, A.t_vtx}, ArrOut<uint32_t>{A.t_items}, n + 1, A.partial,
                         &v.ctr->n_items);
     c.launch("expand", k_expand, grid, kThreads, v, (const uint32_t*)A.t_vtx,
-             (const uint32_t*)A.t_items, n, A.items);
+             (const uint32_t*)A.t_items, n, A.items, (int)mode);
     const uint64_t pgrid = std::min<uint64_t>(div_up(icap, kWaves), 2048);
     const uint64_t tgrid = std::min<uint64_t>(div_up(n, kWaves), 2048);
 

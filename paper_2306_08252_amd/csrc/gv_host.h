@@ -31,6 +31,7 @@ inline void hip_check(hipError_t e, const char* what) {
 struct Ctx {
     hipStream_t stream = nullptr;
     bool prof = false;
+    std::string only;  // when non-empty, only launches of this name are timed
     struct Rec {
         const char* name;
         hipEvent_t e0, e1;
@@ -92,14 +93,15 @@ struct Ctx {
                 Args... args) {
         if (grid == 0) return;
         if (grid > 0x7fffffffull) fail(GV_EINVAL, "grid too large");
+        const bool timed = prof && (only.empty() || only == name);
         hipEvent_t e0 = nullptr;
-        if (prof) {
+        if (timed) {
             e0 = event();
             hip_check(hipEventRecord(e0, stream), "hipEventRecord");
         }
         hipLaunchKernelGGL(kernel, dim3((uint32_t)grid), dim3(block), 0, stream, args...);
         hip_check(hipGetLastError(), name);
-        if (prof) {
+        if (timed) {
             hipEvent_t e1 = event();
             hip_check(hipEventRecord(e1, stream), "hipEventRecord");
             recs.push_back({name, e0, e1});

@@ -53,12 +53,17 @@ class gv_info(C.Structure):
 
 
 class gv_counters(C.Structure):
-    _fields_ = [(n, C.c_uint64) for n in (
-        "batches", "pairs", "touched_vertices", "scanned_slots", "new_blocks",
-        "freed_blocks", "written_slots")]
+    _fields_ = [("batches", C.c_uint64 * 3), ("pairs", C.c_uint64 * 3),
+                ("touched", C.c_uint64 * 3), ("scanned_slots", C.c_uint64 * 3),
+                ("new_blocks", C.c_uint64), ("freed_blocks", C.c_uint64),
+                ("written_slots", C.c_uint64), ("moved_slots", C.c_uint64)]
 
     def as_dict(self):
-        return {n: getattr(self, n) for n, _ in self._fields_}
+        out = {}
+        for n, _ in self._fields_:
+            v = getattr(self, n)
+            out[n] = list(v) if not isinstance(v, int) else v
+        return out
 
 
 _lib = None
@@ -90,6 +95,7 @@ def lib():
             "gv_get_counters": [vp, C.POINTER(gv_counters)],
             "gv_profile_enable": [vp, C.c_int],
             "gv_profile_reset": [vp],
+            "gv_profile_only": [vp, C.c_char_p],
             "gv_kernel_times": [vp, C.c_char_p, u64p, C.POINTER(C.c_double)],
             "gv_set_stream": [vp, vp],
             "gv_sync": [vp],
@@ -264,6 +270,11 @@ def gv_get_counters(g):
 
 def gv_profile_enable(g, enable=True):
     _check(lib().gv_profile_enable(C.c_void_p(g), int(bool(enable))), "gv_profile_enable")
+
+
+def gv_profile_only(g, name=None):
+    _check(lib().gv_profile_only(C.c_void_p(g), name.encode() if name else None),
+           "gv_profile_only")
 
 
 def gv_profile_reset(g):
