@@ -271,7 +271,9 @@ int gv_get_counters(gv_graph* g, gv_counters* out) {
         out->new_blocks = c.c_new_blocks;
         out->freed_blocks = c.c_freed_blocks;
         out->written_slots = c.c_written;
-        out->moved_slots = c.c_moved;
+        unsigned long long moved = 0;
+        for (int k = 0; k < 64; ++k) moved += c.stripe[k][0];
+        out->moved_slots = moved;
     });
 }
 
@@ -327,6 +329,7 @@ int gv_sync(gv_graph* g) {
     int code = GV_OK;
     int rc = guarded(g, [&] {
         read_counters(g);
+        if (g->hctr->err_wait) fail(GV_EDEVICE, "a look-back wait ran out");
         code = (int)g->hctr->err_sticky;
         if (code) {
             set_u32(g, &g->v.ctr->err_sticky, 0);

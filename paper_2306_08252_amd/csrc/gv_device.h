@@ -54,13 +54,18 @@ struct DevCounters {
     uint32_t n_valid, n_T, n_items, n_aux;
     unsigned long long n_uniq;
     uint32_t sum_a, sum_b;             // scan totals of the current batch
-    // errors: err_batch is reset per batch, err_sticky accumulates
-    uint32_t err_batch, err_sticky;
+    // errors: err_batch is reset per batch, err_sticky accumulates; err_wait
+    // is set if a bounded look-back wait ever ran out
+    uint32_t err_batch, err_sticky, err_wait, n_big;
+    // totals of the single-pass scans of the current batch
+    unsigned long long tot[8];
     // statistics of the last batch
     unsigned long long st_applied, st_rejected, st_dups;
     // cumulative work counters
     unsigned long long c_batches[3], c_pairs[3], c_touched[3], c_scanned[3];
     unsigned long long c_new_blocks, c_freed_blocks, c_written, c_moved;
+    // striped accumulators (one 128-byte line each) for per-wave counts
+    unsigned long long stripe[64][16];
     // verification
     unsigned long long live_edges;     // edges stored
     unsigned long long checksum, edges, violations;

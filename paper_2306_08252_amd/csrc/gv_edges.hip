@@ -2,24 +2,30 @@
 //
 // One pipeline serves the three operations (GraphVine Sec. 4.5-4.6, Alg. 1-3,
 // re-designed for wave64):
-//   pack      validate each pair against the activity bitmap and encode it as
-//             a key (src << L) | dst; invalid pairs get a key above all valid
-//             ones.  Queries also carry their input position.
-//   sort      stable LSD radix sort of the keys on 2L+1 bits: the batch is
-//             grouped by source and ordered by destination inside each source
-//             segment (replaces the host CSR conversion of Sec. 4.3).
-//   flags     segment heads (first key of a source) and first occurrences.
-//   segments  the touched sources T with their segment start in the batch.
-//   items     each touched adjacency is cut into work items of kChunk slots.
-//   probe     one wave per work item streams the adjacency slots; each lane
-//             binary-searches its slot value in the source's sorted segment.
-//             Insert: marks batch entries that already exist (set semantics).
-//             Delete: marks hits, remembers their slot and tombstones it.
-//             Query:  marks every query equal to a stored edge.
-//   insert:   keep = first occurrence and not present; scan; per-source block
-//             demand and directory growth; one-thread allocation plan with a
-//             capacity check before any write (all-or-nothing); blocks popped
-//             from the free-list top first, then the bump pointer (the
+//   begin     clear the batch's look-back state.
+//   pack      single-pass scan: validate each pair against the activity
+//             bitmap and write the valid ones, compacted, as keys
+//             (src << L) | dst (queries also carry their input position and
+//             answer invalid pairs with 0 right away).
+//   sort      onesweep LSD radix sort of the valid keys on 2L bits: the batch
+//             is grouped by source and ordered by destination inside each
+//             source segment (the paper's host CSR conversion, Sec. 4.3).
+//   segments  single-pass scan over the sorted keys: segment heads give the
+//             touched sources T and their segment starts; first occurrences
+//             give the distinct pairs.
+//   items     single-pass scan over T: each touched adjacency is cut into
+//             work items of kChunk slots, written as self-contained 32-byte
+//             descriptors (slot range, batch segment, block directory).
+//   probe     16-lane groups, four per wave, each own one work item: the
+//             segment's destinations are staged in LDS, lanes stream slots
+//             (directory entry, then slot) and binary-search each slot value.
+//             Insert: mark batch entries that already exist (set semantics).
+//             Delete: mark hits, remember their slot, tombstone the slot.
+//             Query:  mark every query equal to a stored edge.
+//   insert:   keep = first occurrence and not present (scan); per-source
+//             block demand and directory growth; a one-thread plan checks
+//             capacity before any state is written (all-or-nothing); blocks
+//             come from the free-list top first, then the bump pointer (the
 //             prefix-sum pop of Sec. 4.5.1, without atomics); append.
 //   delete:   per-source compaction pairs the holes below the new degree with
 //             the survivors above it, by rank; emptied blocks are pushed on
@@ -33,6 +39,26 @@
 namespace gv {
 
 constexpr uint8_t kHead = 1, kUniq = 2;
+constexpr int kGroup = 16;                     // lanes per work item
+constexpr int kGroupsPerWave = 64 / kGroup;
+constexpr int kStage = 128;                    // segment entries staged in LDS
+constexpr int kUnroll = 4;                     // slots per lane per step
+constexpr uint32_t kBigR = 256;                // deletes per source handled by a workgroup
+
+// scan-total slots in DevCounters::tot
+enum { kTotValid = 0, kTotSeg = 1, kTotItems = 2, kTotA = 3, kTotB = 4 };
+
+// self-contained work item: slots [s0, s1) of vertex v, batch segment [lo, hi)
+struct alignas(16) Item {
+    uint32_t s0, s1, lo, hi;
+    uint32_t v, dir, dcls, pad;
+};
+
+// per-source compaction descriptor (delete)
+struct alignas(16) CDesc {
+    uint32_t lo, hi, r, v;
+    uint32_t deg, dir, dcls, need;
+};
 
 struct BatchArrays {
     uint64_t* keys0;
@@ -41,24 +67,27 @@ struct BatchArrays {
     uint32_t* vals1;
     uint8_t* flags;
     uint8_t* mark;
-    uint32_t* a;        // n+1: exclusive count of segment heads
+    uint32_t* a;        // segment index of each valid key
     uint32_t* b;        // n+1: exclusive count of kept (insert) / found (delete)
     uint32_t* hitpos;   // delete: slot index of each hit
     uint32_t* holes;    // delete: hole slots per segment
     uint32_t* t_vtx;    // touched source per segment
     uint32_t* t_start;  // n+1: segment start; t_start[n_T] = n_valid
-    uint32_t* t_items;  // n+1: exclusive scan of work items per segment
-    uint32_t* t_need;   // n+1: blocks needed (insert) / freed (delete), scanned
+    uint32_t* t_need;   // n+1: blocks needed (insert), scanned
     uint32_t* t_dreq;   // insert: requested directory class or kNoDir
     uint32_t* t_drank;  // insert: rank among requests of that class
     uint32_t* t_dold;   // insert: replaced directory segment offset
     uint32_t* t_doldc;  // insert: replaced directory segment class or kNoDir
-    uint2* items;       // (segment, chunk) work items
-    uint32_t* partial;  // scan partials
-    SortScratch sort;
+    CDesc* cdesc;       // delete: compaction descriptors
+    uint32_t* big;      // delete: sources with more than kBigR hits
+    Item* items;        // work items
+    unsigned long long* part;  // scan partials
+    uint32_t* state;    // zeroed look-back state of the sort
+    uint64_t state_words;
 };
 
-static void carve_batch(Carver& cv, BatchArrays& A, uint64_t n, uint64_t icap, EdgeMode mode) {
+static void carve_batch(Carver& cv, BatchArrays& A, uint64_t n, uint64_t icap, EdgeMode mode,
+                        int bits) {
     A = BatchArrays{};
     A.keys0 = cv.take<uint64_t>(n);
     A.keys1 = cv.take<uint64_t>(n);
@@ -68,15 +97,16 @@ static void carve_batch(Carver& cv, BatchArrays& A, uint64_t n, uint64_t icap, E
     }
     A.flags = cv.take<uint8_t>(n);
     A.mark = cv.take<uint8_t>(n);
-    A.a = cv.take<uint32_t>(n + 1);
+    A.a = cv.take<uint32_t>(n);
     A.b = cv.take<uint32_t>(n + 1);
     if (mode == kDelete) {
         A.hitpos = cv.take<uint32_t>(n);
         A.holes = cv.take<uint32_t>(n);
+        A.cdesc = cv.take<CDesc>(n);
+        A.big = cv.take<uint32_t>(n);
     }
     A.t_vtx = cv.take<uint32_t>(n);
     A.t_start = cv.take<uint32_t>(n + 1);
-    A.t_items = cv.take<uint32_t>(n + 1);
     A.t_need = cv.take<uint32_t>(n + 1);
     if (mode == kInsert) {
         A.t_dreq = cv.take<uint32_t>(n);
@@ -84,9 +114,10 @@ static void carve_batch(Carver& cv, BatchArrays& A, uint64_t n, uint64_t icap, E
         A.t_dold = cv.take<uint32_t>(n);
         A.t_doldc = cv.take<uint32_t>(n);
     }
-    A.items = cv.take<uint2>(icap);
-    A.partial = cv.take<uint32_t>(scan_partials_needed(n + 1));
-    carve_sort<uint64_t>(cv, A.sort, n);
+    A.items = cv.take<Item>(icap);
+    A.part = cv.take<unsigned long long>(scan2_parts(n + 1));
+    A.state_words = os_words(n, bits);
+    A.state = cv.take<uint32_t>(A.state_words);
 }
 
 __device__ __forceinline__ uint64_t thread_index() {
@@ -97,136 +128,265 @@ __device__ __forceinline__ uint32_t global_wave() {
     return (uint32_t)(((uint64_t)blockIdx.x * kThreads + threadIdx.x) >> 6);
 }
 
-// ------------------------------------------------------------------ common
-__global__ __launch_bounds__(kThreads) void k_pack(GraphView g, const uint32_t* src,
-                                                   const uint32_t* dst, uint64_t n,
-                                                   uint64_t* keys, uint32_t* vals, uint8_t* mark) {
-    const uint64_t i = thread_index();
-    if (i == 0) {
+// ------------------------------------------------------------------ begin
+__global__ __launch_bounds__(kThreads) void k_begin(GraphView g, uint32_t* state, uint64_t words) {
+    const uint64_t stride = (uint64_t)gridDim.x * kThreads;
+    for (uint64_t i = thread_index(); i < words; i += stride) state[i] = 0;
+    if (thread_index() == 0) {
         g.ctr->err_batch = 0;
-        g.ctr->n_uniq = 0;
+        g.ctr->n_big = 0;
+        for (int k = 0; k < 8; ++k) g.ctr->tot[k] = 0;
     }
-    if (i >= n) return;
-    const uint32_t s = src[i], d = dst[i];
-    const bool ok = is_active(g, s) && is_active(g, d);
-    keys[i] = ok ? (((uint64_t)s << g.L) | d) : (1ull << (2 * g.L));
-    if (vals) vals[i] = (uint32_t)i;
-    mark[i] = 0;
 }
 
-__global__ __launch_bounds__(kThreads) void k_flags(GraphView g, const uint64_t* keys, uint64_t n,
-                                                    uint8_t* flags) {
-    __shared__ unsigned long long lds[kWaves];
-    const uint64_t i = thread_index();
-    unsigned long long uniq_count = 0;
-    if (i < n) {
-        const uint64_t invalid = 1ull << (2 * g.L);
-        const uint64_t k = keys[i];
-        const bool valid = k < invalid;
-        const uint64_t prev = i ? keys[i - 1] : 0;
-        const bool head = valid && (i == 0 || (k >> g.L) != (prev >> g.L));
-        const bool uniq = valid && (i == 0 || k != prev);
-        flags[i] = (head ? kHead : 0) | (uniq ? kUniq : 0);
-        uniq_count = uniq;
-        const bool next_valid = (i + 1 < n) && keys[i + 1] < invalid;
-        if (valid && !next_valid) g.ctr->n_valid = (uint32_t)(i + 1);
-        if (i == 0 && !valid) g.ctr->n_valid = 0;
+// ------------------------------------------------------------------ pack
+struct PackIn {
+    GraphView g;
+    const uint32_t* src;
+    const uint32_t* dst;
+    __device__ unsigned long long operator()(uint64_t i) const {
+        return (is_active(g, src[i]) && is_active(g, dst[i])) ? 1ull : 0ull;
     }
-    unsigned long long c = block_sum(uniq_count, lds);
-    if (threadIdx.x == 0 && c) atomicAdd(&g.ctr->n_uniq, c);
-}
-
-struct HeadIn {
-    const uint8_t* flags;
-    uint64_t n;
-    __device__ uint32_t operator()(uint64_t i) const { return i < n ? (flags[i] & kHead) : 0u; }
 };
 
-__global__ __launch_bounds__(kThreads) void k_segments(GraphView g, const uint64_t* keys,
-                                                       const uint8_t* flags, const uint32_t* a,
-                                                       uint64_t n, uint32_t* t_vtx,
-                                                       uint32_t* t_start) {
-    const uint64_t i = thread_index();
-    if (i >= n) return;
-    const uint32_t nv = g.ctr->n_valid;
-    if (i == 0 && nv == 0) t_start[0] = 0;
-    if (i < nv && (flags[i] & kHead)) {
-        const uint32_t t = a[i];
-        t_vtx[t] = (uint32_t)(keys[i] >> g.L);
-        t_start[t] = (uint32_t)i;
+struct PackOut {
+    GraphView g;
+    const uint32_t* src;
+    const uint32_t* dst;
+    uint64_t* keys;
+    uint32_t* vals;     // queries: input position of each valid key
+    uint8_t* answer;    // queries: invalid pairs are answered here
+    uint8_t* mark;
+    __device__ void operator()(uint64_t i, unsigned long long pos) const {
+        const uint32_t s = src[i], d = dst[i];
+        mark[i] = 0;
+        if (is_active(g, s) && is_active(g, d)) {
+            keys[pos] = ((uint64_t)s << g.L) | d;
+            if (vals) vals[pos] = (uint32_t)i;
+        } else if (answer) {
+            answer[i] = 0;
+        }
     }
-    if (nv > 0 && i == nv - 1) t_start[g.ctr->n_T] = nv;
-}
+};
 
+// ------------------------------------------------------------------ segments
+struct SegIn {
+    const uint64_t* keys;
+    const unsigned long long* n_valid;
+    uint32_t L;
+    __device__ unsigned long long operator()(uint64_t i) const {
+        if (i >= *n_valid) return 0ull;
+        const uint64_t k = keys[i];
+        if (i == 0) return 1ull | (1ull << 32);
+        const uint64_t p = keys[i - 1];
+        const unsigned long long head = (k >> L) != (p >> L);
+        const unsigned long long uniq = k != p;
+        return head | (uniq << 32);
+    }
+};
+
+struct SegOut {
+    const uint64_t* keys;
+    const unsigned long long* n_valid;
+    uint32_t L;
+    uint8_t* flags;
+    uint32_t* a;
+    uint32_t* t_vtx;
+    uint32_t* t_start;
+    __device__ void operator()(uint64_t i, unsigned long long pre) const {
+        const uint64_t nv = *n_valid;
+        if (i >= nv) {
+            if (i == 0) t_start[0] = 0;
+            return;
+        }
+        const uint64_t k = keys[i];
+        bool head = true, uniq = true;
+        if (i > 0) {
+            const uint64_t p = keys[i - 1];
+            head = (k >> L) != (p >> L);
+            uniq = k != p;
+        }
+        const uint32_t t = (uint32_t)pre + (head ? 1u : 0u) - 1u;  // segment of key i
+        flags[i] = (head ? kHead : 0) | (uniq ? kUniq : 0);
+        a[i] = t;
+        if (head) {
+            t_vtx[t] = (uint32_t)(k >> L);
+            t_start[t] = (uint32_t)i;
+        }
+        if (i + 1 == nv) t_start[t + 1] = (uint32_t)nv;
+    }
+};
+
+// ------------------------------------------------------------------ items
 struct ItemIn {
     GraphView g;
     const uint32_t* t_vtx;
-    __device__ uint32_t operator()(uint64_t t) const {
-        if (t >= g.ctr->n_T) return 0u;
+    __device__ unsigned long long operator()(uint64_t t) const {
+        if (t >= (uint32_t)g.ctr->tot[kTotSeg]) return 0ull;
         const uint32_t d = g.vt[t_vtx[t]].deg;
-        return (d + kChunk - 1) / kChunk;
+        const unsigned long long items = (d + kChunk - 1) / kChunk;
+        return items | ((unsigned long long)nblocks(g, d) << 32);
     }
 };
 
-__global__ __launch_bounds__(kThreads) void k_expand(GraphView g, const uint32_t* t_vtx,
-                                                     const uint32_t* t_items, uint64_t n,
-                                                     uint2* items, int mode) {
-    __shared__ unsigned long long lds[kWaves];
-    const uint64_t t = thread_index();
-    const uint32_t nT = g.ctr->n_T;
-    unsigned long long slots = 0;
-    if (t < nT) {
-        const uint32_t d = g.vt[t_vtx[t]].deg;
-        const uint32_t cnt = (d + kChunk - 1) / kChunk;
-        const uint32_t base = t_items[t];
-        for (uint32_t c = 0; c < cnt; ++c) items[base + c] = make_uint2((uint32_t)t, c);
-        slots = (unsigned long long)nblocks(g, d) << g.log2B;
+struct ItemOut {
+    GraphView g;
+    const uint32_t* t_vtx;
+    const uint32_t* t_start;
+    Item* items;
+    __device__ void operator()(uint64_t t, unsigned long long pre) const {
+        if (t >= (uint32_t)g.ctr->tot[kTotSeg]) return;
+        const uint32_t v = t_vtx[t];
+        const VRec r = g.vt[v];
+        const uint32_t cnt = (r.deg + kChunk - 1) / kChunk;
+        const uint32_t base = (uint32_t)pre;
+        Item it;
+        it.lo = t_start[t];
+        it.hi = t_start[t + 1];
+        it.v = v;
+        it.dir = r.dir;
+        it.dcls = r.dcls;
+        it.pad = 0;
+        for (uint32_t c = 0; c < cnt; ++c) {
+            it.s0 = c * kChunk;
+            it.s1 = min(r.deg, it.s0 + kChunk);
+            items[base + c] = it;
+        }
     }
-    slots = block_sum(slots, lds);
-    if (threadIdx.x == 0 && slots) atomicAdd(&g.ctr->c_scanned[mode], slots);
-    if (t == 0) {
-        g.ctr->c_touched[mode] += nT;
-        g.ctr->c_batches[mode] += 1;
-        g.ctr->c_pairs[mode] += n;
+};
+
+// ------------------------------------------------------------------ probe
+// Group-level helpers: a group is kGroup consecutive lanes of a wave.
+__device__ __forceinline__ uint64_t group_mask(uint64_t m, uint32_t lane) {
+    const uint32_t g0 = lane & ~(uint32_t)(kGroup - 1);
+    return (m >> g0) & ((1ull << kGroup) - 1);
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int MODE>
+__device__ __forceinline__ void probe_load(const GraphView& g, const Item& I, uint32_t s,
+                                           uint32_t (&x)[kUnroll], uint64_t (&addr)[kUnroll]) {
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+        const uint32_t si = s + u * kGroup;
+        uint32_t blk = I.dir;
+        if (si < I.s1 && I.dcls != kNoDir) blk = g.dir[(uint64_t)I.dir + (si >> g.log2B)];
+        addr[u] = ((uint64_t)blk << g.log2B) + (si & (g.B - 1));
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+        const uint32_t si = s + u * kGroup;
+        x[u] = si < I.s1 ? g.pool[addr[u]] : kTomb;
     }
 }
 
-// One wave per work item: lanes stream consecutive slots of one adjacency and
-// binary-search them in the source's sorted batch segment.
 template <int MODE>
-__global__ __launch_bounds__(kThreads) void k_probe(GraphView g, const uint64_t* keys,
-                                                    const uint32_t* t_vtx, const uint32_t* t_start,
-                                                    const uint2* items, uint8_t* mark,
-                                                    uint32_t* hitpos) {
-    const uint32_t nitems = g.ctr->n_items;
-    const uint32_t lane = lane_id();
-    const uint32_t nw = gridDim.x * kWaves;
-    for (uint32_t it = global_wave(); it < nitems; it += nw) {
-        const uint2 item = items[it];
-        const uint32_t t = item.x;
-        const uint32_t v = t_vtx[t];
-        const VRec r = g.vt[v];
-        const uint32_t lo = t_start[t], hi = t_start[t + 1];
-        const uint32_t s0 = item.y * kChunk;
-        const uint32_t s1 = min(r.deg, s0 + kChunk);
-        const uint64_t vbase = (uint64_t)v << g.L;
-        for (uint32_t s = s0 + lane; s < s1; s += 64) {
-            const uint64_t addr = slot_addr(g, r, s);
-            const uint32_t x = g.pool[addr];
-            const uint64_t target = vbase | x;
-            const uint32_t pos = lower_bound(keys, lo, hi, target);
-            if (pos < hi && keys[pos] == target) {
-                if (MODE == kInsert) {
-                    mark[pos] = 1;
-                } else if (MODE == kDelete) {
-                    mark[pos] = 1;
-                    hitpos[pos] = s;
-                    g.pool[addr] = kTomb;
-                } else {
-                    for (uint32_t j = pos; j < hi && keys[j] == target; ++j) mark[j] = 1;
-                }
+__device__ __forceinline__ void probe_search(const GraphView& g, const Item& I, uint32_t s,
+                                             const uint32_t (&x)[kUnroll],
+                                             const uint64_t (&addr)[kUnroll], const uint32_t* st,
+                                             uint32_t ns, uint32_t shift, const uint64_t* keys,
+                                             uint8_t* mark, uint32_t* hitpos) {
+    const uint32_t len = I.hi - I.lo;
+    const uint64_t vbase = (uint64_t)I.v << g.L;
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+        const uint32_t si = s + u * kGroup;
+        if (si >= I.s1) continue;
+        // first sample >= x
+        uint32_t lo = 0, hi = ns;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (st[mid] < x[u]) lo = mid + 1;
+            else hi = mid;
+        }
+        uint32_t p;  // first segment position whose value is >= x
+        bool hit;
+        const uint64_t target = vbase | x[u];
+        if (shift == 0) {
+            p = lo;
+            hit = lo < ns && st[lo] == x[u];
+        } else {
+            // the answer lies in ((lo - 1) * stride, lo * stride]
+            uint32_t a = lo ? ((lo - 1) << shift) + 1 : 0;
+            uint32_t b = min(lo << shift, len);
+            while (a < b) {
+                const uint32_t mid = (a + b) >> 1;
+                if (keys[I.lo + mid] < target) a = mid + 1;
+                else b = mid;
+            }
+            p = a;
+            hit = a < len && keys[I.lo + a] == target;
+        }
+        if (hit) {
+            const uint32_t pos = I.lo + p;
+            if (MODE == kInsert) {
+                mark[pos] = 1;
+            } else if (MODE == kDelete) {
+                mark[pos] = 1;
+                hitpos[pos] = si;
+                g.pool[addr[u]] = kTomb;
+            } else {
+                for (uint32_t j = pos; j < I.hi && keys[j] == target; ++j) mark[j] = 1;
             }
         }
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_probe(GraphView g, const uint64_t* keys,
+                                                    const Item* items, uint8_t* mark,
+                                                    uint32_t* hitpos) {
+    __shared__ uint32_t stage[kWaves * kGroupsPerWave][kStage];
+    const uint32_t nitems = (uint32_t)g.ctr->tot[kTotItems];
+    const uint32_t lane = lane_id();
+    const uint32_t gl = lane & (kGroup - 1);
+    const uint32_t gid_local = (threadIdx.x >> 6) * kGroupsPerWave + (lane / kGroup);
+    uint32_t* st = stage[gid_local];
+    const uint32_t ngroups = gridDim.x * kWaves * kGroupsPerWave;
+    const uint64_t dmask = (1ull << g.L) - 1;
+    uint32_t it = global_wave() * kGroupsPerWave + lane / kGroup;
+    if (it >= nitems) return;
+    Item I = items[it];
+    while (true) {
+        const uint32_t itn = it + ngroups;
+        const Item In = items[min(itn, nitems - 1)];  // prefetch the next item
+        // slot loads of the first step go out before the segment is staged
+        uint32_t x[kUnroll];
+        uint64_t addr[kUnroll];
+        uint32_t s = I.s0 + gl;
+        probe_load<MODE>(g, I, s, x, addr);
+        const uint32_t len = I.hi - I.lo;
+        // LDS holds the segment (stride 1) or every stride-th entry of it
+        uint32_t shift = 0;
+        while (((len + (1u << shift) - 1) >> shift) > (uint32_t)kStage) ++shift;
+        const uint32_t ns = (len + (1u << shift) - 1) >> shift;  // <= kStage samples
+        for (uint32_t j = gl; j < ns; j += kGroup)
+            st[j] = (uint32_t)(keys[I.lo + (j << shift)] & dmask);
+        wave_lds_sync();
+        // ping-pong between two register sets: load step k+1, search step k
+        uint32_t x2[kUnroll];
+        uint64_t a2[kUnroll];
+        while (true) {
+            const bool more = s + kGroup * kUnroll - gl < I.s1;  // uniform in the group
+            if (more) probe_load<MODE>(g, I, s + kGroup * kUnroll, x2, a2);
+            probe_search<MODE>(g, I, s, x, addr, st, ns, shift, keys, mark, hitpos);
+            if (!more) break;
+            s += kGroup * kUnroll;
+            const bool more2 = s + kGroup * kUnroll - gl < I.s1;
+            if (more2) probe_load<MODE>(g, I, s + kGroup * kUnroll, x, addr);
+            probe_search<MODE>(g, I, s, x2, a2, st, ns, shift, keys, mark, hitpos);
+            if (!more2) break;
+            s += kGroup * kUnroll;
+        }
+        wave_lds_sync();
+        if (itn >= nitems) break;
+        it = itn;
+        I = In;
     }
 }
 
@@ -234,11 +394,16 @@ __global__ __launch_bounds__(kThreads) void k_probe(GraphView g, const uint64_t*
 struct KeepIn {
     const uint8_t* flags;
     const uint8_t* mark;
-    const DevCounters* ctr;
-    __device__ uint32_t operator()(uint64_t i) const {
-        if (i >= ctr->n_valid) return 0u;
-        return ((flags[i] & kUniq) && !mark[i]) ? 1u : 0u;
+    const unsigned long long* n_valid;
+    __device__ unsigned long long operator()(uint64_t i) const {
+        if (i >= *n_valid) return 0ull;
+        return ((flags[i] & kUniq) && !mark[i]) ? 1ull : 0ull;
     }
+};
+
+struct U32Out {
+    uint32_t* a;
+    __device__ void operator()(uint64_t i, unsigned long long v) const { a[i] = (uint32_t)v; }
 };
 
 __global__ __launch_bounds__(kThreads) void k_plan_ins(GraphView g, const uint32_t* t_vtx,
@@ -250,7 +415,7 @@ __global__ __launch_bounds__(kThreads) void k_plan_ins(GraphView g, const uint32
     if (threadIdx.x < kMaxClass) lcnt[threadIdx.x] = 0;
     __syncthreads();
     const uint64_t t = thread_index();
-    const uint32_t nT = g.ctr->n_T;
+    const uint32_t nT = (uint32_t)g.ctr->tot[kTotSeg];
     uint32_t cls = kNoDir, lrank = 0;
     if (t < nT) {
         const uint32_t kp = b[t_start[t + 1]] - b[t_start[t]];
@@ -276,14 +441,20 @@ __global__ __launch_bounds__(kThreads) void k_plan_ins(GraphView g, const uint32
 struct NeedIn {
     const uint32_t* t_need;
     const DevCounters* ctr;
-    __device__ uint32_t operator()(uint64_t t) const { return t < ctr->n_T ? t_need[t] : 0u; }
+    __device__ unsigned long long operator()(uint64_t t) const {
+        return t < (uint32_t)ctr->tot[kTotSeg] ? t_need[t] : 0ull;
+    }
 };
 
 // Allocation plan for the whole batch, one thread: capacity is checked
 // before any state is written, so a failing batch leaves the graph unchanged.
 __global__ void k_plan(GraphView g, uint64_t n, int sticky) {
     DevCounters* c = g.ctr;
-    const unsigned long long N = c->sum_b;
+    const unsigned long long nv = c->tot[kTotValid];
+    const unsigned long long nT = c->tot[kTotSeg] & 0xffffffffull;
+    const unsigned long long nuniq = c->tot[kTotSeg] >> 32;
+    const unsigned long long applied = c->tot[kTotA];
+    const unsigned long long N = c->tot[kTotB];
     const unsigned long long ff = N < c->free_cnt ? N : c->free_cnt;
     const unsigned long long fb = N - ff;
     bool ok = c->bump + fb <= g.cap_blocks;
@@ -296,6 +467,10 @@ __global__ void k_plan(GraphView g, uint64_t n, int sticky) {
         db += (unsigned long long)(req - dff) << k;
     }
     ok = ok && db <= g.dir_cap;
+    c->c_batches[kInsert] += 1;
+    c->c_pairs[kInsert] += n;
+    c->c_touched[kInsert] += nT;
+    c->c_scanned[kInsert] += (c->tot[kTotItems] >> 32) << g.log2B;
     if (!ok) {
         c->err_batch = GV_ENOMEM;
         if (sticky && !c->err_sticky) c->err_sticky = GV_ENOMEM;
@@ -317,12 +492,12 @@ __global__ void k_plan(GraphView g, uint64_t n, int sticky) {
     }
     c->dir_bump = db;
     c->dir_live += live;
-    c->st_applied = c->sum_a;
-    c->st_rejected = n - c->n_valid;
-    c->st_dups = c->n_valid - c->n_uniq;
+    c->st_applied = applied;
+    c->st_rejected = n - nv;
+    c->st_dups = nv - nuniq;
     c->c_new_blocks += N;
-    c->c_written += c->sum_a;
-    c->live_edges += c->sum_a;
+    c->c_written += applied;
+    c->live_edges += applied;
 }
 
 // One wave per touched source: grow its directory segment if needed (copy the
@@ -334,7 +509,7 @@ __global__ __launch_bounds__(kThreads) void k_grow(GraphView g, const uint32_t* 
                                                    uint32_t* t_doldc) {
     const DevCounters* c = g.ctr;
     if (c->err_batch) return;
-    const uint32_t nT = c->n_T;
+    const uint32_t nT = (uint32_t)c->tot[kTotSeg];
     const uint32_t lane = lane_id();
     const uint32_t nw = gridDim.x * kWaves;
     for (uint32_t t = global_wave(); t < nT; t += nw) {
@@ -382,10 +557,10 @@ __global__ __launch_bounds__(kThreads) void k_append(GraphView g, const uint64_t
                                                      const uint32_t* t_start) {
     if (g.ctr->err_batch) return;
     const uint64_t i = thread_index();
-    if (i >= g.ctr->n_valid) return;
+    if (i >= g.ctr->tot[kTotValid]) return;
     const uint8_t f = flags[i];
     if (!(f & kUniq) || mark[i]) return;
-    const uint32_t t = a[i] + (f & kHead) - 1;
+    const uint32_t t = a[i];
     const uint32_t v = t_vtx[t];
     const VRec r = g.vt[v];
     const uint32_t s = r.deg + (b[i] - b[t_start[t]]);
@@ -397,28 +572,44 @@ __global__ __launch_bounds__(kThreads) void k_final_ins(GraphView g, const uint3
                                                         const uint32_t* t_dreq,
                                                         const uint32_t* t_dold,
                                                         const uint32_t* t_doldc) {
-    if (g.ctr->err_batch) return;
+    __shared__ uint32_t lcnt[kMaxClass];
+    __shared__ uint32_t lbase[kMaxClass];
+    __shared__ unsigned long long lfreed;
+    if (threadIdx.x < kMaxClass) lcnt[threadIdx.x] = 0;
+    if (threadIdx.x == 0) lfreed = 0;
+    __syncthreads();
+    const bool ok = !g.ctr->err_batch;
     const uint64_t t = thread_index();
-    if (t >= g.ctr->n_T) return;
-    const uint32_t kp = b[t_start[t + 1]] - b[t_start[t]];
-    const uint32_t v = t_vtx[t];
-    if (kp) g.vt[v].deg += kp;
-    if (t_dreq[t] != kNoDir) {
-        const uint32_t oc = t_doldc[t];
-        if (oc != kNoDir) {
-            const uint32_t pos = atomicAdd(&g.ctr->dfree_cnt[oc], 1u);
-            g.dfree[g.dfree_base[oc] + pos] = t_dold[t];
-            atomicAdd(&g.ctr->dir_live, (unsigned long long)(-(long long)(1ull << oc)));
+    uint32_t oc = kNoDir, lrank = 0;
+    if (ok && t < (uint32_t)g.ctr->tot[kTotSeg]) {
+        const uint32_t kp = b[t_start[t + 1]] - b[t_start[t]];
+        const uint32_t v = t_vtx[t];
+        if (kp) g.vt[v].deg += kp;
+        if (t_dreq[t] != kNoDir) {
+            oc = t_doldc[t];
+            if (oc != kNoDir) {
+                lrank = atomicAdd(&lcnt[oc], 1u);
+                atomicAdd(&lfreed, 1ull << oc);
+            }
         }
     }
+    __syncthreads();
+    if (threadIdx.x < kMaxClass) {
+        const uint32_t c = lcnt[threadIdx.x];
+        lbase[threadIdx.x] = c ? atomicAdd(&g.ctr->dfree_cnt[threadIdx.x], c) : 0u;
+    }
+    if (threadIdx.x == 0 && lfreed)
+        atomicAdd(&g.ctr->dir_live, (unsigned long long)(-(long long)lfreed));
+    __syncthreads();
+    if (oc != kNoDir) g.dfree[g.dfree_base[oc] + lbase[oc] + lrank] = t_dold[t];
 }
 
 // ------------------------------------------------------------------ delete
 struct FoundIn {
     const uint8_t* mark;
-    const DevCounters* ctr;
-    __device__ uint32_t operator()(uint64_t i) const {
-        return i < ctr->n_valid ? (uint32_t)mark[i] : 0u;
+    const unsigned long long* n_valid;
+    __device__ unsigned long long operator()(uint64_t i) const {
+        return i < *n_valid ? (unsigned long long)mark[i] : 0ull;
     }
 };
 
@@ -427,90 +618,185 @@ struct FreedIn {
     const uint32_t* t_vtx;
     const uint32_t* t_start;
     const uint32_t* b;
-    __device__ uint32_t operator()(uint64_t t) const {
-        if (t >= g.ctr->n_T) return 0u;
+    __device__ unsigned long long operator()(uint64_t t) const {
+        if (t >= (uint32_t)g.ctr->tot[kTotSeg]) return 0ull;
         const uint32_t r = b[t_start[t + 1]] - b[t_start[t]];
-        if (!r) return 0u;
+        if (!r) return 0ull;
         const uint32_t d = g.vt[t_vtx[t]].deg;
         return nblocks(g, d) - nblocks(g, d - r);
     }
 };
 
-// One wave per touched source with hits: holes below the new degree (in
-// batch order) receive the survivors found above it (in slot order).
+struct FreedOut {
+    GraphView g;
+    const uint32_t* t_vtx;
+    const uint32_t* t_start;
+    const uint32_t* b;
+    CDesc* cd;
+    uint32_t* big;
+    __device__ void operator()(uint64_t t, unsigned long long pre) const {
+        if (t >= (uint32_t)g.ctr->tot[kTotSeg]) return;
+        CDesc c;
+        c.lo = t_start[t];
+        c.hi = t_start[t + 1];
+        c.r = b[c.hi] - b[c.lo];
+        c.v = t_vtx[t];
+        const VRec r = g.vt[c.v];
+        c.deg = r.deg;
+        c.dir = r.dir;
+        c.dcls = r.dcls;
+        c.need = (uint32_t)pre;
+        cd[t] = c;
+        if (c.r > kBigR) big[atomicAdd(&g.ctr->n_big, 1u)] = (uint32_t)t;
+    }
+};
+
+// 16-lane groups, one touched source each: holes below the new degree (in
+// batch order) receive the survivors found above it (in slot order); emptied
+// blocks go on the free list.
 __global__ __launch_bounds__(kThreads) void k_compact(GraphView g, const uint8_t* mark,
                                                       const uint32_t* hitpos, uint32_t* holes,
-                                                      const uint32_t* b, const uint32_t* t_vtx,
-                                                      const uint32_t* t_start,
-                                                      const uint32_t* t_need) {
+                                                      const CDesc* cdesc) {
     const DevCounters* c = g.ctr;
-    const uint32_t nT = c->n_T;
+    const uint32_t nT = (uint32_t)c->tot[kTotSeg];
     const uint32_t lane = lane_id();
-    const uint32_t nw = gridDim.x * kWaves;
+    const uint32_t gl = lane & (kGroup - 1);
+    const uint64_t below = (1ull << gl) - 1;
+    const uint32_t ngroups = gridDim.x * kWaves * kGroupsPerWave;
     const unsigned long long fbase = c->free_cnt;
     unsigned long long moved = 0;
-    for (uint32_t t = global_wave(); t < nT; t += nw) {
-        const uint32_t lo = t_start[t], hi = t_start[t + 1];
-        const uint32_t r = b[hi] - b[lo];
-        if (!r) continue;
-        const uint32_t v = t_vtx[t];
-        const VRec rec = g.vt[v];
-        const uint32_t d = rec.deg, dn = d - r;
+    for (uint32_t t = global_wave() * kGroupsPerWave + lane / kGroup; t < nT; t += ngroups) {
+        const CDesc D = cdesc[t];
+        if (!D.r || D.r > kBigR) continue;
+        const VRec rec{D.deg, D.dir, D.dcls, 0u};
+        const uint32_t d = D.deg, dn = d - D.r;
         uint32_t nh = 0;
-        for (uint32_t p0 = lo; p0 < hi; p0 += 64) {
-            const uint32_t p = p0 + lane;
+        for (uint32_t p0 = D.lo; p0 < D.hi; p0 += kGroup) {
+            const uint32_t p = p0 + gl;
             bool hole = false;
             uint32_t hp = 0;
-            if (p < hi && mark[p]) {
+            if (p < D.hi && mark[p]) {
                 hp = hitpos[p];
                 hole = hp < dn;
             }
-            const uint64_t m = ballot(hole);
-            if (hole) holes[lo + nh + rank_below(m)] = hp;
+            const uint64_t m = group_mask(ballot(hole), lane);
+            if (hole) holes[D.lo + nh + popc64(m & below)] = hp;
             nh += popc64(m);
         }
         __threadfence_block();
         uint32_t ns = 0;
-        for (uint32_t s0 = dn; s0 < d; s0 += 64) {
-            const uint32_t s = s0 + lane;
+        for (uint32_t s0 = dn; s0 < d; s0 += kGroup) {
+            const uint32_t s = s0 + gl;
             uint32_t x = kTomb;
             if (s < d) x = g.pool[slot_addr(g, rec, s)];
             const bool surv = x != kTomb;
-            const uint64_t m = ballot(surv);
+            const uint64_t m = group_mask(ballot(surv), lane);
             if (surv) {
                 // survivors above dn and holes below it are equal in number;
                 // the guards only keep a broken invariant from writing wild
-                const uint32_t q = ns + rank_below(m);
+                const uint32_t q = ns + popc64(m & below);
                 if (q < nh) {
-                    const uint32_t dest = holes[lo + q];
+                    const uint32_t dest = holes[D.lo + q];
                     if (dest < dn) g.pool[slot_addr(g, rec, dest)] = x;
                 }
             }
             ns += popc64(m);
         }
-        moved += ns;
+        moved += gl == 0 ? ns : 0;
         const uint32_t nb0 = nblocks(g, d), nb1 = nblocks(g, dn);
-        const unsigned long long pb = fbase + t_need[t];
-        for (uint32_t j = nb1 + lane; j < nb0; j += 64)
+        const unsigned long long pb = fbase + D.need;
+        for (uint32_t j = nb1 + gl; j < nb0; j += kGroup)
             g.free_stack[pb + (j - nb1)] = block_of(g, rec, j);
-        if (lane == 0) {
+        if (gl == 0) {
             VRec nr = rec;
             nr.deg = dn;
             if (nb1 == 0 && nr.dcls == kNoDir) nr.dir = 0;
-            g.vt[v] = nr;
+            g.vt[D.v] = nr;
         }
     }
-    if (lane == 0 && moved) atomicAdd(&g.ctr->c_moved, moved);
+    moved = wave_sum(moved);
+    if (lane == 0 && moved) atomicAdd(&g.ctr->stripe[global_wave() & 63][0], moved);
+}
+
+// One workgroup per source with more than kBigR hits (hubs), same pairing.
+__global__ __launch_bounds__(kThreads) void k_compact_big(GraphView g, const uint8_t* mark,
+                                                          const uint32_t* hitpos, uint32_t* holes,
+                                                          const CDesc* cdesc,
+                                                          const uint32_t* big) {
+    __shared__ uint32_t lds[kWaves];
+    const DevCounters* c = g.ctr;
+    const uint32_t nbig = c->n_big;
+    const unsigned long long fbase = c->free_cnt;
+    const uint32_t tid = threadIdx.x;
+    unsigned long long moved = 0;
+    for (uint32_t q = blockIdx.x; q < nbig; q += gridDim.x) {
+        const CDesc D = cdesc[big[q]];
+        const VRec rec{D.deg, D.dir, D.dcls, 0u};
+        const uint32_t d = D.deg, dn = d - D.r;
+        uint32_t nh = 0;
+        for (uint32_t p0 = D.lo; p0 < D.hi; p0 += kThreads) {
+            const uint32_t p = p0 + tid;
+            uint32_t hole = 0, hp = 0;
+            if (p < D.hi && mark[p]) {
+                hp = hitpos[p];
+                hole = hp < dn;
+            }
+            uint32_t tot;
+            const uint32_t ex = block_excl_scan(hole, lds, tot);
+            if (hole) holes[D.lo + nh + ex] = hp;
+            nh += tot;
+        }
+        __syncthreads();
+        uint32_t ns = 0;
+        for (uint32_t s0 = dn; s0 < d; s0 += kThreads) {
+            const uint32_t s = s0 + tid;
+            uint32_t x = kTomb;
+            if (s < d) x = g.pool[slot_addr(g, rec, s)];
+            const uint32_t surv = x != kTomb;
+            uint32_t tot;
+            const uint32_t ex = block_excl_scan(surv, lds, tot);
+            if (surv) {
+                const uint32_t qq = ns + ex;
+                if (qq < nh) {
+                    const uint32_t dest = holes[D.lo + qq];
+                    if (dest < dn) g.pool[slot_addr(g, rec, dest)] = x;
+                }
+            }
+            ns += tot;
+        }
+        moved += tid == 0 ? ns : 0;
+        const uint32_t nb0 = nblocks(g, d), nb1 = nblocks(g, dn);
+        const unsigned long long pb = fbase + D.need;
+        for (uint32_t j = nb1 + tid; j < nb0; j += kThreads)
+            g.free_stack[pb + (j - nb1)] = block_of(g, rec, j);
+        if (tid == 0) {
+            VRec nr = rec;
+            nr.deg = dn;
+            if (nb1 == 0 && nr.dcls == kNoDir) nr.dir = 0;
+            g.vt[D.v] = nr;
+        }
+        __syncthreads();
+    }
+    if (tid == 0 && moved) atomicAdd(&g.ctr->stripe[blockIdx.x & 63][0], moved);
 }
 
 __global__ void k_final_del(GraphView g, uint64_t n) {
     DevCounters* c = g.ctr;
-    c->free_cnt += c->sum_b;
-    c->st_applied = c->sum_a;
-    c->st_rejected = n - c->n_valid;
-    c->st_dups = c->n_valid - c->n_uniq;
-    c->c_freed_blocks += c->sum_b;
-    c->live_edges -= c->sum_a;
+    const unsigned long long nv = c->tot[kTotValid];
+    const unsigned long long nT = c->tot[kTotSeg] & 0xffffffffull;
+    const unsigned long long nuniq = c->tot[kTotSeg] >> 32;
+    const unsigned long long applied = c->tot[kTotA];
+    const unsigned long long freed = c->tot[kTotB];
+    c->free_cnt += freed;
+    c->st_applied = applied;
+    c->st_rejected = n - nv;
+    c->st_dups = nv - nuniq;
+    c->c_batches[kDelete] += 1;
+    c->c_pairs[kDelete] += n;
+    c->c_touched[kDelete] += nT;
+    c->c_scanned[kDelete] += (c->tot[kTotItems] >> 32) << g.log2B;
+    c->c_freed_blocks += freed;
+    c->live_edges -= applied;
 }
 
 // ------------------------------------------------------------------ query
@@ -518,8 +804,15 @@ __global__ __launch_bounds__(kThreads) void k_answer(GraphView g, const uint32_t
                                                      const uint8_t* mark, uint64_t n,
                                                      uint8_t* out) {
     const uint64_t i = thread_index();
-    if (i >= n) return;
-    out[vals[i]] = i < g.ctr->n_valid ? mark[i] : (uint8_t)0;
+    const unsigned long long nv = g.ctr->tot[kTotValid];
+    if (i == 0) {
+        DevCounters* c = g.ctr;
+        c->c_batches[kQuery] += 1;
+        c->c_pairs[kQuery] += n;
+        c->c_touched[kQuery] += c->tot[kTotSeg] & 0xffffffffull;
+        c->c_scanned[kQuery] += (c->tot[kTotItems] >> 32) << g.log2B;
+    }
+    if (i < nv) out[vals[i]] = mark[i];
 }
 
 __global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
@@ -537,52 +830,57 @@ void set_u64(gv_graph* g, unsigned long long* p, unsigned long long value) {
 void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t* dst, uint64_t n,
                 uint8_t* out, bool sticky) {
     if (n == 0) return;
-    if (n >= 0xffffffffull) fail(GV_EINVAL, "batch too large");
+    if (n >= 0x3fffffffull) fail(GV_EINVAL, "batch too large");
     Ctx& c = g->ctx;
     const GraphView& v = g->v;
     const uint64_t icap = n + div_up(g->item_slots, kChunk) + 1;
+    const int bits = 2 * (int)v.L;
     BatchArrays A;
     {
         Carver m(nullptr);
-        carve_batch(m, A, n, icap, mode);
+        carve_batch(m, A, n, icap, mode, bits);
         g->scratch.ensure(m.used, c.stream);
         Carver cv(g->scratch.ptr);
-        carve_batch(cv, A, n, icap, mode);
+        carve_batch(cv, A, n, icap, mode, bits);
     }
+    DevCounters* ctr = v.ctr;
+    uint32_t* err = &ctr->err_wait;
+    unsigned long long* tot = ctr->tot;
+    const unsigned long long* n_valid = &tot[kTotValid];
     const uint64_t grid = div_up(n, kThreads);
-    c.launch("pack", k_pack, grid, kThreads, v, src, dst, n, A.keys0,
-             mode == kQuery ? A.vals0 : (uint32_t*)nullptr, A.mark);
-    const int bits = 2 * (int)v.L + 1;
+
+    c.launch("begin", k_begin, std::min<uint64_t>(div_up(A.state_words, kThreads), 1024),
+             kThreads, v, A.state, A.state_words);
+    scan2(c, "pack", PackIn{v, src, dst},
+          PackOut{v, src, dst, A.keys0, mode == kQuery ? A.vals0 : nullptr,
+                  mode == kQuery ? out : nullptr, A.mark},
+          n, A.part, &tot[kTotValid]);
     bool flip;
     if (mode == kQuery)
-        flip = radix_sort<uint64_t, true>(c, A.keys0, A.keys1, A.vals0, A.vals1, n, bits, A.sort);
+        flip = onesweep<uint64_t, true>(c, A.keys0, A.keys1, A.vals0, A.vals1,
+                                        (const uint32_t*)n_valid, n, bits, A.state, err);
     else
-        flip = radix_sort<uint64_t, false>(c, A.keys0, A.keys1, nullptr, nullptr, n, bits, A.sort);
+        flip = onesweep<uint64_t, false>(c, A.keys0, A.keys1, nullptr, nullptr,
+                                         (const uint32_t*)n_valid, n, bits, A.state, err);
     const uint64_t* keys = flip ? A.keys1 : A.keys0;
     const uint32_t* vals = flip ? A.vals1 : A.vals0;
 
-    c.launch("flags", k_flags, grid, kThreads, v, keys, n, A.flags);
-    scan_excl<uint32_t>(c, HeadIn{A.flags, n}, ArrOut<uint32_t>{A.a}, n + 1, A.partial,
-                        &v.ctr->n_T);
-    c.launch("segments", k_segments, grid, kThreads, v, keys, (const uint8_t*)A.flags,
-             (const uint32_t*)A.a, n, A.t_vtx, A.t_start);
-    scan_excl<uint32_t>(c, ItemIn{v, A.t_vtx}, ArrOut<uint32_t>{A.t_items}, n + 1, A.partial,
-                        &v.ctr->n_items);
-    c.launch("expand", k_expand, grid, kThreads, v, (const uint32_t*)A.t_vtx,
-             (const uint32_t*)A.t_items, n, A.items, (int)mode);
-    const uint64_t pgrid = std::min<uint64_t>(div_up(icap, kWaves), 2048);
+    scan2(c, "segments", SegIn{keys, n_valid, v.L},
+          SegOut{keys, n_valid, v.L, A.flags, A.a, A.t_vtx, A.t_start}, n, A.part,
+          &tot[kTotSeg]);
+    scan2(c, "items", ItemIn{v, A.t_vtx}, ItemOut{v, A.t_vtx, A.t_start, A.items}, n, A.part,
+          &tot[kTotItems]);
+    const uint64_t pgrid = std::min<uint64_t>(div_up(icap, kWaves * kGroupsPerWave), 2048);
     const uint64_t tgrid = std::min<uint64_t>(div_up(n, kWaves), 2048);
 
     if (mode == kInsert) {
-        c.launch("probe_insert", k_probe<kInsert>, pgrid, kThreads, v, keys,
-                 (const uint32_t*)A.t_vtx, (const uint32_t*)A.t_start, (const uint2*)A.items,
+        c.launch("probe_insert", k_probe<kInsert>, pgrid, kThreads, v, keys, (const Item*)A.items,
                  A.mark, (uint32_t*)nullptr);
-        scan_excl<uint32_t>(c, KeepIn{A.flags, A.mark, v.ctr}, ArrOut<uint32_t>{A.b}, n + 1,
-                            A.partial, &v.ctr->sum_a);
+        scan2(c, "keep", KeepIn{A.flags, A.mark, n_valid}, U32Out{A.b}, n + 1, A.part,
+              &tot[kTotA]);
         c.launch("plan_insert", k_plan_ins, grid, kThreads, v, (const uint32_t*)A.t_vtx,
                  (const uint32_t*)A.t_start, (const uint32_t*)A.b, A.t_need, A.t_dreq, A.t_drank);
-        scan_excl<uint32_t>(c, NeedIn{A.t_need, v.ctr}, ArrOut<uint32_t>{A.t_need}, n + 1,
-                            A.partial, &v.ctr->sum_b);
+        scan2(c, "need", NeedIn{A.t_need, ctr}, U32Out{A.t_need}, n + 1, A.part, &tot[kTotB]);
         c.launch("plan", k_plan, 1, 1, v, n, (int)sticky);
         c.launch("grow", k_grow, tgrid, kThreads, v, (const uint32_t*)A.t_vtx,
                  (const uint32_t*)A.t_start, (const uint32_t*)A.b, (const uint32_t*)A.t_need,
@@ -594,20 +892,20 @@ void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t*
                  (const uint32_t*)A.t_start, (const uint32_t*)A.b, (const uint32_t*)A.t_dreq,
                  (const uint32_t*)A.t_dold, (const uint32_t*)A.t_doldc);
     } else if (mode == kDelete) {
-        c.launch("probe_delete", k_probe<kDelete>, pgrid, kThreads, v, keys,
-                 (const uint32_t*)A.t_vtx, (const uint32_t*)A.t_start, (const uint2*)A.items,
+        c.launch("probe_delete", k_probe<kDelete>, pgrid, kThreads, v, keys, (const Item*)A.items,
                  A.mark, A.hitpos);
-        scan_excl<uint32_t>(c, FoundIn{A.mark, v.ctr}, ArrOut<uint32_t>{A.b}, n + 1, A.partial,
-                            &v.ctr->sum_a);
-        scan_excl<uint32_t>(c, FreedIn{v, A.t_vtx, A.t_start, A.b}, ArrOut<uint32_t>{A.t_need},
-                            n + 1, A.partial, &v.ctr->sum_b);
-        c.launch("compact", k_compact, tgrid, kThreads, v, (const uint8_t*)A.mark,
-                 (const uint32_t*)A.hitpos, A.holes, (const uint32_t*)A.b,
-                 (const uint32_t*)A.t_vtx, (const uint32_t*)A.t_start, (const uint32_t*)A.t_need);
+        scan2(c, "found", FoundIn{A.mark, n_valid}, U32Out{A.b}, n + 1, A.part, &tot[kTotA]);
+        scan2(c, "freed", FreedIn{v, A.t_vtx, A.t_start, A.b},
+              FreedOut{v, A.t_vtx, A.t_start, A.b, A.cdesc, A.big}, n, A.part, &tot[kTotB]);
+        c.launch("compact_big", k_compact_big, 256, kThreads, v, (const uint8_t*)A.mark,
+                 (const uint32_t*)A.hitpos, A.holes, (const CDesc*)A.cdesc,
+                 (const uint32_t*)A.big);
+        c.launch("compact", k_compact, std::min<uint64_t>(div_up(n, kWaves * kGroupsPerWave), 2048),
+                 kThreads, v, (const uint8_t*)A.mark, (const uint32_t*)A.hitpos, A.holes,
+                 (const CDesc*)A.cdesc);
         c.launch("final_delete", k_final_del, 1, 1, v, n);
     } else {
-        c.launch("probe_query", k_probe<kQuery>, pgrid, kThreads, v, keys,
-                 (const uint32_t*)A.t_vtx, (const uint32_t*)A.t_start, (const uint2*)A.items,
+        c.launch("probe_query", k_probe<kQuery>, pgrid, kThreads, v, keys, (const Item*)A.items,
                  A.mark, (uint32_t*)nullptr);
         c.launch("answer", k_answer, grid, kThreads, v, vals, (const uint8_t*)A.mark, n, out);
     }

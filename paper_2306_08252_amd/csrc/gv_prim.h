@@ -13,6 +13,8 @@
 // the sort is stable.
 #pragma once
 
+#include <algorithm>
+
 #include "gv_device.h"
 #include "gv_host.h"
 
@@ -209,6 +211,397 @@ bool radix_sort(Ctx& c, K* k0, K* k1, uint32_t* v0, uint32_t* v1, uint64_t n, in
         flip = !flip;
     }
     return flip;
+}
+
+}  // namespace gv
+
+// ======================================================================
+// Single-pass primitives with decoupled look-back.  Their per-tile status
+// words and tile counters live in a caller-provided region that must be zero
+// before the launch (the batch pipeline clears it in its first kernel).
+// Tiles take ids from an atomic counter in launch order, so every tile a
+// tile waits for is already running; every wait is bounded, and a wait that
+// runs out sets an error flag instead of hanging.
+// ======================================================================
+namespace gv {
+
+constexpr uint64_t kFlagAgg = 1ull << 62;
+constexpr uint64_t kFlagIncl = 2ull << 62;
+constexpr uint64_t kValMask = (1ull << 62) - 1;
+constexpr uint32_t kSpinLimit = 1u << 24;
+
+constexpr int kScan1Items = 8;
+constexpr uint64_t kScan1Tile = (uint64_t)kThreads * kScan1Items;  // 2048
+
+__device__ __forceinline__ unsigned long long ld_acquire(unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_release(unsigned long long* p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_acquire32(uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_release32(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Region for one single-pass scan: word 0 = tile counter, words 1.. = status.
+inline uint64_t scan1_words(uint64_t n) { return 1 + div_up(std::max<uint64_t>(n, 1), kScan1Tile); }
+
+// Exclusive prefix of `tile` from the status words of the tiles before it.
+// Called by one full wave; lane 0 of the nearest window slot is tile-1.
+__device__ __forceinline__ unsigned long long scan1_lookback(unsigned long long* status,
+                                                             int64_t tile, uint32_t* err) {
+    const int lane = lane_id();
+    unsigned long long prefix = 0;
+    int64_t end = tile;
+    while (true) {
+        const int64_t j = end - 1 - lane;
+        unsigned long long w = kFlagIncl;  // before tile 0: inclusive zero
+        if (j >= 0) {
+            uint32_t spins = 0;
+            do {
+                w = ld_acquire(&status[j]);
+            } while ((w >> 62) == 0 && ++spins < kSpinLimit);
+            if ((w >> 62) == 0) {
+                *err = 1;
+                w = kFlagIncl;
+            }
+        }
+        const uint64_t incl = ballot((w >> 62) == 2);
+        const int first = incl ? (int)__ffsll((unsigned long long)incl) - 1 : 64;
+        unsigned long long v = lane <= first ? (w & kValMask) : 0ull;
+        prefix += wave_sum(v);
+        if (incl) break;
+        end -= 64;
+    }
+    return prefix;
+}
+
+// Exclusive scan of in(i), i < n (values < 2^62), written as out(i, prefix);
+// the grand total goes to *total when non-null.  One launch.
+template <typename In, typename Out>
+__global__ __launch_bounds__(kThreads) void k_scan1(In in, Out out, uint64_t n,
+                                                    unsigned long long* region,
+                                                    unsigned long long* total, uint32_t* err) {
+    __shared__ uint32_t s_tile;
+    __shared__ unsigned long long s_w[kWaves];
+    __shared__ unsigned long long s_prefix;
+    if (threadIdx.x == 0) s_tile = atomicAdd((uint32_t*)region, 1u);
+    __syncthreads();
+    const uint64_t tile = s_tile;
+    unsigned long long* status = region + 1;
+    const uint64_t base = tile * kScan1Tile + (uint64_t)threadIdx.x * kScan1Items;
+    unsigned long long v[kScan1Items];
+    unsigned long long local = 0;
+#pragma unroll
+    for (int j = 0; j < kScan1Items; ++j) {
+        const uint64_t i = base + j;
+        v[j] = i < n ? (unsigned long long)in(i) : 0ull;
+        local += v[j];
+    }
+    unsigned long long tot;
+    const unsigned long long ex = block_excl_scan(local, s_w, tot);
+    if (threadIdx.x < 64) {
+        unsigned long long prefix = 0;
+        if (tile == 0) {
+            if (threadIdx.x == 0) st_release(&status[0], kFlagIncl | tot);
+        } else {
+            if (threadIdx.x == 0) st_release(&status[tile], kFlagAgg | tot);
+            prefix = scan1_lookback(status, (int64_t)tile, err);
+            if (threadIdx.x == 0) st_release(&status[tile], kFlagIncl | (prefix + tot));
+        }
+        if (threadIdx.x == 0) s_prefix = prefix;
+    }
+    __syncthreads();
+    unsigned long long run = s_prefix + ex;
+#pragma unroll
+    for (int j = 0; j < kScan1Items; ++j) {
+        const uint64_t i = base + j;
+        if (i < n) out(i, run);
+        run += v[j];
+    }
+    if (total && tile == gridDim.x - 1 && threadIdx.x == kThreads - 1) *total = run;
+}
+
+template <typename In, typename Out>
+void scan1(Ctx& c, const char* name, In in, Out out, uint64_t n, unsigned long long* region,
+           unsigned long long* total, uint32_t* err) {
+    if (n == 0) return;
+    c.launch(name, k_scan1<In, Out>, div_up(n, kScan1Tile), kThreads, in, out, n, region, total,
+             err);
+}
+
+// ---------------------------------------------------------------- scan2
+// Two-kernel exclusive scan without inter-tile waits: the first kernel
+// reduces each tile, the second recomputes its tile prefix by reducing the
+// partials of all earlier tiles (at most a few thousand, read from L2) and
+// scans its tile.  Inputs are evaluated twice, outputs written once.
+template <typename In>
+__global__ __launch_bounds__(kThreads) void k_scan2_reduce(In in, uint64_t n,
+                                                           unsigned long long* part) {
+    __shared__ unsigned long long s_w[kWaves];
+    const uint64_t base = (uint64_t)blockIdx.x * kScan1Tile;
+    unsigned long long s = 0;
+#pragma unroll
+    for (int j = 0; j < kScan1Items; ++j) {
+        const uint64_t i = base + (uint64_t)j * kThreads + threadIdx.x;
+        if (i < n) s += in(i);
+    }
+    s = block_sum(s, s_w);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+template <typename In, typename Out>
+__global__ __launch_bounds__(kThreads) void k_scan2_apply(In in, Out out, uint64_t n,
+                                                          const unsigned long long* part,
+                                                          unsigned long long* total) {
+    __shared__ unsigned long long s_w[kWaves];
+    unsigned long long p = 0;
+    for (uint32_t t = threadIdx.x; t < blockIdx.x; t += kThreads) p += part[t];
+    unsigned long long run = block_sum(p, s_w);
+    const uint64_t base = (uint64_t)blockIdx.x * kScan1Tile;
+#pragma unroll
+    for (int j = 0; j < kScan1Items; ++j) {
+        const uint64_t i = base + (uint64_t)j * kThreads + threadIdx.x;
+        const unsigned long long x = i < n ? (unsigned long long)in(i) : 0ull;
+        unsigned long long t2;
+        const unsigned long long ex = block_excl_scan(x, s_w, t2);
+        if (i < n) out(i, run + ex);
+        run += t2;
+    }
+    if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == kThreads - 1) *total = run;
+}
+
+constexpr uint64_t kScan2MaxTiles = 8192;
+inline uint64_t scan2_parts(uint64_t n) { return div_up(std::max<uint64_t>(n, 1), kScan1Tile); }
+
+// Exclusive scan of in(i), i < n, as out(i, prefix); total -> *total.
+// `part` holds scan2_parts(n) words.  n must not exceed kScan2MaxTiles tiles.
+template <typename In, typename Out>
+void scan2(Ctx& c, const char* name, In in, Out out, uint64_t n, unsigned long long* part,
+           unsigned long long* total) {
+    if (n == 0) return;
+    const uint64_t nt = scan2_parts(n);
+    if (nt > kScan2MaxTiles) fail(GV_EINVAL, "scan too large for the two-kernel scan");
+    c.launch(name, k_scan2_reduce<In>, nt, kThreads, in, n, part);
+    c.launch(name, k_scan2_apply<In, Out>, nt, kThreads, in, out, n,
+             (const unsigned long long*)part, total);
+}
+
+// ---------------------------------------------------------------- onesweep
+// Stable LSD radix sort: one histogram kernel for every pass, then one kernel
+// per 8-bit digit pass.  A pass ranks its 4096-key tile locally (ballot peer
+// masks per wave and round, LDS column scans), publishes its per-digit counts,
+// looks back per digit for the counts of earlier tiles, and scatters.  The
+// number of keys may live on the device (n_dev); grids are sized for n_max.
+constexpr int kOsItems = 16;
+constexpr uint64_t kOsTile = (uint64_t)kThreads * kOsItems;  // 4096
+constexpr uint32_t kOsAgg = 1u << 30, kOsIncl = 2u << 30, kOsMask = (1u << 30) - 1;
+
+inline int os_passes(int bits) { return (bits + kRadixBits - 1) / kRadixBits; }
+inline uint64_t os_tiles(uint64_t n) { return div_up(std::max<uint64_t>(n, 1), kOsTile); }
+// uint32 words of zeroed state a sort needs: tile counters, histograms, status
+inline uint64_t os_words(uint64_t n_max, int bits) {
+    const uint64_t p = (uint64_t)os_passes(bits);
+    return 64 + p * kRadix + p * os_tiles(n_max) * kRadix;
+}
+
+constexpr int kOsThreads = 1024;
+constexpr int kOsWaves = kOsThreads / 64;
+constexpr int kOsRounds = (int)(kOsTile / kOsThreads);  // keys per thread
+
+// exclusive scan across a kOsThreads workgroup (all threads call it)
+__device__ __forceinline__ uint32_t os_block_scan(uint32_t x, uint32_t* lds, uint32_t& total) {
+    uint32_t inc = wave_incl_scan(x);
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 63) lds[w] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kOsWaves; ++i) {
+        const uint32_t v = lds[i];
+        off += (i < w) ? v : 0u;
+        tot += v;
+    }
+    __syncthreads();
+    total = tot;
+    return off + inc - x;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kOsThreads) void k_os_hist(const K* keys, const uint32_t* n_dev,
+                                                        uint64_t n_max, int passes,
+                                                        uint32_t* hist) {
+    __shared__ uint32_t h[8][kRadix];
+    const uint64_t n = n_dev ? *n_dev : n_max;
+    for (int i = threadIdx.x; i < 8 * kRadix; i += kOsThreads) h[i / kRadix][i % kRadix] = 0;
+    __syncthreads();
+    const uint64_t base = (uint64_t)blockIdx.x * kOsTile;
+#pragma unroll
+    for (int j = 0; j < kOsRounds; ++j) {
+        const uint64_t i = base + (uint64_t)j * kOsThreads + threadIdx.x;
+        const bool act = i < n;
+        const K key = act ? keys[i] : K(0);
+        for (int p = 0; p < passes; ++p) {
+            const uint32_t d = (uint32_t)(key >> (p * kRadixBits)) & (kRadix - 1);
+            const uint64_t peers = digit_peers(d, act);
+            if (act && rank_below(peers) == 0) atomicAdd(&h[p][d], popc64(peers));
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < passes * kRadix; i += kOsThreads) {
+        const uint32_t c = h[i / kRadix][i % kRadix];
+        if (c) atomicAdd(&hist[i], c);
+    }
+}
+
+// One pass over 8 bits at `shift`: rank the tile locally (ballot peer masks
+// per wave and round, LDS column scans), publish per-digit tile counts, look
+// back per digit for the counts of earlier tiles, scatter.
+template <typename K, bool HasVal>
+__global__ __launch_bounds__(kOsThreads) void k_os_pass(const K* kin, K* kout, const uint32_t* vin,
+                                                        uint32_t* vout, const uint32_t* n_dev,
+                                                        uint64_t n_max, int shift,
+                                                        const uint32_t* hist, uint32_t* status,
+                                                        uint32_t* counter, uint32_t* err) {
+    // cnt[round * waves + wave][digit]: counts, then exclusive prefixes
+    __shared__ uint16_t cnt[kOsRounds * kOsWaves][kRadix];
+    __shared__ uint32_t part[4][kRadix];
+    __shared__ uint32_t s_base[kRadix];
+    __shared__ uint32_t s_w[kOsWaves];
+    __shared__ uint32_t s_tile;
+    const uint32_t t = threadIdx.x;
+    const int w = t >> 6;
+    if (t == 0) s_tile = atomicAdd(counter, 1u);
+    {
+        uint32_t* c32 = (uint32_t*)&cnt[0][0];
+        for (int i = t; i < kOsRounds * kOsWaves * kRadix / 2; i += kOsThreads) c32[i] = 0;
+    }
+    __syncthreads();
+    const uint64_t tile = s_tile;
+    const uint64_t n = n_dev ? *n_dev : n_max;
+    const uint64_t base = tile * kOsTile;
+    K key[kOsRounds];
+    uint32_t val[kOsRounds];
+    uint16_t rk[kOsRounds];
+#pragma unroll
+    for (int j = 0; j < kOsRounds; ++j) {
+        const uint64_t i = base + (uint64_t)j * kOsThreads + t;
+        const bool act = i < n;
+        key[j] = act ? kin[i] : K(0);
+        if (HasVal) val[j] = act ? vin[i] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kOsRounds; ++j) {
+        const uint64_t i = base + (uint64_t)j * kOsThreads + t;
+        const bool act = i < n;
+        const uint32_t d = (uint32_t)(key[j] >> shift) & (kRadix - 1);
+        const uint64_t peers = digit_peers(d, act);
+        rk[j] = (uint16_t)rank_below(peers);
+        if (act && rk[j] == 0) cnt[j * kOsWaves + w][d] = (uint16_t)popc64(peers);
+    }
+    __syncthreads();
+    // column scans: digit d = t % 256, quarter q = t / 256 covers 16 rows
+    const uint32_t d = t & (kRadix - 1), q = t >> 8;
+    constexpr int kRows = kOsRounds * kOsWaves;
+    constexpr int kQRows = kRows / 4;
+    uint32_t run = 0;
+#pragma unroll
+    for (int r = 0; r < kQRows; ++r) {
+        const uint32_t c = cnt[q * kQRows + r][d];
+        cnt[q * kQRows + r][d] = (uint16_t)run;
+        run += c;
+    }
+    part[q][d] = run;
+    __syncthreads();
+    uint32_t qoff = 0;
+    for (uint32_t qq = 0; qq < q; ++qq) qoff += part[qq][d];
+    const uint32_t dcount = part[0][d] + part[1][d] + part[2][d] + part[3][d];
+    if (qoff) {
+#pragma unroll
+        for (int r = 0; r < kQRows; ++r) cnt[q * kQRows + r][d] += (uint16_t)qoff;
+    }
+    // digit threads publish this tile's count and look back
+    uint32_t prefix = 0;
+    if (t < kRadix) {
+        uint32_t* st = status + tile * kRadix + t;
+        st_release32(st, (tile == 0 ? kOsIncl : kOsAgg) | dcount);
+        if (tile > 0) {
+            int64_t j = (int64_t)tile - 1;
+            while (j >= 0) {
+                uint32_t spins = 0, wv;
+                do {
+                    wv = ld_acquire32(status + (uint64_t)j * kRadix + t);
+                } while ((wv >> 30) == 0 && ++spins < kSpinLimit);
+                if ((wv >> 30) == 0) {
+                    *err = 1;
+                    break;
+                }
+                prefix += wv & kOsMask;
+                if ((wv >> 30) == 2) break;
+                --j;
+            }
+            st_release32(st, kOsIncl | (prefix + dcount));
+        }
+    }
+    // global start of each digit: exclusive scan of the pass histogram
+    uint32_t tot;
+    const uint32_t gex = os_block_scan(t < kRadix ? hist[t] : 0u, s_w, tot);
+    if (t < kRadix) s_base[t] = gex + prefix;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kOsRounds; ++j) {
+        const uint64_t i = base + (uint64_t)j * kOsThreads + t;
+        if (i < n) {
+            const uint32_t dd = (uint32_t)(key[j] >> shift) & (kRadix - 1);
+            const uint32_t pos = s_base[dd] + cnt[j * kOsWaves + w][dd] + rk[j];
+            kout[pos] = key[j];
+            if (HasVal) vout[pos] = val[j];
+        }
+    }
+}
+
+// Sorts n keys (n on the device when n_dev != null, n_max bounds it) by bits
+// [0, bits), stably, ping-ponging k0/k1 (v0/v1).  `state` must hold
+// os_words(n_max, bits) zeroed uint32 words.  Returns true if the result is
+// in k1/v1.
+template <typename K, bool HasVal>
+bool onesweep(Ctx& c, K* k0, K* k1, uint32_t* v0, uint32_t* v1, const uint32_t* n_dev,
+              uint64_t n_max, int bits, uint32_t* state, uint32_t* err) {
+    if (n_max <= 1 || bits <= 0) return false;
+    if (n_max > 0xffffffffull) fail(GV_EINVAL, "sort too large");
+    const int passes = os_passes(bits);
+    if (passes > 8) fail(GV_EINVAL, "too many radix passes");
+    const uint64_t nt = os_tiles(n_max);
+    uint32_t* counters = state;           // 64 words
+    uint32_t* hist = state + 64;          // passes * 256
+    uint32_t* status = hist + (uint64_t)passes * kRadix;
+    c.launch("sort_hist", k_os_hist<K>, nt, kOsThreads, (const K*)k0, n_dev, n_max, passes, hist);
+    bool flip = false;
+    for (int p = 0; p < passes; ++p) {
+        K* kin = flip ? k1 : k0;
+        K* kout = flip ? k0 : k1;
+        uint32_t* vin = flip ? v1 : v0;
+        uint32_t* vout = flip ? v0 : v1;
+        c.launch("sort_pass", k_os_pass<K, HasVal>, nt, kOsThreads, (const K*)kin, kout,
+                 (const uint32_t*)vin, vout, n_dev, n_max, p * kRadixBits,
+                 (const uint32_t*)(hist + (uint64_t)p * kRadix), status + (uint64_t)p * nt * kRadix,
+                 counters + p, err);
+        flip = !flip;
+    }
+    return flip;
+}
+
+static __global__ void k_zero_words(uint32_t* p, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+inline void zero_words(Ctx& c, uint32_t* p, uint64_t n) {
+    if (n) c.launch("zero", k_zero_words, std::min<uint64_t>(div_up(n, kThreads), 4096), kThreads, p, n);
 }
 
 }  // namespace gv

@@ -275,3 +275,40 @@ def test_directory_reuse_after_churn():
         assert g.delete_edges(vs[keep], ds[keep]) == o.delete_edges(vs[keep], ds[keep])[1]
         assert_same(g, o, f"shrink {it}")
     g.close()
+
+
+@pytest.mark.parametrize("B", [4, 16])
+def test_segment_lengths_around_lds_stage(B):
+    """Batch segments of lengths around the probe's LDS stage (128 entries)
+    and its sampling strides, with repeated pairs, for every operation."""
+    gv = need_gpu()
+    rng = np.random.default_rng(17)
+    n = 1 << 13
+    base_s = rng.integers(0, n, 40000).astype(np.uint32)
+    base_d = rng.integers(0, n, 40000).astype(np.uint32)
+    g = gv.Graph(n, base_s, base_d, block_slots=B)
+    o = O.OracleGraph(n, base_s, base_d, block_slots=B)
+    lens = [1, 127, 128, 129, 255, 256, 257, 513, 1025, 4097]
+    for rep in range(3):
+        s_parts, d_parts = [], []
+        for j, L in enumerate(lens):
+            v = 11 * j + 3 + rep
+            d = rng.integers(0, n, L).astype(np.uint32)
+            q = L // 4
+            if q:
+                d[L - q:] = d[:q]  # repeats inside the segment
+            s_parts.append(np.full(L, v, np.uint32))
+            d_parts.append(d)
+        s = np.concatenate(s_parts)
+        d = np.concatenate(d_parts)
+        perm = rng.permutation(len(s))
+        s, d = s[perm], d[perm]
+        same_answers(g, o, s, d, f"query rep {rep}")
+        assert g.insert_edges(s, d) == o.insert_edges(s, d)[1]
+        assert_same(g, o, f"insert rep {rep}")
+        same_answers(g, o, s, d, f"query after insert rep {rep}")
+        half = len(s) // 2
+        assert g.delete_edges(s[:half], d[:half]) == o.delete_edges(s[:half], d[:half])[1]
+        assert_same(g, o, f"delete rep {rep}")
+        same_answers(g, o, s, d, f"query after delete rep {rep}")
+    g.close()
