@@ -9,6 +9,7 @@
 
 #include <cstring>
 #include <new>
+#include <iterator>
 #include <set>
 #include <utility>
 #include <vector>
@@ -245,8 +246,11 @@ extern "C" int orc_delete_vertices(orc_graph* g, const uint32_t* ids,
     }
     // A deleted vertex loses its outgoing and its incoming edges.
     for (uint32_t x : gone) g->adj[x].clear();
-    for (uint64_t u = 0; u < g->capacity; ++u)
-        for (uint32_t x : gone) g->adj[u].erase(x);
+    for (uint64_t u = 0; u < g->capacity; ++u) {
+        std::set<uint32_t>& a = g->adj[u];
+        for (auto it = a.begin(); it != a.end();)
+            it = gone.count(*it) ? a.erase(it) : std::next(it);
+    }
     for (uint32_t x : gone) g->active[x] = 0;
     s.applied = gone.size();
     if (stats) *stats = s;
