@@ -47,20 +47,23 @@ def bytes_model(name, per_launch):
     M (slots moved), NEW / FREED (blocks)."""
     k, T, S, NBLK = per_launch["k"], per_launch["T"], per_launch["S"], per_launch["NB"]
     if name in ("probe_insert", "probe_delete", "probe_query"):
-        # adjacency slots + their directory entries + vertex records + the
-        # sorted batch keys (each read once) + one mark byte per pair
-        return 4 * S + 4 * NBLK + 16 * T + 8 * k + k
-    if name == "sort_scatter":
-        return 16 * k  # read and write every key once
+        # adjacency slots + their directory entries + one 32-byte work item
+        # per touched source + the sorted batch keys (each read once) + one
+        # mark byte per pair
+        return 4 * S + 4 * NBLK + 32 * T + 8 * k + k
+    if name == "sort_pass":
+        return 16 * k  # one 8-bit digit pass: read and write every key once
     if name == "sort_hist":
-        return 8 * k
+        return 8 * k  # all digit histograms from one read of the keys
     if name == "pack":
         return 8 * k + 8 * k + k  # pairs in, keys out, mark bytes
-    if name == "flags":
-        return 8 * k + k
+    if name == "segments":
+        return 8 * k + k + 4 * k + 8 * T  # keys in; flags, ranks, segment starts out
+    if name == "items":
+        return 8 * T + 16 * T + 32 * T  # segment list, vertex records, items out
     if name == "append":
         return k + k + 4 * k + 4 * per_launch["W"] + 16 * T
-    if name == "compact":
+    if name in ("compact", "compact_big"):
         return 8 * per_launch["M"] + 16 * T + 4 * per_launch["FREED"]
     return None
 
@@ -137,9 +140,7 @@ def main():
     gv.gv_insert_edges(h, *ins[j], dev, stats=False)
     gv.gv_delete_edges(h, *dels[j], dev, stats=False)
     torch.cuda.synchronize()
-    names = ["pack", "sort_hist", "sort_scatter", "scan_reduce", "scan_partials", "scan_down",
-             "flags", "segments", "expand", "probe_insert", "probe_delete", "plan_insert",
-             "plan", "grow", "append", "final_insert", "compact", "final_delete"]
+    names = gv.gv_kernel_names(h)
     pilot = {}
     for nm in names:
         cnt, ms = gv.gv_kernel_times(h, nm)
@@ -180,7 +181,7 @@ def main():
     pct_m1 = m1 / elapsed / (HBM_PEAK_GBS * 1e9)
 
     # per-launch quantities of the dominant kernel's batch type
-    if dominant.endswith("delete") or dominant == "compact":
+    if dominant in ("probe_delete", "found", "freed", "compact", "compact_big", "final_delete"):
         per = {"k": k, "T": del_T / K, "S": del_S / K, "NB": del_S / K / B,
                "W": 0, "M": d["moved_slots"] / K, "FREED": d["freed_blocks"] / K}
     else:

@@ -199,6 +199,11 @@ int gv_profile_only(gv_graph* g, const char* name);
 int gv_profile_reset(gv_graph* g);
 int gv_kernel_times(gv_graph* g, const char* name, uint64_t* launches,
                     double* total_ms);
+/* Names of the kernels timed since the last reset, comma-separated and
+ * NUL-terminated, in order of first launch.  *needed receives the buffer size
+ * the full list takes (terminator included); when cap is smaller, nothing is
+ * written (buf may be NULL) and GV_ERANGE is returned.  Synchronous. */
+int gv_kernel_names(gv_graph* g, char* buf, size_t cap, size_t* needed);
 
 int gv_set_stream(gv_graph* g, void* hip_stream);
 /* Wait for all queued work; returns and clears the first error of earlier

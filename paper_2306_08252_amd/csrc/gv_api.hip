@@ -315,6 +315,23 @@ int gv_kernel_times(gv_graph* g, const char* name, uint64_t* launches, double* t
     });
 }
 
+int gv_kernel_names(gv_graph* g, char* buf, size_t cap, size_t* needed) {
+    if (!g || !needed) return GV_EINVAL;
+    std::string all;
+    const int rc = guarded(g, [&] {
+        g->ctx.collect();
+        for (auto& s : g->ctx.sums) {
+            if (!all.empty()) all += ',';
+            all += s.name;
+        }
+    });
+    if (rc != GV_OK) return rc;
+    *needed = all.size() + 1;
+    if (!buf || cap < all.size() + 1) return GV_ERANGE;
+    std::memcpy(buf, all.c_str(), all.size() + 1);
+    return GV_OK;
+}
+
 int gv_set_stream(gv_graph* g, void* hip_stream) {
     if (!g) return GV_EINVAL;
     return guarded(g, [&] {

@@ -27,6 +27,23 @@ void read_counters(gv_graph* g) {
     hip_check(hipStreamSynchronize(g->ctx.stream), "hipStreamSynchronize");
 }
 
+// Sort n keys of `bits` bits (n >= 2) with the one-sweep radix sort; `state`
+// holds os_words(n, bits) words.  Synchronous: raises GV_EDEVICE if a
+// look-back did not complete.  Returns true if the result is in k1.
+static bool sort_keys(gv_graph* g, uint64_t* k0, uint64_t* k1, uint64_t n, int bits,
+                      uint32_t* state) {
+    Ctx& c = g->ctx;
+    DevCounters* ctr = g->v.ctr;
+    zero_words(c, state, os_words(n, bits));
+    set_u32(g, &ctr->sort_n, (uint32_t)n);
+    set_u32(g, &ctr->sort_err, 0);
+    const bool flip = onesweep<uint64_t, false>(c, k0, k1, nullptr, nullptr, &ctr->sort_n, n,
+                                                bits, state, &ctr->sort_err);
+    read_counters(g);
+    if (g->hctr->sort_err) fail(GV_EDEVICE, "sort look-back did not complete");
+    return flip;
+}
+
 // ------------------------------------------------------------------ init
 __global__ __launch_bounds__(kThreads) void k_init_vt(GraphView g, uint64_t n_active) {
     const uint64_t v = tidx();
@@ -41,26 +58,36 @@ __global__ __launch_bounds__(kThreads) void k_init_vt(GraphView g, uint64_t n_ac
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_init_check(GraphView g, const uint32_t* src,
-                                                         const uint32_t* dst, uint64_t m,
-                                                         uint64_t n) {
-    const uint64_t i = tidx();
-    if (i < m && ((uint64_t)src[i] >= n || (uint64_t)dst[i] >= n)) g.ctr->vany = 1;
-}
-
+// keys of the initial edges; an id out of range raises a flag (a plain store,
+// taken only on error) that the host checks before any id is used as an index
 __global__ __launch_bounds__(kThreads) void k_init_pack(GraphView g, const uint32_t* src,
                                                         const uint32_t* dst, uint64_t m,
-                                                        uint64_t* keys) {
+                                                        uint64_t n, uint64_t* keys) {
     const uint64_t i = tidx();
-    if (i < m) keys[i] = ((uint64_t)src[i] << g.L) | dst[i];
+    if (i >= m) return;
+    const uint32_t s = src[i], d = dst[i];
+    if ((uint64_t)s >= n || (uint64_t)d >= n) g.ctr->vany = 1;
+    keys[i] = ((uint64_t)s << g.L) | d;
 }
 
+// first occurrence of a key in the low half, first occurrence of a source in
+// the high half: one scan yields the unique positions, the number of distinct
+// edges and the number of vertices of non-zero degree
 struct FirstIn {
     const uint64_t* keys;
     uint64_t m;
-    __device__ uint32_t operator()(uint64_t i) const {
-        return (i < m && (i == 0 || keys[i] != keys[i - 1])) ? 1u : 0u;
+    uint32_t L;
+    __device__ unsigned long long operator()(uint64_t i) const {
+        if (i >= m) return 0ull;
+        if (i == 0) return 1ull | (1ull << 32);
+        const uint64_t a = keys[i - 1], b = keys[i];
+        return (a != b ? 1ull : 0ull) | ((a >> L) != (b >> L) ? (1ull << 32) : 0ull);
     }
+};
+
+struct LowOut {
+    uint32_t* a;
+    __device__ void operator()(uint64_t i, unsigned long long v) const { a[i] = (uint32_t)v; }
 };
 
 __global__ __launch_bounds__(kThreads) void k_init_unique(const uint64_t* keys, const uint32_t* pos,
@@ -69,21 +96,13 @@ __global__ __launch_bounds__(kThreads) void k_init_unique(const uint64_t* keys, 
     if (i < m && (i == 0 || keys[i] != keys[i - 1])) ukeys[pos[i]] = keys[i];
 }
 
-// run starts: vertex first position -> aux; count of non-empty vertices
+// run starts: first position of each source in the unique list -> aux
 __global__ __launch_bounds__(kThreads) void k_init_runs(GraphView g, const uint64_t* ukeys,
                                                         uint64_t mu) {
-    __shared__ unsigned long long lds[kWaves];
     const uint64_t p = tidx();
-    unsigned long long starts = 0;
-    if (p < mu) {
-        const uint32_t v = (uint32_t)(ukeys[p] >> g.L);
-        if (p == 0 || (uint32_t)(ukeys[p - 1] >> g.L) != v) {
-            g.vt[v].aux = (uint32_t)p;
-            starts = 1;
-        }
-    }
-    starts = block_sum(starts, lds);
-    if (threadIdx.x == 0 && starts) atomicAdd((unsigned long long*)&g.ctr->n_uniq, starts);
+    if (p >= mu) return;
+    const uint32_t v = (uint32_t)(ukeys[p] >> g.L);
+    if (p == 0 || (uint32_t)(ukeys[p - 1] >> g.L) != v) g.vt[v].aux = (uint32_t)p;
 }
 
 __global__ __launch_bounds__(kThreads) void k_init_deg(GraphView g, const uint64_t* ukeys,
@@ -181,25 +200,26 @@ void bulk_build(gv_graph* g, uint64_t n, const uint32_t* src, const uint32_t* ds
     const uint64_t vgrid = div_up(std::max<uint64_t>(v.n_cap, (v.n_cap + 31) / 32), kThreads);
     c.launch("init_vt", k_init_vt, vgrid, kThreads, v, n);
     set_u32(g, &v.ctr->vany, 0);
-    set_u64(g, &v.ctr->n_uniq, 0);
 
+    const int bits = 2 * (int)v.L;
     uint64_t mu = 0, nonzero = 0;
     struct Arr {
         uint64_t* k0;
         uint64_t* k1;
         uint32_t* pos;
-        uint32_t* part;
-        SortScratch sort;
+        unsigned long long* part;
+        uint32_t* state;
         unsigned long long* off;
         unsigned long long* part64;
         uint32_t* runstart;
     } A{};
+    const uint64_t state_words = m > 1 ? os_words(m, bits) : 0;
     auto carve = [&](Carver& cv) {
         A.k0 = cv.take<uint64_t>(std::max<uint64_t>(m, 1));
         A.k1 = cv.take<uint64_t>(std::max<uint64_t>(m, 1));
         A.pos = cv.take<uint32_t>(m + 1);
-        A.part = cv.take<uint32_t>(scan_partials_needed(m + 1));
-        carve_sort<uint64_t>(cv, A.sort, std::max<uint64_t>(m, 1));
+        A.part = cv.take<unsigned long long>(scan_partials_needed(m + 1));
+        A.state = cv.take<uint32_t>(std::max<uint64_t>(state_words, 1));
         A.off = cv.take<unsigned long long>(v.n_cap + 1);
         A.part64 = cv.take<unsigned long long>(scan_partials_needed(v.n_cap + 1));
         A.runstart = cv.take<uint32_t>(v.n_cap);
@@ -215,25 +235,21 @@ void bulk_build(gv_graph* g, uint64_t n, const uint32_t* src, const uint32_t* ds
     if (m > 0) {
         if (m >= 0xffffffffull) fail(GV_EINVAL, "too many edges");
         const uint64_t grid = div_up(m, kThreads);
-        c.launch("init_check", k_init_check, grid, kThreads, v, src, dst, m, n);
-        read_counters(g);
-        if (g->hctr->vany) fail(GV_ERANGE, "edge id >= num_vertices");
-        c.launch("init_pack", k_init_pack, grid, kThreads, v, src, dst, m, A.k0);
-        const bool flip = radix_sort<uint64_t, false>(c, A.k0, A.k1, nullptr, nullptr, m,
-                                                      2 * (int)v.L, A.sort);
+        c.launch("init_pack", k_init_pack, grid, kThreads, v, src, dst, m, n, A.k0);
+        const bool flip = m > 1 && sort_keys(g, A.k0, A.k1, m, bits, A.state);
         uint64_t* keys = flip ? A.k1 : A.k0;
         ukeys = flip ? A.k0 : A.k1;
-        scan_excl<uint32_t>(c, FirstIn{keys, m}, ArrOut<uint32_t>{A.pos}, m + 1, A.part,
-                            &v.ctr->sum_a);
+        scan_excl<unsigned long long>(c, FirstIn{keys, m, v.L}, LowOut{A.pos}, m + 1, A.part,
+                                      &v.ctr->edges);
+        read_counters(g);
+        if (g->hctr->vany) fail(GV_ERANGE, "edge id >= num_vertices");
+        mu = g->hctr->edges & 0xffffffffull;
+        nonzero = g->hctr->edges >> 32;
         c.launch("init_unique", k_init_unique, grid, kThreads, (const uint64_t*)keys,
                  (const uint32_t*)A.pos, m, ukeys);
-        read_counters(g);
-        mu = g->hctr->sum_a;
         const uint64_t ugrid = div_up(mu, kThreads);
         c.launch("init_runs", k_init_runs, ugrid, kThreads, v, (const uint64_t*)ukeys, mu);
         c.launch("init_deg", k_init_deg, ugrid, kThreads, v, (const uint64_t*)ukeys, mu);
-        read_counters(g);
-        nonzero = g->hctr->n_uniq;
     }
     uint32_t B = cfg.block_slots ? cfg.block_slots : paper_block_rule(mu, nonzero);
     v.B = B;
@@ -355,11 +371,12 @@ void dump(gv_graph* g, uint64_t* offsets, uint32_t* dst, uint64_t cap, uint64_t*
     // keys (u << L | x) at CSR positions; one sort then orders the
     // destinations of every vertex
     uint64_t *k0 = nullptr, *k1 = nullptr;
-    SortScratch ss{};
+    uint32_t* state = nullptr;
+    const int bits = 2 * (int)v.L;
     auto carve2 = [&](Carver& cv) {
         k0 = cv.take<uint64_t>(e);
         k1 = cv.take<uint64_t>(e);
-        carve_sort<uint64_t>(cv, ss, e);
+        state = cv.take<uint32_t>(os_words(std::max<uint64_t>(e, 2), bits));
     };
     {
         Carver mz(nullptr);
@@ -370,7 +387,7 @@ void dump(gv_graph* g, uint64_t* offsets, uint32_t* dst, uint64_t cap, uint64_t*
     }
     c.launch("dump_gather", k_dump_gather, wgrid, kThreads, v, (const unsigned long long*)offs,
              k0);
-    const bool flip = radix_sort<uint64_t, false>(c, k0, k1, nullptr, nullptr, e, 2 * (int)v.L, ss);
+    const bool flip = e > 1 && sort_keys(g, k0, k1, e, bits, state);
     c.launch("dump_extract", k_dump_extract, div_up(e, kThreads), kThreads,
              (const uint64_t*)(flip ? k1 : k0), e, v.L, dst);
     hip_check(hipStreamSynchronize(c.stream), "hipStreamSynchronize");

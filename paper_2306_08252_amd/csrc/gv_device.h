@@ -23,7 +23,10 @@ constexpr uint32_t kNoDir = 0xFFu;       // vertex has no directory segment
 constexpr int kMaxClass = 32;
 constexpr int kThreads = 256;            // threads per workgroup (4 waves)
 constexpr int kWaves = kThreads / 64;
-constexpr uint32_t kChunk = 256;         // adjacency slots per probe work item
+#ifndef GV_PROBE_CHUNK
+#define GV_PROBE_CHUNK 256
+#endif
+constexpr uint32_t kChunk = GV_PROBE_CHUNK;  // adjacency slots per probe work item
 
 // One vertex dictionary entry.  The adjacency of a vertex of degree deg is the
 // slots [0, deg) of its blocks 0 .. ceil(deg/B)-1 (always compacted).
@@ -57,6 +60,7 @@ struct DevCounters {
     // errors: err_batch is reset per batch, err_sticky accumulates; err_wait
     // is set if a bounded look-back wait ever ran out
     uint32_t err_batch, err_sticky, err_wait, n_big;
+    uint32_t sort_n, sort_err;  // count and look-back error word of whole-graph sorts
     // totals of the single-pass scans of the current batch
     unsigned long long tot[8];
     // statistics of the last batch

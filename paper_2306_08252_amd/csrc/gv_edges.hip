@@ -39,19 +39,27 @@
 namespace gv {
 
 constexpr uint8_t kHead = 1, kUniq = 2;
-constexpr int kGroup = 16;                     // lanes per work item
+#ifndef GV_PROBE_GROUP
+#define GV_PROBE_GROUP 32
+#endif
+#ifndef GV_PROBE_UNROLL
+#define GV_PROBE_UNROLL 4
+#endif
+constexpr int kGroup = GV_PROBE_GROUP;         // lanes per work item
 constexpr int kGroupsPerWave = 64 / kGroup;
 constexpr int kStage = 128;                    // segment entries staged in LDS
-constexpr int kUnroll = 4;                     // slots per lane per step
+constexpr int kUnroll = GV_PROBE_UNROLL;       // slots per lane per step
 constexpr uint32_t kBigR = 256;                // deletes per source handled by a workgroup
 
 // scan-total slots in DevCounters::tot
 enum { kTotValid = 0, kTotSeg = 1, kTotItems = 2, kTotA = 3, kTotB = 4 };
 
-// self-contained work item: slots [s0, s1) of vertex v, batch segment [lo, hi)
+// self-contained work item: slots [s0, s1) of vertex v, batch segment [lo, hi);
+// block j is dir[dirbase + j] when the vertex has a directory segment, else
+// the inline block blk0 (dirbase is then 0, so the load stays in bounds)
 struct alignas(16) Item {
     uint32_t s0, s1, lo, hi;
-    uint32_t v, dir, dcls, pad;
+    uint32_t v, dirbase, blk0, dcls;
 };
 
 // per-source compaction descriptor (delete)
@@ -244,9 +252,9 @@ struct ItemOut {
         it.lo = t_start[t];
         it.hi = t_start[t + 1];
         it.v = v;
-        it.dir = r.dir;
+        it.dirbase = r.dcls != kNoDir ? r.dir : 0u;
+        it.blk0 = r.dcls != kNoDir ? 0u : r.dir;
         it.dcls = r.dcls;
-        it.pad = 0;
         for (uint32_t c = 0; c < cnt; ++c) {
             it.s0 = c * kChunk;
             it.s1 = min(r.deg, it.s0 + kChunk);
@@ -258,8 +266,9 @@ struct ItemOut {
 // ------------------------------------------------------------------ probe
 // Group-level helpers: a group is kGroup consecutive lanes of a wave.
 __device__ __forceinline__ uint64_t group_mask(uint64_t m, uint32_t lane) {
+    if (kGroup == 64) return m;
     const uint32_t g0 = lane & ~(uint32_t)(kGroup - 1);
-    return (m >> g0) & ((1ull << kGroup) - 1);
+    return (m >> g0) & ((1ull << (kGroup & 63)) - 1);
 }
 
 __device__ __forceinline__ void wave_lds_sync() {
@@ -269,51 +278,63 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 template <int MODE>
-__device__ __forceinline__ void probe_load(const GraphView& g, const Item& I, uint32_t s,
-                                           uint32_t (&x)[kUnroll], uint64_t (&addr)[kUnroll]) {
+__device__ __forceinline__ void probe_load(const GraphView& g, const Item& I, const uint32_t* dp,
+                                           uint32_t s, uint32_t (&x)[kUnroll],
+                                           uint64_t (&addr)[kUnroll]) {
+    // unconditional loads at clamped positions; lanes past the item are
+    // masked out by the caller
+    uint32_t e[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-        const uint32_t si = s + u * kGroup;
-        uint32_t blk = I.dir;
-        if (si < I.s1 && I.dcls != kNoDir) blk = g.dir[(uint64_t)I.dir + (si >> g.log2B)];
-        addr[u] = ((uint64_t)blk << g.log2B) + (si & (g.B - 1));
+        const uint32_t si = min(s + u * kGroup, I.s1 - 1);
+        e[u] = dp[si >> g.log2B];
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-        const uint32_t si = s + u * kGroup;
-        x[u] = si < I.s1 ? g.pool[addr[u]] : kTomb;
+        const uint32_t si = min(s + u * kGroup, I.s1 - 1);
+        addr[u] = ((uint64_t)e[u] << g.log2B) + (si & (g.B - 1));
     }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) x[u] = g.pool[addr[u]];
+}
+
+// number of entries < x among st[0, 2^steps - 1), which holds the sorted
+// samples padded with 0xFFFFFFFF (at least one pad entry); branch-free,
+// uniform trip count
+__device__ __forceinline__ uint32_t lds_rank(const uint32_t* st, uint32_t steps, uint32_t x) {
+    uint32_t pos = 0;
+    for (uint32_t k = steps; k-- > 0;) {
+        const uint32_t half = 1u << k;
+        pos += (st[pos + half - 1] < x) ? half : 0u;
+    }
+    return pos;
 }
 
 template <int MODE>
 __device__ __forceinline__ void probe_search(const GraphView& g, const Item& I, uint32_t s,
                                              const uint32_t (&x)[kUnroll],
                                              const uint64_t (&addr)[kUnroll], const uint32_t* st,
-                                             uint32_t ns, uint32_t shift, const uint64_t* keys,
+                                             uint32_t steps, uint32_t shift, const uint64_t* keys,
                                              uint8_t* mark, uint32_t* hitpos) {
     const uint32_t len = I.hi - I.lo;
     const uint64_t vbase = (uint64_t)I.v << g.L;
+    uint32_t lo[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) lo[u] = lds_rank(st, steps, x[u]);
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
         const uint32_t si = s + u * kGroup;
         if (si >= I.s1) continue;
-        // first sample >= x
-        uint32_t lo = 0, hi = ns;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (st[mid] < x[u]) lo = mid + 1;
-            else hi = mid;
-        }
         uint32_t p;  // first segment position whose value is >= x
         bool hit;
         const uint64_t target = vbase | x[u];
         if (shift == 0) {
-            p = lo;
-            hit = lo < ns && st[lo] == x[u];
+            p = lo[u];
+            hit = p < len && st[p] == x[u];
         } else {
             // the answer lies in ((lo - 1) * stride, lo * stride]
-            uint32_t a = lo ? ((lo - 1) << shift) + 1 : 0;
-            uint32_t b = min(lo << shift, len);
+            uint32_t a = lo[u] ? ((lo[u] - 1) << shift) + 1 : 0;
+            uint32_t b = min(lo[u] << shift, len);
             while (a < b) {
                 const uint32_t mid = (a + b) >> 1;
                 if (keys[I.lo + mid] < target) a = mid + 1;
@@ -355,31 +376,62 @@ __global__ __launch_bounds__(kThreads) void k_probe(GraphView g, const uint64_t*
     while (true) {
         const uint32_t itn = it + ngroups;
         const Item In = items[min(itn, nitems - 1)];  // prefetch the next item
-        // slot loads of the first step go out before the segment is staged
+        // item prologue, in issue order: directory entries of the first step,
+        // the segment samples, then the first step's slots; the samples go to
+        // LDS once they arrive, while the slot loads are still in flight
+        const uint32_t len = I.hi - I.lo;
+        // LDS holds the segment (stride 1) or every stride-th entry of it,
+        // padded with 0xFFFFFFFF up to a power of two (at least one pad entry
+        // stays, so the rank can reach ns)
+        const uint32_t q = (len + kStage - 2) / (kStage - 1);
+        const uint32_t shift = q <= 1 ? 0u : 32u - __clz(q - 1);
+        const uint32_t ns = (len + (1u << shift) - 1) >> shift;  // < kStage samples
+        const uint32_t steps = 32u - __clz(ns);                  // 2^steps > ns
+        uint32_t s = I.s0 + gl;
+        // block ids come from the directory, or from the item itself for a
+        // vertex whose only block is stored inline
+        const uint32_t* dp = I.dcls != kNoDir ? g.dir + I.dirbase : &items[it].blk0;
+        uint32_t e[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const uint32_t si = min(s + u * kGroup, I.s1 - 1);
+            e[u] = dp[si >> g.log2B];
+        }
+        constexpr int kSv = kStage / kGroup;
+        const uint32_t* klo = (const uint32_t*)keys;  // low words: destinations
+        uint32_t sv[kSv];
+#pragma unroll
+        for (int r = 0; r < kSv; ++r) {
+            const uint32_t j = min(gl + r * kGroup, ns - 1);
+            sv[r] = klo[2ull * (I.lo + (j << shift))] & (uint32_t)dmask;
+        }
         uint32_t x[kUnroll];
         uint64_t addr[kUnroll];
-        uint32_t s = I.s0 + gl;
-        probe_load<MODE>(g, I, s, x, addr);
-        const uint32_t len = I.hi - I.lo;
-        // LDS holds the segment (stride 1) or every stride-th entry of it
-        uint32_t shift = 0;
-        while (((len + (1u << shift) - 1) >> shift) > (uint32_t)kStage) ++shift;
-        const uint32_t ns = (len + (1u << shift) - 1) >> shift;  // <= kStage samples
-        for (uint32_t j = gl; j < ns; j += kGroup)
-            st[j] = (uint32_t)(keys[I.lo + (j << shift)] & dmask);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const uint32_t si = min(s + u * kGroup, I.s1 - 1);
+            addr[u] = ((uint64_t)e[u] << g.log2B) + (si & (g.B - 1));
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) x[u] = g.pool[addr[u]];
+#pragma unroll
+        for (int r = 0; r < kSv; ++r) {
+            const uint32_t j = gl + r * kGroup;  // covers the whole stage
+            st[j] = j < ns ? sv[r] : 0xFFFFFFFFu;
+        }
         wave_lds_sync();
         // ping-pong between two register sets: load step k+1, search step k
         uint32_t x2[kUnroll];
         uint64_t a2[kUnroll];
         while (true) {
             const bool more = s + kGroup * kUnroll - gl < I.s1;  // uniform in the group
-            if (more) probe_load<MODE>(g, I, s + kGroup * kUnroll, x2, a2);
-            probe_search<MODE>(g, I, s, x, addr, st, ns, shift, keys, mark, hitpos);
+            if (more) probe_load<MODE>(g, I, dp, s + kGroup * kUnroll, x2, a2);
+            probe_search<MODE>(g, I, s, x, addr, st, steps, shift, keys, mark, hitpos);
             if (!more) break;
             s += kGroup * kUnroll;
             const bool more2 = s + kGroup * kUnroll - gl < I.s1;
-            if (more2) probe_load<MODE>(g, I, s + kGroup * kUnroll, x, addr);
-            probe_search<MODE>(g, I, s, x2, a2, st, ns, shift, keys, mark, hitpos);
+            if (more2) probe_load<MODE>(g, I, dp, s + kGroup * kUnroll, x, addr);
+            probe_search<MODE>(g, I, s, x2, a2, st, steps, shift, keys, mark, hitpos);
             if (!more2) break;
             s += kGroup * kUnroll;
         }

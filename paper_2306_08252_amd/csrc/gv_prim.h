@@ -403,9 +403,10 @@ constexpr uint32_t kOsAgg = 1u << 30, kOsIncl = 2u << 30, kOsMask = (1u << 30) -
 inline int os_passes(int bits) { return (bits + kRadixBits - 1) / kRadixBits; }
 inline uint64_t os_tiles(uint64_t n) { return div_up(std::max<uint64_t>(n, 1), kOsTile); }
 // uint32 words of zeroed state a sort needs: tile counters, histograms, status
+constexpr uint32_t kHistStride = 32;  // one 128-byte line per histogram counter
 inline uint64_t os_words(uint64_t n_max, int bits) {
     const uint64_t p = (uint64_t)os_passes(bits);
-    return 64 + p * kRadix + p * os_tiles(n_max) * kRadix;
+    return 64 + p * kRadix * kHistStride + p * os_tiles(n_max) * kRadix;
 }
 
 constexpr int kOsThreads = 1024;
@@ -438,22 +439,30 @@ __global__ __launch_bounds__(kOsThreads) void k_os_hist(const K* keys, const uin
     const uint64_t n = n_dev ? *n_dev : n_max;
     for (int i = threadIdx.x; i < 8 * kRadix; i += kOsThreads) h[i / kRadix][i % kRadix] = 0;
     __syncthreads();
-    const uint64_t base = (uint64_t)blockIdx.x * kOsTile;
+    const uint64_t ntiles = (n + kOsTile - 1) / kOsTile;
+    for (uint64_t tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+        const uint64_t base = tl * kOsTile;
+        K kk[kOsRounds];
 #pragma unroll
-    for (int j = 0; j < kOsRounds; ++j) {
-        const uint64_t i = base + (uint64_t)j * kOsThreads + threadIdx.x;
-        const bool act = i < n;
-        const K key = act ? keys[i] : K(0);
-        for (int p = 0; p < passes; ++p) {
-            const uint32_t d = (uint32_t)(key >> (p * kRadixBits)) & (kRadix - 1);
-            const uint64_t peers = digit_peers(d, act);
-            if (act && rank_below(peers) == 0) atomicAdd(&h[p][d], popc64(peers));
+        for (int j = 0; j < kOsRounds; ++j) {
+            const uint64_t i = base + (uint64_t)j * kOsThreads + threadIdx.x;
+            kk[j] = i < n ? keys[i] : K(0);
+        }
+#pragma unroll
+        for (int j = 0; j < kOsRounds; ++j) {
+            const uint64_t i = base + (uint64_t)j * kOsThreads + threadIdx.x;
+            const bool act = i < n;
+            for (int p = 0; p < passes; ++p) {
+                const uint32_t d = (uint32_t)(kk[j] >> (p * kRadixBits)) & (kRadix - 1);
+                const uint64_t peers = digit_peers(d, act);
+                if (act && rank_below(peers) == 0) atomicAdd(&h[p][d], popc64(peers));
+            }
         }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < passes * kRadix; i += kOsThreads) {
         const uint32_t c = h[i / kRadix][i % kRadix];
-        if (c) atomicAdd(&hist[i], c);
+        if (c) atomicAdd(&hist[(uint64_t)i * kHistStride], c);
     }
 }
 
@@ -469,9 +478,12 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const K* kin, K* kout, c
     // cnt[round * waves + wave][digit]: counts, then exclusive prefixes
     __shared__ uint16_t cnt[kOsRounds * kOsWaves][kRadix];
     __shared__ uint32_t part[4][kRadix];
-    __shared__ uint32_t s_base[kRadix];
+    __shared__ uint32_t s_base[kRadix];   // global start of digit run of this tile
+    __shared__ uint32_t s_lstart[kRadix]; // start of digit run inside the tile
     __shared__ uint32_t s_w[kOsWaves];
     __shared__ uint32_t s_tile;
+    __shared__ K skey[kOsTile];
+    __shared__ uint32_t sval[HasVal ? kOsTile : 1];
     const uint32_t t = threadIdx.x;
     const int w = t >> 6;
     if (t == 0) s_tile = atomicAdd(counter, 1u);
@@ -546,19 +558,38 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const K* kin, K* kout, c
             st_release32(st, kOsIncl | (prefix + dcount));
         }
     }
-    // global start of each digit: exclusive scan of the pass histogram
+    // global start of each digit (pass histogram) and start inside the tile
     uint32_t tot;
-    const uint32_t gex = os_block_scan(t < kRadix ? hist[t] : 0u, s_w, tot);
-    if (t < kRadix) s_base[t] = gex + prefix;
+    const uint32_t gex = os_block_scan(t < kRadix ? hist[t * kHistStride] : 0u, s_w, tot);
+    const uint32_t lex = os_block_scan(t < kRadix ? dcount : 0u, s_w, tot);
+    if (t < kRadix) {
+        s_base[t] = gex + prefix;
+        s_lstart[t] = lex;
+    }
     __syncthreads();
+    // place keys in tile order of their digit, then write each digit run
+    // with consecutive lanes (coalesced)
 #pragma unroll
     for (int j = 0; j < kOsRounds; ++j) {
         const uint64_t i = base + (uint64_t)j * kOsThreads + t;
         if (i < n) {
             const uint32_t dd = (uint32_t)(key[j] >> shift) & (kRadix - 1);
-            const uint32_t pos = s_base[dd] + cnt[j * kOsWaves + w][dd] + rk[j];
-            kout[pos] = key[j];
-            if (HasVal) vout[pos] = val[j];
+            const uint32_t lp = s_lstart[dd] + cnt[j * kOsWaves + w][dd] + rk[j];
+            skey[lp] = key[j];
+            if (HasVal) sval[lp] = val[j];
+        }
+    }
+    __syncthreads();
+    const uint64_t tn = n > base ? min<uint64_t>(n - base, kOsTile) : 0;
+#pragma unroll
+    for (int j = 0; j < kOsRounds; ++j) {
+        const uint32_t lp = j * kOsThreads + t;
+        if (lp < tn) {
+            const K k = skey[lp];
+            const uint32_t dd = (uint32_t)(k >> shift) & (kRadix - 1);
+            const uint32_t pos = s_base[dd] + (lp - s_lstart[dd]);
+            kout[pos] = k;
+            if (HasVal) vout[pos] = sval[lp];
         }
     }
 }
@@ -576,9 +607,10 @@ bool onesweep(Ctx& c, K* k0, K* k1, uint32_t* v0, uint32_t* v1, const uint32_t* 
     if (passes > 8) fail(GV_EINVAL, "too many radix passes");
     const uint64_t nt = os_tiles(n_max);
     uint32_t* counters = state;           // 64 words
-    uint32_t* hist = state + 64;          // passes * 256
-    uint32_t* status = hist + (uint64_t)passes * kRadix;
-    c.launch("sort_hist", k_os_hist<K>, nt, kOsThreads, (const K*)k0, n_dev, n_max, passes, hist);
+    uint32_t* hist = state + 64;          // passes * 256 counters, one line each
+    uint32_t* status = hist + (uint64_t)passes * kRadix * kHistStride;
+    c.launch("sort_hist", k_os_hist<K>, std::min<uint64_t>(nt, 128), kOsThreads, (const K*)k0,
+             n_dev, n_max, passes, hist);
     bool flip = false;
     for (int p = 0; p < passes; ++p) {
         K* kin = flip ? k1 : k0;
@@ -587,7 +619,8 @@ bool onesweep(Ctx& c, K* k0, K* k1, uint32_t* v0, uint32_t* v1, const uint32_t* 
         uint32_t* vout = flip ? v0 : v1;
         c.launch("sort_pass", k_os_pass<K, HasVal>, nt, kOsThreads, (const K*)kin, kout,
                  (const uint32_t*)vin, vout, n_dev, n_max, p * kRadixBits,
-                 (const uint32_t*)(hist + (uint64_t)p * kRadix), status + (uint64_t)p * nt * kRadix,
+                 (const uint32_t*)(hist + (uint64_t)p * kRadix * kHistStride),
+                 status + (uint64_t)p * nt * kRadix,
                  counters + p, err);
         flip = !flip;
     }

@@ -135,45 +135,60 @@ __global__ __launch_bounds__(kThreads) void k_vdel_mark(GraphView g, const uint3
     }
 }
 
-// one wave per vertex: count (EMIT = false) or emit (EMIT = true) the edges
-// that touch a deleted vertex
+// 16-lane groups, one vertex each: count (EMIT = false) or emit (EMIT = true)
+// the edges that touch a deleted vertex; emitted pairs go to the vertex's
+// scanned offset, in slot order
+constexpr int kVGroup = 16;
+
 template <bool EMIT>
 __global__ __launch_bounds__(kThreads) void k_vdel_sweep(GraphView g, const uint32_t* gone,
+                                                         uint32_t* cnt,
+                                                         const unsigned long long* offs,
                                                          uint32_t* psrc, uint32_t* pdst,
                                                          uint64_t cap) {
     const uint32_t lane = lane_id();
-    const uint64_t nw = (uint64_t)gridDim.x * kWaves;
-    const uint64_t wave = ((uint64_t)blockIdx.x * kThreads + threadIdx.x) >> 6;
-    unsigned long long cnt = 0;
-    for (uint64_t u = wave; u < g.n_cap; u += nw) {
+    const uint32_t gl = lane & (kVGroup - 1);
+    const uint32_t g0 = lane & ~(uint32_t)(kVGroup - 1);
+    const uint64_t below = (1ull << gl) - 1;
+    const uint64_t ngroups = (uint64_t)gridDim.x * kThreads / kVGroup;
+    const uint64_t grp = ((uint64_t)blockIdx.x * kThreads + threadIdx.x) / kVGroup;
+    for (uint64_t u = grp; u < g.n_cap; u += ngroups) {
         const VRec r = g.vt[u];
-        if (r.deg == 0 || !is_active(g, u)) continue;
-        const bool src_gone = bit_of(gone, (uint32_t)u);
-        for (uint32_t s0 = 0; s0 < r.deg; s0 += 64) {
-            const uint32_t s = s0 + lane;
-            bool hit = false;
-            uint32_t x = 0;
-            if (s < r.deg) {
-                x = g.pool[slot_addr(g, r, s)];
-                hit = src_gone || bit_of(gone, x);
-            }
-            const uint64_t m = ballot(hit);
-            if (EMIT) {
-                unsigned long long base = 0;
-                if (m && lane == 0) base = atomicAdd(&g.ctr->checksum, (unsigned long long)popc64(m));
-                base = __shfl(base, 0, 64);
-                const uint64_t pos = base + rank_below(m);
-                if (hit && pos < cap) {
-                    psrc[pos] = (uint32_t)u;
-                    pdst[pos] = x;
+        uint32_t c = 0;
+        if (r.deg != 0 && is_active(g, u)) {
+            const bool src_gone = bit_of(gone, (uint32_t)u);
+            const uint64_t base = EMIT ? offs[u] : 0ull;
+            for (uint32_t s0 = 0; s0 < r.deg; s0 += kVGroup) {
+                const uint32_t s = s0 + gl;
+                bool hit = false;
+                uint32_t x = 0;
+                if (s < r.deg) {
+                    x = g.pool[slot_addr(g, r, s)];
+                    hit = src_gone || bit_of(gone, x);
                 }
-            } else {
-                cnt += popc64(m);
+                const uint64_t m = (ballot(hit) >> g0) & ((1ull << kVGroup) - 1);
+                if (EMIT && hit) {
+                    const uint64_t pos = base + c + popc64(m & below);
+                    if (pos < cap) {
+                        psrc[pos] = (uint32_t)u;
+                        pdst[pos] = x;
+                    }
+                }
+                c += popc64(m);
             }
         }
+        if (!EMIT && gl == 0) cnt[u] = c;
     }
-    if (!EMIT && lane == 0 && cnt) atomicAdd(&g.ctr->edges, cnt);
 }
+
+struct CntIn {
+    const uint32_t* cnt;
+    __device__ unsigned long long operator()(uint64_t i) const { return cnt[i]; }
+};
+struct U64Out {
+    unsigned long long* a;
+    __device__ void operator()(uint64_t i, unsigned long long v) const { a[i] = v; }
+};
 
 __global__ __launch_bounds__(kThreads) void k_vdel_finish(GraphView g, const uint32_t* keys,
                                                           uint64_t n, const uint32_t* gone) {
@@ -281,18 +296,28 @@ void vertex_delete(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats*
     const uint64_t rejected = g->hctr->st_rejected;
     const uint64_t uniq = g->hctr->n_uniq;
     if (applied) {
-        const uint64_t wgrid = std::min<uint64_t>(div_up(v.n_cap, kWaves), 4096);
-        c.launch("vdel_count", k_vdel_sweep<false>, wgrid, kThreads, v, (const uint32_t*)gone,
-                 (uint32_t*)nullptr, (uint32_t*)nullptr, (uint64_t)0);
+        const uint64_t vgrid = std::min<uint64_t>(div_up(v.n_cap * kVGroup, kThreads), 8192);
+        DevBuf cb((v.n_cap + 1) * (sizeof(uint32_t) + sizeof(unsigned long long)) +
+                  8 * (scan2_parts(v.n_cap) + scan_partials_needed(v.n_cap) + 2));
+        uint32_t* cnt = (uint32_t*)cb.p;
+        unsigned long long* offs = (unsigned long long*)(cnt + ((v.n_cap + 2) & ~1ull));
+        unsigned long long* part = offs + v.n_cap + 1;
+        c.launch("vdel_count", k_vdel_sweep<false>, vgrid, kThreads, v, (const uint32_t*)gone, cnt,
+                 (const unsigned long long*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr,
+                 (uint64_t)0);
+        if (scan2_parts(v.n_cap) <= kScan2MaxTiles)
+            scan2(c, "vdel_scan", CntIn{cnt}, U64Out{offs}, v.n_cap, part, &v.ctr->edges);
+        else
+            scan_excl<unsigned long long>(c, CntIn{cnt}, U64Out{offs}, v.n_cap, part,
+                                          &v.ctr->edges);
         read_counters(g);
         const uint64_t pairs = g->hctr->edges;
         if (pairs) {
             DevBuf pb(2 * pairs * sizeof(uint32_t));
             uint32_t* psrc = (uint32_t*)pb.p;
             uint32_t* pdst = psrc + pairs;
-            set_u64(g, &v.ctr->checksum, 0);
-            c.launch("vdel_emit", k_vdel_sweep<true>, wgrid, kThreads, v, (const uint32_t*)gone,
-                     psrc, pdst, pairs);
+            c.launch("vdel_emit", k_vdel_sweep<true>, vgrid, kThreads, v, (const uint32_t*)gone,
+                     cnt, (const unsigned long long*)offs, psrc, pdst, pairs);
             edge_batch(g, kDelete, psrc, pdst, pairs, nullptr, false);
             c.launch("vdel_finish", k_vdel_finish, div_up(n, kThreads), kThreads, g->v,
                      (const uint32_t*)sorted, n, (const uint32_t*)gone);

@@ -18,7 +18,8 @@ import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libgraphvine.so")
+# GRAPHVINE_LIB selects another build of the same library (tuning variants)
+LIB_PATH = os.environ.get("GRAPHVINE_LIB", os.path.join(HERE, "libgraphvine.so"))
 
 GV_OK, GV_EINVAL, GV_ERANGE, GV_ENOMEM, GV_EDEVICE = 0, 1, 2, 3, 4
 
@@ -97,6 +98,7 @@ def lib():
             "gv_profile_reset": [vp],
             "gv_profile_only": [vp, C.c_char_p],
             "gv_kernel_times": [vp, C.c_char_p, u64p, C.POINTER(C.c_double)],
+            "gv_kernel_names": [vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)],
             "gv_set_stream": [vp, vp],
             "gv_sync": [vp],
         }
@@ -286,6 +288,18 @@ def gv_kernel_times(g, name):
     _check(lib().gv_kernel_times(C.c_void_p(g), name.encode(), C.byref(n), C.byref(ms)),
            "gv_kernel_times")
     return n.value, ms.value
+
+
+def gv_kernel_names(g):
+    need = C.c_size_t()
+    rc = lib().gv_kernel_names(C.c_void_p(g), None, 0, C.byref(need))
+    if rc not in (0, GV_ERANGE):
+        _check(rc, "gv_kernel_names")
+    buf = C.create_string_buffer(need.value)
+    _check(lib().gv_kernel_names(C.c_void_p(g), buf, need.value, C.byref(need)),
+           "gv_kernel_names")
+    text = buf.value.decode()
+    return text.split(",") if text else []
 
 
 def gv_set_stream(g, stream_ptr):
