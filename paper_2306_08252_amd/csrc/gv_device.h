@@ -60,6 +60,7 @@ struct DevCounters {
     // errors: err_batch is reset per batch, err_sticky accumulates; err_wait
     // is set if a bounded look-back wait ever ran out
     uint32_t err_batch, err_sticky, err_wait, n_big;
+    uint32_t n_heavy, n_heavy_pad;     // sources left to whole waves this batch
     uint32_t sort_n, sort_err;  // count and look-back error word of whole-graph sorts
     // totals of the single-pass scans of the current batch
     unsigned long long tot[8];
@@ -107,6 +108,14 @@ __device__ __forceinline__ uint32_t popc64(uint64_t m) { return __popcll(m); }
 
 __device__ __forceinline__ bool is_active(const GraphView& g, uint64_t v) {
     return v < g.n_cap && ((g.active[v >> 5] >> (v & 31)) & 1u);
+}
+
+// is_active without a branch around the bitmap read (ids >= n_cap read word 0)
+__device__ __forceinline__ bool active_bit(const GraphView& g, uint32_t v) {
+    const bool in = v < g.n_cap;
+    const uint32_t c = in ? v : 0u;
+    const uint32_t w = g.active[c >> 5];
+    return in & (((w >> (c & 31)) & 1u) != 0u);
 }
 
 __device__ __forceinline__ uint32_t nblocks(const GraphView& g, uint32_t deg) {
@@ -157,6 +166,19 @@ __device__ __forceinline__ T wave_sum(T x) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
     return x;
+}
+
+// Appends x to `list` (for the lanes with take set) at slots reserved with
+// one atomic per wave.  Every active lane of the wave must make the call.
+__device__ __forceinline__ void wave_append(bool take, uint32_t x, uint32_t* counter,
+                                            uint32_t* list) {
+    const uint64_t m = ballot(take);
+    if (!m) return;
+    const uint32_t leader = (uint32_t)__ffsll((unsigned long long)m) - 1;
+    uint32_t base = 0;
+    if (lane_id() == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
+    base = __shfl(base, (int)leader, 64);
+    if (take) list[base + rank_below(m)] = x;
 }
 
 // exclusive scan across a kThreads workgroup; `total` receives the sum.

@@ -48,8 +48,13 @@ constexpr uint8_t kHead = 1, kUniq = 2;
 constexpr int kGroup = GV_PROBE_GROUP;         // lanes per work item
 constexpr int kGroupsPerWave = 64 / kGroup;
 constexpr int kStage = 128;                    // segment entries staged in LDS
+constexpr int kStageLog = 7;                   // log2(kStage)
+constexpr int kWinLog = 12;                    // unrolled global search steps
 constexpr int kUnroll = GV_PROBE_UNROLL;       // slots per lane per step
 constexpr uint32_t kBigR = 256;                // deletes per source handled by a workgroup
+constexpr uint32_t kLaneCopy = 8;              // directory entries a lane copies or adds
+constexpr uint32_t kLaneSeg = 8;               // segment entries a lane compacts
+constexpr uint32_t kLaneR = 4;                 // hits a lane compacts
 
 // scan-total slots in DevCounters::tot
 enum { kTotValid = 0, kTotSeg = 1, kTotItems = 2, kTotA = 3, kTotB = 4 };
@@ -88,6 +93,7 @@ struct BatchArrays {
     uint32_t* t_doldc;  // insert: replaced directory segment class or kNoDir
     CDesc* cdesc;       // delete: compaction descriptors
     uint32_t* big;      // delete: sources with more than kBigR hits
+    uint32_t* heavy;    // sources left to whole waves
     Item* items;        // work items
     unsigned long long* part;  // scan partials
     uint32_t* state;    // zeroed look-back state of the sort
@@ -113,6 +119,7 @@ static void carve_batch(Carver& cv, BatchArrays& A, uint64_t n, uint64_t icap, E
         A.cdesc = cv.take<CDesc>(n);
         A.big = cv.take<uint32_t>(n);
     }
+    A.heavy = cv.take<uint32_t>(n);
     A.t_vtx = cv.take<uint32_t>(n);
     A.t_start = cv.take<uint32_t>(n + 1);
     A.t_need = cv.take<uint32_t>(n + 1);
@@ -143,33 +150,40 @@ __global__ __launch_bounds__(kThreads) void k_begin(GraphView g, uint32_t* state
     if (thread_index() == 0) {
         g.ctr->err_batch = 0;
         g.ctr->n_big = 0;
+        g.ctr->n_heavy = 0;
         for (int k = 0; k < 8; ++k) g.ctr->tot[k] = 0;
     }
 }
 
 // ------------------------------------------------------------------ pack
+// Scan sources follow the gather interface of scan2: load() performs every
+// memory read of an element at addresses that are valid whether or not the
+// element is live, value() and the sinks only compute and store.
 struct PackIn {
     GraphView g;
     const uint32_t* src;
     const uint32_t* dst;
-    __device__ unsigned long long operator()(uint64_t i) const {
-        return (is_active(g, src[i]) && is_active(g, dst[i])) ? 1ull : 0ull;
-    }
+    struct Rec {
+        uint32_t s, d;
+        bool ok;
+    };
+    __device__ uint64_t limit(uint64_t n) const { return n; }
+    __device__ Rec load(uint64_t i, bool) const { return Rec{src[i], dst[i], false}; }
+    __device__ void deref(Rec& r) const { r.ok = active_bit(g, r.s) & active_bit(g, r.d); }
+    __device__ unsigned long long value(uint64_t, const Rec& r) const { return r.ok ? 1ull : 0ull; }
 };
 
 struct PackOut {
-    GraphView g;
-    const uint32_t* src;
-    const uint32_t* dst;
+    uint32_t L;
     uint64_t* keys;
     uint32_t* vals;     // queries: input position of each valid key
     uint8_t* answer;    // queries: invalid pairs are answered here
     uint8_t* mark;
-    __device__ void operator()(uint64_t i, unsigned long long pos) const {
-        const uint32_t s = src[i], d = dst[i];
+    __device__ void operator()(uint64_t i, const PackIn::Rec& r, uint64_t,
+                               unsigned long long pos) const {
         mark[i] = 0;
-        if (is_active(g, s) && is_active(g, d)) {
-            keys[pos] = ((uint64_t)s << g.L) | d;
+        if (r.ok) {
+            keys[pos] = ((uint64_t)r.s << L) | r.d;
             if (vals) vals[pos] = (uint32_t)i;
         } else if (answer) {
             answer[i] = 0;
@@ -182,43 +196,41 @@ struct SegIn {
     const uint64_t* keys;
     const unsigned long long* n_valid;
     uint32_t L;
-    __device__ unsigned long long operator()(uint64_t i) const {
-        if (i >= *n_valid) return 0ull;
-        const uint64_t k = keys[i];
-        if (i == 0) return 1ull | (1ull << 32);
-        const uint64_t p = keys[i - 1];
-        const unsigned long long head = (k >> L) != (p >> L);
-        const unsigned long long uniq = k != p;
+    struct Rec {
+        uint64_t k, p;
+    };
+    __device__ uint64_t limit(uint64_t n) const { return min((uint64_t)*n_valid, n); }
+    __device__ Rec load(uint64_t i, bool ok) const {
+        const uint64_t j = ok ? i : 0;
+        return Rec{keys[j], keys[j ? j - 1 : 0]};
+    }
+    __device__ void deref(Rec&) const {}
+    __device__ unsigned long long value(uint64_t i, const Rec& r) const {
+        const unsigned long long head = i == 0 || (r.k >> L) != (r.p >> L);
+        const unsigned long long uniq = i == 0 || r.k != r.p;
         return head | (uniq << 32);
     }
 };
 
 struct SegOut {
-    const uint64_t* keys;
-    const unsigned long long* n_valid;
     uint32_t L;
     uint8_t* flags;
     uint32_t* a;
     uint32_t* t_vtx;
     uint32_t* t_start;
-    __device__ void operator()(uint64_t i, unsigned long long pre) const {
-        const uint64_t nv = *n_valid;
+    __device__ void operator()(uint64_t i, const SegIn::Rec& r, uint64_t nv,
+                               unsigned long long pre) const {
         if (i >= nv) {
             if (i == 0) t_start[0] = 0;
             return;
         }
-        const uint64_t k = keys[i];
-        bool head = true, uniq = true;
-        if (i > 0) {
-            const uint64_t p = keys[i - 1];
-            head = (k >> L) != (p >> L);
-            uniq = k != p;
-        }
+        const bool head = i == 0 || (r.k >> L) != (r.p >> L);
+        const bool uniq = i == 0 || r.k != r.p;
         const uint32_t t = (uint32_t)pre + (head ? 1u : 0u) - 1u;  // segment of key i
         flags[i] = (head ? kHead : 0) | (uniq ? kUniq : 0);
         a[i] = t;
         if (head) {
-            t_vtx[t] = (uint32_t)(k >> L);
+            t_vtx[t] = (uint32_t)(r.k >> L);
             t_start[t] = (uint32_t)i;
         }
         if (i + 1 == nv) t_start[t + 1] = (uint32_t)nv;
@@ -226,32 +238,51 @@ struct SegOut {
 };
 
 // ------------------------------------------------------------------ items
+// a touched source, its batch segment and its vertex record
+struct TouchRec {
+    uint32_t v, lo, hi;
+    VRec r;
+};
+
+__device__ __forceinline__ TouchRec load_touched(const uint32_t* t_vtx, const uint32_t* t_start,
+                                                 uint64_t t, bool ok) {
+    const uint64_t j = ok ? t : 0;
+    const uint32_t v0 = t_vtx[j], lo0 = t_start[j], hi0 = t_start[j + 1];
+    TouchRec x;
+    x.v = ok ? v0 : 0u;
+    x.lo = ok ? lo0 : 0u;
+    x.hi = ok ? hi0 : 0u;
+    return x;
+}
+
 struct ItemIn {
     GraphView g;
     const uint32_t* t_vtx;
-    __device__ unsigned long long operator()(uint64_t t) const {
-        if (t >= (uint32_t)g.ctr->tot[kTotSeg]) return 0ull;
-        const uint32_t d = g.vt[t_vtx[t]].deg;
-        const unsigned long long items = (d + kChunk - 1) / kChunk;
-        return items | ((unsigned long long)nblocks(g, d) << 32);
+    const uint32_t* t_start;
+    using Rec = TouchRec;
+    __device__ uint64_t limit(uint64_t n) const {
+        return min((uint64_t)(uint32_t)g.ctr->tot[kTotSeg], n);
+    }
+    __device__ Rec load(uint64_t t, bool ok) const { return load_touched(t_vtx, t_start, t, ok); }
+    __device__ void deref(Rec& x) const { x.r = g.vt[x.v]; }
+    __device__ unsigned long long value(uint64_t, const Rec& x) const {
+        const unsigned long long items = (x.r.deg + kChunk - 1) / kChunk;
+        return items | ((unsigned long long)nblocks(g, x.r.deg) << 32);
     }
 };
 
 struct ItemOut {
-    GraphView g;
-    const uint32_t* t_vtx;
-    const uint32_t* t_start;
     Item* items;
-    __device__ void operator()(uint64_t t, unsigned long long pre) const {
-        if (t >= (uint32_t)g.ctr->tot[kTotSeg]) return;
-        const uint32_t v = t_vtx[t];
-        const VRec r = g.vt[v];
+    __device__ void operator()(uint64_t t, const TouchRec& x, uint64_t lim,
+                               unsigned long long pre) const {
+        if (t >= lim) return;
+        const VRec r = x.r;
         const uint32_t cnt = (r.deg + kChunk - 1) / kChunk;
         const uint32_t base = (uint32_t)pre;
         Item it;
-        it.lo = t_start[t];
-        it.hi = t_start[t + 1];
-        it.v = v;
+        it.lo = x.lo;
+        it.hi = x.hi;
+        it.v = x.v;
         it.dirbase = r.dcls != kNoDir ? r.dir : 0u;
         it.blk0 = r.dcls != kNoDir ? 0u : r.dir;
         it.dcls = r.dcls;
@@ -298,18 +329,8 @@ __device__ __forceinline__ void probe_load(const GraphView& g, const Item& I, co
     for (int u = 0; u < kUnroll; ++u) x[u] = g.pool[addr[u]];
 }
 
-// number of entries < x among st[0, 2^steps - 1), which holds the sorted
-// samples padded with 0xFFFFFFFF (at least one pad entry); branch-free,
-// uniform trip count
-__device__ __forceinline__ uint32_t lds_rank(const uint32_t* st, uint32_t steps, uint32_t x) {
-    uint32_t pos = 0;
-    for (uint32_t k = steps; k-- > 0;) {
-        const uint32_t half = 1u << k;
-        pos += (st[pos + half - 1] < x) ? half : 0u;
-    }
-    return pos;
-}
-
+// Searches of the kUnroll slots of a lane run in lockstep, so that each step
+// issues kUnroll independent reads and waits once.
 template <int MODE>
 __device__ __forceinline__ void probe_search(const GraphView& g, const Item& I, uint32_t s,
                                              const uint32_t (&x)[kUnroll],
@@ -318,42 +339,76 @@ __device__ __forceinline__ void probe_search(const GraphView& g, const Item& I, 
                                              uint8_t* mark, uint32_t* hitpos) {
     const uint32_t len = I.hi - I.lo;
     const uint64_t vbase = (uint64_t)I.v << g.L;
+    // rank among the LDS samples: st[0, 2^steps - 1) holds the sorted samples
+    // padded with 0xFFFFFFFF (at least one pad entry, so the rank can reach ns)
     uint32_t lo[kUnroll];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) lo[u] = lds_rank(st, steps, x[u]);
+    for (int u = 0; u < kUnroll; ++u) lo[u] = 0;
+    // unrolled to the largest step count so that no loop carries outstanding
+    // loads (the next step's slot loads stay in flight meanwhile)
+#pragma unroll
+    for (int k = kStageLog - 1; k >= 0; --k) {
+        if ((uint32_t)k >= steps) continue;
+        const uint32_t half = 1u << k;
+        uint32_t sv[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) sv[u] = st[lo[u] + half - 1];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) lo[u] += sv[u] < x[u] ? half : 0u;
+    }
+    uint32_t p[kUnroll];  // first segment position whose value is >= x
+    bool hit[kUnroll];
+    if (shift == 0) {
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            p[u] = lo[u];
+            const uint32_t v = st[lo[u]];  // lo <= ns < kStage
+            hit[u] = (lo[u] < len) & (v == x[u]);
+        }
+    } else {
+        // the answer lies in ((lo - 1) * stride, lo * stride]: a window of
+        // fewer than 2^shift entries before the sample at lo * stride (or
+        // the end of the segment); branch-free lower bound in `shift` steps
+        uint32_t end[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            p[u] = lo[u] ? ((lo[u] - 1) << shift) + 1 : 0;
+            end[u] = min(lo[u] << shift, len);
+        }
+        auto step = [&](uint32_t half) {
+            uint64_t kv[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) kv[u] = keys[I.lo + min(p[u] + half - 1, len - 1)];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u)
+                p[u] += (p[u] + half - 1 < end[u] && kv[u] < (vbase | x[u])) ? half : 0u;
+        };
+        // windows of up to 2^kWinLog entries take unrolled steps; longer ones
+        // (segments beyond about half a million pairs) a loop
+        for (uint32_t k = shift; k-- > kWinLog;) step(1u << k);
+#pragma unroll
+        for (int k = kWinLog - 1; k >= 0; --k)
+            if ((uint32_t)k < shift) step(1u << k);
+        uint64_t kv[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) kv[u] = keys[I.lo + min(p[u], len - 1)];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) hit[u] = p[u] < len && kv[u] == (vbase | x[u]);
+    }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
         const uint32_t si = s + u * kGroup;
-        if (si >= I.s1) continue;
-        uint32_t p;  // first segment position whose value is >= x
-        bool hit;
-        const uint64_t target = vbase | x[u];
-        if (shift == 0) {
-            p = lo[u];
-            hit = p < len && st[p] == x[u];
+        if (si >= I.s1 || !hit[u]) continue;
+        const uint32_t pos = I.lo + p[u];
+        if (MODE == kInsert) {
+            mark[pos] = 1;
+        } else if (MODE == kDelete) {
+            mark[pos] = 1;
+            hitpos[pos] = si;
+            g.pool[addr[u]] = kTomb;
         } else {
-            // the answer lies in ((lo - 1) * stride, lo * stride]
-            uint32_t a = lo[u] ? ((lo[u] - 1) << shift) + 1 : 0;
-            uint32_t b = min(lo[u] << shift, len);
-            while (a < b) {
-                const uint32_t mid = (a + b) >> 1;
-                if (keys[I.lo + mid] < target) a = mid + 1;
-                else b = mid;
-            }
-            p = a;
-            hit = a < len && keys[I.lo + a] == target;
-        }
-        if (hit) {
-            const uint32_t pos = I.lo + p;
-            if (MODE == kInsert) {
-                mark[pos] = 1;
-            } else if (MODE == kDelete) {
-                mark[pos] = 1;
-                hitpos[pos] = si;
-                g.pool[addr[u]] = kTomb;
-            } else {
-                for (uint32_t j = pos; j < I.hi && keys[j] == target; ++j) mark[j] = 1;
-            }
+            const uint64_t target = vbase | x[u];
+            for (uint32_t j = pos; j < I.hi && keys[j] == target; ++j) mark[j] = 1;
         }
     }
 }
@@ -420,20 +475,21 @@ __global__ __launch_bounds__(kThreads) void k_probe(GraphView g, const uint64_t*
             st[j] = j < ns ? sv[r] : 0xFFFFFFFFu;
         }
         wave_lds_sync();
-        // ping-pong between two register sets: load step k+1, search step k
-        uint32_t x2[kUnroll];
-        uint64_t a2[kUnroll];
+        // the loads of step k+1 are issued before step k is searched and
+        // copied over after it, so they overlap the search
         while (true) {
             const bool more = s + kGroup * kUnroll - gl < I.s1;  // uniform in the group
+            uint32_t x2[kUnroll];
+            uint64_t a2[kUnroll];
             if (more) probe_load<MODE>(g, I, dp, s + kGroup * kUnroll, x2, a2);
             probe_search<MODE>(g, I, s, x, addr, st, steps, shift, keys, mark, hitpos);
             if (!more) break;
             s += kGroup * kUnroll;
-            const bool more2 = s + kGroup * kUnroll - gl < I.s1;
-            if (more2) probe_load<MODE>(g, I, dp, s + kGroup * kUnroll, x, addr);
-            probe_search<MODE>(g, I, s, x2, a2, st, steps, shift, keys, mark, hitpos);
-            if (!more2) break;
-            s += kGroup * kUnroll;
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                x[u] = x2[u];
+                addr[u] = a2[u];
+            }
         }
         wave_lds_sync();
         if (itn >= nitems) break;
@@ -447,21 +503,32 @@ struct KeepIn {
     const uint8_t* flags;
     const uint8_t* mark;
     const unsigned long long* n_valid;
-    __device__ unsigned long long operator()(uint64_t i) const {
-        if (i >= *n_valid) return 0ull;
-        return ((flags[i] & kUniq) && !mark[i]) ? 1ull : 0ull;
+    struct Rec {
+        uint8_t f, m;
+    };
+    __device__ uint64_t limit(uint64_t n) const { return min((uint64_t)*n_valid, n); }
+    __device__ Rec load(uint64_t i, bool ok) const {
+        const uint64_t j = ok ? i : 0;
+        return Rec{flags[j], mark[j]};
+    }
+    __device__ void deref(Rec&) const {}
+    __device__ unsigned long long value(uint64_t, const Rec& r) const {
+        return ((r.f & kUniq) && !r.m) ? 1ull : 0ull;
     }
 };
 
 struct U32Out {
     uint32_t* a;
-    __device__ void operator()(uint64_t i, unsigned long long v) const { a[i] = (uint32_t)v; }
+    template <typename R>
+    __device__ void operator()(uint64_t i, const R&, uint64_t, unsigned long long v) const {
+        a[i] = (uint32_t)v;
+    }
 };
 
 __global__ __launch_bounds__(kThreads) void k_plan_ins(GraphView g, const uint32_t* t_vtx,
                                                        const uint32_t* t_start, const uint32_t* b,
                                                        uint32_t* t_need, uint32_t* t_dreq,
-                                                       uint32_t* t_drank) {
+                                                       uint32_t* t_drank, uint32_t* heavy) {
     __shared__ uint32_t lcnt[kMaxClass];
     __shared__ uint32_t lbase[kMaxClass];
     if (threadIdx.x < kMaxClass) lcnt[threadIdx.x] = 0;
@@ -469,6 +536,7 @@ __global__ __launch_bounds__(kThreads) void k_plan_ins(GraphView g, const uint32
     const uint64_t t = thread_index();
     const uint32_t nT = (uint32_t)g.ctr->tot[kTotSeg];
     uint32_t cls = kNoDir, lrank = 0;
+    bool big = false;
     if (t < nT) {
         const uint32_t kp = b[t_start[t + 1]] - b[t_start[t]];
         const VRec r = g.vt[t_vtx[t]];
@@ -480,7 +548,9 @@ __global__ __launch_bounds__(kThreads) void k_plan_ins(GraphView g, const uint32
             lrank = atomicAdd(&lcnt[cls], 1u);
         }
         t_dreq[t] = cls;
+        big = (cls != kNoDir && nb0 > kLaneCopy) || nb1 - nb0 > kLaneCopy;
     }
+    wave_append(big, (uint32_t)t, &g.ctr->n_heavy, heavy);
     __syncthreads();
     if (threadIdx.x < kMaxClass) {
         const uint32_t c = lcnt[threadIdx.x];
@@ -493,9 +563,15 @@ __global__ __launch_bounds__(kThreads) void k_plan_ins(GraphView g, const uint32
 struct NeedIn {
     const uint32_t* t_need;
     const DevCounters* ctr;
-    __device__ unsigned long long operator()(uint64_t t) const {
-        return t < (uint32_t)ctr->tot[kTotSeg] ? t_need[t] : 0ull;
+    struct Rec {
+        uint32_t need;
+    };
+    __device__ uint64_t limit(uint64_t n) const {
+        return min((uint64_t)(uint32_t)ctr->tot[kTotSeg], n);
     }
+    __device__ Rec load(uint64_t t, bool ok) const { return Rec{t_need[ok ? t : 0]}; }
+    __device__ void deref(Rec&) const {}
+    __device__ unsigned long long value(uint64_t, const Rec& r) const { return r.need; }
 };
 
 // Allocation plan for the whole batch, one thread: capacity is checked
@@ -554,31 +630,113 @@ __global__ void k_plan(GraphView g, uint64_t n, int sticky) {
 
 // One wave per touched source: grow its directory segment if needed (copy the
 // old entries) and record the ids of its new blocks.
+// id of the p-th block the batch allocates (free-list top first, then bump)
+__device__ __forceinline__ uint32_t planned_block(const GraphView& g, const DevCounters* c,
+                                                  uint64_t p) {
+    return p < c->plan_from_free ? g.free_stack[c->plan_free_top - 1 - p]
+                                 : (uint32_t)(c->plan_bump0 + (p - c->plan_from_free));
+}
+
+// Append: every kept pair is written to slot deg + rank of its source, read
+// from the vertex record as it was before the batch; new blocks come from
+// the allocation plan, so this runs before the directory is updated.
+__global__ __launch_bounds__(kThreads) void k_append(GraphView g, const uint64_t* keys,
+                                                     const uint8_t* flags, const uint8_t* mark,
+                                                     const uint32_t* a, const uint32_t* b,
+                                                     const uint32_t* t_vtx,
+                                                     const uint32_t* t_start,
+                                                     const uint32_t* t_need) {
+    const DevCounters* c = g.ctr;
+    if (c->err_batch) return;
+    const uint64_t i = thread_index();
+    if (i >= c->tot[kTotValid]) return;
+    const uint8_t f = flags[i], m = mark[i];
+    const uint32_t t = a[i], bi = b[i];
+    const uint64_t key = keys[i];
+    if (!(f & kUniq) || m) return;
+    const uint32_t v = t_vtx[t], lo = t_start[t], p0 = t_need[t];
+    const VRec r = g.vt[v];
+    const uint32_t sl = r.deg + (bi - b[lo]);
+    const uint32_t j = sl >> g.log2B, nb0 = nblocks(g, r.deg);
+    const uint32_t blk = j < nb0 ? block_of(g, r, j) : planned_block(g, c, (uint64_t)p0 + (j - nb0));
+    g.pool[((uint64_t)blk << g.log2B) + (sl & (g.B - 1))] = (uint32_t)(key & ((1ull << g.L) - 1));
+}
+
+__device__ __forceinline__ uint32_t planned_segment(const GraphView& g, const DevCounters* c,
+                                                    uint32_t cls, uint32_t rk) {
+    return rk < c->plan_dff[cls]
+               ? g.dfree[g.dfree_base[cls] + c->plan_dtop[cls] - 1 - rk]
+               : (uint32_t)(c->plan_dbump[cls] + ((unsigned long long)(rk - c->plan_dff[cls]) << cls));
+}
+
+// Grow: every touched source with kept pairs gets its new block ids (and,
+// when its block count outgrows its directory segment, a new segment holding
+// a copy of the old entries) and its new vertex record.  A lane takes a
+// source that copies and adds at most kLaneCopy entries; the others, listed
+// by the planning kernel, are taken by whole waves afterwards.
 __global__ __launch_bounds__(kThreads) void k_grow(GraphView g, const uint32_t* t_vtx,
                                                    const uint32_t* t_start, const uint32_t* b,
                                                    const uint32_t* t_need, const uint32_t* t_dreq,
                                                    const uint32_t* t_drank, uint32_t* t_dold,
-                                                   uint32_t* t_doldc) {
+                                                   uint32_t* t_doldc, const uint32_t* heavy) {
     const DevCounters* c = g.ctr;
     if (c->err_batch) return;
     const uint32_t nT = (uint32_t)c->tot[kTotSeg];
     const uint32_t lane = lane_id();
+    const uint32_t stride = gridDim.x * kThreads;
+    for (uint32_t base = global_wave() * 64; base < nT; base += stride) {
+        const bool live = base + lane < nT;
+        const uint32_t t = live ? base + lane : nT - 1;
+        const uint32_t v = t_vtx[t], lo = t_start[t], hi = t_start[t + 1];
+        const uint32_t p0 = t_need[t], cls = t_dreq[t], rk = t_drank[t];
+        const VRec r = g.vt[v];
+        const uint32_t kp = b[hi] - b[lo];
+        const uint32_t nb0 = nblocks(g, r.deg), nb1 = nblocks(g, r.deg + kp);
+        const bool big = (cls != kNoDir && nb0 > kLaneCopy) || nb1 - nb0 > kLaneCopy;
+        if (!live || !kp || big) continue;
+        VRec nr = r;
+        nr.deg = r.deg + kp;
+        if (cls != kNoDir) {
+            const uint32_t off = planned_segment(g, c, cls, rk);
+            uint32_t old[kLaneCopy];
+#pragma unroll
+            for (uint32_t j = 0; j < kLaneCopy; ++j) old[j] = block_of(g, r, min(j, nb0 - 1));
+#pragma unroll
+            for (uint32_t j = 0; j < kLaneCopy; ++j)
+                if (j < nb0) g.dir[(uint64_t)off + j] = old[j];
+            t_dold[t] = r.dir;
+            t_doldc[t] = r.dcls;
+            nr.dir = off;
+            nr.dcls = cls;
+        }
+        const uint32_t nnew = nb1 - nb0;
+        if (nnew) {
+            uint32_t ids[kLaneCopy];
+#pragma unroll
+            for (uint32_t j = 0; j < kLaneCopy; ++j)
+                ids[j] = planned_block(g, c, (uint64_t)p0 + min(j, nnew - 1));
+#pragma unroll
+            for (uint32_t j = 0; j < kLaneCopy; ++j) {
+                if (j >= nnew) continue;
+                if (nr.dcls == kNoDir) nr.dir = ids[j];  // the only block, inline
+                else g.dir[(uint64_t)nr.dir + nb0 + j] = ids[j];
+            }
+        }
+        g.vt[v] = nr;
+    }
+    const uint32_t nh = c->n_heavy;
     const uint32_t nw = gridDim.x * kWaves;
-    for (uint32_t t = global_wave(); t < nT; t += nw) {
+    for (uint32_t k = global_wave(); k < nh; k += nw) {
+        const uint32_t t = heavy[k];
         const uint32_t v = t_vtx[t];
         const VRec r = g.vt[v];
         const uint32_t kp = b[t_start[t + 1]] - b[t_start[t]];
         const uint32_t nb0 = nblocks(g, r.deg), nb1 = nblocks(g, r.deg + kp);
         const uint32_t cls = t_dreq[t];
         VRec nr = r;
+        nr.deg = r.deg + kp;
         if (cls != kNoDir) {
-            const uint32_t rk = t_drank[t];
-            uint32_t off;
-            if (rk < c->plan_dff[cls])
-                off = g.dfree[g.dfree_base[cls] + c->plan_dtop[cls] - 1 - rk];
-            else
-                off = (uint32_t)(c->plan_dbump[cls] +
-                                 ((unsigned long long)(rk - c->plan_dff[cls]) << cls));
+            const uint32_t off = planned_segment(g, c, cls, t_drank[t]);
             for (uint32_t j = lane; j < nb0; j += 64) g.dir[(uint64_t)off + j] = block_of(g, r, j);
             if (lane == 0) {
                 t_dold[t] = r.dir;
@@ -586,42 +744,17 @@ __global__ __launch_bounds__(kThreads) void k_grow(GraphView g, const uint32_t* 
             }
             nr.dir = off;
             nr.dcls = cls;
-        } else if (lane == 0) {
-            t_doldc[t] = kNoDir;
         }
         const uint64_t p0 = t_need[t];
-        for (uint32_t j = nb0 + lane; j < nb1; j += 64) {
-            const uint64_t p = p0 + (j - nb0);
-            const uint32_t id = p < c->plan_from_free
-                                    ? g.free_stack[c->plan_free_top - 1 - p]
-                                    : (uint32_t)(c->plan_bump0 + (p - c->plan_from_free));
-            if (nr.dcls == kNoDir) nr.dir = id;  // inline: only block 0, lane 0
-            else g.dir[(uint64_t)nr.dir + j] = id;
-        }
+        for (uint32_t j = nb0 + lane; j < nb1; j += 64)
+            g.dir[(uint64_t)nr.dir + j] = planned_block(g, c, p0 + (j - nb0));
         if (lane == 0) g.vt[v] = nr;
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_append(GraphView g, const uint64_t* keys,
-                                                     const uint8_t* flags, const uint8_t* mark,
-                                                     const uint32_t* a, const uint32_t* b,
-                                                     const uint32_t* t_vtx,
-                                                     const uint32_t* t_start) {
-    if (g.ctr->err_batch) return;
-    const uint64_t i = thread_index();
-    if (i >= g.ctr->tot[kTotValid]) return;
-    const uint8_t f = flags[i];
-    if (!(f & kUniq) || mark[i]) return;
-    const uint32_t t = a[i];
-    const uint32_t v = t_vtx[t];
-    const VRec r = g.vt[v];
-    const uint32_t s = r.deg + (b[i] - b[t_start[t]]);
-    g.pool[slot_addr(g, r, s)] = (uint32_t)(keys[i] & ((1ull << g.L) - 1));
-}
-
-__global__ __launch_bounds__(kThreads) void k_final_ins(GraphView g, const uint32_t* t_vtx,
-                                                        const uint32_t* t_start, const uint32_t* b,
-                                                        const uint32_t* t_dreq,
+// Old directory segments of the sources that moved go on the per-class free
+// lists (after the commit kernel has taken its segments from them).
+__global__ __launch_bounds__(kThreads) void k_final_ins(GraphView g, const uint32_t* t_dreq,
                                                         const uint32_t* t_dold,
                                                         const uint32_t* t_doldc) {
     __shared__ uint32_t lcnt[kMaxClass];
@@ -633,16 +766,11 @@ __global__ __launch_bounds__(kThreads) void k_final_ins(GraphView g, const uint3
     const bool ok = !g.ctr->err_batch;
     const uint64_t t = thread_index();
     uint32_t oc = kNoDir, lrank = 0;
-    if (ok && t < (uint32_t)g.ctr->tot[kTotSeg]) {
-        const uint32_t kp = b[t_start[t + 1]] - b[t_start[t]];
-        const uint32_t v = t_vtx[t];
-        if (kp) g.vt[v].deg += kp;
-        if (t_dreq[t] != kNoDir) {
-            oc = t_doldc[t];
-            if (oc != kNoDir) {
-                lrank = atomicAdd(&lcnt[oc], 1u);
-                atomicAdd(&lfreed, 1ull << oc);
-            }
+    if (ok && t < (uint32_t)g.ctr->tot[kTotSeg] && t_dreq[t] != kNoDir) {
+        oc = t_doldc[t];
+        if (oc != kNoDir) {
+            lrank = atomicAdd(&lcnt[oc], 1u);
+            atomicAdd(&lfreed, 1ull << oc);
         }
     }
     __syncthreads();
@@ -660,9 +788,19 @@ __global__ __launch_bounds__(kThreads) void k_final_ins(GraphView g, const uint3
 struct FoundIn {
     const uint8_t* mark;
     const unsigned long long* n_valid;
-    __device__ unsigned long long operator()(uint64_t i) const {
-        return i < *n_valid ? (unsigned long long)mark[i] : 0ull;
-    }
+    struct Rec {
+        uint8_t m;
+    };
+    __device__ uint64_t limit(uint64_t n) const { return min((uint64_t)*n_valid, n); }
+    __device__ Rec load(uint64_t i, bool ok) const { return Rec{mark[ok ? i : 0]}; }
+    __device__ void deref(Rec&) const {}
+    __device__ unsigned long long value(uint64_t, const Rec& r) const { return r.m; }
+};
+
+// a touched source of a delete batch with its hit count r
+struct FreedRec {
+    TouchRec x;
+    uint32_t r;
 };
 
 struct FreedIn {
@@ -670,100 +808,181 @@ struct FreedIn {
     const uint32_t* t_vtx;
     const uint32_t* t_start;
     const uint32_t* b;
-    __device__ unsigned long long operator()(uint64_t t) const {
-        if (t >= (uint32_t)g.ctr->tot[kTotSeg]) return 0ull;
-        const uint32_t r = b[t_start[t + 1]] - b[t_start[t]];
-        if (!r) return 0ull;
-        const uint32_t d = g.vt[t_vtx[t]].deg;
-        return nblocks(g, d) - nblocks(g, d - r);
+    using Rec = FreedRec;
+    __device__ uint64_t limit(uint64_t n) const {
+        return min((uint64_t)(uint32_t)g.ctr->tot[kTotSeg], n);
+    }
+    __device__ Rec load(uint64_t t, bool ok) const {
+        return Rec{load_touched(t_vtx, t_start, t, ok), 0u};
+    }
+    __device__ void deref(Rec& f) const {
+        f.x.r = g.vt[f.x.v];
+        f.r = b[f.x.hi] - b[f.x.lo];
+    }
+    __device__ unsigned long long value(uint64_t, const Rec& f) const {
+        const uint32_t d = f.x.r.deg;
+        return f.r ? nblocks(g, d) - nblocks(g, d - f.r) : 0ull;
     }
 };
+
+// a source that one lane compacts by itself
+__device__ __forceinline__ bool lane_compactable(uint32_t r, uint32_t lo, uint32_t hi) {
+    return r <= kLaneR && hi - lo <= kLaneSeg;
+}
 
 struct FreedOut {
-    GraphView g;
-    const uint32_t* t_vtx;
-    const uint32_t* t_start;
-    const uint32_t* b;
+    DevCounters* ctr;
     CDesc* cd;
     uint32_t* big;
-    __device__ void operator()(uint64_t t, unsigned long long pre) const {
-        if (t >= (uint32_t)g.ctr->tot[kTotSeg]) return;
+    uint32_t* mid;  // sources for whole waves
+    __device__ void operator()(uint64_t t, const FreedRec& f, uint64_t lim,
+                               unsigned long long pre) const {
+        const bool live = t < lim;
+        wave_append(live && f.r && f.r <= kBigR && !lane_compactable(f.r, f.x.lo, f.x.hi),
+                    (uint32_t)t, &ctr->n_heavy, mid);
+        if (!live) return;
         CDesc c;
-        c.lo = t_start[t];
-        c.hi = t_start[t + 1];
-        c.r = b[c.hi] - b[c.lo];
-        c.v = t_vtx[t];
-        const VRec r = g.vt[c.v];
-        c.deg = r.deg;
-        c.dir = r.dir;
-        c.dcls = r.dcls;
+        c.lo = f.x.lo;
+        c.hi = f.x.hi;
+        c.r = f.r;
+        c.v = f.x.v;
+        c.deg = f.x.r.deg;
+        c.dir = f.x.r.dir;
+        c.dcls = f.x.r.dcls;
         c.need = (uint32_t)pre;
         cd[t] = c;
-        if (c.r > kBigR) big[atomicAdd(&g.ctr->n_big, 1u)] = (uint32_t)t;
+        if (c.r > kBigR) big[atomicAdd(&ctr->n_big, 1u)] = (uint32_t)t;
     }
 };
 
-// 16-lane groups, one touched source each: holes below the new degree (in
-// batch order) receive the survivors found above it (in slot order); emptied
-// blocks go on the free list.
+// Compaction of every touched source with at most kBigR hits: holes below the
+// new degree (taken in batch order) receive the survivors found above it (in
+// slot order), and emptied blocks go on the free list.  A lane takes a source
+// with at most kLaneR hits and a short segment; the others are taken by the
+// whole wave in turn.
 __global__ __launch_bounds__(kThreads) void k_compact(GraphView g, const uint8_t* mark,
                                                       const uint32_t* hitpos, uint32_t* holes,
-                                                      const CDesc* cdesc) {
+                                                      const CDesc* cdesc, const uint32_t* mid) {
     const DevCounters* c = g.ctr;
     const uint32_t nT = (uint32_t)c->tot[kTotSeg];
     const uint32_t lane = lane_id();
-    const uint32_t gl = lane & (kGroup - 1);
-    const uint64_t below = (1ull << gl) - 1;
-    const uint32_t ngroups = gridDim.x * kWaves * kGroupsPerWave;
+    const uint64_t below = (1ull << lane) - 1;
+    const uint32_t stride = gridDim.x * kThreads;
     const unsigned long long fbase = c->free_cnt;
+    const uint32_t bm = g.B - 1;
     unsigned long long moved = 0;
-    for (uint32_t t = global_wave() * kGroupsPerWave + lane / kGroup; t < nT; t += ngroups) {
-        const CDesc D = cdesc[t];
-        if (!D.r || D.r > kBigR) continue;
-        const VRec rec{D.deg, D.dir, D.dcls, 0u};
-        const uint32_t d = D.deg, dn = d - D.r;
-        uint32_t nh = 0;
-        for (uint32_t p0 = D.lo; p0 < D.hi; p0 += kGroup) {
-            const uint32_t p = p0 + gl;
-            bool hole = false;
-            uint32_t hp = 0;
-            if (p < D.hi && mark[p]) {
-                hp = hitpos[p];
-                hole = hp < dn;
+    for (uint32_t base = global_wave() * 64; base < nT; base += stride) {
+        const bool live = base + lane < nT;
+        const CDesc D = cdesc[live ? base + lane : nT - 1];
+        if (live && D.r && lane_compactable(D.r, D.lo, D.hi)) {
+            const VRec rec{D.deg, D.dir, D.dcls, 0u};
+            const uint32_t d = D.deg, dn = d - D.r;
+            uint8_t mk[kLaneSeg];
+            uint32_t hp[kLaneSeg], sb[kLaneR];
+#pragma unroll
+            for (uint32_t u = 0; u < kLaneSeg; ++u) {
+                const uint32_t q = min(D.lo + u, D.hi - 1);
+                mk[u] = mark[q];
+                hp[u] = hitpos[q];
             }
-            const uint64_t m = group_mask(ballot(hole), lane);
-            if (hole) holes[D.lo + nh + popc64(m & below)] = hp;
-            nh += popc64(m);
-        }
-        __threadfence_block();
-        uint32_t ns = 0;
-        for (uint32_t s0 = dn; s0 < d; s0 += kGroup) {
-            const uint32_t s = s0 + gl;
-            uint32_t x = kTomb;
-            if (s < d) x = g.pool[slot_addr(g, rec, s)];
-            const bool surv = x != kTomb;
-            const uint64_t m = group_mask(ballot(surv), lane);
-            if (surv) {
-                // survivors above dn and holes below it are equal in number;
-                // the guards only keep a broken invariant from writing wild
-                const uint32_t q = ns + popc64(m & below);
-                if (q < nh) {
-                    const uint32_t dest = holes[D.lo + q];
-                    if (dest < dn) g.pool[slot_addr(g, rec, dest)] = x;
+#pragma unroll
+            for (uint32_t k = 0; k < kLaneR; ++k)
+                sb[k] = block_of(g, rec, min(dn + k, d - 1) >> g.log2B);
+            uint32_t sv[kLaneR];
+#pragma unroll
+            for (uint32_t k = 0; k < kLaneR; ++k)
+                sv[k] = g.pool[((uint64_t)sb[k] << g.log2B) + (min(dn + k, d - 1) & bm)];
+            // holes in batch order, survivors in slot order
+            uint32_t hm = 0, sm = 0;
+#pragma unroll
+            for (uint32_t u = 0; u < kLaneSeg; ++u)
+                hm |= (D.lo + u < D.hi && mk[u] && hp[u] < dn) ? (1u << u) : 0u;
+#pragma unroll
+            for (uint32_t k = 0; k < kLaneR; ++k)
+                sm |= (k < D.r && sv[k] != kTomb) ? (1u << k) : 0u;
+            uint32_t hslot[kLaneR], hval[kLaneR];
+            uint32_t nmove = 0;
+#pragma unroll
+            for (uint32_t k = 0; k < kLaneR; ++k) {
+                hslot[k] = 0;
+                hval[k] = 0;
+                if (hm && sm) {
+                    const uint32_t u = __builtin_ctz(hm), w = __builtin_ctz(sm);
+                    hm &= hm - 1;
+                    sm &= sm - 1;
+                    hslot[k] = hp[u];
+                    hval[k] = sv[w];
+                    nmove = k + 1;
                 }
             }
-            ns += popc64(m);
-        }
-        moved += gl == 0 ? ns : 0;
-        const uint32_t nb0 = nblocks(g, d), nb1 = nblocks(g, dn);
-        const unsigned long long pb = fbase + D.need;
-        for (uint32_t j = nb1 + gl; j < nb0; j += kGroup)
-            g.free_stack[pb + (j - nb1)] = block_of(g, rec, j);
-        if (gl == 0) {
+            uint32_t hb[kLaneR];
+#pragma unroll
+            for (uint32_t k = 0; k < kLaneR; ++k) hb[k] = block_of(g, rec, hslot[k] >> g.log2B);
+#pragma unroll
+            for (uint32_t k = 0; k < kLaneR; ++k)
+                if (k < nmove) g.pool[((uint64_t)hb[k] << g.log2B) + (hslot[k] & bm)] = hval[k];
+            moved += nmove;
+            const uint32_t nb0 = nblocks(g, d), nb1 = nblocks(g, dn);
+            const unsigned long long pb = fbase + D.need;
+#pragma unroll
+            for (uint32_t k = 0; k < kLaneR; ++k)
+                if (nb1 + k < nb0) g.free_stack[pb + k] = block_of(g, rec, nb1 + k);
             VRec nr = rec;
             nr.deg = dn;
             if (nb1 == 0 && nr.dcls == kNoDir) nr.dir = 0;
             g.vt[D.v] = nr;
+        }
+    }
+    // sources with more hits or longer segments, listed by the freed scan:
+    // one wave each
+    const uint32_t nmid = c->n_heavy;
+    const uint32_t nw = gridDim.x * kWaves;
+    for (uint32_t k = global_wave(); k < nmid; k += nw) {
+        {
+            const CDesc H = cdesc[mid[k]];
+            const VRec rec{H.deg, H.dir, H.dcls, 0u};
+            const uint32_t d = H.deg, dn = d - H.r;
+            uint32_t nh = 0;
+            for (uint32_t p0 = H.lo; p0 < H.hi; p0 += 64) {
+                const uint32_t p = p0 + lane;
+                const uint32_t q = min(p, H.hi - 1);
+                const uint8_t m = mark[q];
+                const uint32_t hpv = hitpos[q];
+                const bool hole = p < H.hi && m && hpv < dn;
+                const uint64_t bal = ballot(hole);
+                if (hole) holes[H.lo + nh + popc64(bal & below)] = hpv;
+                nh += popc64(bal);
+            }
+            __threadfence_block();
+            uint32_t ns = 0;
+            for (uint32_t s0 = dn; s0 < d; s0 += 64) {
+                const uint32_t sl = s0 + lane;
+                uint32_t x = kTomb;
+                if (sl < d) x = g.pool[slot_addr(g, rec, sl)];
+                const bool surv = x != kTomb;
+                const uint64_t bal = ballot(surv);
+                if (surv) {
+                    // survivors above dn and holes below it are equal in number;
+                    // the guards only keep a broken invariant from writing wild
+                    const uint32_t qq = ns + popc64(bal & below);
+                    if (qq < nh) {
+                        const uint32_t dest = holes[H.lo + qq];
+                        if (dest < dn) g.pool[slot_addr(g, rec, dest)] = x;
+                    }
+                }
+                ns += popc64(bal);
+            }
+            moved += lane == 0 ? ns : 0;
+            const uint32_t nb0 = nblocks(g, d), nb1 = nblocks(g, dn);
+            const unsigned long long pb = fbase + H.need;
+            for (uint32_t j = nb1 + lane; j < nb0; j += 64)
+                g.free_stack[pb + (j - nb1)] = block_of(g, rec, j);
+            if (lane == 0) {
+                VRec nr = rec;
+                nr.deg = dn;
+                if (nb1 == 0 && nr.dcls == kNoDir) nr.dir = 0;
+                g.vt[H.v] = nr;
+            }
         }
     }
     moved = wave_sum(moved);
@@ -904,8 +1123,8 @@ void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t*
     c.launch("begin", k_begin, std::min<uint64_t>(div_up(A.state_words, kThreads), 1024),
              kThreads, v, A.state, A.state_words);
     scan2(c, "pack", PackIn{v, src, dst},
-          PackOut{v, src, dst, A.keys0, mode == kQuery ? A.vals0 : nullptr,
-                  mode == kQuery ? out : nullptr, A.mark},
+          PackOut{v.L, A.keys0, mode == kQuery ? A.vals0 : nullptr, mode == kQuery ? out : nullptr,
+                  A.mark},
           n, A.part, &tot[kTotValid]);
     bool flip;
     if (mode == kQuery)
@@ -918,12 +1137,12 @@ void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t*
     const uint32_t* vals = flip ? A.vals1 : A.vals0;
 
     scan2(c, "segments", SegIn{keys, n_valid, v.L},
-          SegOut{keys, n_valid, v.L, A.flags, A.a, A.t_vtx, A.t_start}, n, A.part,
+          SegOut{v.L, A.flags, A.a, A.t_vtx, A.t_start}, n, A.part,
           &tot[kTotSeg]);
-    scan2(c, "items", ItemIn{v, A.t_vtx}, ItemOut{v, A.t_vtx, A.t_start, A.items}, n, A.part,
+    scan2(c, "items", ItemIn{v, A.t_vtx, A.t_start}, ItemOut{A.items}, n, A.part,
           &tot[kTotItems]);
     const uint64_t pgrid = std::min<uint64_t>(div_up(icap, kWaves * kGroupsPerWave), 2048);
-    const uint64_t tgrid = std::min<uint64_t>(div_up(n, kWaves), 2048);
+    const uint64_t tgrid = std::min<uint64_t>(div_up(n, kThreads), 2048);  // a lane per source
 
     if (mode == kInsert) {
         c.launch("probe_insert", k_probe<kInsert>, pgrid, kThreads, v, keys, (const Item*)A.items,
@@ -931,30 +1150,33 @@ void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t*
         scan2(c, "keep", KeepIn{A.flags, A.mark, n_valid}, U32Out{A.b}, n + 1, A.part,
               &tot[kTotA]);
         c.launch("plan_insert", k_plan_ins, grid, kThreads, v, (const uint32_t*)A.t_vtx,
-                 (const uint32_t*)A.t_start, (const uint32_t*)A.b, A.t_need, A.t_dreq, A.t_drank);
+                 (const uint32_t*)A.t_start, (const uint32_t*)A.b, A.t_need, A.t_dreq, A.t_drank,
+                 A.heavy);
         scan2(c, "need", NeedIn{A.t_need, ctr}, U32Out{A.t_need}, n + 1, A.part, &tot[kTotB]);
         c.launch("plan", k_plan, 1, 1, v, n, (int)sticky);
-        c.launch("grow", k_grow, tgrid, kThreads, v, (const uint32_t*)A.t_vtx,
-                 (const uint32_t*)A.t_start, (const uint32_t*)A.b, (const uint32_t*)A.t_need,
-                 (const uint32_t*)A.t_dreq, (const uint32_t*)A.t_drank, A.t_dold, A.t_doldc);
         c.launch("append", k_append, grid, kThreads, v, keys, (const uint8_t*)A.flags,
                  (const uint8_t*)A.mark, (const uint32_t*)A.a, (const uint32_t*)A.b,
-                 (const uint32_t*)A.t_vtx, (const uint32_t*)A.t_start);
-        c.launch("final_insert", k_final_ins, grid, kThreads, v, (const uint32_t*)A.t_vtx,
-                 (const uint32_t*)A.t_start, (const uint32_t*)A.b, (const uint32_t*)A.t_dreq,
-                 (const uint32_t*)A.t_dold, (const uint32_t*)A.t_doldc);
+                 (const uint32_t*)A.t_vtx, (const uint32_t*)A.t_start,
+                 (const uint32_t*)A.t_need);
+        c.launch("grow", k_grow, tgrid, kThreads, v, (const uint32_t*)A.t_vtx,
+                 (const uint32_t*)A.t_start, (const uint32_t*)A.b, (const uint32_t*)A.t_need,
+                 (const uint32_t*)A.t_dreq, (const uint32_t*)A.t_drank, A.t_dold, A.t_doldc,
+                 (const uint32_t*)A.heavy);
+        c.launch("final_insert", k_final_ins, grid, kThreads, v,
+                 (const uint32_t*)A.t_dreq, (const uint32_t*)A.t_dold,
+                 (const uint32_t*)A.t_doldc);
     } else if (mode == kDelete) {
         c.launch("probe_delete", k_probe<kDelete>, pgrid, kThreads, v, keys, (const Item*)A.items,
                  A.mark, A.hitpos);
         scan2(c, "found", FoundIn{A.mark, n_valid}, U32Out{A.b}, n + 1, A.part, &tot[kTotA]);
         scan2(c, "freed", FreedIn{v, A.t_vtx, A.t_start, A.b},
-              FreedOut{v, A.t_vtx, A.t_start, A.b, A.cdesc, A.big}, n, A.part, &tot[kTotB]);
+              FreedOut{ctr, A.cdesc, A.big, A.heavy}, n, A.part, &tot[kTotB]);
         c.launch("compact_big", k_compact_big, 256, kThreads, v, (const uint8_t*)A.mark,
                  (const uint32_t*)A.hitpos, A.holes, (const CDesc*)A.cdesc,
                  (const uint32_t*)A.big);
-        c.launch("compact", k_compact, std::min<uint64_t>(div_up(n, kWaves * kGroupsPerWave), 2048),
-                 kThreads, v, (const uint8_t*)A.mark, (const uint32_t*)A.hitpos, A.holes,
-                 (const CDesc*)A.cdesc);
+        c.launch("compact", k_compact, std::min<uint64_t>(div_up(n, kThreads), 2048), kThreads, v,
+                 (const uint8_t*)A.mark, (const uint32_t*)A.hitpos, A.holes, (const CDesc*)A.cdesc,
+                 (const uint32_t*)A.heavy);
         c.launch("final_delete", k_final_del, 1, 1, v, n);
     } else {
         c.launch("probe_query", k_probe<kQuery>, pgrid, kThreads, v, keys, (const Item*)A.items,

@@ -338,16 +338,40 @@ void scan1(Ctx& c, const char* name, In in, Out out, uint64_t n, unsigned long l
 // reduces each tile, the second recomputes its tile prefix by reducing the
 // partials of all earlier tiles (at most a few thousand, read from L2) and
 // scans its tile.  Inputs are evaluated twice, outputs written once.
+//
+// The source is a gather: it splits each element into its memory reads and
+// the arithmetic on them, so that a thread issues the reads of all of its
+// elements before it waits on any of them.
+//   uint64_t limit(uint64_t n)          live elements (<= n, may be read from
+//                                       device memory); the rest count 0
+//   Rec load(uint64_t i, bool ok)       first-level reads of element i (always
+//                                       i < n); every address must be valid
+//                                       also when !ok, and no read may sit
+//                                       behind a branch
+//   void deref(Rec&)                    reads at addresses that load() read
+//                                       (same rules)
+//   ull value(uint64_t i, const Rec&)   the element's value (called when ok)
+// The sink takes (i, rec, lim, exclusive prefix) for every i < n; the
+// element is live when i < lim.
 template <typename In>
 __global__ __launch_bounds__(kThreads) void k_scan2_reduce(In in, uint64_t n,
                                                            unsigned long long* part) {
     __shared__ unsigned long long s_w[kWaves];
-    const uint64_t base = (uint64_t)blockIdx.x * kScan1Tile;
+    const uint64_t lim = in.limit(n);
+    const uint64_t base = (uint64_t)blockIdx.x * kScan1Tile + threadIdx.x;
+    typename In::Rec r[kScan1Items];
+#pragma unroll
+    for (int j = 0; j < kScan1Items; ++j) {
+        const uint64_t i = base + (uint64_t)j * kThreads;
+        r[j] = in.load(i < n ? i : n - 1, i < lim);
+    }
+#pragma unroll
+    for (int j = 0; j < kScan1Items; ++j) in.deref(r[j]);
     unsigned long long s = 0;
 #pragma unroll
     for (int j = 0; j < kScan1Items; ++j) {
-        const uint64_t i = base + (uint64_t)j * kThreads + threadIdx.x;
-        if (i < n) s += in(i);
+        const uint64_t i = base + (uint64_t)j * kThreads;
+        s += i < lim ? in.value(i, r[j]) : 0ull;
     }
     s = block_sum(s, s_w);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
@@ -357,19 +381,47 @@ template <typename In, typename Out>
 __global__ __launch_bounds__(kThreads) void k_scan2_apply(In in, Out out, uint64_t n,
                                                           const unsigned long long* part,
                                                           unsigned long long* total) {
-    __shared__ unsigned long long s_w[kWaves];
-    unsigned long long p = 0;
-    for (uint32_t t = threadIdx.x; t < blockIdx.x; t += kThreads) p += part[t];
-    unsigned long long run = block_sum(p, s_w);
-    const uint64_t base = (uint64_t)blockIdx.x * kScan1Tile;
+    __shared__ unsigned long long s_w[kScan1Items][kWaves];
+    __shared__ unsigned long long s_p[kWaves];
+    const uint64_t lim = in.limit(n);
+    const uint64_t base = (uint64_t)blockIdx.x * kScan1Tile + threadIdx.x;
+    typename In::Rec r[kScan1Items];
 #pragma unroll
     for (int j = 0; j < kScan1Items; ++j) {
-        const uint64_t i = base + (uint64_t)j * kThreads + threadIdx.x;
-        const unsigned long long x = i < n ? (unsigned long long)in(i) : 0ull;
-        unsigned long long t2;
-        const unsigned long long ex = block_excl_scan(x, s_w, t2);
-        if (i < n) out(i, run + ex);
-        run += t2;
+        const uint64_t i = base + (uint64_t)j * kThreads;
+        r[j] = in.load(i < n ? i : n - 1, i < lim);
+    }
+#pragma unroll
+    for (int j = 0; j < kScan1Items; ++j) in.deref(r[j]);
+    unsigned long long p = 0;
+    for (uint32_t t = threadIdx.x; t < blockIdx.x; t += kThreads) p += part[t];
+    // one wave scan per row of the tile, then a single exchange of the
+    // per-wave row totals
+    unsigned long long x[kScan1Items], inc[kScan1Items];
+#pragma unroll
+    for (int j = 0; j < kScan1Items; ++j) {
+        const uint64_t i = base + (uint64_t)j * kThreads;
+        x[j] = i < lim ? in.value(i, r[j]) : 0ull;
+        inc[j] = wave_incl_scan(x[j]);
+    }
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 63) {
+#pragma unroll
+        for (int j = 0; j < kScan1Items; ++j) s_w[j][w] = inc[j];
+    }
+    unsigned long long run = block_sum(p, s_p);  // its barriers publish s_w
+#pragma unroll
+    for (int j = 0; j < kScan1Items; ++j) {
+        const uint64_t i = base + (uint64_t)j * kThreads;
+        unsigned long long before = 0, tot = 0;
+#pragma unroll
+        for (int q = 0; q < kWaves; ++q) {
+            const unsigned long long v = s_w[j][q];
+            before += q < w ? v : 0ull;
+            tot += v;
+        }
+        if (i < n) out(i, r[j], lim, run + before + inc[j] - x[j]);
+        run += tot;
     }
     if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == kThreads - 1) *total = run;
 }

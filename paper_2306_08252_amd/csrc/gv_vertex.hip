@@ -181,13 +181,26 @@ __global__ __launch_bounds__(kThreads) void k_vdel_sweep(GraphView g, const uint
     }
 }
 
+// per-vertex pair counts; both the gather interface of scan2 and the plain
+// one of scan_excl
 struct CntIn {
     const uint32_t* cnt;
+    struct Rec {
+        uint32_t c;
+    };
+    __device__ uint64_t limit(uint64_t n) const { return n; }
+    __device__ Rec load(uint64_t i, bool) const { return Rec{cnt[i]}; }
+    __device__ void deref(Rec&) const {}
+    __device__ unsigned long long value(uint64_t, const Rec& r) const { return r.c; }
     __device__ unsigned long long operator()(uint64_t i) const { return cnt[i]; }
 };
 struct U64Out {
     unsigned long long* a;
     __device__ void operator()(uint64_t i, unsigned long long v) const { a[i] = v; }
+    template <typename R>
+    __device__ void operator()(uint64_t i, const R&, uint64_t, unsigned long long v) const {
+        a[i] = v;
+    }
 };
 
 __global__ __launch_bounds__(kThreads) void k_vdel_finish(GraphView g, const uint32_t* keys,
