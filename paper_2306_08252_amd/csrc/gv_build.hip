@@ -34,7 +34,7 @@ static bool sort_keys(gv_graph* g, uint64_t* k0, uint64_t* k1, uint64_t n, int b
                       uint32_t* state) {
     Ctx& c = g->ctx;
     DevCounters* ctr = g->v.ctr;
-    zero_words(c, state, os_words(n, bits));
+    zero_words(c, state, os_zero_words(n, bits));
     set_u32(g, &ctr->sort_n, (uint32_t)n);
     set_u32(g, &ctr->sort_err, 0);
     const bool flip = onesweep<uint64_t, false>(c, k0, k1, nullptr, nullptr, &ctr->sort_n, n,

@@ -55,6 +55,7 @@ constexpr uint32_t kBigR = 256;                // deletes per source handled by 
 constexpr uint32_t kLaneCopy = 8;              // directory entries a lane copies or adds
 constexpr uint32_t kLaneSeg = 8;               // segment entries a lane compacts
 constexpr uint32_t kLaneR = 4;                 // hits a lane compacts
+constexpr uint32_t kRelease = 0x80000000u;     // flag bit in the per-source demand
 
 // scan-total slots in DevCounters::tot
 enum { kTotValid = 0, kTotSeg = 1, kTotItems = 2, kTotA = 3, kTotB = 4 };
@@ -91,6 +92,7 @@ struct BatchArrays {
     uint32_t* t_drank;  // insert: rank among requests of that class
     uint32_t* t_dold;   // insert: replaced directory segment offset
     uint32_t* t_doldc;  // insert: replaced directory segment class or kNoDir
+    uint32_t* rel;      // insert: sources that give back a directory segment
     CDesc* cdesc;       // delete: compaction descriptors
     uint32_t* big;      // delete: sources with more than kBigR hits
     uint32_t* heavy;    // sources left to whole waves
@@ -128,11 +130,12 @@ static void carve_batch(Carver& cv, BatchArrays& A, uint64_t n, uint64_t icap, E
         A.t_drank = cv.take<uint32_t>(n);
         A.t_dold = cv.take<uint32_t>(n);
         A.t_doldc = cv.take<uint32_t>(n);
+        A.rel = cv.take<uint32_t>(n);
     }
     A.items = cv.take<Item>(icap);
     A.part = cv.take<unsigned long long>(scan2_parts(n + 1));
-    A.state_words = os_words(n, bits);
-    A.state = cv.take<uint32_t>(A.state_words);
+    A.state_words = os_zero_words(n, bits);  // the part the batch zeroes
+    A.state = cv.take<uint32_t>(os_words(n, bits));
 }
 
 __device__ __forceinline__ uint64_t thread_index() {
@@ -541,12 +544,13 @@ __global__ __launch_bounds__(kThreads) void k_plan_ins(GraphView g, const uint32
         const uint32_t kp = b[t_start[t + 1]] - b[t_start[t]];
         const VRec r = g.vt[t_vtx[t]];
         const uint32_t nb0 = nblocks(g, r.deg), nb1 = nblocks(g, r.deg + kp);
-        t_need[t] = nb1 - nb0;
         const uint64_t cap0 = r.dcls == kNoDir ? 1ull : (1ull << r.dcls);
         if (nb1 > cap0) {
             cls = ceil_log2(nb1);
             lrank = atomicAdd(&lcnt[cls], 1u);
         }
+        // top bit: the source gives back a directory segment
+        t_need[t] = (nb1 - nb0) | (cls != kNoDir && r.dcls != kNoDir ? kRelease : 0u);
         t_dreq[t] = cls;
         big = (cls != kNoDir && nb0 > kLaneCopy) || nb1 - nb0 > kLaneCopy;
     }
@@ -560,6 +564,8 @@ __global__ __launch_bounds__(kThreads) void k_plan_ins(GraphView g, const uint32
     if (t < nT && cls != kNoDir) t_drank[t] = lbase[cls] + lrank;
 }
 
+// blocks needed in the low half, directory segments given back in the high
+// half (their rank is their slot in the release list)
 struct NeedIn {
     const uint32_t* t_need;
     const DevCounters* ctr;
@@ -571,30 +577,57 @@ struct NeedIn {
     }
     __device__ Rec load(uint64_t t, bool ok) const { return Rec{t_need[ok ? t : 0]}; }
     __device__ void deref(Rec&) const {}
-    __device__ unsigned long long value(uint64_t, const Rec& r) const { return r.need; }
+    __device__ unsigned long long value(uint64_t, const Rec& r) const {
+        return (unsigned long long)(r.need & ~kRelease) | ((unsigned long long)(r.need >> 31) << 32);
+    }
+};
+
+struct NeedOut {
+    uint32_t* t_need;
+    uint32_t* rel;
+    __device__ void operator()(uint64_t t, const NeedIn::Rec& r, uint64_t lim,
+                               unsigned long long pre) const {
+        t_need[t] = (uint32_t)pre;
+        if (t < lim && (r.need & kRelease)) rel[(uint32_t)(pre >> 32)] = (uint32_t)t;
+    }
 };
 
 // Allocation plan for the whole batch, one thread: capacity is checked
 // before any state is written, so a failing batch leaves the graph unchanged.
-__global__ void k_plan(GraphView g, uint64_t n, int sticky) {
+// Allocation plan for the whole batch, one wave (a lane per directory class):
+// capacity is checked before any state is written, so a failing batch leaves
+// the graph unchanged.
+__global__ __launch_bounds__(64) void k_plan(GraphView g, uint64_t n, int sticky) {
     DevCounters* c = g.ctr;
+    const uint32_t k = lane_id();
+    const bool cl = k < kMaxClass;
+    const unsigned long long N = c->tot[kTotB] & 0xffffffffull;
+    const unsigned long long free0 = c->free_cnt, bump0 = c->bump;
+    const unsigned long long ff = N < free0 ? N : free0;
+    const unsigned long long fb = N - ff;
+    const uint32_t req = cl ? c->dreq[k] : 0u;
+    const uint32_t have = cl ? c->dfree_cnt[k] : 0u;
+    const uint32_t dff = req < have ? req : have;
+    const unsigned long long grow = cl ? (unsigned long long)(req - dff) << k : 0ull;
+    const unsigned long long gincl = wave_incl_scan(grow);
+    const unsigned long long db0 = c->dir_bump;
+    const unsigned long long db_end = db0 + __shfl(gincl, 63, 64);
+    const bool ok = bump0 + fb <= g.cap_blocks && db_end <= g.dir_cap;
+    if (cl) {
+        c->plan_dff[k] = dff;
+        c->plan_dbump[k] = db0 + gincl - grow;
+        c->dreq[k] = 0;
+        if (ok) {
+            c->plan_dtop[k] = have;
+            c->dfree_cnt[k] = have - dff;
+        }
+    }
+    const unsigned long long live = wave_sum(cl ? (unsigned long long)req << k : 0ull);
+    if (k != 0) return;
     const unsigned long long nv = c->tot[kTotValid];
     const unsigned long long nT = c->tot[kTotSeg] & 0xffffffffull;
     const unsigned long long nuniq = c->tot[kTotSeg] >> 32;
     const unsigned long long applied = c->tot[kTotA];
-    const unsigned long long N = c->tot[kTotB];
-    const unsigned long long ff = N < c->free_cnt ? N : c->free_cnt;
-    const unsigned long long fb = N - ff;
-    bool ok = c->bump + fb <= g.cap_blocks;
-    unsigned long long db = c->dir_bump;
-    for (int k = 0; k < kMaxClass; ++k) {
-        const uint32_t req = c->dreq[k];
-        const uint32_t dff = req < c->dfree_cnt[k] ? req : c->dfree_cnt[k];
-        c->plan_dff[k] = dff;
-        c->plan_dbump[k] = db;
-        db += (unsigned long long)(req - dff) << k;
-    }
-    ok = ok && db <= g.dir_cap;
     c->c_batches[kInsert] += 1;
     c->c_pairs[kInsert] += n;
     c->c_touched[kInsert] += nT;
@@ -602,23 +635,15 @@ __global__ void k_plan(GraphView g, uint64_t n, int sticky) {
     if (!ok) {
         c->err_batch = GV_ENOMEM;
         if (sticky && !c->err_sticky) c->err_sticky = GV_ENOMEM;
-        for (int k = 0; k < kMaxClass; ++k) c->dreq[k] = 0;
         c->st_applied = c->st_rejected = c->st_dups = 0;
         return;
     }
-    c->plan_free_top = c->free_cnt;
+    c->plan_free_top = free0;
     c->plan_from_free = ff;
-    c->plan_bump0 = c->bump;
-    c->free_cnt -= ff;
-    c->bump += fb;
-    unsigned long long live = 0;
-    for (int k = 0; k < kMaxClass; ++k) {
-        c->plan_dtop[k] = c->dfree_cnt[k];
-        c->dfree_cnt[k] -= c->plan_dff[k];
-        live += (unsigned long long)c->dreq[k] << k;
-        c->dreq[k] = 0;
-    }
-    c->dir_bump = db;
+    c->plan_bump0 = bump0;
+    c->free_cnt = free0 - ff;
+    c->bump = bump0 + fb;
+    c->dir_bump = db_end;
     c->dir_live += live;
     c->st_applied = applied;
     c->st_rejected = n - nv;
@@ -754,34 +779,37 @@ __global__ __launch_bounds__(kThreads) void k_grow(GraphView g, const uint32_t* 
 
 // Old directory segments of the sources that moved go on the per-class free
 // lists (after the commit kernel has taken its segments from them).
-__global__ __launch_bounds__(kThreads) void k_final_ins(GraphView g, const uint32_t* t_dreq,
+__global__ __launch_bounds__(kThreads) void k_final_ins(GraphView g, const uint32_t* rel,
                                                         const uint32_t* t_dold,
                                                         const uint32_t* t_doldc) {
     __shared__ uint32_t lcnt[kMaxClass];
     __shared__ uint32_t lbase[kMaxClass];
     __shared__ unsigned long long lfreed;
-    if (threadIdx.x < kMaxClass) lcnt[threadIdx.x] = 0;
-    if (threadIdx.x == 0) lfreed = 0;
-    __syncthreads();
-    const bool ok = !g.ctr->err_batch;
-    const uint64_t t = thread_index();
-    uint32_t oc = kNoDir, lrank = 0;
-    if (ok && t < (uint32_t)g.ctr->tot[kTotSeg] && t_dreq[t] != kNoDir) {
-        oc = t_doldc[t];
-        if (oc != kNoDir) {
+    const uint32_t nrel = g.ctr->err_batch ? 0u : (uint32_t)(g.ctr->tot[kTotB] >> 32);
+    for (uint32_t base = blockIdx.x * kThreads; base < nrel; base += gridDim.x * kThreads) {
+        if (threadIdx.x < kMaxClass) lcnt[threadIdx.x] = 0;
+        if (threadIdx.x == 0) lfreed = 0;
+        __syncthreads();
+        const uint32_t k = base + threadIdx.x;
+        uint32_t oc = kNoDir, lrank = 0, old = 0;
+        if (k < nrel) {
+            const uint32_t t = rel[k];
+            oc = t_doldc[t];
+            old = t_dold[t];
             lrank = atomicAdd(&lcnt[oc], 1u);
             atomicAdd(&lfreed, 1ull << oc);
         }
+        __syncthreads();
+        if (threadIdx.x < kMaxClass) {
+            const uint32_t c = lcnt[threadIdx.x];
+            lbase[threadIdx.x] = c ? atomicAdd(&g.ctr->dfree_cnt[threadIdx.x], c) : 0u;
+        }
+        if (threadIdx.x == 0 && lfreed)
+            atomicAdd(&g.ctr->dir_live, (unsigned long long)(-(long long)lfreed));
+        __syncthreads();
+        if (oc != kNoDir) g.dfree[g.dfree_base[oc] + lbase[oc] + lrank] = old;
+        __syncthreads();
     }
-    __syncthreads();
-    if (threadIdx.x < kMaxClass) {
-        const uint32_t c = lcnt[threadIdx.x];
-        lbase[threadIdx.x] = c ? atomicAdd(&g.ctr->dfree_cnt[threadIdx.x], c) : 0u;
-    }
-    if (threadIdx.x == 0 && lfreed)
-        atomicAdd(&g.ctr->dir_live, (unsigned long long)(-(long long)lfreed));
-    __syncthreads();
-    if (oc != kNoDir) g.dfree[g.dfree_base[oc] + lbase[oc] + lrank] = t_dold[t];
 }
 
 // ------------------------------------------------------------------ delete
@@ -796,6 +824,11 @@ struct FoundIn {
     __device__ void deref(Rec&) const {}
     __device__ unsigned long long value(uint64_t, const Rec& r) const { return r.m; }
 };
+
+// a source that one lane compacts by itself
+__device__ __forceinline__ bool lane_compactable(uint32_t r, uint32_t lo, uint32_t hi) {
+    return r <= kLaneR && hi - lo <= kLaneSeg;
+}
 
 // a touched source of a delete batch with its hit count r
 struct FreedRec {
@@ -819,16 +852,16 @@ struct FreedIn {
         f.x.r = g.vt[f.x.v];
         f.r = b[f.x.hi] - b[f.x.lo];
     }
+    // freed blocks in the low half; in the high half, 1 for a source that a
+    // whole wave compacts (its rank among those is its slot in the list)
     __device__ unsigned long long value(uint64_t, const Rec& f) const {
         const uint32_t d = f.x.r.deg;
-        return f.r ? nblocks(g, d) - nblocks(g, d - f.r) : 0ull;
+        if (!f.r) return 0ull;
+        const unsigned long long mid =
+            f.r <= kBigR && !lane_compactable(f.r, f.x.lo, f.x.hi) ? 1ull : 0ull;
+        return (unsigned long long)(nblocks(g, d) - nblocks(g, d - f.r)) | (mid << 32);
     }
 };
-
-// a source that one lane compacts by itself
-__device__ __forceinline__ bool lane_compactable(uint32_t r, uint32_t lo, uint32_t hi) {
-    return r <= kLaneR && hi - lo <= kLaneSeg;
-}
 
 struct FreedOut {
     DevCounters* ctr;
@@ -837,10 +870,9 @@ struct FreedOut {
     uint32_t* mid;  // sources for whole waves
     __device__ void operator()(uint64_t t, const FreedRec& f, uint64_t lim,
                                unsigned long long pre) const {
-        const bool live = t < lim;
-        wave_append(live && f.r && f.r <= kBigR && !lane_compactable(f.r, f.x.lo, f.x.hi),
-                    (uint32_t)t, &ctr->n_heavy, mid);
-        if (!live) return;
+        if (t >= lim) return;
+        if (f.r && f.r <= kBigR && !lane_compactable(f.r, f.x.lo, f.x.hi))
+            mid[(uint32_t)(pre >> 32)] = (uint32_t)t;
         CDesc c;
         c.lo = f.x.lo;
         c.hi = f.x.hi;
@@ -935,7 +967,7 @@ __global__ __launch_bounds__(kThreads) void k_compact(GraphView g, const uint8_t
     }
     // sources with more hits or longer segments, listed by the freed scan:
     // one wave each
-    const uint32_t nmid = c->n_heavy;
+    const uint32_t nmid = (uint32_t)(c->tot[kTotB] >> 32);
     const uint32_t nw = gridDim.x * kWaves;
     for (uint32_t k = global_wave(); k < nmid; k += nw) {
         {
@@ -1057,7 +1089,7 @@ __global__ void k_final_del(GraphView g, uint64_t n) {
     const unsigned long long nT = c->tot[kTotSeg] & 0xffffffffull;
     const unsigned long long nuniq = c->tot[kTotSeg] >> 32;
     const unsigned long long applied = c->tot[kTotA];
-    const unsigned long long freed = c->tot[kTotB];
+    const unsigned long long freed = c->tot[kTotB] & 0xffffffffull;
     c->free_cnt += freed;
     c->st_applied = applied;
     c->st_rejected = n - nv;
@@ -1152,8 +1184,9 @@ void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t*
         c.launch("plan_insert", k_plan_ins, grid, kThreads, v, (const uint32_t*)A.t_vtx,
                  (const uint32_t*)A.t_start, (const uint32_t*)A.b, A.t_need, A.t_dreq, A.t_drank,
                  A.heavy);
-        scan2(c, "need", NeedIn{A.t_need, ctr}, U32Out{A.t_need}, n + 1, A.part, &tot[kTotB]);
-        c.launch("plan", k_plan, 1, 1, v, n, (int)sticky);
+        scan2(c, "need", NeedIn{A.t_need, ctr}, NeedOut{A.t_need, A.rel}, n + 1, A.part,
+              &tot[kTotB]);
+        c.launch("plan", k_plan, 1, 64, v, n, (int)sticky);
         c.launch("append", k_append, grid, kThreads, v, keys, (const uint8_t*)A.flags,
                  (const uint8_t*)A.mark, (const uint32_t*)A.a, (const uint32_t*)A.b,
                  (const uint32_t*)A.t_vtx, (const uint32_t*)A.t_start,
@@ -1162,9 +1195,8 @@ void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t*
                  (const uint32_t*)A.t_start, (const uint32_t*)A.b, (const uint32_t*)A.t_need,
                  (const uint32_t*)A.t_dreq, (const uint32_t*)A.t_drank, A.t_dold, A.t_doldc,
                  (const uint32_t*)A.heavy);
-        c.launch("final_insert", k_final_ins, grid, kThreads, v,
-                 (const uint32_t*)A.t_dreq, (const uint32_t*)A.t_dold,
-                 (const uint32_t*)A.t_doldc);
+        c.launch("final_insert", k_final_ins, std::min<uint64_t>(grid, 64), kThreads, v,
+                 (const uint32_t*)A.rel, (const uint32_t*)A.t_dold, (const uint32_t*)A.t_doldc);
     } else if (mode == kDelete) {
         c.launch("probe_delete", k_probe<kDelete>, pgrid, kThreads, v, keys, (const Item*)A.items,
                  A.mark, A.hitpos);

@@ -454,15 +454,24 @@ constexpr uint32_t kOsAgg = 1u << 30, kOsIncl = 2u << 30, kOsMask = (1u << 30) -
 
 inline int os_passes(int bits) { return (bits + kRadixBits - 1) / kRadixBits; }
 inline uint64_t os_tiles(uint64_t n) { return div_up(std::max<uint64_t>(n, 1), kOsTile); }
-// uint32 words of zeroed state a sort needs: tile counters, histograms, status
-constexpr uint32_t kHistStride = 32;  // one 128-byte line per histogram counter
+// Digit histograms: every histogram workgroup writes its own counts (no
+// atomics), one small kernel adds them up.
+constexpr uint64_t kHistGroups = 256;
+inline uint64_t os_hist_groups(uint64_t n) { return std::min<uint64_t>(os_tiles(n), kHistGroups); }
+// uint32 words of state a sort needs: tile counters and look-back status
+// (the first os_zero_words, which must be zeroed), then the histograms and
+// the per-group histograms
+inline uint64_t os_zero_words(uint64_t n_max, int bits) {
+    return 64 + (uint64_t)os_passes(bits) * os_tiles(n_max) * kRadix;
+}
 inline uint64_t os_words(uint64_t n_max, int bits) {
     const uint64_t p = (uint64_t)os_passes(bits);
-    return 64 + p * kRadix * kHistStride + p * os_tiles(n_max) * kRadix;
+    return os_zero_words(n_max, bits) + p * kRadix + os_hist_groups(n_max) * p * kRadix;
 }
 
 constexpr int kOsThreads = 1024;
 constexpr int kOsWaves = kOsThreads / 64;
+static_assert(kOsThreads == 4 * kRadix, "the pass kernel works in four quarters of 256 threads");
 constexpr int kOsRounds = (int)(kOsTile / kOsThreads);  // keys per thread
 
 // exclusive scan across a kOsThreads workgroup (all threads call it)
@@ -486,7 +495,7 @@ __device__ __forceinline__ uint32_t os_block_scan(uint32_t x, uint32_t* lds, uin
 template <typename K>
 __global__ __launch_bounds__(kOsThreads) void k_os_hist(const K* keys, const uint32_t* n_dev,
                                                         uint64_t n_max, int passes,
-                                                        uint32_t* hist) {
+                                                        uint32_t* hpart) {
     __shared__ uint32_t h[8][kRadix];
     const uint64_t n = n_dev ? *n_dev : n_max;
     for (int i = threadIdx.x; i < 8 * kRadix; i += kOsThreads) h[i / kRadix][i % kRadix] = 0;
@@ -512,9 +521,35 @@ __global__ __launch_bounds__(kOsThreads) void k_os_hist(const K* keys, const uin
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < passes * kRadix; i += kOsThreads) {
-        const uint32_t c = h[i / kRadix][i % kRadix];
-        if (c) atomicAdd(&hist[(uint64_t)i * kHistStride], c);
+    uint32_t* out = hpart + (uint64_t)blockIdx.x * passes * kRadix;
+    for (int i = threadIdx.x; i < passes * kRadix; i += kOsThreads) out[i] = h[i / kRadix][i % kRadix];
+}
+
+// hist[i] = sum over the histogram workgroups of their count i: a
+// workgroup takes 16 counters, its 16 row groups each add every 16th
+// workgroup's count with independent loads, LDS adds the row groups
+static __global__ __launch_bounds__(kThreads) void k_os_hist_sum(const uint32_t* hpart,
+                                                                 uint32_t groups, uint32_t words,
+                                                                 uint32_t* hist) {
+    __shared__ uint32_t red[16][17];
+    const uint32_t col = threadIdx.x & 15, rg = threadIdx.x >> 4;
+    const uint32_t i = blockIdx.x * 16 + col;
+    const uint32_t ic = i < words ? i : 0u;
+    uint32_t s = 0;
+    constexpr uint32_t kRows = (uint32_t)(kHistGroups / 16);
+#pragma unroll
+    for (uint32_t r = 0; r < kRows; ++r) {
+        const uint32_t gi = rg + 16 * r;
+        const uint32_t x = hpart[(uint64_t)(gi < groups ? gi : 0u) * words + ic];
+        s += gi < groups ? x : 0u;
+    }
+    red[rg][col] = s;
+    __syncthreads();
+    if (rg == 0 && i < words) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) t += red[k][col];
+        hist[i] = t;
     }
 }
 
@@ -587,32 +622,49 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const K* kin, K* kout, c
 #pragma unroll
         for (int r = 0; r < kQRows; ++r) cnt[q * kQRows + r][d] += (uint16_t)qoff;
     }
-    // digit threads publish this tile's count and look back
-    uint32_t prefix = 0;
-    if (t < kRadix) {
-        uint32_t* st = status + tile * kRadix + t;
-        st_release32(st, (tile == 0 ? kOsIncl : kOsAgg) | dcount);
-        if (tile > 0) {
-            int64_t j = (int64_t)tile - 1;
-            while (j >= 0) {
-                uint32_t spins = 0, wv;
+    // publish this tile's counts, then look back with four consecutive lanes
+    // per digit: each round reads the status of four earlier tiles at once
+    // and adds them, in order, up to the first inclusive one
+    __shared__ uint32_t lb_prefix[kRadix];
+    if (t < kRadix) st_release32(status + tile * kRadix + t, (tile == 0 ? kOsIncl : kOsAgg) | dcount);
+    {
+        const uint32_t ld = t >> 2, lq = t & 3, gbase = lane_id() & ~3u;
+        uint32_t lp = 0;
+        bool open = tile > 0;
+        int64_t j0 = (int64_t)tile - 1;
+        while (open) {
+            const int64_t j = j0 - (int64_t)lq;
+            uint32_t wv = kOsIncl;  // before tile 0: an inclusive zero
+            if (j >= 0) {
+                uint32_t spins = 0;
                 do {
-                    wv = ld_acquire32(status + (uint64_t)j * kRadix + t);
+                    wv = ld_acquire32(status + (uint64_t)j * kRadix + ld);
                 } while ((wv >> 30) == 0 && ++spins < kSpinLimit);
                 if ((wv >> 30) == 0) {
                     *err = 1;
-                    break;
+                    wv = kOsIncl;
                 }
-                prefix += wv & kOsMask;
-                if ((wv >> 30) == 2) break;
-                --j;
             }
-            st_release32(st, kOsIncl | (prefix + dcount));
+            bool hit = false;
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) {
+                const uint32_t v = __shfl(wv, (int)(gbase + qq), 64);
+                if (!hit) {
+                    lp += v & kOsMask;
+                    hit = (v >> 30) == 2;
+                }
+            }
+            open = !hit;
+            j0 -= 4;
         }
+        if (lq == 0) lb_prefix[ld] = lp;
     }
+    __syncthreads();
+    const uint32_t prefix = t < kRadix ? lb_prefix[t] : 0u;
+    if (t < kRadix && tile > 0) st_release32(status + tile * kRadix + t, kOsIncl | (prefix + dcount));
     // global start of each digit (pass histogram) and start inside the tile
     uint32_t tot;
-    const uint32_t gex = os_block_scan(t < kRadix ? hist[t * kHistStride] : 0u, s_w, tot);
+    const uint32_t gex = os_block_scan(t < kRadix ? hist[t] : 0u, s_w, tot);
     const uint32_t lex = os_block_scan(t < kRadix ? dcount : 0u, s_w, tot);
     if (t < kRadix) {
         s_base[t] = gex + prefix;
@@ -648,8 +700,8 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const K* kin, K* kout, c
 
 // Sorts n keys (n on the device when n_dev != null, n_max bounds it) by bits
 // [0, bits), stably, ping-ponging k0/k1 (v0/v1).  `state` must hold
-// os_words(n_max, bits) zeroed uint32 words.  Returns true if the result is
-// in k1/v1.
+// os_words(n_max, bits) uint32 words, the first os_zero_words of them
+// zeroed.  Returns true if the result is in k1/v1.
 template <typename K, bool HasVal>
 bool onesweep(Ctx& c, K* k0, K* k1, uint32_t* v0, uint32_t* v1, const uint32_t* n_dev,
               uint64_t n_max, int bits, uint32_t* state, uint32_t* err) {
@@ -658,11 +710,15 @@ bool onesweep(Ctx& c, K* k0, K* k1, uint32_t* v0, uint32_t* v1, const uint32_t* 
     const int passes = os_passes(bits);
     if (passes > 8) fail(GV_EINVAL, "too many radix passes");
     const uint64_t nt = os_tiles(n_max);
+    const uint64_t hg = os_hist_groups(n_max);
+    const uint32_t hwords = (uint32_t)passes * kRadix;
     uint32_t* counters = state;           // 64 words
-    uint32_t* hist = state + 64;          // passes * 256 counters, one line each
-    uint32_t* status = hist + (uint64_t)passes * kRadix * kHistStride;
-    c.launch("sort_hist", k_os_hist<K>, std::min<uint64_t>(nt, 128), kOsThreads, (const K*)k0,
-             n_dev, n_max, passes, hist);
+    uint32_t* status = state + 64;        // passes * tiles * 256
+    uint32_t* hist = state + os_zero_words(n_max, bits);  // passes * 256 counters
+    uint32_t* hpart = hist + hwords;      // per histogram workgroup
+    c.launch("sort_hist", k_os_hist<K>, hg, kOsThreads, (const K*)k0, n_dev, n_max, passes, hpart);
+    c.launch("sort_hist", k_os_hist_sum, div_up(hwords, 16), kThreads, (const uint32_t*)hpart,
+             (uint32_t)hg, hwords, hist);
     bool flip = false;
     for (int p = 0; p < passes; ++p) {
         K* kin = flip ? k1 : k0;
@@ -671,7 +727,7 @@ bool onesweep(Ctx& c, K* k0, K* k1, uint32_t* v0, uint32_t* v1, const uint32_t* 
         uint32_t* vout = flip ? v0 : v1;
         c.launch("sort_pass", k_os_pass<K, HasVal>, nt, kOsThreads, (const K*)kin, kout,
                  (const uint32_t*)vin, vout, n_dev, n_max, p * kRadixBits,
-                 (const uint32_t*)(hist + (uint64_t)p * kRadix * kHistStride),
+                 (const uint32_t*)(hist + (uint64_t)p * kRadix),
                  status + (uint64_t)p * nt * kRadix,
                  counters + p, err);
         flip = !flip;
