@@ -274,13 +274,18 @@ struct ItemIn {
     }
 };
 
+// A source's work items: one per kChunk slots.  A lane writes up to
+// kLaneItems of them; sources with more are written by the whole wave, 64
+// items per store.  All active lanes of a wave make the call.
+constexpr uint32_t kLaneItems = 4;
+
 struct ItemOut {
     Item* items;
     __device__ void operator()(uint64_t t, const TouchRec& x, uint64_t lim,
                                unsigned long long pre) const {
-        if (t >= lim) return;
+        const bool live = t < lim;
         const VRec r = x.r;
-        const uint32_t cnt = (r.deg + kChunk - 1) / kChunk;
+        const uint32_t cnt = live ? (r.deg + kChunk - 1) / kChunk : 0u;
         const uint32_t base = (uint32_t)pre;
         Item it;
         it.lo = x.lo;
@@ -289,10 +294,31 @@ struct ItemOut {
         it.dirbase = r.dcls != kNoDir ? r.dir : 0u;
         it.blk0 = r.dcls != kNoDir ? 0u : r.dir;
         it.dcls = r.dcls;
-        for (uint32_t c = 0; c < cnt; ++c) {
-            it.s0 = c * kChunk;
-            it.s1 = min(r.deg, it.s0 + kChunk);
-            items[base + c] = it;
+        if (cnt <= kLaneItems) {
+            for (uint32_t c = 0; c < cnt; ++c) {
+                it.s0 = c * kChunk;
+                it.s1 = min(r.deg, it.s0 + kChunk);
+                items[base + c] = it;
+            }
+        }
+        uint64_t m = ballot(cnt > kLaneItems);
+        while (m) {
+            const int l = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            Item w;
+            w.lo = __shfl(it.lo, l, 64);
+            w.hi = __shfl(it.hi, l, 64);
+            w.v = __shfl(it.v, l, 64);
+            w.dirbase = __shfl(it.dirbase, l, 64);
+            w.blk0 = __shfl(it.blk0, l, 64);
+            w.dcls = __shfl(it.dcls, l, 64);
+            const uint32_t wdeg = __shfl(r.deg, l, 64);
+            const uint32_t wcnt = __shfl(cnt, l, 64), wbase = __shfl(base, l, 64);
+            for (uint32_t c = lane_id(); c < wcnt; c += 64) {
+                w.s0 = c * kChunk;
+                w.s1 = min(wdeg, w.s0 + kChunk);
+                items[wbase + c] = w;
+            }
         }
     }
 };
@@ -1173,11 +1199,12 @@ void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t*
           &tot[kTotSeg]);
     scan2(c, "items", ItemIn{v, A.t_vtx, A.t_start}, ItemOut{A.items}, n, A.part,
           &tot[kTotItems]);
-    const uint64_t pgrid = std::min<uint64_t>(div_up(icap, kWaves * kGroupsPerWave), 2048);
-    const uint64_t tgrid = std::min<uint64_t>(div_up(n, kThreads), 2048);  // a lane per source
+    const uint64_t pwant = div_up(icap, kWaves * kGroupsPerWave);
+    auto pgrid_of = [&](auto kernel) { return std::min<uint64_t>(pwant, resident_grid(kernel, kThreads)); };
+    const uint64_t tgrid = std::min<uint64_t>(div_up(n, kThreads), resident_grid(k_grow, kThreads));
 
     if (mode == kInsert) {
-        c.launch("probe_insert", k_probe<kInsert>, pgrid, kThreads, v, keys, (const Item*)A.items,
+        c.launch("probe_insert", k_probe<kInsert>, pgrid_of(k_probe<kInsert>), kThreads, v, keys, (const Item*)A.items,
                  A.mark, (uint32_t*)nullptr);
         scan2(c, "keep", KeepIn{A.flags, A.mark, n_valid}, U32Out{A.b}, n + 1, A.part,
               &tot[kTotA]);
@@ -1198,7 +1225,7 @@ void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t*
         c.launch("final_insert", k_final_ins, std::min<uint64_t>(grid, 64), kThreads, v,
                  (const uint32_t*)A.rel, (const uint32_t*)A.t_dold, (const uint32_t*)A.t_doldc);
     } else if (mode == kDelete) {
-        c.launch("probe_delete", k_probe<kDelete>, pgrid, kThreads, v, keys, (const Item*)A.items,
+        c.launch("probe_delete", k_probe<kDelete>, pgrid_of(k_probe<kDelete>), kThreads, v, keys, (const Item*)A.items,
                  A.mark, A.hitpos);
         scan2(c, "found", FoundIn{A.mark, n_valid}, U32Out{A.b}, n + 1, A.part, &tot[kTotA]);
         scan2(c, "freed", FreedIn{v, A.t_vtx, A.t_start, A.b},
@@ -1206,12 +1233,13 @@ void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t*
         c.launch("compact_big", k_compact_big, 256, kThreads, v, (const uint8_t*)A.mark,
                  (const uint32_t*)A.hitpos, A.holes, (const CDesc*)A.cdesc,
                  (const uint32_t*)A.big);
-        c.launch("compact", k_compact, std::min<uint64_t>(div_up(n, kThreads), 2048), kThreads, v,
+        c.launch("compact", k_compact,
+                 std::min<uint64_t>(div_up(n, kThreads), resident_grid(k_compact, kThreads)), kThreads, v,
                  (const uint8_t*)A.mark, (const uint32_t*)A.hitpos, A.holes, (const CDesc*)A.cdesc,
                  (const uint32_t*)A.heavy);
         c.launch("final_delete", k_final_del, 1, 1, v, n);
     } else {
-        c.launch("probe_query", k_probe<kQuery>, pgrid, kThreads, v, keys, (const Item*)A.items,
+        c.launch("probe_query", k_probe<kQuery>, pgrid_of(k_probe<kQuery>), kThreads, v, keys, (const Item*)A.items,
                  A.mark, (uint32_t*)nullptr);
         c.launch("answer", k_answer, grid, kThreads, v, vals, (const uint8_t*)A.mark, n, out);
     }

@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -24,6 +26,35 @@ struct Error {
 inline void hip_check(hipError_t e, const char* what) {
     if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) fail(GV_ENOMEM, what);
     if (e != hipSuccess) fail(GV_EDEVICE, what);
+}
+
+// Workgroups of `kernel` (launched with `block` threads) that the current
+// device holds at once: compute units times resident workgroups per unit.
+// Kernels that loop over their work size their grid with it, so that no
+// workgroup waits for a second round.  Cached per kernel and device.
+template <typename... KArgs>
+uint64_t resident_grid(void (*kernel)(KArgs...), uint32_t block) {
+    struct Entry {
+        const void* k;
+        int dev;
+        uint32_t block;
+        uint64_t grid;
+    };
+    static std::mutex mu;
+    static std::vector<Entry> cache;
+    int dev = 0;
+    hip_check(hipGetDevice(&dev), "hipGetDevice");
+    std::lock_guard<std::mutex> lock(mu);
+    for (const Entry& e : cache)
+        if (e.k == (const void*)kernel && e.dev == dev && e.block == block) return e.grid;
+    int cus = 0, per = 0;
+    hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev),
+              "hipDeviceGetAttribute");
+    hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, (int)block, 0),
+              "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+    const uint64_t grid = (uint64_t)std::max(cus, 1) * (uint64_t)std::max(per, 1);
+    cache.push_back({(const void*)kernel, dev, block, grid});
+    return grid;
 }
 
 // Kernel launches go through Ctx so that they can be timed with HIP events on
