@@ -33,6 +33,36 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+CPU_STEPS = 12  # batch pairs the oracle replays (about 10 s of one core)
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_JSON = os.path.join(PROFILES, "traffic_rmat20_b16_batch1e6.json")
+
+
+def sources_digest():
+    """SHA-256 over the kernel sources; a stored counter reading is used only
+    while it matches (the kernels have not changed since it was taken)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2306_08252_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when there is none for it or the kernel sources changed since."""
+    try:
+        with open(TRAFFIC_JSON) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("sources_sha256") != sources_digest():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else int(k["fetch_bytes"] + k["write_bytes"])
 
 
 def log(*a):
@@ -68,6 +98,108 @@ def bytes_model(name, per_launch):
     return None
 
 
+# library launch names -> kernel symbol prefix in rocprofv3 output
+KERNEL_SYMBOLS = {
+    "sort_pass": "gv::k_os_pass<unsigned long, false>",
+    "sort_hist": "gv::k_os_hist<unsigned long>",
+    "probe_insert": "gv::k_probe<0>",
+    "probe_delete": "gv::k_probe<1>",
+    "probe_query": "gv::k_probe<2>",
+    "compact": "gv::k_compact(",
+    "append": "gv::k_append(",
+}
+
+
+def _rows(csv_dir, kind):
+    import csv
+    import glob
+    files = glob.glob(os.path.join(csv_dir, "**", f"*{kind}.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no *{kind}.csv under {csv_dir}")
+    with open(files[0]) as f:
+        return list(csv.DictReader(f))
+
+
+def _short(name):
+    return name.replace("void ", "").split("(")[0]
+
+
+def summarize_trace(trace_dir, out_md, command):
+    """Per-kernel launch counts and durations of the library kernels."""
+    import statistics
+    agg = {}
+    for r in _rows(trace_dir, "kernel_trace"):
+        if "gv::" not in r["Kernel_Name"]:
+            continue
+        wg = int(r["Grid_Size_X"]) // max(1, int(r["Workgroup_Size_X"]))
+        key = (_short(r["Kernel_Name"]), wg)
+        agg.setdefault(key, []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    lines = ["| kernel | grid (WGs) | launches | avg us | total us |", "|---|---|---|---|---|"]
+    for (k, wg), v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"| `{k}` | {wg} | {len(v)} | {statistics.mean(v) / 1e3:.2f} | "
+                     f"{sum(v) / 1e3:.1f} |")
+    with open(out_md, "w") as f:
+        f.write(f"# Kernel trace: {os.path.basename(out_md)[:-3]}\n\nCommand (GPU box, repo root "
+                f"as $R):\n\n```\n{command}\n```\n\nDurations from the kernel trace (ns -> "
+                f"us), library kernels only:\n\n" + "\n".join(lines) + "\n")
+
+
+def summarize_traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, grid_wgs, out_md, commands):
+    """HBM bytes per dispatch from FETCH_SIZE / WRITE_SIZE (KiB per dispatch),
+    scaled by what the same counters read for a plain 1 GiB device copy."""
+    import statistics
+
+    def per_kernel(d, counter, pick):
+        acc = {}
+        for r in _rows(d, "counter_collection"):
+            if r["Counter_Name"] != counter or not pick(r):
+                continue
+            wg = int(r["Grid_Size"]) // max(1, int(r["Workgroup_Size"]))
+            acc.setdefault((r["Kernel_Name"], wg), []).append(float(r["Counter_Value"]) * 1024)
+        return acc
+
+    copy = lambda r: "gv::" not in r["Kernel_Name"] and "copy" in r["Kernel_Name"].lower()
+    cf = per_kernel(cfetch_dir, "FETCH_SIZE", copy)
+    cw = per_kernel(cwrite_dir, "WRITE_SIZE", copy)
+    gib = float(1 << 30)
+    f_factor = gib / statistics.mean(max(cf.values(), key=len))
+    w_factor = gib / statistics.mean(max(cw.values(), key=len))
+    kf = per_kernel(fetch_dir, "FETCH_SIZE", lambda r: "gv::" in r["Kernel_Name"])
+    kw = per_kernel(write_dir, "WRITE_SIZE", lambda r: "gv::" in r["Kernel_Name"])
+    kernels = {}
+    lines = ["| launch name | kernel | grid (WGs) | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB "
+             "| HBM read B (scaled) | HBM write B (scaled) |", "|---|---|---|---|---|---|---|---|"]
+    for name, sym in KERNEL_SYMBOLS.items():
+        wg = grid_wgs.get(name)
+        same = lambda k, g: _short(k) == sym.rstrip("(") and (wg is None or g == wg)
+        fk = [v for (k, g), v in kf.items() if same(k, g)]
+        wk = [v for (k, g), v in kw.items() if same(k, g)]
+        if not fk or not wk:
+            continue
+        fv = max(fk, key=len)
+        wv = max(wk, key=len)
+        fb = statistics.mean(fv) / 1024
+        wb = statistics.mean(wv) / 1024
+        kernels[name] = {"fetch_bytes": round(fb * 1024 * f_factor), "write_bytes":
+                         round(wb * 1024 * w_factor), "dispatches": len(fv)}
+        lines.append(f"| {name} | `{sym.rstrip('(')}` | {wg} | {len(fv)} | {fb:.0f} | {wb:.0f} | "
+                     f"{kernels[name]['fetch_bytes']} | {kernels[name]['write_bytes']} |")
+    t = {"sources_sha256": sources_digest(), "fetch_factor": f_factor, "write_factor": w_factor,
+         "kernels": kernels}
+    with open(TRAFFIC_JSON, "w") as f:
+        json.dump(t, f, indent=1)
+    with open(out_md, "w") as f:
+        f.write("# HBM traffic per dispatch: R-MAT 2^20 / 2^24 edges, B=16, batches of 10^6\n\n"
+                "Commands (GPU box, repo root as $R):\n\n```\n" + "\n".join(commands) +
+                "\n```\n\nCalibration: a plain 1 GiB device copy reads "
+                f"{1 / f_factor:.3f} GiB by FETCH_SIZE and writes {1 / w_factor:.3f} GiB by "
+                f"WRITE_SIZE, so FETCH_SIZE is scaled by {f_factor:.3f} and WRITE_SIZE by "
+                f"{w_factor:.3f}.  The scaled bytes per dispatch are stored in "
+                f"`{os.path.basename(TRAFFIC_JSON)}` with the SHA-256 of the kernel sources "
+                "they were measured on; `bench.py` reports them as `roofline.traffic` only "
+                "while the sources match.\n\n" + "\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,10 +211,28 @@ def main():
     ap.add_argument("--edges", type=int, default=1 << 24)
     ap.add_argument("--queries", type=int, default=5, help="timed query batches")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "OUT_MD"),
+                    help="write a kernel-trace summary (no GPU)")
+    ap.add_argument("--summarize-traffic", nargs=5,
+                    metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR", "OUT_MD"),
+                    help="write the HBM traffic summary and its JSON (no GPU)")
+    ap.add_argument("--command", action="append", default=[],
+                    help="command line recorded in a summary")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
 
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace, "\n".join(args.command))
+        return
+    if args.summarize_traffic:
+        k = args.batch
+        grid = {"sort_pass": (k + 4095) // 4096, "probe_insert": None, "probe_delete": None,
+                "probe_query": None, "compact": None, "append": (k + 255) // 256,
+                "sort_hist": min((k + 4095) // 4096, 256)}
+        summarize_traffic(*args.summarize_traffic[:4], grid, args.summarize_traffic[4],
+                          args.command)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -196,7 +346,7 @@ def main():
         ach = bpl / avg_s / 1e9
         roof = {"bound": "hbm", "kernel": dominant, "achieved": round(ach, 2),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5),
-                "traffic": None, "bytes_per_launch": int(bpl),
+                "traffic": stored_traffic(dominant), "bytes_per_launch": int(bpl),
                 "avg_launch_us": round(avg_s * 1e6, 3), "launches": dom_launches}
 
     # ---- queries, in their own loop
@@ -242,7 +392,7 @@ def main():
         o = O.OracleGraph(n, src_np[sel], dst_np[sel], block_slots=B)
         pairs = 0
         t0 = time.perf_counter()
-        for j in range(min(2, args.steps)):
+        for j in range(min(CPU_STEPS, args.steps)):
             jj = args.warmup + 1 + j
             for batch, fn in ((ins[jj], o.insert_edges), (dels[jj], o.delete_edges)):
                 bs = batch[0].cpu().numpy().view(np.uint32)
@@ -254,7 +404,7 @@ def main():
         o.close()
         cpu = {"value": round(pairs / cpu_s, 1), "unit": "edges/s", "cores": 1,
                "kind": "oracle",
-               "sample": f"{min(2, args.steps)} insert + delete batch pairs whose source "
+               "sample": f"{min(CPU_STEPS, args.steps)} insert + delete batch pairs whose source "
                          f"hashes to 0 mod 4 ({pairs} pairs) against the graph restricted "
                          f"to those sources ({int(sel.sum())} edges)"}
 

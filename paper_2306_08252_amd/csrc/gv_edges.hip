@@ -47,8 +47,11 @@ constexpr uint8_t kHead = 1, kUniq = 2;
 #endif
 constexpr int kGroup = GV_PROBE_GROUP;         // lanes per work item
 constexpr int kGroupsPerWave = 64 / kGroup;
-constexpr int kStage = 128;                    // segment entries staged in LDS
-constexpr int kStageLog = 7;                   // log2(kStage)
+#ifndef GV_PROBE_STAGE_LOG
+#define GV_PROBE_STAGE_LOG 7
+#endif
+constexpr int kStageLog = GV_PROBE_STAGE_LOG;  // log2(kStage)
+constexpr int kStage = 1 << kStageLog;         // segment entries staged in LDS
 constexpr int kWinLog = 12;                    // unrolled global search steps
 constexpr int kUnroll = GV_PROBE_UNROLL;       // slots per lane per step
 constexpr uint32_t kBigR = 256;                // deletes per source handled by a workgroup
@@ -476,10 +479,16 @@ __global__ __launch_bounds__(kThreads) void k_probe(GraphView g, const uint64_t*
         // vertex whose only block is stored inline
         const uint32_t* dp = I.dcls != kNoDir ? g.dir + I.dirbase : &items[it].blk0;
         uint32_t e[kUnroll];
+        if (I.dcls != kNoDir) {
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const uint32_t si = min(s + u * kGroup, I.s1 - 1);
-            e[u] = dp[si >> g.log2B];
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint32_t si = min(s + u * kGroup, I.s1 - 1);
+                e[u] = dp[si >> g.log2B];
+            }
+        } else {
+            // the only block: its id is in the descriptor, no load
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) e[u] = I.blk0;
         }
         constexpr int kSv = kStage / kGroup;
         const uint32_t* klo = (const uint32_t*)keys;  // low words: destinations
@@ -487,7 +496,7 @@ __global__ __launch_bounds__(kThreads) void k_probe(GraphView g, const uint64_t*
 #pragma unroll
         for (int r = 0; r < kSv; ++r) {
             const uint32_t j = min(gl + r * kGroup, ns - 1);
-            sv[r] = klo[2ull * (I.lo + (j << shift))] & (uint32_t)dmask;
+            sv[r] = r * kGroup < ns ? klo[2ull * (I.lo + (j << shift))] & (uint32_t)dmask : 0u;
         }
         uint32_t x[kUnroll];
         uint64_t addr[kUnroll];
@@ -500,8 +509,9 @@ __global__ __launch_bounds__(kThreads) void k_probe(GraphView g, const uint64_t*
         for (int u = 0; u < kUnroll; ++u) x[u] = g.pool[addr[u]];
 #pragma unroll
         for (int r = 0; r < kSv; ++r) {
-            const uint32_t j = gl + r * kGroup;  // covers the whole stage
-            st[j] = j < ns ? sv[r] : 0xFFFFFFFFu;
+            // the searches read st[0, 2^steps) only
+            const uint32_t j = gl + r * kGroup;
+            if (r * kGroup < (1u << steps)) st[j] = j < ns ? sv[r] : 0xFFFFFFFFu;
         }
         wave_lds_sync();
         // the loads of step k+1 are issued before step k is searched and
