@@ -49,6 +49,7 @@ void free_graph(gv_graph* g) {
     hipStreamSynchronize(g->ctx.stream);
     g->ctx.release();
     g->scratch.release();
+    for (auto& v : g->vscr) v.release();
     void* mem[] = {g->mem_pool, g->mem_free, g->mem_dir, g->mem_dfree,
                    g->mem_vt,   g->mem_active, g->mem_ctr};
     for (void* p : mem)

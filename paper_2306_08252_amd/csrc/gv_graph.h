@@ -11,6 +11,7 @@ struct gv_graph {
     gv::GraphView v{};            // device pointers and sizes
     gv::DevCounters* hctr = nullptr;  // pinned host copy for read-back
     gv::Scratch scratch;          // per-call temporaries
+    gv::Scratch vscr[3];          // vertex-batch buffers that outlive an inner edge batch
     uint64_t item_slots = 0;      // bound on live adjacency slots (pool slots)
     // device allocations owned by the graph
     void* mem_pool = nullptr;

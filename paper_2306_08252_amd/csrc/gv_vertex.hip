@@ -138,10 +138,71 @@ __global__ __launch_bounds__(kThreads) void k_vdel_mark(GraphView g, const uint3
 // 16-lane groups, one vertex each: count (EMIT = false) or emit (EMIT = true)
 // the edges that touch a deleted vertex; emitted pairs go to the vertex's
 // scanned offset, in slot order
-constexpr int kVGroup = 16;
+constexpr int kVGroup = 16;          // lanes per sweep unit
+constexpr int kVUnroll = 4;          // slots per lane per step
+constexpr uint32_t kVChunk = 256;    // adjacency slots per sweep unit
 
+// Sweep units: every active vertex with edges is cut into units of kVChunk
+// slots, so that a hub is swept by many groups at once.  The scan gives each
+// vertex the index of its first unit.
+struct UnitIn {
+    GraphView g;
+    struct Rec {
+        VRec r;
+        bool act;
+    };
+    __device__ uint64_t limit(uint64_t n) const { return n; }
+    __device__ Rec load(uint64_t u, bool) const {
+        Rec x;
+        x.r = g.vt[u];
+        x.act = active_bit(g, (uint32_t)u);
+        return x;
+    }
+    __device__ void deref(Rec&) const {}
+    __device__ unsigned long long value(uint64_t, const Rec& x) const {
+        return x.act ? (x.r.deg + kVChunk - 1) / kVChunk : 0u;
+    }
+};
+
+// plain form of UnitIn for the three-kernel scan
+struct UnitCount {
+    GraphView g;
+    __device__ unsigned long long operator()(uint64_t u) const {
+        if (u >= g.n_cap || !active_bit(g, (uint32_t)u)) return 0ull;
+        return (g.vt[u].deg + kVChunk - 1) / kVChunk;
+    }
+};
+
+// unit = (vertex, first slot) at the vertex's scanned offset; a lane writes
+// the units of its vertex, the whole wave those of a vertex with more than 4
+__global__ __launch_bounds__(kThreads) void k_vdel_units(GraphView g,
+                                                         const unsigned long long* uoff,
+                                                         uint2* units) {
+    const uint64_t u = vt_tidx();
+    uint32_t cnt = 0;
+    unsigned long long base = 0;
+    if (u < g.n_cap && active_bit(g, (uint32_t)u)) {
+        cnt = (g.vt[u].deg + kVChunk - 1) / kVChunk;
+        base = uoff[u];
+    }
+    if (cnt <= 4)
+        for (uint32_t c = 0; c < cnt; ++c) units[base + c] = make_uint2((uint32_t)u, c * kVChunk);
+    uint64_t m = ballot(cnt > 4);
+    while (m) {
+        const int l = __ffsll((unsigned long long)m) - 1;
+        m &= m - 1;
+        const uint32_t wu = __shfl((uint32_t)u, l, 64), wc = __shfl(cnt, l, 64);
+        const unsigned long long wb = __shfl(base, l, 64);
+        for (uint32_t c = lane_id(); c < wc; c += 64) units[wb + c] = make_uint2(wu, c * kVChunk);
+    }
+}
+
+// Count (EMIT = false) or emit (EMIT = true) the pairs of each unit that
+// touch a deleted vertex: all slots of a deleted source, and every slot that
+// holds a deleted destination.  Emitted pairs go to offs[unit] + rank.
 template <bool EMIT>
 __global__ __launch_bounds__(kThreads) void k_vdel_sweep(GraphView g, const uint32_t* gone,
+                                                         const uint2* units, uint64_t nunits,
                                                          uint32_t* cnt,
                                                          const unsigned long long* offs,
                                                          uint32_t* psrc, uint32_t* pdst,
@@ -152,32 +213,41 @@ __global__ __launch_bounds__(kThreads) void k_vdel_sweep(GraphView g, const uint
     const uint64_t below = (1ull << gl) - 1;
     const uint64_t ngroups = (uint64_t)gridDim.x * kThreads / kVGroup;
     const uint64_t grp = ((uint64_t)blockIdx.x * kThreads + threadIdx.x) / kVGroup;
-    for (uint64_t u = grp; u < g.n_cap; u += ngroups) {
-        const VRec r = g.vt[u];
+    for (uint64_t k = grp; k < nunits; k += ngroups) {
+        const uint2 U = units[k];
+        const VRec r = g.vt[U.x];
+        const uint32_t s1 = min(r.deg, U.y + kVChunk);
+        const bool src_gone = bit_of(gone, U.x);
+        const uint64_t base = EMIT ? offs[k] : 0ull;
         uint32_t c = 0;
-        if (r.deg != 0 && is_active(g, u)) {
-            const bool src_gone = bit_of(gone, (uint32_t)u);
-            const uint64_t base = EMIT ? offs[u] : 0ull;
-            for (uint32_t s0 = 0; s0 < r.deg; s0 += kVGroup) {
-                const uint32_t s = s0 + gl;
-                bool hit = false;
-                uint32_t x = 0;
-                if (s < r.deg) {
-                    x = g.pool[slot_addr(g, r, s)];
-                    hit = src_gone || bit_of(gone, x);
-                }
-                const uint64_t m = (ballot(hit) >> g0) & ((1ull << kVGroup) - 1);
-                if (EMIT && hit) {
+        for (uint32_t s0 = U.y; s0 < s1; s0 += kVGroup * kVUnroll) {
+            uint32_t blk[kVUnroll], x[kVUnroll];
+            bool hit[kVUnroll];
+#pragma unroll
+            for (int j = 0; j < kVUnroll; ++j)
+                blk[j] = block_of(g, r, min(s0 + j * kVGroup + gl, s1 - 1) >> g.log2B);
+#pragma unroll
+            for (int j = 0; j < kVUnroll; ++j) {
+                const uint32_t s = min(s0 + j * kVGroup + gl, s1 - 1);
+                x[j] = g.pool[((uint64_t)blk[j] << g.log2B) + (s & (g.B - 1))];
+            }
+#pragma unroll
+            for (int j = 0; j < kVUnroll; ++j)
+                hit[j] = s0 + j * kVGroup + gl < s1 && (src_gone || bit_of(gone, x[j]));
+#pragma unroll
+            for (int j = 0; j < kVUnroll; ++j) {
+                const uint64_t m = (ballot(hit[j]) >> g0) & ((1ull << kVGroup) - 1);
+                if (EMIT && hit[j]) {
                     const uint64_t pos = base + c + popc64(m & below);
                     if (pos < cap) {
-                        psrc[pos] = (uint32_t)u;
-                        pdst[pos] = x;
+                        psrc[pos] = U.x;
+                        pdst[pos] = x[j];
                     }
                 }
                 c += popc64(m);
             }
         }
-        if (!EMIT && gl == 0) cnt[u] = c;
+        if (!EMIT && gl == 0) cnt[k] = c;
     }
 }
 
@@ -235,15 +305,11 @@ static uint32_t* sorted_ids(gv_graph* g, const uint32_t* ids, uint64_t n, uint32
     return radix_sort<uint32_t, false>(c, k0, k1, nullptr, nullptr, n, 32, ss) ? k1 : k0;
 }
 
-struct DevBuf {
-    void* p = nullptr;
-    explicit DevBuf(size_t bytes) { hip_check(hipMalloc(&p, std::max<size_t>(bytes, 4)), "hipMalloc"); }
-    ~DevBuf() {
-        if (p) hipFree(p);
-    }
-    DevBuf(const DevBuf&) = delete;
-    DevBuf& operator=(const DevBuf&) = delete;
-};
+// a vertex batch's own buffer, kept by the graph between calls
+static void* vbuf(gv_graph* g, int slot, size_t bytes) {
+    g->vscr[slot].ensure(std::max<size_t>(bytes, 4), g->ctx.stream);
+    return g->vscr[slot].ptr;
+}
 
 static void grow_table(gv_graph* g, uint64_t new_cap) {
     Ctx& c = g->ctx;
@@ -279,8 +345,7 @@ void vertex_insert(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats*
         while (cap <= (uint64_t)g->hctr->vmax) cap <<= 1;
         grow_table(g, cap);
     }
-    DevBuf keys(2 * n * sizeof(uint32_t));
-    uint32_t* k0 = (uint32_t*)keys.p;
+    uint32_t* k0 = (uint32_t*)vbuf(g, 0, 2 * n * sizeof(uint32_t));
     uint32_t* sorted = sorted_ids(g, ids, n, k0, k0 + n);
     c.launch("vinsert", k_vins, div_up(n, kThreads), kThreads, g->v, (const uint32_t*)sorted, n);
     read_counters(g);
@@ -296,8 +361,7 @@ void vertex_delete(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats*
     const GraphView& v = g->v;
     if (n >= 0xffffffffull) fail(GV_EINVAL, "batch too large");
     const uint64_t words = (v.n_cap + 31) / 32;
-    DevBuf tmp((2 * n + words) * sizeof(uint32_t));
-    uint32_t* k0 = (uint32_t*)tmp.p;
+    uint32_t* k0 = (uint32_t*)vbuf(g, 0, (2 * n + words) * sizeof(uint32_t));
     uint32_t* gone = k0 + 2 * n;
     c.launch("vreset", k_vreset, 1, 1, v.ctr);
     c.launch("vzero", k_vzero, div_up(words, kThreads), kThreads, gone, words);
@@ -309,37 +373,55 @@ void vertex_delete(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats*
     const uint64_t rejected = g->hctr->st_rejected;
     const uint64_t uniq = g->hctr->n_uniq;
     if (applied) {
-        const uint64_t vgrid = std::min<uint64_t>(div_up(v.n_cap * kVGroup, kThreads), 8192);
-        DevBuf cb((v.n_cap + 1) * (sizeof(uint32_t) + sizeof(unsigned long long)) +
-                  8 * (scan2_parts(v.n_cap) + scan_partials_needed(v.n_cap) + 2));
-        uint32_t* cnt = (uint32_t*)cb.p;
-        unsigned long long* offs = (unsigned long long*)(cnt + ((v.n_cap + 2) & ~1ull));
-        unsigned long long* part = offs + v.n_cap + 1;
-        c.launch("vdel_count", k_vdel_sweep<false>, vgrid, kThreads, v, (const uint32_t*)gone, cnt,
-                 (const unsigned long long*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr,
-                 (uint64_t)0);
-        if (scan2_parts(v.n_cap) <= kScan2MaxTiles)
-            scan2(c, "vdel_scan", CntIn{cnt}, U64Out{offs}, v.n_cap, part, &v.ctr->edges);
+        // sweep units of every active vertex with edges
+        const uint64_t ncap = v.n_cap;
+        const bool small_scan = scan2_parts(ncap + 1) <= kScan2MaxTiles;
+        unsigned long long* uoff = (unsigned long long*)vbuf(
+            g, 1, (ncap + 1) * 8 + 8 * (scan2_parts(ncap + 1) + scan_partials_needed(ncap + 1) + 2));
+        unsigned long long* upart = uoff + ncap + 1;
+        if (small_scan)
+            scan2(c, "vdel_units", UnitIn{v}, U64Out{uoff}, ncap, upart, &v.ctr->edges);
         else
-            scan_excl<unsigned long long>(c, CntIn{cnt}, U64Out{offs}, v.n_cap, part,
+            scan_excl<unsigned long long>(c, UnitCount{v}, U64Out{uoff}, ncap, upart,
                                           &v.ctr->edges);
         read_counters(g);
-        const uint64_t pairs = g->hctr->edges;
+        const uint64_t nunits = g->hctr->edges;
+        // the unit offsets are done with once the units are written: the
+        // units, their counts and offsets take the next buffer
+        uint2* units = (uint2*)vbuf(
+            g, 2, nunits * (sizeof(uint2) + sizeof(uint32_t) + sizeof(unsigned long long)) +
+                      8 * (scan2_parts(nunits + 1) + scan_partials_needed(nunits + 1) + 4));
+        uint32_t* cnt = (uint32_t*)(units + nunits);
+        unsigned long long* offs = (unsigned long long*)(((uintptr_t)(cnt + nunits) + 7) & ~(uintptr_t)7);
+        unsigned long long* part = offs + nunits;
+        c.launch("vdel_units", k_vdel_units, div_up(ncap, kThreads), kThreads, v,
+                 (const unsigned long long*)uoff, units);
+        const uint64_t vgrid = std::min<uint64_t>(div_up(nunits * kVGroup, kThreads),
+                                                  resident_grid(k_vdel_sweep<false>, kThreads));
+        uint64_t pairs = 0;
+        if (nunits) {
+            c.launch("vdel_count", k_vdel_sweep<false>, vgrid, kThreads, v, (const uint32_t*)gone,
+                     (const uint2*)units, nunits, cnt, (const unsigned long long*)nullptr,
+                     (uint32_t*)nullptr, (uint32_t*)nullptr, (uint64_t)0);
+            if (scan2_parts(nunits) <= kScan2MaxTiles)
+                scan2(c, "vdel_scan", CntIn{cnt}, U64Out{offs}, nunits, part, &v.ctr->edges);
+            else
+                scan_excl<unsigned long long>(c, CntIn{cnt}, U64Out{offs}, nunits, part,
+                                              &v.ctr->edges);
+            read_counters(g);
+            pairs = g->hctr->edges;
+        }
         if (pairs) {
-            DevBuf pb(2 * pairs * sizeof(uint32_t));
-            uint32_t* psrc = (uint32_t*)pb.p;
+            uint32_t* psrc = (uint32_t*)vbuf(g, 1, 2 * pairs * sizeof(uint32_t));
             uint32_t* pdst = psrc + pairs;
             c.launch("vdel_emit", k_vdel_sweep<true>, vgrid, kThreads, v, (const uint32_t*)gone,
-                     cnt, (const unsigned long long*)offs, psrc, pdst, pairs);
+                     (const uint2*)units, nunits, cnt, (const unsigned long long*)offs, psrc, pdst,
+                     pairs);
             edge_batch(g, kDelete, psrc, pdst, pairs, nullptr, false);
-            c.launch("vdel_finish", k_vdel_finish, div_up(n, kThreads), kThreads, g->v,
-                     (const uint32_t*)sorted, n, (const uint32_t*)gone);
-            hip_check(hipStreamSynchronize(c.stream), "hipStreamSynchronize");
-        } else {
-            c.launch("vdel_finish", k_vdel_finish, div_up(n, kThreads), kThreads, g->v,
-                     (const uint32_t*)sorted, n, (const uint32_t*)gone);
-            hip_check(hipStreamSynchronize(c.stream), "hipStreamSynchronize");
         }
+        c.launch("vdel_finish", k_vdel_finish, div_up(n, kThreads), kThreads, g->v,
+                 (const uint32_t*)sorted, n, (const uint32_t*)gone);
+        hip_check(hipStreamSynchronize(c.stream), "hipStreamSynchronize");
     }
     if (st) {
         st->applied = applied;
