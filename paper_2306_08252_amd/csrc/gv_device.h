@@ -62,6 +62,8 @@ struct DevCounters {
     uint32_t err_batch, err_sticky, err_wait, n_big;
     uint32_t n_heavy, n_heavy_pad;     // sources left to whole waves this batch
     uint32_t sort_n, sort_err;  // count and look-back error word of whole-graph sorts
+    // vertex delete: sweep units, kept slots, freed blocks | removed edges << 32
+    unsigned long long v_units, v_kept, v_fr;
     // totals of the single-pass scans of the current batch
     unsigned long long tot[8];
     // statistics of the last batch

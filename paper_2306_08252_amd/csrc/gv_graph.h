@@ -38,7 +38,9 @@ void bulk_build(gv_graph* g, uint64_t num_vertices, const uint32_t* src, const u
                 uint64_t m, const gv_config& cfg);
 
 void vertex_insert(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats* st);
-void vertex_delete(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats* st);
+// edge_bound: upper bound on the edges stored (0: read it, synchronising)
+void vertex_delete(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats* st,
+                   uint64_t edge_bound = 0);
 
 void adjacency(gv_graph* g, uint32_t v, uint32_t* out, uint64_t cap, uint64_t* degree);
 void dump(gv_graph* g, uint64_t* offsets, uint32_t* dst, uint64_t cap, uint64_t* checksum,

@@ -4,11 +4,15 @@
 // the dictionary is replaced by one of the next power-of-two capacity (copy
 // kernel, then the old one is freed); inactive ids are switched on.
 //
-// Delete: the deleted set is marked in a bitmap; one sweep over every
-// adjacency emits the out-edges of deleted vertices and the in-edges that
-// point at them; those pairs go through the batched edge-delete pipeline
-// (which compacts and frees blocks); finally the vertices are switched off
-// and their directory segments returned.
+// Delete: the deleted set is marked in a bitmap.  Every adjacency is cut
+// into sweep units of 256 slots; a count pass finds the slots each unit keeps
+// (none for a deleted source, else those whose destination is not deleted),
+// a scan over units places them, the kept slots of every vertex that loses
+// any are gathered into a staging buffer and written back in order from
+// slot 0, emptied blocks go on the free list (a scan over vertices places
+// them), and the deleted vertices are switched off with their directory
+// segments returned.  All sizes are bounds known on the host, so the path has
+// no host round trip.
 #include <algorithm>
 
 #include "gv_graph.h"
@@ -197,73 +201,182 @@ __global__ __launch_bounds__(kThreads) void k_vdel_units(GraphView g,
     }
 }
 
-// Count (EMIT = false) or emit (EMIT = true) the pairs of each unit that
-// touch a deleted vertex: all slots of a deleted source, and every slot that
-// holds a deleted destination.  Emitted pairs go to offs[unit] + rank.
-template <bool EMIT>
-__global__ __launch_bounds__(kThreads) void k_vdel_sweep(GraphView g, const uint32_t* gone,
-                                                         const uint2* units, uint64_t nunits,
-                                                         uint32_t* cnt,
-                                                         const unsigned long long* offs,
-                                                         uint32_t* psrc, uint32_t* pdst,
-                                                         uint64_t cap) {
+// Three passes over the sweep units (unit count on the device):
+//   kCount   kept[k] = slots of unit k that stay
+//   kGather  for a vertex that loses slots, its unit's kept values go to
+//            stage[P[k] + rank] (P = exclusive scan of kept)
+//   kScatter they are written back to the vertex's slots P[k] - P[first] ...
+enum VPass { kCount = 0, kGather = 1, kScatter = 2 };
+
+template <int PASS>
+__global__ __launch_bounds__(kThreads) void k_vdel_pass(GraphView g, const uint32_t* gone,
+                                                        const uint2* units,
+                                                        const unsigned long long* uoff,
+                                                        uint32_t* kept,
+                                                        const unsigned long long* P,
+                                                        uint32_t* stage) {
     const uint32_t lane = lane_id();
     const uint32_t gl = lane & (kVGroup - 1);
     const uint32_t g0 = lane & ~(uint32_t)(kVGroup - 1);
     const uint64_t below = (1ull << gl) - 1;
     const uint64_t ngroups = (uint64_t)gridDim.x * kThreads / kVGroup;
     const uint64_t grp = ((uint64_t)blockIdx.x * kThreads + threadIdx.x) / kVGroup;
+    const uint64_t nunits = g.ctr->v_units;
     for (uint64_t k = grp; k < nunits; k += ngroups) {
         const uint2 U = units[k];
         const VRec r = g.vt[U.x];
         const uint32_t s1 = min(r.deg, U.y + kVChunk);
         const bool src_gone = bit_of(gone, U.x);
-        const uint64_t base = EMIT ? offs[k] : 0ull;
+        unsigned long long base = 0, vbase = 0;
+        if (PASS != kCount) {
+            // the vertex's new degree: kept slots over all its units
+            const unsigned long long f = uoff[U.x];
+            const unsigned long long nu = (r.deg + kVChunk - 1) / kVChunk;
+            vbase = P[f];
+            const unsigned long long newdeg = P[f + nu] - vbase;
+            if (newdeg == r.deg) continue;  // the vertex keeps every slot
+            base = P[k];
+        }
+        if (PASS == kScatter) {
+            // stage[P[k] .. P[k] + kept[k]) -> slots P[k] - P[first] ...
+            const uint32_t nk = kept[k];
+            const uint32_t d0 = (uint32_t)(base - vbase);
+            for (uint32_t j = gl; j < nk; j += kVGroup) {
+                const uint32_t sl = d0 + j;
+                g.pool[slot_addr(g, r, sl)] = stage[base + j];
+            }
+            continue;
+        }
         uint32_t c = 0;
         for (uint32_t s0 = U.y; s0 < s1; s0 += kVGroup * kVUnroll) {
             uint32_t blk[kVUnroll], x[kVUnroll];
-            bool hit[kVUnroll];
+            bool keep[kVUnroll];
 #pragma unroll
             for (int j = 0; j < kVUnroll; ++j)
                 blk[j] = block_of(g, r, min(s0 + j * kVGroup + gl, s1 - 1) >> g.log2B);
 #pragma unroll
             for (int j = 0; j < kVUnroll; ++j) {
-                const uint32_t s = min(s0 + j * kVGroup + gl, s1 - 1);
-                x[j] = g.pool[((uint64_t)blk[j] << g.log2B) + (s & (g.B - 1))];
+                const uint32_t sl = min(s0 + j * kVGroup + gl, s1 - 1);
+                x[j] = g.pool[((uint64_t)blk[j] << g.log2B) + (sl & (g.B - 1))];
             }
 #pragma unroll
             for (int j = 0; j < kVUnroll; ++j)
-                hit[j] = s0 + j * kVGroup + gl < s1 && (src_gone || bit_of(gone, x[j]));
+                keep[j] = s0 + j * kVGroup + gl < s1 && !src_gone && !bit_of(gone, x[j]);
 #pragma unroll
             for (int j = 0; j < kVUnroll; ++j) {
-                const uint64_t m = (ballot(hit[j]) >> g0) & ((1ull << kVGroup) - 1);
-                if (EMIT && hit[j]) {
-                    const uint64_t pos = base + c + popc64(m & below);
-                    if (pos < cap) {
-                        psrc[pos] = U.x;
-                        pdst[pos] = x[j];
-                    }
-                }
+                const uint64_t m = (ballot(keep[j]) >> g0) & ((1ull << kVGroup) - 1);
+                if (PASS == kGather && keep[j]) stage[base + c + popc64(m & below)] = x[j];
                 c += popc64(m);
             }
         }
-        if (!EMIT && gl == 0) cnt[k] = c;
+        if (PASS == kCount && gl == 0) kept[k] = c;
     }
 }
 
-// per-vertex pair counts; both the gather interface of scan2 and the plain
-// one of scan_excl
-struct CntIn {
-    const uint32_t* cnt;
+// kept slots per unit, for the scan that places them
+struct KeptIn {
+    const uint32_t* kept;
+    const DevCounters* ctr;
     struct Rec {
         uint32_t c;
     };
-    __device__ uint64_t limit(uint64_t n) const { return n; }
-    __device__ Rec load(uint64_t i, bool) const { return Rec{cnt[i]}; }
+    __device__ uint64_t limit(uint64_t n) const { return min((uint64_t)ctr->v_units, n); }
+    __device__ Rec load(uint64_t i, bool ok) const { return Rec{kept[ok ? i : 0]}; }
     __device__ void deref(Rec&) const {}
     __device__ unsigned long long value(uint64_t, const Rec& r) const { return r.c; }
-    __device__ unsigned long long operator()(uint64_t i) const { return cnt[i]; }
+    __device__ unsigned long long operator()(uint64_t i) const {
+        return i < ctr->v_units ? kept[i] : 0ull;
+    }
 };
+
+// Per vertex: blocks it gives up (low half) and slots it loses (high half).
+struct LossIn {
+    GraphView g;
+    const unsigned long long* uoff;
+    const unsigned long long* P;
+    struct Rec {
+        VRec r;
+        unsigned long long f, a, b;
+    };
+    __device__ uint64_t limit(uint64_t n) const { return n; }
+    __device__ Rec load(uint64_t u, bool) const {
+        Rec x;
+        x.r = g.vt[u];
+        x.f = uoff[u];
+        x.a = x.b = 0;
+        return x;
+    }
+    __device__ void deref(Rec& x) const {
+        const unsigned long long nu = (x.r.deg + kVChunk - 1) / kVChunk;
+        x.a = P[x.f];
+        x.b = P[x.f + nu];
+    }
+    __device__ unsigned long long value(uint64_t u, const Rec& x) const {
+        if (!active_bit(g, (uint32_t)u)) return 0ull;
+        const uint32_t nd = (uint32_t)(x.b - x.a);
+        const unsigned long long lost = x.r.deg - nd;
+        return (unsigned long long)(nblocks(g, x.r.deg) - nblocks(g, nd)) | (lost << 32);
+    }
+    __device__ unsigned long long operator()(uint64_t u) const {
+        Rec x = load(u, true);
+        deref(x);
+        return value(u, x);
+    }
+};
+
+// Per vertex that lost slots: emptied blocks to the free list (at the
+// scanned position after the current free count), new degree.  A lane frees
+// up to 4 blocks, the whole wave the blocks of a vertex that frees more.
+__global__ __launch_bounds__(kThreads) void k_vdel_loss(GraphView g,
+                                                        const unsigned long long* uoff,
+                                                        const unsigned long long* P,
+                                                        const unsigned long long* pre) {
+    const uint64_t u = vt_tidx();
+    const bool live = u < g.n_cap && active_bit(g, (uint32_t)u);
+    VRec r{0u, 0u, kNoDir, 0u};
+    uint32_t nd = 0, nb0 = 0, nb1 = 0;
+    unsigned long long pos = 0;
+    if (live) {
+        r = g.vt[u];
+        const unsigned long long f = uoff[u];
+        nd = (uint32_t)(P[f + (r.deg + kVChunk - 1) / kVChunk] - P[f]);
+        nb0 = nblocks(g, r.deg);
+        nb1 = nblocks(g, nd);
+        pos = g.ctr->free_cnt + (pre[u] & 0xffffffffull);
+    }
+    const bool changed = live && nd != r.deg;
+    const uint32_t nfree = nb0 - nb1;
+    if (changed && nfree <= 4)
+        for (uint32_t j = 0; j < nfree; ++j) g.free_stack[pos + j] = block_of(g, r, nb1 + j);
+    uint64_t m = ballot(changed && nfree > 4);
+    while (m) {
+        const int l = __ffsll((unsigned long long)m) - 1;
+        m &= m - 1;
+        VRec w;
+        w.deg = __shfl(r.deg, l, 64);
+        w.dir = __shfl(r.dir, l, 64);
+        w.dcls = __shfl(r.dcls, l, 64);
+        w.aux = 0;
+        const uint32_t wb1 = __shfl(nb1, l, 64), wn = __shfl(nfree, l, 64);
+        const unsigned long long wp = __shfl(pos, l, 64);
+        for (uint32_t j = lane_id(); j < wn; j += 64) g.free_stack[wp + j] = block_of(g, w, wb1 + j);
+    }
+    if (changed) {
+        VRec nr = r;
+        nr.deg = nd;
+        if (nb1 == 0 && nr.dcls == kNoDir) nr.dir = 0;
+        g.vt[u] = nr;
+    }
+}
+
+__global__ void k_vdel_tail(DevCounters* c) {
+    const unsigned long long fr = c->v_fr;
+    c->free_cnt += fr & 0xffffffffull;
+    c->c_freed_blocks += fr & 0xffffffffull;
+    c->live_edges -= fr >> 32;
+}
+
+// offsets out of a scan, in both sink forms
 struct U64Out {
     unsigned long long* a;
     __device__ void operator()(uint64_t i, unsigned long long v) const { a[i] = v; }
@@ -356,11 +469,30 @@ void vertex_insert(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats*
     }
 }
 
-void vertex_delete(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats* st) {
+// scan over n elements with the two-kernel scan when it fits, else the
+// three-kernel one; `part` holds enough partials for either
+template <typename In, typename Plain, typename Out>
+static void scan_any(Ctx& c, const char* name, In in, Plain plain, Out out, uint64_t n,
+                     unsigned long long* part, unsigned long long* total) {
+    if (scan2_parts(n) <= kScan2MaxTiles)
+        scan2(c, name, in, out, n, part, total);
+    else
+        scan_excl<unsigned long long>(c, plain, out, n, part, total);
+}
+
+static uint64_t scan_words(uint64_t n) {
+    return scan2_parts(n) + scan_partials_needed(n) + 2;
+}
+
+// edge_bound: an upper bound on the edges stored when the call runs (0: read
+// it from the device, which synchronises)
+void vertex_delete(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats* st,
+                   uint64_t edge_bound) {
     Ctx& c = g->ctx;
     const GraphView& v = g->v;
     if (n >= 0xffffffffull) fail(GV_EINVAL, "batch too large");
-    const uint64_t words = (v.n_cap + 31) / 32;
+    const uint64_t ncap = v.n_cap;
+    const uint64_t words = (ncap + 31) / 32;
     uint32_t* k0 = (uint32_t*)vbuf(g, 0, (2 * n + words) * sizeof(uint32_t));
     uint32_t* gone = k0 + 2 * n;
     c.launch("vreset", k_vreset, 1, 1, v.ctr);
@@ -368,65 +500,71 @@ void vertex_delete(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats*
     uint32_t* sorted = sorted_ids(g, ids, n, k0, k0 + n);
     c.launch("vdel_mark", k_vdel_mark, div_up(n, kThreads), kThreads, v, (const uint32_t*)sorted,
              n, gone);
-    read_counters(g);
-    const uint64_t applied = g->hctr->st_applied;
-    const uint64_t rejected = g->hctr->st_rejected;
-    const uint64_t uniq = g->hctr->n_uniq;
-    if (applied) {
-        // sweep units of every active vertex with edges
-        const uint64_t ncap = v.n_cap;
-        const bool small_scan = scan2_parts(ncap + 1) <= kScan2MaxTiles;
-        unsigned long long* uoff = (unsigned long long*)vbuf(
-            g, 1, (ncap + 1) * 8 + 8 * (scan2_parts(ncap + 1) + scan_partials_needed(ncap + 1) + 2));
-        unsigned long long* upart = uoff + ncap + 1;
-        if (small_scan)
-            scan2(c, "vdel_units", UnitIn{v}, U64Out{uoff}, ncap, upart, &v.ctr->edges);
-        else
-            scan_excl<unsigned long long>(c, UnitCount{v}, U64Out{uoff}, ncap, upart,
-                                          &v.ctr->edges);
+    if (!edge_bound) {
         read_counters(g);
-        const uint64_t nunits = g->hctr->edges;
-        // the unit offsets are done with once the units are written: the
-        // units, their counts and offsets take the next buffer
-        uint2* units = (uint2*)vbuf(
-            g, 2, nunits * (sizeof(uint2) + sizeof(uint32_t) + sizeof(unsigned long long)) +
-                      8 * (scan2_parts(nunits + 1) + scan_partials_needed(nunits + 1) + 4));
-        uint32_t* cnt = (uint32_t*)(units + nunits);
-        unsigned long long* offs = (unsigned long long*)(((uintptr_t)(cnt + nunits) + 7) & ~(uintptr_t)7);
-        unsigned long long* part = offs + nunits;
-        c.launch("vdel_units", k_vdel_units, div_up(ncap, kThreads), kThreads, v,
-                 (const unsigned long long*)uoff, units);
-        const uint64_t vgrid = std::min<uint64_t>(div_up(nunits * kVGroup, kThreads),
-                                                  resident_grid(k_vdel_sweep<false>, kThreads));
-        uint64_t pairs = 0;
-        if (nunits) {
-            c.launch("vdel_count", k_vdel_sweep<false>, vgrid, kThreads, v, (const uint32_t*)gone,
-                     (const uint2*)units, nunits, cnt, (const unsigned long long*)nullptr,
-                     (uint32_t*)nullptr, (uint32_t*)nullptr, (uint64_t)0);
-            if (scan2_parts(nunits) <= kScan2MaxTiles)
-                scan2(c, "vdel_scan", CntIn{cnt}, U64Out{offs}, nunits, part, &v.ctr->edges);
-            else
-                scan_excl<unsigned long long>(c, CntIn{cnt}, U64Out{offs}, nunits, part,
-                                              &v.ctr->edges);
-            read_counters(g);
-            pairs = g->hctr->edges;
+        if (!g->hctr->st_applied) {
+            if (st) {
+                st->applied = 0;
+                st->rejected = g->hctr->st_rejected;
+                st->batch_duplicates = n - g->hctr->st_rejected - g->hctr->n_uniq;
+            }
+            return;
         }
-        if (pairs) {
-            uint32_t* psrc = (uint32_t*)vbuf(g, 1, 2 * pairs * sizeof(uint32_t));
-            uint32_t* pdst = psrc + pairs;
-            c.launch("vdel_emit", k_vdel_sweep<true>, vgrid, kThreads, v, (const uint32_t*)gone,
-                     (const uint2*)units, nunits, cnt, (const unsigned long long*)offs, psrc, pdst,
-                     pairs);
-            edge_batch(g, kDelete, psrc, pdst, pairs, nullptr, false);
-        }
-        c.launch("vdel_finish", k_vdel_finish, div_up(n, kThreads), kThreads, g->v,
-                 (const uint32_t*)sorted, n, (const uint32_t*)gone);
-        hip_check(hipStreamSynchronize(c.stream), "hipStreamSynchronize");
+        edge_bound = g->hctr->live_edges;
     }
+    // per-vertex buffers: unit offsets, loss prefixes, scan partials
+    unsigned long long* uoff = (unsigned long long*)vbuf(
+        g, 1, (2 * (ncap + 1) + scan_words(ncap + 1)) * sizeof(unsigned long long));
+    unsigned long long* lpre = uoff + ncap + 1;
+    unsigned long long* vpart = lpre + ncap + 1;
+    // per-unit buffers: units, kept counts, their scan, staging
+    const uint64_t ubound = ncap + edge_bound / kVChunk + 1;
+    uint2* units = nullptr;
+    uint32_t *kept = nullptr, *stage = nullptr;
+    unsigned long long *P = nullptr, *upart = nullptr;
+    auto carve = [&](Carver& cv) {
+        units = cv.take<uint2>(ubound);
+        kept = cv.take<uint32_t>(ubound);
+        P = cv.take<unsigned long long>(ubound + 1);
+        upart = cv.take<unsigned long long>(scan_words(ubound + 1));
+        stage = cv.take<uint32_t>(std::max<uint64_t>(edge_bound, 1));
+    };
+    {
+        Carver m0(nullptr);
+        carve(m0);
+        Carver cv(vbuf(g, 2, m0.used));
+        carve(cv);
+    }
+    scan_any(c, "vdel_units", UnitIn{v}, UnitCount{v}, U64Out{uoff}, ncap, vpart,
+             &v.ctr->v_units);
+    c.launch("vdel_units", k_vdel_units, div_up(ncap, kThreads), kThreads, v,
+             (const unsigned long long*)uoff, units);
+    const uint64_t vgrid = std::min<uint64_t>(div_up(ubound * kVGroup, kThreads),
+                                              resident_grid(k_vdel_pass<kCount>, kThreads));
+    c.launch("vdel_count", k_vdel_pass<kCount>, vgrid, kThreads, v, (const uint32_t*)gone,
+             (const uint2*)units, (const unsigned long long*)uoff, kept,
+             (const unsigned long long*)nullptr, (uint32_t*)nullptr);
+    scan_any(c, "vdel_place", KeptIn{kept, v.ctr}, KeptIn{kept, v.ctr}, U64Out{P}, ubound + 1,
+             upart, &v.ctr->v_kept);
+    c.launch("vdel_gather", k_vdel_pass<kGather>, vgrid, kThreads, v, (const uint32_t*)gone,
+             (const uint2*)units, (const unsigned long long*)uoff, kept,
+             (const unsigned long long*)P, stage);
+    c.launch("vdel_scatter", k_vdel_pass<kScatter>, vgrid, kThreads, v, (const uint32_t*)gone,
+             (const uint2*)units, (const unsigned long long*)uoff, kept,
+             (const unsigned long long*)P, stage);
+    scan_any(c, "vdel_loss", LossIn{v, uoff, P}, LossIn{v, uoff, P}, U64Out{lpre}, ncap, vpart,
+             &v.ctr->v_fr);
+    c.launch("vdel_loss", k_vdel_loss, div_up(ncap, kThreads), kThreads, v,
+             (const unsigned long long*)uoff, (const unsigned long long*)P,
+             (const unsigned long long*)lpre);
+    c.launch("vdel_tail", k_vdel_tail, 1, 1, v.ctr);
+    c.launch("vdel_finish", k_vdel_finish, div_up(n, kThreads), kThreads, g->v,
+             (const uint32_t*)sorted, n, (const uint32_t*)gone);
     if (st) {
-        st->applied = applied;
-        st->rejected = rejected;
-        st->batch_duplicates = n - rejected - uniq;
+        read_counters(g);
+        st->applied = g->hctr->st_applied;
+        st->rejected = g->hctr->st_rejected;
+        st->batch_duplicates = n - g->hctr->st_rejected - g->hctr->n_uniq;
     }
 }
 
