@@ -205,11 +205,58 @@ int gv_kernel_times(gv_graph* g, const char* name, uint64_t* launches,
  * written (buf may be NULL) and GV_ERANGE is returned.  Synchronous. */
 int gv_kernel_names(gv_graph* g, char* buf, size_t cap, size_t* needed);
 
+/* ---- Batched form ----------------------------------------------------
+ * Many update batches of uneven sizes applied in order (the paper's batch
+ * model, Sec. 4.3: a graph receives a sequence of vertex and edge insert /
+ * delete batches).  One op is one batch; its arrays are device pointers read
+ * when the op runs.  The result is the same as calling the single-batch
+ * entry points in order with a NULL stats pointer. */
+enum {
+    GV_OP_INSERT_EDGES = 0,    /* a = src, b = dst, n pairs */
+    GV_OP_DELETE_EDGES = 1,    /* a = src, b = dst, n pairs */
+    GV_OP_INSERT_VERTICES = 2, /* a = ids, n ids (b unused) */
+    GV_OP_DELETE_VERTICES = 3  /* a = ids, n ids (b unused) */
+};
+typedef struct {
+    uint32_t kind;
+    uint32_t reserved;
+    const uint32_t* a;
+    const uint32_t* b;
+    uint64_t n;
+} gv_op;
+
+/* A plan records every kernel of ops[0, n_ops) into one HIP graph, so that
+ * the whole sequence is launched at once (gv_plan_launch) instead of one
+ * launch per kernel per batch.  Everything a plan needs is sized when it is
+ * created (synchronous): the scratch for the largest batch and, for vertex
+ * deletes, buffers for a full pool (4 bytes per pool slot).  Vertex inserts
+ * in a plan never grow the dictionary: an id at or past the current vertex
+ * capacity makes the plan's run fail with a sticky GV_ERANGE (reserve
+ * capacity with gv_config.vertex_capacity).  A plan may be launched any
+ * number of times; each launch applies the ops again to the graph as it is,
+ * reading the op arrays at that time (refill them between launches to stream
+ * new batches of the same sizes).  gv_plan_launch is asynchronous (errors are
+ * sticky, see gv_sync) and returns GV_EINVAL when a buffer the plan records
+ * was reallocated since creation (a larger single call or a dictionary
+ * growth in between: create the plan again).  A plan belongs to its graph
+ * and must be destroyed before it. */
+typedef struct gv_plan gv_plan;
+int gv_plan_create(gv_graph* g, const gv_op* ops, uint64_t n_ops, gv_plan** out);
+int gv_plan_launch(gv_plan* p);
+void gv_plan_destroy(gv_plan* p);
+
+/* One launch sequence per batch: ops applied in order through the
+ * single-batch paths (the baseline the plan is compared with). */
+int gv_apply_ops(gv_graph* g, const gv_op* ops, uint64_t n_ops);
+
 int gv_set_stream(gv_graph* g, void* hip_stream);
 /* Wait for all queued work; returns and clears the first error of earlier
  * asynchronous calls. */
 int gv_sync(gv_graph* g);
 const char* gv_strerror(int code);
+/* The HIP call and HIP error text of the last GV_EDEVICE / GV_ENOMEM raised
+ * by a HIP call on this host thread ("" if none); owned by the library. */
+const char* gv_last_error(void);
 void gv_graph_destroy(gv_graph* g);
 
 #ifdef __cplusplus

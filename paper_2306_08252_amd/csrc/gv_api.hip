@@ -70,6 +70,8 @@ void fill_stats(gv_graph* g, gv_batch_stats* st) {
 
 extern "C" {
 
+const char* gv_last_error(void) { return last_error_text(); }
+
 const char* gv_strerror(int code) {
     switch (code) {
         case GV_OK: return "ok";

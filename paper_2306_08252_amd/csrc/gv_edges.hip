@@ -1166,6 +1166,23 @@ void set_u64(gv_graph* g, unsigned long long* p, unsigned long long value) {
 }
 
 // ------------------------------------------------------------------ driver
+// occupancy queries of the looping kernels, made before a recording
+void edge_batch_warm() {
+    resident_grid(k_probe<kInsert>, kThreads);
+    resident_grid(k_probe<kDelete>, kThreads);
+    resident_grid(k_probe<kQuery>, kThreads);
+    resident_grid(k_grow, kThreads);
+    resident_grid(k_compact, kThreads);
+}
+
+size_t edge_batch_bytes(const gv_graph* g, EdgeMode mode, uint64_t n) {
+    if (n == 0) return 0;
+    BatchArrays A;
+    Carver m(nullptr);
+    carve_batch(m, A, n, n + div_up(g->item_slots, kChunk) + 1, mode, 2 * (int)g->v.L);
+    return m.used;
+}
+
 void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t* dst, uint64_t n,
                 uint8_t* out, bool sticky) {
     if (n == 0) return;

@@ -12,6 +12,7 @@ struct gv_graph {
     gv::DevCounters* hctr = nullptr;  // pinned host copy for read-back
     gv::Scratch scratch;          // per-call temporaries
     gv::Scratch vscr[3];          // vertex-batch buffers that outlive an inner edge batch
+    uint64_t table_gen = 0;       // counts vertex-table reallocations
     uint64_t item_slots = 0;      // bound on live adjacency slots (pool slots)
     // device allocations owned by the graph
     void* mem_pool = nullptr;
@@ -33,11 +34,23 @@ enum EdgeMode { kInsert = 0, kDelete = 1, kQuery = 2 };
 void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t* dst,
                 uint64_t n, uint8_t* out, bool sticky);
 
+// occupancy queries made ahead of a recording
+void edge_batch_warm();
+void vertex_batch_warm();
+// bytes of g->scratch an edge batch of n pairs carves
+size_t edge_batch_bytes(const gv_graph* g, EdgeMode mode, uint64_t n);
+// bytes a vertex batch needs: [0] g->scratch, [1..3] g->vscr[0..2]
+void vertex_batch_bytes(const gv_graph* g, bool del, uint64_t n, uint64_t edge_bound,
+                        size_t out[4]);
+
 // bulk build into a graph whose vertex table is allocated (synchronous)
 void bulk_build(gv_graph* g, uint64_t num_vertices, const uint32_t* src, const uint32_t* dst,
                 uint64_t m, const gv_config& cfg);
 
-void vertex_insert(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats* st);
+// fixed_table: never grow the dictionary (and never read back); ids past it
+// raise a sticky GV_ERANGE
+void vertex_insert(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats* st,
+                   bool fixed_table = false);
 // edge_bound: upper bound on the edges stored (0: read it, synchronising)
 void vertex_delete(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats* st,
                    uint64_t edge_bound = 0);

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -23,9 +24,17 @@ struct Error {
 
 [[noreturn]] inline void fail(int code, const char* what) { throw Error{code, what}; }
 
+// Text of the last internal failure on this thread ("call: HIP error").
+inline char* last_error_text() {
+    static thread_local char buf[256] = "";
+    return buf;
+}
+
 inline void hip_check(hipError_t e, const char* what) {
+    if (e == hipSuccess) return;
+    std::snprintf(last_error_text(), 256, "%s: %s", what, hipGetErrorString(e));
     if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) fail(GV_ENOMEM, what);
-    if (e != hipSuccess) fail(GV_EDEVICE, what);
+    fail(GV_EDEVICE, what);
 }
 
 // Workgroups of `kernel` (launched with `block` threads) that the current
@@ -160,6 +169,7 @@ struct Carver {
 struct Scratch {
     void* ptr = nullptr;
     size_t cap = 0;
+    uint64_t gen = 0;  // counts reallocations
     void ensure(size_t bytes, hipStream_t s) {
         if (bytes <= cap) return;
         if (ptr) {
@@ -171,6 +181,7 @@ struct Scratch {
         size_t want = bytes + bytes / 4 + (1 << 20);
         hip_check(hipMalloc(&ptr, want), "hipMalloc scratch");
         cap = want;
+        ++gen;
     }
     void release() {
         if (ptr) hipFree(ptr);

@@ -88,12 +88,18 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(In in, Out out, uint64_t
 
 inline uint64_t scan_partials_needed(uint64_t n) { return div_up(n, kScanTile) + 1; }
 
+template <typename T>
+__global__ void k_zero_total(T* p) {
+    *p = T(0);
+}
+
 // Exclusive scan of in(0..n-1) into out(i, prefix); the sum goes to the device
 // location `total` when non-null.  `partial` needs scan_partials_needed(n).
 template <typename T, typename In, typename Out>
 void scan_excl(Ctx& c, In in, Out out, uint64_t n, T* partial, T* total) {
     if (n == 0) {
-        if (total) hip_check(hipMemsetAsync(total, 0, sizeof(T), c.stream), "memset");
+        // a kernel, not a memset, so that the call can be recorded in a graph
+        if (total) c.launch("scan_zero", k_zero_total<T>, 1, 1, total);
         return;
     }
     uint64_t nt = div_up(n, kScanTile);

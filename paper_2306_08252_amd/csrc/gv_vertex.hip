@@ -49,6 +49,16 @@ __global__ __launch_bounds__(kThreads) void k_vmax(const uint32_t* ids, uint64_t
     }
 }
 
+// ids that a fixed table cannot hold raise a sticky GV_ERANGE (plain stores
+// of one value)
+__global__ __launch_bounds__(kThreads) void k_vfit(GraphView g, const uint32_t* ids, uint64_t n) {
+    const uint64_t i = vt_tidx();
+    if (i < n && ids[i] <= kMaxId && (uint64_t)ids[i] >= g.n_cap) {
+        g.ctr->err_sticky = GV_ERANGE;
+        g.ctr->err_batch = GV_ERANGE;
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void k_vcopy_ids(const uint32_t* ids, uint64_t n,
                                                         uint32_t* out) {
     const uint64_t i = vt_tidx();
@@ -445,28 +455,64 @@ static void grow_table(gv_graph* g, uint64_t new_cap) {
     v.active = (uint32_t*)act2;
     v.n_cap = new_cap;
     v.L = log2_exact(new_cap);
+    ++g->table_gen;
 }
 
-void vertex_insert(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats* st) {
+void vertex_insert(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats* st,
+                   bool fixed_table) {
     Ctx& c = g->ctx;
     if (n >= 0xffffffffull) fail(GV_EINVAL, "batch too large");
     c.launch("vreset", k_vreset, 1, 1, g->v.ctr);
-    c.launch("vmax", k_vmax, div_up(n, kThreads), kThreads, ids, n, g->v.ctr);
-    read_counters(g);
-    if (g->hctr->vany && (uint64_t)g->hctr->vmax >= g->v.n_cap) {
-        uint64_t cap = g->v.n_cap;
-        while (cap <= (uint64_t)g->hctr->vmax) cap <<= 1;
-        grow_table(g, cap);
+    if (fixed_table) {
+        // no growth (and no read-back): an id past the table is an error
+        c.launch("vfit", k_vfit, div_up(n, kThreads), kThreads, g->v, ids, n);
+    } else {
+        c.launch("vmax", k_vmax, div_up(n, kThreads), kThreads, ids, n, g->v.ctr);
+        read_counters(g);
+        if (g->hctr->vany && (uint64_t)g->hctr->vmax >= g->v.n_cap) {
+            uint64_t cap = g->v.n_cap;
+            while (cap <= (uint64_t)g->hctr->vmax) cap <<= 1;
+            grow_table(g, cap);
+        }
     }
     uint32_t* k0 = (uint32_t*)vbuf(g, 0, 2 * n * sizeof(uint32_t));
     uint32_t* sorted = sorted_ids(g, ids, n, k0, k0 + n);
     c.launch("vinsert", k_vins, div_up(n, kThreads), kThreads, g->v, (const uint32_t*)sorted, n);
-    read_counters(g);
     if (st) {
+        read_counters(g);
         st->applied = g->hctr->st_applied;
         st->rejected = g->hctr->st_rejected;
         st->batch_duplicates = n - g->hctr->st_rejected - g->hctr->n_uniq;
     }
+}
+
+void vertex_batch_warm() {
+    resident_grid(k_vdel_pass<kCount>, kThreads);
+}
+
+// Buffer sizes a vertex batch of n ids needs: g->scratch (the id sort) and
+// the three graph-owned vertex buffers; edge_bound as in vertex_delete.
+void vertex_batch_bytes(const gv_graph* g, bool del, uint64_t n, uint64_t edge_bound,
+                        size_t out[4]) {
+    SortScratch ss{};
+    Carver ms(nullptr);
+    carve_sort<uint32_t>(ms, ss, n);
+    out[0] = ms.used;
+    const uint64_t ncap = g->v.n_cap;
+    const uint64_t words = (ncap + 31) / 32;
+    out[1] = (2 * n + (del ? words : 0)) * sizeof(uint32_t);
+    out[2] = out[3] = 0;
+    if (!del) return;
+    out[2] = (2 * (ncap + 1) + scan2_parts(ncap + 1) + scan_partials_needed(ncap + 1) + 2) *
+             sizeof(unsigned long long);
+    const uint64_t ubound = ncap + edge_bound / kVChunk + 1;
+    Carver m(nullptr);
+    m.take<uint2>(ubound);
+    m.take<uint32_t>(ubound);
+    m.take<unsigned long long>(ubound + 1);
+    m.take<unsigned long long>(scan2_parts(ubound + 1) + scan_partials_needed(ubound + 1) + 2);
+    m.take<uint32_t>(std::max<uint64_t>(edge_bound, 1));
+    out[3] = m.used;
 }
 
 // scan over n elements with the two-kernel scan when it fits, else the

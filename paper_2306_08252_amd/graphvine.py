@@ -67,6 +67,13 @@ class gv_counters(C.Structure):
         return out
 
 
+class gv_op(C.Structure):
+    _fields_ = [("kind", C.c_uint32), ("reserved", C.c_uint32), ("a", C.c_void_p),
+                ("b", C.c_void_p), ("n", C.c_uint64)]
+
+
+OP_INSERT_EDGES, OP_DELETE_EDGES, OP_INSERT_VERTICES, OP_DELETE_VERTICES = 0, 1, 2, 3
+
 _lib = None
 
 
@@ -101,6 +108,9 @@ def lib():
             "gv_kernel_names": [vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)],
             "gv_set_stream": [vp, vp],
             "gv_sync": [vp],
+            "gv_apply_ops": [vp, C.POINTER(gv_op), C.c_uint64],
+            "gv_plan_create": [vp, C.POINTER(gv_op), C.c_uint64, C.POINTER(C.c_void_p)],
+            "gv_plan_launch": [vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -108,15 +118,21 @@ def lib():
             f.restype = C.c_int
         L.gv_strerror.argtypes = [C.c_int]
         L.gv_strerror.restype = C.c_char_p
+        L.gv_last_error.argtypes = []
+        L.gv_last_error.restype = C.c_char_p
         L.gv_graph_destroy.argtypes = [vp]
         L.gv_graph_destroy.restype = None
+        L.gv_plan_destroy.argtypes = [vp]
+        L.gv_plan_destroy.restype = None
         _lib = L
     return _lib
 
 
 class GraphVineError(RuntimeError):
     def __init__(self, code, fn):
-        super().__init__(f"{fn}: {gv_strerror(code)} (code {code})")
+        detail = lib().gv_last_error().decode() if code in (GV_ENOMEM, GV_EDEVICE) else ""
+        super().__init__(f"{fn}: {gv_strerror(code)} (code {code})" +
+                         (f" [{detail}]" if detail else ""))
         self.code = code
 
 
@@ -370,3 +386,55 @@ class Graph:
 
     def sync(self):
         return gv_sync(self.h)
+
+
+# ------------------------------------------------------------------ batched form
+def _ops(ops, device):
+    """[(kind, a, b or None)] -> (gv_op array, device tensors kept alive)."""
+    arr = (gv_op * max(len(ops), 1))()
+    keep = []
+    for i, (kind, a, b) in enumerate(ops):
+        ta = as_device_u32(a, device)
+        keep.append(ta)
+        arr[i].kind = kind
+        arr[i].a = ta.data_ptr() if ta.numel() else None
+        arr[i].n = ta.numel()
+        if kind in (OP_INSERT_EDGES, OP_DELETE_EDGES):
+            tb = as_device_u32(b, device)
+            if tb.numel() != ta.numel():
+                raise ValueError("src/dst length mismatch")
+            keep.append(tb)
+            arr[i].b = tb.data_ptr() if tb.numel() else None
+    return arr, keep
+
+
+def gv_apply_ops(g, ops, device="cuda:0"):
+    arr, keep = _ops(ops, device)
+    _check(lib().gv_apply_ops(C.c_void_p(g), arr, len(ops)), "gv_apply_ops")
+    return keep
+
+
+class Plan:
+    """A recorded sequence of batches (gv_plan_*); holds its input tensors."""
+
+    def __init__(self, g, ops, device="cuda:0"):
+        self.h = None
+        self.arr, self.keep = _ops(ops, device)
+        h = C.c_void_p()
+        _check(lib().gv_plan_create(C.c_void_p(g), self.arr, len(ops), C.byref(h)),
+               "gv_plan_create")
+        self.h = h.value
+
+    def launch(self):
+        _check(lib().gv_plan_launch(C.c_void_p(self.h)), "gv_plan_launch")
+
+    def close(self):
+        if self.h:
+            lib().gv_plan_destroy(C.c_void_p(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
