@@ -479,6 +479,11 @@ constexpr int kOsThreads = 1024;
 constexpr int kOsWaves = kOsThreads / 64;
 static_assert(kOsThreads == 4 * kRadix, "the pass kernel works in four quarters of 256 threads");
 constexpr int kOsRounds = (int)(kOsTile / kOsThreads);  // keys per thread
+// earlier tiles whose status one look-back lane reads per round
+#ifndef GV_OS_LOOK_K
+#define GV_OS_LOOK_K 4
+#endif
+constexpr int kOsLookK = GV_OS_LOOK_K;
 
 // exclusive scan across a kOsThreads workgroup (all threads call it)
 __device__ __forceinline__ uint32_t os_block_scan(uint32_t x, uint32_t* lds, uint32_t& total) {
@@ -498,22 +503,38 @@ __device__ __forceinline__ uint32_t os_block_scan(uint32_t x, uint32_t* lds, uin
     return off + inc - x;
 }
 
+// Histogram counting: 0 = the lowest lane of each group of equal digits adds
+// the group's size (eight ballots per digit, no conflicting LDS atomics);
+// 1 = every lane adds one to a histogram shared by a quarter of the
+// workgroup (LDS atomics, conflicts only between equal digits).
+#ifndef GV_OS_HIST_MODE
+#define GV_OS_HIST_MODE 1
+#endif
+#ifndef GV_OS_HIST_COPIES
+#define GV_OS_HIST_COPIES 4
+#endif
+constexpr int kOsHistMode = GV_OS_HIST_MODE;
+constexpr int kOsHistCopies = kOsHistMode == 1 ? GV_OS_HIST_COPIES : 1;
+
 template <typename K>
 __global__ __launch_bounds__(kOsThreads) void k_os_hist(const K* keys, const uint32_t* n_dev,
                                                         uint64_t n_max, int passes,
                                                         uint32_t* hpart) {
-    __shared__ uint32_t h[8][kRadix];
-    const uint64_t n = n_dev ? *n_dev : n_max;
-    for (int i = threadIdx.x; i < 8 * kRadix; i += kOsThreads) h[i / kRadix][i % kRadix] = 0;
+    __shared__ uint32_t h[kOsHistCopies][8][kRadix];
+    const uint64_t n = n_dev ? min<uint64_t>(*n_dev, n_max) : n_max;
+    for (int i = threadIdx.x; i < kOsHistCopies * 8 * kRadix; i += kOsThreads)
+        (&h[0][0][0])[i] = 0;
     __syncthreads();
-    const uint64_t ntiles = (n + kOsTile - 1) / kOsTile;
+    const uint32_t copy = kOsHistCopies == 1 ? 0u : (threadIdx.x >> 6) & (kOsHistCopies - 1);
+    // tiles of n_max: loads need not wait for n, counting masks with it
+    const uint64_t ntiles = (n_max + kOsTile - 1) / kOsTile;
     for (uint64_t tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
         const uint64_t base = tl * kOsTile;
         K kk[kOsRounds];
 #pragma unroll
         for (int j = 0; j < kOsRounds; ++j) {
             const uint64_t i = base + (uint64_t)j * kOsThreads + threadIdx.x;
-            kk[j] = i < n ? keys[i] : K(0);
+            kk[j] = i < n_max ? keys[i] : K(0);
         }
 #pragma unroll
         for (int j = 0; j < kOsRounds; ++j) {
@@ -521,14 +542,23 @@ __global__ __launch_bounds__(kOsThreads) void k_os_hist(const K* keys, const uin
             const bool act = i < n;
             for (int p = 0; p < passes; ++p) {
                 const uint32_t d = (uint32_t)(kk[j] >> (p * kRadixBits)) & (kRadix - 1);
-                const uint64_t peers = digit_peers(d, act);
-                if (act && rank_below(peers) == 0) atomicAdd(&h[p][d], popc64(peers));
+                if (kOsHistMode == 1) {
+                    if (act) atomicAdd(&h[copy][p][d], 1u);
+                } else {
+                    const uint64_t peers = digit_peers(d, act);
+                    if (act && rank_below(peers) == 0) atomicAdd(&h[0][p][d], popc64(peers));
+                }
             }
         }
     }
     __syncthreads();
     uint32_t* out = hpart + (uint64_t)blockIdx.x * passes * kRadix;
-    for (int i = threadIdx.x; i < passes * kRadix; i += kOsThreads) out[i] = h[i / kRadix][i % kRadix];
+    for (int i = threadIdx.x; i < passes * kRadix; i += kOsThreads) {
+        uint32_t x = 0;
+#pragma unroll
+        for (int c = 0; c < kOsHistCopies; ++c) x += h[c][i / kRadix][i % kRadix];
+        out[i] = x;
+    }
 }
 
 // hist[i] = sum over the histogram workgroups of their count i: a
@@ -580,23 +610,33 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const K* kin, K* kout, c
     const uint32_t t = threadIdx.x;
     const int w = t >> 6;
     if (t == 0) s_tile = atomicAdd(counter, 1u);
+    // the key count is read while the ticket is in flight
+    const uint64_t n = n_dev ? min<uint64_t>(*n_dev, n_max) : n_max;
     {
         uint32_t* c32 = (uint32_t*)&cnt[0][0];
         for (int i = t; i < kOsRounds * kOsWaves * kRadix / 2; i += kOsThreads) c32[i] = 0;
     }
     __syncthreads();
     const uint64_t tile = s_tile;
-    const uint64_t n = n_dev ? *n_dev : n_max;
     const uint64_t base = tile * kOsTile;
     K key[kOsRounds];
     uint32_t val[kOsRounds];
     uint16_t rk[kOsRounds];
+    // loads bounded by n_max (the buffer size), so they need not wait for n
 #pragma unroll
     for (int j = 0; j < kOsRounds; ++j) {
         const uint64_t i = base + (uint64_t)j * kOsThreads + t;
-        const bool act = i < n;
-        key[j] = act ? kin[i] : K(0);
-        if (HasVal) val[j] = act ? vin[i] : 0u;
+        const bool in = i < n_max;
+        key[j] = in ? kin[i] : K(0);
+        if (HasVal) val[j] = in ? vin[i] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kOsRounds; ++j) {
+        const uint64_t i = base + (uint64_t)j * kOsThreads + t;
+        if (i >= n) {
+            key[j] = K(0);
+            if (HasVal) val[j] = 0u;
+        }
     }
 #pragma unroll
     for (int j = 0; j < kOsRounds; ++j) {
@@ -629,8 +669,9 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const K* kin, K* kout, c
         for (int r = 0; r < kQRows; ++r) cnt[q * kQRows + r][d] += (uint16_t)qoff;
     }
     // publish this tile's counts, then look back with four consecutive lanes
-    // per digit: each round reads the status of four earlier tiles at once
-    // and adds them, in order, up to the first inclusive one
+    // per digit: each round a lane reads the status of kOsLookK earlier
+    // tiles with independent loads, and the four lanes add them, newest
+    // first, up to the first inclusive one
     __shared__ uint32_t lb_prefix[kRadix];
     if (t < kRadix) st_release32(status + tile * kRadix + t, (tile == 0 ? kOsIncl : kOsAgg) | dcount);
     {
@@ -639,29 +680,48 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const K* kin, K* kout, c
         bool open = tile > 0;
         int64_t j0 = (int64_t)tile - 1;
         while (open) {
-            const int64_t j = j0 - (int64_t)lq;
-            uint32_t wv = kOsIncl;  // before tile 0: an inclusive zero
-            if (j >= 0) {
-                uint32_t spins = 0;
-                do {
-                    wv = ld_acquire32(status + (uint64_t)j * kRadix + ld);
-                } while ((wv >> 30) == 0 && ++spins < kSpinLimit);
-                if ((wv >> 30) == 0) {
-                    *err = 1;
-                    wv = kOsIncl;
+            uint32_t wv[kOsLookK];
+#pragma unroll
+            for (int kk = 0; kk < kOsLookK; ++kk) {
+                const int64_t j = j0 - (int64_t)(lq * kOsLookK + kk);
+                // before tile 0: an inclusive zero
+                wv[kk] = j >= 0 ? ld_acquire32(status + (uint64_t)j * kRadix + ld) : kOsIncl;
+            }
+#pragma unroll
+            for (int kk = 0; kk < kOsLookK; ++kk) {
+                const int64_t j = j0 - (int64_t)(lq * kOsLookK + kk);
+                if ((wv[kk] >> 30) == 0) {
+                    uint32_t spins = 0;
+                    do {
+                        wv[kk] = ld_acquire32(status + (uint64_t)j * kRadix + ld);
+                    } while ((wv[kk] >> 30) == 0 && ++spins < kSpinLimit);
+                    if ((wv[kk] >> 30) == 0) {
+                        *err = 1;
+                        wv[kk] = kOsIncl;
+                    }
+                }
+            }
+            uint32_t ls = 0;
+            bool lh = false;
+#pragma unroll
+            for (int kk = 0; kk < kOsLookK; ++kk) {
+                if (!lh) {
+                    ls += wv[kk] & kOsMask;
+                    lh = (wv[kk] >> 30) == 2;
                 }
             }
             bool hit = false;
 #pragma unroll
             for (int qq = 0; qq < 4; ++qq) {
-                const uint32_t v = __shfl(wv, (int)(gbase + qq), 64);
+                const uint32_t vs = __shfl(ls, (int)(gbase + qq), 64);
+                const int vh = __shfl((int)lh, (int)(gbase + qq), 64);
                 if (!hit) {
-                    lp += v & kOsMask;
-                    hit = (v >> 30) == 2;
+                    lp += vs;
+                    hit = vh != 0;
                 }
             }
             open = !hit;
-            j0 -= 4;
+            j0 -= 4 * kOsLookK;
         }
         if (lq == 0) lb_prefix[ld] = lp;
     }
@@ -698,8 +758,12 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const K* kin, K* kout, c
             const K k = skey[lp];
             const uint32_t dd = (uint32_t)(k >> shift) & (kRadix - 1);
             const uint32_t pos = s_base[dd] + (lp - s_lstart[dd]);
-            kout[pos] = k;
-            if (HasVal) vout[pos] = sval[lp];
+            // stays below n unless a look-back wait ran out (err is set);
+            // then the write is dropped rather than sent out of bounds
+            if (pos < n) {
+                kout[pos] = k;
+                if (HasVal) vout[pos] = sval[lp];
+            }
         }
     }
 }

@@ -124,13 +124,21 @@ def test_plan_errors():
     assert e.value.code == gv.GV_ERANGE
     assert g.sync() == 0  # reported once
     plan.close()
-    # a plan with a vertex delete stays valid as the graph grows
-    plan = gv.Plan(g.h, [(3, np.array([1, 2], np.uint32), None)])
+    # a plan with a vertex delete stays valid as the graph gains edges (its
+    # buffers are sized for a full pool); the first batch of this size sizes
+    # the scratch, so the second one reallocates nothing
     s, d = I.uniform_pairs(I.stream_seed("batched-err-more"), 300, n)
     g.insert_edges(s, d)
+    o = O.OracleGraph(n, s0, d0, block_slots=8, vertex_capacity=n)
+    o.insert_edges(s, d)
+    plan = gv.Plan(g.h, [(3, np.array([1, 2], np.uint32), None)])
+    s2, d2 = I.uniform_pairs(I.stream_seed("batched-err-more2"), 300, n)
+    g.insert_edges(s2, d2)
+    o.insert_edges(s2, d2)
     plan.launch()
     assert g.sync() == 0
-    assert g.audit() == 0
+    o.delete_vertices([1, 2])
+    assert_same(g, o, "plan with a vertex delete after growth")
     plan.close()
     # buffers moved (a larger single batch grew the scratch): recreate
     plan = gv.Plan(g.h, [(0, s[:10], d[:10])])
