@@ -2,28 +2,30 @@
 //
 // One pipeline serves the three operations (GraphVine Sec. 4.5-4.6, Alg. 1-3,
 // re-designed for wave64):
-//   begin     clear the batch's look-back state.
-//   pack      single-pass scan: validate each pair against the activity
+//   begin     clear the batch's look-back state and counters.
+//   pack      two-kernel scan: validate each pair against the activity
 //             bitmap and write the valid ones, compacted, as keys
 //             (src << L) | dst (queries also carry their input position and
 //             answer invalid pairs with 0 right away).
 //   sort      onesweep LSD radix sort of the valid keys on 2L bits: the batch
 //             is grouped by source and ordered by destination inside each
 //             source segment (the paper's host CSR conversion, Sec. 4.3).
-//   segments  single-pass scan over the sorted keys: segment heads give the
-//             touched sources T and their segment starts; first occurrences
-//             give the distinct pairs.
-//   items     single-pass scan over T: each touched adjacency is cut into
-//             work items of kChunk slots, written as self-contained 32-byte
-//             descriptors (slot range, batch segment, block directory).
-//   probe     16-lane groups, four per wave, each own one work item: the
-//             segment's destinations are staged in LDS, lanes stream slots
-//             (directory entry, then slot) and binary-search each slot value.
+//   segments  scan over the sorted keys: segment heads give the touched
+//             sources T and their segment starts; first occurrences give the
+//             distinct pairs.
+//   items     scan over T: each touched adjacency is cut into work items of
+//             kChunk slots, written as self-contained 32-byte descriptors
+//             (slot range, batch segment, block directory); a source with a
+//             single small block and a short segment becomes one small item.
+//   probe     small items one per lane (slots and segment loaded whole, all
+//             pairs compared); the others by lane groups that stage the
+//             segment's destinations in LDS, stream slots (directory entry,
+//             then slot) and binary-search each slot value.
 //             Insert: mark batch entries that already exist (set semantics).
 //             Delete: mark hits, remember their slot, tombstone the slot.
 //             Query:  mark every query equal to a stored edge.
 //   insert:   keep = first occurrence and not present (scan); per-source
-//             block demand and directory growth; a one-thread plan checks
+//             block demand and directory growth; a one-wave plan checks
 //             capacity before any state is written (all-or-nothing); blocks
 //             come from the free-list top first, then the bump pointer (the
 //             prefix-sum pop of Sec. 4.5.1, without atomics); append.
@@ -100,6 +102,7 @@ struct BatchArrays {
     uint32_t* big;      // delete: sources with more than kBigR hits
     uint32_t* heavy;    // sources left to whole waves
     Item* items;        // work items
+    Item* small;        // per touched source: its small item or an empty entry
     unsigned long long* part;  // scan partials
     uint32_t* state;    // zeroed look-back state of the sort
     uint64_t state_words;
@@ -136,6 +139,7 @@ static void carve_batch(Carver& cv, BatchArrays& A, uint64_t n, uint64_t icap, E
         A.rel = cv.take<uint32_t>(n);
     }
     A.items = cv.take<Item>(icap);
+    A.small = cv.take<Item>(n);
     A.part = cv.take<unsigned long long>(scan2_parts(n + 1));
     A.state_words = os_zero_words(n, bits);  // the part the batch zeroes
     A.state = cv.take<uint32_t>(os_words(n, bits));
@@ -261,6 +265,17 @@ __device__ __forceinline__ TouchRec load_touched(const uint32_t* t_vtx, const ui
     return x;
 }
 
+// Small items: a source whose adjacency is a single block of at most
+// kSmallDeg slots and whose batch segment has at most kSmallSeg pairs is
+// probed by one lane (64 such sources per wave) instead of a lane group.
+// Their descriptors go to a second array indexed by touched source, where
+// the other sources get an empty entry (s1 = 0).
+constexpr uint32_t kSmallDeg = 16;
+constexpr uint32_t kSmallSeg = 8;
+__device__ __forceinline__ bool small_item(uint32_t B, uint32_t deg, uint32_t len) {
+    return B >= 4 && deg > 0 && deg <= min(B, kSmallDeg) && len <= kSmallSeg;
+}
+
 struct ItemIn {
     GraphView g;
     const uint32_t* t_vtx;
@@ -272,7 +287,8 @@ struct ItemIn {
     __device__ Rec load(uint64_t t, bool ok) const { return load_touched(t_vtx, t_start, t, ok); }
     __device__ void deref(Rec& x) const { x.r = g.vt[x.v]; }
     __device__ unsigned long long value(uint64_t, const Rec& x) const {
-        const unsigned long long items = (x.r.deg + kChunk - 1) / kChunk;
+        const unsigned long long items =
+            small_item(g.B, x.r.deg, x.hi - x.lo) ? 0ull : (x.r.deg + kChunk - 1) / kChunk;
         return items | ((unsigned long long)nblocks(g, x.r.deg) << 32);
     }
 };
@@ -284,11 +300,14 @@ constexpr uint32_t kLaneItems = 4;
 
 struct ItemOut {
     Item* items;
+    Item* small;        // per touched source: its small item, or s1 = 0
+    uint32_t B;
     __device__ void operator()(uint64_t t, const TouchRec& x, uint64_t lim,
                                unsigned long long pre) const {
         const bool live = t < lim;
         const VRec r = x.r;
-        const uint32_t cnt = live ? (r.deg + kChunk - 1) / kChunk : 0u;
+        const bool small = live && small_item(B, r.deg, x.hi - x.lo);
+        const uint32_t cnt = live && !small ? (r.deg + kChunk - 1) / kChunk : 0u;
         const uint32_t base = (uint32_t)pre;
         Item it;
         it.lo = x.lo;
@@ -297,6 +316,14 @@ struct ItemOut {
         it.dirbase = r.dcls != kNoDir ? r.dir : 0u;
         it.blk0 = r.dcls != kNoDir ? 0u : r.dir;
         it.dcls = r.dcls;
+        if (small) {
+            Item w = it;
+            w.s0 = 0;
+            w.s1 = r.deg;
+            this->small[t] = w;
+        } else if (live) {
+            *(uint4*)&this->small[t] = make_uint4(0u, 0u, 0u, 0u);
+        }
         if (cnt <= kLaneItems) {
             for (uint32_t c = 0; c < cnt; ++c) {
                 it.s0 = c * kChunk;
@@ -445,11 +472,66 @@ __device__ __forceinline__ void probe_search(const GraphView& g, const Item& I, 
     }
 }
 
+// One lane probes one small item: its single block's slots and its batch
+// segment's destinations are loaded whole, and every segment entry is
+// compared with every slot.  Same marks as the group search: insert and
+// delete mark the first occurrence of a stored pair (delete also records the
+// slot and tombstones it), query marks every occurrence.
+template <int MODE>
+__device__ __forceinline__ void probe_small(const GraphView& g, const Item& I, const uint64_t* keys,
+                                            uint8_t* mark, uint32_t* hitpos) {
+    const uint32_t deg = I.s1;
+    const uint32_t len = I.hi - I.lo;
+    const uint32_t* klo = (const uint32_t*)keys;  // low words: destinations
+    const uint32_t dmask = (uint32_t)((1ull << g.L) - 1);
+    uint32_t d[kSmallSeg];
+#pragma unroll
+    for (uint32_t j = 0; j < kSmallSeg; ++j)
+        d[j] = j < len ? klo[2ull * (I.lo + j)] & dmask : 0u;
+    const uint32_t blk = I.dcls != kNoDir ? g.dir[I.dirbase] : I.blk0;
+    const uint64_t b0 = (uint64_t)blk << g.log2B;
+    // whole 16-byte groups of the block (B >= 4, so they stay inside it)
+    uint32_t x[kSmallDeg];
+#pragma unroll
+    for (uint32_t u = 0; u < kSmallDeg; u += 4) {
+        uint4 q = make_uint4(kTomb, kTomb, kTomb, kTomb);
+        if (u < deg) q = *(const uint4*)(g.pool + b0 + u);
+        x[u] = q.x;
+        x[u + 1] = q.y;
+        x[u + 2] = q.z;
+        x[u + 3] = q.w;
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < kSmallSeg; ++j) {
+        if (j >= len) break;
+        if (MODE != kQuery && j > 0 && d[j] == d[j - 1]) continue;  // not a first occurrence
+        uint32_t hu = kSmallDeg;
+#pragma unroll
+        for (uint32_t u = 0; u < kSmallDeg; ++u)
+            if (u < deg && x[u] == d[j]) hu = u;
+        if (hu == kSmallDeg) continue;
+        mark[I.lo + j] = 1;
+        if (MODE == kDelete) {
+            hitpos[I.lo + j] = hu;
+            g.pool[b0 + hu] = kTomb;
+        }
+    }
+}
+
 template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_probe(GraphView g, const uint64_t* keys,
-                                                    const Item* items, uint8_t* mark,
-                                                    uint32_t* hitpos) {
+                                                    const Item* items, const Item* small,
+                                                    uint8_t* mark, uint32_t* hitpos) {
     __shared__ uint32_t stage[kWaves * kGroupsPerWave][kStage];
+    {
+        // small items first, one touched source per lane
+        const uint32_t nT = (uint32_t)g.ctr->tot[kTotSeg];
+        const uint32_t stride = gridDim.x * kThreads;
+        for (uint32_t t = blockIdx.x * kThreads + threadIdx.x; t < nT; t += stride) {
+            const Item I = small[t];
+            if (I.s1) probe_small<MODE>(g, I, keys, mark, hitpos);
+        }
+    }
     const uint32_t nitems = (uint32_t)g.ctr->tot[kTotItems];
     const uint32_t lane = lane_id();
     const uint32_t gl = lane & (kGroup - 1);
@@ -1224,14 +1306,14 @@ void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t*
     scan2(c, "segments", SegIn{keys, n_valid, v.L},
           SegOut{v.L, A.flags, A.a, A.t_vtx, A.t_start}, n, A.part,
           &tot[kTotSeg]);
-    scan2(c, "items", ItemIn{v, A.t_vtx, A.t_start}, ItemOut{A.items}, n, A.part,
+    scan2(c, "items", ItemIn{v, A.t_vtx, A.t_start}, ItemOut{A.items, A.small, v.B}, n, A.part,
           &tot[kTotItems]);
     const uint64_t pwant = div_up(icap, kWaves * kGroupsPerWave);
     auto pgrid_of = [&](auto kernel) { return std::min<uint64_t>(pwant, resident_grid(kernel, kThreads)); };
     const uint64_t tgrid = std::min<uint64_t>(div_up(n, kThreads), resident_grid(k_grow, kThreads));
 
     if (mode == kInsert) {
-        c.launch("probe_insert", k_probe<kInsert>, pgrid_of(k_probe<kInsert>), kThreads, v, keys, (const Item*)A.items,
+        c.launch("probe_insert", k_probe<kInsert>, pgrid_of(k_probe<kInsert>), kThreads, v, keys, (const Item*)A.items, (const Item*)A.small,
                  A.mark, (uint32_t*)nullptr);
         scan2(c, "keep", KeepIn{A.flags, A.mark, n_valid}, U32Out{A.b}, n + 1, A.part,
               &tot[kTotA]);
@@ -1252,7 +1334,7 @@ void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t*
         c.launch("final_insert", k_final_ins, std::min<uint64_t>(grid, 64), kThreads, v,
                  (const uint32_t*)A.rel, (const uint32_t*)A.t_dold, (const uint32_t*)A.t_doldc);
     } else if (mode == kDelete) {
-        c.launch("probe_delete", k_probe<kDelete>, pgrid_of(k_probe<kDelete>), kThreads, v, keys, (const Item*)A.items,
+        c.launch("probe_delete", k_probe<kDelete>, pgrid_of(k_probe<kDelete>), kThreads, v, keys, (const Item*)A.items, (const Item*)A.small,
                  A.mark, A.hitpos);
         scan2(c, "found", FoundIn{A.mark, n_valid}, U32Out{A.b}, n + 1, A.part, &tot[kTotA]);
         scan2(c, "freed", FreedIn{v, A.t_vtx, A.t_start, A.b},
@@ -1266,7 +1348,7 @@ void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t*
                  (const uint32_t*)A.heavy);
         c.launch("final_delete", k_final_del, 1, 1, v, n);
     } else {
-        c.launch("probe_query", k_probe<kQuery>, pgrid_of(k_probe<kQuery>), kThreads, v, keys, (const Item*)A.items,
+        c.launch("probe_query", k_probe<kQuery>, pgrid_of(k_probe<kQuery>), kThreads, v, keys, (const Item*)A.items, (const Item*)A.small,
                  A.mark, (uint32_t*)nullptr);
         c.launch("answer", k_answer, grid, kThreads, v, vals, (const uint8_t*)A.mark, n, out);
     }
