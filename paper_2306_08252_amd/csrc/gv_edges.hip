@@ -265,15 +265,16 @@ __device__ __forceinline__ TouchRec load_touched(const uint32_t* t_vtx, const ui
     return x;
 }
 
-// Small items: a source whose adjacency is a single block of at most
-// kSmallDeg slots and whose batch segment has at most kSmallSeg pairs is
-// probed by one lane (64 such sources per wave) instead of a lane group.
-// Their descriptors go to a second array indexed by touched source, where
-// the other sources get an empty entry (s1 = 0).
-constexpr uint32_t kSmallDeg = 16;
+// Small items: a source with at most kSmallLanes * kSmallDeg slots and at
+// most kSmallSeg pairs in its batch segment is probed by kSmallLanes lanes,
+// kSmallDeg slots each, instead of a lane group.  Their descriptors go to a
+// second array indexed by touched source, where the other sources get an
+// empty entry (s1 = 0).
+constexpr uint32_t kSmallDeg = 16;    // slots per lane (whole 16-byte groups of a block)
+constexpr uint32_t kSmallLanes = 4;   // lanes per small item
 constexpr uint32_t kSmallSeg = 8;
 __device__ __forceinline__ bool small_item(uint32_t B, uint32_t deg, uint32_t len) {
-    return B >= 4 && deg > 0 && deg <= min(B, kSmallDeg) && len <= kSmallSeg;
+    return B >= 4 && deg > 0 && deg <= kSmallLanes * kSmallDeg && len <= kSmallSeg;
 }
 
 struct ItemIn {
@@ -472,34 +473,43 @@ __device__ __forceinline__ void probe_search(const GraphView& g, const Item& I, 
     }
 }
 
-// One lane probes one small item: its single block's slots and its batch
-// segment's destinations are loaded whole, and every segment entry is
-// compared with every slot.  Same marks as the group search: insert and
-// delete mark the first occurrence of a stored pair (delete also records the
-// slot and tombstones it), query marks every occurrence.
+// Lane q of a small item's lanes probes slots [q * kSmallDeg, (q + 1) *
+// kSmallDeg) of its adjacency: those slots and the segment's destinations are
+// loaded whole and compared pairwise.  Same marks as the group search: insert
+// and delete mark the first occurrence of a stored pair (delete also records
+// the slot and tombstones it), query marks every occurrence.  A stored pair
+// sits in one slot, so one lane at most marks a segment entry.
 template <int MODE>
-__device__ __forceinline__ void probe_small(const GraphView& g, const Item& I, const uint64_t* keys,
-                                            uint8_t* mark, uint32_t* hitpos) {
+__device__ __forceinline__ void probe_small(const GraphView& g, const Item& I, uint32_t q,
+                                            const uint64_t* keys, uint8_t* mark,
+                                            uint32_t* hitpos) {
     const uint32_t deg = I.s1;
     const uint32_t len = I.hi - I.lo;
+    const uint32_t first = q * kSmallDeg;
     const uint32_t* klo = (const uint32_t*)keys;  // low words: destinations
     const uint32_t dmask = (uint32_t)((1ull << g.L) - 1);
     uint32_t d[kSmallSeg];
 #pragma unroll
     for (uint32_t j = 0; j < kSmallSeg; ++j)
         d[j] = j < len ? klo[2ull * (I.lo + j)] & dmask : 0u;
-    const uint32_t blk = I.dcls != kNoDir ? g.dir[I.dirbase] : I.blk0;
-    const uint64_t b0 = (uint64_t)blk << g.log2B;
-    // whole 16-byte groups of the block (B >= 4, so they stay inside it)
+    // whole 16-byte groups of a block (B >= 4, so a group stays inside it)
     uint32_t x[kSmallDeg];
+    uint64_t a[kSmallDeg / 4];
 #pragma unroll
     for (uint32_t u = 0; u < kSmallDeg; u += 4) {
-        uint4 q = make_uint4(kTomb, kTomb, kTomb, kTomb);
-        if (u < deg) q = *(const uint4*)(g.pool + b0 + u);
-        x[u] = q.x;
-        x[u + 1] = q.y;
-        x[u + 2] = q.z;
-        x[u + 3] = q.w;
+        const uint32_t sl = first + u;
+        const uint32_t j = sl >> g.log2B;
+        const uint32_t blk = I.dcls != kNoDir ? g.dir[I.dirbase + (sl < deg ? j : 0u)] : I.blk0;
+        a[u / 4] = ((uint64_t)blk << g.log2B) + (sl & (g.B - 1));
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kSmallDeg; u += 4) {
+        uint4 v = make_uint4(kTomb, kTomb, kTomb, kTomb);
+        if (first + u < deg) v = *(const uint4*)(g.pool + a[u / 4]);
+        x[u] = v.x;
+        x[u + 1] = v.y;
+        x[u + 2] = v.z;
+        x[u + 3] = v.w;
     }
 #pragma unroll
     for (uint32_t j = 0; j < kSmallSeg; ++j) {
@@ -508,12 +518,12 @@ __device__ __forceinline__ void probe_small(const GraphView& g, const Item& I, c
         uint32_t hu = kSmallDeg;
 #pragma unroll
         for (uint32_t u = 0; u < kSmallDeg; ++u)
-            if (u < deg && x[u] == d[j]) hu = u;
+            if (first + u < deg && x[u] == d[j]) hu = u;
         if (hu == kSmallDeg) continue;
         mark[I.lo + j] = 1;
         if (MODE == kDelete) {
-            hitpos[I.lo + j] = hu;
-            g.pool[b0 + hu] = kTomb;
+            hitpos[I.lo + j] = first + hu;
+            g.pool[a[hu / 4] + (hu & 3)] = kTomb;
         }
     }
 }
@@ -524,12 +534,13 @@ __global__ __launch_bounds__(kThreads) void k_probe(GraphView g, const uint64_t*
                                                     uint8_t* mark, uint32_t* hitpos) {
     __shared__ uint32_t stage[kWaves * kGroupsPerWave][kStage];
     {
-        // small items first, one touched source per lane
-        const uint32_t nT = (uint32_t)g.ctr->tot[kTotSeg];
-        const uint32_t stride = gridDim.x * kThreads;
-        for (uint32_t t = blockIdx.x * kThreads + threadIdx.x; t < nT; t += stride) {
-            const Item I = small[t];
-            if (I.s1) probe_small<MODE>(g, I, keys, mark, hitpos);
+        // small items first, kSmallLanes consecutive lanes per touched source
+        const uint64_t nq = (uint64_t)(uint32_t)g.ctr->tot[kTotSeg] * kSmallLanes;
+        const uint64_t stride = (uint64_t)gridDim.x * kThreads;
+        for (uint64_t k = (uint64_t)blockIdx.x * kThreads + threadIdx.x; k < nq; k += stride) {
+            const Item I = small[k / kSmallLanes];
+            const uint32_t q = (uint32_t)(k % kSmallLanes);
+            if (I.s1 > q * kSmallDeg) probe_small<MODE>(g, I, q, keys, mark, hitpos);
         }
     }
     const uint32_t nitems = (uint32_t)g.ctr->tot[kTotItems];
