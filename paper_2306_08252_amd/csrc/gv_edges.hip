@@ -106,6 +106,7 @@ struct BatchArrays {
     unsigned long long* part;  // scan partials
     uint32_t* state;    // zeroed look-back state of the sort
     uint64_t state_words;
+    uint32_t* vpart;    // insert / delete: valid pairs per packing workgroup
 };
 
 static void carve_batch(Carver& cv, BatchArrays& A, uint64_t n, uint64_t icap, EdgeMode mode,
@@ -143,6 +144,7 @@ static void carve_batch(Carver& cv, BatchArrays& A, uint64_t n, uint64_t icap, E
     A.part = cv.take<unsigned long long>(scan2_parts(n + 1));
     A.state_words = os_zero_words(n, bits);  // the part the batch zeroes
     A.state = cv.take<uint32_t>(os_words(n, bits));
+    A.vpart = cv.take<uint32_t>(kHistGroups);
 }
 
 __device__ __forceinline__ uint64_t thread_index() {
@@ -200,6 +202,78 @@ struct PackOut {
         }
     }
 };
+
+// Insert and delete batches: pack without compaction.  Every pair keeps its
+// input position; a pair with an inactive or out-of-range endpoint gets the
+// all-ones key of the sort's bit width, which sorts after every valid key.
+// All such keys are equal, so whether or not a valid pair shares that key,
+// the first n_valid sorted keys are exactly the valid ones.  The same kernel
+// clears the batch's look-back state and counters and counts the sort's
+// digits (per workgroup, summed by the next kernel together with the valid
+// pairs).
+__global__ __launch_bounds__(kOsThreads) void k_pack_hist(GraphView g, const uint32_t* src,
+                                                          const uint32_t* dst, uint64_t n,
+                                                          int passes, uint64_t sentinel,
+                                                          uint64_t* keys, uint8_t* mark,
+                                                          uint32_t* state, uint64_t zero_words,
+                                                          uint32_t* hpart, uint32_t* vpart) {
+    __shared__ uint32_t h[kOsHistCopies][8][kRadix];
+    __shared__ uint32_t s_v[kOsWaves];
+    const uint32_t t = threadIdx.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * kOsThreads + t; i < zero_words;
+         i += (uint64_t)gridDim.x * kOsThreads)
+        state[i] = 0;
+    if (blockIdx.x == 0 && t == 0) {
+        g.ctr->err_batch = 0;
+        g.ctr->n_big = 0;
+        g.ctr->n_heavy = 0;
+        for (int k = 0; k < 8; ++k) g.ctr->tot[k] = 0;
+    }
+    for (int i = t; i < kOsHistCopies * 8 * kRadix; i += kOsThreads) (&h[0][0][0])[i] = 0;
+    __syncthreads();
+    const uint32_t copy = kOsHistCopies == 1 ? 0u : (t >> 6) & (kOsHistCopies - 1);
+    uint32_t valid = 0;
+    const uint64_t ntiles = (n + kOsTile - 1) / kOsTile;
+    for (uint64_t tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+        const uint64_t base = tl * kOsTile;
+        uint32_t su[kOsRounds], du[kOsRounds];
+        bool ok[kOsRounds];
+#pragma unroll
+        for (int j = 0; j < kOsRounds; ++j) {
+            const uint64_t i = base + (uint64_t)j * kOsThreads + t;
+            su[j] = i < n ? src[i] : 0u;
+            du[j] = i < n ? dst[i] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < kOsRounds; ++j) ok[j] = active_bit(g, su[j]) & active_bit(g, du[j]);
+#pragma unroll
+        for (int j = 0; j < kOsRounds; ++j) {
+            const uint64_t i = base + (uint64_t)j * kOsThreads + t;
+            if (i >= n) continue;
+            const uint64_t key = ok[j] ? ((uint64_t)su[j] << g.L) | du[j] : sentinel;
+            keys[i] = key;
+            mark[i] = 0;
+            valid += ok[j] ? 1u : 0u;
+            for (int p = 0; p < passes; ++p)
+                atomicAdd(&h[copy][p][(uint32_t)(key >> (p * kRadixBits)) & (kRadix - 1)], 1u);
+        }
+    }
+    const uint32_t vw = (uint32_t)wave_sum((unsigned long long)valid);
+    if (lane_id() == 0) s_v[t >> 6] = vw;
+    __syncthreads();
+    uint32_t* out = hpart + (uint64_t)blockIdx.x * passes * kRadix;
+    for (int i = t; i < passes * kRadix; i += kOsThreads) {
+        uint32_t x = 0;
+#pragma unroll
+        for (int c = 0; c < kOsHistCopies; ++c) x += h[c][i / kRadix][i % kRadix];
+        out[i] = x;
+    }
+    if (t == 0) {
+        uint32_t x = 0;
+        for (int w = 0; w < kOsWaves; ++w) x += s_v[w];
+        vpart[blockIdx.x] = x;
+    }
+}
 
 // ------------------------------------------------------------------ segments
 struct SegIn {
@@ -1298,19 +1372,23 @@ void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t*
     const unsigned long long* n_valid = &tot[kTotValid];
     const uint64_t grid = div_up(n, kThreads);
 
-    c.launch("begin", k_begin, std::min<uint64_t>(div_up(A.state_words, kThreads), 1024),
-             kThreads, v, A.state, A.state_words);
-    scan2(c, "pack", PackIn{v, src, dst},
-          PackOut{v.L, A.keys0, mode == kQuery ? A.vals0 : nullptr, mode == kQuery ? out : nullptr,
-                  A.mark},
-          n, A.part, &tot[kTotValid]);
     bool flip;
-    if (mode == kQuery)
+    if (mode == kQuery) {
+        c.launch("begin", k_begin, std::min<uint64_t>(div_up(A.state_words, kThreads), 1024),
+                 kThreads, v, A.state, A.state_words);
+        scan2(c, "pack", PackIn{v, src, dst}, PackOut{v.L, A.keys0, A.vals0, out, A.mark}, n,
+              A.part, &tot[kTotValid]);
         flip = onesweep<uint64_t, true>(c, A.keys0, A.keys1, A.vals0, A.vals1,
                                         (const uint32_t*)n_valid, n, bits, A.state, err);
-    else
-        flip = onesweep<uint64_t, false>(c, A.keys0, A.keys1, nullptr, nullptr,
-                                         (const uint32_t*)n_valid, n, bits, A.state, err);
+    } else {
+        const uint64_t sentinel = bits >= 64 ? ~0ull : (1ull << bits) - 1;
+        c.launch("pack", k_pack_hist, os_hist_groups(n), kOsThreads, v, src, dst, n,
+                 bits > 0 ? os_passes(bits) : 0, sentinel, A.keys0, A.mark, A.state,
+                 A.state_words, os_hpart(A.state, n, bits), A.vpart);
+        os_hist_sum(c, A.state, n, bits, (const uint32_t*)A.vpart, &tot[kTotValid]);
+        flip = onesweep_passes<uint64_t, false>(c, A.keys0, A.keys1, nullptr, nullptr, nullptr, n,
+                                                bits, A.state, err);
+    }
     const uint64_t* keys = flip ? A.keys1 : A.keys0;
     const uint32_t* vals = flip ? A.vals1 : A.vals0;
 

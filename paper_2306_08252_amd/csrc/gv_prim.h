@@ -564,10 +564,22 @@ __global__ __launch_bounds__(kOsThreads) void k_os_hist(const K* keys, const uin
 // hist[i] = sum over the histogram workgroups of their count i: a
 // workgroup takes 16 counters, its 16 row groups each add every 16th
 // workgroup's count with independent loads, LDS adds the row groups
+// (when vpart is given, workgroup 0 also adds the groups' vpart counts into
+// *vtotal)
 static __global__ __launch_bounds__(kThreads) void k_os_hist_sum(const uint32_t* hpart,
                                                                  uint32_t groups, uint32_t words,
-                                                                 uint32_t* hist) {
+                                                                 uint32_t* hist,
+                                                                 const uint32_t* vpart,
+                                                                 unsigned long long* vtotal) {
     __shared__ uint32_t red[16][17];
+    __shared__ unsigned long long s_v[kWaves];
+    if (vpart && blockIdx.x == 0) {
+        static_assert(kHistGroups <= kThreads, "one thread per histogram group");
+        const unsigned long long x = threadIdx.x < groups ? vpart[threadIdx.x] : 0u;
+        const unsigned long long t = block_sum(x, s_v);
+        if (threadIdx.x == 0) *vtotal = t;
+    }
+    if (words == 0) return;
     const uint32_t col = threadIdx.x & 15, rg = threadIdx.x >> 4;
     const uint32_t i = blockIdx.x * 16 + col;
     const uint32_t ic = i < words ? i : 0u;
@@ -768,6 +780,10 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const K* kin, K* kout, c
     }
 }
 
+template <typename K, bool HasVal>
+bool onesweep_passes(Ctx& c, K* k0, K* k1, uint32_t* v0, uint32_t* v1, const uint32_t* n_dev,
+                     uint64_t n_max, int bits, uint32_t* state, uint32_t* err);
+
 // Sorts n keys (n on the device when n_dev != null, n_max bounds it) by bits
 // [0, bits), stably, ping-ponging k0/k1 (v0/v1).  `state` must hold
 // os_words(n_max, bits) uint32 words, the first os_zero_words of them
@@ -779,16 +795,47 @@ bool onesweep(Ctx& c, K* k0, K* k1, uint32_t* v0, uint32_t* v1, const uint32_t* 
     if (n_max > 0xffffffffull) fail(GV_EINVAL, "sort too large");
     const int passes = os_passes(bits);
     if (passes > 8) fail(GV_EINVAL, "too many radix passes");
-    const uint64_t nt = os_tiles(n_max);
     const uint64_t hg = os_hist_groups(n_max);
     const uint32_t hwords = (uint32_t)passes * kRadix;
-    uint32_t* counters = state;           // 64 words
-    uint32_t* status = state + 64;        // passes * tiles * 256
     uint32_t* hist = state + os_zero_words(n_max, bits);  // passes * 256 counters
     uint32_t* hpart = hist + hwords;      // per histogram workgroup
     c.launch("sort_hist", k_os_hist<K>, hg, kOsThreads, (const K*)k0, n_dev, n_max, passes, hpart);
     c.launch("sort_hist", k_os_hist_sum, div_up(hwords, 16), kThreads, (const uint32_t*)hpart,
-             (uint32_t)hg, hwords, hist);
+             (uint32_t)hg, hwords, hist, (const uint32_t*)nullptr, (unsigned long long*)nullptr);
+    return onesweep_passes<K, HasVal>(c, k0, k1, v0, v1, n_dev, n_max, bits, state, err);
+}
+
+// Per-group digit counts of a sort whose histogram kernel is fused into the
+// kernel that writes the keys: group g writes os_passes(bits) * kRadix counts
+// at os_hpart(...) + g * os_passes(bits) * kRadix, for os_hist_groups(n_max)
+// groups of kOsTile-key tiles (tile t to group t % groups).
+inline uint32_t* os_hpart(uint32_t* state, uint64_t n_max, int bits) {
+    return state + os_zero_words(n_max, bits) + (uint64_t)os_passes(bits) * kRadix;
+}
+
+// Adds the per-group counts into the pass histograms; with vpart, also adds
+// os_hist_groups(n_max) per-group counts into *vtotal.  One launch, also when
+// there is nothing to sort.
+inline void os_hist_sum(Ctx& c, uint32_t* state, uint64_t n_max, int bits, const uint32_t* vpart,
+                        unsigned long long* vtotal) {
+    const uint32_t hwords = bits > 0 ? (uint32_t)os_passes(bits) * kRadix : 0u;
+    c.launch("sort_hist", k_os_hist_sum, std::max<uint64_t>(div_up(hwords, 16), 1), kThreads,
+             (const uint32_t*)os_hpart(state, n_max, bits), (uint32_t)os_hist_groups(n_max), hwords,
+             state + os_zero_words(n_max, bits), vpart, vtotal);
+}
+
+// The passes of onesweep, once the pass histograms are in the state.
+template <typename K, bool HasVal>
+bool onesweep_passes(Ctx& c, K* k0, K* k1, uint32_t* v0, uint32_t* v1, const uint32_t* n_dev,
+                     uint64_t n_max, int bits, uint32_t* state, uint32_t* err) {
+    if (n_max <= 1 || bits <= 0) return false;
+    if (n_max > 0xffffffffull) fail(GV_EINVAL, "sort too large");
+    const int passes = os_passes(bits);
+    if (passes > 8) fail(GV_EINVAL, "too many radix passes");
+    const uint64_t nt = os_tiles(n_max);
+    uint32_t* counters = state;           // 64 words
+    uint32_t* status = state + 64;        // passes * tiles * 256
+    uint32_t* hist = state + os_zero_words(n_max, bits);  // passes * 256 counters
     bool flip = false;
     for (int p = 0; p < passes; ++p) {
         K* kin = flip ? k1 : k0;
