@@ -314,7 +314,9 @@ struct SegOut {
         flags[i] = (head ? kHead : 0) | (uniq ? kUniq : 0);
         a[i] = t;
         if (head) {
-            t_vtx[t] = (uint32_t)(r.k >> L);
+            // masked to the table: a valid key's source is below 2^L already;
+            // the mask keeps even a corrupted key's record read in bounds
+            t_vtx[t] = (uint32_t)(r.k >> L) & (uint32_t)((1ull << L) - 1);
             t_start[t] = (uint32_t)i;
         }
         if (i + 1 == nv) t_start[t + 1] = (uint32_t)nv;
@@ -1340,6 +1342,8 @@ void edge_batch_warm() {
     resident_grid(k_probe<kQuery>, kThreads);
     resident_grid(k_grow, kThreads);
     resident_grid(k_compact, kThreads);
+    resident_grid(k_os_pass<uint64_t, false>, kOsThreads);
+    resident_grid(k_os_pass<uint64_t, true>, kOsThreads);
 }
 
 size_t edge_batch_bytes(const gv_graph* g, EdgeMode mode, uint64_t n) {

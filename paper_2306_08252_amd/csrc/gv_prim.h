@@ -609,7 +609,8 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const K* kin, K* kout, c
                                                         uint32_t* vout, const uint32_t* n_dev,
                                                         uint64_t n_max, int shift,
                                                         const uint32_t* hist, uint32_t* status,
-                                                        uint32_t* counter, uint32_t* err) {
+                                                        uint32_t* counter, int block_tiles,
+                                                        uint32_t* err) {
     // cnt[round * waves + wave][digit]: counts, then exclusive prefixes
     __shared__ uint16_t cnt[kOsRounds * kOsWaves][kRadix];
     __shared__ uint32_t part[4][kRadix];
@@ -621,15 +622,19 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const K* kin, K* kout, c
     __shared__ uint32_t sval[HasVal ? kOsTile : 1];
     const uint32_t t = threadIdx.x;
     const int w = t >> 6;
-    if (t == 0) s_tile = atomicAdd(counter, 1u);
-    // the key count is read while the ticket is in flight
+    // the pass histogram and the key count do not depend on the tile
+    const uint32_t hv = t < kRadix ? hist[t] : 0u;
     const uint64_t n = n_dev ? min<uint64_t>(*n_dev, n_max) : n_max;
-    {
-        uint32_t* c32 = (uint32_t*)&cnt[0][0];
-        for (int i = t; i < kOsRounds * kOsWaves * kRadix / 2; i += kOsThreads) c32[i] = 0;
+    // Tile ids: when every tile's workgroup fits on the device at once, the
+    // workgroup index (all tiles run together, so each one a tile waits for
+    // is running); else a ticket in launch order, so that every tile a tile
+    // waits for has started.
+    uint64_t tile = blockIdx.x;
+    if (!block_tiles) {
+        if (t == 0) s_tile = atomicAdd(counter, 1u);
+        __syncthreads();
+        tile = s_tile;
     }
-    __syncthreads();
-    const uint64_t tile = s_tile;
     const uint64_t base = tile * kOsTile;
     K key[kOsRounds];
     uint32_t val[kOsRounds];
@@ -642,6 +647,11 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const K* kin, K* kout, c
         key[j] = in ? kin[i] : K(0);
         if (HasVal) val[j] = in ? vin[i] : 0u;
     }
+    {
+        uint32_t* c32 = (uint32_t*)&cnt[0][0];
+        for (int i = t; i < kOsRounds * kOsWaves * kRadix / 2; i += kOsThreads) c32[i] = 0;
+    }
+    __syncthreads();
 #pragma unroll
     for (int j = 0; j < kOsRounds; ++j) {
         const uint64_t i = base + (uint64_t)j * kOsThreads + t;
@@ -742,7 +752,7 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const K* kin, K* kout, c
     if (t < kRadix && tile > 0) st_release32(status + tile * kRadix + t, kOsIncl | (prefix + dcount));
     // global start of each digit (pass histogram) and start inside the tile
     uint32_t tot;
-    const uint32_t gex = os_block_scan(t < kRadix ? hist[t] : 0u, s_w, tot);
+    const uint32_t gex = os_block_scan(hv, s_w, tot);
     const uint32_t lex = os_block_scan(t < kRadix ? dcount : 0u, s_w, tot);
     if (t < kRadix) {
         s_base[t] = gex + prefix;
@@ -836,6 +846,7 @@ bool onesweep_passes(Ctx& c, K* k0, K* k1, uint32_t* v0, uint32_t* v1, const uin
     uint32_t* counters = state;           // 64 words
     uint32_t* status = state + 64;        // passes * tiles * 256
     uint32_t* hist = state + os_zero_words(n_max, bits);  // passes * 256 counters
+    const int block_tiles = nt <= resident_grid(k_os_pass<K, HasVal>, kOsThreads) ? 1 : 0;
     bool flip = false;
     for (int p = 0; p < passes; ++p) {
         K* kin = flip ? k1 : k0;
@@ -846,7 +857,7 @@ bool onesweep_passes(Ctx& c, K* k0, K* k1, uint32_t* v0, uint32_t* v1, const uin
                  (const uint32_t*)vin, vout, n_dev, n_max, p * kRadixBits,
                  (const uint32_t*)(hist + (uint64_t)p * kRadix),
                  status + (uint64_t)p * nt * kRadix,
-                 counters + p, err);
+                 counters + p, block_tiles, err);
         flip = !flip;
     }
     return flip;
