@@ -48,7 +48,13 @@ class Checker:
         deg = np.diff(offs)
         src = np.repeat(np.arange(len(deg), dtype=np.uint64), deg)
         keys = keys_of(src, dst)
-        assert np.all(keys[1:] > keys[:-1]), label  # sorted, no duplicates
+        bad = np.nonzero(keys[1:] <= keys[:-1])[0]
+        if len(bad):  # sorted, no duplicates; else say where
+            u = (keys[bad[:8] + 1] >> np.uint64(32)).astype(np.int64)
+            detail = [(int(v), int(keys[i + 1] & np.uint64(0xffffffff)), int(deg[v]))
+                      for v, i in zip(u, bad[:8])]
+            raise AssertionError(f"{label}: {len(bad)} order violations in {len(np.unique(u))}+ "
+                                 f"rows; (src, dst, degree): {detail}; sync={g.sync()}")
         mem = g.memory_used()
         assert mem["num_edges"] == e == len(dst)
         B = self.B
