@@ -14,6 +14,7 @@
 #pragma once
 
 #include <algorithm>
+#include <type_traits>
 
 #include "gv_device.h"
 #include "gv_host.h"
@@ -342,7 +343,8 @@ void scan1(Ctx& c, const char* name, In in, Out out, uint64_t n, unsigned long l
 // ---------------------------------------------------------------- scan2
 // Two-kernel exclusive scan without inter-tile waits: the first kernel
 // reduces each tile, the second recomputes its tile prefix by reducing the
-// partials of all earlier tiles (at most a few thousand, read from L2) and
+// partials of all earlier tiles (up to kScan2MaxTiles, read from L2; with
+// more tiles a one-workgroup kernel between the two scans the partials) and
 // scans its tile.  Inputs are evaluated twice, outputs written once.
 //
 // The source is a gather: it splits each element into its memory reads and
@@ -359,23 +361,36 @@ void scan1(Ctx& c, const char* name, In in, Out out, uint64_t n, unsigned long l
 //   ull value(uint64_t i, const Rec&)   the element's value (called when ok)
 // The sink takes (i, rec, lim, exclusive prefix) for every i < n; the
 // element is live when i < lim.
+// Elements per thread: In::kItems when the source defines it (sources with
+// large records take fewer, to keep registers low), else kScan1Items.
+template <typename In, typename = void>
+struct scan2_items {
+    static constexpr int value = kScan1Items;
+};
+template <typename In>
+struct scan2_items<In, std::void_t<decltype(In::kItems)>> {
+    static constexpr int value = In::kItems;
+};
+constexpr int kScan2MinItems = 4;  // the fewest any source takes
+
 template <typename In>
 __global__ __launch_bounds__(kThreads) void k_scan2_reduce(In in, uint64_t n,
                                                            unsigned long long* part) {
+    constexpr int kI = scan2_items<In>::value;
     __shared__ unsigned long long s_w[kWaves];
     const uint64_t lim = in.limit(n);
-    const uint64_t base = (uint64_t)blockIdx.x * kScan1Tile + threadIdx.x;
-    typename In::Rec r[kScan1Items];
+    const uint64_t base = (uint64_t)blockIdx.x * kThreads * kI + threadIdx.x;
+    typename In::Rec r[kI];
 #pragma unroll
-    for (int j = 0; j < kScan1Items; ++j) {
+    for (int j = 0; j < kI; ++j) {
         const uint64_t i = base + (uint64_t)j * kThreads;
         r[j] = in.load(i < n ? i : n - 1, i < lim);
     }
 #pragma unroll
-    for (int j = 0; j < kScan1Items; ++j) in.deref(r[j]);
+    for (int j = 0; j < kI; ++j) in.deref(r[j]);
     unsigned long long s = 0;
 #pragma unroll
-    for (int j = 0; j < kScan1Items; ++j) {
+    for (int j = 0; j < kI; ++j) {
         const uint64_t i = base + (uint64_t)j * kThreads;
         s += i < lim ? in.value(i, r[j]) : 0ull;
     }
@@ -383,29 +398,52 @@ __global__ __launch_bounds__(kThreads) void k_scan2_reduce(In in, uint64_t n,
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// Exclusive scan of the nt tile sums in place (one workgroup), for inputs
+// with more tiles than the apply kernel adds up itself.
+static __global__ __launch_bounds__(kThreads) void k_scan2_partials(unsigned long long* part,
+                                                                    uint64_t nt) {
+    __shared__ unsigned long long lds[kWaves];
+    unsigned long long carry = 0;
+    for (uint64_t b = 0; b < nt; b += kThreads) {
+        const uint64_t i = b + threadIdx.x;
+        const unsigned long long x = i < nt ? part[i] : 0ull;
+        unsigned long long tot;
+        const unsigned long long ex = block_excl_scan(x, lds, tot);
+        if (i < nt) part[i] = carry + ex;
+        carry += tot;
+    }
+}
+
+// scanned: part already holds exclusive tile prefixes
 template <typename In, typename Out>
 __global__ __launch_bounds__(kThreads) void k_scan2_apply(In in, Out out, uint64_t n,
                                                           const unsigned long long* part,
+                                                          int scanned,
                                                           unsigned long long* total) {
-    __shared__ unsigned long long s_w[kScan1Items][kWaves];
+    constexpr int kI = scan2_items<In>::value;
+    __shared__ unsigned long long s_w[kI][kWaves];
     __shared__ unsigned long long s_p[kWaves];
     const uint64_t lim = in.limit(n);
-    const uint64_t base = (uint64_t)blockIdx.x * kScan1Tile + threadIdx.x;
-    typename In::Rec r[kScan1Items];
+    const uint64_t base = (uint64_t)blockIdx.x * kThreads * kI + threadIdx.x;
+    typename In::Rec r[kI];
 #pragma unroll
-    for (int j = 0; j < kScan1Items; ++j) {
+    for (int j = 0; j < kI; ++j) {
         const uint64_t i = base + (uint64_t)j * kThreads;
         r[j] = in.load(i < n ? i : n - 1, i < lim);
     }
 #pragma unroll
-    for (int j = 0; j < kScan1Items; ++j) in.deref(r[j]);
+    for (int j = 0; j < kI; ++j) in.deref(r[j]);
     unsigned long long p = 0;
-    for (uint32_t t = threadIdx.x; t < blockIdx.x; t += kThreads) p += part[t];
+    if (scanned) {
+        p = threadIdx.x == 0 ? part[blockIdx.x] : 0ull;
+    } else {
+        for (uint32_t t = threadIdx.x; t < blockIdx.x; t += kThreads) p += part[t];
+    }
     // one wave scan per row of the tile, then a single exchange of the
     // per-wave row totals
-    unsigned long long x[kScan1Items], inc[kScan1Items];
+    unsigned long long x[kI], inc[kI];
 #pragma unroll
-    for (int j = 0; j < kScan1Items; ++j) {
+    for (int j = 0; j < kI; ++j) {
         const uint64_t i = base + (uint64_t)j * kThreads;
         x[j] = i < lim ? in.value(i, r[j]) : 0ull;
         inc[j] = wave_incl_scan(x[j]);
@@ -413,11 +451,11 @@ __global__ __launch_bounds__(kThreads) void k_scan2_apply(In in, Out out, uint64
     const int w = threadIdx.x >> 6;
     if (lane_id() == 63) {
 #pragma unroll
-        for (int j = 0; j < kScan1Items; ++j) s_w[j][w] = inc[j];
+        for (int j = 0; j < kI; ++j) s_w[j][w] = inc[j];
     }
     unsigned long long run = block_sum(p, s_p);  // its barriers publish s_w
 #pragma unroll
-    for (int j = 0; j < kScan1Items; ++j) {
+    for (int j = 0; j < kI; ++j) {
         const uint64_t i = base + (uint64_t)j * kThreads;
         unsigned long long before = 0, tot = 0;
 #pragma unroll
@@ -432,20 +470,26 @@ __global__ __launch_bounds__(kThreads) void k_scan2_apply(In in, Out out, uint64
     if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == kThreads - 1) *total = run;
 }
 
+// tiles the apply kernel adds up itself; beyond, a middle kernel scans them
 constexpr uint64_t kScan2MaxTiles = 8192;
-inline uint64_t scan2_parts(uint64_t n) { return div_up(std::max<uint64_t>(n, 1), kScan1Tile); }
+// partial words any scan2 over n elements needs
+inline uint64_t scan2_parts(uint64_t n) {
+    return div_up(std::max<uint64_t>(n, 1), (uint64_t)kThreads * kScan2MinItems);
+}
 
-// Exclusive scan of in(i), i < n, as out(i, prefix); total -> *total.
-// `part` holds scan2_parts(n) words.  n must not exceed kScan2MaxTiles tiles.
+// Exclusive scan of in(i), i < n, as out(i, rec, lim, prefix); total ->
+// *total.  `part` holds scan2_parts(n) words.
 template <typename In, typename Out>
 void scan2(Ctx& c, const char* name, In in, Out out, uint64_t n, unsigned long long* part,
            unsigned long long* total) {
     if (n == 0) return;
-    const uint64_t nt = scan2_parts(n);
-    if (nt > kScan2MaxTiles) fail(GV_EINVAL, "scan too large for the two-kernel scan");
+    const uint64_t nt = div_up(n, (uint64_t)kThreads * scan2_items<In>::value);
+    if (nt > 0xffffffffull) fail(GV_EINVAL, "scan too large");
     c.launch(name, k_scan2_reduce<In>, nt, kThreads, in, n, part);
+    const int scanned = nt > kScan2MaxTiles ? 1 : 0;
+    if (scanned) c.launch(name, k_scan2_partials, 1, kThreads, part, nt);
     c.launch(name, k_scan2_apply<In, Out>, nt, kThreads, in, out, n,
-             (const unsigned long long*)part, total);
+             (const unsigned long long*)part, scanned, total);
 }
 
 // ---------------------------------------------------------------- onesweep

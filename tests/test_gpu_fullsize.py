@@ -17,6 +17,7 @@ import torch
 
 from gpu_helpers import need_gpu, say, u32
 from oracle import pyoracle as O
+from paper_2306_08252_amd import inputs as I
 from paper_2306_08252_amd import inputs_torch as T
 
 pytestmark = pytest.mark.gpu
@@ -96,4 +97,32 @@ def test_rmat20_full_size_batches():
     np.testing.assert_array_equal(ans, np.isin(keys_of(qs, qd), E).astype(np.uint8))
     sel = in_sample[qs]
     np.testing.assert_array_equal(ans[sel], o.edge_exists(qs[sel], qd[sel]))
+    g.close()
+
+
+def test_batch_beyond_two_kernel_scan():
+    """A batch of 2^24 + 12345 pairs: its scans have more tiles than the apply
+    kernel adds up itself, so the partials are scanned by a middle kernel.
+    Insert, then delete half: the dump equals the set algebra exactly."""
+    gv = need_gpu()
+    n, k = 1 << 16, (1 << 24) + 12345
+    s, d = I.uniform_pairs(I.stream_seed("big-batch"), k, n)
+    s0, d0 = I.uniform_pairs(I.stream_seed("big-batch-init"), 100000, n)
+    say(f"batch of {k} pairs into 2^16 vertices")
+    g = gv.Graph(n, s0, d0, block_slots=16)
+    E = np.unique(keys_of(s0, d0))
+    bk = keys_of(s, d)
+    st = g.insert_edges(s, d)
+    E2 = np.union1d(E, bk)
+    assert st == (len(E2) - len(E), 0, k - len(np.unique(bk)))
+    got, _ = dump_keys(g)
+    np.testing.assert_array_equal(got, E2)
+    assert g.audit() == 0
+    half = k // 2
+    st = g.delete_edges(s[:half], d[:half])
+    E3 = np.setdiff1d(E2, bk[:half])
+    assert st[0] == len(E2) - len(E3)
+    got, _ = dump_keys(g)
+    np.testing.assert_array_equal(got, E3)
+    assert g.audit() == 0
     g.close()
