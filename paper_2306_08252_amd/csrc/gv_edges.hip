@@ -354,7 +354,7 @@ __device__ __forceinline__ bool small_item(uint32_t B, uint32_t deg, uint32_t le
 }
 
 struct ItemIn {
-    static constexpr int kItems = 4;  // large records: fewer per thread
+    static constexpr int kItems = 2;  // large records: fewer per thread
     GraphView g;
     const uint32_t* t_vtx;
     const uint32_t* t_start;

@@ -498,7 +498,10 @@ void scan2(Ctx& c, const char* name, In in, Out out, uint64_t n, unsigned long l
 // masks per wave and round, LDS column scans), publishes its per-digit counts,
 // looks back per digit for the counts of earlier tiles, and scatters.  The
 // number of keys may live on the device (n_dev); grids are sized for n_max.
-constexpr int kOsItems = 16;
+#ifndef GV_OS_ITEMS
+#define GV_OS_ITEMS 16
+#endif
+constexpr int kOsItems = GV_OS_ITEMS;  // keys per tile = kThreads * kOsItems
 constexpr uint64_t kOsTile = (uint64_t)kThreads * kOsItems;  // 4096
 constexpr uint32_t kOsAgg = 1u << 30, kOsIncl = 2u << 30, kOsMask = (1u << 30) - 1;
 
@@ -511,8 +514,12 @@ inline uint64_t os_hist_groups(uint64_t n) { return std::min<uint64_t>(os_tiles(
 // uint32 words of state a sort needs: tile counters and look-back status
 // (the first os_zero_words, which must be zeroed), then the histograms and
 // the per-group histograms
+// Tiles per group of the two-level prefix that workgroup-index tiles use.
+constexpr uint64_t kOsGroup = 16;
+inline uint64_t os_groups(uint64_t n) { return div_up(os_tiles(n), kOsGroup); }
 inline uint64_t os_zero_words(uint64_t n_max, int bits) {
-    return 64 + (uint64_t)os_passes(bits) * os_tiles(n_max) * kRadix;
+    const uint64_t p = (uint64_t)os_passes(bits);
+    return 64 + p * os_tiles(n_max) * kRadix + p * os_groups(n_max) * kRadix;
 }
 inline uint64_t os_words(uint64_t n_max, int bits) {
     const uint64_t p = (uint64_t)os_passes(bits);
@@ -653,8 +660,8 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const K* kin, K* kout, c
                                                         uint32_t* vout, const uint32_t* n_dev,
                                                         uint64_t n_max, int shift,
                                                         const uint32_t* hist, uint32_t* status,
-                                                        uint32_t* counter, int block_tiles,
-                                                        uint32_t* err) {
+                                                        uint32_t* gstatus, uint32_t* counter,
+                                                        int block_tiles, uint32_t* err) {
     // cnt[round * waves + wave][digit]: counts, then exclusive prefixes
     __shared__ uint16_t cnt[kOsRounds * kOsWaves][kRadix];
     __shared__ uint32_t part[4][kRadix];
@@ -734,11 +741,58 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const K* kin, K* kout, c
 #pragma unroll
         for (int r = 0; r < kQRows; ++r) cnt[q * kQRows + r][d] += (uint16_t)qoff;
     }
+    __shared__ uint32_t lb_prefix[kRadix];
+    if (block_tiles) {
+        // Every tile runs at once: a two-level prefix, two rounds of loads
+        // whatever the tile's position.  Four lanes per digit add the counts
+        // of the earlier tiles of the tile's group of kOsGroup; the group's
+        // last tile publishes the group total; then the four lanes add the
+        // totals of the earlier groups.
+        if (t < kRadix) st_release32(status + tile * kRadix + t, kOsAgg | dcount);
+        const uint32_t ld = t >> 2, lq = t & 3, gbase = lane_id() & ~3u;
+        const uint64_t G = tile / kOsGroup;
+        auto wait_sum = [&](uint32_t* base, uint64_t first, uint64_t end) {
+            uint32_t wv[kOsLookK];
+#pragma unroll
+            for (int kk = 0; kk < kOsLookK; ++kk) {
+                const uint64_t j = first + lq * kOsLookK + kk;
+                wv[kk] = j < end ? ld_acquire32(base + j * kRadix + ld) : kOsAgg;
+            }
+            uint32_t sum = 0;
+#pragma unroll
+            for (int kk = 0; kk < kOsLookK; ++kk) {
+                const uint64_t j = first + lq * kOsLookK + kk;
+                if ((wv[kk] >> 30) == 0) {
+                    uint32_t spins = 0;
+                    do {
+                        wv[kk] = ld_acquire32(base + j * kRadix + ld);
+                    } while ((wv[kk] >> 30) == 0 && ++spins < kSpinLimit);
+                    if ((wv[kk] >> 30) == 0) {
+                        *err = 1;
+                        wv[kk] = kOsAgg;
+                    }
+                }
+                sum += wv[kk] & kOsMask;
+            }
+            uint32_t all = 0;
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) all += __shfl(sum, (int)(gbase + qq), 64);
+            return all;
+        };
+        static_assert(kOsGroup == 4 * kOsLookK, "a group is one round of four lanes");
+        const uint32_t local = wait_sum(status, G * kOsGroup, tile);
+        if (tile % kOsGroup == kOsGroup - 1 && lq == 0) {
+            const uint32_t own = part[0][ld] + part[1][ld] + part[2][ld] + part[3][ld];
+            st_release32(gstatus + G * kRadix + ld, kOsAgg | (local + own));
+        }
+        uint32_t global = 0;
+        for (uint64_t g0 = 0; g0 < G; g0 += kOsGroup) global += wait_sum(gstatus, g0, G);
+        if (lq == 0) lb_prefix[ld] = local + global;
+    } else {
     // publish this tile's counts, then look back with four consecutive lanes
     // per digit: each round a lane reads the status of kOsLookK earlier
     // tiles with independent loads, and the four lanes add them, newest
     // first, up to the first inclusive one
-    __shared__ uint32_t lb_prefix[kRadix];
     if (t < kRadix) st_release32(status + tile * kRadix + t, (tile == 0 ? kOsIncl : kOsAgg) | dcount);
     {
         const uint32_t ld = t >> 2, lq = t & 3, gbase = lane_id() & ~3u;
@@ -791,9 +845,11 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const K* kin, K* kout, c
         }
         if (lq == 0) lb_prefix[ld] = lp;
     }
+    }
     __syncthreads();
     const uint32_t prefix = t < kRadix ? lb_prefix[t] : 0u;
-    if (t < kRadix && tile > 0) st_release32(status + tile * kRadix + t, kOsIncl | (prefix + dcount));
+    if (!block_tiles && t < kRadix && tile > 0)
+        st_release32(status + tile * kRadix + t, kOsIncl | (prefix + dcount));
     // global start of each digit (pass histogram) and start inside the tile
     uint32_t tot;
     const uint32_t gex = os_block_scan(hv, s_w, tot);
@@ -889,6 +945,8 @@ bool onesweep_passes(Ctx& c, K* k0, K* k1, uint32_t* v0, uint32_t* v1, const uin
     const uint64_t nt = os_tiles(n_max);
     uint32_t* counters = state;           // 64 words
     uint32_t* status = state + 64;        // passes * tiles * 256
+    uint32_t* gstatus = status + (uint64_t)passes * nt * kRadix;  // passes * groups * 256
+    const uint64_t ng = os_groups(n_max);
     uint32_t* hist = state + os_zero_words(n_max, bits);  // passes * 256 counters
     const int block_tiles = nt <= resident_grid(k_os_pass<K, HasVal>, kOsThreads) ? 1 : 0;
     bool flip = false;
@@ -900,7 +958,7 @@ bool onesweep_passes(Ctx& c, K* k0, K* k1, uint32_t* v0, uint32_t* v1, const uin
         c.launch("sort_pass", k_os_pass<K, HasVal>, nt, kOsThreads, (const K*)kin, kout,
                  (const uint32_t*)vin, vout, n_dev, n_max, p * kRadixBits,
                  (const uint32_t*)(hist + (uint64_t)p * kRadix),
-                 status + (uint64_t)p * nt * kRadix,
+                 status + (uint64_t)p * nt * kRadix, gstatus + (uint64_t)p * ng * kRadix,
                  counters + p, block_tiles, err);
         flip = !flip;
     }
