@@ -81,12 +81,20 @@ def bytes_model(name, per_launch):
         # per touched source + the sorted batch keys (each read once) + one
         # mark byte per pair
         return 4 * S + 4 * NBLK + 32 * T + 8 * k + k
+    P = per_launch.get("passes", 5)
+    tiles = (k + 4095) // 4096
+    groups = min(tiles, 256)
     if name == "sort_pass":
         return 16 * k  # one 8-bit digit pass: read and write every key once
     if name == "sort_hist":
-        return 8 * k  # all digit histograms from one read of the keys
+        # insert / delete batches: add the per-group digit counts of the
+        # packing kernel (and the valid-pair counts) into the pass histograms
+        return 4 * 256 * P * (groups + 1) + 4 * groups
     if name == "pack":
-        return 8 * k + 8 * k + k  # pairs in, keys out, mark bytes
+        # pairs in, keys and mark bytes out, the batch's look-back state
+        # cleared, per-group digit counts out
+        return 8 * k + 8 * k + k + 4 * (64 + P * tiles * 256 + P * ((tiles + 15) // 16) * 256) \
+            + 4 * 256 * P * groups
     if name == "segments":
         return 8 * k + k + 4 * k + 8 * T  # keys in; flags, ranks, segment starts out
     if name == "items":
@@ -101,7 +109,8 @@ def bytes_model(name, per_launch):
 # library launch names -> kernel symbol prefix in rocprofv3 output
 KERNEL_SYMBOLS = {
     "sort_pass": "gv::k_os_pass<unsigned long, false>",
-    "sort_hist": "gv::k_os_hist<unsigned long>",
+    "sort_hist": "gv::k_os_hist_sum",
+    "pack": "gv::k_pack_hist(",
     "probe_insert": "gv::k_probe<0>",
     "probe_delete": "gv::k_probe<1>",
     "probe_query": "gv::k_probe<2>",
@@ -229,7 +238,7 @@ def main():
         k = args.batch
         grid = {"sort_pass": (k + 4095) // 4096, "probe_insert": None, "probe_delete": None,
                 "probe_query": None, "compact": None, "append": (k + 255) // 256,
-                "sort_hist": min((k + 4095) // 4096, 256)}
+                "sort_hist": None, "pack": min((k + 4095) // 4096, 256)}
         summarize_traffic(*args.summarize_traffic[:4], grid, args.summarize_traffic[4],
                           args.command)
         return
@@ -339,6 +348,7 @@ def main():
                "W": d["written_slots"] / K, "M": 0, "FREED": 0}
     if dominant.startswith("sort_"):
         per["k"] = k
+    per["passes"] = (2 * args.scale + 7) // 8  # 8-bit digits of (src << L) | dst
     bpl = bytes_model(dominant, per)
     avg_s = dom_ms / 1e3 / dom_launches if dom_launches else None
     roof = None
