@@ -209,6 +209,65 @@ def summarize_traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, grid_wgs, ou
                 "while the sources match.\n\n" + "\n".join(lines) + "\n")
 
 
+def batched_form(gv, I, T, dev, B, scale=22, edges=1 << 26, nbatch=256, seed_name="batched"):
+    """The batched form: `nbatch` batches of log-uniform size in [10^2, 10^6],
+    45 % edge inserts (R-MAT pairs), 45 % edge deletes (80 % stored pairs, 20 %
+    uniform), 10 % vertex batches (min(size, 10^4) uniform ids, insert or
+    delete alike), applied in order with gv_apply_ops (one launch sequence
+    per batch).  Scratch is sized by a warm-up insert and delete of the
+    largest batch and a vertex delete and re-insert before the timed pass."""
+    import numpy as np
+    import torch
+    w = T.RmatWorkload(scale, edges, name=seed_name, device=dev)
+    n = w.num_vertices
+    draws = I.splitmix64(I.stream_seed(seed_name, "ops"), 3 * nbatch)
+    ops, pairs, vids = [], 0, 0
+    for j in range(nbatch):
+        u = float(draws[3 * j] >> np.uint64(11)) / float(1 << 53)
+        size = int(round(100 * np.exp(u * np.log(10**4))))
+        r = float(draws[3 * j + 1] >> np.uint64(11)) / float(1 << 53)
+        if r < 0.45:
+            s, d = w.insert_batch(size, j)
+            ops.append((0, s, d))
+            pairs += size
+        elif r < 0.90:
+            ne = int(round(0.8 * size))
+            es, ed = T.pick(I.stream_seed(seed_name, "del-existing", j), ne, w.src, w.dst)
+            us, ud = T.uniform_pairs(I.stream_seed(seed_name, "del-uniform", j), size - ne, n,
+                                     device=dev)
+            ops.append((1, torch.cat([es, us]), torch.cat([ed, ud])))
+            pairs += size
+        else:
+            m = min(size, 10**4)
+            ids = torch.from_numpy((I.splitmix64(I.stream_seed(seed_name, "vertices", j), m)
+                                    % np.uint64(n)).astype(np.uint32).view(np.int32)).to(dev)
+            ops.append((2 if draws[3 * j + 2] & np.uint64(1) else 3, ids, None))
+            vids += m
+    g = gv.Graph(n, w.src, w.dst, block_slots=B, device=dev)
+    big = max((o for o in ops if o[0] == 0), key=lambda o: o[1].numel())
+    g.insert_edges(big[1], big[2], stats=False)
+    g.delete_edges(big[1], big[2], stats=False)
+    one = ops[[o[0] for o in ops].index(3)][1][:1] if any(o[0] == 3 for o in ops) else None
+    if one is not None:
+        g.delete_vertices(one)
+        g.insert_vertices(one)
+    keep = gv.gv_apply_ops(g.h, ops[:1])  # marshalling warm-up
+    torch.cuda.synchronize()
+    arr, keep = gv._ops(ops, dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gv._check(gv.lib().gv_apply_ops(gv.C.c_void_p(g.h), arr, len(ops)), "gv_apply_ops")
+    rc = g.sync()
+    el = time.perf_counter() - t0
+    g.close()
+    if rc != 0:
+        raise RuntimeError(f"batched form: {gv.gv_strerror(rc)}")
+    return {"workload": f"rmat{scale} {edges} edges, B={B}, {nbatch} batches of log-uniform "
+                        "size in [1e2, 1e6], 45/45/10 insert/delete/vertex",
+            "pairs": pairs, "vertex_ids": vids, "ms": round(el * 1e3, 3),
+            "edges_per_s": round(pairs / el, 1), "form": "one launch sequence per batch"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -220,6 +279,9 @@ def main():
     ap.add_argument("--edges", type=int, default=1 << 24)
     ap.add_argument("--queries", type=int, default=5, help="timed query batches")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched", action="store_true",
+                    help="also run the batched-form workload (off: its one run ended in a "
+                         "device fault whose cause is not found yet)")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "OUT_MD"),
                     help="write a kernel-trace summary (no GPU)")
     ap.add_argument("--summarize-traffic", nargs=5,
@@ -391,6 +453,9 @@ def main():
     vins_ms = (time.perf_counter() - t0) * 1e3
     g.close()
 
+    # ---- batched form on its own workload
+    batched = batched_form(gv, I, T, dev, B) if args.batched else None
+
     # ---- CPU oracle baseline on a quarter of the sources
     cpu = None
     if not args.no_cpu_baseline:
@@ -444,6 +509,7 @@ def main():
         "vertex_insert_1e4": {"ms": round(vins_ms, 3), "stats": vins},
         "memory": {"live_bytes": mem["live_bytes"], "blocks_in_use": mem["blocks_in_use"],
                    "num_edges": mem["num_edges"]},
+        "batched_form": batched,
         "served_p50_p99": None,
         "pilot_kernels_ms": pilot,
         "roofline": roof,
