@@ -372,8 +372,10 @@ struct ItemIn {
 };
 
 // A source's work items: one per kChunk slots.  A lane writes up to
-// kLaneItems of them; sources with more are written by the whole wave, 64
-// items per store.  All active lanes of a wave make the call.
+// kLaneItems of them; sources with more are written by all the lanes of the
+// wave that make the call, one item each per store.  The scan calls the sink
+// for elements below its size only, so in the last wave of a scan some lanes
+// may not take part: the loop counts the lanes that do.
 constexpr uint32_t kLaneItems = 4;
 
 struct ItemOut {
@@ -409,6 +411,8 @@ struct ItemOut {
                 items[base + c] = it;
             }
         }
+        const uint64_t act = ballot(true);
+        const uint32_t nact = popc64(act), me = rank_below(act);
         uint64_t m = ballot(cnt > kLaneItems);
         while (m) {
             const int l = __ffsll((unsigned long long)m) - 1;
@@ -422,7 +426,7 @@ struct ItemOut {
             w.dcls = __shfl(it.dcls, l, 64);
             const uint32_t wdeg = __shfl(r.deg, l, 64);
             const uint32_t wcnt = __shfl(cnt, l, 64), wbase = __shfl(base, l, 64);
-            for (uint32_t c = lane_id(); c < wcnt; c += 64) {
+            for (uint32_t c = me; c < wcnt; c += nact) {
                 w.s0 = c * kChunk;
                 w.s1 = min(wdeg, w.s0 + kChunk);
                 items[wbase + c] = w;
@@ -929,9 +933,12 @@ __global__ __launch_bounds__(kThreads) void k_grow(GraphView g, const uint32_t* 
         nr.deg = r.deg + kp;
         if (cls != kNoDir) {
             const uint32_t off = planned_segment(g, c, cls, rk);
+            // (a record keeps its segment when its degree drops, down to zero,
+            // so nb0 may be 0 here: then entry 0 of the segment is read)
             uint32_t old[kLaneCopy];
 #pragma unroll
-            for (uint32_t j = 0; j < kLaneCopy; ++j) old[j] = block_of(g, r, min(j, nb0 - 1));
+            for (uint32_t j = 0; j < kLaneCopy; ++j)
+                old[j] = block_of(g, r, min(j, nb0 ? nb0 - 1 : 0u));
 #pragma unroll
             for (uint32_t j = 0; j < kLaneCopy; ++j)
                 if (j < nb0) g.dir[(uint64_t)off + j] = old[j];

@@ -371,7 +371,7 @@ template <typename In>
 struct scan2_items<In, std::void_t<decltype(In::kItems)>> {
     static constexpr int value = In::kItems;
 };
-constexpr int kScan2MinItems = 4;  // the fewest any source takes
+constexpr int kScan2MinItems = 2;  // the fewest any source takes (scan2 checks it)
 
 template <typename In>
 __global__ __launch_bounds__(kThreads) void k_scan2_reduce(In in, uint64_t n,
@@ -482,6 +482,8 @@ inline uint64_t scan2_parts(uint64_t n) {
 template <typename In, typename Out>
 void scan2(Ctx& c, const char* name, In in, Out out, uint64_t n, unsigned long long* part,
            unsigned long long* total) {
+    static_assert(scan2_items<In>::value >= kScan2MinItems,
+                  "the partials are sized for kScan2MinItems elements per thread");
     if (n == 0) return;
     const uint64_t nt = div_up(n, (uint64_t)kThreads * scan2_items<In>::value);
     if (nt > 0xffffffffull) fail(GV_EINVAL, "scan too large");

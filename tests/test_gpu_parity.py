@@ -312,3 +312,37 @@ def test_segment_lengths_around_lds_stage(B):
         assert_same(g, o, f"delete rep {rep}")
         same_answers(g, o, s, d, f"query after delete rep {rep}")
     g.close()
+
+
+@pytest.mark.parametrize("B", [4, 16])
+def test_small_batches_touching_hubs(B):
+    """Batches whose size is not a multiple of the 64-lane wave (1 to 127
+    pairs) touching sources with tens of work items: the last wave of the
+    work-item scan has lanes that do not take part, and every item of a hub
+    must still be written (stale items there once sent the probe to wild
+    addresses)."""
+    gv = need_gpu()
+    rng = np.random.default_rng(23)
+    n = 1 << 15
+    hubs = np.array([0, 5, 77, 4096], np.uint32)
+    degs = [41 * 256 + 3, 20 * 256, 5 * 256 + 1, 9000]
+    s0 = np.concatenate([np.full(k, h, np.uint32) for h, k in zip(hubs, degs)])
+    d0 = np.concatenate([rng.permutation(n)[:k].astype(np.uint32) for k in degs])
+    g = gv.Graph(n, s0, d0, block_slots=B)
+    o = O.OracleGraph(n, s0, d0, block_slots=B)
+    assert_same(g, o, "init")
+    for j, size in enumerate([1, 2, 5, 31, 63, 65, 100, 127]):
+        s = rng.choice(hubs, size).astype(np.uint32)
+        s[: size // 3] = rng.integers(0, n, size // 3).astype(np.uint32)  # some light sources
+        d = rng.integers(0, n, size).astype(np.uint32)
+        known = rng.integers(0, len(s0), size)
+        ds, dd = s.copy(), d.copy()
+        ds[size // 2:], dd[size // 2:] = s0[known[size // 2:]], d0[known[size // 2:]]
+        say(f"size {size} B={B}")
+        same_answers(g, o, ds, dd, f"query {size}")
+        assert g.insert_edges(s, d) == o.insert_edges(s, d)[1], f"insert {size}"
+        assert_same(g, o, f"insert {size}")
+        assert g.delete_edges(ds, dd) == o.delete_edges(ds, dd)[1], f"delete {size}"
+        assert_same(g, o, f"delete {size}")
+        same_answers(g, o, ds, dd, f"query after delete {size}")
+    g.close()
