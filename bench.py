@@ -214,8 +214,11 @@ def batched_form(gv, I, T, dev, B, scale=22, edges=1 << 26, nbatch=256, seed_nam
     45 % edge inserts (R-MAT pairs), 45 % edge deletes (80 % stored pairs, 20 %
     uniform), 10 % vertex batches (min(size, 10^4) uniform ids, insert or
     delete alike), applied in order with gv_apply_ops (one launch sequence
-    per batch).  Scratch is sized by a warm-up insert and delete of the
-    largest batch and a vertex delete and re-insert before the timed pass."""
+    per batch), then, on a second copy of the same graph, recorded into one
+    HIP graph (gv_plan_create, not timed) and launched once; both results
+    must have the same checksum and edge count.  Scratch is sized by a
+    warm-up insert and delete of the largest batch and a vertex delete and
+    re-insert before the timed passes."""
     import numpy as np
     import torch
     w = T.RmatWorkload(scale, edges, name=seed_name, device=dev)
@@ -243,14 +246,27 @@ def batched_form(gv, I, T, dev, B, scale=22, edges=1 << 26, nbatch=256, seed_nam
                                     % np.uint64(n)).astype(np.uint32).view(np.int32)).to(dev)
             ops.append((2 if draws[3 * j + 2] & np.uint64(1) else 3, ids, None))
             vids += m
-    g = gv.Graph(n, w.src, w.dst, block_slots=B, device=dev)
     big = max((o for o in ops if o[0] == 0), key=lambda o: o[1].numel())
-    g.insert_edges(big[1], big[2], stats=False)
-    g.delete_edges(big[1], big[2], stats=False)
     one = ops[[o[0] for o in ops].index(3)][1][:1] if any(o[0] == 3 for o in ops) else None
-    if one is not None:
-        g.delete_vertices(one)
-        g.insert_vertices(one)
+
+    def fresh():
+        # the same graph and warm-up for both forms
+        g = gv.Graph(n, w.src, w.dst, block_slots=B, device=dev)
+        g.insert_edges(big[1], big[2], stats=False)
+        g.delete_edges(big[1], big[2], stats=False)
+        if one is not None:
+            g.delete_vertices(one)
+            g.insert_vertices(one)
+        return g
+
+    def digest(g):
+        ck, e = gv.C.c_uint64(), gv.C.c_uint64()
+        gv._check(gv.lib().gv_dump_canonical(gv.C.c_void_p(g.h), None, None, 0, gv.C.byref(ck),
+                                             gv.C.byref(e)), "gv_dump_canonical")
+        return ck.value, e.value
+
+    # eager: one launch sequence per batch
+    g = fresh()
     keep = gv.gv_apply_ops(g.h, ops[:1])  # marshalling warm-up
     torch.cuda.synchronize()
     arr, keep = gv._ops(ops, dev)
@@ -259,13 +275,34 @@ def batched_form(gv, I, T, dev, B, scale=22, edges=1 << 26, nbatch=256, seed_nam
     gv._check(gv.lib().gv_apply_ops(gv.C.c_void_p(g.h), arr, len(ops)), "gv_apply_ops")
     rc = g.sync()
     el = time.perf_counter() - t0
-    g.close()
     if rc != 0:
         raise RuntimeError(f"batched form: {gv.gv_strerror(rc)}")
+    want = digest(g)
+    g.close()
+    # recorded: the same sequence as one HIP graph (recording not timed)
+    g = fresh()
+    gv.gv_apply_ops(g.h, ops[:1])
+    plan = gv.Plan(g.h, ops, dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.launch()
+    rc = g.sync()
+    el_plan = time.perf_counter() - t0
+    plan.close()
+    if rc != 0:
+        raise RuntimeError(f"batched form (plan): {gv.gv_strerror(rc)}")
+    got = digest(g)
+    g.close()
+    if got != want:
+        raise RuntimeError(f"batched form: plan {got} and eager {want} results differ")
     return {"workload": f"rmat{scale} {edges} edges, B={B}, {nbatch} batches of log-uniform "
                         "size in [1e2, 1e6], 45/45/10 insert/delete/vertex",
             "pairs": pairs, "vertex_ids": vids, "ms": round(el * 1e3, 3),
-            "edges_per_s": round(pairs / el, 1), "form": "one launch sequence per batch"}
+            "edges_per_s": round(pairs / el, 1), "form": "one launch sequence per batch",
+            "plan_ms": round(el_plan * 1e3, 3),
+            "plan_edges_per_s": round(pairs / el_plan, 1),
+            "plan_form": "the same sequence recorded as one HIP graph",
+            "plan_matches_eager": True, "checksum": want[0], "edges_after": want[1]}
 
 
 def main():
@@ -279,9 +316,8 @@ def main():
     ap.add_argument("--edges", type=int, default=1 << 24)
     ap.add_argument("--queries", type=int, default=5, help="timed query batches")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--batched", action="store_true",
-                    help="also run the batched-form workload (off: its one run ended in a "
-                         "device fault whose cause is not found yet)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-form workload (eager and recorded forms)")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "OUT_MD"),
                     help="write a kernel-trace summary (no GPU)")
     ap.add_argument("--summarize-traffic", nargs=5,
@@ -454,7 +490,7 @@ def main():
     g.close()
 
     # ---- batched form on its own workload
-    batched = batched_form(gv, I, T, dev, B) if args.batched else None
+    batched = None if args.no_batched else batched_form(gv, I, T, dev, B)
 
     # ---- CPU oracle baseline on a quarter of the sources
     cpu = None
