@@ -367,7 +367,8 @@ def main():
     log(f"generating R-MAT 2^{args.scale} / {args.edges} edges on the GPU")
     w = T.RmatWorkload(args.scale, args.edges, device=dev)
     n = w.num_vertices
-    nsteps = args.warmup + 1 + args.steps
+    # warm-up, pilot, timed steps, then as many steps again with events
+    nsteps = args.warmup + 1 + 2 * args.steps
     ins = [w.insert_batch(k, j) for j in range(nsteps)]
     dels = [w.delete_batch(k, j) for j in range(nsteps)]
     qry = [w.query_batch(k, j) for j in range(args.queries + 1)]
@@ -406,21 +407,33 @@ def main():
     dominant = max(pilot, key=lambda x: pilot[x]["ms"])
     log("pilot step kernels:", json.dumps(pilot))
 
-    # ---- timed region: steps of insert + delete; events around the dominant
-    # kernel only
-    gv.gv_profile_only(h, dominant)
-    gv.gv_profile_reset(h)
+    # ---- timed region: steps of insert + delete, no events (an event record
+    # between two kernels costs about 5 us of GPU time)
+    gv.gv_profile_enable(h, False)
     c0 = g.counters()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for j in range(args.warmup + 1, nsteps):
+    first = args.warmup + 1
+    for j in range(first, first + args.steps):
         gv.gv_insert_edges(h, *ins[j], dev, stats=False)
         gv.gv_delete_edges(h, *dels[j], dev, stats=False)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    c1 = g.counters()
+    # ---- the same number of steps again, with HIP events around every launch
+    # of the dominant kernel on the graph's stream (roofline entry)
+    gv.gv_profile_enable(h, True)
+    gv.gv_profile_only(h, dominant)
+    gv.gv_profile_reset(h)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for j in range(first + args.steps, nsteps):
+        gv.gv_insert_edges(h, *ins[j], dev, stats=False)
+        gv.gv_delete_edges(h, *dels[j], dev, stats=False)
+    torch.cuda.synchronize()
+    elapsed_ev = time.perf_counter() - t1
     dom_launches, dom_ms = gv.gv_kernel_times(h, dominant)
     gv.gv_profile_enable(h, False)
-    c1 = g.counters()
     rc = g.sync()
     if rc != 0:
         raise RuntimeError(f"batch error during timed steps: {gv.gv_strerror(rc)}")
@@ -455,7 +468,10 @@ def main():
         roof = {"bound": "hbm", "kernel": dominant, "achieved": round(ach, 2),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5),
                 "traffic": stored_traffic(dominant), "bytes_per_launch": int(bpl),
-                "avg_launch_us": round(avg_s * 1e6, 3), "launches": dom_launches}
+                "avg_launch_us": round(avg_s * 1e6, 3), "launches": dom_launches,
+                "timed_steps": "a second run of the same number of steps, right after the "
+                               "timed region, with HIP events around every launch of the "
+                               "kernel (%.4f ms per step with the events)" % (elapsed_ev / K * 1e3)}
 
     # ---- queries, in their own loop
     gv.gv_edge_exists(h, *qry[0], dev)
