@@ -114,6 +114,18 @@ extern "C" int orc_graph_init(orc_graph** out, uint64_t num_vertices,
 
 extern "C" void orc_graph_destroy(orc_graph* g) { delete g; }
 
+extern "C" int orc_apply_edge_ops(orc_graph* g, const uint8_t* op, const uint32_t* src,
+                                  const uint32_t* dst, uint64_t n) {
+    if (!g || (n && (!op || !src || !dst))) return ORC_EINVAL;
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint32_t u = src[i], v = dst[i];
+        if (!valid_vertex(g, u) || !valid_vertex(g, v)) continue;
+        if (op[i] == 0) g->adj[u].insert(v);
+        else if (op[i] == 1) g->adj[u].erase(v);
+    }
+    return ORC_OK;
+}
+
 extern "C" int orc_insert_edges(orc_graph* g, const uint32_t* src,
                                 const uint32_t* dst, uint64_t n,
                                 orc_stats* stats) {

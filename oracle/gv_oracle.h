@@ -78,6 +78,15 @@ int orc_insert_edges(orc_graph* g, const uint32_t* src, const uint32_t* dst,
 int orc_delete_edges(orc_graph* g, const uint32_t* src, const uint32_t* dst,
                      uint64_t n, orc_stats* stats);
 
+/* Mixed edge updates (the tick of the served form; the order inside a batch
+ * is ours, the batch model is Sec. 4.3): entry i inserts (op[i] == 0) or
+ * deletes (op[i] == 1) the pair (src[i], dst[i]), the entries applied one at
+ * a time in index order with set semantics.  An entry with an inactive or
+ * out-of-range endpoint, or another op value, changes nothing.  The pool
+ * bound is not checked. */
+int orc_apply_edge_ops(orc_graph* g, const uint8_t* op, const uint32_t* src,
+                       const uint32_t* dst, uint64_t n);
+
 /* Batched vertex operations (Sec. 4.4).  Insert activates inactive ids,
  * growing the capacity to next_pow2(id + 1) when needed; ids > 2^31 - 1 are
  * rejected.  Delete removes every out- and in-edge of each active id and

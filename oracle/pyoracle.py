@@ -49,6 +49,8 @@ def lib():
             f = getattr(L, name)
             f.restype = C.c_int
             f.argtypes = [C.c_void_p, u32p, u32p, C.c_uint64, C.POINTER(Stats)]
+        L.orc_apply_edge_ops.restype = C.c_int
+        L.orc_apply_edge_ops.argtypes = [C.c_void_p, u8p, u32p, u32p, C.c_uint64]
         for name in ("orc_insert_vertices", "orc_delete_vertices"):
             f = getattr(L, name)
             f.restype = C.c_int
@@ -139,6 +141,17 @@ class OracleGraph:
 
     def delete_edges(self, src, dst):
         return self._edges(lib().orc_delete_edges, src, dst)
+
+    def apply_edge_ops(self, op, src, dst):
+        """Entry i inserts (op 0) or deletes (op 1) (src[i], dst[i]), one at a
+        time in order.  Returns rc."""
+        o = np.ascontiguousarray(np.asarray(op, dtype=np.uint8))
+        s, sp = _u32(src)
+        d, dp = _u32(dst)
+        if not (len(o) == len(s) == len(d)):
+            raise ValueError("op/src/dst length mismatch")
+        return lib().orc_apply_edge_ops(self._h, o.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                        sp, dp, len(s))
 
     def _verts(self, fn, ids):
         a, ap = _u32(ids)

@@ -266,3 +266,73 @@ def test_invariants_symmetry_lattice():
         assert g.degree(x) == 0 and not g.is_active(x)
     o, t, _ = g.dump()
     assert not np.isin(t, [5, 77, 500]).any()
+
+
+@pytest.mark.parametrize("n,seed", [(16, 11), (64, 12), (200, 13)])
+def test_mixed_edge_ops_match_one_pair_at_a_time(n, seed):
+    """orc_apply_edge_ops against the bitset brute force fed one pair per
+    call, in list order (insert and delete of single pairs), with repeated
+    pairs, inactive and out-of-range endpoints and unknown op values."""
+    rng = np.random.default_rng(seed)
+    s0 = rng.integers(0, n, 3 * n).astype(np.uint32)
+    d0 = rng.integers(0, n, 3 * n).astype(np.uint32)
+    o = O.OracleGraph(n, s0, d0, vertex_capacity=2 * n, block_slots=4)
+    b = BruteGraph(n, s0, d0, vertex_capacity=2 * n, block_slots=4)
+    dead = rng.choice(n, n // 8, replace=False).astype(np.uint32)
+    o.delete_vertices(dead)
+    b.delete_vertices(dead)
+    for rep in range(6):
+        m = int(rng.integers(1, 4 * n))
+        few = rng.integers(0, n, (8, 2))  # a few pairs that recur in the list
+        s = rng.integers(0, 2 * n + 3, m).astype(np.uint32)
+        d = rng.integers(0, 2 * n + 3, m).astype(np.uint32)
+        k = rng.integers(0, 8, m)
+        rec = rng.random(m) < 0.5
+        s[rec], d[rec] = few[k[rec], 0], few[k[rec], 1]
+        op = rng.choice(np.array([0, 1, 2], np.uint8), m, p=[0.45, 0.45, 0.1])
+        assert o.apply_edge_ops(op, s, d) == O.OK
+        for i in range(m):
+            if op[i] == 0:
+                b.insert_edges(s[i:i + 1], d[i:i + 1])
+            elif op[i] == 1:
+                b.delete_edges(s[i:i + 1], d[i:i + 1])
+        _compare(o, b)
+
+
+def _compare_graphs(a, c):
+    ao, ad, ack = a.dump()
+    co, cd, cck = c.dump()
+    np.testing.assert_array_equal(ao, co)
+    np.testing.assert_array_equal(ad, cd)
+    assert ack == cck and a.blocks_in_use == c.blocks_in_use
+
+
+def test_mixed_edge_ops_last_writer_closed_form(rmat_small):
+    """Each pair ends stored iff its last entry is an insert; all-insert and
+    all-delete lists equal the batch operations."""
+    s0, d0 = rmat_small
+    n = 1 << 12
+    rng = np.random.default_rng(5)
+    o = O.OracleGraph(n, s0, d0, block_slots=8)
+    m = 3000
+    pick = rng.integers(0, len(s0), m)
+    s = np.where(rng.random(m) < 0.5, s0[pick], rng.integers(0, n, m)).astype(np.uint32)
+    d = np.where(rng.random(m) < 0.5, d0[pick], rng.integers(0, n, m)).astype(np.uint32)
+    op = rng.integers(0, 2, m).astype(np.uint8)
+    before = o.edge_exists(s, d)
+    last = {}
+    for i in range(m):
+        last[(int(s[i]), int(d[i]))] = int(op[i])
+    o.apply_edge_ops(op, s, d)
+    after = o.edge_exists(s, d)
+    for i in range(m):
+        assert after[i] == (1 if last[(int(s[i]), int(d[i]))] == 0 else 0)
+    assert before.sum() > 0
+    a = O.OracleGraph(n, s0, d0, block_slots=8)
+    c = O.OracleGraph(n, s0, d0, block_slots=8)
+    a.apply_edge_ops(np.zeros(m, np.uint8), s, d)
+    c.insert_edges(s, d)
+    _compare_graphs(a, c)
+    a.apply_edge_ops(np.ones(m, np.uint8), s, d)
+    c.delete_edges(s, d)
+    _compare_graphs(a, c)
