@@ -305,6 +305,81 @@ def batched_form(gv, I, T, dev, B, scale=22, edges=1 << 26, nbatch=256, seed_nam
             "plan_matches_eager": True, "checksum": want[0], "edges_after": want[1]}
 
 
+def served_form(gv, I, T, dev, B, scale=24, edges=1 << 28, nreq=1500, loads=(0.3, 0.6, 0.9),
+                seed_name="served"):
+    """The served form: requests of log-uniform size in [1, 10^5] pairs, 40 %
+    edge inserts (R-MAT pairs), 40 % edge deletes (80 % stored pairs), 15 %
+    queries (half stored pairs), 5 % vertex batches (min(size, 10^4) ids,
+    insert or delete alike), served by continuous batching (ticks of at most
+    2^20 pairs; one mixed update list and one query batch per tick; vertex
+    requests alone).  Saturated throughput: every request available at time
+    0.  Then open-loop Poisson arrivals at `loads` x that throughput, a fresh
+    request list each; latency = completion - scheduled arrival, p50 / p99
+    by nearest rank."""
+    import numpy as np
+    import torch
+    from paper_2306_08252_amd import served as S
+    w = T.RmatWorkload(scale, edges, name=seed_name, device=dev)
+    n = w.num_vertices
+
+    def requests(tag):
+        draws = I.splitmix64(I.stream_seed(seed_name, "requests", tag), 3 * nreq)
+        base = 1_000_000 * (1 + ["warm", "saturated", *(f"load{x}" for x in loads)].index(tag))
+        reqs = []
+        for j in range(nreq):
+            u = float(draws[3 * j] >> np.uint64(11)) / float(1 << 53)
+            size = max(1, int(round(np.exp(u * np.log(10**5)))))
+            r = float(draws[3 * j + 1] >> np.uint64(11)) / float(1 << 53)
+            if r < 0.40:
+                reqs.append((S.INSERT,) + tuple(w.insert_batch(size, base + j)))
+            elif r < 0.80:
+                ne = int(round(0.8 * size))
+                es, ed = T.pick(I.stream_seed(seed_name, "del", tag, j), ne, w.src, w.dst)
+                us, ud = T.uniform_pairs(I.stream_seed(seed_name, "del-u", tag, j), size - ne, n,
+                                         device=dev)
+                reqs.append((S.DELETE, torch.cat([es, us]), torch.cat([ed, ud])))
+            elif r < 0.95:
+                qe = size // 2
+                es, ed = T.pick(I.stream_seed(seed_name, "q", tag, j), qe, w.src, w.dst)
+                us, ud = T.uniform_pairs(I.stream_seed(seed_name, "q-u", tag, j), size - qe, n,
+                                         device=dev)
+                reqs.append((S.QUERY, torch.cat([es, us]), torch.cat([ed, ud])))
+            else:
+                m = min(size, 10**4)
+                ids = torch.from_numpy((I.splitmix64(I.stream_seed(seed_name, "v", tag, j), m)
+                                        % np.uint64(n)).astype(np.uint32).view(np.int32)).to(dev)
+                kind = S.VINSERT if draws[3 * j + 2] & np.uint64(1) else S.VDELETE
+                reqs.append((kind, ids, None))
+        return reqs
+
+    g = gv.Graph(n, w.src, w.dst, block_slots=B, device=dev)
+    warm = requests("warm")
+    S.serve(g, warm[:64])
+    sat_reqs = requests("saturated")
+    torch.cuda.synchronize()
+    done, ticks, _ = S.serve(g, sat_reqs)
+    sat = nreq / done[-1]
+    out = {"workload": f"rmat{scale} {edges} edges, B={B}, {nreq} requests per run of "
+                       "log-uniform size in [1, 1e5], 40/40/15/5 insert/delete/query/vertex",
+           "saturated_req_per_s": round(sat, 1), "saturated_ticks": len(ticks), "runs": []}
+    for load in loads:
+        reqs = requests(f"load{load}")
+        draws = I.splitmix64(I.stream_seed(seed_name, "arrivals", load), nreq)
+        arr = S.poisson_arrivals(draws, load * sat)
+        torch.cuda.synchronize()
+        done, ticks, _ = S.serve(g, reqs, arr)
+        lat = (done - arr) * 1e3
+        out["runs"].append({"load": load, "offered_req_per_s": round(load * sat, 1),
+                            "p50_ms": round(S.nearest_rank(lat, 0.5), 3),
+                            "p99_ms": round(S.nearest_rank(lat, 0.99), 3),
+                            "ticks": len(ticks), "span_s": round(float(done[-1]), 3)})
+    rc = g.sync()
+    g.close()
+    if rc != 0:
+        raise RuntimeError(f"served form: {gv.gv_strerror(rc)}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -318,6 +393,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-form workload (eager and recorded forms)")
+    ap.add_argument("--no-served", action="store_true",
+                    help="skip the served-form workload (continuous batching, p50/p99)")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "OUT_MD"),
                     help="write a kernel-trace summary (no GPU)")
     ap.add_argument("--summarize-traffic", nargs=5,
@@ -507,6 +584,7 @@ def main():
 
     # ---- batched form on its own workload
     batched = None if args.no_batched else batched_form(gv, I, T, dev, B)
+    served = None if args.no_served else served_form(gv, I, T, dev, B)
 
     # ---- CPU oracle baseline on a quarter of the sources
     cpu = None
@@ -562,7 +640,7 @@ def main():
         "memory": {"live_bytes": mem["live_bytes"], "blocks_in_use": mem["blocks_in_use"],
                    "num_edges": mem["num_edges"]},
         "batched_form": batched,
-        "served_p50_p99": None,
+        "served_p50_p99": served,
         "pilot_kernels_ms": pilot,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -152,6 +152,20 @@ int gv_insert_vertices(gv_graph* g, const uint32_t* d_ids, uint64_t n,
 int gv_delete_vertices(gv_graph* g, const uint32_t* d_ids, uint64_t n,
                        gv_batch_stats* stats_or_null);
 
+/* Mixed edge updates, the tick of the served form: entry i inserts
+ * (d_op[i] == 0) or deletes (d_op[i] == 1) the pair (d_src[i], d_dst[i]).
+ * The graph ends as if the entries were applied one at a time in index
+ * order with set semantics (the batch model of Sec. 4.3 with an order inside
+ * the batch, ours): each pair's last entry decides whether it is stored;
+ * entries with an inactive or out-of-range endpoint, or another op value,
+ * change nothing.  All three arrays are device arrays of n entries, read
+ * only.  Asynchronous, no statistics; an allocation failure is sticky
+ * (reported by gv_sync) and leaves a consistent graph in which the delete
+ * part may have been applied.  GV_EINVAL for null arrays with n > 0 or
+ * n >= 2^30. */
+int gv_apply_edge_ops(gv_graph* g, const uint8_t* d_op, const uint32_t* d_src,
+                      const uint32_t* d_dst, uint64_t n);
+
 /* Edge query (Sec. 4.6, Alg. 3), batched: d_out[i] = 1 if edge
  * (d_src[i], d_dst[i]) exists, else 0, in input order.  Asynchronous. */
 int gv_edge_exists(gv_graph* g, const uint32_t* d_src, const uint32_t* d_dst,

@@ -196,6 +196,14 @@ int gv_edge_exists(gv_graph* g, const uint32_t* d_src, const uint32_t* d_dst, ui
     return guarded(g, [&] { edge_batch(g, kQuery, d_src, d_dst, n, d_out, true); });
 }
 
+int gv_apply_edge_ops(gv_graph* g, const uint8_t* d_op, const uint32_t* d_src,
+                      const uint32_t* d_dst, uint64_t n) {
+    if (!g) return GV_EINVAL;
+    if (n && (!d_op || !d_src || !d_dst)) return GV_EINVAL;
+    if (n == 0) return GV_OK;
+    return guarded(g, [&] { mixed_edges(g, d_op, d_src, d_dst, n); });
+}
+
 int gv_get_adjacency(gv_graph* g, uint32_t v, uint32_t* d_out, uint64_t out_capacity,
                      uint64_t* degree) {
     if (!g || !degree) return GV_EINVAL;

@@ -34,6 +34,12 @@ enum EdgeMode { kInsert = 0, kDelete = 1, kQuery = 2 };
 void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t* dst,
                 uint64_t n, uint8_t* out, bool sticky);
 
+// a list of (op, src, dst) entries, op 0 insert / 1 delete, applied as if one
+// at a time in list order (last-writer reduction, then one delete batch and
+// one insert batch; no host sync)
+void mixed_edges(gv_graph* g, const uint8_t* op, const uint32_t* src, const uint32_t* dst,
+                 uint64_t n);
+
 // occupancy queries made ahead of a recording
 void edge_batch_warm();
 void vertex_batch_warm();

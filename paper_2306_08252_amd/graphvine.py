@@ -95,6 +95,7 @@ def lib():
             "gv_insert_vertices": [vp, u32p, C.c_uint64, C.POINTER(gv_batch_stats)],
             "gv_delete_vertices": [vp, u32p, C.c_uint64, C.POINTER(gv_batch_stats)],
             "gv_edge_exists": [vp, u32p, u32p, C.c_uint64, vp],
+            "gv_apply_edge_ops": [vp, vp, u32p, u32p, C.c_uint64],
             "gv_get_adjacency": [vp, C.c_uint32, u32p, C.c_uint64, u64p],
             "gv_memory_used": [vp, C.POINTER(gv_mem)],
             "gv_dump_canonical": [vp, vp, u32p, C.c_uint64, u64p, u64p],
@@ -227,6 +228,30 @@ def gv_edge_exists(g, src, dst, device="cuda:0", out=None):
     _check(lib().gv_edge_exists(C.c_void_p(g), _ptr(s), _ptr(d), s.numel(), _ptr(out)),
            "gv_edge_exists")
     return out
+
+
+def as_device_u8(x, device) -> torch.Tensor:
+    """A contiguous uint8 tensor holding x on `device`."""
+    if isinstance(x, torch.Tensor):
+        if x.dtype != torch.uint8:
+            raise TypeError("op tensors must be uint8")
+        if x.device != torch.device(device):
+            raise ValueError(f"tensor on {x.device}, graph on {device}")
+        return x.contiguous()
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(x, dtype=np.uint8))).to(device)
+
+
+def gv_apply_edge_ops(g, op, src, dst, device="cuda:0"):
+    """Entry i inserts (op 0) or deletes (op 1) (src[i], dst[i]); the result is
+    that of applying the entries one at a time in order.  Asynchronous."""
+    o = as_device_u8(op, device)
+    s = as_device_u32(src, device)
+    d = as_device_u32(dst, device)
+    if not (o.numel() == s.numel() == d.numel()):
+        raise ValueError("op/src/dst length mismatch")
+    _check(lib().gv_apply_edge_ops(C.c_void_p(g), _ptr(o), _ptr(s), _ptr(d), s.numel()),
+           "gv_apply_edge_ops")
+    return o, s, d
 
 
 def gv_get_adjacency(g, v, device="cuda:0", out=None):
@@ -365,6 +390,9 @@ class Graph:
 
     def edge_exists(self, src, dst, out=None):
         return gv_edge_exists(self.h, src, dst, self.device, out)
+
+    def apply_edge_ops(self, op, src, dst):
+        return gv_apply_edge_ops(self.h, op, src, dst, self.device)
 
     def get_adjacency(self, v):
         return gv_get_adjacency(self.h, v, self.device)

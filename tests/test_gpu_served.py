@@ -1,0 +1,106 @@
+"""Served form: mixed update lists (gv_apply_edge_ops) and continuous-batching
+ticks against the oracle.
+
+Bar: bit-exact.  A mixed list must leave the graph the oracle leaves after
+applying its entries one at a time; a served run must give every query the
+answer of the oracle replaying the server's commit order (each tick's writes
+in arrival order, then its queries) and end in the same graph.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import assert_same, need_gpu, say
+from oracle import pyoracle as O
+from paper_2306_08252_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def mixed_list(rng, n, m, s0, d0, few=16):
+    """Entries with recurring pairs, stored pairs, out-of-range ids and
+    unknown op values."""
+    s = rng.integers(0, 2 * n + 3, m).astype(np.uint32)
+    d = rng.integers(0, 2 * n + 3, m).astype(np.uint32)
+    hot = rng.integers(0, n, (few, 2))
+    k = rng.integers(0, few, m)
+    rec = rng.random(m) < 0.4
+    s[rec], d[rec] = hot[k[rec], 0], hot[k[rec], 1]
+    pk = rng.integers(0, len(s0), m)
+    ex = rng.random(m) < 0.3
+    s[ex], d[ex] = s0[pk[ex]], d0[pk[ex]]
+    op = rng.choice(np.array([0, 1, 2], np.uint8), m, p=[0.45, 0.45, 0.1])
+    return op, s, d
+
+
+@pytest.mark.parametrize("n,B,seed", [(300, 4, 1), (5000, 16, 2), (1 << 14, 8, 3)])
+def test_mixed_lists_match_oracle(n, B, seed):
+    gv = need_gpu()
+    rng = np.random.default_rng(seed)
+    s0 = rng.integers(0, n, 6 * n).astype(np.uint32)
+    d0 = rng.integers(0, n, 6 * n).astype(np.uint32)
+    g = gv.Graph(n, s0, d0, block_slots=B, vertex_capacity=2 * n)
+    o = O.OracleGraph(n, s0, d0, block_slots=B, vertex_capacity=2 * n)
+    dead = rng.choice(n, n // 10, replace=False).astype(np.uint32)
+    g.delete_vertices(dead)
+    o.delete_vertices(dead)
+    for rep, m in enumerate([1, 2, 63, 65, 4097, 3 * n]):
+        op, s, d = mixed_list(rng, n, m, s0, d0)
+        say(f"mixed n={n} B={B} m={m}")
+        g.apply_edge_ops(op, s, d)
+        assert g.sync() == 0
+        o.apply_edge_ops(op, s, d)
+        assert_same(g, o, f"mixed rep {rep} m {m}")
+    g.close()
+
+
+def test_served_ticks_match_oracle_replay():
+    gv = need_gpu()
+    from paper_2306_08252_amd import served as S
+    scale, m, B = 12, 1 << 16, 8
+    n = 1 << scale
+    s0, d0 = I.rmat_graph(I.stream_seed("served-test", scale), scale, m)
+    g = gv.Graph(n, s0, d0, block_slots=B, vertex_capacity=n)
+    o = O.OracleGraph(n, s0, d0, block_slots=B, vertex_capacity=n)
+    rng = np.random.default_rng(8)
+    dev = g.device
+    reqs, host = [], []
+    for j in range(120):
+        kind = int(rng.choice(5, p=[0.35, 0.35, 0.2, 0.05, 0.05]))
+        size = int(np.exp(rng.random() * np.log(3000))) + 1
+        if kind in (S.VINSERT, S.VDELETE):
+            ids = rng.integers(0, n, min(size, 40)).astype(np.uint32)
+            host.append((kind, ids, None))
+        else:
+            pk = rng.integers(0, len(s0), size)
+            s = np.where(rng.random(size) < 0.6, s0[pk], rng.integers(0, n, size)).astype(np.uint32)
+            d = np.where(rng.random(size) < 0.6, d0[pk], rng.integers(0, n, size)).astype(np.uint32)
+            host.append((kind, s, d))
+    for kind, a, b in host:
+        ta = torch.from_numpy(a.view(np.int32)).to(dev)
+        tb = None if b is None else torch.from_numpy(b.view(np.int32)).to(dev)
+        reqs.append((kind, ta, tb))
+    done, ticks, answers = S.serve(g, reqs, None, max_tick_pairs=6000, keep_answers=True)
+    say(f"{len(reqs)} requests in {len(ticks)} ticks")
+    assert len(ticks) > 10 and max(e - f for f, e in ticks) > 2  # ticks do mix requests
+    for f, e in ticks:
+        kinds = [host[i][0] for i in range(f, e)]
+        if kinds[0] in (S.VINSERT, S.VDELETE):
+            assert e == f + 1
+            if kinds[0] == S.VINSERT:
+                o.insert_vertices(host[f][1])
+            else:
+                o.delete_vertices(host[f][1])
+            continue
+        ws = [host[i] for i in range(f, e) if host[i][0] in (S.INSERT, S.DELETE)]
+        if ws:
+            op = np.concatenate([np.full(len(w[1]), w[0], np.uint8) for w in ws])
+            o.apply_edge_ops(op, np.concatenate([w[1] for w in ws]),
+                             np.concatenate([w[2] for w in ws]))
+        for i in range(f, e):
+            if host[i][0] == S.QUERY:
+                np.testing.assert_array_equal(answers[i], o.edge_exists(host[i][1], host[i][2]),
+                                              err_msg=f"query {i}")
+    assert_same(g, o, "after the served run")
+    assert np.all(np.diff(done) >= 0)
+    g.close()
