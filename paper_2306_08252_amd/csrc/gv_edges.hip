@@ -57,6 +57,7 @@ constexpr int kStage = 1 << kStageLog;         // segment entries staged in LDS
 constexpr int kWinLog = 12;                    // unrolled global search steps
 constexpr int kUnroll = GV_PROBE_UNROLL;       // slots per lane per step
 constexpr uint32_t kBigR = 256;                // deletes per source handled by a workgroup
+constexpr uint32_t kBigGroups = 256;           // workgroups for those sources
 constexpr uint32_t kLaneCopy = 8;              // directory entries a lane copies or adds
 constexpr uint32_t kLaneSeg = 8;               // segment entries a lane compacts
 constexpr uint32_t kLaneR = 4;                 // hits a lane compacts
@@ -1106,18 +1107,20 @@ struct FreedOut {
 // slot order), and emptied blocks go on the free list.  A lane takes a source
 // with at most kLaneR hits and a short segment; the others are taken by the
 // whole wave in turn.
-__global__ __launch_bounds__(kThreads) void k_compact(GraphView g, const uint8_t* mark,
-                                                      const uint32_t* hitpos, uint32_t* holes,
-                                                      const CDesc* cdesc, const uint32_t* mid) {
+__device__ __forceinline__ void compact_body(const GraphView& g, const uint8_t* mark,
+                                             const uint32_t* hitpos, uint32_t* holes,
+                                             const CDesc* cdesc, const uint32_t* mid,
+                                             uint32_t vb, uint32_t vg) {
+    const uint32_t gwave = (vb * kThreads + threadIdx.x) >> 6;
     const DevCounters* c = g.ctr;
     const uint32_t nT = (uint32_t)c->tot[kTotSeg];
     const uint32_t lane = lane_id();
     const uint64_t below = (1ull << lane) - 1;
-    const uint32_t stride = gridDim.x * kThreads;
+    const uint32_t stride = vg * kThreads;
     const unsigned long long fbase = c->free_cnt;
     const uint32_t bm = g.B - 1;
     unsigned long long moved = 0;
-    for (uint32_t base = global_wave() * 64; base < nT; base += stride) {
+    for (uint32_t base = gwave * 64; base < nT; base += stride) {
         const bool live = base + lane < nT;
         const CDesc D = cdesc[live ? base + lane : nT - 1];
         if (live && D.r && lane_compactable(D.r, D.lo, D.hi)) {
@@ -1182,8 +1185,8 @@ __global__ __launch_bounds__(kThreads) void k_compact(GraphView g, const uint8_t
     // sources with more hits or longer segments, listed by the freed scan:
     // one wave each
     const uint32_t nmid = (uint32_t)(c->tot[kTotB] >> 32);
-    const uint32_t nw = gridDim.x * kWaves;
-    for (uint32_t k = global_wave(); k < nmid; k += nw) {
+    const uint32_t nw = vg * kWaves;
+    for (uint32_t k = gwave; k < nmid; k += nw) {
         {
             const CDesc H = cdesc[mid[k]];
             const VRec rec{H.deg, H.dir, H.dcls, 0u};
@@ -1232,21 +1235,21 @@ __global__ __launch_bounds__(kThreads) void k_compact(GraphView g, const uint8_t
         }
     }
     moved = wave_sum(moved);
-    if (lane == 0 && moved) atomicAdd(&g.ctr->stripe[global_wave() & 63][0], moved);
+    if (lane == 0 && moved) atomicAdd(&g.ctr->stripe[gwave & 63][0], moved);
 }
 
 // One workgroup per source with more than kBigR hits (hubs), same pairing.
-__global__ __launch_bounds__(kThreads) void k_compact_big(GraphView g, const uint8_t* mark,
-                                                          const uint32_t* hitpos, uint32_t* holes,
-                                                          const CDesc* cdesc,
-                                                          const uint32_t* big) {
+__device__ __forceinline__ void compact_big_body(const GraphView& g, const uint8_t* mark,
+                                                 const uint32_t* hitpos, uint32_t* holes,
+                                                 const CDesc* cdesc, const uint32_t* big,
+                                                 uint32_t vb, uint32_t vg) {
     __shared__ uint32_t lds[kWaves];
     const DevCounters* c = g.ctr;
     const uint32_t nbig = c->n_big;
     const unsigned long long fbase = c->free_cnt;
     const uint32_t tid = threadIdx.x;
     unsigned long long moved = 0;
-    for (uint32_t q = blockIdx.x; q < nbig; q += gridDim.x) {
+    for (uint32_t q = vb; q < nbig; q += vg) {
         const CDesc D = cdesc[big[q]];
         const VRec rec{D.deg, D.dir, D.dcls, 0u};
         const uint32_t d = D.deg, dn = d - D.r;
@@ -1294,8 +1297,21 @@ __global__ __launch_bounds__(kThreads) void k_compact_big(GraphView g, const uin
         }
         __syncthreads();
     }
-    if (tid == 0 && moved) atomicAdd(&g.ctr->stripe[blockIdx.x & 63][0], moved);
+    if (tid == 0 && moved) atomicAdd(&g.ctr->stripe[vb & 63][0], moved);
 }
+
+// Both compactions in one launch: the first nbig workgroups take the hubs
+// (they run longest, so they start first), the rest the other sources.
+__global__ __launch_bounds__(kThreads) void k_compact(GraphView g, const uint8_t* mark,
+                                                      const uint32_t* hitpos, uint32_t* holes,
+                                                      const CDesc* cdesc, const uint32_t* mid,
+                                                      const uint32_t* big, uint32_t nbig) {
+    if (blockIdx.x < nbig)
+        compact_big_body(g, mark, hitpos, holes, cdesc, big, blockIdx.x, nbig);
+    else
+        compact_body(g, mark, hitpos, holes, cdesc, mid, blockIdx.x - nbig, gridDim.x - nbig);
+}
+
 
 __global__ void k_final_del(GraphView g, uint64_t n) {
     DevCounters* c = g.ctr;
@@ -1441,13 +1457,11 @@ void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t*
         scan2(c, "found", FoundIn{A.mark, n_valid}, U32Out{A.b}, n + 1, A.part, &tot[kTotA]);
         scan2(c, "freed", FreedIn{v, A.t_vtx, A.t_start, A.b},
               FreedOut{ctr, A.cdesc, A.big, A.heavy}, n, A.part, &tot[kTotB]);
-        c.launch("compact_big", k_compact_big, 256, kThreads, v, (const uint8_t*)A.mark,
-                 (const uint32_t*)A.hitpos, A.holes, (const CDesc*)A.cdesc,
-                 (const uint32_t*)A.big);
+        const uint32_t nbig = kBigGroups;
         c.launch("compact", k_compact,
-                 std::min<uint64_t>(div_up(n, kThreads), resident_grid(k_compact, kThreads)), kThreads, v,
-                 (const uint8_t*)A.mark, (const uint32_t*)A.hitpos, A.holes, (const CDesc*)A.cdesc,
-                 (const uint32_t*)A.heavy);
+                 nbig + std::min<uint64_t>(div_up(n, kThreads), resident_grid(k_compact, kThreads)),
+                 kThreads, v, (const uint8_t*)A.mark, (const uint32_t*)A.hitpos, A.holes,
+                 (const CDesc*)A.cdesc, (const uint32_t*)A.heavy, (const uint32_t*)A.big, nbig);
         c.launch("final_delete", k_final_del, 1, 1, v, n);
     } else {
         c.launch("probe_query", k_probe<kQuery>, pgrid_of(k_probe<kQuery>), kThreads, v, keys, (const Item*)A.items, (const Item*)A.small,
