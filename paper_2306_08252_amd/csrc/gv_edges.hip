@@ -793,22 +793,27 @@ struct NeedIn {
     }
 };
 
+__device__ __forceinline__ void plan_batch(const GraphView& g, uint64_t n, int sticky);
+
 struct NeedOut {
     uint32_t* t_need;
     uint32_t* rel;
+    GraphView g;
+    uint64_t n;
+    int sticky;
     __device__ void operator()(uint64_t t, const NeedIn::Rec& r, uint64_t lim,
                                unsigned long long pre) const {
         t_need[t] = (uint32_t)pre;
         if (t < lim && (r.need & kRelease)) rel[(uint32_t)(pre >> 32)] = (uint32_t)t;
     }
+    __device__ void finish() const { plan_batch(g, n, sticky); }
 };
 
-// Allocation plan for the whole batch, one thread: capacity is checked
-// before any state is written, so a failing batch leaves the graph unchanged.
 // Allocation plan for the whole batch, one wave (a lane per directory class):
 // capacity is checked before any state is written, so a failing batch leaves
-// the graph unchanged.
-__global__ __launch_bounds__(64) void k_plan(GraphView g, uint64_t n, int sticky) {
+// the graph unchanged.  Run by the first wave of the demand scan's last
+// workgroup, once the scan total (blocks needed) is written.
+__device__ __forceinline__ void plan_batch(const GraphView& g, uint64_t n, int sticky) {
     DevCounters* c = g.ctr;
     const uint32_t k = lane_id();
     const bool cl = k < kMaxClass;
@@ -1438,9 +1443,8 @@ void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t*
         c.launch("plan_insert", k_plan_ins, grid, kThreads, v, (const uint32_t*)A.t_vtx,
                  (const uint32_t*)A.t_start, (const uint32_t*)A.b, A.t_need, A.t_dreq, A.t_drank,
                  A.heavy);
-        scan2(c, "need", NeedIn{A.t_need, ctr}, NeedOut{A.t_need, A.rel}, n + 1, A.part,
-              &tot[kTotB]);
-        c.launch("plan", k_plan, 1, 64, v, n, (int)sticky);
+        scan2(c, "need", NeedIn{A.t_need, ctr}, NeedOut{A.t_need, A.rel, v, n, (int)sticky},
+              n + 1, A.part, &tot[kTotB]);
         c.launch("append", k_append, grid, kThreads, v, keys, (const uint8_t*)A.flags,
                  (const uint8_t*)A.mark, (const uint32_t*)A.a, (const uint32_t*)A.b,
                  (const uint32_t*)A.t_vtx, (const uint32_t*)A.t_start,

@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <type_traits>
+#include <utility>
 
 #include "gv_device.h"
 #include "gv_host.h"
@@ -371,6 +372,11 @@ template <typename In>
 struct scan2_items<In, std::void_t<decltype(In::kItems)>> {
     static constexpr int value = In::kItems;
 };
+template <typename Out, typename = void>
+struct scan2_has_finish : std::false_type {};
+template <typename Out>
+struct scan2_has_finish<Out, std::void_t<decltype(std::declval<const Out&>().finish())>>
+    : std::true_type {};
 constexpr int kScan2MinItems = 2;  // the fewest any source takes (scan2 checks it)
 
 template <typename In>
@@ -468,6 +474,14 @@ __global__ __launch_bounds__(kThreads) void k_scan2_apply(In in, Out out, uint64
         run += tot;
     }
     if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == kThreads - 1) *total = run;
+    if constexpr (scan2_has_finish<Out>::value) {
+        // a sink may finish the scan in its last workgroup: the first wave
+        // runs out.finish() once the total is written
+        if (blockIdx.x == gridDim.x - 1) {
+            __syncthreads();
+            if (threadIdx.x < 64) out.finish();
+        }
+    }
 }
 
 // tiles the apply kernel adds up itself; beyond, a middle kernel scans them
