@@ -104,3 +104,35 @@ def test_served_ticks_match_oracle_replay():
     assert_same(g, o, "after the served run")
     assert np.all(np.diff(done) >= 0)
     g.close()
+
+
+def test_mixed_list_past_the_pool_is_sticky_and_consistent():
+    """A mixed list whose inserts do not fit: gv_sync reports GV_ENOMEM once,
+    the deletes of the list are applied, the inserts are not, and the graph
+    stays consistent."""
+    gv = need_gpu()
+    rng = np.random.default_rng(9)
+    n, B = 64, 4
+    s0 = rng.integers(0, n, 100).astype(np.uint32)
+    d0 = rng.integers(0, n, 100).astype(np.uint32)
+    pool = 4 * B * 60
+    g = gv.Graph(n, s0, d0, block_slots=B, pool_bytes=pool)
+    o = O.OracleGraph(n, s0, d0, block_slots=B, pool_bytes=pool)
+    m = 600
+    s = rng.integers(0, n, m).astype(np.uint32)
+    d = rng.integers(0, n, m).astype(np.uint32)
+    op = (rng.random(m) < 0.2).astype(np.uint8)  # mostly inserts: past the pool
+    s[:40], d[:40], op[:40] = s0[:40], d0[:40], 1  # and some stored pairs deleted
+    last = {}
+    for i in range(m):
+        last[(int(s[i]), int(d[i]))] = int(op[i])
+    gone = [k for k, v in last.items() if v == 1]
+    g.apply_edge_ops(op, s, d)
+    with pytest.raises(gv.GraphVineError) as e:
+        gv._check(g.sync(), "gv_sync")
+    assert e.value.code == gv.GV_ENOMEM
+    assert g.sync() == 0  # reported once
+    o.delete_edges(np.array([k[0] for k in gone], np.uint32),
+                   np.array([k[1] for k in gone], np.uint32))
+    assert_same(g, o, "deletes applied, inserts not")
+    g.close()
