@@ -2,11 +2,14 @@
 //
 // One pipeline serves the three operations (GraphVine Sec. 4.5-4.6, Alg. 1-3,
 // re-designed for wave64):
-//   begin     clear the batch's look-back state and counters.
-//   pack      two-kernel scan: validate each pair against the activity
-//             bitmap and write the valid ones, compacted, as keys
-//             (src << L) | dst (queries also carry their input position and
-//             answer invalid pairs with 0 right away).
+//   pack      insert / delete: one kernel validates each pair against the
+//             activity bitmap and writes its key (src << L) | dst in place
+//             (an invalid pair gets the all-ones key, which sorts last),
+//             clears the batch's look-back state and counters and counts
+//             the sort's digits per workgroup.  Query: a kernel clears the
+//             state, then a two-kernel scan writes the valid pairs,
+//             compacted, with their input positions (invalid pairs are
+//             answered 0 right away).
 //   sort      onesweep LSD radix sort of the valid keys on 2L bits: the batch
 //             is grouped by source and ordered by destination inside each
 //             source segment (the paper's host CSR conversion, Sec. 4.3).
@@ -25,13 +28,16 @@
 //             Delete: mark hits, remember their slot, tombstone the slot.
 //             Query:  mark every query equal to a stored edge.
 //   insert:   keep = first occurrence and not present (scan); per-source
-//             block demand and directory growth; a one-wave plan checks
-//             capacity before any state is written (all-or-nothing); blocks
-//             come from the free-list top first, then the bump pointer (the
-//             prefix-sum pop of Sec. 4.5.1, without atomics); append.
+//             block demand and directory growth; a one-wave plan, run by the
+//             demand scan's last workgroup, checks capacity before any state
+//             is written (all-or-nothing); blocks come from the free-list top
+//             first, then the bump pointer (the prefix-sum pop of Sec. 4.5.1,
+//             without atomics); append; grow; old directory segments freed.
 //   delete:   per-source compaction pairs the holes below the new degree with
-//             the survivors above it, by rank; emptied blocks are pushed on
-//             the free list at scanned positions (reclamation, Sec. 4.2).
+//             the survivors above it, by rank (one launch: a workgroup per
+//             hub first, then lanes and waves for the other sources); emptied
+//             blocks are pushed on the free list at scanned positions
+//             (reclamation, Sec. 4.2).
 //   query:    answers are scattered back to input order.
 #include <algorithm>
 
