@@ -101,7 +101,7 @@ def bytes_model(name, per_launch):
         return 8 * T + 16 * T + 32 * T  # segment list, vertex records, items out
     if name == "append":
         return k + k + 4 * k + 4 * per_launch["W"] + 16 * T
-    if name in ("compact", "compact_big"):
+    if name == "compact":
         return 8 * per_launch["M"] + 16 * T + 4 * per_launch["FREED"]
     return None
 
@@ -528,7 +528,7 @@ def main():
     pct_m1 = m1 / elapsed / (HBM_PEAK_GBS * 1e9)
 
     # per-launch quantities of the dominant kernel's batch type
-    if dominant in ("probe_delete", "found", "freed", "compact", "compact_big", "final_delete"):
+    if dominant in ("probe_delete", "found", "freed", "compact", "final_delete"):
         per = {"k": k, "T": del_T / K, "S": del_S / K, "NB": del_S / K / B,
                "W": 0, "M": d["moved_slots"] / K, "FREED": d["freed_blocks"] / K}
     else:
