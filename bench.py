@@ -209,16 +209,47 @@ def summarize_traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, grid_wgs, ou
                 "while the sources match.\n\n" + "\n".join(lines) + "\n")
 
 
-def batched_form(gv, I, T, dev, B, scale=22, edges=1 << 26, nbatch=256, seed_name="batched"):
+def block_size_sweep(gv, w, dev, ks=(10**4, 10**5, 10**6), block_slots=(8, 16, 32, 64),
+                     steps=4):
+    """Insert + delete edges/s on the same R-MAT graph for every block size
+    and batch size (a fresh graph per block size; one untimed step, then
+    `steps` timed ones per batch size, in order of batch size)."""
+    import torch
+    out = []
+    for bs in block_slots:
+        g = gv.Graph(w.num_vertices, w.src, w.dst, block_slots=bs, device=dev)
+        for k in ks:
+            ins = [w.insert_batch(k, 90000 + j) for j in range(steps + 1)]
+            dels = [w.delete_batch(k, 90000 + j) for j in range(steps + 1)]
+            gv.gv_insert_edges(g.h, *ins[0], dev, stats=False)
+            gv.gv_delete_edges(g.h, *dels[0], dev, stats=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for j in range(1, steps + 1):
+                gv.gv_insert_edges(g.h, *ins[j], dev, stats=False)
+                gv.gv_delete_edges(g.h, *dels[j], dev, stats=False)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            out.append({"block_slots": bs, "batch": k,
+                        "edges_per_s": round(2 * k * steps / el, 1)})
+        rc = g.sync()
+        g.close()
+        if rc != 0:
+            raise RuntimeError(f"block-size sweep: {gv.gv_strerror(rc)}")
+    return out
+
+
+def batched_form(gv, I, T, dev, scale=22, edges=1 << 26, nbatch=256, seed_name="batched"):
     """The batched form: `nbatch` batches of log-uniform size in [10^2, 10^6],
     45 % edge inserts (R-MAT pairs), 45 % edge deletes (80 % stored pairs, 20 %
     uniform), 10 % vertex batches (min(size, 10^4) uniform ids, insert or
     delete alike), applied in order with gv_apply_ops (one launch sequence
-    per batch), then, on a second copy of the same graph, recorded into one
-    HIP graph (gv_plan_create, not timed) and launched once; both results
-    must have the same checksum and edge count.  Scratch is sized by a
-    warm-up insert and delete of the largest batch and a vertex delete and
-    re-insert before the timed passes."""
+    per batch) at block sizes 8, 16, 32 and 64 slots; the tuner keeps the
+    fastest.  Then, at that block size, on another copy of the same graph,
+    the sequence is recorded into one HIP graph (gv_plan_create, not timed)
+    and launched once.  Every run must end with the same checksum and edge
+    count.  Scratch is sized by a warm-up insert and delete of the largest
+    batch and a vertex delete and re-insert before the timed passes."""
     import numpy as np
     import torch
     w = T.RmatWorkload(scale, edges, name=seed_name, device=dev)
@@ -249,9 +280,9 @@ def batched_form(gv, I, T, dev, B, scale=22, edges=1 << 26, nbatch=256, seed_nam
     big = max((o for o in ops if o[0] == 0), key=lambda o: o[1].numel())
     one = ops[[o[0] for o in ops].index(3)][1][:1] if any(o[0] == 3 for o in ops) else None
 
-    def fresh():
-        # the same graph and warm-up for both forms
-        g = gv.Graph(n, w.src, w.dst, block_slots=B, device=dev)
+    def fresh(bs):
+        # the same graph and warm-up for every run
+        g = gv.Graph(n, w.src, w.dst, block_slots=bs, device=dev)
         g.insert_edges(big[1], big[2], stats=False)
         g.delete_edges(big[1], big[2], stats=False)
         if one is not None:
@@ -265,22 +296,28 @@ def batched_form(gv, I, T, dev, B, scale=22, edges=1 << 26, nbatch=256, seed_nam
                                              gv.C.byref(e)), "gv_dump_canonical")
         return ck.value, e.value
 
-    # eager: one launch sequence per batch
-    g = fresh()
-    keep = gv.gv_apply_ops(g.h, ops[:1])  # marshalling warm-up
-    torch.cuda.synchronize()
+    # eager (one launch sequence per batch) at every block size: the tuner
+    # keeps the fastest
     arr, keep = gv._ops(ops, dev)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    gv._check(gv.lib().gv_apply_ops(gv.C.c_void_p(g.h), arr, len(ops)), "gv_apply_ops")
-    rc = g.sync()
-    el = time.perf_counter() - t0
-    if rc != 0:
-        raise RuntimeError(f"batched form: {gv.gv_strerror(rc)}")
-    want = digest(g)
-    g.close()
+    by_b, digests = {}, {}
+    for bs in (8, 16, 32, 64):
+        g = fresh(bs)
+        gv.gv_apply_ops(g.h, ops[:1])  # marshalling warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gv._check(gv.lib().gv_apply_ops(gv.C.c_void_p(g.h), arr, len(ops)), "gv_apply_ops")
+        rc = g.sync()
+        by_b[bs] = time.perf_counter() - t0
+        if rc != 0:
+            raise RuntimeError(f"batched form: {gv.gv_strerror(rc)}")
+        digests[bs] = digest(g)
+        g.close()
+    if len(set(digests.values())) != 1:
+        raise RuntimeError(f"batched form: block sizes disagree: {digests}")
+    best = min(by_b, key=by_b.get)
+    el, want = by_b[best], digests[best]
     # recorded: the same sequence as one HIP graph (recording not timed)
-    g = fresh()
+    g = fresh(best)
     gv.gv_apply_ops(g.h, ops[:1])
     plan = gv.Plan(g.h, ops, dev)
     torch.cuda.synchronize()
@@ -295,13 +332,15 @@ def batched_form(gv, I, T, dev, B, scale=22, edges=1 << 26, nbatch=256, seed_nam
     g.close()
     if got != want:
         raise RuntimeError(f"batched form: plan {got} and eager {want} results differ")
-    return {"workload": f"rmat{scale} {edges} edges, B={B}, {nbatch} batches of log-uniform "
+    return {"workload": f"rmat{scale} {edges} edges, {nbatch} batches of log-uniform "
                         "size in [1e2, 1e6], 45/45/10 insert/delete/vertex",
-            "pairs": pairs, "vertex_ids": vids, "ms": round(el * 1e3, 3),
+            "pairs": pairs, "vertex_ids": vids,
+            "eager_ms_by_block_slots": {str(k): round(v * 1e3, 3) for k, v in by_b.items()},
+            "tuned_block_slots": best, "ms": round(el * 1e3, 3),
             "edges_per_s": round(pairs / el, 1), "form": "one launch sequence per batch",
             "plan_ms": round(el_plan * 1e3, 3),
             "plan_edges_per_s": round(pairs / el_plan, 1),
-            "plan_form": "the same sequence recorded as one HIP graph",
+            "plan_form": "the same sequence recorded as one HIP graph, tuned block size",
             "plan_matches_eager": True, "checksum": want[0], "edges_after": want[1]}
 
 
@@ -315,7 +354,8 @@ def served_form(gv, I, T, dev, B, scale=24, edges=1 << 28, nreq=1500, loads=(0.3
     requests alone).  Saturated throughput: every request available at time
     0.  Then open-loop Poisson arrivals at `loads` x that throughput, a fresh
     request list each; latency = completion - scheduled arrival, p50 / p99
-    by nearest rank."""
+    by nearest rank.  Baseline: another request list of the same mix applied
+    one request at a time with the single-batch calls, back to back."""
     import numpy as np
     import torch
     from paper_2306_08252_amd import served as S
@@ -324,7 +364,8 @@ def served_form(gv, I, T, dev, B, scale=24, edges=1 << 28, nreq=1500, loads=(0.3
 
     def requests(tag):
         draws = I.splitmix64(I.stream_seed(seed_name, "requests", tag), 3 * nreq)
-        base = 1_000_000 * (1 + ["warm", "saturated", *(f"load{x}" for x in loads)].index(tag))
+        base = 1_000_000 * (1 + ["warm", "baseline", "saturated",
+                                 *(f"load{x}" for x in loads)].index(tag))
         reqs = []
         for j in range(nreq):
             u = float(draws[3 * j] >> np.uint64(11)) / float(1 << 53)
@@ -352,16 +393,41 @@ def served_form(gv, I, T, dev, B, scale=24, edges=1 << 28, nreq=1500, loads=(0.3
                 reqs.append((kind, ids, None))
         return reqs
 
+    def pairs_of(reqs):
+        return sum(int(r[1].numel()) for r in reqs if r[0] in (S.INSERT, S.DELETE, S.QUERY))
+
     g = gv.Graph(n, w.src, w.dst, block_slots=B, device=dev)
     warm = requests("warm")
     S.serve(g, warm[:64])
+    # one launch sequence per request, back to back (the baseline)
+    base_reqs = requests("baseline")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for kind, a, b in base_reqs:
+        if kind == S.INSERT:
+            gv.gv_insert_edges(g.h, a, b, dev, stats=False)
+        elif kind == S.DELETE:
+            gv.gv_delete_edges(g.h, a, b, dev, stats=False)
+        elif kind == S.QUERY:
+            g.edge_exists(a, b)
+        elif kind == S.VINSERT:
+            g.insert_vertices(a)
+        else:
+            g.delete_vertices(a)
+    torch.cuda.synchronize()
+    el_base = time.perf_counter() - t0
+    # served, saturated: every request available at time 0
     sat_reqs = requests("saturated")
     torch.cuda.synchronize()
     done, ticks, _ = S.serve(g, sat_reqs)
     sat = nreq / done[-1]
     out = {"workload": f"rmat{scale} {edges} edges, B={B}, {nreq} requests per run of "
                        "log-uniform size in [1, 1e5], 40/40/15/5 insert/delete/query/vertex",
-           "saturated_req_per_s": round(sat, 1), "saturated_ticks": len(ticks), "runs": []}
+           "one_launch_per_request": {"req_per_s": round(nreq / el_base, 1),
+                                      "edges_per_s": round(pairs_of(base_reqs) / el_base, 1)},
+           "saturated_req_per_s": round(sat, 1),
+           "saturated_edges_per_s": round(pairs_of(sat_reqs) / done[-1], 1),
+           "saturated_ticks": len(ticks), "runs": []}
     for load in loads:
         reqs = requests(f"load{load}")
         draws = I.splitmix64(I.stream_seed(seed_name, "arrivals", load), nreq)
@@ -370,6 +436,7 @@ def served_form(gv, I, T, dev, B, scale=24, edges=1 << 28, nreq=1500, loads=(0.3
         done, ticks, _ = S.serve(g, reqs, arr)
         lat = (done - arr) * 1e3
         out["runs"].append({"load": load, "offered_req_per_s": round(load * sat, 1),
+                            "edges_per_s": round(pairs_of(reqs) / done[-1], 1),
                             "p50_ms": round(S.nearest_rank(lat, 0.5), 3),
                             "p99_ms": round(S.nearest_rank(lat, 0.99), 3),
                             "ticks": len(ticks), "span_s": round(float(done[-1]), 3)})
@@ -393,6 +460,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-form workload (eager and recorded forms)")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the block-size x batch-size sweep")
     ap.add_argument("--no-served", action="store_true",
                     help="skip the served-form workload (continuous batching, p50/p99)")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "OUT_MD"),
@@ -583,7 +652,8 @@ def main():
     g.close()
 
     # ---- batched form on its own workload
-    batched = None if args.no_batched else batched_form(gv, I, T, dev, B)
+    sweep = None if args.no_sweep else block_size_sweep(gv, w, dev)
+    batched = None if args.no_batched else batched_form(gv, I, T, dev)
     served = None if args.no_served else served_form(gv, I, T, dev, B)
 
     # ---- CPU oracle baseline on a quarter of the sources
@@ -641,6 +711,7 @@ def main():
                    "num_edges": mem["num_edges"]},
         "batched_form": batched,
         "served_p50_p99": served,
+        "block_size_sweep": sweep,
         "pilot_kernels_ms": pilot,
         "roofline": roof,
         "cpu_baseline": cpu,
