@@ -282,6 +282,112 @@ __global__ __launch_bounds__(kOsThreads) void k_pack_hist(GraphView g, const uin
     }
 }
 
+// Insert and delete batches of at most kOsTile pairs: one workgroup packs
+// the pairs as k_pack_hist does and sorts the keys in LDS, every radix pass
+// in the same kernel (the ranking of k_os_pass on a single tile, so no
+// look-back), instead of the pack, histogram and pass kernels.  Writes the
+// sorted keys to `keys` and the valid-pair count to tot[kTotValid].
+__global__ __launch_bounds__(kOsThreads) void k_pack_sort_tile(GraphView g, const uint32_t* src,
+                                                               const uint32_t* dst, uint64_t n,
+                                                               int passes, uint64_t sentinel,
+                                                               uint64_t* keys, uint8_t* mark) {
+    __shared__ uint16_t cnt[kOsRounds * kOsWaves][kRadix];
+    __shared__ uint32_t part[4][kRadix];
+    __shared__ uint32_t s_start[kRadix];
+    __shared__ uint32_t s_w[kOsWaves];
+    __shared__ uint64_t skey[kOsTile];
+    __shared__ unsigned long long s_v[kOsWaves];
+    const uint32_t t = threadIdx.x;
+    const int w = t >> 6;
+    if (t == 0) {
+        g.ctr->err_batch = 0;
+        g.ctr->n_big = 0;
+        g.ctr->n_heavy = 0;
+        for (int k = 0; k < 8; ++k) g.ctr->tot[k] = 0;
+    }
+    uint64_t key[kOsRounds];
+    unsigned long long valid = 0;
+#pragma unroll
+    for (int j = 0; j < kOsRounds; ++j) {
+        const uint64_t i = (uint64_t)j * kOsThreads + t;
+        const uint32_t su = i < n ? src[i] : 0u, du = i < n ? dst[i] : 0u;
+        const bool ok = active_bit(g, su) & active_bit(g, du);
+        key[j] = ok ? ((uint64_t)su << g.L) | du : sentinel;
+        if (i < n) {
+            mark[i] = 0;
+            valid += ok ? 1u : 0u;
+        }
+    }
+    const uint32_t d = t & (kRadix - 1), q = t >> 8;
+    constexpr int kQRows = kOsRounds * kOsWaves / 4;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = p * kRadixBits;
+        {
+            uint32_t* c32 = (uint32_t*)&cnt[0][0];
+            for (int i = t; i < kOsRounds * kOsWaves * kRadix / 2; i += kOsThreads) c32[i] = 0;
+        }
+        __syncthreads();
+        uint16_t rk[kOsRounds];
+#pragma unroll
+        for (int j = 0; j < kOsRounds; ++j) {
+            const bool act = (uint64_t)j * kOsThreads + t < n;
+            const uint32_t dg = (uint32_t)(key[j] >> shift) & (kRadix - 1);
+            const uint64_t peers = digit_peers(dg, act);
+            rk[j] = (uint16_t)rank_below(peers);
+            if (act && rk[j] == 0) cnt[j * kOsWaves + w][dg] = (uint16_t)popc64(peers);
+        }
+        __syncthreads();
+        // rows in key order: exclusive prefixes per digit, 16 rows per quarter
+        uint32_t run = 0;
+#pragma unroll
+        for (int r = 0; r < kQRows; ++r) {
+            const uint32_t c = cnt[q * kQRows + r][d];
+            cnt[q * kQRows + r][d] = (uint16_t)run;
+            run += c;
+        }
+        part[q][d] = run;
+        __syncthreads();
+        uint32_t qoff = 0;
+        for (uint32_t qq = 0; qq < q; ++qq) qoff += part[qq][d];
+        if (qoff) {
+#pragma unroll
+            for (int r = 0; r < kQRows; ++r) cnt[q * kQRows + r][d] += (uint16_t)qoff;
+        }
+        const uint32_t dcount = part[0][d] + part[1][d] + part[2][d] + part[3][d];
+        uint32_t tot;
+        const uint32_t ex = os_block_scan(q == 0 ? dcount : 0u, s_w, tot);
+        if (q == 0) s_start[d] = ex;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kOsRounds; ++j) {
+            if ((uint64_t)j * kOsThreads + t < n) {
+                const uint32_t dg = (uint32_t)(key[j] >> shift) & (kRadix - 1);
+                skey[s_start[dg] + cnt[j * kOsWaves + w][dg] + rk[j]] = key[j];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kOsRounds; ++j) {
+            const uint64_t i = (uint64_t)j * kOsThreads + t;
+            key[j] = i < n ? skey[i] : sentinel;
+        }
+        __syncthreads();  // skey and cnt are rewritten by the next pass
+    }
+#pragma unroll
+    for (int j = 0; j < kOsRounds; ++j) {
+        const uint64_t i = (uint64_t)j * kOsThreads + t;
+        if (i < n) keys[i] = key[j];
+    }
+    valid = wave_sum(valid);
+    if (lane_id() == 0) s_v[w] = valid;
+    __syncthreads();
+    if (t == 0) {
+        unsigned long long x = 0;
+        for (int k = 0; k < kOsWaves; ++k) x += s_v[k];
+        g.ctr->tot[kTotValid] = x;
+    }
+}
+
 // ------------------------------------------------------------------ segments
 struct SegIn {
     const uint64_t* keys;
@@ -1420,6 +1526,11 @@ void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t*
               A.part, &tot[kTotValid]);
         flip = onesweep<uint64_t, true>(c, A.keys0, A.keys1, A.vals0, A.vals1,
                                         (const uint32_t*)n_valid, n, bits, A.state, err);
+    } else if (n <= kOsTile && bits > 0) {
+        const uint64_t sentinel = bits >= 64 ? ~0ull : (1ull << bits) - 1;
+        c.launch("pack", k_pack_sort_tile, 1, kOsThreads, v, src, dst, n, os_passes(bits),
+                 sentinel, A.keys0, A.mark);
+        flip = false;
     } else {
         const uint64_t sentinel = bits >= 64 ? ~0ull : (1ull << bits) - 1;
         c.launch("pack", k_pack_hist, os_hist_groups(n), kOsThreads, v, src, dst, n,
