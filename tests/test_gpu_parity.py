@@ -346,3 +346,28 @@ def test_small_batches_touching_hubs(B):
         assert_same(g, o, f"delete {size}")
         same_answers(g, o, ds, dd, f"query after delete {size}")
     g.close()
+
+
+@pytest.mark.parametrize("size", [4095, 4096, 4097])
+def test_one_workgroup_sort_boundary(size):
+    """Batches on both sides of the single-workgroup pack and sort (at most
+    4096 pairs), with invalid pairs, repeated pairs and the largest valid
+    key (both endpoints the last id of the table)."""
+    gv = need_gpu()
+    rng = np.random.default_rng(size)
+    n, B = 1 << 12, 8
+    s0 = rng.integers(0, n, 5 * n).astype(np.uint32)
+    d0 = rng.integers(0, n, 5 * n).astype(np.uint32)
+    g = gv.Graph(n, s0, d0, block_slots=B)
+    o = O.OracleGraph(n, s0, d0, block_slots=B)
+    for rep in range(2):
+        s = rng.integers(0, n + 50, size).astype(np.uint32)  # some past the table
+        d = rng.integers(0, n, size).astype(np.uint32)
+        s[: size // 8], d[: size // 8] = s[size // 8: 2 * (size // 8)], d[size // 8: 2 * (size // 8)]
+        s[-1] = d[-1] = n - 1
+        same_answers(g, o, s, d, f"query {size} rep {rep}")
+        assert g.insert_edges(s, d) == o.insert_edges(s, d)[1]
+        assert_same(g, o, f"insert {size} rep {rep}")
+        assert g.delete_edges(d, s) == o.delete_edges(d, s)[1]
+        assert_same(g, o, f"delete {size} rep {rep}")
+    g.close()
