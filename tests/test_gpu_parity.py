@@ -348,11 +348,12 @@ def test_small_batches_touching_hubs(B):
     g.close()
 
 
-@pytest.mark.parametrize("size", [4095, 4096, 4097])
+@pytest.mark.parametrize("size", [4095, 4096, 4097, 8192, 12288, 12289])
 def test_one_workgroup_sort_boundary(size):
-    """Batches on both sides of the single-workgroup pack and sort (at most
-    4096 pairs), with invalid pairs, repeated pairs and the largest valid
-    key (both endpoints the last id of the table)."""
+    """Batches on both sides of the single-workgroup pack and sort (one tile
+    in LDS, at most 4096 pairs) and a few tiles past it, with invalid pairs,
+    repeated pairs and the largest valid key (both endpoints the last id of
+    the table)."""
     gv = need_gpu()
     rng = np.random.default_rng(size)
     n, B = 1 << 12, 8
