@@ -11,6 +11,20 @@ arrival order, then its queries.  Vertex requests are barriers: a tick ends
 before one, and it runs alone.  A request completes when its tick has
 synchronised; latency is completion time minus scheduled arrival time (open
 loop, so a late server does not lower the arrival rate).
+
+Admission by free blocks: an edge-insert request of k pairs may need up to
+ceil(k / B) + min(k, V) new blocks (its pairs packed into full blocks, plus
+one partly filled block per touched source, at most V sources).  A tick
+admits requests, in arrival order, while their bounds fit in the pool's
+free blocks, so a tick's insert batch cannot run out of pool; the rest wait
+for a later tick.  The free count is kept on the host as a lower bound (each
+tick subtracts its bounds; deletes only add) and read back from the device
+only when a request does not fit.  The directory arena is not part of the
+bound: by default it holds four entries per pool block, and a segment holds
+at most twice its vertex's blocks, but a directory shortfall would still
+fail a tick's inserts with GV_ENOMEM (sticky, reported by gv_sync).  A request whose bound exceeds
+the free blocks of an empty tick is rejected (it could fail the whole
+tick's inserts) and reported as such.
 """
 import math
 import time
@@ -23,29 +37,37 @@ from . import graphvine as gv
 INSERT, DELETE, QUERY, VINSERT, VDELETE = 0, 1, 2, 3, 4
 
 
-class Tick:
-    __slots__ = ("first", "end", "writes", "queries")
-
-    def __init__(self, first, end):
-        self.first, self.end = first, end
-
-
 def _size(req):
     return int(req[1].numel())
 
 
+def insert_block_bound(k, block_slots, vertex_capacity):
+    """New blocks an insert of k pairs can take at most."""
+    return -(-k // block_slots) + min(k, vertex_capacity)
+
+
+def free_blocks(graph):
+    m = graph.memory_used()
+    return m["pool_capacity_blocks"] - m["blocks_in_use"]
+
+
 def serve(graph, requests, arrivals=None, max_tick_pairs=1 << 20, keep_answers=False,
-          clock=time.perf_counter):
+          clock=time.perf_counter, rejected=None):
     """Runs `requests` [(kind, a, b)] (device id tensors; b is None for vertex
     requests) against `graph` (a graphvine.Graph).  `arrivals[i]` is request
     i's scheduled time in seconds from the start (None: all at time 0).
     Returns (completion times, ticks as (first, end) request ranges, answers
-    of the query requests by index if keep_answers)."""
+    of the query requests by index if keep_answers).  Indices of requests
+    rejected by admission are appended to `rejected` (a list) if given; a
+    rejected request is not in any tick."""
     n = len(requests)
     arr = np.zeros(n) if arrivals is None else np.asarray(arrivals, np.float64)
     if n and np.any(np.diff(arr) < 0):
         raise ValueError("arrivals must be in order")
     dev = graph.device
+    info = graph.info()
+    bs, vcap = info["block_slots"], info["vertex_capacity"]
+    free = free_blocks(graph)
     done = np.zeros(n)
     ticks = []
     answers = {}
@@ -69,13 +91,26 @@ def serve(graph, requests, arrivals=None, max_tick_pairs=1 << 20, keep_answers=F
             ticks.append((i, i + 1))
             i += 1
             continue
-        j, pairs = i, 0
+        j, pairs, need, fresh = i, 0, 0, False
         while j < n and arr[j] <= now and requests[j][0] in (INSERT, DELETE, QUERY):
             k = _size(requests[j])
+            b = insert_block_bound(k, bs, vcap) if requests[j][0] == INSERT else 0
             if j > i and pairs + k > max_tick_pairs:
                 break
+            if need + b > free and not fresh:
+                free = free_blocks(graph)  # the last tick has synchronised
+                fresh = True
+            if need + b > free:
+                break  # waits for a later tick (or, alone, is rejected)
             pairs += k
+            need += b
             j += 1
+        if j == i:
+            if rejected is not None:
+                rejected.append(i)
+            done[i] = clock() - t0
+            i += 1
+            continue
         ws = [r for r in requests[i:j] if r[0] in (INSERT, DELETE)]
         qs = [(m, r) for m, r in enumerate(requests[i:j], start=i) if r[0] == QUERY]
         if ws:
@@ -97,6 +132,7 @@ def serve(graph, requests, arrivals=None, max_tick_pairs=1 << 20, keep_answers=F
                 answers[m] = out[o:o + _size(r)]
                 o += _size(r)
         ticks.append((i, j))
+        free -= need
         i = j
     return done, ticks, answers
 

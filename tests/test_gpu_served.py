@@ -136,3 +136,51 @@ def test_mixed_list_past_the_pool_is_sticky_and_consistent():
                    np.array([k[1] for k in gone], np.uint32))
     assert_same(g, o, "deletes applied, inserts not")
     g.close()
+
+
+def test_served_admission_by_free_blocks():
+    """A pool with little room: inserts wait for ticks whose bounds fit the
+    free blocks, an insert too large for the whole free pool is rejected,
+    no tick runs out of pool, and the graph equals the oracle replaying the
+    admitted requests in commit order."""
+    gv = need_gpu()
+    from paper_2306_08252_amd import served as S
+    rng = np.random.default_rng(10)
+    n, B = 256, 4
+    s0 = rng.integers(0, n, 600).astype(np.uint32)
+    d0 = rng.integers(0, n, 600).astype(np.uint32)
+    pool = 4 * B * 1200
+    g = gv.Graph(n, s0, d0, block_slots=B, pool_bytes=pool, vertex_capacity=n)
+    o = O.OracleGraph(n, s0, d0, block_slots=B, pool_bytes=pool, vertex_capacity=n)
+    dev = g.device
+    host = []
+    for j in range(60):
+        kind = int(rng.choice(3, p=[0.5, 0.3, 0.2]))
+        size = int(rng.integers(1, 120))
+        if j == 30:
+            kind, size = S.INSERT, 5000  # bound past the whole pool
+        s = rng.integers(0, n, size).astype(np.uint32)
+        d = rng.integers(0, n, size).astype(np.uint32)
+        if kind == S.DELETE:
+            pk = rng.integers(0, len(s0), size)
+            s, d = s0[pk], d0[pk]
+        host.append((kind, s, d))
+    reqs = [(k, torch.from_numpy(a.view(np.int32)).to(dev), torch.from_numpy(b.view(np.int32)).to(dev))
+            for k, a, b in host]
+    rejected = []
+    done, ticks, answers = S.serve(g, reqs, None, max_tick_pairs=400, keep_answers=True,
+                                   rejected=rejected)
+    assert g.sync() == 0  # no tick ran out of pool
+    assert 30 in rejected
+    assert sum(e - f for f, e in ticks) + len(rejected) == len(reqs)
+    for f, e in ticks:
+        ws = [host[i] for i in range(f, e) if host[i][0] in (S.INSERT, S.DELETE)]
+        if ws:
+            op = np.concatenate([np.full(len(w[1]), w[0], np.uint8) for w in ws])
+            o.apply_edge_ops(op, np.concatenate([w[1] for w in ws]),
+                             np.concatenate([w[2] for w in ws]))
+        for i in range(f, e):
+            if host[i][0] == S.QUERY:
+                np.testing.assert_array_equal(answers[i], o.edge_exists(host[i][1], host[i][2]))
+    assert_same(g, o, "after admission-controlled serving")
+    g.close()
