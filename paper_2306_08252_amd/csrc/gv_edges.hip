@@ -489,7 +489,7 @@ struct ItemIn {
 // wave that make the call, one item each per store.  The scan calls the sink
 // for elements below its size only, so in the last wave of a scan some lanes
 // may not take part: the loop counts the lanes that do.
-constexpr uint32_t kLaneItems = 4;
+constexpr uint32_t kLaneItems = 16;
 
 struct ItemOut {
     Item* items;
