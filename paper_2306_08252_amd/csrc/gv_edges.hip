@@ -65,8 +65,8 @@ constexpr int kUnroll = GV_PROBE_UNROLL;       // slots per lane per step
 constexpr uint32_t kBigR = 256;                // deletes per source handled by a workgroup
 constexpr uint32_t kBigGroups = 256;           // workgroups for those sources
 constexpr uint32_t kLaneCopy = 8;              // directory entries a lane copies or adds
-constexpr uint32_t kLaneSeg = 8;               // segment entries a lane compacts
-constexpr uint32_t kLaneR = 4;                 // hits a lane compacts
+constexpr uint32_t kLaneSeg = 16;              // segment entries a lane compacts
+constexpr uint32_t kLaneR = 8;                 // hits a lane compacts
 constexpr uint32_t kRelease = 0x80000000u;     // flag bit in the per-source demand
 
 // scan-total slots in DevCounters::tot
