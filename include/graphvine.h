@@ -162,7 +162,7 @@ int gv_delete_vertices(gv_graph* g, const uint32_t* d_ids, uint64_t n,
  * only.  Asynchronous, no statistics; an allocation failure is sticky
  * (reported by gv_sync) and leaves a consistent graph in which the delete
  * part may have been applied.  GV_EINVAL for null arrays with n > 0 or
- * n >= 2^30. */
+ * n >= 2^30 - 1 (the limit of every edge batch). */
 int gv_apply_edge_ops(gv_graph* g, const uint8_t* d_op, const uint32_t* d_src,
                       const uint32_t* d_dst, uint64_t n);
 
