@@ -570,6 +570,26 @@ __device__ __forceinline__ uint32_t os_block_scan(uint32_t x, uint32_t* lds, uin
     return off + inc - x;
 }
 
+// the same for 64-bit values
+__device__ __forceinline__ unsigned long long os_block_scan64(unsigned long long x,
+                                                              unsigned long long* lds,
+                                                              unsigned long long& total) {
+    unsigned long long inc = wave_incl_scan(x);
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 63) lds[w] = inc;
+    __syncthreads();
+    unsigned long long off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kOsWaves; ++i) {
+        const unsigned long long v = lds[i];
+        off += (i < w) ? v : 0ull;
+        tot += v;
+    }
+    __syncthreads();
+    total = tot;
+    return off + inc - x;
+}
+
 // Histogram counting: 0 = the lowest lane of each group of equal digits adds
 // the group's size (eight ballots per digit, no conflicting LDS atomics);
 // 1 = every lane adds one to a histogram shared by a quarter of the
@@ -683,7 +703,7 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const K* kin, K* kout, c
     __shared__ uint32_t part[4][kRadix];
     __shared__ uint32_t s_base[kRadix];   // global start of digit run of this tile
     __shared__ uint32_t s_lstart[kRadix]; // start of digit run inside the tile
-    __shared__ uint32_t s_w[kOsWaves];
+    __shared__ unsigned long long s_w64[kOsWaves];
     __shared__ uint32_t s_tile;
     __shared__ K skey[kOsTile];
     __shared__ uint32_t sval[HasVal ? kOsTile : 1];
@@ -866,10 +886,12 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const K* kin, K* kout, c
     const uint32_t prefix = t < kRadix ? lb_prefix[t] : 0u;
     if (!block_tiles && t < kRadix && tile > 0)
         st_release32(status + tile * kRadix + t, kOsIncl | (prefix + dcount));
-    // global start of each digit (pass histogram) and start inside the tile
-    uint32_t tot;
-    const uint32_t gex = os_block_scan(hv, s_w, tot);
-    const uint32_t lex = os_block_scan(t < kRadix ? dcount : 0u, s_w, tot);
+    // global start of each digit (pass histogram) and start inside the tile:
+    // one scan of both, the histogram in the high half (neither half carries)
+    unsigned long long tot;
+    const unsigned long long both =
+        os_block_scan64(((unsigned long long)hv << 32) | (t < kRadix ? dcount : 0u), s_w64, tot);
+    const uint32_t gex = (uint32_t)(both >> 32), lex = (uint32_t)both;
     if (t < kRadix) {
         s_base[t] = gex + prefix;
         s_lstart[t] = lex;
