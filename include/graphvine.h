@@ -34,8 +34,17 @@
  * synchronising call.  With a non-NULL stats pointer the call waits for its
  * own completion and reports its own result.
  *
+ * Device-side checks.  Every edge batch verifies its own grouping sort on the
+ * device: the sorted keys must be in order and must have the same mix64 sum
+ * as the packed keys, and no look-back wait between workgroups may have run
+ * out.  If a check fails, that batch and every later one change nothing; the
+ * next synchronising call (a batch call with stats, gv_sync) returns
+ * GV_EDEVICE and the graph is unusable.
+ *
  * Ids are uint32.  The largest dictionary capacity is 2^31 vertices, so the
- * largest vertex id is 2^31 - 1; 0xFFFFFFFF is never a valid id.
+ * largest vertex id is 2^31 - 1; 0xFFFFFFFF is never a valid id.  A batch
+ * holds fewer than 2^30 - 1 pairs; a graph holds fewer than 2^30 edges when
+ * it is built or dumped (GV_EINVAL otherwise).
  */
 #ifndef GRAPHVINE_H
 #define GRAPHVINE_H
@@ -52,7 +61,8 @@ enum {
     GV_ERANGE = 2,  /* id outside the dictionary, or an output buffer too small */
     GV_ENOMEM = 3,  /* pool, directory or device memory exhausted; the batch is
                        not applied and the graph is unchanged                  */
-    GV_EDEVICE = 4  /* a HIP runtime failure; the graph must be destroyed      */
+    GV_EDEVICE = 4  /* a HIP runtime failure, or a batch whose device-side
+                       checks failed (see below); the graph must be destroyed  */
 };
 
 #define GV_MAX_CAPACITY (1ull << 31)
@@ -264,6 +274,11 @@ void gv_plan_destroy(gv_plan* p);
 int gv_apply_ops(gv_graph* g, const gv_op* ops, uint64_t n_ops);
 
 int gv_set_stream(gv_graph* g, void* hip_stream);
+/* Test support: the number of extra status loads each look-back wait of a
+ * batch sort makes before it gives up (default 2^24).  0 makes every wait give
+ * up at once, so the failure path (GV_EDEVICE, no change to the graph) can be
+ * exercised without a real stall.  Synchronous. */
+int gv_debug_spin_limit(gv_graph* g, uint32_t limit);
 /* Wait for all queued work; returns and clears the first error of earlier
  * asynchronous calls. */
 int gv_sync(gv_graph* g);

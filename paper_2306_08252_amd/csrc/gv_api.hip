@@ -60,6 +60,15 @@ void free_graph(gv_graph* g) {
 
 bool pow2(uint64_t x) { return x && !(x & (x - 1)); }
 
+// A batch sort that failed (a look-back wait ran out, or the sorted keys were
+// out of order or not the packed keys) left its batch and every later batch
+// undone: the graph is unusable.  Reads the counters last copied to the host.
+void check_sort(gv_graph* g) {
+    if (g->hctr->err_wait) fail(GV_EDEVICE, "a batch sort's look-back wait ran out");
+    if (g->hctr->err_order == 2) fail(GV_EDEVICE, "a batch's sorted keys were out of order");
+    if (g->hctr->err_order) fail(GV_EDEVICE, "a batch's sorted keys were not its packed keys");
+}
+
 void fill_stats(gv_graph* g, gv_batch_stats* st) {
     st->applied = g->hctr->st_applied;
     st->rejected = g->hctr->st_rejected;
@@ -150,6 +159,7 @@ static int edge_update(gv_graph* g, EdgeMode mode, const uint32_t* s, const uint
         edge_batch(g, mode, s, d, n, nullptr, st == nullptr);
         if (st) {
             read_counters(g);
+            check_sort(g);
             if (g->hctr->err_batch) fail((int)g->hctr->err_batch, "batch failed");
             fill_stats(g, st);
         }
@@ -343,6 +353,14 @@ int gv_kernel_names(gv_graph* g, char* buf, size_t cap, size_t* needed) {
     return GV_OK;
 }
 
+int gv_debug_spin_limit(gv_graph* g, uint32_t limit) {
+    if (!g) return GV_EINVAL;
+    return guarded(g, [&] {
+        hip_check(hipStreamSynchronize(g->ctx.stream), "hipStreamSynchronize");
+        g->spin_limit = limit;
+    });
+}
+
 int gv_set_stream(gv_graph* g, void* hip_stream) {
     if (!g) return GV_EINVAL;
     return guarded(g, [&] {
@@ -357,7 +375,7 @@ int gv_sync(gv_graph* g) {
     int code = GV_OK;
     int rc = guarded(g, [&] {
         read_counters(g);
-        if (g->hctr->err_wait) fail(GV_EDEVICE, "a look-back wait ran out");
+        check_sort(g);
         code = (int)g->hctr->err_sticky;
         if (code) {
             set_u32(g, &g->v.ctr->err_sticky, 0);

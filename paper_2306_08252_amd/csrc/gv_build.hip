@@ -233,7 +233,7 @@ void bulk_build(gv_graph* g, uint64_t n, const uint32_t* src, const uint32_t* ds
     }
     uint64_t* ukeys = nullptr;
     if (m > 0) {
-        if (m >= 0xffffffffull) fail(GV_EINVAL, "too many edges");
+        if (m >= kOsMaxKeys) fail(GV_EINVAL, "2^30 or more edges");
         const uint64_t grid = div_up(m, kThreads);
         c.launch("init_pack", k_init_pack, grid, kThreads, v, src, dst, m, n, A.k0);
         const bool flip = m > 1 && sort_keys(g, A.k0, A.k1, m, bits, A.state);

@@ -21,6 +21,7 @@ namespace gv {
 constexpr uint32_t kTomb = 0xFFFFFFFFu;  // empty / deleted slot marker
 constexpr uint32_t kNoDir = 0xFFu;       // vertex has no directory segment
 constexpr int kMaxClass = 32;
+constexpr uint32_t kSpinLimitDefault = 1u << 24;  // loads before a look-back wait gives up
 constexpr int kThreads = 256;            // threads per workgroup (4 waves)
 constexpr int kWaves = kThreads / 64;
 #ifndef GV_PROBE_CHUNK
@@ -60,7 +61,8 @@ struct DevCounters {
     // errors: err_batch is reset per batch, err_sticky accumulates; err_wait
     // is set if a bounded look-back wait ever ran out
     uint32_t err_batch, err_sticky, err_wait, n_big;
-    uint32_t n_heavy, n_heavy_pad;     // sources left to whole waves this batch
+    uint32_t n_heavy;                  // sources left to whole waves this batch
+    uint32_t err_order;                // a batch's sorted keys failed their check
     uint32_t sort_n, sort_err;  // count and look-back error word of whole-graph sorts
     // vertex delete: sweep units, kept slots, freed blocks | removed edges << 32
     unsigned long long v_units, v_kept, v_fr;
@@ -78,6 +80,13 @@ struct DevCounters {
     unsigned long long checksum, edges, violations;
     uint32_t vmax, vany;
 };
+
+// A batch sort that failed (a look-back wait ran out, or the sorted keys are
+// out of order or not the packed keys) makes every later batch step a no-op;
+// the graph reports GV_EDEVICE from then on.
+__device__ __forceinline__ bool batch_failed(const DevCounters* c) {
+    return (c->err_wait | c->err_order) != 0u;
+}
 
 // Everything a kernel needs to reach the structure, passed by value.
 struct GraphView {

@@ -70,7 +70,9 @@ constexpr uint32_t kLaneR = 8;                 // hits a lane compacts
 constexpr uint32_t kRelease = 0x80000000u;     // flag bit in the per-source demand
 
 // scan-total slots in DevCounters::tot
-enum { kTotValid = 0, kTotSeg = 1, kTotItems = 2, kTotA = 3, kTotB = 4 };
+enum { kTotValid = 0, kTotSeg = 1, kTotItems = 2, kTotA = 3, kTotB = 4, kTotHash = 5 };
+// stripe[k][kStripeHash]: per-workgroup sums of mix64 over the sorted keys
+constexpr int kStripeHash = 1;
 
 // self-contained work item: slots [s0, s1) of vertex v, batch segment [lo, hi);
 // block j is dir[dirbase + j] when the vertex has a directory segment, else
@@ -114,6 +116,7 @@ struct BatchArrays {
     uint32_t* state;    // zeroed look-back state of the sort
     uint64_t state_words;
     uint32_t* vpart;    // insert / delete: valid pairs per packing workgroup
+    unsigned long long* hpart;  // insert / delete: mix64 sum of valid keys per packing workgroup
 };
 
 static void carve_batch(Carver& cv, BatchArrays& A, uint64_t n, uint64_t icap, EdgeMode mode,
@@ -152,6 +155,7 @@ static void carve_batch(Carver& cv, BatchArrays& A, uint64_t n, uint64_t icap, E
     A.state_words = os_zero_words(n, bits);  // the part the batch zeroes
     A.state = cv.take<uint32_t>(os_words(n, bits));
     A.vpart = cv.take<uint32_t>(kHistGroups);
+    A.hpart = cv.take<unsigned long long>(kHistGroups);
 }
 
 __device__ __forceinline__ uint64_t thread_index() {
@@ -163,15 +167,22 @@ __device__ __forceinline__ uint32_t global_wave() {
 }
 
 // ------------------------------------------------------------------ begin
+// Per-batch counters, cleared by the first kernel of a batch (threads 0..63
+// of its first workgroup).
+__device__ __forceinline__ void clear_batch_counters(DevCounters* c, uint32_t t) {
+    if (t == 0) {
+        c->err_batch = 0;
+        c->n_big = 0;
+        c->n_heavy = 0;
+        for (int k = 0; k < 8; ++k) c->tot[k] = 0;
+    }
+    if (t < 64) c->stripe[t][kStripeHash] = 0;
+}
+
 __global__ __launch_bounds__(kThreads) void k_begin(GraphView g, uint32_t* state, uint64_t words) {
     const uint64_t stride = (uint64_t)gridDim.x * kThreads;
     for (uint64_t i = thread_index(); i < words; i += stride) state[i] = 0;
-    if (thread_index() == 0) {
-        g.ctr->err_batch = 0;
-        g.ctr->n_big = 0;
-        g.ctr->n_heavy = 0;
-        for (int k = 0; k < 8; ++k) g.ctr->tot[k] = 0;
-    }
+    if (blockIdx.x == 0) clear_batch_counters(g.ctr, threadIdx.x);
 }
 
 // ------------------------------------------------------------------ pack
@@ -223,23 +234,21 @@ __global__ __launch_bounds__(kOsThreads) void k_pack_hist(GraphView g, const uin
                                                           int passes, uint64_t sentinel,
                                                           uint64_t* keys, uint8_t* mark,
                                                           uint32_t* state, uint64_t zero_words,
-                                                          uint32_t* hpart, uint32_t* vpart) {
+                                                          uint32_t* hpart, uint32_t* vpart,
+                                                          unsigned long long* kpart) {
     __shared__ uint32_t h[kOsHistCopies][8][kRadix];
     __shared__ uint32_t s_v[kOsWaves];
+    __shared__ unsigned long long s_k[kOsWaves];
     const uint32_t t = threadIdx.x;
     for (uint64_t i = (uint64_t)blockIdx.x * kOsThreads + t; i < zero_words;
          i += (uint64_t)gridDim.x * kOsThreads)
         state[i] = 0;
-    if (blockIdx.x == 0 && t == 0) {
-        g.ctr->err_batch = 0;
-        g.ctr->n_big = 0;
-        g.ctr->n_heavy = 0;
-        for (int k = 0; k < 8; ++k) g.ctr->tot[k] = 0;
-    }
+    if (blockIdx.x == 0) clear_batch_counters(g.ctr, t);
     for (int i = t; i < kOsHistCopies * 8 * kRadix; i += kOsThreads) (&h[0][0][0])[i] = 0;
     __syncthreads();
     const uint32_t copy = kOsHistCopies == 1 ? 0u : (t >> 6) & (kOsHistCopies - 1);
     uint32_t valid = 0;
+    unsigned long long khash = 0;  // multiset hash of the valid keys (checked after the sort)
     const uint64_t ntiles = (n + kOsTile - 1) / kOsTile;
     for (uint64_t tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
         const uint64_t base = tl * kOsTile;
@@ -261,12 +270,17 @@ __global__ __launch_bounds__(kOsThreads) void k_pack_hist(GraphView g, const uin
             keys[i] = key;
             mark[i] = 0;
             valid += ok[j] ? 1u : 0u;
+            khash += ok[j] ? mix64(key) : 0ull;
             for (int p = 0; p < passes; ++p)
                 atomicAdd(&h[copy][p][(uint32_t)(key >> (p * kRadixBits)) & (kRadix - 1)], 1u);
         }
     }
     const uint32_t vw = (uint32_t)wave_sum((unsigned long long)valid);
-    if (lane_id() == 0) s_v[t >> 6] = vw;
+    const unsigned long long kw = wave_sum(khash);
+    if (lane_id() == 0) {
+        s_v[t >> 6] = vw;
+        s_k[t >> 6] = kw;
+    }
     __syncthreads();
     uint32_t* out = hpart + (uint64_t)blockIdx.x * passes * kRadix;
     for (int i = t; i < passes * kRadix; i += kOsThreads) {
@@ -277,8 +291,13 @@ __global__ __launch_bounds__(kOsThreads) void k_pack_hist(GraphView g, const uin
     }
     if (t == 0) {
         uint32_t x = 0;
-        for (int w = 0; w < kOsWaves; ++w) x += s_v[w];
+        unsigned long long y = 0;
+        for (int w = 0; w < kOsWaves; ++w) {
+            x += s_v[w];
+            y += s_k[w];
+        }
         vpart[blockIdx.x] = x;
+        kpart[blockIdx.x] = y;
     }
 }
 
@@ -299,14 +318,9 @@ __global__ __launch_bounds__(kOsThreads) void k_pack_sort_tile(GraphView g, cons
     __shared__ unsigned long long s_v[kOsWaves];
     const uint32_t t = threadIdx.x;
     const int w = t >> 6;
-    if (t == 0) {
-        g.ctr->err_batch = 0;
-        g.ctr->n_big = 0;
-        g.ctr->n_heavy = 0;
-        for (int k = 0; k < 8; ++k) g.ctr->tot[k] = 0;
-    }
+    clear_batch_counters(g.ctr, t);
     uint64_t key[kOsRounds];
-    unsigned long long valid = 0;
+    unsigned long long valid = 0, khash = 0;
 #pragma unroll
     for (int j = 0; j < kOsRounds; ++j) {
         const uint64_t i = (uint64_t)j * kOsThreads + t;
@@ -316,6 +330,7 @@ __global__ __launch_bounds__(kOsThreads) void k_pack_sort_tile(GraphView g, cons
         if (i < n) {
             mark[i] = 0;
             valid += ok ? 1u : 0u;
+            khash += ok ? mix64(key[j]) : 0ull;
         }
     }
     const uint32_t d = t & (kRadix - 1), q = t >> 8;
@@ -379,24 +394,36 @@ __global__ __launch_bounds__(kOsThreads) void k_pack_sort_tile(GraphView g, cons
         if (i < n) keys[i] = key[j];
     }
     valid = wave_sum(valid);
-    if (lane_id() == 0) s_v[w] = valid;
+    khash = wave_sum(khash);
+    __shared__ unsigned long long s_k[kOsWaves];
+    if (lane_id() == 0) {
+        s_v[w] = valid;
+        s_k[w] = khash;
+    }
     __syncthreads();
     if (t == 0) {
-        unsigned long long x = 0;
-        for (int k = 0; k < kOsWaves; ++k) x += s_v[k];
+        unsigned long long x = 0, y = 0;
+        for (int k = 0; k < kOsWaves; ++k) {
+            x += s_v[k];
+            y += s_k[k];
+        }
         g.ctr->tot[kTotValid] = x;
+        g.ctr->tot[kTotHash] = y;
     }
 }
 
 // ------------------------------------------------------------------ segments
 struct SegIn {
     const uint64_t* keys;
-    const unsigned long long* n_valid;
+    const DevCounters* ctr;
     uint32_t L;
     struct Rec {
         uint64_t k, p;
     };
-    __device__ uint64_t limit(uint64_t n) const { return min((uint64_t)*n_valid, n); }
+    // no segments after a look-back wait ran out (the keys are not sorted)
+    __device__ uint64_t limit(uint64_t n) const {
+        return ctr->err_wait ? 0ull : min((uint64_t)ctr->tot[kTotValid], n);
+    }
     __device__ Rec load(uint64_t i, bool ok) const {
         const uint64_t j = ok ? i : 0;
         return Rec{keys[j], keys[j ? j - 1 : 0]};
@@ -409,18 +436,24 @@ struct SegIn {
     }
 };
 
+// The segment scan also checks the sort: every key is at least its
+// predecessor (else err_order = 2), and the mix64 sum of the sorted keys,
+// added up per workgroup in the hash stripes, must equal the packed keys'
+// sum (compared by the probe, which runs next but one).
 struct SegOut {
     uint32_t L;
     uint8_t* flags;
     uint32_t* a;
     uint32_t* t_vtx;
     uint32_t* t_start;
+    DevCounters* ctr;
     __device__ void operator()(uint64_t i, const SegIn::Rec& r, uint64_t nv,
                                unsigned long long pre) const {
         if (i >= nv) {
             if (i == 0) t_start[0] = 0;
             return;
         }
+        if (i > 0 && r.k < r.p) ctr->err_order = 2;
         const bool head = i == 0 || (r.k >> L) != (r.p >> L);
         const bool uniq = i == 0 || r.k != r.p;
         const uint32_t t = (uint32_t)pre + (head ? 1u : 0u) - 1u;  // segment of key i
@@ -433,6 +466,10 @@ struct SegOut {
             t_start[t] = (uint32_t)i;
         }
         if (i + 1 == nv) t_start[t + 1] = (uint32_t)nv;
+    }
+    __device__ unsigned long long tally(uint64_t, const SegIn::Rec& r) const { return mix64(r.k); }
+    __device__ void commit(unsigned long long sum) const {
+        atomicAdd(&ctr->stripe[blockIdx.x & 63][kStripeHash], sum);
     }
 };
 
@@ -473,7 +510,7 @@ struct ItemIn {
     const uint32_t* t_start;
     using Rec = TouchRec;
     __device__ uint64_t limit(uint64_t n) const {
-        return min((uint64_t)(uint32_t)g.ctr->tot[kTotSeg], n);
+        return batch_failed(g.ctr) ? 0ull : min((uint64_t)(uint32_t)g.ctr->tot[kTotSeg], n);
     }
     __device__ Rec load(uint64_t t, bool ok) const { return load_touched(t_vtx, t_start, t, ok); }
     __device__ void deref(Rec& x) const { x.r = g.vt[x.v]; }
@@ -495,6 +532,7 @@ struct ItemOut {
     Item* items;
     Item* small;        // per touched source: its small item, or s1 = 0
     uint32_t B;
+    uint64_t icap;      // capacity of items (the scan of distinct sources stays below it)
     __device__ void operator()(uint64_t t, const TouchRec& x, uint64_t lim,
                                unsigned long long pre) const {
         const bool live = t < lim;
@@ -521,7 +559,7 @@ struct ItemOut {
             for (uint32_t c = 0; c < cnt; ++c) {
                 it.s0 = c * kChunk;
                 it.s1 = min(r.deg, it.s0 + kChunk);
-                items[base + c] = it;
+                if (base + c < icap) items[base + c] = it;
             }
         }
         const uint64_t act = ballot(true);
@@ -542,7 +580,7 @@ struct ItemOut {
             for (uint32_t c = me; c < wcnt; c += nact) {
                 w.s0 = c * kChunk;
                 w.s1 = min(wdeg, w.s0 + kChunk);
-                items[wbase + c] = w;
+                if ((uint64_t)wbase + c < icap) items[wbase + c] = w;
             }
         }
     }
@@ -727,6 +765,16 @@ __global__ __launch_bounds__(kThreads) void k_probe(GraphView g, const uint64_t*
                                                     const Item* items, const Item* small,
                                                     uint8_t* mark, uint32_t* hitpos) {
     __shared__ uint32_t stage[kWaves * kGroupsPerWave][kStage];
+    if (batch_failed(g.ctr)) return;
+    if (MODE != kQuery) {
+        // the sorted keys must be the packed keys: their mix64 sums agree
+        // (per-workgroup sums of the segment scan in 64 stripes; one load a lane)
+        const unsigned long long sorted = wave_sum(g.ctr->stripe[lane_id()][kStripeHash]);
+        if (sorted != g.ctr->tot[kTotHash]) {
+            if (lane_id() == 0) g.ctr->err_order = 3;
+            return;
+        }
+    }
     {
         // small items first, kSmallLanes consecutive lanes per touched source
         const uint64_t nq = (uint64_t)(uint32_t)g.ctr->tot[kTotSeg] * kSmallLanes;
@@ -828,11 +876,13 @@ __global__ __launch_bounds__(kThreads) void k_probe(GraphView g, const uint64_t*
 struct KeepIn {
     const uint8_t* flags;
     const uint8_t* mark;
-    const unsigned long long* n_valid;
+    const DevCounters* ctr;
     struct Rec {
         uint8_t f, m;
     };
-    __device__ uint64_t limit(uint64_t n) const { return min((uint64_t)*n_valid, n); }
+    __device__ uint64_t limit(uint64_t n) const {
+        return batch_failed(ctr) ? 0ull : min((uint64_t)ctr->tot[kTotValid], n);
+    }
     __device__ Rec load(uint64_t i, bool ok) const {
         const uint64_t j = ok ? i : 0;
         return Rec{flags[j], mark[j]};
@@ -860,6 +910,7 @@ __global__ __launch_bounds__(kThreads) void k_plan_ins(GraphView g, const uint32
     if (threadIdx.x < kMaxClass) lcnt[threadIdx.x] = 0;
     __syncthreads();
     const uint64_t t = thread_index();
+    if (batch_failed(g.ctr)) return;  // uniform over the launch
     const uint32_t nT = (uint32_t)g.ctr->tot[kTotSeg];
     uint32_t cls = kNoDir, lrank = 0;
     bool big = false;
@@ -896,7 +947,7 @@ struct NeedIn {
         uint32_t need;
     };
     __device__ uint64_t limit(uint64_t n) const {
-        return min((uint64_t)(uint32_t)ctr->tot[kTotSeg], n);
+        return batch_failed(ctr) ? 0ull : min((uint64_t)(uint32_t)ctr->tot[kTotSeg], n);
     }
     __device__ Rec load(uint64_t t, bool ok) const { return Rec{t_need[ok ? t : 0]}; }
     __device__ void deref(Rec&) const {}
@@ -928,6 +979,11 @@ struct NeedOut {
 __device__ __forceinline__ void plan_batch(const GraphView& g, uint64_t n, int sticky) {
     DevCounters* c = g.ctr;
     const uint32_t k = lane_id();
+    if (batch_failed(c)) {
+        // nothing is committed; append, grow and release see the error
+        if (k == 0) c->err_batch = GV_EDEVICE;
+        return;
+    }
     const bool cl = k < kMaxClass;
     const unsigned long long N = c->tot[kTotB] & 0xffffffffull;
     const unsigned long long free0 = c->free_cnt, bump0 = c->bump;
@@ -1146,11 +1202,13 @@ __global__ __launch_bounds__(kThreads) void k_final_ins(GraphView g, const uint3
 // ------------------------------------------------------------------ delete
 struct FoundIn {
     const uint8_t* mark;
-    const unsigned long long* n_valid;
+    const DevCounters* ctr;
     struct Rec {
         uint8_t m;
     };
-    __device__ uint64_t limit(uint64_t n) const { return min((uint64_t)*n_valid, n); }
+    __device__ uint64_t limit(uint64_t n) const {
+        return batch_failed(ctr) ? 0ull : min((uint64_t)ctr->tot[kTotValid], n);
+    }
     __device__ Rec load(uint64_t i, bool ok) const { return Rec{mark[ok ? i : 0]}; }
     __device__ void deref(Rec&) const {}
     __device__ unsigned long long value(uint64_t, const Rec& r) const { return r.m; }
@@ -1175,7 +1233,7 @@ struct FreedIn {
     const uint32_t* b;
     using Rec = FreedRec;
     __device__ uint64_t limit(uint64_t n) const {
-        return min((uint64_t)(uint32_t)g.ctr->tot[kTotSeg], n);
+        return batch_failed(g.ctr) ? 0ull : min((uint64_t)(uint32_t)g.ctr->tot[kTotSeg], n);
     }
     __device__ Rec load(uint64_t t, bool ok) const {
         return Rec{load_touched(t_vtx, t_start, t, ok), 0u};
@@ -1423,6 +1481,7 @@ __global__ __launch_bounds__(kThreads) void k_compact(GraphView g, const uint8_t
                                                       const uint32_t* hitpos, uint32_t* holes,
                                                       const CDesc* cdesc, const uint32_t* mid,
                                                       const uint32_t* big, uint32_t nbig) {
+    if (batch_failed(g.ctr)) return;
     if (blockIdx.x < nbig)
         compact_big_body(g, mark, hitpos, holes, cdesc, big, blockIdx.x, nbig);
     else
@@ -1432,6 +1491,10 @@ __global__ __launch_bounds__(kThreads) void k_compact(GraphView g, const uint8_t
 
 __global__ void k_final_del(GraphView g, uint64_t n) {
     DevCounters* c = g.ctr;
+    if (batch_failed(c)) {
+        c->err_batch = GV_EDEVICE;
+        return;
+    }
     const unsigned long long nv = c->tot[kTotValid];
     const unsigned long long nT = c->tot[kTotSeg] & 0xffffffffull;
     const unsigned long long nuniq = c->tot[kTotSeg] >> 32;
@@ -1454,6 +1517,7 @@ __global__ __launch_bounds__(kThreads) void k_answer(GraphView g, const uint32_t
                                                      const uint8_t* mark, uint64_t n,
                                                      uint8_t* out) {
     const uint64_t i = thread_index();
+    if (batch_failed(g.ctr)) return;  // the answers are not written; the call reports the error
     const unsigned long long nv = g.ctr->tot[kTotValid];
     if (i == 0) {
         DevCounters* c = g.ctr;
@@ -1462,7 +1526,7 @@ __global__ __launch_bounds__(kThreads) void k_answer(GraphView g, const uint32_t
         c->c_touched[kQuery] += c->tot[kTotSeg] & 0xffffffffull;
         c->c_scanned[kQuery] += (c->tot[kTotItems] >> 32) << g.log2B;
     }
-    if (i < nv) out[vals[i]] = mark[i];
+    if (i < nv && vals[i] < n) out[vals[i]] = mark[i];
 }
 
 __global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
@@ -1525,7 +1589,8 @@ void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t*
         scan2(c, "pack", PackIn{v, src, dst}, PackOut{v.L, A.keys0, A.vals0, out, A.mark}, n,
               A.part, &tot[kTotValid]);
         flip = onesweep<uint64_t, true>(c, A.keys0, A.keys1, A.vals0, A.vals1,
-                                        (const uint32_t*)n_valid, n, bits, A.state, err);
+                                        (const uint32_t*)n_valid, n, bits, A.state, err,
+                                        g->spin_limit);
     } else if (n <= kOsTile && bits > 0) {
         const uint64_t sentinel = bits >= 64 ? ~0ull : (1ull << bits) - 1;
         c.launch("pack", k_pack_sort_tile, 1, kOsThreads, v, src, dst, n, os_passes(bits),
@@ -1535,18 +1600,19 @@ void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t*
         const uint64_t sentinel = bits >= 64 ? ~0ull : (1ull << bits) - 1;
         c.launch("pack", k_pack_hist, os_hist_groups(n), kOsThreads, v, src, dst, n,
                  bits > 0 ? os_passes(bits) : 0, sentinel, A.keys0, A.mark, A.state,
-                 A.state_words, os_hpart(A.state, n, bits), A.vpart);
-        os_hist_sum(c, A.state, n, bits, (const uint32_t*)A.vpart, &tot[kTotValid]);
+                 A.state_words, os_hpart(A.state, n, bits), A.vpart, A.hpart);
+        os_hist_sum(c, A.state, n, bits, (const uint32_t*)A.vpart, &tot[kTotValid],
+                    (const unsigned long long*)A.hpart, &tot[kTotHash]);
         flip = onesweep_passes<uint64_t, false>(c, A.keys0, A.keys1, nullptr, nullptr, nullptr, n,
-                                                bits, A.state, err);
+                                                bits, A.state, err, g->spin_limit);
     }
     const uint64_t* keys = flip ? A.keys1 : A.keys0;
     const uint32_t* vals = flip ? A.vals1 : A.vals0;
 
-    scan2(c, "segments", SegIn{keys, n_valid, v.L},
-          SegOut{v.L, A.flags, A.a, A.t_vtx, A.t_start}, n, A.part,
+    scan2(c, "segments", SegIn{keys, ctr, v.L},
+          SegOut{v.L, A.flags, A.a, A.t_vtx, A.t_start, ctr}, n, A.part,
           &tot[kTotSeg]);
-    scan2(c, "items", ItemIn{v, A.t_vtx, A.t_start}, ItemOut{A.items, A.small, v.B}, n, A.part,
+    scan2(c, "items", ItemIn{v, A.t_vtx, A.t_start}, ItemOut{A.items, A.small, v.B, icap}, n, A.part,
           &tot[kTotItems]);
     const uint64_t pwant = div_up(icap, kWaves * kGroupsPerWave);
     auto pgrid_of = [&](auto kernel) { return std::min<uint64_t>(pwant, resident_grid(kernel, kThreads)); };
@@ -1555,7 +1621,7 @@ void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t*
     if (mode == kInsert) {
         c.launch("probe_insert", k_probe<kInsert>, pgrid_of(k_probe<kInsert>), kThreads, v, keys, (const Item*)A.items, (const Item*)A.small,
                  A.mark, (uint32_t*)nullptr);
-        scan2(c, "keep", KeepIn{A.flags, A.mark, n_valid}, U32Out{A.b}, n + 1, A.part,
+        scan2(c, "keep", KeepIn{A.flags, A.mark, ctr}, U32Out{A.b}, n + 1, A.part,
               &tot[kTotA]);
         c.launch("plan_insert", k_plan_ins, grid, kThreads, v, (const uint32_t*)A.t_vtx,
                  (const uint32_t*)A.t_start, (const uint32_t*)A.b, A.t_need, A.t_dreq, A.t_drank,
@@ -1575,7 +1641,7 @@ void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t*
     } else if (mode == kDelete) {
         c.launch("probe_delete", k_probe<kDelete>, pgrid_of(k_probe<kDelete>), kThreads, v, keys, (const Item*)A.items, (const Item*)A.small,
                  A.mark, A.hitpos);
-        scan2(c, "found", FoundIn{A.mark, n_valid}, U32Out{A.b}, n + 1, A.part, &tot[kTotA]);
+        scan2(c, "found", FoundIn{A.mark, ctr}, U32Out{A.b}, n + 1, A.part, &tot[kTotA]);
         scan2(c, "freed", FreedIn{v, A.t_vtx, A.t_start, A.b},
               FreedOut{ctr, A.cdesc, A.big, A.heavy}, n, A.part, &tot[kTotB]);
         const uint32_t nbig = kBigGroups;

@@ -14,6 +14,7 @@ struct gv_graph {
     gv::Scratch vscr[3];          // vertex-batch buffers that outlive an inner edge batch
     uint64_t table_gen = 0;       // counts vertex-table reallocations
     uint64_t item_slots = 0;      // bound on live adjacency slots (pool slots)
+    uint32_t spin_limit = gv::kSpinLimitDefault;  // bound on each look-back wait of batch sorts
     // device allocations owned by the graph
     void* mem_pool = nullptr;
     void* mem_free = nullptr;

@@ -224,121 +224,25 @@ bool radix_sort(Ctx& c, K* k0, K* k1, uint32_t* v0, uint32_t* v1, uint64_t n, in
 }  // namespace gv
 
 // ======================================================================
-// Single-pass primitives with decoupled look-back.  Their per-tile status
-// words and tile counters live in a caller-provided region that must be zero
-// before the launch (the batch pipeline clears it in its first kernel).
-// Tiles take ids from an atomic counter in launch order, so every tile a
-// tile waits for is already running; every wait is bounded, and a wait that
-// runs out sets an error flag instead of hanging.
+// Primitives with decoupled look-back between workgroups.  Look-back status
+// words live in a caller-provided region that must be zero before the launch
+// (the batch pipeline clears it in its first kernel).  Every wait is bounded:
+// a wait that runs out sets an error flag instead of hanging, and the callers
+// treat the result as failed.
 // ======================================================================
 namespace gv {
 
-constexpr uint64_t kFlagAgg = 1ull << 62;
-constexpr uint64_t kFlagIncl = 2ull << 62;
-constexpr uint64_t kValMask = (1ull << 62) - 1;
-constexpr uint32_t kSpinLimit = 1u << 24;
+constexpr uint32_t kSpinLimit = kSpinLimitDefault;
 
 constexpr int kScan1Items = 8;
-constexpr uint64_t kScan1Tile = (uint64_t)kThreads * kScan1Items;  // 2048
 
-__device__ __forceinline__ unsigned long long ld_acquire(unsigned long long* p) {
+// Status words carry their own value (flag and count in one word), so no other
+// data is ordered by them: relaxed loads and stores at device scope suffice.
+__device__ __forceinline__ uint32_t ld_status32(uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void st_release(unsigned long long* p, unsigned long long v) {
+__device__ __forceinline__ void st_status32(uint32_t* p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint32_t ld_acquire32(uint32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_release32(uint32_t* p, uint32_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Region for one single-pass scan: word 0 = tile counter, words 1.. = status.
-inline uint64_t scan1_words(uint64_t n) { return 1 + div_up(std::max<uint64_t>(n, 1), kScan1Tile); }
-
-// Exclusive prefix of `tile` from the status words of the tiles before it.
-// Called by one full wave; lane 0 of the nearest window slot is tile-1.
-__device__ __forceinline__ unsigned long long scan1_lookback(unsigned long long* status,
-                                                             int64_t tile, uint32_t* err) {
-    const int lane = lane_id();
-    unsigned long long prefix = 0;
-    int64_t end = tile;
-    while (true) {
-        const int64_t j = end - 1 - lane;
-        unsigned long long w = kFlagIncl;  // before tile 0: inclusive zero
-        if (j >= 0) {
-            uint32_t spins = 0;
-            do {
-                w = ld_acquire(&status[j]);
-            } while ((w >> 62) == 0 && ++spins < kSpinLimit);
-            if ((w >> 62) == 0) {
-                *err = 1;
-                w = kFlagIncl;
-            }
-        }
-        const uint64_t incl = ballot((w >> 62) == 2);
-        const int first = incl ? (int)__ffsll((unsigned long long)incl) - 1 : 64;
-        unsigned long long v = lane <= first ? (w & kValMask) : 0ull;
-        prefix += wave_sum(v);
-        if (incl) break;
-        end -= 64;
-    }
-    return prefix;
-}
-
-// Exclusive scan of in(i), i < n (values < 2^62), written as out(i, prefix);
-// the grand total goes to *total when non-null.  One launch.
-template <typename In, typename Out>
-__global__ __launch_bounds__(kThreads) void k_scan1(In in, Out out, uint64_t n,
-                                                    unsigned long long* region,
-                                                    unsigned long long* total, uint32_t* err) {
-    __shared__ uint32_t s_tile;
-    __shared__ unsigned long long s_w[kWaves];
-    __shared__ unsigned long long s_prefix;
-    if (threadIdx.x == 0) s_tile = atomicAdd((uint32_t*)region, 1u);
-    __syncthreads();
-    const uint64_t tile = s_tile;
-    unsigned long long* status = region + 1;
-    const uint64_t base = tile * kScan1Tile + (uint64_t)threadIdx.x * kScan1Items;
-    unsigned long long v[kScan1Items];
-    unsigned long long local = 0;
-#pragma unroll
-    for (int j = 0; j < kScan1Items; ++j) {
-        const uint64_t i = base + j;
-        v[j] = i < n ? (unsigned long long)in(i) : 0ull;
-        local += v[j];
-    }
-    unsigned long long tot;
-    const unsigned long long ex = block_excl_scan(local, s_w, tot);
-    if (threadIdx.x < 64) {
-        unsigned long long prefix = 0;
-        if (tile == 0) {
-            if (threadIdx.x == 0) st_release(&status[0], kFlagIncl | tot);
-        } else {
-            if (threadIdx.x == 0) st_release(&status[tile], kFlagAgg | tot);
-            prefix = scan1_lookback(status, (int64_t)tile, err);
-            if (threadIdx.x == 0) st_release(&status[tile], kFlagIncl | (prefix + tot));
-        }
-        if (threadIdx.x == 0) s_prefix = prefix;
-    }
-    __syncthreads();
-    unsigned long long run = s_prefix + ex;
-#pragma unroll
-    for (int j = 0; j < kScan1Items; ++j) {
-        const uint64_t i = base + j;
-        if (i < n) out(i, run);
-        run += v[j];
-    }
-    if (total && tile == gridDim.x - 1 && threadIdx.x == kThreads - 1) *total = run;
-}
-
-template <typename In, typename Out>
-void scan1(Ctx& c, const char* name, In in, Out out, uint64_t n, unsigned long long* region,
-           unsigned long long* total, uint32_t* err) {
-    if (n == 0) return;
-    c.launch(name, k_scan1<In, Out>, div_up(n, kScan1Tile), kThreads, in, out, n, region, total,
-             err);
 }
 
 // ---------------------------------------------------------------- scan2
@@ -361,7 +265,12 @@ void scan1(Ctx& c, const char* name, In in, Out out, uint64_t n, unsigned long l
 //                                       (same rules)
 //   ull value(uint64_t i, const Rec&)   the element's value (called when ok)
 // The sink takes (i, rec, lim, exclusive prefix) for every i < n; the
-// element is live when i < lim.
+// element is live when i < lim.  A sink may also define
+//   ull tally(uint64_t i, const Rec&)   a 64-bit value per live element
+//   void commit(ull sum)                called once per workgroup with the sum
+// and
+//   void finish()                       run by the first wave of the last
+//                                       workgroup once the total is written
 // Elements per thread: In::kItems when the source defines it (sources with
 // large records take fewer, to keep registers low), else kScan1Items.
 template <typename In, typename = void>
@@ -372,6 +281,11 @@ template <typename In>
 struct scan2_items<In, std::void_t<decltype(In::kItems)>> {
     static constexpr int value = In::kItems;
 };
+template <typename Out, typename = void>
+struct scan2_has_tally : std::false_type {};
+template <typename Out>
+struct scan2_has_tally<Out, std::void_t<decltype(std::declval<const Out&>().commit(0ull))>>
+    : std::true_type {};
 template <typename Out, typename = void>
 struct scan2_has_finish : std::false_type {};
 template <typename Out>
@@ -474,6 +388,18 @@ __global__ __launch_bounds__(kThreads) void k_scan2_apply(In in, Out out, uint64
         run += tot;
     }
     if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == kThreads - 1) *total = run;
+    if constexpr (scan2_has_tally<Out>::value) {
+        // a sink may add up a 64-bit tally of the live elements: one sum per
+        // workgroup goes to out.commit()
+        unsigned long long t = 0;
+#pragma unroll
+        for (int j = 0; j < kI; ++j) {
+            const uint64_t i = base + (uint64_t)j * kThreads;
+            t += i < lim ? out.tally(i, r[j]) : 0ull;
+        }
+        t = block_sum(t, s_p);
+        if (threadIdx.x == 0) out.commit(t);
+    }
     if constexpr (scan2_has_finish<Out>::value) {
         // a sink may finish the scan in its last workgroup: the first wave
         // runs out.finish() once the total is written
@@ -652,19 +578,22 @@ __global__ __launch_bounds__(kOsThreads) void k_os_hist(const K* keys, const uin
 // workgroup takes 16 counters, its 16 row groups each add every 16th
 // workgroup's count with independent loads, LDS adds the row groups
 // (when vpart is given, workgroup 0 also adds the groups' vpart counts into
-// *vtotal)
-static __global__ __launch_bounds__(kThreads) void k_os_hist_sum(const uint32_t* hpart,
-                                                                 uint32_t groups, uint32_t words,
-                                                                 uint32_t* hist,
-                                                                 const uint32_t* vpart,
-                                                                 unsigned long long* vtotal) {
+// *vtotal, and their kpart sums into *ktotal)
+static __global__ __launch_bounds__(kThreads) void k_os_hist_sum(
+    const uint32_t* hpart, uint32_t groups, uint32_t words, uint32_t* hist, const uint32_t* vpart,
+    unsigned long long* vtotal, const unsigned long long* kpart, unsigned long long* ktotal) {
     __shared__ uint32_t red[16][17];
     __shared__ unsigned long long s_v[kWaves];
     if (vpart && blockIdx.x == 0) {
         static_assert(kHistGroups <= kThreads, "one thread per histogram group");
         const unsigned long long x = threadIdx.x < groups ? vpart[threadIdx.x] : 0u;
         const unsigned long long t = block_sum(x, s_v);
-        if (threadIdx.x == 0) *vtotal = t;
+        const unsigned long long y = threadIdx.x < groups ? kpart[threadIdx.x] : 0ull;
+        const unsigned long long u = block_sum(y, s_v);
+        if (threadIdx.x == 0) {
+            *vtotal = t;
+            *ktotal = u;
+        }
     }
     if (words == 0) return;
     const uint32_t col = threadIdx.x & 15, rg = threadIdx.x >> 4;
@@ -697,7 +626,8 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const K* kin, K* kout, c
                                                         uint64_t n_max, int shift,
                                                         const uint32_t* hist, uint32_t* status,
                                                         uint32_t* gstatus, uint32_t* counter,
-                                                        int block_tiles, uint32_t* err) {
+                                                        int block_tiles, uint32_t* err,
+                                                        uint32_t spin_limit) {
     // cnt[round * waves + wave][digit]: counts, then exclusive prefixes
     __shared__ uint16_t cnt[kOsRounds * kOsWaves][kRadix];
     __shared__ uint32_t part[4][kRadix];
@@ -784,7 +714,7 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const K* kin, K* kout, c
         // of the earlier tiles of the tile's group of kOsGroup; the group's
         // last tile publishes the group total; then the four lanes add the
         // totals of the earlier groups.
-        if (t < kRadix) st_release32(status + tile * kRadix + t, kOsAgg | dcount);
+        if (t < kRadix) st_status32(status + tile * kRadix + t, kOsAgg | dcount);
         const uint32_t ld = t >> 2, lq = t & 3, gbase = lane_id() & ~3u;
         const uint64_t G = tile / kOsGroup;
         auto wait_sum = [&](uint32_t* base, uint64_t first, uint64_t end) {
@@ -792,18 +722,17 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const K* kin, K* kout, c
 #pragma unroll
             for (int kk = 0; kk < kOsLookK; ++kk) {
                 const uint64_t j = first + lq * kOsLookK + kk;
-                wv[kk] = j < end ? ld_acquire32(base + j * kRadix + ld) : kOsAgg;
+                wv[kk] = j < end ? ld_status32(base + j * kRadix + ld) : kOsAgg;
             }
             uint32_t sum = 0;
 #pragma unroll
             for (int kk = 0; kk < kOsLookK; ++kk) {
                 const uint64_t j = first + lq * kOsLookK + kk;
-                if ((wv[kk] >> 30) == 0) {
+                if ((wv[kk] >> 30) == 0 || spin_limit == 0) {
                     uint32_t spins = 0;
-                    do {
-                        wv[kk] = ld_acquire32(base + j * kRadix + ld);
-                    } while ((wv[kk] >> 30) == 0 && ++spins < kSpinLimit);
-                    if ((wv[kk] >> 30) == 0) {
+                    while ((wv[kk] >> 30) == 0 && spins++ < spin_limit)
+                        wv[kk] = ld_status32(base + j * kRadix + ld);
+                    if ((wv[kk] >> 30) == 0 || spin_limit == 0) {
                         *err = 1;
                         wv[kk] = kOsAgg;
                     }
@@ -819,7 +748,7 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const K* kin, K* kout, c
         const uint32_t local = wait_sum(status, G * kOsGroup, tile);
         if (tile % kOsGroup == kOsGroup - 1 && lq == 0) {
             const uint32_t own = part[0][ld] + part[1][ld] + part[2][ld] + part[3][ld];
-            st_release32(gstatus + G * kRadix + ld, kOsAgg | (local + own));
+            st_status32(gstatus + G * kRadix + ld, kOsAgg | (local + own));
         }
         uint32_t global = 0;
         for (uint64_t g0 = 0; g0 < G; g0 += kOsGroup) global += wait_sum(gstatus, g0, G);
@@ -829,7 +758,7 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const K* kin, K* kout, c
     // per digit: each round a lane reads the status of kOsLookK earlier
     // tiles with independent loads, and the four lanes add them, newest
     // first, up to the first inclusive one
-    if (t < kRadix) st_release32(status + tile * kRadix + t, (tile == 0 ? kOsIncl : kOsAgg) | dcount);
+    if (t < kRadix) st_status32(status + tile * kRadix + t, (tile == 0 ? kOsIncl : kOsAgg) | dcount);
     {
         const uint32_t ld = t >> 2, lq = t & 3, gbase = lane_id() & ~3u;
         uint32_t lp = 0;
@@ -841,17 +770,16 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const K* kin, K* kout, c
             for (int kk = 0; kk < kOsLookK; ++kk) {
                 const int64_t j = j0 - (int64_t)(lq * kOsLookK + kk);
                 // before tile 0: an inclusive zero
-                wv[kk] = j >= 0 ? ld_acquire32(status + (uint64_t)j * kRadix + ld) : kOsIncl;
+                wv[kk] = j >= 0 ? ld_status32(status + (uint64_t)j * kRadix + ld) : kOsIncl;
             }
 #pragma unroll
             for (int kk = 0; kk < kOsLookK; ++kk) {
                 const int64_t j = j0 - (int64_t)(lq * kOsLookK + kk);
-                if ((wv[kk] >> 30) == 0) {
+                if ((wv[kk] >> 30) == 0 || (spin_limit == 0 && j >= 0)) {
                     uint32_t spins = 0;
-                    do {
-                        wv[kk] = ld_acquire32(status + (uint64_t)j * kRadix + ld);
-                    } while ((wv[kk] >> 30) == 0 && ++spins < kSpinLimit);
-                    if ((wv[kk] >> 30) == 0) {
+                    while ((wv[kk] >> 30) == 0 && spins++ < spin_limit)
+                        wv[kk] = ld_status32(status + (uint64_t)j * kRadix + ld);
+                    if ((wv[kk] >> 30) == 0 || spin_limit == 0) {
                         *err = 1;
                         wv[kk] = kOsIncl;
                     }
@@ -885,7 +813,7 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const K* kin, K* kout, c
     __syncthreads();
     const uint32_t prefix = t < kRadix ? lb_prefix[t] : 0u;
     if (!block_tiles && t < kRadix && tile > 0)
-        st_release32(status + tile * kRadix + t, kOsIncl | (prefix + dcount));
+        st_status32(status + tile * kRadix + t, kOsIncl | (prefix + dcount));
     // global start of each digit (pass histogram) and start inside the tile:
     // one scan of both, the histogram in the high half (neither half carries)
     unsigned long long tot;
@@ -930,7 +858,12 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const K* kin, K* kout, c
 
 template <typename K, bool HasVal>
 bool onesweep_passes(Ctx& c, K* k0, K* k1, uint32_t* v0, uint32_t* v1, const uint32_t* n_dev,
-                     uint64_t n_max, int bits, uint32_t* state, uint32_t* err);
+                     uint64_t n_max, int bits, uint32_t* state, uint32_t* err,
+                     uint32_t spin_limit = kSpinLimit);
+
+// Look-back counts are 30-bit fields of the status words: a sort takes fewer
+// than 2^30 keys.
+constexpr uint64_t kOsMaxKeys = 1ull << 30;
 
 // Sorts n keys (n on the device when n_dev != null, n_max bounds it) by bits
 // [0, bits), stably, ping-ponging k0/k1 (v0/v1).  `state` must hold
@@ -938,9 +871,10 @@ bool onesweep_passes(Ctx& c, K* k0, K* k1, uint32_t* v0, uint32_t* v1, const uin
 // zeroed.  Returns true if the result is in k1/v1.
 template <typename K, bool HasVal>
 bool onesweep(Ctx& c, K* k0, K* k1, uint32_t* v0, uint32_t* v1, const uint32_t* n_dev,
-              uint64_t n_max, int bits, uint32_t* state, uint32_t* err) {
+              uint64_t n_max, int bits, uint32_t* state, uint32_t* err,
+              uint32_t spin_limit = kSpinLimit) {
     if (n_max <= 1 || bits <= 0) return false;
-    if (n_max > 0xffffffffull) fail(GV_EINVAL, "sort too large");
+    if (n_max >= kOsMaxKeys) fail(GV_EINVAL, "sort of 2^30 or more keys");
     const int passes = os_passes(bits);
     if (passes > 8) fail(GV_EINVAL, "too many radix passes");
     const uint64_t hg = os_hist_groups(n_max);
@@ -949,8 +883,10 @@ bool onesweep(Ctx& c, K* k0, K* k1, uint32_t* v0, uint32_t* v1, const uint32_t* 
     uint32_t* hpart = hist + hwords;      // per histogram workgroup
     c.launch("sort_hist", k_os_hist<K>, hg, kOsThreads, (const K*)k0, n_dev, n_max, passes, hpart);
     c.launch("sort_hist", k_os_hist_sum, div_up(hwords, 16), kThreads, (const uint32_t*)hpart,
-             (uint32_t)hg, hwords, hist, (const uint32_t*)nullptr, (unsigned long long*)nullptr);
-    return onesweep_passes<K, HasVal>(c, k0, k1, v0, v1, n_dev, n_max, bits, state, err);
+             (uint32_t)hg, hwords, hist, (const uint32_t*)nullptr, (unsigned long long*)nullptr,
+             (const unsigned long long*)nullptr, (unsigned long long*)nullptr);
+    return onesweep_passes<K, HasVal>(c, k0, k1, v0, v1, n_dev, n_max, bits, state, err,
+                                      spin_limit);
 }
 
 // Per-group digit counts of a sort whose histogram kernel is fused into the
@@ -962,22 +898,24 @@ inline uint32_t* os_hpart(uint32_t* state, uint64_t n_max, int bits) {
 }
 
 // Adds the per-group counts into the pass histograms; with vpart, also adds
-// os_hist_groups(n_max) per-group counts into *vtotal.  One launch, also when
-// there is nothing to sort.
+// os_hist_groups(n_max) per-group counts into *vtotal and the groups' 64-bit
+// kpart sums into *ktotal.  One launch, also when there is nothing to sort.
 inline void os_hist_sum(Ctx& c, uint32_t* state, uint64_t n_max, int bits, const uint32_t* vpart,
-                        unsigned long long* vtotal) {
+                        unsigned long long* vtotal, const unsigned long long* kpart,
+                        unsigned long long* ktotal) {
     const uint32_t hwords = bits > 0 ? (uint32_t)os_passes(bits) * kRadix : 0u;
     c.launch("sort_hist", k_os_hist_sum, std::max<uint64_t>(div_up(hwords, 16), 1), kThreads,
              (const uint32_t*)os_hpart(state, n_max, bits), (uint32_t)os_hist_groups(n_max), hwords,
-             state + os_zero_words(n_max, bits), vpart, vtotal);
+             state + os_zero_words(n_max, bits), vpart, vtotal, kpart, ktotal);
 }
 
 // The passes of onesweep, once the pass histograms are in the state.
 template <typename K, bool HasVal>
 bool onesweep_passes(Ctx& c, K* k0, K* k1, uint32_t* v0, uint32_t* v1, const uint32_t* n_dev,
-                     uint64_t n_max, int bits, uint32_t* state, uint32_t* err) {
+                     uint64_t n_max, int bits, uint32_t* state, uint32_t* err,
+                     uint32_t spin_limit) {
     if (n_max <= 1 || bits <= 0) return false;
-    if (n_max > 0xffffffffull) fail(GV_EINVAL, "sort too large");
+    if (n_max >= kOsMaxKeys) fail(GV_EINVAL, "sort of 2^30 or more keys");
     const int passes = os_passes(bits);
     if (passes > 8) fail(GV_EINVAL, "too many radix passes");
     const uint64_t nt = os_tiles(n_max);
@@ -997,7 +935,7 @@ bool onesweep_passes(Ctx& c, K* k0, K* k1, uint32_t* v0, uint32_t* v1, const uin
                  (const uint32_t*)vin, vout, n_dev, n_max, p * kRadixBits,
                  (const uint32_t*)(hist + (uint64_t)p * kRadix),
                  status + (uint64_t)p * nt * kRadix, gstatus + (uint64_t)p * ng * kRadix,
-                 counters + p, block_tiles, err);
+                 counters + p, block_tiles, err, spin_limit);
         flip = !flip;
     }
     return flip;

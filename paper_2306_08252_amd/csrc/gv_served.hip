@@ -97,7 +97,7 @@ void mixed_edges(gv_graph* g, const uint8_t* op, const uint32_t* src, const uint
     c.launch("mixed_pack", k_mixed_pack, div_up(n, kThreads), kThreads, v, op, src, dst, n, k0,
              p0);
     const bool flip = onesweep<uint64_t, true>(c, k0, k1, p0, p1, nullptr, n, bits, state,
-                                               &v.ctr->err_wait);
+                                               &v.ctr->err_wait, g->spin_limit);
     c.launch("mixed_split", k_mixed_split, div_up(n, kThreads), kThreads, v,
              (const uint64_t*)(flip ? k1 : k0), (const uint32_t*)(flip ? p1 : p0), op, n, ins_src,
              ins_dst, del_src, del_dst);

@@ -18,8 +18,7 @@ import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# GRAPHVINE_LIB selects another build of the same library (tuning variants)
-LIB_PATH = os.environ.get("GRAPHVINE_LIB", os.path.join(HERE, "libgraphvine.so"))
+LIB_PATH = os.path.join(HERE, "libgraphvine.so")
 
 GV_OK, GV_EINVAL, GV_ERANGE, GV_ENOMEM, GV_EDEVICE = 0, 1, 2, 3, 4
 
@@ -108,6 +107,7 @@ def lib():
             "gv_kernel_times": [vp, C.c_char_p, u64p, C.POINTER(C.c_double)],
             "gv_kernel_names": [vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)],
             "gv_set_stream": [vp, vp],
+            "gv_debug_spin_limit": [vp, C.c_uint32],
             "gv_sync": [vp],
             "gv_apply_ops": [vp, C.POINTER(gv_op), C.c_uint64],
             "gv_plan_create": [vp, C.POINTER(gv_op), C.c_uint64, C.POINTER(C.c_void_p)],
@@ -349,6 +349,10 @@ def gv_set_stream(g, stream_ptr):
 
 def gv_sync(g):
     return lib().gv_sync(C.c_void_p(g))
+
+
+def gv_debug_spin_limit(g, limit):
+    _check(lib().gv_debug_spin_limit(C.c_void_p(g), int(limit)), "gv_debug_spin_limit")
 
 
 def gv_graph_destroy(g):
