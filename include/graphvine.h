@@ -181,6 +181,19 @@ int gv_apply_edge_ops(gv_graph* g, const uint8_t* d_op, const uint32_t* d_src,
 int gv_edge_exists(gv_graph* g, const uint32_t* d_src, const uint32_t* d_dst,
                    uint64_t n, uint8_t* d_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): gv_edge_exists
+ * with every temporary of the query batch in one fixed 64 MiB device array
+ * per GPU (a static __device__ array, looked up at graph creation), so the
+ * call allocates nothing.  n <= 2^18 pairs, and the batch's temporaries
+ * (about 120 bytes per pair plus 32 bytes per 256 pool slots of the graph)
+ * must fit the array: GV_ERANGE otherwise, before any device work.  Same
+ * arguments, result and asynchrony as gv_edge_exists.  Every call on one GPU
+ * shares the array: calls that overlap on a GPU (several graphs or streams)
+ * race and must be serialised by the caller. */
+int gv_edge_exists_noalloc(gv_graph* g, const uint32_t* d_src, const uint32_t* d_dst,
+                           uint64_t n, uint8_t* d_out);
+
 /* Adjacency of v in ascending order into d_out (device, out_capacity
  * entries).  *degree is always set when v < capacity.  v >= capacity gives
  * GV_ERANGE with *degree = 0; out_capacity < degree gives GV_ERANGE with

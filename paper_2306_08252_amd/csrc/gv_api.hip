@@ -124,6 +124,7 @@ int gv_graph_init(gv_graph** out, uint64_t num_vertices, const uint32_t* d_src,
         v.vt = (VRec*)g->mem_vt;
         v.active = (uint32_t*)g->mem_active;
         v.ctr = (DevCounters*)g->mem_ctr;
+        noalloc_setup();
         bulk_build(g, num_vertices, d_src, d_dst, num_edges, c);
     } catch (const Error& e) {
         free_graph(g);
@@ -204,6 +205,14 @@ int gv_edge_exists(gv_graph* g, const uint32_t* d_src, const uint32_t* d_dst, ui
     if (n && (!d_src || !d_dst || !d_out)) return GV_EINVAL;
     if (n == 0) return GV_OK;
     return guarded(g, [&] { edge_batch(g, kQuery, d_src, d_dst, n, d_out, true); });
+}
+
+int gv_edge_exists_noalloc(gv_graph* g, const uint32_t* d_src, const uint32_t* d_dst,
+                           uint64_t n, uint8_t* d_out) {
+    if (!g) return GV_EINVAL;
+    if (n && (!d_src || !d_dst || !d_out)) return GV_EINVAL;
+    if (n == 0) return GV_OK;
+    return guarded(g, [&] { gv_noalloc_query(g, d_src, d_dst, n, d_out); });
 }
 
 int gv_apply_edge_ops(gv_graph* g, const uint8_t* d_op, const uint32_t* d_src,

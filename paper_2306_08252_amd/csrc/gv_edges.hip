@@ -1561,7 +1561,7 @@ size_t edge_batch_bytes(const gv_graph* g, EdgeMode mode, uint64_t n) {
 }
 
 void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t* dst, uint64_t n,
-                uint8_t* out, bool sticky) {
+                uint8_t* out, bool sticky, void* fixed, size_t fixed_bytes) {
     if (n == 0) return;
     if (n >= 0x3fffffffull) fail(GV_EINVAL, "batch too large");
     Ctx& c = g->ctx;
@@ -1572,8 +1572,14 @@ void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t*
     {
         Carver m(nullptr);
         carve_batch(m, A, n, icap, mode, bits);
-        g->scratch.ensure(m.used, c.stream);
-        Carver cv(g->scratch.ptr);
+        void* base = fixed;
+        if (fixed) {
+            if (m.used > fixed_bytes) fail(GV_ERANGE, "batch does not fit the fixed scratch");
+        } else {
+            g->scratch.ensure(m.used, c.stream);
+            base = g->scratch.ptr;
+        }
+        Carver cv(base);
         carve_batch(cv, A, n, icap, mode, bits);
     }
     DevCounters* ctr = v.ctr;

@@ -32,8 +32,24 @@ enum EdgeMode { kInsert = 0, kDelete = 1, kQuery = 2 };
 
 // queue one batched edge operation on the graph's stream (no host sync);
 // `sticky` makes an allocation failure visible to later gv_sync calls
+// `fixed` (optional): carve the batch's temporaries from this device buffer of
+// fixed_bytes instead of the graph's growable scratch (GV_ERANGE if they do
+// not fit); nothing is allocated then
 void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t* dst,
-                uint64_t n, uint8_t* out, bool sticky);
+                uint64_t n, uint8_t* out, bool sticky, void* fixed = nullptr,
+                size_t fixed_bytes = 0);
+
+// the per-device address of the fixed scratch of gv_edge_exists_noalloc,
+// looked up once per device (graph creation calls it with the device current)
+void noalloc_setup();
+
+}  // namespace gv
+
+// the query batch of gv_edge_exists_noalloc (gv_noalloc.hip)
+void gv_noalloc_query(gv_graph* g, const uint32_t* d_src, const uint32_t* d_dst, uint64_t n,
+                      uint8_t* d_out);
+
+namespace gv {
 
 // a list of (op, src, dst) entries, op 0 insert / 1 delete, applied as if one
 // at a time in list order (last-writer reduction, then one delete batch and
