@@ -68,6 +68,8 @@ constexpr uint32_t kLaneCopy = 8;              // directory entries a lane copie
 constexpr uint32_t kLaneSeg = 16;              // segment entries a lane compacts
 constexpr uint32_t kLaneR = 8;                 // hits a lane compacts
 constexpr uint32_t kRelease = 0x80000000u;     // flag bit in the per-source demand
+constexpr uint32_t kHeavy = 0x100u;            // flag bit in t_dreq: whole waves grow this source
+constexpr uint32_t kClassMask = 0xFFu;         // t_dreq & kClassMask: requested class or kNoDir
 
 // scan-total slots in DevCounters::tot
 enum { kTotValid = 0, kTotSeg = 1, kTotItems = 2, kTotA = 3, kTotB = 4, kTotHash = 5 };
@@ -925,8 +927,11 @@ __global__ __launch_bounds__(kThreads) void k_plan_ins(GraphView g, const uint32
         }
         // top bit: the source gives back a directory segment
         t_need[t] = (nb1 - nb0) | (cls != kNoDir && r.dcls != kNoDir ? kRelease : 0u);
-        t_dreq[t] = cls;
         big = (cls != kNoDir && nb0 > kLaneCopy) || nb1 - nb0 > kLaneCopy;
+        // the grow kernel takes this decision from here: its heavy sources'
+        // records change while other waves still run the lane loop, so it
+        // must not be made again from the record there
+        t_dreq[t] = cls | (big ? kHeavy : 0u);
     }
     wave_append(big, (uint32_t)t, &g.ctr->n_heavy, heavy);
     __syncthreads();
@@ -1082,7 +1087,10 @@ __device__ __forceinline__ uint32_t planned_segment(const GraphView& g, const De
 // when its block count outgrows its directory segment, a new segment holding
 // a copy of the old entries) and its new vertex record.  A lane takes a
 // source that copies and adds at most kLaneCopy entries; the others, listed
-// by the planning kernel, are taken by whole waves afterwards.
+// (and flagged kHeavy) by the planning kernel, are taken by whole waves.
+// The lane loop skips the flagged sources by the flag: a wave that has left
+// the lane loop may already have written a heavy source's new record, and a
+// decision made again from that record could take the source a second time.
 __global__ __launch_bounds__(kThreads) void k_grow(GraphView g, const uint32_t* t_vtx,
                                                    const uint32_t* t_start, const uint32_t* b,
                                                    const uint32_t* t_need, const uint32_t* t_dreq,
@@ -1097,12 +1105,12 @@ __global__ __launch_bounds__(kThreads) void k_grow(GraphView g, const uint32_t* 
         const bool live = base + lane < nT;
         const uint32_t t = live ? base + lane : nT - 1;
         const uint32_t v = t_vtx[t], lo = t_start[t], hi = t_start[t + 1];
-        const uint32_t p0 = t_need[t], cls = t_dreq[t], rk = t_drank[t];
-        const VRec r = g.vt[v];
+        const uint32_t p0 = t_need[t], req = t_dreq[t], rk = t_drank[t];
         const uint32_t kp = b[hi] - b[lo];
+        if (!live || !kp || (req & kHeavy)) continue;
+        const uint32_t cls = req & kClassMask;
+        const VRec r = g.vt[v];  // only this lane writes it
         const uint32_t nb0 = nblocks(g, r.deg), nb1 = nblocks(g, r.deg + kp);
-        const bool big = (cls != kNoDir && nb0 > kLaneCopy) || nb1 - nb0 > kLaneCopy;
-        if (!live || !kp || big) continue;
         VRec nr = r;
         nr.deg = r.deg + kp;
         if (cls != kNoDir) {
@@ -1144,7 +1152,7 @@ __global__ __launch_bounds__(kThreads) void k_grow(GraphView g, const uint32_t* 
         const VRec r = g.vt[v];
         const uint32_t kp = b[t_start[t + 1]] - b[t_start[t]];
         const uint32_t nb0 = nblocks(g, r.deg), nb1 = nblocks(g, r.deg + kp);
-        const uint32_t cls = t_dreq[t];
+        const uint32_t cls = t_dreq[t] & kClassMask;
         VRec nr = r;
         nr.deg = r.deg + kp;
         if (cls != kNoDir) {

@@ -7,7 +7,7 @@ structural audit and query answers after every batch.
 import numpy as np
 import pytest
 
-from gpu_helpers import assert_same, need_gpu, same_answers, say, u32
+from gpu_helpers import assert_same, gpu_dump, need_gpu, same_answers, say, u32
 from oracle import pyoracle as O
 from paper_2306_08252_amd import inputs as I
 
@@ -371,4 +371,70 @@ def test_one_workgroup_sort_boundary(size):
         assert_same(g, o, f"insert {size} rep {rep}")
         assert g.delete_edges(d, s) == o.delete_edges(d, s)[1]
         assert_same(g, o, f"delete {size} rep {rep}")
+    g.close()
+
+
+def test_heavy_grow_sources_are_grown_once():
+    """Sources on the edge of the grow kernel's two paths: each needs 9 new
+    blocks of B = 4 (grown by a whole wave) while its next 33 pairs would need
+    only 8 (a lane's share).  The lane loop must skip them by the planning
+    kernel's decision: a record re-read after a wave has grown it would look
+    light and the source would be grown twice (degree + 2k, its new blocks
+    listed twice).  The heavy sources have the largest ids, so their lane-loop
+    visits come last, after millions of light sources (several lane-loop
+    rounds per wave), while the first waves to leave the loop grow them.
+    Exact comparison by set algebra after each batch."""
+    gv = need_gpu()
+    rng = np.random.default_rng(4242)
+    n, B = 1 << 22, 4
+    heavy = np.arange(n - 30000, n, dtype=np.uint32)
+    light = rng.choice(n - 30000, 3_000_000, replace=False).astype(np.uint32)
+
+    def rows(src_ids, deg, exclude=None):
+        s = np.repeat(src_ids, deg)
+        d = rng.integers(0, n, len(s)).astype(np.uint32)
+        keys = np.unique((s.astype(np.uint64) << np.uint64(32)) | d.astype(np.uint64))
+        if exclude is not None:
+            keys = np.setdiff1d(keys, exclude)
+        return keys
+
+    def pick(keys, src_ids, per):
+        # exactly `per` keys of every source in src_ids (keys sorted)
+        s = (keys >> np.uint64(32)).astype(np.uint32)
+        first = np.searchsorted(s, src_ids)
+        cnt = np.searchsorted(s, src_ids, side="right") - first
+        assert (cnt >= per).all()
+        idx = (first[:, None] + np.arange(per)[None, :]).ravel()
+        return keys[idx]
+
+    def split(keys):
+        return (keys >> np.uint64(32)).astype(np.uint32), (keys & np.uint64(0xffffffff)).astype(np.uint32)
+
+    init = np.union1d(pick(rows(heavy, 48), heavy, 36), rows(light, 1))
+    g = gv.Graph(n, *split(init), block_slots=B)
+    have = init
+    for rep in range(2):
+        hnew = pick(rows(heavy, 48, have), heavy, 33)
+        add = np.union1d(hnew, rows(light, 1, have))
+        say(f"heavy grow: batch {rep} with {len(add)} new pairs")
+        sh = rng.permutation(len(add))
+        st = g.insert_edges(*split(add[sh]))
+        assert st == (len(add), 0, 0)
+        have = np.union1d(have, add)
+        offs, dst, _, e = gpu_dump(g)
+        deg = np.diff(offs.astype(np.int64))
+        src = np.repeat(np.arange(len(deg), dtype=np.uint64), deg)
+        got = (src << np.uint64(32)) | dst.astype(np.uint64)
+        if e != len(have):
+            twice = np.nonzero(deg[heavy] != 69)[0]
+            raise AssertionError(f"batch {rep}: {e} edges, want {len(have)}; "
+                                 f"{len(twice)} heavy sources off their degree 69")
+        np.testing.assert_array_equal(got, have, err_msg=f"batch {rep}")
+        m = g.memory_used()
+        assert m["blocks_in_use"] == int(((deg + B - 1) // B).sum())
+        assert g.audit() == 0
+        # back to 36 entries per heavy source for the next batch
+        st = g.delete_edges(*split(hnew))
+        assert st[0] == len(hnew)
+        have = np.setdiff1d(have, hnew)
     g.close()
