@@ -14,8 +14,16 @@ edges/s), batched edge queries, vertex insert/delete batches, an adjacency
 read of the largest hub and the memory report.
 
 roofline: the kernel with the largest share of the step's GPU time, its
-algorithmic bytes per launch (model below) over its average launch time,
-measured with HIP events on the graph's stream inside the timed region.
+algorithmic bytes per launch over its average launch time.  Algorithmic bytes
+follow the bytes-touched model M1 (counted once per batch): the grouping of a
+batch is 16 B per pair (one write and one read of the packed pairs) however
+many radix passes it takes, so a pass is credited 16 B per pair / passes; a
+probe is credited the touched adjacency (4 B per slot, block granular).  The
+launch time comes from HIP events on the graph's stream in a second run of
+the same steps, one event pair per run of consecutive launches of the kernel
+(the passes of one sort share a pair, so the events' own cost is spread over
+them); the committed kernel-trace summary of the same command gives the
+durations without events.
 
 cpu_baseline: the CPU oracle (ordered sets, one thread) applying the same
 batches restricted to a quarter of the sources (those whose SplitMix64 hash
@@ -76,16 +84,16 @@ def bytes_model(name, per_launch):
     adjacencies), NB (blocks per touched adjacency, S / B), W (slots written),
     M (slots moved), NEW / FREED (blocks)."""
     k, T, S, NBLK = per_launch["k"], per_launch["T"], per_launch["S"], per_launch["NB"]
-    if name in ("probe_insert", "probe_delete", "probe_query"):
-        # adjacency slots + their directory entries + one 32-byte work item
-        # per touched source + the sorted batch keys (each read once) + one
-        # mark byte per pair
-        return 4 * S + 4 * NBLK + 32 * T + 8 * k + k
     P = per_launch.get("passes", 5)
+    if name in ("probe_insert", "probe_delete", "probe_query"):
+        # M1: the touched adjacency, scanned once (block-granular slots)
+        return 4 * S
     tiles = (k + 4095) // 4096
     groups = min(tiles, 256)
     if name == "sort_pass":
-        return 16 * k  # one 8-bit digit pass: read and write every key once
+        # M1: grouping is one write and one read of the packed pairs per
+        # batch (16 B per pair), shared by the batch's radix passes
+        return 16 * k / P
     if name == "sort_hist":
         # insert / delete batches: add the per-group digit counts of the
         # packing kernel (and the valid-pair counts) into the pass histograms
@@ -104,6 +112,60 @@ def bytes_model(name, per_launch):
     if name == "compact":
         return 8 * per_launch["M"] + 16 * T + 4 * per_launch["FREED"]
     return None
+
+
+def implementation_bytes(name, per_launch):
+    """What the kernel itself must move per launch (not M1): a radix pass
+    reads and writes every key; a probe also reads directory entries, work
+    items, the batch keys and writes marks."""
+    k, T, S, NBLK = per_launch["k"], per_launch["T"], per_launch["S"], per_launch["NB"]
+    if name == "sort_pass":
+        return 16 * k
+    if name in ("probe_insert", "probe_delete", "probe_query"):
+        return 4 * S + 4 * NBLK + 32 * T + 8 * k + k
+    return None
+
+
+def host_cpu():
+    """CPU model (from /proc/cpuinfo) and the number of logical CPUs."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "cpus_available": avail}
+
+
+def summarize_counters(pmc_dir, out_md, command, title):
+    """Per-kernel averages of every counter in a rocprofv3 --pmc run (library
+    kernels, grouped by kernel and grid size)."""
+    import statistics
+    acc = {}
+    for r in _rows(pmc_dir, "counter_collection"):
+        if "gv::" not in r["Kernel_Name"]:
+            continue
+        wg = int(r["Grid_Size"]) // max(1, int(r["Workgroup_Size"]))
+        acc.setdefault((_short(r["Kernel_Name"]), wg), {}).setdefault(
+            r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    names = sorted({c for v in acc.values() for c in v})
+    lines = ["| kernel | grid (WGs) | dispatches | " + " | ".join(names) + " |",
+             "|---|---|---|" + "---|" * len(names)]
+    for (k, wg), cs in sorted(acc.items(), key=lambda kv: kv[0]):
+        nd = max(len(v) for v in cs.values())
+        vals = [f"{statistics.mean(cs[c]):.0f}" if c in cs else "" for c in names]
+        lines.append(f"| `{k}` | {wg} | {nd} | " + " | ".join(vals) + " |")
+    with open(out_md, "w") as f:
+        f.write(f"# {title}\n\nCommand (GPU box, repo root as $R):\n\n```\n{command}\n```\n\n"
+                "Average counter value per dispatch, library kernels only:\n\n" +
+                "\n".join(lines) + "\n")
 
 
 # library launch names -> kernel symbol prefix in rocprofv3 output
@@ -469,6 +531,9 @@ def main():
     ap.add_argument("--summarize-traffic", nargs=5,
                     metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR", "OUT_MD"),
                     help="write the HBM traffic summary and its JSON (no GPU)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("PMC_DIR", "OUT_MD"),
+                    help="write per-kernel averages of a rocprofv3 --pmc run (no GPU)")
+    ap.add_argument("--title", default="Counters per dispatch")
     ap.add_argument("--command", action="append", default=[],
                     help="command line recorded in a summary")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -477,6 +542,9 @@ def main():
 
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace, "\n".join(args.command))
+        return
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters, "\n".join(args.command), args.title)
         return
     if args.summarize_traffic:
         k = args.batch
@@ -607,6 +675,7 @@ def main():
         per["k"] = k
     per["passes"] = (2 * args.scale + 7) // 8  # 8-bit digits of (src << L) | dst
     bpl = bytes_model(dominant, per)
+    ibpl = implementation_bytes(dominant, per)
     avg_s = dom_ms / 1e3 / dom_launches if dom_launches else None
     roof = None
     if bpl is not None and avg_s:
@@ -614,10 +683,19 @@ def main():
         roof = {"bound": "hbm", "kernel": dominant, "achieved": round(ach, 2),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5),
                 "traffic": stored_traffic(dominant), "bytes_per_launch": int(bpl),
+                "bytes_model": ("M1 share: 16 B per pair per batch, over %d radix passes" % per["passes"]
+                                if dominant == "sort_pass" else
+                                "M1 share: touched adjacency, 4 B per block-granular slot"
+                                if dominant.startswith("probe") else "see DESIGN"),
+                "implementation_bytes_per_launch": None if ibpl is None else int(ibpl),
+                "implementation_frac": None if ibpl is None else
+                round(ibpl / avg_s / 1e9 / HBM_PEAK_GBS, 5),
                 "avg_launch_us": round(avg_s * 1e6, 3), "launches": dom_launches,
+                "step_m1_frac": round(pct_m1, 5),
                 "timed_steps": "a second run of the same number of steps, right after the "
-                               "timed region, with HIP events around every launch of the "
-                               "kernel (%.4f ms per step with the events)" % (elapsed_ev / K * 1e3)}
+                               "timed region, one HIP event pair around each run of "
+                               "consecutive launches of the kernel (%.4f ms per step with the "
+                               "events)" % (elapsed_ev / K * 1e3)}
 
     # ---- queries, in their own loop
     gv.gv_edge_exists(h, *qry[0], dev)
@@ -665,23 +743,28 @@ def main():
         keep_v = (I.mix64(np.arange(n, dtype=np.uint64)) & np.uint64(3)) == 0
         sel = keep_v[src_np]
         o = O.OracleGraph(n, src_np[sel], dst_np[sel], block_slots=B)
-        pairs = 0
-        t0 = time.perf_counter()
+        # the restricted batches are copied to the host and selected before
+        # the clock starts: only the oracle's own work is timed
+        work, pairs = [], 0
         for j in range(min(CPU_STEPS, args.steps)):
             jj = args.warmup + 1 + j
             for batch, fn in ((ins[jj], o.insert_edges), (dels[jj], o.delete_edges)):
                 bs = batch[0].cpu().numpy().view(np.uint32)
                 bd = batch[1].cpu().numpy().view(np.uint32)
                 m = keep_v[bs]
-                fn(bs[m], bd[m])
+                work.append((fn, np.ascontiguousarray(bs[m]), np.ascontiguousarray(bd[m])))
                 pairs += int(m.sum())
+        t0 = time.perf_counter()
+        for fn, bs, bd in work:
+            fn(bs, bd)
         cpu_s = time.perf_counter() - t0
         o.close()
         cpu = {"value": round(pairs / cpu_s, 1), "unit": "edges/s", "cores": 1,
-               "kind": "oracle",
+               "kind": "oracle", **host_cpu(), "threads": 1,
                "sample": f"{min(CPU_STEPS, args.steps)} insert + delete batch pairs whose source "
                          f"hashes to 0 mod 4 ({pairs} pairs) against the graph restricted "
-                         f"to those sources ({int(sel.sum())} edges)"}
+                         f"to those sources ({int(sel.sum())} edges); host copies and "
+                         f"selection outside the timed loop"}
 
     out = {
         "metric": "batch insert/delete edges/s + % HBM peak; init edges/s; served p50/p99 latency",

@@ -67,7 +67,12 @@ uint64_t resident_grid(void (*kernel)(KArgs...), uint32_t block) {
 }
 
 // Kernel launches go through Ctx so that they can be timed with HIP events on
-// the graph's stream when profiling is enabled.
+// the graph's stream when profiling is enabled.  With every kernel timed, each
+// launch gets its own pair of events.  When only one kernel name is timed,
+// one pair of events brackets each run of consecutive launches of it (the
+// radix passes of a sort are one run): an event record costs GPU time of its
+// own, and a run shares one, so the average per launch stays close to the
+// kernels' own durations.
 struct Ctx {
     hipStream_t stream = nullptr;
     bool prof = false;
@@ -75,7 +80,11 @@ struct Ctx {
     struct Rec {
         const char* name;
         hipEvent_t e0, e1;
+        uint64_t launches;
     };
+    hipEvent_t run_e0 = nullptr;   // open run of the timed kernel
+    const char* run_name = nullptr;
+    uint64_t run_n = 0;
     std::vector<Rec> recs;
     std::vector<hipEvent_t> spare;
     struct Sum {
@@ -96,8 +105,19 @@ struct Ctx {
         return e;
     }
 
+    // Closes an open run of the timed kernel (records its end event).
+    void close_run() {
+        if (!run_e0) return;
+        hipEvent_t e1 = event();
+        hip_check(hipEventRecord(e1, stream), "hipEventRecord");
+        recs.push_back({run_name, run_e0, e1, run_n});
+        run_e0 = nullptr;
+        run_n = 0;
+    }
+
     // Fold finished records into per-name sums (synchronises the stream).
     void collect() {
+        close_run();
         if (recs.empty()) return;
         hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
         for (auto& r : recs) {
@@ -106,12 +126,12 @@ struct Ctx {
             bool found = false;
             for (auto& s : sums)
                 if (s.name == r.name) {
-                    s.launches++;
+                    s.launches += r.launches;
                     s.ms += ms;
                     found = true;
                     break;
                 }
-            if (!found) sums.push_back({r.name, 1, (double)ms});
+            if (!found) sums.push_back({r.name, r.launches, (double)ms});
             spare.push_back(r.e0);
             spare.push_back(r.e1);
         }
@@ -119,6 +139,8 @@ struct Ctx {
     }
 
     void release() {
+        if (run_e0) hipEventDestroy(run_e0);
+        run_e0 = nullptr;
         for (auto& r : recs) {
             hipEventDestroy(r.e0);
             hipEventDestroy(r.e1);
@@ -134,6 +156,21 @@ struct Ctx {
         if (grid == 0) return;
         if (grid > 0x7fffffffull) fail(GV_EINVAL, "grid too large");
         const bool timed = prof && (only.empty() || only == name);
+        if (prof && !only.empty()) {
+            // runs of the one timed kernel
+            if (!timed) {
+                close_run();
+            } else if (!run_e0) {
+                run_e0 = event();
+                run_name = name;
+                hip_check(hipEventRecord(run_e0, stream), "hipEventRecord");
+            }
+            hipLaunchKernelGGL(kernel, dim3((uint32_t)grid), dim3(block), 0, stream, args...);
+            hip_check(hipGetLastError(), name);
+            if (timed) ++run_n;
+            if (recs.size() > 4096) collect();
+            return;
+        }
         hipEvent_t e0 = nullptr;
         if (timed) {
             e0 = event();
@@ -144,7 +181,7 @@ struct Ctx {
         if (timed) {
             hipEvent_t e1 = event();
             hip_check(hipEventRecord(e1, stream), "hipEventRecord");
-            recs.push_back({name, e0, e1});
+            recs.push_back({name, e0, e1, 1});
             if (recs.size() > 4096) collect();
         }
     }
