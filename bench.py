@@ -271,6 +271,38 @@ def summarize_traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, grid_wgs, ou
                 "while the sources match.\n\n" + "\n".join(lines) + "\n")
 
 
+def cbt_form(gv, w, dev, B, ins, dels, first, steps=2):
+    """The paper's own layout and algorithms (complete binary tree of edge
+    blocks, one thread per vertex, Alg. 1-3; gv_cbt_*) on the same graph and
+    the same insert + delete batches as the timed steps: build, one untimed
+    step, then `steps` timed ones."""
+    import torch
+    n = w.num_vertices
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c = gv.CbtGraph(n, w.src, w.dst, block_slots=B, device=dev)
+    torch.cuda.synchronize()
+    init_s = time.perf_counter() - t0
+    c.insert_edges(*ins[first - 1])
+    c.delete_edges(*dels[first - 1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pairs = 0
+    for j in range(first, first + steps):
+        c.insert_edges(*ins[j])
+        c.delete_edges(*dels[j])
+        pairs += int(ins[j][0].numel()) + int(dels[j][0].numel())
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    blocks = c.blocks()
+    c.close()
+    return {"form": "complete binary tree of edge blocks, bit-string placement, one thread "
+                    "per vertex for insert and delete (Alg. 1-2), holes left by deletes",
+            "steps": steps, "ms_per_step": round(el / steps * 1e3, 3),
+            "edges_per_s": round(pairs / el, 1), "init_ms": round(init_s * 1e3, 3),
+            "blocks_handed_out": blocks}
+
+
 def block_size_sweep(gv, w, dev, ks=(10**4, 10**5, 10**6), block_slots=(8, 16, 32, 64),
                      steps=4):
     """Insert + delete edges/s on the same R-MAT graph for every block size
@@ -524,6 +556,8 @@ def main():
                     help="skip the batched-form workload (eager and recorded forms)")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the block-size x batch-size sweep")
+    ap.add_argument("--no-cbt", action="store_true",
+                    help="skip the paper-faithful ablation (complete binary tree, Alg. 1-3)")
     ap.add_argument("--no-served", action="store_true",
                     help="skip the served-form workload (continuous batching, p50/p99)")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "OUT_MD"),
@@ -729,6 +763,13 @@ def main():
     vins_ms = (time.perf_counter() - t0) * 1e3
     g.close()
 
+    # ---- the paper's own layout on the same steps
+    cbt = None
+    if not args.no_cbt:
+        cbt = cbt_form(gv, w, dev, B, ins, dels, first)
+        cbt["directory_path_speedup"] = round(value / cbt["edges_per_s"], 2)
+        log("paper-faithful ablation:", json.dumps(cbt))
+
     # ---- batched form on its own workload
     sweep = None if args.no_sweep else block_size_sweep(gv, w, dev)
     batched = None if args.no_batched else batched_form(gv, I, T, dev)
@@ -792,6 +833,7 @@ def main():
         "vertex_insert_1e4": {"ms": round(vins_ms, 3), "stats": vins},
         "memory": {"live_bytes": mem["live_bytes"], "blocks_in_use": mem["blocks_in_use"],
                    "num_edges": mem["num_edges"]},
+        "paper_cbt_ablation": cbt,
         "batched_form": batched,
         "served_p50_p99": served,
         "block_size_sweep": sweep,

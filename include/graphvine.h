@@ -286,6 +286,46 @@ void gv_plan_destroy(gv_plan* p);
  * single-batch paths (the baseline the plan is compared with). */
 int gv_apply_ops(gv_graph* g, const gv_op* ops, uint64_t n_ops);
 
+/* ---- Paper-faithful ablation: complete binary tree of edge blocks ---------
+ * The layout and algorithms of the paper itself on the same kind of device
+ * pool, beside the directory path above, to measure what the redesign buys.
+ * Each vertex's blocks form a complete binary tree (Sec. 4.1, Fig. 2): block
+ * k (1-based, in attachment order) is level-order node k, attached by its bit
+ * string (Sec. 4.5.1, Fig. 4: the binary form of k without its leading 1;
+ * 0 = left, 1 = right; the 9th block gets "001").  Blocks come from an edge
+ * queue popped at prefix-sum positions over all vertices (Sec. 4.5.1).
+ * Insert (Alg. 1) and delete (Alg. 2) run one thread per vertex of the graph;
+ * deletes leave holes and return no block (Sec. 4.5.2).  A query batch
+ * (Alg. 3) collects each source's blocks by an in-order traversal, one
+ * thread per query, then compares with one thread per slot.  Adjacencies are
+ * sets (as above); all vertices 0 .. num_vertices - 1 exist, pairs with an
+ * id past them are rejected.  There are no vertex operations.  All arrays are
+ * device pointers; every call is synchronous.  Errors as above; GV_ENOMEM
+ * when the edge queue cannot hold an insert batch (the batch is then not
+ * applied). */
+typedef struct gv_cbt gv_cbt;
+int gv_cbt_init(gv_cbt** out, uint64_t num_vertices, const uint32_t* d_src,
+                const uint32_t* d_dst, uint64_t num_edges, uint32_t block_slots,
+                uint64_t pool_blocks, void* hip_stream);
+int gv_cbt_insert_edges(gv_cbt* g, const uint32_t* d_src, const uint32_t* d_dst,
+                        uint64_t n, gv_batch_stats* out_or_null);
+int gv_cbt_delete_edges(gv_cbt* g, const uint32_t* d_src, const uint32_t* d_dst,
+                        uint64_t n, gv_batch_stats* out_or_null);
+int gv_cbt_edge_exists(gv_cbt* g, const uint32_t* d_src, const uint32_t* d_dst,
+                       uint64_t n, uint8_t* d_out);
+/* Canonical CSR dump (as gv_dump_canonical, without checksum): d_offsets has
+ * capacity + 1 entries (capacity = the smallest power of two >= num_vertices);
+ * both NULL to count only. */
+int gv_cbt_dump(gv_cbt* g, uint64_t* d_offsets, uint32_t* d_dst, uint64_t dst_capacity,
+                uint64_t* num_edges);
+/* Blocks handed out by the edge queue (holes included: none return). */
+int gv_cbt_blocks(gv_cbt* g, uint64_t* blocks_in_use);
+int gv_cbt_set_stream(gv_cbt* g, void* hip_stream);
+void gv_cbt_destroy(gv_cbt* g);
+/* Host only: the bit string of level-order position k >= 1, NUL-terminated
+ * into out (cap bytes); GV_ERANGE if it does not fit. */
+int gv_cbt_bitstring(uint64_t k, char* out, uint64_t cap);
+
 int gv_set_stream(gv_graph* g, void* hip_stream);
 /* Test support: the number of extra status loads each look-back wait of a
  * batch sort makes before it gives up (default 2^24).  0 makes every wait give

@@ -108,6 +108,15 @@ def lib():
             "gv_kernel_names": [vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)],
             "gv_set_stream": [vp, vp],
             "gv_debug_spin_limit": [vp, C.c_uint32],
+            "gv_cbt_init": [C.POINTER(C.c_void_p), C.c_uint64, u32p, u32p, C.c_uint64,
+                            C.c_uint32, C.c_uint64, vp],
+            "gv_cbt_insert_edges": [vp, u32p, u32p, C.c_uint64, C.POINTER(gv_batch_stats)],
+            "gv_cbt_delete_edges": [vp, u32p, u32p, C.c_uint64, C.POINTER(gv_batch_stats)],
+            "gv_cbt_edge_exists": [vp, u32p, u32p, C.c_uint64, vp],
+            "gv_cbt_dump": [vp, vp, u32p, C.c_uint64, u64p],
+            "gv_cbt_blocks": [vp, u64p],
+            "gv_cbt_set_stream": [vp, vp],
+            "gv_cbt_bitstring": [C.c_uint64, C.c_char_p, C.c_uint64],
             "gv_sync": [vp],
             "gv_apply_ops": [vp, C.POINTER(gv_op), C.c_uint64],
             "gv_plan_create": [vp, C.POINTER(gv_op), C.c_uint64, C.POINTER(C.c_void_p)],
@@ -125,6 +134,8 @@ def lib():
         L.gv_graph_destroy.restype = None
         L.gv_plan_destroy.argtypes = [vp]
         L.gv_plan_destroy.restype = None
+        L.gv_cbt_destroy.argtypes = [vp]
+        L.gv_cbt_destroy.restype = None
         _lib = L
     return _lib
 
@@ -470,3 +481,87 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------ paper-faithful ablation
+def gv_cbt_bitstring(k: int) -> str:
+    """Bit string of level-order position k >= 1 (computed by the library)."""
+    buf = C.create_string_buffer(72)
+    _check(lib().gv_cbt_bitstring(int(k), buf, 72), "gv_cbt_bitstring")
+    return buf.value.decode()
+
+
+class CbtGraph:
+    """The paper's own layout (complete binary tree of edge blocks, one thread
+    per vertex) through gv_cbt_*; all calls synchronous."""
+
+    def __init__(self, num_vertices, src=(), dst=(), block_slots=16, pool_blocks=None,
+                 device="cuda:0"):
+        self.device = torch.device(device)
+        s = as_device_u32(src, self.device)
+        d = as_device_u32(dst, self.device)
+        if s.numel() != d.numel():
+            raise ValueError("src/dst length mismatch")
+        if pool_blocks is None:
+            pool_blocks = 4 * (s.numel() // block_slots + 1) + 2 * int(num_vertices) + (1 << 16)
+        self.h = None
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = lib().gv_cbt_init(C.byref(h), int(num_vertices), _ptr(s), _ptr(d), s.numel(),
+                                   int(block_slots), int(pool_blocks), _stream_ptr(self.device))
+        _check(rc, "gv_cbt_init")
+        self.h = h.value
+        cap = 1
+        while cap < int(num_vertices):
+            cap <<= 1
+        self.capacity = cap
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().gv_cbt_destroy(C.c_void_p(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _edges(self, fn, name, src, dst):
+        s = as_device_u32(src, self.device)
+        d = as_device_u32(dst, self.device)
+        if s.numel() != d.numel():
+            raise ValueError("src/dst length mismatch")
+        st = gv_batch_stats()
+        _check(fn(C.c_void_p(self.h), _ptr(s), _ptr(d), s.numel(), C.byref(st)), name)
+        return st.as_tuple()
+
+    def insert_edges(self, src, dst):
+        return self._edges(lib().gv_cbt_insert_edges, "gv_cbt_insert_edges", src, dst)
+
+    def delete_edges(self, src, dst):
+        return self._edges(lib().gv_cbt_delete_edges, "gv_cbt_delete_edges", src, dst)
+
+    def edge_exists(self, src, dst):
+        s = as_device_u32(src, self.device)
+        d = as_device_u32(dst, self.device)
+        out = torch.empty(max(s.numel(), 1), dtype=torch.uint8, device=self.device)
+        _check(lib().gv_cbt_edge_exists(C.c_void_p(self.h), _ptr(s), _ptr(d), s.numel(),
+                                        _ptr(out)), "gv_cbt_edge_exists")
+        return out[: s.numel()]
+
+    def dump(self):
+        """(offsets int64[capacity+1], dst int32[E], E)"""
+        e = C.c_uint64()
+        L = lib()
+        _check(L.gv_cbt_dump(C.c_void_p(self.h), None, None, 0, C.byref(e)), "gv_cbt_dump")
+        offs = torch.empty(self.capacity + 1, dtype=torch.int64, device=self.device)
+        dst = torch.empty(max(e.value, 1), dtype=torch.int32, device=self.device)
+        _check(L.gv_cbt_dump(C.c_void_p(self.h), _ptr(offs), _ptr(dst), dst.numel(),
+                             C.byref(e)), "gv_cbt_dump")
+        return offs, dst[: e.value], e.value
+
+    def blocks(self):
+        b = C.c_uint64()
+        _check(lib().gv_cbt_blocks(C.c_void_p(self.h), C.byref(b)), "gv_cbt_blocks")
+        return b.value
