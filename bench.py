@@ -346,31 +346,10 @@ def batched_form(gv, I, T, dev, scale=22, edges=1 << 26, nbatch=256, seed_name="
     batch and a vertex delete and re-insert before the timed passes."""
     import numpy as np
     import torch
+    from paper_2306_08252_amd import workloads as Wk
     w = T.RmatWorkload(scale, edges, name=seed_name, device=dev)
     n = w.num_vertices
-    draws = I.splitmix64(I.stream_seed(seed_name, "ops"), 3 * nbatch)
-    ops, pairs, vids = [], 0, 0
-    for j in range(nbatch):
-        u = float(draws[3 * j] >> np.uint64(11)) / float(1 << 53)
-        size = int(round(100 * np.exp(u * np.log(10**4))))
-        r = float(draws[3 * j + 1] >> np.uint64(11)) / float(1 << 53)
-        if r < 0.45:
-            s, d = w.insert_batch(size, j)
-            ops.append((0, s, d))
-            pairs += size
-        elif r < 0.90:
-            ne = int(round(0.8 * size))
-            es, ed = T.pick(I.stream_seed(seed_name, "del-existing", j), ne, w.src, w.dst)
-            us, ud = T.uniform_pairs(I.stream_seed(seed_name, "del-uniform", j), size - ne, n,
-                                     device=dev)
-            ops.append((1, torch.cat([es, us]), torch.cat([ed, ud])))
-            pairs += size
-        else:
-            m = min(size, 10**4)
-            ids = torch.from_numpy((I.splitmix64(I.stream_seed(seed_name, "vertices", j), m)
-                                    % np.uint64(n)).astype(np.uint32).view(np.int32)).to(dev)
-            ops.append((2 if draws[3 * j + 2] & np.uint64(1) else 3, ids, None))
-            vids += m
+    ops, pairs, vids = Wk.batched_ops(w, seed_name, nbatch, dev)
     big = max((o for o in ops if o[0] == 0), key=lambda o: o[1].numel())
     one = ops[[o[0] for o in ops].index(3)][1][:1] if any(o[0] == 3 for o in ops) else None
 

@@ -7,10 +7,14 @@ budget.  Its edge inserts and deletes go to the device as one mixed list
 (gv_apply_edge_ops), whose last-writer reduction gives the result of
 applying them one pair at a time in arrival order; then the tick's queries
 are answered (gv_edge_exists).  So the commit order is: a tick's writes in
-arrival order, then its queries.  Vertex requests are barriers: a tick ends
-before one, and it runs alone.  A request completes when its tick has
-synchronised; latency is completion time minus scheduled arrival time (open
-loop, so a late server does not lower the arrival rate).
+arrival order, then its queries.  Ticks overlap: a tick is queued as soon as
+it is formed, while earlier ones still run on the device (a few at most),
+and its answers come back by an asynchronous copy; requests that arrive
+meanwhile form the next tick.  Vertex requests are barriers: a tick ends
+before one, and it runs alone once the running ticks are done.  A request
+completes when its tick's event has passed; latency is completion time
+minus scheduled arrival time (open loop, so a late server does not lower
+the arrival rate).
 
 Admission by free blocks: an edge-insert request of k pairs may need up to
 ceil(k / B) + min(k, V) new blocks (its pairs packed into full blocks, plus
@@ -51,11 +55,42 @@ def free_blocks(graph):
     return m["pool_capacity_blocks"] - m["blocks_in_use"]
 
 
+def _enqueue_tick(graph, requests, i, j, dev):
+    """Queues one tick's work on the graph's stream without waiting: the
+    tick's edge inserts and deletes as one mixed list, then its queries as
+    one batch whose answers are copied to pinned host memory.  Returns the
+    tick record (its tensors stay referenced until it completes)."""
+    ws = [r for r in requests[i:j] if r[0] in (INSERT, DELETE)]
+    qs = [(m, r) for m, r in enumerate(requests[i:j], start=i) if r[0] == QUERY]
+    keep = []
+    if ws:
+        op = torch.cat([torch.full((_size(r),), r[0], dtype=torch.uint8, device=dev)
+                        for r in ws])
+        src = torch.cat([r[1] for r in ws])
+        dst = torch.cat([r[2] for r in ws])
+        keep += list(gv.gv_apply_edge_ops(graph.h, op, src, dst, dev))
+    host = None
+    if qs:
+        out = graph.edge_exists(torch.cat([r[1] for _, r in qs]),
+                                torch.cat([r[2] for _, r in qs]))
+        host = torch.empty(out.shape, dtype=out.dtype, pin_memory=True)
+        host.copy_(out, non_blocking=True)
+        keep.append(out)
+    ev = torch.cuda.Event()
+    ev.record(torch.cuda.current_stream(dev))
+    return {"range": (i, j), "event": ev, "queries": qs, "answers": host, "keep": keep}
+
+
 def serve(graph, requests, arrivals=None, max_tick_pairs=1 << 20, keep_answers=False,
-          clock=time.perf_counter, rejected=None):
+          clock=time.perf_counter, rejected=None, max_inflight=3):
     """Runs `requests` [(kind, a, b)] (device id tensors; b is None for vertex
     requests) against `graph` (a graphvine.Graph).  `arrivals[i]` is request
     i's scheduled time in seconds from the start (None: all at time 0).
+    Ticks overlap: a tick is queued on the graph's stream as soon as it is
+    formed, while up to `max_inflight - 1` earlier ticks are still running,
+    so requests that arrive meanwhile form the next tick and run right after
+    (stream order keeps the commit order); a tick's requests complete when
+    its event has passed.  Vertex requests wait for every running tick.
     Returns (completion times, ticks as (first, end) request ranges, answers
     of the query requests by index if keep_answers).  Indices of requests
     rejected by admission are appended to `rejected` (a list) if given; a
@@ -71,16 +106,37 @@ def serve(graph, requests, arrivals=None, max_tick_pairs=1 << 20, keep_answers=F
     done = np.zeros(n)
     ticks = []
     answers = {}
+    flight = []
     t0 = clock()
+
+    def retire(block):
+        # completes the ticks whose events have passed (all of them if block)
+        while flight and (block or flight[0]["event"].query()):
+            tk = flight.pop(0)
+            tk["event"].synchronize()
+            t = clock() - t0
+            f, e = tk["range"]
+            done[f:e] = t
+            if keep_answers and tk["queries"]:
+                out = tk["answers"].numpy()
+                o = 0
+                for m, r in tk["queries"]:
+                    answers[m] = out[o:o + _size(r)].copy()
+                    o += _size(r)
+
     i = 0
     while i < n:
+        retire(False)
         now = clock() - t0
-        if arr[i] > now:
+        if arr[i] > now or len(flight) >= max_inflight:
+            if flight:
+                continue  # poll the running ticks
             while clock() - t0 < arr[i]:
                 pass
             now = clock() - t0
         kind = requests[i][0]
         if kind in (VINSERT, VDELETE):
+            retire(True)
             ids = requests[i][1]
             if kind == VINSERT:
                 graph.insert_vertices(ids)
@@ -89,6 +145,7 @@ def serve(graph, requests, arrivals=None, max_tick_pairs=1 << 20, keep_answers=F
             torch.cuda.synchronize(dev)
             done[i] = clock() - t0
             ticks.append((i, i + 1))
+            free = free_blocks(graph)
             i += 1
             continue
         j, pairs, need, fresh = i, 0, 0, False
@@ -98,7 +155,8 @@ def serve(graph, requests, arrivals=None, max_tick_pairs=1 << 20, keep_answers=F
             if j > i and pairs + k > max_tick_pairs:
                 break
             if need + b > free and not fresh:
-                free = free_blocks(graph)  # the last tick has synchronised
+                retire(True)
+                free = free_blocks(graph)  # every queued tick has completed
                 fresh = True
             if need + b > free:
                 break  # waits for a later tick (or, alone, is rejected)
@@ -111,29 +169,11 @@ def serve(graph, requests, arrivals=None, max_tick_pairs=1 << 20, keep_answers=F
             done[i] = clock() - t0
             i += 1
             continue
-        ws = [r for r in requests[i:j] if r[0] in (INSERT, DELETE)]
-        qs = [(m, r) for m, r in enumerate(requests[i:j], start=i) if r[0] == QUERY]
-        if ws:
-            op = torch.cat([torch.full((_size(r),), r[0], dtype=torch.uint8, device=dev)
-                            for r in ws])
-            src = torch.cat([r[1] for r in ws])
-            dst = torch.cat([r[2] for r in ws])
-            gv.gv_apply_edge_ops(graph.h, op, src, dst, dev)
-        if qs:
-            out = graph.edge_exists(torch.cat([r[1] for _, r in qs]),
-                                    torch.cat([r[2] for _, r in qs]))
-        torch.cuda.synchronize(dev)
-        t = clock() - t0
-        done[i:j] = t
-        if qs and keep_answers:
-            o = 0
-            out = out.cpu().numpy()
-            for m, r in qs:
-                answers[m] = out[o:o + _size(r)]
-                o += _size(r)
+        flight.append(_enqueue_tick(graph, requests, i, j, dev))
         ticks.append((i, j))
         free -= need
         i = j
+    retire(True)
     return done, ticks, answers
 
 

@@ -148,3 +148,68 @@ def test_plan_errors():
     assert e.value.code == gv.GV_EINVAL
     plan.close()
     g.close()
+
+
+@pytest.mark.timeout(900)
+def test_plan_rmat22_full_size_against_set_algebra():
+    """The batched-form workload at its size: R-MAT 2^22 vertices / 2^26
+    edges, 256 batches of log-uniform size in [10^2, 10^6] (45 / 45 / 10 edge
+    inserts / edge deletes / vertex batches), recorded into one plan and
+    launched once.  The whole edge set afterwards equals set algebra applying
+    the batches in order (and the dump's checksum the sum computed from those
+    keys); rows of sampled sources equal the CPU oracle applying the same
+    batches restricted to those sources (vertex batches in full)."""
+    gv = need_gpu()
+    from gpu_helpers import EdgeSet, keys_of, mix64_sum, u32
+    from paper_2306_08252_amd import inputs_torch as T
+    from paper_2306_08252_amd import workloads as Wk
+    scale, m, B = 22, 1 << 26, 16
+    say("generate R-MAT 2^22 / 2^26 and 256 uneven batches on the GPU")
+    w = T.RmatWorkload(scale, m, name="batched", device="cuda:0")
+    n = w.num_vertices
+    ops, pairs, vids = Wk.batched_ops(w, "batched", 256, "cuda:0")
+    g = gv.Graph(n, w.src, w.dst, block_slots=B, vertex_capacity=n)
+    plan = gv.Plan(g.h, ops)
+    plan.launch()
+    assert g.sync() == 0
+    plan.close()
+    say(f"plan applied: {pairs} pairs, {vids} vertex ids; set algebra")
+    src, dst = u32(w.src), u32(w.dst)
+    S = EdgeSet(n, src, dst)
+    rng = np.random.default_rng(22)
+    deg0 = np.bincount(src, minlength=n)
+    sample = np.unique(np.concatenate([np.argsort(deg0)[-24:], rng.integers(0, n, 100)]))
+    in_sample = np.zeros(n, bool)
+    in_sample[sample] = True
+    sel = in_sample[src]
+    o = O.OracleGraph(n, src[sel], dst[sel], block_slots=B, vertex_capacity=n)
+    for kind, a, b in ops:
+        a = u32(a)
+        if kind in (0, 1):
+            b = u32(b)
+            r = in_sample[a]
+            if kind == 0:
+                S.insert(a, b)
+                o.insert_edges(a[r], b[r])
+            else:
+                S.delete(a, b)
+                o.delete_edges(a[r], b[r])
+        elif kind == 2:
+            S.insert_vertices(a)
+            o.insert_vertices(a)
+        else:
+            S.delete_vertices(a)
+            o.delete_vertices(a)
+    offs, gdst, ck, e = gpu_dump(g)
+    deg = np.diff(offs.astype(np.int64))
+    keys = keys_of(np.repeat(np.arange(len(deg), dtype=np.uint64), deg), gdst)
+    assert e == len(S.E), f"{e} edges, want {len(S.E)}"
+    np.testing.assert_array_equal(keys, S.E, err_msg="whole edge set")
+    assert ck == mix64_sum(S.E)
+    ooffs, odst, _ = o.dump()
+    for v in sample:
+        np.testing.assert_array_equal(gdst[offs[v]:offs[v + 1]], odst[ooffs[v]:ooffs[v + 1]],
+                                      err_msg=f"row {v}")
+    assert g.memory_used()["blocks_in_use"] == int(((deg + B - 1) // B).sum())
+    assert g.audit() == 0
+    g.close()

@@ -1,28 +1,25 @@
 """Scale workloads: R-MAT with 2^24 vertices and 2^28 edges, and the road-like
 4096 x 4096 lattice, with batches of 10^7 edges and of 10^4 vertices.
 
-The oracle cannot hold these graphs in a test's time, so the checks are:
-  * rows of sampled sources (the largest hubs plus random vertices) equal the
-    oracle's, run on the same inputs restricted to those sources (edge
-    operations of different sources are independent; vertex deletes are
-    applied to the restricted oracle too);
-  * properties that hold at any size: the dump is sorted and duplicate-free,
-    edge counts follow the batch statistics exactly, blocks in use equal the
-    sum of ceil(deg / B), the structural audit is clean, the lattice stays
-    symmetric under symmetric updates.
+The whole edge set is checked after every operation, exactly: the expected
+set is kept by set algebra on sorted uint64 keys (src << 32 | dst) -- union
+with the valid new pairs of an insert, difference with a delete, removal of
+every edge touching a deleted vertex, re-activation of an inserted vertex --
+and the dump must equal it key for key; the dump's checksum must equal
+sum(mix64(key)) mod 2^64 computed here from those keys (SplitMix64 output
+function, written out in numpy).  Rows of sampled sources (the largest hubs
+plus random vertices) are also compared with the CPU oracle run on the same
+inputs restricted to those sources, and block accounting and the structural
+audit are checked.
 """
 import numpy as np
 import pytest
-from gpu_helpers import need_gpu, say, u32
+from gpu_helpers import EdgeSet, keys_of, mix64_sum, need_gpu, say, u32
 from oracle import pyoracle as O
 from paper_2306_08252_amd import inputs as I
 from paper_2306_08252_amd import inputs_torch as T
 
 pytestmark = pytest.mark.gpu
-
-
-def keys_of(s, d):
-    return (np.asarray(s, np.uint64) << np.uint64(32)) | np.asarray(d, np.uint64)
 
 
 class Checker:
@@ -33,6 +30,7 @@ class Checker:
         self.in_sample[sample] = True
         sel = self.in_sample[src]
         self.o = O.OracleGraph(n, src[sel], dst[sel], block_slots=B)
+        self.S = EdgeSet(n, src, dst)
         self.edges = None
 
     def restrict(self, s, d):
@@ -55,6 +53,9 @@ class Checker:
                       for v, i in zip(u, bad[:8])]
             raise AssertionError(f"{label}: {len(bad)} order violations in {len(np.unique(u))}+ "
                                  f"rows; (src, dst, degree): {detail}; sync={g.sync()}")
+        assert len(keys) == len(self.S.E), f"{label}: {len(keys)} edges, want {len(self.S.E)}"
+        np.testing.assert_array_equal(keys, self.S.E, err_msg=f"{label}: whole edge set")
+        assert ck == mix64_sum(self.S.E), f"{label}: checksum"
         mem = g.memory_used()
         assert mem["num_edges"] == e == len(dst)
         B = self.B
@@ -88,12 +89,14 @@ def test_rmat24_scale():
     s, d = w.insert_batch(k, 0)
     st = g.insert_edges(s, d)
     C.o.insert_edges(*C.restrict(u32(s), u32(d)))
+    assert st[0] == C.S.insert(u32(s), u32(d))
     e0 = C.edges
     C.check("insert 1e7")
     assert C.edges == e0 + st[0] and st[1] == 0
     s, d = w.delete_batch(k, 0)
     st = g.delete_edges(s, d)
     C.o.delete_edges(*C.restrict(u32(s), u32(d)))
+    assert st[0] == C.S.delete(u32(s), u32(d))
     e0 = C.edges
     C.check("delete 1e7")
     assert C.edges == e0 - st[0] and st[0] > 0
@@ -102,14 +105,20 @@ def test_rmat24_scale():
     ids[:8] = sample[:8]  # some sampled rows lose their out-edges
     st = g.delete_vertices(ids)
     assert st == C.o.delete_vertices(ids)[1]
+    C.S.delete_vertices(ids)
     C.check("vertex delete 1e4")
     st = g.insert_vertices(ids)
     assert st == C.o.insert_vertices(ids)[1]
+    C.S.insert_vertices(ids)
     C.check("vertex insert 1e4")
     qs, qd = w.query_batch(10**6, 0)
     ans = g.edge_exists(qs, qd).cpu().numpy()
     sel = C.in_sample[u32(qs)]
     np.testing.assert_array_equal(ans[sel], C.o.edge_exists(u32(qs)[sel], u32(qd)[sel]))
+    # every answer against membership in the expected set
+    qk = keys_of(u32(qs), u32(qd))
+    pos = np.minimum(np.searchsorted(C.S.E, qk), len(C.S.E) - 1)
+    np.testing.assert_array_equal(ans, (C.S.E[pos] == qk).astype(np.uint8), err_msg="queries")
     g.close()
 
 
@@ -136,6 +145,7 @@ def test_lattice_road_scale():
     s, d = np.concatenate([a, b]), np.concatenate([b, a])
     st = g.insert_edges(s, d)
     C.o.insert_edges(*C.restrict(s, d))
+    assert st[0] == C.S.insert(s, d)
     e0 = C.edges
     assert symmetric(C.check("insert 1e7"))
     assert C.edges == e0 + st[0]
@@ -146,12 +156,15 @@ def test_lattice_road_scale():
     d = np.concatenate([b2, a2, lb, la])
     st = g.delete_edges(s, d)
     C.o.delete_edges(*C.restrict(s, d))
+    assert st[0] == C.S.delete(s, d)
     e0 = C.edges
     assert symmetric(C.check("delete 1e7"))
     assert C.edges == e0 - st[0]
     ids = rng.choice(n, 10**4, replace=False).astype(np.uint32)
     assert g.delete_vertices(ids) == C.o.delete_vertices(ids)[1]
+    C.S.delete_vertices(ids)
     assert symmetric(C.check("vertex delete 1e4"))
     assert g.insert_vertices(ids) == C.o.insert_vertices(ids)[1]
+    C.S.insert_vertices(ids)
     C.check("vertex insert 1e4")
     g.close()

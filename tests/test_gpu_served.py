@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_helpers import assert_same, need_gpu, say
+from gpu_helpers import assert_same, gpu_dump, need_gpu, say
 from oracle import pyoracle as O
 from paper_2306_08252_amd import inputs as I
 
@@ -184,3 +184,118 @@ def test_served_admission_by_free_blocks():
                 np.testing.assert_array_equal(answers[i], o.edge_exists(host[i][1], host[i][2]))
     assert_same(g, o, "after admission-controlled serving")
     g.close()
+
+
+def _requests(rng, n, count, s0, d0, dev, max_size, vertex_share=0.05):
+    """Seeded requests of log-uniform size: edge inserts and deletes (60 % of
+    their pairs stored ones), queries, vertex inserts and deletes."""
+    from paper_2306_08252_amd import served as S
+    host = []
+    p = [0.4 - vertex_share / 2, 0.4 - vertex_share / 2, 0.2, vertex_share / 2, vertex_share / 2]
+    for _ in range(count):
+        kind = int(rng.choice(5, p=p))
+        size = max(1, int(np.exp(rng.random() * np.log(max_size))))
+        if kind in (S.VINSERT, S.VDELETE):
+            host.append((kind, rng.integers(0, n, min(size, 200)).astype(np.uint32), None))
+        else:
+            pk = rng.integers(0, len(s0), size)
+            own = rng.random(size) < 0.6
+            s = np.where(own, s0[pk], rng.integers(0, n, size)).astype(np.uint32)
+            d = np.where(own, d0[pk], rng.integers(0, n, size)).astype(np.uint32)
+            host.append((kind, s, d))
+    reqs = [(k, torch.from_numpy(a.view(np.int32)).to(dev),
+             None if b is None else torch.from_numpy(b.view(np.int32)).to(dev))
+            for k, a, b in host]
+    return host, reqs
+
+
+def test_served_request_alone_equals_in_the_mix():
+    """Every request's result is the same alone as in the mix: a second
+    graph, from the same initial state, applies the requests one at a time,
+    each alone with the single-batch calls, in the server's commit order (a
+    tick's writes in arrival order, then its queries); every query answered
+    in a mixed tick equals the same query run alone on that graph at its
+    commit point, and both graphs end equal.  The ticks overlap on the
+    device (several in flight)."""
+    gv = need_gpu()
+    from paper_2306_08252_amd import served as S
+    scale, m, B = 16, 1 << 20, 16
+    n = 1 << scale
+    s0, d0 = I.rmat_graph(I.stream_seed("served-alone", scale), scale, m)
+    g = gv.Graph(n, s0, d0, block_slots=B, vertex_capacity=n)
+    alone = gv.Graph(n, s0, d0, block_slots=B, vertex_capacity=n)
+    rng = np.random.default_rng(11)
+    host, reqs = _requests(rng, n, 300, s0, d0, g.device, 10**4)
+    done, ticks, answers = S.serve(g, reqs, None, max_tick_pairs=20000, keep_answers=True,
+                                   max_inflight=3)
+    assert g.sync() == 0
+    say(f"{len(reqs)} requests in {len(ticks)} ticks")
+    assert max(e - f for f, e in ticks) > 3  # ticks mix requests
+    checked = 0
+    for f, e in ticks:
+        order = [i for i in range(f, e) if host[i][0] != S.QUERY] + \
+                [i for i in range(f, e) if host[i][0] == S.QUERY]
+        for i in order:
+            kind, a, b = host[i]
+            if kind == S.INSERT:
+                alone.insert_edges(a, b)
+            elif kind == S.DELETE:
+                alone.delete_edges(a, b)
+            elif kind == S.VINSERT:
+                alone.insert_vertices(a)
+            elif kind == S.VDELETE:
+                alone.delete_vertices(a)
+            else:
+                np.testing.assert_array_equal(answers[i], alone.edge_exists(a, b).cpu().numpy(),
+                                              err_msg=f"query request {i}")
+                checked += 1
+    assert checked > 30
+    oa, da, ca, ea = gpu_dump(g)
+    ob, db, cb, eb = gpu_dump(alone)
+    assert ea == eb and ca == cb
+    np.testing.assert_array_equal(oa, ob)
+    np.testing.assert_array_equal(da, db)
+    g.close()
+    alone.close()
+
+
+@pytest.mark.timeout(900)
+def test_served_rmat20_against_oracle_replay():
+    """The served form on R-MAT 2^20 vertices / 2^24 edges: requests of
+    log-uniform size in [1, 10^5] (40 / 40 / 15 / 5 inserts / deletes /
+    queries / vertex batches), overlapping ticks; every query answer and the
+    final graph equal the CPU oracle replaying the server's commit order."""
+    gv = need_gpu()
+    from paper_2306_08252_amd import inputs_torch as T
+    from paper_2306_08252_amd import served as S
+    scale, m, B = 20, 1 << 24, 16
+    say("generate R-MAT 2^20 / 2^24 on the GPU")
+    w = T.RmatWorkload(scale, m, name="served-replay", device="cuda:0")
+    n = w.num_vertices
+    s0, d0 = gv_u32(w.src), gv_u32(w.dst)
+    g = gv.Graph(n, w.src, w.dst, block_slots=B, vertex_capacity=n)
+    rng = np.random.default_rng(20)
+    host, reqs = _requests(rng, n, 200, s0, d0, g.device, 10**5)
+    done, ticks, answers = S.serve(g, reqs, None, max_tick_pairs=1 << 20, keep_answers=True)
+    assert g.sync() == 0
+    say(f"{len(reqs)} requests in {len(ticks)} ticks; oracle replay")
+    o = O.OracleGraph(n, s0, d0, block_slots=B, vertex_capacity=n)
+    for f, e in ticks:
+        if host[f][0] in (S.VINSERT, S.VDELETE):
+            (o.insert_vertices if host[f][0] == S.VINSERT else o.delete_vertices)(host[f][1])
+            continue
+        ws = [host[i] for i in range(f, e) if host[i][0] in (S.INSERT, S.DELETE)]
+        if ws:
+            op = np.concatenate([np.full(len(x[1]), x[0], np.uint8) for x in ws])
+            o.apply_edge_ops(op, np.concatenate([x[1] for x in ws]),
+                             np.concatenate([x[2] for x in ws]))
+        for i in range(f, e):
+            if host[i][0] == S.QUERY:
+                np.testing.assert_array_equal(answers[i], o.edge_exists(host[i][1], host[i][2]),
+                                              err_msg=f"query request {i}")
+    assert_same(g, o, "after the served run")
+    g.close()
+
+
+def gv_u32(t):
+    return t.detach().cpu().numpy().view(np.uint32)
