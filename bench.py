@@ -337,84 +337,50 @@ def batched_form(gv, I, T, dev, scale=22, edges=1 << 26, nbatch=256, seed_name="
     """The batched form: `nbatch` batches of log-uniform size in [10^2, 10^6],
     45 % edge inserts (R-MAT pairs), 45 % edge deletes (80 % stored pairs, 20 %
     uniform), 10 % vertex batches (min(size, 10^4) uniform ids, insert or
-    delete alike), applied in order with gv_apply_ops (one launch sequence
-    per batch) at block sizes 8, 16, 32 and 64 slots; the tuner keeps the
-    fastest.  Then, at that block size, on another copy of the same graph,
-    the sequence is recorded into one HIP graph (gv_plan_create, not timed)
-    and launched once.  Every run must end with the same checksum and edge
-    count.  Scratch is sized by a warm-up insert and delete of the largest
-    batch and a vertex delete and re-insert before the timed passes."""
-    import numpy as np
+    delete alike), applied in order.  Baseline: gv_apply_ops at the default
+    settings (B = 16, no coalescing), one launch sequence per batch.  Tuned:
+    the setting the autotuner stored for this workload in tuning.json (block
+    size, coalescing of edge-batch runs into mixed lists, run cap, small-sort
+    cutoff; tuned here when none is stored), first eagerly, then recorded
+    into one HIP graph (gv_plan_create, not timed) and launched once.  Each
+    run starts from a fresh copy of the graph after the same warm-up (which
+    sizes the scratch buffers); every run must end with the same checksum
+    and edge count."""
     import torch
+    from paper_2306_08252_amd import tuner as Tu
     from paper_2306_08252_amd import workloads as Wk
     w = T.RmatWorkload(scale, edges, name=seed_name, device=dev)
-    n = w.num_vertices
     ops, pairs, vids = Wk.batched_ops(w, seed_name, nbatch, dev)
-    big = max((o for o in ops if o[0] == 0), key=lambda o: o[1].numel())
-    one = ops[[o[0] for o in ops].index(3)][1][:1] if any(o[0] == 3 for o in ops) else None
-
-    def fresh(bs):
-        # the same graph and warm-up for every run
-        g = gv.Graph(n, w.src, w.dst, block_slots=bs, device=dev)
-        g.insert_edges(big[1], big[2], stats=False)
-        g.delete_edges(big[1], big[2], stats=False)
-        if one is not None:
-            g.delete_vertices(one)
-            g.insert_vertices(one)
-        return g
-
-    def digest(g):
-        ck, e = gv.C.c_uint64(), gv.C.c_uint64()
-        gv._check(gv.lib().gv_dump_canonical(gv.C.c_void_p(g.h), None, None, 0, gv.C.byref(ck),
-                                             gv.C.byref(e)), "gv_dump_canonical")
-        return ck.value, e.value
-
-    # eager (one launch sequence per batch) at every block size: the tuner
-    # keeps the fastest
-    arr, keep = gv._ops(ops, dev)
-    by_b, digests = {}, {}
-    for bs in (8, 16, 32, 64):
-        g = fresh(bs)
-        gv.gv_apply_ops(g.h, ops[:1])  # marshalling warm-up
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        gv._check(gv.lib().gv_apply_ops(gv.C.c_void_p(g.h), arr, len(ops)), "gv_apply_ops")
-        rc = g.sync()
-        by_b[bs] = time.perf_counter() - t0
-        if rc != 0:
-            raise RuntimeError(f"batched form: {gv.gv_strerror(rc)}")
-        digests[bs] = digest(g)
-        g.close()
-    if len(set(digests.values())) != 1:
-        raise RuntimeError(f"batched form: block sizes disagree: {digests}")
-    best = min(by_b, key=by_b.get)
-    el, want = by_b[best], digests[best]
-    # recorded: the same sequence as one HIP graph (recording not timed)
-    g = fresh(best)
-    gv.gv_apply_ops(g.h, ops[:1])
-    plan = gv.Plan(g.h, ops, dev)
+    warm = Wk.batched_warmup(ops)
+    key = Tu.workload_key(scale, edges, nbatch, seed_name)
+    stored = Tu.load(key)
+    if stored is None:
+        best, points = Tu.tune(gv, w, ops, dev, warm, log=lambda *a: None)
+        source = "tuned in this run"
+    else:
+        best, points = stored["setting"], stored["measured_ms"]
+        source = "tuning.json"
+    knobs = {k: best[k] for k in ("coalesce", "max_run_pairs", "small_sort_max")}
+    base = {"coalesce": 0, "max_run_pairs": 0, "small_sort_max": 4096}
+    el_base, want = Tu.measure(gv, w, ops, dev, 16, base, warm, "eager")
+    el_eager, got_e = Tu.measure(gv, w, ops, dev, best["block_slots"], knobs, warm, "eager")
+    el_plan, got_p = Tu.measure(gv, w, ops, dev, best["block_slots"], knobs, warm, "plan")
+    if got_e != want or got_p != want:
+        raise RuntimeError(f"batched form: results differ: {want} {got_e} {got_p}")
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plan.launch()
-    rc = g.sync()
-    el_plan = time.perf_counter() - t0
-    plan.close()
-    if rc != 0:
-        raise RuntimeError(f"batched form (plan): {gv.gv_strerror(rc)}")
-    got = digest(g)
-    g.close()
-    if got != want:
-        raise RuntimeError(f"batched form: plan {got} and eager {want} results differ")
     return {"workload": f"rmat{scale} {edges} edges, {nbatch} batches of log-uniform "
                         "size in [1e2, 1e6], 45/45/10 insert/delete/vertex",
             "pairs": pairs, "vertex_ids": vids,
-            "eager_ms_by_block_slots": {str(k): round(v * 1e3, 3) for k, v in by_b.items()},
-            "tuned_block_slots": best, "ms": round(el * 1e3, 3),
-            "edges_per_s": round(pairs / el, 1), "form": "one launch sequence per batch",
+            "baseline_form": "one launch sequence per batch, B=16, no coalescing",
+            "ms": round(el_base * 1e3, 3), "edges_per_s": round(pairs / el_base, 1),
+            "tuned_setting": best, "tuning_source": source,
+            "tuner_points_ms": points,
+            "tuned_eager_ms": round(el_eager * 1e3, 3),
             "plan_ms": round(el_plan * 1e3, 3),
             "plan_edges_per_s": round(pairs / el_plan, 1),
-            "plan_form": "the same sequence recorded as one HIP graph, tuned block size",
-            "plan_matches_eager": True, "checksum": want[0], "edges_after": want[1]}
+            "plan_form": "the sequence recorded as one HIP graph, tuned setting",
+            "plan_gain_vs_baseline": round(el_base / el_plan - 1.0, 4),
+            "results_match": True, "checksum": want[0], "edges_after": want[1]}
 
 
 def served_form(gv, I, T, dev, B, scale=24, edges=1 << 28, nreq=1500, loads=(0.3, 0.6, 0.9),

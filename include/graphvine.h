@@ -262,6 +262,30 @@ typedef struct {
     uint64_t n;
 } gv_op;
 
+/* Tuning of one graph's batch paths.  The batched form's autotuner
+ * (paper_2306_08252_amd/tuner.py) measures the settings per workload and
+ * stores them in tuning.json; the binding applies them before creating a
+ * plan.  Defaults: coalesce 0, max_run_pairs 0, small_sort_max 4096.
+ *   coalesce       gv_apply_ops and gv_plan_create apply every run of
+ *                  consecutive edge batches (up to the next vertex batch) as
+ *                  one mixed list (gv_apply_edge_ops): the same result as the
+ *                  batches one after the other (each pair's last entry
+ *                  decides), one grouping sort per run instead of one per
+ *                  batch.  A run whose inserts do not fit the pool fails
+ *                  them as a whole (sticky GV_ENOMEM) with its deletes applied.
+ *   max_run_pairs  longest run coalesced, in pairs (0: 2^28; a batch
+ *                  longer than the limit runs alone)
+ *   small_sort_max insert / delete batches of at most this many pairs
+ *                  (<= 4096) are packed and sorted by one workgroup */
+typedef struct {
+    uint32_t coalesce;
+    uint32_t max_run_pairs;
+    uint32_t small_sort_max;
+    uint32_t reserved[5];
+} gv_tuning;
+int gv_set_tuning(gv_graph* g, const gv_tuning* t);
+int gv_get_tuning(gv_graph* g, gv_tuning* t);
+
 /* A plan records every kernel of ops[0, n_ops) into one HIP graph, so that
  * the whole sequence is launched at once (gv_plan_launch) instead of one
  * launch per kernel per batch.  Everything a plan needs is sized when it is

@@ -50,6 +50,7 @@ void free_graph(gv_graph* g) {
     g->ctx.release();
     g->scratch.release();
     for (auto& v : g->vscr) v.release();
+    g->cscr.release();
     void* mem[] = {g->mem_pool, g->mem_free, g->mem_dir, g->mem_dfree,
                    g->mem_vt,   g->mem_active, g->mem_ctr};
     for (void* p : mem)
@@ -359,6 +360,21 @@ int gv_kernel_names(gv_graph* g, char* buf, size_t cap, size_t* needed) {
     *needed = all.size() + 1;
     if (!buf || cap < all.size() + 1) return GV_ERANGE;
     std::memcpy(buf, all.c_str(), all.size() + 1);
+    return GV_OK;
+}
+
+int gv_set_tuning(gv_graph* g, const gv_tuning* t) {
+    if (!g || !t) return GV_EINVAL;
+    if (t->coalesce > 1 || t->small_sort_max > 4096) return GV_EINVAL;
+    return guarded(g, [&] {
+        hip_check(hipStreamSynchronize(g->ctx.stream), "hipStreamSynchronize");
+        g->tune = *t;
+    });
+}
+
+int gv_get_tuning(gv_graph* g, gv_tuning* t) {
+    if (!g || !t) return GV_EINVAL;
+    *t = g->tune;
     return GV_OK;
 }
 

@@ -6,6 +6,12 @@
 // for the largest batch before recording, vertex inserts keep the dictionary
 // as it is, and vertex deletes size their buffers for a full pool (every
 // stored edge holds a pool slot) instead of reading the edge count back.
+//
+// With coalescing on (gv_tuning), every run of consecutive edge batches up
+// to the next vertex batch is copied into one list of (op, src, dst) entries
+// (one kernel per up to 16 batches) and applied as a mixed list: the same
+// result as the batches in order, since each pair's last entry decides, with
+// one grouping sort per run instead of one per batch.
 #include <algorithm>
 #include <cstring>
 #include <new>
@@ -23,9 +29,92 @@ struct gv_plan {
     uint64_t scratch_gen = 0;
     uint64_t vscr_gen[3] = {0, 0, 0};
     uint64_t table_gen = 0;
+    uint64_t cscr_gen = 0;
 };
 
 namespace {
+
+struct CopyDesc {
+    const uint32_t* a;
+    const uint32_t* b;
+    unsigned long long n, off;
+    uint32_t kind, pad;
+};
+constexpr int kCopyDescs = 16;
+struct CopyArgs {
+    CopyDesc d[kCopyDescs];
+};
+
+// batch blockIdx.y of the group goes to entries [off, off + n) of the run
+__global__ __launch_bounds__(kThreads) void k_coalesce(CopyArgs args, uint8_t* op, uint32_t* src,
+                                                       uint32_t* dst) {
+    const CopyDesc D = args.d[blockIdx.y];
+    const uint64_t stride = (uint64_t)gridDim.x * kThreads;
+    for (uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x; i < D.n; i += stride) {
+        src[D.off + i] = D.a[i];
+        dst[D.off + i] = D.b[i];
+        op[D.off + i] = (uint8_t)D.kind;
+    }
+}
+
+bool is_edge(const gv_op& op) {
+    return op.kind == GV_OP_INSERT_EDGES || op.kind == GV_OP_DELETE_EDGES;
+}
+
+// Longest run coalesced when the tuning sets no limit (a mixed list's sort
+// takes fewer than 2^30 entries).
+constexpr uint64_t kRunCap = 1ull << 28;
+
+// End of the run of edge batches that starts at i (batches of no pairs do
+// not end a run), within max_pairs pairs (0: kRunCap; a run takes at least
+// its first batch).
+uint64_t run_end(const gv_op* ops, uint64_t n_ops, uint64_t i, uint64_t max_pairs,
+                 uint64_t* pairs) {
+    const uint64_t cap = max_pairs ? std::min(max_pairs, kRunCap) : kRunCap;
+    uint64_t j = i, tot = 0;
+    while (j < n_ops && (is_edge(ops[j]) || ops[j].n == 0)) {
+        if (j > i && tot + ops[j].n > cap) break;
+        tot += is_edge(ops[j]) ? ops[j].n : 0;
+        ++j;
+    }
+    *pairs = tot;
+    return j;
+}
+
+// apply a run of edge batches as one mixed list
+void run_coalesced(gv_graph* g, const gv_op* ops, uint64_t i, uint64_t j, uint64_t pairs) {
+    Ctx& c = g->ctx;
+    g->cscr.ensure(std::max<size_t>(pairs * 9, 4), c.stream);
+    uint32_t* src = (uint32_t*)g->cscr.ptr;
+    uint32_t* dst = src + pairs;
+    uint8_t* op = (uint8_t*)(dst + pairs);
+    CopyArgs args{};
+    uint32_t cnt = 0;
+    uint64_t off = 0, big = 0;
+    auto flush = [&] {
+        if (!cnt) return;
+        const uint64_t gx = std::min<uint64_t>(std::max<uint64_t>(div_up(big, kThreads), 1), 1024);
+        hipLaunchKernelGGL(k_coalesce, dim3((uint32_t)gx, cnt), dim3(kThreads), 0, c.stream, args,
+                           op, src, dst);
+        hip_check(hipGetLastError(), "coalesce");
+        cnt = 0;
+        big = 0;
+    };
+    for (uint64_t k = i; k < j; ++k) {
+        if (!is_edge(ops[k]) || !ops[k].n) continue;
+        args.d[cnt] = CopyDesc{ops[k].a, ops[k].b, ops[k].n, off,
+                               ops[k].kind == GV_OP_INSERT_EDGES ? 0u : 1u, 0u};
+        off += ops[k].n;
+        big = std::max<uint64_t>(big, ops[k].n);
+        if (++cnt == kCopyDescs) flush();
+    }
+    flush();
+    mixed_edges(g, op, src, dst, pairs);
+}
+
+// ops[0, n_ops) in order, coalescing runs of edge batches when the graph's
+// tuning says so
+void run_ops(gv_graph* g, const gv_op* ops, uint64_t n_ops, bool recorded, uint64_t bound);
 
 int check_ops(const gv_op* ops, uint64_t n_ops) {
     if (n_ops && !ops) return GV_EINVAL;
@@ -82,6 +171,27 @@ int guarded_call(gv_graph* g, F&& f) {
     return rc;
 }
 
+void run_ops(gv_graph* g, const gv_op* ops, uint64_t n_ops, bool recorded, uint64_t bound) {
+    uint64_t i = 0;
+    while (i < n_ops) {
+        if (g->tune.coalesce && is_edge(ops[i])) {
+            uint64_t pairs = 0;
+            const uint64_t j = run_end(ops, n_ops, i, g->tune.max_run_pairs, &pairs);
+            uint64_t batches = 0;
+            for (uint64_t k = i; k < j; ++k) batches += ops[k].n ? 1 : 0;
+            if (batches > 1) {
+                run_coalesced(g, ops, i, j, pairs);
+            } else {
+                for (uint64_t k = i; k < j; ++k) run_op(g, ops[k], recorded, bound);
+            }
+            i = j;
+            continue;
+        }
+        run_op(g, ops[i], recorded, bound);
+        ++i;
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -90,9 +200,7 @@ int gv_apply_ops(gv_graph* g, const gv_op* ops, uint64_t n_ops) {
     if (!g) return GV_EINVAL;
     const int rc = check_ops(ops, n_ops);
     if (rc != GV_OK) return rc;
-    return guarded_call(g, [&] {
-        for (uint64_t i = 0; i < n_ops; ++i) run_op(g, ops[i], false, 0);
-    });
+    return guarded_call(g, [&] { run_ops(g, ops, n_ops, false, 0); });
 }
 
 int gv_plan_create(gv_graph* g, const gv_op* ops, uint64_t n_ops, gv_plan** out) {
@@ -107,8 +215,22 @@ int gv_plan_create(gv_graph* g, const gv_op* ops, uint64_t n_ops, gv_plan** out)
         Ctx& c = g->ctx;
         // every stored edge holds a pool slot
         const uint64_t bound = std::max<uint64_t>(g->v.cap_blocks * (uint64_t)g->v.B, 1);
-        // size every buffer for the largest op
-        size_t sc = 0, vs[3] = {0, 0, 0};
+        // size every buffer for the largest op (and run)
+        size_t sc = 0, vs[3] = {0, 0, 0}, csz = 0;
+        for (uint64_t i = 0; g->tune.coalesce && i < n_ops;) {
+            if (!is_edge(ops[i])) {
+                ++i;
+                continue;
+            }
+            uint64_t pairs = 0;
+            const uint64_t j = run_end(ops, n_ops, i, g->tune.max_run_pairs, &pairs);
+            size_t mb[2];
+            mixed_bytes(g, std::max<uint64_t>(pairs, 1), mb);
+            sc = std::max(sc, mb[0]);
+            vs[0] = std::max(vs[0], mb[1]);
+            csz = std::max<size_t>(csz, pairs * 9);
+            i = j;
+        }
         for (uint64_t i = 0; i < n_ops; ++i) {
             const gv_op& op = ops[i];
             if (!op.n) continue;
@@ -125,6 +247,7 @@ int gv_plan_create(gv_graph* g, const gv_op* ops, uint64_t n_ops, gv_plan** out)
         }
         g->scratch.ensure(std::max<size_t>(sc, 4), c.stream);
         for (int k = 0; k < 3; ++k) g->vscr[k].ensure(std::max<size_t>(vs[k], 4), c.stream);
+        g->cscr.ensure(std::max<size_t>(csz, 4), c.stream);
         hip_check(hipStreamSynchronize(c.stream), "hipStreamSynchronize");
         edge_batch_warm();
         vertex_batch_warm();
@@ -139,7 +262,7 @@ int gv_plan_create(gv_graph* g, const gv_op* ops, uint64_t n_ops, gv_plan** out)
         try {
             hip_check(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal),
                       "hipStreamBeginCapture");
-            for (uint64_t i = 0; i < n_ops; ++i) run_op(g, ops[i], true, bound);
+            run_ops(g, ops, n_ops, true, bound);
             hip_check(hipStreamEndCapture(cs, &graph), "hipStreamEndCapture");
         } catch (...) {
             hipGraph_t dropped = nullptr;
@@ -159,6 +282,7 @@ int gv_plan_create(gv_graph* g, const gv_op* ops, uint64_t n_ops, gv_plan** out)
         p->scratch_gen = g->scratch.gen;
         for (int k = 0; k < 3; ++k) p->vscr_gen[k] = g->vscr[k].gen;
         p->table_gen = g->table_gen;
+        p->cscr_gen = g->cscr.gen;
     });
     if (rc != GV_OK) {
         gv_plan_destroy(p);
@@ -172,7 +296,8 @@ int gv_plan_launch(gv_plan* p) {
     if (!p || !p->g || !p->exec) return GV_EINVAL;
     gv_graph* g = p->g;
     return guarded_call(g, [&] {
-        bool same = g->scratch.gen == p->scratch_gen && g->table_gen == p->table_gen;
+        bool same = g->scratch.gen == p->scratch_gen && g->table_gen == p->table_gen &&
+                    g->cscr.gen == p->cscr_gen;
         for (int k = 0; k < 3; ++k) same = same && g->vscr[k].gen == p->vscr_gen[k];
         if (!same) fail(GV_EINVAL, "graph buffers moved since the plan was created");
         hip_check(hipGraphLaunch(p->exec, g->ctx.stream), "hipGraphLaunch");

@@ -1560,6 +1560,8 @@ void edge_batch_warm() {
     resident_grid(k_os_pass<uint64_t, true>, kOsThreads);
 }
 
+// bytes of g->scratch edge_batch carves for n pairs (edge_batch_sorted carves
+// the same)
 size_t edge_batch_bytes(const gv_graph* g, EdgeMode mode, uint64_t n) {
     if (n == 0) return 0;
     BatchArrays A;
@@ -1568,8 +1570,45 @@ size_t edge_batch_bytes(const gv_graph* g, EdgeMode mode, uint64_t n) {
     return m.used;
 }
 
+// Insert and delete batches whose keys arrive sorted (keys[0, *count), the
+// count on the device): the first kernel clears the batch counters and sets
+// the valid count, the second clears the marks and adds up the keys' mix64
+// sum (the probe's multiset check then holds the sorted keys to it).
+__global__ void k_sorted_prep_a(GraphView g, const unsigned long long* count) {
+    clear_batch_counters(g.ctr, threadIdx.x);
+    if (threadIdx.x == 0) g.ctr->tot[kTotValid] = *count;
+}
+
+__global__ __launch_bounds__(kThreads) void k_sorted_prep_b(GraphView g, const uint64_t* keys,
+                                                            const unsigned long long* count,
+                                                            uint64_t n, uint8_t* mark) {
+    __shared__ unsigned long long s_w[kWaves];
+    const uint64_t i = thread_index();
+    const uint64_t nv = *count;
+    if (i < n) mark[i] = 0;
+    const unsigned long long h = i < nv ? mix64(keys[i]) : 0ull;
+    const unsigned long long t = block_sum(h, s_w);
+    if (threadIdx.x == 0 && t) atomicAdd(&g.ctr->tot[kTotHash], t);
+}
+
+static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t* dst,
+                     const uint64_t* sorted, const unsigned long long* sorted_n, uint64_t n,
+                     uint8_t* out, bool sticky, void* fixed, size_t fixed_bytes);
+
 void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t* dst, uint64_t n,
                 uint8_t* out, bool sticky, void* fixed, size_t fixed_bytes) {
+    edge_run(g, mode, src, dst, nullptr, nullptr, n, out, sticky, fixed, fixed_bytes);
+}
+
+void edge_batch_sorted(gv_graph* g, EdgeMode mode, const uint64_t* keys,
+                       const unsigned long long* count, uint64_t n_max, bool sticky) {
+    if (mode == kQuery) fail(GV_EINVAL, "sorted batches are inserts or deletes");
+    edge_run(g, mode, nullptr, nullptr, keys, count, n_max, nullptr, sticky, nullptr, 0);
+}
+
+static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t* dst,
+                     const uint64_t* sorted, const unsigned long long* sorted_n, uint64_t n,
+                     uint8_t* out, bool sticky, void* fixed, size_t fixed_bytes) {
     if (n == 0) return;
     if (n >= 0x3fffffffull) fail(GV_EINVAL, "batch too large");
     Ctx& c = g->ctx;
@@ -1597,7 +1636,13 @@ void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t*
     const uint64_t grid = div_up(n, kThreads);
 
     bool flip;
-    if (mode == kQuery) {
+    const uint64_t* keys_in = nullptr;
+    if (sorted) {
+        c.launch("pack", k_sorted_prep_a, 1, 64, v, sorted_n);
+        c.launch("pack", k_sorted_prep_b, grid, kThreads, v, sorted, sorted_n, n, A.mark);
+        keys_in = sorted;
+        flip = false;
+    } else if (mode == kQuery) {
         c.launch("begin", k_begin, std::min<uint64_t>(div_up(A.state_words, kThreads), 1024),
                  kThreads, v, A.state, A.state_words);
         scan2(c, "pack", PackIn{v, src, dst}, PackOut{v.L, A.keys0, A.vals0, out, A.mark}, n,
@@ -1605,7 +1650,7 @@ void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t*
         flip = onesweep<uint64_t, true>(c, A.keys0, A.keys1, A.vals0, A.vals1,
                                         (const uint32_t*)n_valid, n, bits, A.state, err,
                                         g->spin_limit);
-    } else if (n <= kOsTile && bits > 0) {
+    } else if (n <= std::min<uint64_t>(g->tune.small_sort_max, kOsTile) && bits > 0) {
         const uint64_t sentinel = bits >= 64 ? ~0ull : (1ull << bits) - 1;
         c.launch("pack", k_pack_sort_tile, 1, kOsThreads, v, src, dst, n, os_passes(bits),
                  sentinel, A.keys0, A.mark);
@@ -1620,7 +1665,7 @@ void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t*
         flip = onesweep_passes<uint64_t, false>(c, A.keys0, A.keys1, nullptr, nullptr, nullptr, n,
                                                 bits, A.state, err, g->spin_limit);
     }
-    const uint64_t* keys = flip ? A.keys1 : A.keys0;
+    const uint64_t* keys = keys_in ? keys_in : flip ? A.keys1 : A.keys0;
     const uint32_t* vals = flip ? A.vals1 : A.vals0;
 
     scan2(c, "segments", SegIn{keys, ctr, v.L},

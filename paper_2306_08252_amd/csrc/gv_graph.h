@@ -12,6 +12,8 @@ struct gv_graph {
     gv::DevCounters* hctr = nullptr;  // pinned host copy for read-back
     gv::Scratch scratch;          // per-call temporaries
     gv::Scratch vscr[3];          // vertex-batch buffers that outlive an inner edge batch
+    gv::Scratch cscr;             // a coalesced run of edge batches (batched form)
+    gv_tuning tune{0u, 0u, 4096u, {0u, 0u, 0u, 0u, 0u}};
     uint64_t table_gen = 0;       // counts vertex-table reallocations
     uint64_t item_slots = 0;      // bound on live adjacency slots (pool slots)
     uint32_t spin_limit = gv::kSpinLimitDefault;  // bound on each look-back wait of batch sorts
@@ -39,6 +41,12 @@ void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t*
                 uint64_t n, uint8_t* out, bool sticky, void* fixed = nullptr,
                 size_t fixed_bytes = 0);
 
+// an insert or delete batch whose keys (src << L) | dst are already sorted
+// and valid: keys[0, *count) with the count on the device (at most n_max);
+// keys must not live in g->scratch, which the batch carves
+void edge_batch_sorted(gv_graph* g, EdgeMode mode, const uint64_t* keys,
+                       const unsigned long long* count, uint64_t n_max, bool sticky);
+
 // the per-device address of the fixed scratch of gv_edge_exists_noalloc,
 // looked up once per device (graph creation calls it with the device current)
 void noalloc_setup();
@@ -62,6 +70,8 @@ void edge_batch_warm();
 void vertex_batch_warm();
 // bytes of g->scratch an edge batch of n pairs carves
 size_t edge_batch_bytes(const gv_graph* g, EdgeMode mode, uint64_t n);
+// bytes of g->scratch ([0]) and g->vscr[0] ([1]) a mixed list of n entries needs
+void mixed_bytes(const gv_graph* g, uint64_t n, size_t out[2]);
 // bytes a vertex batch needs: [0] g->scratch, [1..3] g->vscr[0..2]
 void vertex_batch_bytes(const gv_graph* g, bool del, uint64_t n, uint64_t edge_bound,
                         size_t out[4]);

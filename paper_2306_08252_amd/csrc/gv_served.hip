@@ -1,25 +1,25 @@
 // gv_served.hip -- mixed edge updates with last-writer reduction: the tick of
-// the served form.
+// the served form, and the unit the batched form coalesces runs of edge
+// batches into.
 //
 // A list of (op, src, dst) entries, op 0 = insert and 1 = delete, has the
 // effect of applying the entries one at a time in list order with set
 // semantics (Sec. 4.3's batch model; the order inside a batch is ours): a
 // pair's final membership is decided by its last entry, and entries with an
 // inactive or out-of-range endpoint change nothing.  On the device: pack the
-// valid entries as keys (src << L) | dst with their list position, sort them
-// stably, keep the last entry of every key, and write it to the delete list
-// or the insert list at its sorted position (the other positions hold an
-// out-of-range pair, which the batch paths reject).  The two lists are then
-// applied as one delete batch and one insert batch: no key is in both, so
-// their order does not matter.
+// valid entries as keys (src << L) | dst with their list position (an invalid
+// entry gets bit 2L, after every valid key), sort them stably, and keep the
+// last entry of every key: a scan writes the kept deletes and the kept
+// inserts, compacted and still sorted, to two key lists.  The two lists are
+// then applied as a delete batch and an insert batch that start from their
+// sorted keys (no second sort); no key is in both, so their order does not
+// matter.
 #include "gv_graph.h"
 #include "gv_prim.h"
 
 namespace gv {
 
 namespace {
-
-constexpr uint32_t kNoPair = 0xFFFFFFFFu;  // an id past every table
 
 __global__ __launch_bounds__(kThreads) void k_mixed_pack(GraphView g, const uint8_t* op,
                                                          const uint32_t* src,
@@ -29,40 +29,80 @@ __global__ __launch_bounds__(kThreads) void k_mixed_pack(GraphView g, const uint
     if (i >= n) return;
     const uint32_t s = src[i], d = dst[i];
     const bool ok = active_bit(g, s) & active_bit(g, d) & (op[i] <= 1);
-    // an invalid entry gets bit 2L: it sorts after every valid key
     keys[i] = ok ? ((uint64_t)s << g.L) | d : (1ull << (2 * g.L));
     pos[i] = (uint32_t)i;
 }
 
-__global__ __launch_bounds__(kThreads) void k_mixed_split(GraphView g, const uint64_t* keys,
-                                                          const uint32_t* pos, const uint8_t* op,
-                                                          uint64_t n, uint32_t* ins_src,
-                                                          uint32_t* ins_dst, uint32_t* del_src,
-                                                          uint32_t* del_dst) {
-    const uint64_t p = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (p >= n) return;
-    const uint64_t k = keys[p];
-    const bool valid = (k >> (2 * g.L)) == 0;
-    const bool last = p + 1 == n || keys[p + 1] != k;  // stable sort: last in list order
-    uint32_t is = kNoPair, id = kNoPair, ds = kNoPair, dd = kNoPair;
-    if (valid && last) {
-        const uint32_t s = (uint32_t)(k >> g.L);
-        const uint32_t d = (uint32_t)(k & ((1ull << g.L) - 1));
-        if (op[pos[p]] == 0) {
-            is = s;
-            id = d;
-        } else {
-            ds = s;
-            dd = d;
-        }
+// Scan source over the sorted entries: an entry counts when it is valid and
+// the last of its key (the sort is stable: last in list order), as a delete
+// (low half) or an insert (high half).
+struct SplitIn {
+    const uint64_t* keys;
+    const uint32_t* pos;
+    const uint8_t* op;
+    uint64_t n;
+    uint32_t L;
+    struct Rec {
+        uint64_t k;
+        uint32_t p;
+        uint8_t o;
+        bool last;  // no later entry has the same key
+    };
+    __device__ uint64_t limit(uint64_t m) const { return m; }
+    __device__ Rec load(uint64_t i, bool) const {
+        Rec r;
+        r.k = keys[i];
+        r.last = i + 1 >= n || keys[i + 1] != r.k;
+        r.p = pos[i];
+        r.o = 0;
+        return r;
     }
-    ins_src[p] = is;
-    ins_dst[p] = id;
-    del_src[p] = ds;
-    del_dst[p] = dd;
+    __device__ void deref(Rec& r) const { r.o = op[r.p]; }
+    // 0 = not kept, 1 = kept delete, 2 = kept insert
+    __device__ int kind(const Rec& r) const {
+        if ((r.k >> (2 * L)) != 0 || !r.last) return 0;
+        return r.o == 1 ? 1 : 2;
+    }
+    __device__ unsigned long long value(uint64_t, const Rec& r) const {
+        const int k = kind(r);
+        return k == 1 ? 1ull : k == 2 ? (1ull << 32) : 0ull;
+    }
+};
+
+struct SplitOut {
+    SplitIn in;
+    uint64_t* del_keys;
+    uint64_t* ins_keys;
+    __device__ void operator()(uint64_t, const SplitIn::Rec& r, uint64_t,
+                               unsigned long long pre) const {
+        const int k = in.kind(r);
+        if (k == 1) del_keys[(uint32_t)pre] = r.k;
+        else if (k == 2) ins_keys[(uint32_t)(pre >> 32)] = r.k;
+    }
+};
+
+// the scan total holds both counts; the two sorted batches read one each
+__global__ void k_mixed_counts(const unsigned long long* total, unsigned long long* del_n,
+                               unsigned long long* ins_n) {
+    *del_n = *total & 0xffffffffull;
+    *ins_n = *total >> 32;
 }
 
 }  // namespace
+
+// bytes of g->scratch and of g->vscr[0] a mixed list of n entries needs
+void mixed_bytes(const gv_graph* g, uint64_t n, size_t out[2]) {
+    const int bits = 2 * (int)g->v.L + 1;
+    Carver m(nullptr);
+    m.take<uint64_t>(n);
+    m.take<uint64_t>(n);
+    m.take<uint32_t>(n);
+    m.take<uint32_t>(n);
+    m.take<unsigned long long>(scan2_parts(n));
+    m.take<uint32_t>(os_words(n, bits));
+    out[0] = std::max(m.used, edge_batch_bytes(g, kInsert, n));
+    out[1] = 2 * n * sizeof(uint64_t) + 4 * sizeof(unsigned long long);
+}
 
 void mixed_edges(gv_graph* g, const uint8_t* op, const uint32_t* src, const uint32_t* dst,
                  uint64_t n) {
@@ -71,19 +111,21 @@ void mixed_edges(gv_graph* g, const uint8_t* op, const uint32_t* src, const uint
     Ctx& c = g->ctx;
     const GraphView& v = g->v;
     const int bits = 2 * (int)v.L + 1;
-    // the lists outlive the two inner batches, which carve g->scratch
-    g->vscr[0].ensure(std::max<size_t>(4 * n * sizeof(uint32_t), 4), c.stream);
-    uint32_t* ins_src = (uint32_t*)g->vscr[0].ptr;
-    uint32_t* ins_dst = ins_src + n;
-    uint32_t* del_src = ins_dst + n;
-    uint32_t* del_dst = del_src + n;
+    // the key lists and counts outlive the two inner batches, which carve
+    // g->scratch
+    g->vscr[0].ensure(2 * n * sizeof(uint64_t) + 4 * sizeof(unsigned long long), c.stream);
+    uint64_t* del_keys = (uint64_t*)g->vscr[0].ptr;
+    uint64_t* ins_keys = del_keys + n;
+    unsigned long long* cnt = (unsigned long long*)(ins_keys + n);  // total, deletes, inserts
     uint64_t *k0, *k1;
     uint32_t *p0, *p1, *state;
+    unsigned long long* part;
     auto carve = [&](Carver& cv) {
         k0 = cv.take<uint64_t>(n);
         k1 = cv.take<uint64_t>(n);
         p0 = cv.take<uint32_t>(n);
         p1 = cv.take<uint32_t>(n);
+        part = cv.take<unsigned long long>(scan2_parts(n));
         state = cv.take<uint32_t>(os_words(n, bits));
     };
     {
@@ -98,11 +140,14 @@ void mixed_edges(gv_graph* g, const uint8_t* op, const uint32_t* src, const uint
              p0);
     const bool flip = onesweep<uint64_t, true>(c, k0, k1, p0, p1, nullptr, n, bits, state,
                                                &v.ctr->err_wait, g->spin_limit);
-    c.launch("mixed_split", k_mixed_split, div_up(n, kThreads), kThreads, v,
-             (const uint64_t*)(flip ? k1 : k0), (const uint32_t*)(flip ? p1 : p0), op, n, ins_src,
-             ins_dst, del_src, del_dst);
-    edge_batch(g, kDelete, del_src, del_dst, n, nullptr, true);
-    edge_batch(g, kInsert, ins_src, ins_dst, n, nullptr, true);
+    const uint64_t* sk = flip ? k1 : k0;
+    const uint32_t* sp = flip ? p1 : p0;
+    const SplitIn in{sk, sp, op, n, v.L};
+    scan2(c, "mixed_split", in, SplitOut{in, del_keys, ins_keys}, n, part, &cnt[0]);
+    c.launch("mixed_split", k_mixed_counts, 1, 1, (const unsigned long long*)&cnt[0], &cnt[1],
+             &cnt[2]);
+    edge_batch_sorted(g, kDelete, del_keys, &cnt[1], n, true);
+    edge_batch_sorted(g, kInsert, ins_keys, &cnt[2], n, true);
 }
 
 }  // namespace gv

@@ -66,6 +66,15 @@ class gv_counters(C.Structure):
         return out
 
 
+class gv_tuning(C.Structure):
+    _fields_ = [("coalesce", C.c_uint32), ("max_run_pairs", C.c_uint32),
+                ("small_sort_max", C.c_uint32), ("reserved", C.c_uint32 * 5)]
+
+    def as_dict(self):
+        return {"coalesce": self.coalesce, "max_run_pairs": self.max_run_pairs,
+                "small_sort_max": self.small_sort_max}
+
+
 class gv_op(C.Structure):
     _fields_ = [("kind", C.c_uint32), ("reserved", C.c_uint32), ("a", C.c_void_p),
                 ("b", C.c_void_p), ("n", C.c_uint64)]
@@ -108,6 +117,8 @@ def lib():
             "gv_kernel_names": [vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)],
             "gv_set_stream": [vp, vp],
             "gv_debug_spin_limit": [vp, C.c_uint32],
+            "gv_set_tuning": [vp, C.POINTER(gv_tuning)],
+            "gv_get_tuning": [vp, C.POINTER(gv_tuning)],
             "gv_cbt_init": [C.POINTER(C.c_void_p), C.c_uint64, u32p, u32p, C.c_uint64,
                             C.c_uint32, C.c_uint64, vp],
             "gv_cbt_insert_edges": [vp, u32p, u32p, C.c_uint64, C.POINTER(gv_batch_stats)],
@@ -360,6 +371,26 @@ def gv_set_stream(g, stream_ptr):
 
 def gv_sync(g):
     return lib().gv_sync(C.c_void_p(g))
+
+
+def gv_set_tuning(g, coalesce=None, max_run_pairs=None, small_sort_max=None):
+    """Sets the given fields of the graph's gv_tuning (others unchanged)."""
+    t = gv_tuning()
+    _check(lib().gv_get_tuning(C.c_void_p(g), C.byref(t)), "gv_get_tuning")
+    if coalesce is not None:
+        t.coalesce = int(coalesce)
+    if max_run_pairs is not None:
+        t.max_run_pairs = int(max_run_pairs)
+    if small_sort_max is not None:
+        t.small_sort_max = int(small_sort_max)
+    _check(lib().gv_set_tuning(C.c_void_p(g), C.byref(t)), "gv_set_tuning")
+    return t.as_dict()
+
+
+def gv_get_tuning(g):
+    t = gv_tuning()
+    _check(lib().gv_get_tuning(C.c_void_p(g), C.byref(t)), "gv_get_tuning")
+    return t.as_dict()
 
 
 def gv_debug_spin_limit(g, limit):

@@ -41,3 +41,20 @@ def batched_ops(w, seed_name="batched", nbatch=256, device="cuda:0", lo=100, hi=
             ops.append((2 if draws[3 * j + 2] & np.uint64(1) else 3, ids, None))
             vids += m
     return ops, pairs, vids
+
+
+def batched_warmup(ops):
+    """A warm-up for a fresh graph before timing `ops`: an insert and a delete
+    of the largest insert batch, a vertex delete and re-insert of one id of
+    the first vertex-delete batch (sizes the scratch buffers)."""
+    big = max((o for o in ops if o[0] == 0), key=lambda o: o[1].numel())
+    one = ops[[o[0] for o in ops].index(3)][1][:1] if any(o[0] == 3 for o in ops) else None
+
+    def warm(g):
+        g.insert_edges(big[1], big[2], stats=False)
+        g.delete_edges(big[1], big[2], stats=False)
+        if one is not None:
+            g.delete_vertices(one)
+            g.insert_vertices(one)
+        torch.cuda.synchronize()
+    return warm

@@ -57,15 +57,26 @@ def oracle_apply(o, ops):
             o.delete_vertices(a)
 
 
-@pytest.mark.parametrize("B", [4, 16])
-def test_plan_matches_eager_and_oracle(B):
+@pytest.mark.parametrize("B,coalesce,max_run", [(4, 0, 0), (16, 0, 0), (4, 1, 0), (16, 1, 0),
+                                                 (16, 1, 1500)])
+def test_plan_matches_eager_and_oracle(B, coalesce, max_run):
+    """With coalescing, every run of edge batches is one mixed list (capped at
+    max_run pairs); the result must still be the batches in order."""
     gv = need_gpu()
     n = 1024
     s0, d0 = I.uniform_pairs(I.stream_seed("batched-init", B), 6000, n)
     ops = op_sequence(I.stream_seed("batched-ops", B), n, 40, 700, known=(s0, d0))
-    say(f"plan vs eager vs oracle, B={B}, {len(ops)} ops")
+    # a pair inserted then deleted, and deleted then inserted, within one run
+    ops[1:1] = [(0, np.array([5, 6], np.uint32), np.array([7, 8], np.uint32)),
+                (1, np.array([5, 9], np.uint32), np.array([7, 9], np.uint32)),
+                (0, np.array([9], np.uint32), np.array([9], np.uint32)),
+                (0, np.array([], np.uint32), np.array([], np.uint32))]
+    say(f"plan vs eager vs oracle, B={B}, coalesce={coalesce}/{max_run}, {len(ops)} ops")
     ga = gv.Graph(n, s0, d0, block_slots=B, vertex_capacity=n)
     gb = gv.Graph(n, s0, d0, block_slots=B, vertex_capacity=n)
+    for g in (ga, gb):
+        t = gv.gv_set_tuning(g.h, coalesce=coalesce, max_run_pairs=max_run)
+        assert t["coalesce"] == coalesce and gv.gv_get_tuning(g.h) == t
     o = O.OracleGraph(n, s0, d0, block_slots=B, vertex_capacity=n)
     plan = gv.Plan(gb.h, ops)
     for rnd in range(3):
@@ -150,8 +161,20 @@ def test_plan_errors():
     g.close()
 
 
+def test_tuning_rejects_bad_values():
+    gv = need_gpu()
+    g = gv.Graph(64, [1], [2], block_slots=8)
+    with pytest.raises(gv.GraphVineError):
+        gv.gv_set_tuning(g.h, coalesce=2)
+    with pytest.raises(gv.GraphVineError):
+        gv.gv_set_tuning(g.h, small_sort_max=4097)
+    assert gv.gv_get_tuning(g.h) == {"coalesce": 0, "max_run_pairs": 0, "small_sort_max": 4096}
+    g.close()
+
+
 @pytest.mark.timeout(900)
-def test_plan_rmat22_full_size_against_set_algebra():
+@pytest.mark.parametrize("coalesce", [0, 1])
+def test_plan_rmat22_full_size_against_set_algebra(coalesce):
     """The batched-form workload at its size: R-MAT 2^22 vertices / 2^26
     edges, 256 batches of log-uniform size in [10^2, 10^6] (45 / 45 / 10 edge
     inserts / edge deletes / vertex batches), recorded into one plan and
@@ -169,6 +192,7 @@ def test_plan_rmat22_full_size_against_set_algebra():
     n = w.num_vertices
     ops, pairs, vids = Wk.batched_ops(w, "batched", 256, "cuda:0")
     g = gv.Graph(n, w.src, w.dst, block_slots=B, vertex_capacity=n)
+    gv.gv_set_tuning(g.h, coalesce=coalesce)
     plan = gv.Plan(g.h, ops)
     plan.launch()
     assert g.sync() == 0
