@@ -114,6 +114,96 @@ def bytes_model(name, per_launch):
     return None
 
 
+def counter_delta(c0, c1):
+    import numpy as np
+    return {key: (np.array(c1[key]) - np.array(c0[key])) for key in c1}
+
+
+def m1_bytes(pairs, d):
+    """Bytes model M1 of edge batches (pairs read, one grouping pass, touched
+    adjacency scan, slot writes, vertex records, block bookkeeping) from the
+    library's counter deltas `d`."""
+    return pairs * (8 + 16) + 4 * int(d["scanned_slots"][0] + d["scanned_slots"][1]) \
+        + 4 * int(d["written_slots"]) + 16 * int(d["touched"][0] + d["touched"][1]) \
+        + 8 * int(d["new_blocks"]) + 8 * int(d["moved_slots"]) + 4 * int(d["freed_blocks"])
+
+
+def config3_form(gv, I, T, dev, k=10**7, nv=10**4):
+    """Large graphs: R-MAT 2^24 vertices / 2^28 edges (B = 16) and the
+    road-like 4096 x 4096 lattice (B = 8), each with one insert and one
+    delete batch of 10^7 edges (R-MAT: R-MAT pairs, then 80 % stored and 20 %
+    uniform pairs; lattice: 5 * 10^6 uniform undirected pairs stored both
+    ways, then half of them and a slice of the lattice, both ways), then a
+    vertex delete and re-insert batch of 10^4 uniform ids.  Each graph first
+    takes an untimed insert and delete of other batches of the same sizes
+    (sizes the scratch).  Per batch: edges/s and the M1 fraction of HBM
+    peak from the library's counters."""
+    import numpy as np
+    import torch
+
+    def timed(g, fn, *a):
+        torch.cuda.synchronize()
+        c0 = g.counters()
+        t0 = time.perf_counter()
+        st = fn(*a)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        return st, el, counter_delta(c0, g.counters())
+
+    def edge_row(g, fn, s, d, label):
+        st, el, dd = timed(g, fn, s, d)
+        m1 = m1_bytes(int(s.numel() if hasattr(s, "numel") else len(s)), dd)
+        return {"pairs": int(len(s)), "ms": round(el * 1e3, 3),
+                "edges_per_s": round(len(s) / el, 1), "applied": int(st[0]),
+                "pct_hbm_m1": round(m1 / el / (HBM_PEAK_GBS * 1e9), 5), "op": label}
+
+    def vertex_rows(g, n, tag):
+        ids = torch.from_numpy((I.splitmix64(I.stream_seed(tag, "vertices"), nv) % np.uint64(n))
+                               .astype(np.uint32).view(np.int32)).to(dev)
+        st, el_d, _ = timed(g, g.delete_vertices, ids)
+        st2, el_i, _ = timed(g, g.insert_vertices, ids)
+        return {"ids": nv, "delete_ms": round(el_d * 1e3, 3), "insert_ms": round(el_i * 1e3, 3),
+                "delete_stats": st, "insert_stats": st2}
+
+    out = {}
+    w = T.RmatWorkload(24, 1 << 28, name="scale", device=dev)
+    g = gv.Graph(w.num_vertices, w.src, w.dst, block_slots=16, device=dev)
+    g.insert_edges(*w.insert_batch(k, 7), stats=False)
+    g.delete_edges(*w.delete_batch(k, 7), stats=False)
+    ins = edge_row(g, g.insert_edges, *w.insert_batch(k, 0), "insert")
+    dele = edge_row(g, g.delete_edges, *w.delete_batch(k, 0), "delete")
+    out["rmat24_e2^28_b16"] = {"insert_1e7": ins, "delete_1e7": dele,
+                               "vertex_1e4": vertex_rows(g, w.num_vertices, "config3-rmat"),
+                               "edges_after": g.memory_used()["num_edges"]}
+    g.close()
+    del w
+    torch.cuda.empty_cache()
+    side = 4096
+    n = side * side
+    src, dst = I.lattice_graph(I.stream_seed("road", side), side)
+    g = gv.Graph(n, src, dst, block_slots=8, device=dev)
+
+    def both(a, b):
+        return (torch.from_numpy(np.concatenate([a, b]).view(np.int32)).to(dev),
+                torch.from_numpy(np.concatenate([b, a]).view(np.int32)).to(dev))
+    wa, wb = I.uniform_pairs(I.stream_seed("road-warm", side), k // 2, n)
+    g.insert_edges(*both(wa, wb), stats=False)
+    g.delete_edges(*both(wa, wb), stats=False)
+    a, b = I.uniform_pairs(I.stream_seed("road-ins", side), k // 2, n)
+    ins = edge_row(g, g.insert_edges, *both(a, b), "insert")
+    da = np.concatenate([a[: k // 4], src[: k // 4]])
+    db = np.concatenate([b[: k // 4], dst[: k // 4]])
+    dele = edge_row(g, g.delete_edges, *both(da, db), "delete")
+    out["lattice4096_b8"] = {"insert_1e7": ins, "delete_1e7": dele,
+                             "vertex_1e4": vertex_rows(g, n, "config3-road"),
+                             "edges_after": g.memory_used()["num_edges"]}
+    rc = g.sync()
+    g.close()
+    if rc != 0:
+        raise RuntimeError(f"config3: {gv.gv_strerror(rc)}")
+    return out
+
+
 def implementation_bytes(name, per_launch):
     """What the kernel itself must move per launch (not M1): a radix pass
     reads and writes every key; a probe also reads directory entries, work
@@ -503,6 +593,8 @@ def main():
                     help="skip the block-size x batch-size sweep")
     ap.add_argument("--no-cbt", action="store_true",
                     help="skip the paper-faithful ablation (complete binary tree, Alg. 1-3)")
+    ap.add_argument("--no-config3", action="store_true",
+                    help="skip R-MAT 2^24 / 2^28 and the 4096^2 lattice with 10^7-edge batches")
     ap.add_argument("--no-served", action="store_true",
                     help="skip the served-form workload (continuous batching, p50/p99)")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "OUT_MD"),
@@ -633,14 +725,10 @@ def main():
     K = args.steps
     value = 2 * k * K / elapsed
 
-    d = {key: (np.array(c1[key]) - np.array(c0[key])) for key in c1}
+    d = counter_delta(c0, c1)
     ins_T, del_T = d["touched"][0], d["touched"][1]
     ins_S, del_S = d["scanned_slots"][0], d["scanned_slots"][1]
-    # bytes model M1 of the whole batch path (pairs read, one grouping pass,
-    # touched adjacency scan, slot writes, vertex records, block bookkeeping)
-    m1 = (2 * K * k) * (8 + 16) + 4 * (ins_S + del_S) + 4 * d["written_slots"] \
-        + 16 * (ins_T + del_T) + 8 * d["new_blocks"] + 8 * d["moved_slots"] \
-        + 4 * d["freed_blocks"]
+    m1 = m1_bytes(2 * K * k, d)
     pct_m1 = m1 / elapsed / (HBM_PEAK_GBS * 1e9)
 
     # per-launch quantities of the dominant kernel's batch type
@@ -719,6 +807,9 @@ def main():
     sweep = None if args.no_sweep else block_size_sweep(gv, w, dev)
     batched = None if args.no_batched else batched_form(gv, I, T, dev)
     served = None if args.no_served else served_form(gv, I, T, dev, B)
+    config3 = None if args.no_config3 else config3_form(gv, I, T, dev)
+    if config3:
+        log("config3:", json.dumps(config3))
 
     # ---- CPU oracle baseline on a quarter of the sources
     cpu = None
@@ -780,6 +871,7 @@ def main():
                    "num_edges": mem["num_edges"]},
         "paper_cbt_ablation": cbt,
         "batched_form": batched,
+        "config3": config3,
         "served_p50_p99": served,
         "block_size_sweep": sweep,
         "pilot_kernels_ms": pilot,
