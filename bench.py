@@ -135,8 +135,9 @@ def config3_form(gv, I, T, dev, k=10**7, nv=10**4):
     uniform pairs; lattice: 5 * 10^6 uniform undirected pairs stored both
     ways, then half of them and a slice of the lattice, both ways), then a
     vertex delete and re-insert batch of 10^4 uniform ids.  Each graph first
-    takes an untimed insert and delete of other batches of the same sizes
-    (sizes the scratch).  Per batch: edges/s and the M1 fraction of HBM
+    takes an untimed insert and delete of other batches of the same sizes,
+    and the vertex batches an untimed delete and re-insert of other ids
+    (sizes the buffers).  Per batch: edges/s and the M1 fraction of HBM
     peak from the library's counters."""
     import numpy as np
     import torch
@@ -158,8 +159,13 @@ def config3_form(gv, I, T, dev, k=10**7, nv=10**4):
                 "pct_hbm_m1": round(m1 / el / (HBM_PEAK_GBS * 1e9), 5), "op": label}
 
     def vertex_rows(g, n, tag):
-        ids = torch.from_numpy((I.splitmix64(I.stream_seed(tag, "vertices"), nv) % np.uint64(n))
-                               .astype(np.uint32).view(np.int32)).to(dev)
+        def draw(*name):
+            return torch.from_numpy((I.splitmix64(I.stream_seed(tag, *name), nv) % np.uint64(n))
+                                    .astype(np.uint32).view(np.int32)).to(dev)
+        warm = draw("warm")  # untimed: sizes the buffers
+        g.delete_vertices(warm)
+        g.insert_vertices(warm)
+        ids = draw("vertices")
         st, el_d, _ = timed(g, g.delete_vertices, ids)
         st2, el_i, _ = timed(g, g.insert_vertices, ids)
         return {"ids": nv, "delete_ms": round(el_d * 1e3, 3), "insert_ms": round(el_i * 1e3, 3),
@@ -783,10 +789,15 @@ def main():
     adj_ms = (time.perf_counter() - t0) * 1e3
     mem = g.memory_used()
 
-    # ---- vertex batches of 10^4: delete then re-insert the same ids
-    vids = torch.from_numpy(
-        (I.splitmix64(I.stream_seed("bench-vertices"), 10**4) % np.uint64(n))
-        .astype(np.uint32).view(np.int32)).to(dev)
+    # ---- vertex batches of 10^4: delete then re-insert the same ids, after
+    # an untimed delete and re-insert of other ids (sizes the buffers)
+    def vertex_ids(tag):
+        return torch.from_numpy((I.splitmix64(I.stream_seed(tag), 10**4) % np.uint64(n))
+                                .astype(np.uint32).view(np.int32)).to(dev)
+    warm_ids = vertex_ids("bench-vertices-warm")
+    g.delete_vertices(warm_ids)
+    g.insert_vertices(warm_ids)
+    vids = vertex_ids("bench-vertices")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     vdel = g.delete_vertices(vids)

@@ -63,10 +63,13 @@ bool pow2(uint64_t x) { return x && !(x & (x - 1)); }
 
 // A batch sort that failed (a look-back wait ran out, or the sorted keys were
 // out of order or not the packed keys) left its batch and every later batch
-// undone: the graph is unusable.  Reads the counters last copied to the host.
+// undone, and a vertex delete that ran past one of its list bounds left its
+// batch partly applied: either way the graph is unusable.  Reads the
+// counters last copied to the host.
 void check_sort(gv_graph* g) {
     if (g->hctr->err_wait) fail(GV_EDEVICE, "a batch sort's look-back wait ran out");
     if (g->hctr->err_order == 2) fail(GV_EDEVICE, "a batch's sorted keys were out of order");
+    if (g->hctr->err_order == 4) fail(GV_EDEVICE, "a vertex delete exceeded a device-side bound");
     if (g->hctr->err_order) fail(GV_EDEVICE, "a batch's sorted keys were not its packed keys");
 }
 
@@ -195,7 +198,10 @@ int gv_delete_vertices(gv_graph* g, const uint32_t* d_ids, uint64_t n, gv_batch_
     if (!g || (n && !d_ids)) return GV_EINVAL;
     if (n == 0) return GV_OK;
     gv_batch_stats tmp{};
-    int rc = guarded(g, [&] { vertex_delete(g, d_ids, n, &tmp); });
+    int rc = guarded(g, [&] {
+        vertex_delete(g, d_ids, n, &tmp);
+        check_sort(g);  // counters were read back for the statistics
+    });
     if (rc == GV_OK && st) *st = tmp;
     return rc;
 }

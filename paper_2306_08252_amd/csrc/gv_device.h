@@ -64,8 +64,8 @@ struct DevCounters {
     uint32_t n_heavy;                  // sources left to whole waves this batch
     uint32_t err_order;                // a batch's sorted keys failed their check
     uint32_t sort_n, sort_err;  // count and look-back error word of whole-graph sorts
-    // vertex delete: sweep units, kept slots, freed blocks | removed edges << 32
-    unsigned long long v_units, v_kept, v_fr;
+    // vertex delete: units listed, hubs listed, hole / survivor entries reserved
+    unsigned long long vd_units, vd_hubs, vd_pairs;
     // totals of the single-pass scans of the current batch
     unsigned long long tot[8];
     // statistics of the last batch
@@ -82,8 +82,9 @@ struct DevCounters {
 };
 
 // A batch sort that failed (a look-back wait ran out, or the sorted keys are
-// out of order or not the packed keys) makes every later batch step a no-op;
-// the graph reports GV_EDEVICE from then on.
+// out of order or not the packed keys), or a vertex delete that ran past a
+// list bound, makes every later edge-batch step a no-op; the graph reports
+// GV_EDEVICE from then on.
 __device__ __forceinline__ bool batch_failed(const DevCounters* c) {
     return (c->err_wait | c->err_order) != 0u;
 }

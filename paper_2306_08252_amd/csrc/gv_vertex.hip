@@ -4,15 +4,15 @@
 // the dictionary is replaced by one of the next power-of-two capacity (copy
 // kernel, then the old one is freed); inactive ids are switched on.
 //
-// Delete: the deleted set is marked in a bitmap.  Every adjacency is cut
-// into sweep units of 256 slots; a count pass finds the slots each unit keeps
-// (none for a deleted source, else those whose destination is not deleted),
-// a scan over units places them, the kept slots of every vertex that loses
-// any are gathered into a staging buffer and written back in order from
-// slot 0, emptied blocks go on the free list (a scan over vertices places
-// them), and the deleted vertices are switched off with their directory
-// segments returned.  All sizes are bounds known on the host, so the path has
-// no host round trip.
+// Delete: the deleted set is marked in a bitmap.  One sweep over the vertex
+// table compacts every small adjacency in place (thread per vertex) and cuts
+// the larger ones into units of 1024 slots; a wave per unit compacts a
+// vertex of one unit, and a vertex of several units fills the holes below
+// its new degree with its kept slots past it (three short kernels over its
+// units and one over such vertices).  Emptied blocks go on the free list,
+// and the deleted vertices are switched off with their directory segments
+// returned.  All sizes are bounds known on the host, so the path has no host
+// round trip.
 #include <algorithm>
 
 #include "gv_graph.h"
@@ -90,6 +90,7 @@ __global__ void k_vreset(DevCounters* c) {
     c->vany = 0;
     c->edges = 0;
     c->checksum = 0;
+    c->vd_units = c->vd_hubs = c->vd_pairs = 0;
 }
 
 // sorted ids: count rejected and distinct, activate the inactive ones
@@ -149,252 +150,322 @@ __global__ __launch_bounds__(kThreads) void k_vdel_mark(GraphView g, const uint3
     }
 }
 
-// 16-lane groups, one vertex each: count (EMIT = false) or emit (EMIT = true)
-// the edges that touch a deleted vertex; emitted pairs go to the vertex's
-// scanned offset, in slot order
-constexpr int kVGroup = 16;          // lanes per sweep unit
-constexpr int kVUnroll = 4;          // slots per lane per step
-constexpr uint32_t kVChunk = 256;    // adjacency slots per sweep unit
+// Vertex delete sweep.  Every active vertex with edges is visited once.
+//   small (deg <= kVSmall): one thread keeps the slots whose destination
+//     stays (none for a deleted source) in order from slot 0, in place, frees
+//     the emptied blocks and writes the new degree, all in the sweep kernel;
+//   larger vertices are cut into units of kVUnit slots, one wave per unit.  A
+//     vertex of one unit is compacted by its wave (stable, in registers).  A
+//     vertex of several units (a hub) takes three steps: its units count the
+//     slots they lose; the hub reserves room for min(lost, new degree) moves;
+//     its units list the holes below the new degree and the kept slots at or
+//     past it (as many as the holes); then the hub's wave fills every hole
+//     with one of those slots (any pairing: an adjacency is a set) and frees
+//     the emptied blocks.
+// Only the vertex table is read in full (once); slots are read once, and a
+// hub's units a second time only where they hold holes or survivors.
+constexpr uint32_t kVSmall = 64;         // slots compacted by one thread
+constexpr uint32_t kVPer = 16;           // slots per lane in a unit
+constexpr uint32_t kVUnit = 64 * kVPer;  // slots per unit
+constexpr uint32_t kVSingle = 0xFFFFFFFFu;
+constexpr uint32_t kVErrBound = 4;       // err_order value: a device-side bound was exceeded
 
-// Sweep units: every active vertex with edges is cut into units of kVChunk
-// slots, so that a hub is swept by many groups at once.  The scan gives each
-// vertex the index of its first unit.
-struct UnitIn {
-    GraphView g;
-    struct Rec {
-        VRec r;
-        bool act;
-    };
-    __device__ uint64_t limit(uint64_t n) const { return n; }
-    __device__ Rec load(uint64_t u, bool) const {
-        Rec x;
-        x.r = g.vt[u];
-        x.act = active_bit(g, (uint32_t)u);
-        return x;
-    }
-    __device__ void deref(Rec&) const {}
-    __device__ unsigned long long value(uint64_t, const Rec& x) const {
-        return x.act ? (x.r.deg + kVChunk - 1) / kVChunk : 0u;
-    }
+struct VDel {
+    const uint32_t* gone;
+    uint2* units;                // {vertex, kVSingle} or {hub, unit index}
+    uint32_t* ulost;             // per unit of a hub: slots lost
+    uint32_t* hv;                // per hub: vertex
+    uint32_t* hlost;             // per hub: slots lost
+    uint32_t* hnd;               // per hub: new degree
+    uint32_t* hholes;            // per hub: holes listed
+    uint32_t* hsurv;             // per hub: survivors listed
+    unsigned long long* hoff;    // per hub: first entry in holes / surv
+    uint32_t* holes;             // slot positions
+    uint32_t* surv;              // destination values
+    unsigned long long ucap, hcap, pcap;
 };
 
-// plain form of UnitIn for the three-kernel scan
-struct UnitCount {
-    GraphView g;
-    __device__ unsigned long long operator()(uint64_t u) const {
-        if (u >= g.n_cap || !active_bit(g, (uint32_t)u)) return 0ull;
-        return (g.vt[u].deg + kVChunk - 1) / kVChunk;
-    }
-};
+__device__ __forceinline__ void vd_error(const GraphView& g) {
+    g.ctr->err_order = kVErrBound;
+}
 
-// unit = (vertex, first slot) at the vertex's scanned offset; a lane writes
-// the units of its vertex, the whole wave those of a vertex with more than 4
-__global__ __launch_bounds__(kThreads) void k_vdel_units(GraphView g,
-                                                         const unsigned long long* uoff,
-                                                         uint2* units) {
-    const uint64_t u = vt_tidx();
-    uint32_t cnt = 0;
+// new record of a vertex left with nd slots
+__device__ __forceinline__ VRec vd_record(const GraphView& g, VRec r, uint32_t nd) {
+    r.deg = nd;
+    if (nblocks(g, nd) == 0 && r.dcls == kNoDir) r.dir = 0;
+    return r;
+}
+
+// Every lane of the wave calls this: lane-wise edges lost and blocks freed
+// go into the graph's counters with one atomic each per wave.
+__device__ __forceinline__ void vd_count(const GraphView& g, unsigned long long lost,
+                                         unsigned long long freed) {
+    lost = wave_sum(lost);
+    freed = wave_sum(freed);
+    if (lane_id() == 0) {
+        if (lost) atomicAdd(&g.ctr->live_edges, 0ull - lost);
+        if (freed) atomicAdd(&g.ctr->c_freed_blocks, freed);
+    }
+}
+
+// Every lane of the wave calls this: each lane pushes blocks [b0, b1) of its
+// record r onto the free stack, at slots reserved with one atomic per wave.
+__device__ __forceinline__ void vd_free_lanes(const GraphView& g, const VRec& r, uint32_t b0,
+                                              uint32_t b1) {
+    const uint32_t nf = b1 - b0;
+    const uint32_t inc = wave_incl_scan(nf);
+    const uint32_t tot = __shfl(inc, 63, 64);
+    if (!tot) return;
     unsigned long long base = 0;
-    if (u < g.n_cap && active_bit(g, (uint32_t)u)) {
-        cnt = (g.vt[u].deg + kVChunk - 1) / kVChunk;
-        base = uoff[u];
-    }
-    if (cnt <= 4)
-        for (uint32_t c = 0; c < cnt; ++c) units[base + c] = make_uint2((uint32_t)u, c * kVChunk);
-    uint64_t m = ballot(cnt > 4);
-    while (m) {
-        const int l = __ffsll((unsigned long long)m) - 1;
-        m &= m - 1;
-        const uint32_t wu = __shfl((uint32_t)u, l, 64), wc = __shfl(cnt, l, 64);
-        const unsigned long long wb = __shfl(base, l, 64);
-        for (uint32_t c = lane_id(); c < wc; c += 64) units[wb + c] = make_uint2(wu, c * kVChunk);
-    }
+    if (lane_id() == 63) base = atomicAdd(&g.ctr->free_cnt, (unsigned long long)tot);
+    base = __shfl(base, 63, 64) + (inc - nf);
+    for (uint32_t j = 0; j < nf; ++j) g.free_stack[base + j] = block_of(g, r, b0 + j);
 }
 
-// Three passes over the sweep units (unit count on the device):
-//   kCount   kept[k] = slots of unit k that stay
-//   kGather  for a vertex that loses slots, its unit's kept values go to
-//            stage[P[k] + rank] (P = exclusive scan of kept)
-//   kScatter they are written back to the vertex's slots P[k] - P[first] ...
-enum VPass { kCount = 0, kGather = 1, kScatter = 2 };
-
-template <int PASS>
-__global__ __launch_bounds__(kThreads) void k_vdel_pass(GraphView g, const uint32_t* gone,
-                                                        const uint2* units,
-                                                        const unsigned long long* uoff,
-                                                        uint32_t* kept,
-                                                        const unsigned long long* P,
-                                                        uint32_t* stage) {
-    const uint32_t lane = lane_id();
-    const uint32_t gl = lane & (kVGroup - 1);
-    const uint32_t g0 = lane & ~(uint32_t)(kVGroup - 1);
-    const uint64_t below = (1ull << gl) - 1;
-    const uint64_t ngroups = (uint64_t)gridDim.x * kThreads / kVGroup;
-    const uint64_t grp = ((uint64_t)blockIdx.x * kThreads + threadIdx.x) / kVGroup;
-    const uint64_t nunits = g.ctr->v_units;
-    for (uint64_t k = grp; k < nunits; k += ngroups) {
-        const uint2 U = units[k];
-        const VRec r = g.vt[U.x];
-        const uint32_t s1 = min(r.deg, U.y + kVChunk);
-        const bool src_gone = bit_of(gone, U.x);
-        unsigned long long base = 0, vbase = 0;
-        if (PASS != kCount) {
-            // the vertex's new degree: kept slots over all its units
-            const unsigned long long f = uoff[U.x];
-            const unsigned long long nu = (r.deg + kVChunk - 1) / kVChunk;
-            vbase = P[f];
-            const unsigned long long newdeg = P[f + nu] - vbase;
-            if (newdeg == r.deg) continue;  // the vertex keeps every slot
-            base = P[k];
-        }
-        if (PASS == kScatter) {
-            // stage[P[k] .. P[k] + kept[k]) -> slots P[k] - P[first] ...
-            const uint32_t nk = kept[k];
-            const uint32_t d0 = (uint32_t)(base - vbase);
-            for (uint32_t j = gl; j < nk; j += kVGroup) {
-                const uint32_t sl = d0 + j;
-                g.pool[slot_addr(g, r, sl)] = stage[base + j];
-            }
-            continue;
-        }
-        uint32_t c = 0;
-        for (uint32_t s0 = U.y; s0 < s1; s0 += kVGroup * kVUnroll) {
-            uint32_t blk[kVUnroll], x[kVUnroll];
-            bool keep[kVUnroll];
-#pragma unroll
-            for (int j = 0; j < kVUnroll; ++j)
-                blk[j] = block_of(g, r, min(s0 + j * kVGroup + gl, s1 - 1) >> g.log2B);
-#pragma unroll
-            for (int j = 0; j < kVUnroll; ++j) {
-                const uint32_t sl = min(s0 + j * kVGroup + gl, s1 - 1);
-                x[j] = g.pool[((uint64_t)blk[j] << g.log2B) + (sl & (g.B - 1))];
-            }
-#pragma unroll
-            for (int j = 0; j < kVUnroll; ++j)
-                keep[j] = s0 + j * kVGroup + gl < s1 && !src_gone && !bit_of(gone, x[j]);
-#pragma unroll
-            for (int j = 0; j < kVUnroll; ++j) {
-                const uint64_t m = (ballot(keep[j]) >> g0) & ((1ull << kVGroup) - 1);
-                if (PASS == kGather && keep[j]) stage[base + c + popc64(m & below)] = x[j];
-                c += popc64(m);
-            }
-        }
-        if (PASS == kCount && gl == 0) kept[k] = c;
-    }
+// One wave pushes blocks [b0, b1) of r onto the free stack.
+__device__ __forceinline__ void vd_free_wave(const GraphView& g, const VRec& r, uint32_t b0,
+                                             uint32_t b1) {
+    if (b1 <= b0) return;
+    unsigned long long base = 0;
+    if (lane_id() == 0) base = atomicAdd(&g.ctr->free_cnt, (unsigned long long)(b1 - b0));
+    base = __shfl(base, 0, 64);
+    for (uint32_t j = lane_id(); j < b1 - b0; j += 64) g.free_stack[base + j] = block_of(g, r, b0 + j);
 }
 
-// kept slots per unit, for the scan that places them
-struct KeptIn {
-    const uint32_t* kept;
-    const DevCounters* ctr;
-    struct Rec {
-        uint32_t c;
-    };
-    __device__ uint64_t limit(uint64_t n) const { return min((uint64_t)ctr->v_units, n); }
-    __device__ Rec load(uint64_t i, bool ok) const { return Rec{kept[ok ? i : 0]}; }
-    __device__ void deref(Rec&) const {}
-    __device__ unsigned long long value(uint64_t, const Rec& r) const { return r.c; }
-    __device__ unsigned long long operator()(uint64_t i) const {
-        return i < ctr->v_units ? kept[i] : 0ull;
+// One thread: keeps the slots of r whose destination is not in `gone`, in
+// order from slot 0, and returns how many.  In place: a kept slot is written
+// at or below the position being read, so nothing unread is overwritten.
+__device__ uint32_t vd_compact_small(const GraphView& g, const VRec& r, const uint32_t* gone) {
+    const uint32_t nb = nblocks(g, r.deg);
+    uint32_t w = 0;
+    for (uint32_t j = 0; j < nb; ++j) {
+        const uint32_t s0 = j << g.log2B;
+        const uint32_t cnt = min(g.B, r.deg - s0);
+        const uint64_t base = (uint64_t)block_of(g, r, j) << g.log2B;
+        if (g.B >= 4) {
+            for (uint32_t o = 0; o < cnt; o += 4) {
+                const uint4 q = *reinterpret_cast<const uint4*>(g.pool + base + o);
+                const uint32_t xs[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+                for (uint32_t i = 0; i < 4; ++i) {
+                    if (o + i < cnt && !bit_of(gone, xs[i])) {
+                        if (w != s0 + o + i) g.pool[slot_addr(g, r, w)] = xs[i];
+                        ++w;
+                    }
+                }
+            }
+        } else {
+            for (uint32_t o = 0; o < cnt; ++o) {
+                const uint32_t x = g.pool[base + o];
+                if (!bit_of(gone, x)) {
+                    if (w != s0 + o) g.pool[slot_addr(g, r, w)] = x;
+                    ++w;
+                }
+            }
+        }
     }
-};
+    return w;
+}
 
-// Per vertex: blocks it gives up (low half) and slots it loses (high half).
-struct LossIn {
-    GraphView g;
-    const unsigned long long* uoff;
-    const unsigned long long* P;
-    struct Rec {
-        VRec r;
-        unsigned long long f, a, b;
-    };
-    __device__ uint64_t limit(uint64_t n) const { return n; }
-    __device__ Rec load(uint64_t u, bool) const {
-        Rec x;
-        x.r = g.vt[u];
-        x.f = uoff[u];
-        x.a = x.b = 0;
-        return x;
-    }
-    __device__ void deref(Rec& x) const {
-        const unsigned long long nu = (x.r.deg + kVChunk - 1) / kVChunk;
-        x.a = P[x.f];
-        x.b = P[x.f + nu];
-    }
-    __device__ unsigned long long value(uint64_t u, const Rec& x) const {
-        if (!active_bit(g, (uint32_t)u)) return 0ull;
-        const uint32_t nd = (uint32_t)(x.b - x.a);
-        const unsigned long long lost = x.r.deg - nd;
-        return (unsigned long long)(nblocks(g, x.r.deg) - nblocks(g, nd)) | (lost << 32);
-    }
-    __device__ unsigned long long operator()(uint64_t u) const {
-        Rec x = load(u, true);
-        deref(x);
-        return value(u, x);
-    }
-};
-
-// Per vertex that lost slots: emptied blocks to the free list (at the
-// scanned position after the current free count), new degree.  A lane frees
-// up to 4 blocks, the whole wave the blocks of a vertex that frees more.
-__global__ __launch_bounds__(kThreads) void k_vdel_loss(GraphView g,
-                                                        const unsigned long long* uoff,
-                                                        const unsigned long long* P,
-                                                        const unsigned long long* pre) {
+// The sweep: one thread per vertex of the table.
+__global__ __launch_bounds__(kThreads) void k_vd_sweep(GraphView g, VDel d) {
     const uint64_t u = vt_tidx();
     const bool live = u < g.n_cap && active_bit(g, (uint32_t)u);
     VRec r{0u, 0u, kNoDir, 0u};
-    uint32_t nd = 0, nb0 = 0, nb1 = 0;
-    unsigned long long pos = 0;
-    if (live) {
-        r = g.vt[u];
-        const unsigned long long f = uoff[u];
-        nd = (uint32_t)(P[f + (r.deg + kVChunk - 1) / kVChunk] - P[f]);
-        nb0 = nblocks(g, r.deg);
-        nb1 = nblocks(g, nd);
-        pos = g.ctr->free_cnt + (pre[u] & 0xffffffffull);
+    if (live) r = g.vt[u];
+    const bool small = live && r.deg > 0 && r.deg <= kVSmall;
+    uint32_t nd = r.deg;
+    if (small) nd = bit_of(d.gone, (uint32_t)u) ? 0u : vd_compact_small(g, r, d.gone);
+    const bool changed = small && nd != r.deg;
+    if (changed) g.vt[u] = vd_record(g, r, nd);
+    vd_free_lanes(g, r, changed ? nblocks(g, nd) : 0u, changed ? nblocks(g, r.deg) : 0u);
+    vd_count(g, changed ? r.deg - nd : 0u,
+             changed ? nblocks(g, r.deg) - nblocks(g, nd) : 0u);
+    // larger vertices: hubs get an index, every unit a record
+    const uint32_t nu = live && r.deg > kVSmall ? (r.deg + kVUnit - 1) / kVUnit : 0u;
+    const bool hub = nu > 1;
+    const uint64_t hm = ballot(hub);
+    unsigned long long h = 0;
+    if (hm) {
+        const int leader = __ffsll((unsigned long long)hm) - 1;
+        if ((int)lane_id() == leader) h = atomicAdd(&g.ctr->vd_hubs, (unsigned long long)__popcll(hm));
+        h = __shfl(h, leader, 64) + rank_below(hm);
     }
-    const bool changed = live && nd != r.deg;
-    const uint32_t nfree = nb0 - nb1;
-    if (changed && nfree <= 4)
-        for (uint32_t j = 0; j < nfree; ++j) g.free_stack[pos + j] = block_of(g, r, nb1 + j);
-    uint64_t m = ballot(changed && nfree > 4);
-    while (m) {
-        const int l = __ffsll((unsigned long long)m) - 1;
-        m &= m - 1;
-        VRec w;
-        w.deg = __shfl(r.deg, l, 64);
-        w.dir = __shfl(r.dir, l, 64);
-        w.dcls = __shfl(r.dcls, l, 64);
-        w.aux = 0;
-        const uint32_t wb1 = __shfl(nb1, l, 64), wn = __shfl(nfree, l, 64);
-        const unsigned long long wp = __shfl(pos, l, 64);
-        for (uint32_t j = lane_id(); j < wn; j += 64) g.free_stack[wp + j] = block_of(g, w, wb1 + j);
+    const bool hub_ok = hub && h < d.hcap;
+    if (hub && !hub_ok) vd_error(g);
+    if (hub_ok) {
+        d.hv[h] = (uint32_t)u;
+        d.hlost[h] = 0u;
+        d.hholes[h] = 0u;
+        d.hsurv[h] = 0u;
     }
-    if (changed) {
-        VRec nr = r;
-        nr.deg = nd;
-        if (nb1 == 0 && nr.dcls == kNoDir) nr.dir = 0;
-        g.vt[u] = nr;
+    const uint32_t mine = hub && !hub_ok ? 0u : nu;
+    const uint32_t inc = wave_incl_scan(mine);
+    const uint32_t tot = __shfl(inc, 63, 64);
+    if (!tot) return;
+    unsigned long long base = 0;
+    if (lane_id() == 63) base = atomicAdd(&g.ctr->vd_units, (unsigned long long)tot);
+    base = __shfl(base, 63, 64) + (inc - mine);
+    for (uint32_t k = 0; k < mine; ++k) {
+        if (base + k >= d.ucap) {
+            vd_error(g);
+            break;
+        }
+        d.units[base + k] = hub ? make_uint2((uint32_t)h, k) : make_uint2((uint32_t)u, kVSingle);
     }
 }
 
-__global__ void k_vdel_tail(DevCounters* c) {
-    const unsigned long long fr = c->v_fr;
-    c->free_cnt += fr & 0xffffffffull;
-    c->c_freed_blocks += fr & 0xffffffffull;
-    c->live_edges -= fr >> 32;
-}
-
-// offsets out of a scan, in both sink forms
-struct U64Out {
-    unsigned long long* a;
-    __device__ void operator()(uint64_t i, unsigned long long v) const { a[i] = v; }
-    template <typename R>
-    __device__ void operator()(uint64_t i, const R&, uint64_t, unsigned long long v) const {
-        a[i] = v;
-    }
+// The slots of one unit in a wave's registers: lane l holds positions
+// p0 + 64 j + l, j < kVPer; keep = the slot exists and stays.
+struct VUnitSlots {
+    uint32_t x[kVPer];
+    bool valid[kVPer], keep[kVPer];
 };
+
+__device__ __forceinline__ void vd_load_unit(const GraphView& g, const VRec& r, uint32_t p0,
+                                             bool src_gone, const uint32_t* gone, VUnitSlots& s) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (uint32_t j = 0; j < kVPer; ++j) {
+        const uint32_t p = p0 + 64 * j + lane;
+        s.valid[j] = p < r.deg;
+        s.x[j] = s.valid[j] ? g.pool[slot_addr(g, r, p)] : 0u;
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < kVPer; ++j)
+        s.keep[j] = s.valid[j] && !src_gone && !bit_of(gone, s.x[j]);
+}
+
+// Units, one wave each.  Pass 0: a single-unit vertex is compacted and
+// finished; a hub's unit counts its lost slots.  Pass 1 (after the hubs'
+// reservations): a hub's unit lists its holes below the new degree and its
+// kept slots at or past it.
+template <int PASS>
+__global__ __launch_bounds__(kThreads) void k_vd_units(GraphView g, VDel d) {
+    const uint32_t lane = lane_id();
+    const uint64_t nw = (uint64_t)gridDim.x * kWaves;
+    const uint64_t nunits = min(g.ctr->vd_units, d.ucap);
+    for (uint64_t k = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); k < nunits; k += nw) {
+        const uint2 U = d.units[k];
+        const bool single = U.y == kVSingle;
+        if (PASS == 1 && single) continue;
+        const uint32_t v = single ? U.x : d.hv[U.x];
+        const VRec r = g.vt[v];
+        const uint32_t p0 = single ? 0u : U.y * kVUnit;
+        uint32_t nd = 0;
+        if (PASS == 1) {
+            nd = d.hnd[U.x];
+            // nothing to list: the hub keeps every slot or none, or this unit
+            // lies below the new degree and has no holes
+            if (d.hlost[U.x] == 0 || nd == 0 || (p0 + kVUnit <= nd && d.ulost[k] == 0)) continue;
+        }
+        VUnitSlots s;
+        vd_load_unit(g, r, p0, bit_of(d.gone, v), d.gone, s);
+        if (PASS == 0 && !single) {
+            uint32_t lost = 0;
+#pragma unroll
+            for (uint32_t j = 0; j < kVPer; ++j) lost += s.valid[j] && !s.keep[j];
+            lost = wave_sum(lost);
+            if (lane == 0) {
+                d.ulost[k] = lost;
+                if (lost) atomicAdd(&d.hlost[U.x], lost);
+            }
+            continue;
+        }
+        if (PASS == 1) {
+            const uint32_t h = U.x;
+            const uint32_t cap = min(d.hlost[h], nd);
+            const unsigned long long off = d.hoff[h];
+#pragma unroll
+            for (uint32_t j = 0; j < kVPer; ++j) {
+                const uint32_t p = p0 + 64 * j + lane;
+                const bool hole = s.valid[j] && !s.keep[j] && p < nd;
+                const bool sv = s.keep[j] && p >= nd;
+                const uint64_t mh = ballot(hole), ms = ballot(sv);
+                uint32_t bh = 0, bs = 0;
+                if (lane == 0) {
+                    if (mh) bh = atomicAdd(&d.hholes[h], (uint32_t)__popcll(mh));
+                    if (ms) bs = atomicAdd(&d.hsurv[h], (uint32_t)__popcll(ms));
+                }
+                bh = __shfl(bh, 0, 64) + rank_below(mh);
+                bs = __shfl(bs, 0, 64) + rank_below(ms);
+                if ((hole && bh >= cap) || (sv && bs >= cap)) {
+                    vd_error(g);
+                } else {
+                    if (hole) d.holes[off + bh] = p;
+                    if (sv) d.surv[off + bs] = s.x[j];
+                }
+            }
+            continue;
+        }
+        // a single-unit vertex: stable compaction of the kept slots
+        uint32_t base = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < kVPer; ++j) {
+            const uint64_t m = ballot(s.keep[j]);
+            const uint32_t q = base + rank_below(m);
+            const uint32_t p = 64 * j + lane;
+            if (s.keep[j] && q != p) g.pool[slot_addr(g, r, q)] = s.x[j];
+            base += popc64(m);
+        }
+        if (base == r.deg) continue;
+        vd_free_wave(g, r, nblocks(g, base), nblocks(g, r.deg));
+        if (lane == 0) {
+            g.vt[v] = vd_record(g, r, base);
+            atomicAdd(&g.ctr->live_edges, 0ull - (unsigned long long)(r.deg - base));
+            atomicAdd(&g.ctr->c_freed_blocks,
+                      (unsigned long long)(nblocks(g, r.deg) - nblocks(g, base)));
+        }
+    }
+}
+
+// One thread per hub: new degree, room for min(lost, new degree) moves.
+__global__ __launch_bounds__(kThreads) void k_vd_reserve(GraphView g, VDel d) {
+    const uint64_t h = vt_tidx();
+    if (h >= min(g.ctr->vd_hubs, d.hcap)) return;
+    const uint32_t deg = g.vt[d.hv[h]].deg;
+    const uint32_t lost = min(d.hlost[h], deg);
+    const uint32_t nd = deg - lost;
+    d.hnd[h] = nd;
+    const uint32_t cap = min(lost, nd);
+    const unsigned long long off = atomicAdd(&g.ctr->vd_pairs, (unsigned long long)cap);
+    if (off + cap > d.pcap) {
+        vd_error(g);
+        d.hlost[h] = 0u;  // lists nothing and stays as it is
+        d.hnd[h] = deg;
+        d.hoff[h] = 0ull;
+        return;
+    }
+    d.hoff[h] = off;
+}
+
+// One wave per hub: fill the holes, free the emptied blocks, new degree.
+__global__ __launch_bounds__(kThreads) void k_vd_fill(GraphView g, VDel d) {
+    const uint32_t lane = lane_id();
+    const uint64_t nw = (uint64_t)gridDim.x * kWaves;
+    const uint64_t nh = min(g.ctr->vd_hubs, d.hcap);
+    for (uint64_t h = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); h < nh; h += nw) {
+        const uint32_t v = d.hv[h];
+        const VRec r = g.vt[v];
+        const uint32_t nd = d.hnd[h];
+        if (nd == r.deg) continue;
+        const uint32_t n = d.hholes[h];
+        if (n != d.hsurv[h] || n > min(r.deg - nd, nd)) {
+            if (lane == 0) vd_error(g);
+            continue;
+        }
+        const unsigned long long off = d.hoff[h];
+        for (uint32_t i = lane; i < n; i += 64)
+            g.pool[slot_addr(g, r, d.holes[off + i])] = d.surv[off + i];
+        vd_free_wave(g, r, nblocks(g, nd), nblocks(g, r.deg));
+        if (lane == 0) {
+            g.vt[v] = vd_record(g, r, nd);
+            atomicAdd(&g.ctr->live_edges, 0ull - (unsigned long long)(r.deg - nd));
+            atomicAdd(&g.ctr->c_freed_blocks,
+                      (unsigned long long)(nblocks(g, r.deg) - nblocks(g, nd)));
+        }
+    }
+}
 
 __global__ __launch_bounds__(kThreads) void k_vdel_finish(GraphView g, const uint32_t* keys,
                                                           uint64_t n, const uint32_t* gone) {
@@ -485,49 +556,65 @@ void vertex_insert(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats*
         st->batch_duplicates = n - g->hctr->st_rejected - g->hctr->n_uniq;
     }
 }
-
 void vertex_batch_warm() {
-    resident_grid(k_vdel_pass<kCount>, kThreads);
+    resident_grid(k_vd_units<0>, kThreads);
+    resident_grid(k_vd_units<1>, kThreads);
+    resident_grid(k_vd_fill, kThreads);
 }
 
+namespace {
+
+// Capacities of a vertex delete's lists, from an upper bound on the edges
+// stored (every bound holds for any graph with at most that many edges).
+struct VDelCaps {
+    uint64_t units, hubs, pairs;
+};
+
+VDelCaps vdel_caps(const gv_graph* g, uint64_t edge_bound) {
+    VDelCaps k;
+    // a vertex with units has more than kVSmall slots; a hub more than kVUnit
+    const uint64_t big = std::min<uint64_t>(g->v.n_cap, edge_bound / (kVSmall + 1) + 1);
+    k.units = big + edge_bound / kVUnit + 1;
+    k.hubs = std::min<uint64_t>(g->v.n_cap, edge_bound / (kVUnit + 1) + 1);
+    // sum over hubs of min(lost, kept) <= half their slots
+    k.pairs = edge_bound / 2 + 1;
+    return k;
+}
+
+void vdel_carve(Carver& cv, const VDelCaps& k, VDel& d) {
+    d.units = cv.take<uint2>(k.units);
+    d.ulost = cv.take<uint32_t>(k.units);
+    d.hv = cv.take<uint32_t>(k.hubs);
+    d.hlost = cv.take<uint32_t>(k.hubs);
+    d.hnd = cv.take<uint32_t>(k.hubs);
+    d.hholes = cv.take<uint32_t>(k.hubs);
+    d.hsurv = cv.take<uint32_t>(k.hubs);
+    d.hoff = cv.take<unsigned long long>(k.hubs);
+    d.holes = cv.take<uint32_t>(k.pairs);
+    d.surv = cv.take<uint32_t>(k.pairs);
+    d.ucap = k.units;
+    d.hcap = k.hubs;
+    d.pcap = k.pairs;
+}
+
+}  // namespace
+
 // Buffer sizes a vertex batch of n ids needs: g->scratch (the id sort) and
-// the three graph-owned vertex buffers; edge_bound as in vertex_delete.
+// the graph-owned vertex buffers; edge_bound as in vertex_delete.
 void vertex_batch_bytes(const gv_graph* g, bool del, uint64_t n, uint64_t edge_bound,
                         size_t out[4]) {
     SortScratch ss{};
     Carver ms(nullptr);
     carve_sort<uint32_t>(ms, ss, n);
     out[0] = ms.used;
-    const uint64_t ncap = g->v.n_cap;
-    const uint64_t words = (ncap + 31) / 32;
+    const uint64_t words = (g->v.n_cap + 31) / 32;
     out[1] = (2 * n + (del ? words : 0)) * sizeof(uint32_t);
     out[2] = out[3] = 0;
     if (!del) return;
-    out[2] = (2 * (ncap + 1) + scan2_parts(ncap + 1) + scan_partials_needed(ncap + 1) + 2) *
-             sizeof(unsigned long long);
-    const uint64_t ubound = ncap + edge_bound / kVChunk + 1;
+    VDel d{};
     Carver m(nullptr);
-    m.take<uint2>(ubound);
-    m.take<uint32_t>(ubound);
-    m.take<unsigned long long>(ubound + 1);
-    m.take<unsigned long long>(scan2_parts(ubound + 1) + scan_partials_needed(ubound + 1) + 2);
-    m.take<uint32_t>(std::max<uint64_t>(edge_bound, 1));
-    out[3] = m.used;
-}
-
-// scan over n elements with the two-kernel scan when it fits, else the
-// three-kernel one; `part` holds enough partials for either
-template <typename In, typename Plain, typename Out>
-static void scan_any(Ctx& c, const char* name, In in, Plain plain, Out out, uint64_t n,
-                     unsigned long long* part, unsigned long long* total) {
-    if (scan2_parts(n) <= kScan2MaxTiles)
-        scan2(c, name, in, out, n, part, total);
-    else
-        scan_excl<unsigned long long>(c, plain, out, n, part, total);
-}
-
-static uint64_t scan_words(uint64_t n) {
-    return scan2_parts(n) + scan_partials_needed(n) + 2;
+    vdel_carve(m, vdel_caps(g, edge_bound), d);
+    out[2] = m.used;
 }
 
 // edge_bound: an upper bound on the edges stored when the call runs (0: read
@@ -558,52 +645,21 @@ void vertex_delete(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats*
         }
         edge_bound = g->hctr->live_edges;
     }
-    // per-vertex buffers: unit offsets, loss prefixes, scan partials
-    unsigned long long* uoff = (unsigned long long*)vbuf(
-        g, 1, (2 * (ncap + 1) + scan_words(ncap + 1)) * sizeof(unsigned long long));
-    unsigned long long* lpre = uoff + ncap + 1;
-    unsigned long long* vpart = lpre + ncap + 1;
-    // per-unit buffers: units, kept counts, their scan, staging
-    const uint64_t ubound = ncap + edge_bound / kVChunk + 1;
-    uint2* units = nullptr;
-    uint32_t *kept = nullptr, *stage = nullptr;
-    unsigned long long *P = nullptr, *upart = nullptr;
-    auto carve = [&](Carver& cv) {
-        units = cv.take<uint2>(ubound);
-        kept = cv.take<uint32_t>(ubound);
-        P = cv.take<unsigned long long>(ubound + 1);
-        upart = cv.take<unsigned long long>(scan_words(ubound + 1));
-        stage = cv.take<uint32_t>(std::max<uint64_t>(edge_bound, 1));
-    };
+    VDel d{};
     {
+        const VDelCaps k = vdel_caps(g, edge_bound);
         Carver m0(nullptr);
-        carve(m0);
-        Carver cv(vbuf(g, 2, m0.used));
-        carve(cv);
+        vdel_carve(m0, k, d);
+        Carver cv(vbuf(g, 1, m0.used));
+        vdel_carve(cv, k, d);
     }
-    scan_any(c, "vdel_units", UnitIn{v}, UnitCount{v}, U64Out{uoff}, ncap, vpart,
-             &v.ctr->v_units);
-    c.launch("vdel_units", k_vdel_units, div_up(ncap, kThreads), kThreads, v,
-             (const unsigned long long*)uoff, units);
-    const uint64_t vgrid = std::min<uint64_t>(div_up(ubound * kVGroup, kThreads),
-                                              resident_grid(k_vdel_pass<kCount>, kThreads));
-    c.launch("vdel_count", k_vdel_pass<kCount>, vgrid, kThreads, v, (const uint32_t*)gone,
-             (const uint2*)units, (const unsigned long long*)uoff, kept,
-             (const unsigned long long*)nullptr, (uint32_t*)nullptr);
-    scan_any(c, "vdel_place", KeptIn{kept, v.ctr}, KeptIn{kept, v.ctr}, U64Out{P}, ubound + 1,
-             upart, &v.ctr->v_kept);
-    c.launch("vdel_gather", k_vdel_pass<kGather>, vgrid, kThreads, v, (const uint32_t*)gone,
-             (const uint2*)units, (const unsigned long long*)uoff, kept,
-             (const unsigned long long*)P, stage);
-    c.launch("vdel_scatter", k_vdel_pass<kScatter>, vgrid, kThreads, v, (const uint32_t*)gone,
-             (const uint2*)units, (const unsigned long long*)uoff, kept,
-             (const unsigned long long*)P, stage);
-    scan_any(c, "vdel_loss", LossIn{v, uoff, P}, LossIn{v, uoff, P}, U64Out{lpre}, ncap, vpart,
-             &v.ctr->v_fr);
-    c.launch("vdel_loss", k_vdel_loss, div_up(ncap, kThreads), kThreads, v,
-             (const unsigned long long*)uoff, (const unsigned long long*)P,
-             (const unsigned long long*)lpre);
-    c.launch("vdel_tail", k_vdel_tail, 1, 1, v.ctr);
+    d.gone = gone;
+    c.launch("vdel_sweep", k_vd_sweep, div_up(ncap, kThreads), kThreads, v, d);
+    const uint64_t ugrid = resident_grid(k_vd_units<0>, kThreads);
+    c.launch("vdel_units", k_vd_units<0>, ugrid, kThreads, v, d);
+    c.launch("vdel_reserve", k_vd_reserve, div_up(d.hcap, kThreads), kThreads, v, d);
+    c.launch("vdel_collect", k_vd_units<1>, ugrid, kThreads, v, d);
+    c.launch("vdel_fill", k_vd_fill, resident_grid(k_vd_fill, kThreads), kThreads, v, d);
     c.launch("vdel_finish", k_vdel_finish, div_up(n, kThreads), kThreads, g->v,
              (const uint32_t*)sorted, n, (const uint32_t*)gone);
     if (st) {
