@@ -176,6 +176,22 @@ int gv_delete_vertices(gv_graph* g, const uint32_t* d_ids, uint64_t n,
 int gv_apply_edge_ops(gv_graph* g, const uint8_t* d_op, const uint32_t* d_src,
                       const uint32_t* d_dst, uint64_t n);
 
+/* gv_apply_edge_ops with per-request statistics: the entries are cut into
+ * n_req requests, request r being entries [d_req_end[r-1], d_req_end[r])
+ * (d_req_end: device array, ascending, last == n; bad ends give meaningless
+ * counts but no bad access).  d_stats (device, n_req entries) receives each
+ * request's statistics as if the requests were applied alone, one after the
+ * other: rejected = entries with an invalid endpoint or op; batch_duplicates
+ * = entries whose previous entry of the same pair is in the same request
+ * with the same op; applied = the other entries that change the graph (an
+ * insert of a pair absent just before it, a delete of a pair present).  The
+ * graph ends as with gv_apply_edge_ops.  Asynchronous; d_stats is valid once
+ * gv_sync returns GV_OK.  GV_EINVAL for n_req == 0 with n > 0, or null
+ * arrays. */
+int gv_apply_edge_ops_stats(gv_graph* g, const uint8_t* d_op, const uint32_t* d_src,
+                            const uint32_t* d_dst, uint64_t n, const uint64_t* d_req_end,
+                            uint64_t n_req, gv_batch_stats* d_stats);
+
 /* Edge query (Sec. 4.6, Alg. 3), batched: d_out[i] = 1 if edge
  * (d_src[i], d_dst[i]) exists, else 0, in input order.  Asynchronous. */
 int gv_edge_exists(gv_graph* g, const uint32_t* d_src, const uint32_t* d_dst,
@@ -218,7 +234,9 @@ int gv_dump_canonical(gv_graph* g, uint64_t* d_offsets, uint32_t* d_dst,
  * (every block id below the bump pointer is owned by exactly one adjacency or
  * sits on the free list exactly once; every vertex of degree d holds
  * ceil(d / B) blocks; no slot below a degree holds 0xFFFFFFFF or an inactive
- * id; inactive vertices have degree 0).  *violations = 0 means consistent.
+ * id; inactive vertices have degree 0; the owner record of every held block
+ * names its vertex and index; the vertex-delete scratch is clear).
+ * *violations = 0 means consistent.
  * Synchronous. */
 int gv_audit(gv_graph* g, uint64_t* violations);
 

@@ -51,8 +51,8 @@ void free_graph(gv_graph* g) {
     g->scratch.release();
     for (auto& v : g->vscr) v.release();
     g->cscr.release();
-    void* mem[] = {g->mem_pool, g->mem_free, g->mem_dir, g->mem_dfree,
-                   g->mem_vt,   g->mem_active, g->mem_ctr};
+    void* mem[] = {g->mem_pool, g->mem_free,   g->mem_dir, g->mem_dfree, g->mem_vt,
+                   g->mem_active, g->mem_ctr, g->mem_bown, g->mem_vlost};
     for (void* p : mem)
         if (p) hipFree(p);
     if (g->hctr) hipHostFree(g->hctr);
@@ -121,6 +121,9 @@ int gv_graph_init(gv_graph** out, uint64_t num_vertices, const uint32_t* d_src,
         hip_check(hipMalloc(&g->mem_vt, cap * sizeof(VRec)), "hipMalloc vertex table");
         hip_check(hipMalloc(&g->mem_active, ((cap + 31) / 32) * 4), "hipMalloc active");
         hip_check(hipMalloc(&g->mem_ctr, sizeof(DevCounters)), "hipMalloc counters");
+        hip_check(hipMalloc(&g->mem_vlost, cap * sizeof(uint32_t)), "hipMalloc vertex scratch");
+        hip_check(hipMemsetAsync(g->mem_vlost, 0, cap * sizeof(uint32_t), g->ctx.stream),
+                  "hipMemsetAsync");
         hip_check(hipHostMalloc((void**)&g->hctr, sizeof(DevCounters), hipHostMallocDefault),
                   "hipHostMalloc");
         hip_check(hipMemsetAsync(g->mem_ctr, 0, sizeof(DevCounters), g->ctx.stream),
@@ -128,6 +131,7 @@ int gv_graph_init(gv_graph** out, uint64_t num_vertices, const uint32_t* d_src,
         v.vt = (VRec*)g->mem_vt;
         v.active = (uint32_t*)g->mem_active;
         v.ctr = (DevCounters*)g->mem_ctr;
+        v.vlost = (uint32_t*)g->mem_vlost;
         noalloc_setup();
         bulk_build(g, num_vertices, d_src, d_dst, num_edges, c);
     } catch (const Error& e) {
@@ -230,6 +234,16 @@ int gv_apply_edge_ops(gv_graph* g, const uint8_t* d_op, const uint32_t* d_src,
     return guarded(g, [&] { mixed_edges(g, d_op, d_src, d_dst, n); });
 }
 
+int gv_apply_edge_ops_stats(gv_graph* g, const uint8_t* d_op, const uint32_t* d_src,
+                            const uint32_t* d_dst, uint64_t n, const uint64_t* d_req_end,
+                            uint64_t n_req, gv_batch_stats* d_stats) {
+    if (!g) return GV_EINVAL;
+    if (n && (!d_op || !d_src || !d_dst)) return GV_EINVAL;
+    if (n_req == 0) return n == 0 ? GV_OK : GV_EINVAL;
+    if (!d_req_end || !d_stats || n_req >= 0xffffffffull) return GV_EINVAL;
+    return guarded(g, [&] { mixed_edges(g, d_op, d_src, d_dst, n, d_req_end, n_req, d_stats); });
+}
+
 int gv_get_adjacency(gv_graph* g, uint32_t v, uint32_t* d_out, uint64_t out_capacity,
                      uint64_t* degree) {
     if (!g || !degree) return GV_EINVAL;
@@ -261,8 +275,8 @@ int gv_memory_used(gv_graph* g, gv_mem* out) {
         m.live_bytes = m.blocks_in_use * m.block_bytes + m.vertex_table_bytes + 4ull * c.dir_live;
         m.num_edges = c.live_edges;
         m.reserved_bytes = v.cap_blocks * m.block_bytes + 4ull * v.cap_blocks +
-                           m.directory_bytes + m.vertex_table_bytes + sizeof(DevCounters) +
-                           g->scratch.cap;
+                           8ull * v.cap_blocks + 4ull * v.n_cap + m.directory_bytes +
+                           m.vertex_table_bytes + sizeof(DevCounters) + g->scratch.cap;
         *out = m;
     });
 }

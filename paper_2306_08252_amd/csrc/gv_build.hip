@@ -145,6 +145,7 @@ __global__ __launch_bounds__(kThreads) void k_init_layout(GraphView g,
         r.dcls = ceil_log2(nb);
         for (uint32_t j = 0; j < nb; ++j) g.dir[(uint64_t)doff + j] = boff + j;
     }
+    for (uint32_t j = 0; j < nb; ++j) g.bown[(uint64_t)boff + j] = make_uint2((uint32_t)v, j);
     g.vt[v] = r;
 }
 
@@ -275,6 +276,8 @@ void bulk_build(gv_graph* g, uint64_t n, const uint32_t* src, const uint32_t* ds
               "hipMalloc pool");
     hip_check(hipMalloc(&g->mem_free, std::max<uint64_t>(cap_blocks * 4ull, 4)),
               "hipMalloc free list");
+    hip_check(hipMalloc(&g->mem_bown, std::max<uint64_t>(cap_blocks * 8ull, 8)),
+              "hipMalloc block owners");
     hip_check(hipMalloc(&g->mem_dir, std::max<uint64_t>(dir_cap * 4ull, 4)), "hipMalloc dir");
     uint64_t dfree_total = 0;
     for (int k = 0; k < kMaxClass; ++k) {
@@ -285,6 +288,7 @@ void bulk_build(gv_graph* g, uint64_t n, const uint32_t* src, const uint32_t* ds
               "hipMalloc dir free");
     v.pool = (uint32_t*)g->mem_pool;
     v.free_stack = (uint32_t*)g->mem_free;
+    v.bown = (uint2*)g->mem_bown;
     v.dir = (uint32_t*)g->mem_dir;
     v.dfree = (uint32_t*)g->mem_dfree;
     v.cap_blocks = cap_blocks;
@@ -455,6 +459,7 @@ __global__ __launch_bounds__(kThreads) void k_audit_vertices(GraphView g, uint32
     for (uint64_t u = gwave(); u < g.n_cap; u += nw) {
         const VRec r = g.vt[u];
         const bool act = is_active(g, u);
+        if (lane == 0 && g.vlost[u] != 0u) bad++;  // vertex-delete scratch left set
         if (!act) {
             if (lane == 0 && (r.deg != 0 || r.dcls != kNoDir)) bad++;
             continue;
@@ -472,8 +477,13 @@ __global__ __launch_bounds__(kThreads) void k_audit_vertices(GraphView g, uint32
         }
         for (uint32_t j = lane; j < nb; j += 64) {
             const uint32_t id = block_of(g, r, j);
-            if (id >= bump) bad++;
-            else atomicAdd(&seen[id], 1u);
+            if (id >= bump) {
+                bad++;
+            } else {
+                atomicAdd(&seen[id], 1u);
+                const uint2 ow = g.bown[id];  // the owner record names this vertex and index
+                if (ow.x != (uint32_t)u || ow.y != j) bad++;
+            }
         }
         for (uint32_t s = lane; s < r.deg; s += 64) {
             const uint32_t id = block_of(g, r, s >> g.log2B);

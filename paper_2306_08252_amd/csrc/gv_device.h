@@ -11,6 +11,10 @@
 //   dfree       per-class free-segment stacks (class c region holds at most
 //               dir_cap >> c segment offsets).
 //   ctr         DevCounters: pool/directory heads, per-batch sizes, errors.
+//   bown        cap_blocks (vertex, index) pairs: the owner of each block the
+//               pool has handed out, written when the block is assigned (a
+//               freed block keeps its last owner; readers check it).
+//   vlost       n_cap uint32, zero between vertex deletions (their scratch).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -64,8 +68,8 @@ struct DevCounters {
     uint32_t n_heavy;                  // sources left to whole waves this batch
     uint32_t err_order;                // a batch's sorted keys failed their check
     uint32_t sort_n, sort_err;  // count and look-back error word of whole-graph sorts
-    // vertex delete: units listed, hubs listed, hole / survivor entries reserved
-    unsigned long long vd_units, vd_hubs, vd_pairs;
+    // vertex delete: slots hit, vertices touched, hole entries reserved
+    unsigned long long vd_hits, vd_touched, vd_pairs;
     // totals of the single-pass scans of the current batch
     unsigned long long tot[8];
     // statistics of the last batch
@@ -98,6 +102,8 @@ struct GraphView {
     VRec* vt;
     uint32_t* active;
     DevCounters* ctr;
+    uint2* bown;
+    uint32_t* vlost;
     unsigned long long n_cap;
     unsigned long long cap_blocks;
     unsigned long long dir_cap;

@@ -1140,6 +1140,7 @@ __global__ __launch_bounds__(kThreads) void k_grow(GraphView g, const uint32_t* 
                 if (j >= nnew) continue;
                 if (nr.dcls == kNoDir) nr.dir = ids[j];  // the only block, inline
                 else g.dir[(uint64_t)nr.dir + nb0 + j] = ids[j];
+                g.bown[ids[j]] = make_uint2(v, nb0 + j);
             }
         }
         g.vt[v] = nr;
@@ -1166,8 +1167,11 @@ __global__ __launch_bounds__(kThreads) void k_grow(GraphView g, const uint32_t* 
             nr.dcls = cls;
         }
         const uint64_t p0 = t_need[t];
-        for (uint32_t j = nb0 + lane; j < nb1; j += 64)
-            g.dir[(uint64_t)nr.dir + j] = planned_block(g, c, p0 + (j - nb0));
+        for (uint32_t j = nb0 + lane; j < nb1; j += 64) {
+            const uint32_t blk = planned_block(g, c, p0 + (j - nb0));
+            g.dir[(uint64_t)nr.dir + j] = blk;
+            g.bown[blk] = make_uint2(v, j);
+        }
         if (lane == 0) g.vt[v] = nr;
     }
 }
@@ -1593,22 +1597,35 @@ __global__ __launch_bounds__(kThreads) void k_sorted_prep_b(GraphView g, const u
 
 static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t* dst,
                      const uint64_t* sorted, const unsigned long long* sorted_n, uint64_t n,
-                     uint8_t* out, bool sticky, void* fixed, size_t fixed_bytes);
+                     uint8_t* out, bool sticky, void* fixed, size_t fixed_bytes,
+                     uint8_t* mark_out);
+
+// the probe's per-key result of a sorted batch (stored before the batch, for
+// an insert; found, for a delete), out of the batch's scratch
+__global__ __launch_bounds__(kThreads) void k_copy_marks(const uint8_t* mark,
+                                                         const unsigned long long* count,
+                                                         uint64_t n_max, uint8_t* out) {
+    const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < min((uint64_t)*count, n_max)) out[i] = mark[i];
+}
 
 void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t* dst, uint64_t n,
                 uint8_t* out, bool sticky, void* fixed, size_t fixed_bytes) {
-    edge_run(g, mode, src, dst, nullptr, nullptr, n, out, sticky, fixed, fixed_bytes);
+    edge_run(g, mode, src, dst, nullptr, nullptr, n, out, sticky, fixed, fixed_bytes, nullptr);
 }
 
 void edge_batch_sorted(gv_graph* g, EdgeMode mode, const uint64_t* keys,
-                       const unsigned long long* count, uint64_t n_max, bool sticky) {
+                       const unsigned long long* count, uint64_t n_max, bool sticky,
+                       uint8_t* mark_out) {
     if (mode == kQuery) fail(GV_EINVAL, "sorted batches are inserts or deletes");
-    edge_run(g, mode, nullptr, nullptr, keys, count, n_max, nullptr, sticky, nullptr, 0);
+    edge_run(g, mode, nullptr, nullptr, keys, count, n_max, nullptr, sticky, nullptr, 0,
+             mark_out);
 }
 
 static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t* dst,
                      const uint64_t* sorted, const unsigned long long* sorted_n, uint64_t n,
-                     uint8_t* out, bool sticky, void* fixed, size_t fixed_bytes) {
+                     uint8_t* out, bool sticky, void* fixed, size_t fixed_bytes,
+                     uint8_t* mark_out) {
     if (n == 0) return;
     if (n >= 0x3fffffffull) fail(GV_EINVAL, "batch too large");
     Ctx& c = g->ctx;
@@ -1714,6 +1731,9 @@ static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint
                  A.mark, (uint32_t*)nullptr);
         c.launch("answer", k_answer, grid, kThreads, v, vals, (const uint8_t*)A.mark, n, out);
     }
+    if (mark_out && sorted)
+        c.launch("marks", k_copy_marks, grid, kThreads, (const uint8_t*)A.mark, sorted_n, n,
+                 mark_out);
 }
 
 }  // namespace gv

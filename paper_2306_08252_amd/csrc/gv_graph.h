@@ -25,6 +25,8 @@ struct gv_graph {
     void* mem_vt = nullptr;
     void* mem_active = nullptr;
     void* mem_ctr = nullptr;
+    void* mem_bown = nullptr;
+    void* mem_vlost = nullptr;
     bool dead = false;            // set after a device failure
 };
 
@@ -41,11 +43,14 @@ void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t*
                 uint64_t n, uint8_t* out, bool sticky, void* fixed = nullptr,
                 size_t fixed_bytes = 0);
 
-// an insert or delete batch whose keys (src << L) | dst are already sorted
-// and valid: keys[0, *count) with the count on the device (at most n_max);
-// keys must not live in g->scratch, which the batch carves
+// an insert or delete batch whose keys (src << L) | dst are already sorted,
+// distinct and valid: keys[0, *count) with the count on the device (at most
+// n_max); keys must not live in g->scratch, which the batch carves.
+// mark_out (optional, n_max bytes): per key, 1 if the pair was stored when
+// the batch started
 void edge_batch_sorted(gv_graph* g, EdgeMode mode, const uint64_t* keys,
-                       const unsigned long long* count, uint64_t n_max, bool sticky);
+                       const unsigned long long* count, uint64_t n_max, bool sticky,
+                       uint8_t* mark_out = nullptr);
 
 // the per-device address of the fixed scratch of gv_edge_exists_noalloc,
 // looked up once per device (graph creation calls it with the device current)
@@ -62,8 +67,12 @@ namespace gv {
 // a list of (op, src, dst) entries, op 0 insert / 1 delete, applied as if one
 // at a time in list order (last-writer reduction, then one delete batch and
 // one insert batch; no host sync)
+// With req_end (device array of n_req ascending ends, the last == n) and
+// stats (device array of n_req): each request's statistics as if the
+// requests were applied alone, in order.
 void mixed_edges(gv_graph* g, const uint8_t* op, const uint32_t* src, const uint32_t* dst,
-                 uint64_t n);
+                 uint64_t n, const uint64_t* req_end = nullptr, uint64_t n_req = 0,
+                 gv_batch_stats* stats = nullptr);
 
 // occupancy queries made ahead of a recording
 void edge_batch_warm();

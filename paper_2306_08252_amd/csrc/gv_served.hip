@@ -88,6 +88,106 @@ __global__ void k_mixed_counts(const unsigned long long* total, unsigned long lo
     *ins_n = *total >> 32;
 }
 
+// ---- per-request statistics
+// Request r is entries [end[r-1], end[r]).  As if each request were applied
+// alone, in order: an entry is rejected when an endpoint is invalid or the op
+// is neither 0 nor 1; a duplicate when the pair's previous entry is in the
+// same request with the same op; applied when it changes the graph (an
+// insert of a pair absent just before it, a delete of a pair present).
+// Whether a pair is present just before an entry follows from its previous
+// entry in the list (an insert leaves it present, a delete absent), and for
+// its first entry from the graph before the list, which the delete or insert
+// batch that applies the pair's last entry reports per key.
+enum : uint8_t { kFNone = 0, kFApplied = 1, kFDup = 2, kFRej = 3, kFNeedIns = 4, kFNeedDel = 5 };
+constexpr uint32_t kRefIns = 0x80000000u;
+
+__device__ __forceinline__ uint32_t request_of(const uint64_t* end, uint32_t n_req, uint64_t p) {
+    uint32_t lo = 0, hi = n_req;  // first r with end[r] > p
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (end[mid] > p) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+// one thread per sorted entry: its flag, and for a pair's first entry the
+// index of the pair in the kept delete or insert keys
+__global__ __launch_bounds__(kThreads) void k_mixed_flags(
+    GraphView g, const uint64_t* sk, const uint32_t* sp, const uint8_t* op, uint64_t n,
+    const uint64_t* end, uint32_t n_req, const uint64_t* del_keys, const uint64_t* ins_keys,
+    const unsigned long long* cnt, uint8_t* flag, uint32_t* fref) {
+    const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t k = sk[i];
+    const uint32_t p = sp[i];
+    const uint8_t o = op[p];
+    uint8_t f = kFNone;
+    uint32_t ref = 0;
+    if ((k >> (2 * g.L)) != 0) {
+        f = kFRej;
+    } else if (i > 0 && sk[i - 1] == k) {
+        const uint32_t pp = sp[i - 1];
+        const uint8_t po = op[pp];
+        if (po == o && request_of(end, n_req, pp) == request_of(end, n_req, p)) {
+            f = kFDup;
+        } else {
+            const bool present = po == 0;
+            f = (o == 0) != present ? kFApplied : kFNone;
+        }
+    } else {
+        // the pair's last entry decides which kept list holds it
+        const uint32_t hi = lower_bound(sk, (uint32_t)i + 1, (uint32_t)n, k + 1);
+        const bool del = op[sp[hi - 1]] == 1;
+        const uint64_t* list = del ? del_keys : ins_keys;
+        const uint32_t m = (uint32_t)(del ? cnt[1] : cnt[2]);
+        ref = lower_bound(list, 0u, m, k) | (del ? 0u : kRefIns);
+        f = o == 0 ? kFNeedIns : kFNeedDel;
+    }
+    flag[p] = f;
+    fref[p] = ref;
+}
+
+// one workgroup per request (grid-stride): its three counts
+__global__ __launch_bounds__(kThreads) void k_request_stats(const uint64_t* end, uint64_t n_req,
+                                                            uint64_t n,
+                                                            const uint8_t* flag,
+                                                            const uint32_t* fref,
+                                                            const uint8_t* del_found,
+                                                            const uint8_t* ins_had,
+                                                            gv_batch_stats* stats) {
+    __shared__ unsigned long long lds[kWaves];
+    for (uint64_t r = blockIdx.x; r < n_req; r += gridDim.x) {
+        // ends are clamped to the list, so bad ends give bad counts, not bad reads
+        const uint64_t hi = min(end[r], n), lo = r ? min(end[r - 1], hi) : 0ull;
+        unsigned long long a = 0, d = 0, j = 0;
+        for (uint64_t p = lo + threadIdx.x; p < hi; p += kThreads) {
+            const uint8_t f = flag[p];
+            if (f == kFApplied) {
+                ++a;
+            } else if (f == kFDup) {
+                ++d;
+            } else if (f == kFRej) {
+                ++j;
+            } else if (f >= kFNeedIns) {
+                const uint32_t ref = fref[p];
+                const bool present = (ref & kRefIns) ? ins_had[ref & ~kRefIns] != 0
+                                                     : del_found[ref] != 0;
+                a += (f == kFNeedIns) != present;
+            }
+        }
+        a = block_sum(a, lds);
+        d = block_sum(d, lds);
+        j = block_sum(j, lds);
+        if (threadIdx.x == 0) stats[r] = gv_batch_stats{a, j, d};
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_stats_zero(gv_batch_stats* stats, uint64_t n) {
+    const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) stats[i] = gv_batch_stats{0ull, 0ull, 0ull};
+}
+
 }  // namespace
 
 // bytes of g->scratch and of g->vscr[0] a mixed list of n entries needs
@@ -105,18 +205,41 @@ void mixed_bytes(const gv_graph* g, uint64_t n, size_t out[2]) {
 }
 
 void mixed_edges(gv_graph* g, const uint8_t* op, const uint32_t* src, const uint32_t* dst,
-                 uint64_t n) {
-    if (n == 0) return;
-    if (n >= 0x3fffffffull) fail(GV_EINVAL, "batch too large");
+                 uint64_t n, const uint64_t* req_end, uint64_t n_req, gv_batch_stats* stats) {
     Ctx& c = g->ctx;
+    if (n == 0) {
+        if (stats && n_req)
+            c.launch("mixed_stats", k_stats_zero, div_up(n_req, kThreads), kThreads, stats, n_req);
+        return;
+    }
+    if (n >= 0x3fffffffull) fail(GV_EINVAL, "batch too large");
     const GraphView& v = g->v;
     const int bits = 2 * (int)v.L + 1;
-    // the key lists and counts outlive the two inner batches, which carve
-    // g->scratch
-    g->vscr[0].ensure(2 * n * sizeof(uint64_t) + 4 * sizeof(unsigned long long), c.stream);
-    uint64_t* del_keys = (uint64_t*)g->vscr[0].ptr;
-    uint64_t* ins_keys = del_keys + n;
-    unsigned long long* cnt = (unsigned long long*)(ins_keys + n);  // total, deletes, inserts
+    // the key lists, counts and statistics buffers outlive the two inner
+    // batches, which carve g->scratch
+    uint64_t *del_keys, *ins_keys;
+    const uint64_t* end = req_end;
+    unsigned long long* cnt;  // total, deletes, inserts
+    uint32_t* fref = nullptr;
+    uint8_t *flag = nullptr, *del_found = nullptr, *ins_had = nullptr;
+    auto carve_keep = [&](Carver& cv) {
+        del_keys = cv.take<uint64_t>(n);
+        ins_keys = cv.take<uint64_t>(n);
+        cnt = cv.take<unsigned long long>(4);
+        if (stats) {
+            fref = cv.take<uint32_t>(n);
+            flag = cv.take<uint8_t>(n);
+            del_found = cv.take<uint8_t>(n);
+            ins_had = cv.take<uint8_t>(n);
+        }
+    };
+    {
+        Carver m(nullptr);
+        carve_keep(m);
+        g->vscr[0].ensure(m.used, c.stream);
+        Carver cv(g->vscr[0].ptr);
+        carve_keep(cv);
+    }
     uint64_t *k0, *k1;
     uint32_t *p0, *p1, *state;
     unsigned long long* part;
@@ -146,8 +269,16 @@ void mixed_edges(gv_graph* g, const uint8_t* op, const uint32_t* src, const uint
     scan2(c, "mixed_split", in, SplitOut{in, del_keys, ins_keys}, n, part, &cnt[0]);
     c.launch("mixed_split", k_mixed_counts, 1, 1, (const unsigned long long*)&cnt[0], &cnt[1],
              &cnt[2]);
-    edge_batch_sorted(g, kDelete, del_keys, &cnt[1], n, true);
-    edge_batch_sorted(g, kInsert, ins_keys, &cnt[2], n, true);
+    if (stats)  // before the batches reuse the sorted entries' scratch
+        c.launch("mixed_stats", k_mixed_flags, div_up(n, kThreads), kThreads, v, sk, sp, op, n,
+                 end, (uint32_t)n_req, (const uint64_t*)del_keys,
+                 (const uint64_t*)ins_keys, (const unsigned long long*)cnt, flag, fref);
+    edge_batch_sorted(g, kDelete, del_keys, &cnt[1], n, true, del_found);
+    edge_batch_sorted(g, kInsert, ins_keys, &cnt[2], n, true, ins_had);
+    if (stats)
+        c.launch("mixed_stats", k_request_stats, std::min<uint64_t>(n_req, 4096), kThreads,
+                 end, n_req, n, (const uint8_t*)flag, (const uint32_t*)fref,
+                 (const uint8_t*)del_found, (const uint8_t*)ins_had, stats);
 }
 
 }  // namespace gv

@@ -4,12 +4,11 @@
 // the dictionary is replaced by one of the next power-of-two capacity (copy
 // kernel, then the old one is freed); inactive ids are switched on.
 //
-// Delete: the deleted set is marked in a bitmap.  One sweep over the vertex
-// table compacts every small adjacency in place (thread per vertex) and cuts
-// the larger ones into units of 1024 slots; a wave per unit compacts a
-// vertex of one unit, and a vertex of several units fills the holes below
-// its new degree with its kept slots past it (three short kernels over its
-// units and one over such vertices).  Emptied blocks go on the free list,
+// Delete: the deleted set is marked in a bitmap.  One streaming pass over
+// the pool's handed-out blocks finds every slot whose destination is deleted
+// (checked against the block's owner record); each vertex that loses slots
+// fills the holes below its new degree with the kept slots past it, emptied
+// blocks go on the free list, a deleted source gives all its blocks back,
 // and the deleted vertices are switched off with their directory segments
 // returned.  All sizes are bounds known on the host, so the path has no host
 // round trip.
@@ -90,7 +89,7 @@ __global__ void k_vreset(DevCounters* c) {
     c->vany = 0;
     c->edges = 0;
     c->checksum = 0;
-    c->vd_units = c->vd_hubs = c->vd_pairs = 0;
+    c->vd_hits = c->vd_touched = c->vd_pairs = 0;
 }
 
 // sorted ids: count rejected and distinct, activate the inactive ones
@@ -150,39 +149,41 @@ __global__ __launch_bounds__(kThreads) void k_vdel_mark(GraphView g, const uint3
     }
 }
 
-// Vertex delete sweep.  Every active vertex with edges is visited once.
-//   small (deg <= kVSmall): one thread keeps the slots whose destination
-//     stays (none for a deleted source) in order from slot 0, in place, frees
-//     the emptied blocks and writes the new degree, all in the sweep kernel;
-//   larger vertices are cut into units of kVUnit slots, one wave per unit.  A
-//     vertex of one unit is compacted by its wave (stable, in registers).  A
-//     vertex of several units (a hub) takes three steps: its units count the
-//     slots they lose; the hub reserves room for min(lost, new degree) moves;
-//     its units list the holes below the new degree and the kept slots at or
-//     past it (as many as the holes); then the hub's wave fills every hole
-//     with one of those slots (any pairing: an adjacency is a set) and frees
-//     the emptied blocks.
-// Only the vertex table is read in full (once); slots are read once, and a
-// hub's units a second time only where they hold holes or survivors.
-constexpr uint32_t kVSmall = 64;         // slots compacted by one thread
-constexpr uint32_t kVPer = 16;           // slots per lane in a unit
-constexpr uint32_t kVUnit = 64 * kVPer;  // slots per unit
-constexpr uint32_t kVSingle = 0xFFFFFFFFu;
-constexpr uint32_t kVErrBound = 4;       // err_order value: a device-side bound was exceeded
+// Vertex delete.  The slots that lose their destination are found by one
+// flat pass over the pool's handed-out blocks (streaming reads, no walk of
+// any adjacency): a slot whose value is a deleted id is checked against the
+// block's owner record (the owner is live, not deleted, still holds this
+// block at that index, and the slot is below its degree) and becomes a hit
+// (vertex, position); each owner counts its hits.  Then, per vertex with
+// hits (touched), with nd = degree - hits: the hits below nd are holes and
+// the kept slots in [nd, degree) are exactly as many; the k-th kept slot of
+// that tail fills the k-th hole (any pairing: an adjacency is a set), the
+// emptied blocks go on the free list and the degree becomes nd.  A deleted
+// source gives all its blocks back.  Shared counters take one atomic per
+// workgroup or per wave, not per slot.
+//
+// A summary of the deleted set sits in LDS for the pass over the pool: bit
+// b is set when a vertex in [b << sum_shift, (b + 1) << sum_shift) is
+// deleted, so most slots are cleared without touching the bitmap in memory.
+constexpr uint32_t kVSumBits = 1u << 17;
+constexpr uint32_t kVSumWords = kVSumBits / 32;
+constexpr uint32_t kVQuads = 4;        // 4-slot groups per thread per round of the pass
+constexpr uint32_t kVHitBuf = 1024;    // hits staged in LDS per workgroup
+constexpr uint32_t kVLane = 32;        // tails and frees a lane takes; larger ones take the wave
+constexpr uint32_t kVErrBound = 4;     // err_order value: a device-side bound was exceeded
 
 struct VDel {
     const uint32_t* gone;
-    uint2* units;                // {vertex, kVSingle} or {hub, unit index}
-    uint32_t* ulost;             // per unit of a hub: slots lost
-    uint32_t* hv;                // per hub: vertex
-    uint32_t* hlost;             // per hub: slots lost
-    uint32_t* hnd;               // per hub: new degree
-    uint32_t* hholes;            // per hub: holes listed
-    uint32_t* hsurv;             // per hub: survivors listed
-    unsigned long long* hoff;    // per hub: first entry in holes / surv
-    uint32_t* holes;             // slot positions
-    uint32_t* surv;              // destination values
-    unsigned long long ucap, hcap, pcap;
+    uint32_t* summary;           // kVSumWords words
+    uint32_t sum_shift, sum_words;
+    uint2* hits;                 // (vertex, position) of every slot that loses its destination
+    uint32_t* touched;           // vertices with hits
+    uint32_t* tnd;               // per touched vertex: new degree
+    uint32_t* tcap;              // per touched vertex: room for holes
+    uint32_t* tholes;            // per touched vertex: holes listed
+    unsigned long long* toff;    // per touched vertex: first entry in holes
+    uint32_t* holes;             // positions below the new degree whose slot is lost
+    unsigned long long hcap, tcapn, pcap;
 };
 
 __device__ __forceinline__ void vd_error(const GraphView& g) {
@@ -196,275 +197,338 @@ __device__ __forceinline__ VRec vd_record(const GraphView& g, VRec r, uint32_t n
     return r;
 }
 
-// Every lane of the wave calls this: lane-wise edges lost and blocks freed
-// go into the graph's counters with one atomic each per wave.
-__device__ __forceinline__ void vd_count(const GraphView& g, unsigned long long lost,
-                                         unsigned long long freed) {
-    lost = wave_sum(lost);
-    freed = wave_sum(freed);
-    if (lane_id() == 0) {
+// the summary into LDS (every thread calls it; one barrier)
+__device__ __forceinline__ void vd_load_summary(const VDel& d, uint32_t* s_sum) {
+    for (uint32_t i = threadIdx.x; i < d.sum_words; i += kThreads) s_sum[i] = d.summary[i];
+    __syncthreads();
+}
+
+// is destination x deleted: the LDS summary first, the bitmap only when the
+// summary's range holds a deleted id
+__device__ __forceinline__ bool vd_gone(const VDel& d, const uint32_t* s_sum, uint32_t x) {
+    const uint32_t b = x >> d.sum_shift;
+    if (!((s_sum[b >> 5] >> (b & 31)) & 1u)) return false;
+    return bit_of(d.gone, x);
+}
+
+// summary bits of the deleted set (one thread per bitmap word)
+__global__ __launch_bounds__(kThreads) void k_vd_summary(VDel d, uint64_t words) {
+    const uint64_t w = vt_tidx();
+    if (w >= words) return;
+    for (uint32_t m = d.gone[w]; m; m &= m - 1) {
+        const uint64_t b = ((w << 5) + (uint32_t)__ffs(m) - 1) >> d.sum_shift;
+        atomicOr(&d.summary[b >> 5], 1u << (b & 31));
+    }
+}
+
+// exclusive prefix of x over the workgroup and one atomic add of the total
+// to *counter; every thread calls it (barriers inside)
+__device__ __forceinline__ unsigned long long vd_reserve(unsigned long long x,
+                                                        unsigned long long* counter,
+                                                        unsigned long long* lds,
+                                                        unsigned long long* s_base) {
+    unsigned long long tot;
+    const unsigned long long ex = block_excl_scan(x, lds, tot);
+    if (threadIdx.x == 0) *s_base = tot ? atomicAdd(counter, tot) : 0ull;
+    __syncthreads();
+    const unsigned long long b = *s_base;
+    __syncthreads();
+    return b + ex;
+}
+
+// Every thread of the workgroup calls this once, at the end of a kernel:
+// edges lost and blocks freed go into the graph's counters.
+__device__ __forceinline__ void vd_flush(const GraphView& g, unsigned long long lost,
+                                         unsigned long long freed, unsigned long long* lds) {
+    lost = block_sum(lost, lds);
+    freed = block_sum(freed, lds);
+    if (threadIdx.x == 0) {
         if (lost) atomicAdd(&g.ctr->live_edges, 0ull - lost);
         if (freed) atomicAdd(&g.ctr->c_freed_blocks, freed);
     }
 }
 
-// Every lane of the wave calls this: each lane pushes blocks [b0, b1) of its
-// record r onto the free stack, at slots reserved with one atomic per wave.
-__device__ __forceinline__ void vd_free_lanes(const GraphView& g, const VRec& r, uint32_t b0,
-                                              uint32_t b1) {
-    const uint32_t nf = b1 - b0;
-    const uint32_t inc = wave_incl_scan(nf);
-    const uint32_t tot = __shfl(inc, 63, 64);
-    if (!tot) return;
-    unsigned long long base = 0;
-    if (lane_id() == 63) base = atomicAdd(&g.ctr->free_cnt, (unsigned long long)tot);
-    base = __shfl(base, 63, 64) + (inc - nf);
-    for (uint32_t j = 0; j < nf; ++j) g.free_stack[base + j] = block_of(g, r, b0 + j);
+// a slot whose value is deleted: is it a live slot of a vertex that stays,
+// and at which position
+__device__ __forceinline__ bool vd_hit(const GraphView& g, const VDel& d, uint64_t s,
+                                       uint32_t* v_out, uint32_t* p_out) {
+    const uint64_t blk = s >> g.log2B;
+    const uint2 ow = g.bown[blk];
+    const uint32_t v = ow.x, j = ow.y;
+    if ((uint64_t)v >= g.n_cap || bit_of(d.gone, v) || !active_bit(g, v)) return false;
+    const VRec r = g.vt[v];
+    if (j >= nblocks(g, r.deg) || (uint64_t)block_of(g, r, j) != blk) return false;
+    const uint32_t p = (j << g.log2B) + (uint32_t)(s & (g.B - 1));
+    if (p >= r.deg) return false;
+    *v_out = v;
+    *p_out = p;
+    return true;
 }
 
-// One wave pushes blocks [b0, b1) of r onto the free stack.
-__device__ __forceinline__ void vd_free_wave(const GraphView& g, const VRec& r, uint32_t b0,
-                                             uint32_t b1) {
-    if (b1 <= b0) return;
-    unsigned long long base = 0;
-    if (lane_id() == 0) base = atomicAdd(&g.ctr->free_cnt, (unsigned long long)(b1 - b0));
-    base = __shfl(base, 0, 64);
-    for (uint32_t j = lane_id(); j < b1 - b0; j += 64) g.free_stack[base + j] = block_of(g, r, b0 + j);
-}
-
-// One thread: keeps the slots of r whose destination is not in `gone`, in
-// order from slot 0, and returns how many.  In place: a kept slot is written
-// at or below the position being read, so nothing unread is overwritten.
-__device__ uint32_t vd_compact_small(const GraphView& g, const VRec& r, const uint32_t* gone) {
-    const uint32_t nb = nblocks(g, r.deg);
-    uint32_t w = 0;
-    for (uint32_t j = 0; j < nb; ++j) {
-        const uint32_t s0 = j << g.log2B;
-        const uint32_t cnt = min(g.B, r.deg - s0);
-        const uint64_t base = (uint64_t)block_of(g, r, j) << g.log2B;
-        if (g.B >= 4) {
-            for (uint32_t o = 0; o < cnt; o += 4) {
-                const uint4 q = *reinterpret_cast<const uint4*>(g.pool + base + o);
-                const uint32_t xs[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-                for (uint32_t i = 0; i < 4; ++i) {
-                    if (o + i < cnt && !bit_of(gone, xs[i])) {
-                        if (w != s0 + o + i) g.pool[slot_addr(g, r, w)] = xs[i];
-                        ++w;
-                    }
-                }
-            }
+// The pass over the pool's handed-out blocks [0, bump), grid-stride in rounds
+// of kThreads * kVQuads groups of 4 slots, with no barrier between rounds.
+// Hits, and the vertices whose first hit this is, are staged in LDS and
+// appended with one atomic per workgroup at the end (a full stage spills to
+// direct appends).
+__global__ __launch_bounds__(kThreads) void k_vd_scan(GraphView g, VDel d) {
+    __shared__ uint32_t s_sum[kVSumWords];
+    __shared__ uint2 s_hit[kVHitBuf];
+    __shared__ uint32_t s_tv[kVHitBuf];
+    __shared__ uint32_t s_nh, s_nt;
+    __shared__ unsigned long long s_bh, s_bt;
+    __shared__ unsigned long long lds[kWaves];
+    vd_load_summary(d, s_sum);
+    if (threadIdx.x == 0) s_nh = s_nt = 0u;
+    __syncthreads();
+    const uint64_t slots = (uint64_t)g.ctr->bump << g.log2B;
+    const uint64_t nq = (slots + 3) / 4;
+    constexpr uint64_t kRound = (uint64_t)kThreads * kVQuads;
+    unsigned long long lost = 0;
+    auto add_hit = [&](uint32_t v, uint32_t p) {
+        ++lost;
+        const uint32_t k = atomicAdd(&s_nh, 1u);
+        if (k < kVHitBuf) {
+            s_hit[k] = make_uint2(v, p);
         } else {
-            for (uint32_t o = 0; o < cnt; ++o) {
-                const uint32_t x = g.pool[base + o];
-                if (!bit_of(gone, x)) {
-                    if (w != s0 + o) g.pool[slot_addr(g, r, w)] = x;
-                    ++w;
-                }
+            const unsigned long long i = atomicAdd(&g.ctr->vd_hits, 1ull);
+            if (i < d.hcap) d.hits[i] = make_uint2(v, p);
+            else vd_error(g);
+        }
+        if (atomicAdd(&g.vlost[v], 1u) == 0u) {
+            const uint32_t kt = atomicAdd(&s_nt, 1u);
+            if (kt < kVHitBuf) {
+                s_tv[kt] = v;
+            } else {
+                const unsigned long long i = atomicAdd(&g.ctr->vd_touched, 1ull);
+                if (i < d.tcapn) d.touched[i] = v;
+                else vd_error(g);
+            }
+        }
+    };
+    for (uint64_t q0 = (uint64_t)blockIdx.x * kRound; q0 < nq; q0 += (uint64_t)gridDim.x * kRound) {
+        uint32_t xs[kVQuads][4];
+#pragma unroll
+        for (uint32_t u = 0; u < kVQuads; ++u) {
+            const uint64_t q = q0 + (uint64_t)u * kThreads + threadIdx.x;
+            if (q < nq && g.B >= 4) {
+                const uint4 w = *reinterpret_cast<const uint4*>(g.pool + 4 * q);
+                xs[u][0] = w.x;
+                xs[u][1] = w.y;
+                xs[u][2] = w.z;
+                xs[u][3] = w.w;
+            } else {
+#pragma unroll
+                for (uint32_t i = 0; i < 4; ++i) xs[u][i] = 4 * q + i < slots ? g.pool[4 * q + i] : 0u;
+            }
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kVQuads; ++u) {
+            const uint64_t q = q0 + (uint64_t)u * kThreads + threadIdx.x;
+#pragma unroll
+            for (uint32_t i = 0; i < 4; ++i) {
+                uint32_t v, p;
+                if (4 * q + i < slots && (uint64_t)xs[u][i] < g.n_cap &&
+                    vd_gone(d, s_sum, xs[u][i]) && vd_hit(g, d, 4 * q + i, &v, &p))
+                    add_hit(v, p);
             }
         }
     }
-    return w;
+    // move the staged hits and touched vertices out
+    __syncthreads();
+    const uint32_t nh = min(s_nh, kVHitBuf), nt = min(s_nt, kVHitBuf);
+    if (threadIdx.x == 0) {
+        s_bh = nh ? atomicAdd(&g.ctr->vd_hits, (unsigned long long)nh) : 0ull;
+        s_bt = nt ? atomicAdd(&g.ctr->vd_touched, (unsigned long long)nt) : 0ull;
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nh; i += kThreads) {
+        if (s_bh + i < d.hcap) d.hits[s_bh + i] = s_hit[i];
+        else vd_error(g);
+    }
+    for (uint32_t i = threadIdx.x; i < nt; i += kThreads) {
+        if (s_bt + i < d.tcapn) d.touched[s_bt + i] = s_tv[i];
+        else vd_error(g);
+    }
+    vd_flush(g, lost, 0ull, lds);
 }
 
-// The sweep: one thread per vertex of the table.
-__global__ __launch_bounds__(kThreads) void k_vd_sweep(GraphView g, VDel d) {
-    const uint64_t u = vt_tidx();
-    const bool live = u < g.n_cap && active_bit(g, (uint32_t)u);
+// Deleted sources (sorted ids, one thread each): all their blocks go on the
+// free list (one reservation per workgroup), their edges off the count.
+__global__ __launch_bounds__(kThreads) void k_vd_sources(GraphView g, const uint32_t* keys,
+                                                         uint64_t n, const uint32_t* gone) {
+    __shared__ unsigned long long lds[kWaves];
+    __shared__ unsigned long long s_base;
+    const uint64_t i = vt_tidx();
     VRec r{0u, 0u, kNoDir, 0u};
-    if (live) r = g.vt[u];
-    const bool small = live && r.deg > 0 && r.deg <= kVSmall;
-    uint32_t nd = r.deg;
-    if (small) nd = bit_of(d.gone, (uint32_t)u) ? 0u : vd_compact_small(g, r, d.gone);
-    const bool changed = small && nd != r.deg;
-    if (changed) g.vt[u] = vd_record(g, r, nd);
-    vd_free_lanes(g, r, changed ? nblocks(g, nd) : 0u, changed ? nblocks(g, r.deg) : 0u);
-    vd_count(g, changed ? r.deg - nd : 0u,
-             changed ? nblocks(g, r.deg) - nblocks(g, nd) : 0u);
-    // larger vertices: hubs get an index, every unit a record
-    const uint32_t nu = live && r.deg > kVSmall ? (r.deg + kVUnit - 1) / kVUnit : 0u;
-    const bool hub = nu > 1;
-    const uint64_t hm = ballot(hub);
-    unsigned long long h = 0;
-    if (hm) {
-        const int leader = __ffsll((unsigned long long)hm) - 1;
-        if ((int)lane_id() == leader) h = atomicAdd(&g.ctr->vd_hubs, (unsigned long long)__popcll(hm));
-        h = __shfl(h, leader, 64) + rank_below(hm);
+    bool mine = false;
+    if (i < n) {
+        const uint32_t id = keys[i];
+        mine = (uint64_t)id < g.n_cap && (i == 0 || keys[i - 1] != id) && bit_of(gone, id);
+        if (mine) r = g.vt[id];
     }
-    const bool hub_ok = hub && h < d.hcap;
-    if (hub && !hub_ok) vd_error(g);
-    if (hub_ok) {
-        d.hv[h] = (uint32_t)u;
-        d.hlost[h] = 0u;
-        d.hholes[h] = 0u;
-        d.hsurv[h] = 0u;
+    const uint32_t nb = mine ? nblocks(g, r.deg) : 0u;
+    const unsigned long long pos = vd_reserve(nb, &g.ctr->free_cnt, lds, &s_base);
+    if (nb <= kVLane) {
+        for (uint32_t j = 0; j < nb; ++j) g.free_stack[pos + j] = block_of(g, r, j);
     }
-    const uint32_t mine = hub && !hub_ok ? 0u : nu;
-    const uint32_t inc = wave_incl_scan(mine);
-    const uint32_t tot = __shfl(inc, 63, 64);
-    if (!tot) return;
-    unsigned long long base = 0;
-    if (lane_id() == 63) base = atomicAdd(&g.ctr->vd_units, (unsigned long long)tot);
-    base = __shfl(base, 63, 64) + (inc - mine);
-    for (uint32_t k = 0; k < mine; ++k) {
-        if (base + k >= d.ucap) {
+    uint64_t m = ballot(nb > kVLane);  // larger ones by the whole wave
+    while (m) {
+        const int l = __ffsll((unsigned long long)m) - 1;
+        m &= m - 1;
+        VRec w;
+        w.deg = __shfl(r.deg, l, 64);
+        w.dir = __shfl(r.dir, l, 64);
+        w.dcls = __shfl(r.dcls, l, 64);
+        w.aux = 0;
+        const uint32_t wn = __shfl(nb, l, 64);
+        const unsigned long long wp = __shfl(pos, l, 64);
+        for (uint32_t j = lane_id(); j < wn; j += 64) g.free_stack[wp + j] = block_of(g, w, j);
+    }
+    vd_flush(g, mine ? r.deg : 0u, nb, lds);
+}
+
+// One thread per touched vertex (grid-stride rounds): new degree, room for
+// min(hits, new degree) holes (one reservation per workgroup round), and the
+// vertex's scratch word becomes its index in the touched list.
+__global__ __launch_bounds__(kThreads) void k_vd_plan(GraphView g, VDel d) {
+    __shared__ unsigned long long lds[kWaves];
+    __shared__ unsigned long long s_base;
+    const uint64_t nt = min(g.ctr->vd_touched, d.tcapn);
+    for (uint64_t t0 = (uint64_t)blockIdx.x * kThreads; t0 < nt; t0 += (uint64_t)gridDim.x * kThreads) {
+        const uint64_t t = t0 + threadIdx.x;
+        uint32_t v = 0, deg = 0, lost = 0, cap = 0;
+        if (t < nt) {
+            v = d.touched[t];
+            deg = g.vt[v].deg;
+            lost = min(g.vlost[v], deg);
+            cap = min(lost, deg - lost);
+        }
+        const unsigned long long off = vd_reserve(cap, &g.ctr->vd_pairs, lds, &s_base);
+        if (t < nt) {
+            if (off + cap > d.pcap) {
+                vd_error(g);
+                d.tnd[t] = deg;  // left as it is
+                d.tcap[t] = 0u;
+            } else {
+                d.tnd[t] = deg - lost;
+                d.tcap[t] = cap;
+            }
+            d.toff[t] = off;
+            d.tholes[t] = 0u;
+            g.vlost[v] = (uint32_t)t;
+        }
+    }
+}
+
+// One thread per hit (grid-stride): a hit below its vertex's new degree is a
+// hole.
+__global__ __launch_bounds__(kThreads) void k_vd_holes(GraphView g, VDel d) {
+    const uint64_t nh = min(g.ctr->vd_hits, d.hcap);
+    const uint64_t nt = min(g.ctr->vd_touched, d.tcapn);
+    for (uint64_t i = vt_tidx(); i < nh; i += (uint64_t)gridDim.x * kThreads) {
+        const uint2 h = d.hits[i];
+        const uint32_t t = g.vlost[h.x];
+        if (t >= nt) {
             vd_error(g);
-            break;
-        }
-        d.units[base + k] = hub ? make_uint2((uint32_t)h, k) : make_uint2((uint32_t)u, kVSingle);
-    }
-}
-
-// The slots of one unit in a wave's registers: lane l holds positions
-// p0 + 64 j + l, j < kVPer; keep = the slot exists and stays.
-struct VUnitSlots {
-    uint32_t x[kVPer];
-    bool valid[kVPer], keep[kVPer];
-};
-
-__device__ __forceinline__ void vd_load_unit(const GraphView& g, const VRec& r, uint32_t p0,
-                                             bool src_gone, const uint32_t* gone, VUnitSlots& s) {
-    const uint32_t lane = lane_id();
-#pragma unroll
-    for (uint32_t j = 0; j < kVPer; ++j) {
-        const uint32_t p = p0 + 64 * j + lane;
-        s.valid[j] = p < r.deg;
-        s.x[j] = s.valid[j] ? g.pool[slot_addr(g, r, p)] : 0u;
-    }
-#pragma unroll
-    for (uint32_t j = 0; j < kVPer; ++j)
-        s.keep[j] = s.valid[j] && !src_gone && !bit_of(gone, s.x[j]);
-}
-
-// Units, one wave each.  Pass 0: a single-unit vertex is compacted and
-// finished; a hub's unit counts its lost slots.  Pass 1 (after the hubs'
-// reservations): a hub's unit lists its holes below the new degree and its
-// kept slots at or past it.
-template <int PASS>
-__global__ __launch_bounds__(kThreads) void k_vd_units(GraphView g, VDel d) {
-    const uint32_t lane = lane_id();
-    const uint64_t nw = (uint64_t)gridDim.x * kWaves;
-    const uint64_t nunits = min(g.ctr->vd_units, d.ucap);
-    for (uint64_t k = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); k < nunits; k += nw) {
-        const uint2 U = d.units[k];
-        const bool single = U.y == kVSingle;
-        if (PASS == 1 && single) continue;
-        const uint32_t v = single ? U.x : d.hv[U.x];
-        const VRec r = g.vt[v];
-        const uint32_t p0 = single ? 0u : U.y * kVUnit;
-        uint32_t nd = 0;
-        if (PASS == 1) {
-            nd = d.hnd[U.x];
-            // nothing to list: the hub keeps every slot or none, or this unit
-            // lies below the new degree and has no holes
-            if (d.hlost[U.x] == 0 || nd == 0 || (p0 + kVUnit <= nd && d.ulost[k] == 0)) continue;
-        }
-        VUnitSlots s;
-        vd_load_unit(g, r, p0, bit_of(d.gone, v), d.gone, s);
-        if (PASS == 0 && !single) {
-            uint32_t lost = 0;
-#pragma unroll
-            for (uint32_t j = 0; j < kVPer; ++j) lost += s.valid[j] && !s.keep[j];
-            lost = wave_sum(lost);
-            if (lane == 0) {
-                d.ulost[k] = lost;
-                if (lost) atomicAdd(&d.hlost[U.x], lost);
-            }
             continue;
         }
-        if (PASS == 1) {
-            const uint32_t h = U.x;
-            const uint32_t cap = min(d.hlost[h], nd);
-            const unsigned long long off = d.hoff[h];
-#pragma unroll
-            for (uint32_t j = 0; j < kVPer; ++j) {
-                const uint32_t p = p0 + 64 * j + lane;
-                const bool hole = s.valid[j] && !s.keep[j] && p < nd;
-                const bool sv = s.keep[j] && p >= nd;
-                const uint64_t mh = ballot(hole), ms = ballot(sv);
-                uint32_t bh = 0, bs = 0;
-                if (lane == 0) {
-                    if (mh) bh = atomicAdd(&d.hholes[h], (uint32_t)__popcll(mh));
-                    if (ms) bs = atomicAdd(&d.hsurv[h], (uint32_t)__popcll(ms));
-                }
-                bh = __shfl(bh, 0, 64) + rank_below(mh);
-                bs = __shfl(bs, 0, 64) + rank_below(ms);
-                if ((hole && bh >= cap) || (sv && bs >= cap)) {
-                    vd_error(g);
-                } else {
-                    if (hole) d.holes[off + bh] = p;
-                    if (sv) d.surv[off + bs] = s.x[j];
-                }
-            }
-            continue;
-        }
-        // a single-unit vertex: stable compaction of the kept slots
-        uint32_t base = 0;
-#pragma unroll
-        for (uint32_t j = 0; j < kVPer; ++j) {
-            const uint64_t m = ballot(s.keep[j]);
-            const uint32_t q = base + rank_below(m);
-            const uint32_t p = 64 * j + lane;
-            if (s.keep[j] && q != p) g.pool[slot_addr(g, r, q)] = s.x[j];
-            base += popc64(m);
-        }
-        if (base == r.deg) continue;
-        vd_free_wave(g, r, nblocks(g, base), nblocks(g, r.deg));
-        if (lane == 0) {
-            g.vt[v] = vd_record(g, r, base);
-            atomicAdd(&g.ctr->live_edges, 0ull - (unsigned long long)(r.deg - base));
-            atomicAdd(&g.ctr->c_freed_blocks,
-                      (unsigned long long)(nblocks(g, r.deg) - nblocks(g, base)));
-        }
+        if (h.y >= d.tnd[t]) continue;
+        const uint32_t k = atomicAdd(&d.tholes[t], 1u);
+        if (k < d.tcap[t]) d.holes[d.toff[t] + k] = h.y;
+        else vd_error(g);
     }
 }
 
-// One thread per hub: new degree, room for min(lost, new degree) moves.
-__global__ __launch_bounds__(kThreads) void k_vd_reserve(GraphView g, VDel d) {
-    const uint64_t h = vt_tidx();
-    if (h >= min(g.ctr->vd_hubs, d.hcap)) return;
-    const uint32_t deg = g.vt[d.hv[h]].deg;
-    const uint32_t lost = min(d.hlost[h], deg);
-    const uint32_t nd = deg - lost;
-    d.hnd[h] = nd;
-    const uint32_t cap = min(lost, nd);
-    const unsigned long long off = atomicAdd(&g.ctr->vd_pairs, (unsigned long long)cap);
-    if (off + cap > d.pcap) {
-        vd_error(g);
-        d.hlost[h] = 0u;  // lists nothing and stays as it is
-        d.hnd[h] = deg;
-        d.hoff[h] = 0ull;
-        return;
-    }
-    d.hoff[h] = off;
-}
-
-// One wave per hub: fill the holes, free the emptied blocks, new degree.
+// Per touched vertex (a lane each; a vertex whose tail or freed blocks
+// exceed kVLane is taken by the whole wave): the kept slots of the tail
+// [nd, deg) fill the holes in order, emptied blocks go on the free list, the
+// record gets the new degree, the scratch word is cleared.
 __global__ __launch_bounds__(kThreads) void k_vd_fill(GraphView g, VDel d) {
+    __shared__ unsigned long long lds[kWaves];
     const uint32_t lane = lane_id();
-    const uint64_t nw = (uint64_t)gridDim.x * kWaves;
-    const uint64_t nh = min(g.ctr->vd_hubs, d.hcap);
-    for (uint64_t h = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); h < nh; h += nw) {
-        const uint32_t v = d.hv[h];
-        const VRec r = g.vt[v];
-        const uint32_t nd = d.hnd[h];
-        if (nd == r.deg) continue;
-        const uint32_t n = d.hholes[h];
-        if (n != d.hsurv[h] || n > min(r.deg - nd, nd)) {
-            if (lane == 0) vd_error(g);
-            continue;
+    const uint64_t nt = min(g.ctr->vd_touched, d.tcapn);
+    unsigned long long lost_err = 0, freed = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * kThreads;
+    for (uint64_t t0 = (uint64_t)blockIdx.x * kThreads; t0 < nt; t0 += stride) {
+        const uint64_t t = t0 + threadIdx.x;
+        const bool live = t < nt;
+        uint32_t v = 0, nd = 0, nh = 0;
+        unsigned long long off = 0;
+        VRec r{0u, 0u, kNoDir, 0u};
+        if (live) {
+            v = d.touched[t];
+            r = g.vt[v];
+            nd = d.tnd[t];
+            nh = d.tholes[t];
+            off = d.toff[t];
+            if (nh > d.tcap[t]) {  // the holes kernel reported it; list only what was kept
+                nh = d.tcap[t];
+                vd_error(g);
+            }
         }
-        const unsigned long long off = d.hoff[h];
-        for (uint32_t i = lane; i < n; i += 64)
-            g.pool[slot_addr(g, r, d.holes[off + i])] = d.surv[off + i];
-        vd_free_wave(g, r, nblocks(g, nd), nblocks(g, r.deg));
-        if (lane == 0) {
+        const bool change = live && nd < r.deg;
+        const uint32_t b0 = change ? nblocks(g, nd) : 0u, b1 = change ? nblocks(g, r.deg) : 0u;
+        const bool big = change && (r.deg - nd > kVLane || b1 - b0 > kVLane);
+        if (change && !big) {
+            uint32_t k = 0;
+            for (uint32_t p = nd; p < r.deg; ++p) {
+                const uint32_t x = g.pool[slot_addr(g, r, p)];
+                if (bit_of(d.gone, x)) continue;
+                if (k < nh) g.pool[slot_addr(g, r, d.holes[off + k])] = x;
+                ++k;
+            }
+            if (k != nh) vd_error(g);
+        }
+        // frees of the lane-sized vertices: one reservation per wave
+        const uint32_t nf = change && !big ? b1 - b0 : 0u;
+        const uint32_t inc = wave_incl_scan(nf);
+        const uint32_t tot = __shfl(inc, 63, 64);
+        if (tot) {
+            unsigned long long fb = 0;
+            if (lane == 63) fb = atomicAdd(&g.ctr->free_cnt, (unsigned long long)tot);
+            fb = __shfl(fb, 63, 64) + (inc - nf);
+            for (uint32_t j = 0; j < nf; ++j) g.free_stack[fb + j] = block_of(g, r, b0 + j);
+        }
+        // the larger vertices, one at a time by the whole wave
+        uint64_t m = ballot(big);
+        while (m) {
+            const int l = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            VRec w;
+            w.deg = __shfl(r.deg, l, 64);
+            w.dir = __shfl(r.dir, l, 64);
+            w.dcls = __shfl(r.dcls, l, 64);
+            w.aux = 0;
+            const uint32_t wnd = __shfl(nd, l, 64), wnh = __shfl(nh, l, 64);
+            const unsigned long long woff = __shfl(off, l, 64);
+            uint32_t k = 0;
+            for (uint32_t p0 = wnd; p0 < w.deg; p0 += 64) {
+                const uint32_t p = p0 + lane;
+                uint32_t x = 0;
+                bool keep = false;
+                if (p < w.deg) {
+                    x = g.pool[slot_addr(g, w, p)];
+                    keep = !bit_of(d.gone, x);
+                }
+                const uint64_t km = ballot(keep);
+                const uint32_t kk = k + rank_below(km);
+                if (keep && kk < wnh) g.pool[slot_addr(g, w, d.holes[woff + kk])] = x;
+                k += popc64(km);
+            }
+            if (k != wnh && lane == 0) vd_error(g);
+            const uint32_t wb0 = nblocks(g, wnd), wb1 = nblocks(g, w.deg);
+            unsigned long long fb = 0;
+            if (lane == 0 && wb1 > wb0) fb = atomicAdd(&g.ctr->free_cnt, (unsigned long long)(wb1 - wb0));
+            fb = __shfl(fb, 0, 64);
+            for (uint32_t j = lane; j < wb1 - wb0; j += 64) g.free_stack[fb + j] = block_of(g, w, wb0 + j);
+        }
+        if (change) {
             g.vt[v] = vd_record(g, r, nd);
-            atomicAdd(&g.ctr->live_edges, 0ull - (unsigned long long)(r.deg - nd));
-            atomicAdd(&g.ctr->c_freed_blocks,
-                      (unsigned long long)(nblocks(g, r.deg) - nblocks(g, nd)));
+            freed += b1 - b0;
         }
+        if (live) g.vlost[v] = 0u;
     }
+    vd_flush(g, lost_err, freed, lds);
 }
 
 __global__ __launch_bounds__(kThreads) void k_vdel_finish(GraphView g, const uint32_t* keys,
@@ -517,11 +581,22 @@ static void grow_table(gv_graph* g, uint64_t new_cap) {
     }
     c.launch("grow_table", k_grow_table, div_up(new_cap, kThreads), kThreads, (const VRec*)v.vt,
              (const uint32_t*)v.active, (uint64_t)v.n_cap, (VRec*)vt2, (uint32_t*)act2, new_cap);
+    void* vl2 = nullptr;
+    if (hipMalloc(&vl2, new_cap * sizeof(uint32_t)) != hipSuccess) {
+        hip_check(hipStreamSynchronize(c.stream), "hipStreamSynchronize");
+        hipFree(vt2);
+        hipFree(act2);
+        fail(GV_ENOMEM, "hipMalloc vertex scratch");
+    }
+    c.launch("grow_table", k_vzero, div_up(new_cap, kThreads), kThreads, (uint32_t*)vl2, new_cap);
     hip_check(hipStreamSynchronize(c.stream), "hipStreamSynchronize");
     hipFree(g->mem_vt);
     hipFree(g->mem_active);
+    hipFree(g->mem_vlost);
     g->mem_vt = vt2;
     g->mem_active = act2;
+    g->mem_vlost = vl2;
+    v.vlost = (uint32_t*)vl2;
     v.vt = (VRec*)vt2;
     v.active = (uint32_t*)act2;
     v.n_cap = new_cap;
@@ -557,8 +632,9 @@ void vertex_insert(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats*
     }
 }
 void vertex_batch_warm() {
-    resident_grid(k_vd_units<0>, kThreads);
-    resident_grid(k_vd_units<1>, kThreads);
+    resident_grid(k_vd_scan, kThreads);
+    resident_grid(k_vd_plan, kThreads);
+    resident_grid(k_vd_holes, kThreads);
     resident_grid(k_vd_fill, kThreads);
 }
 
@@ -567,33 +643,28 @@ namespace {
 // Capacities of a vertex delete's lists, from an upper bound on the edges
 // stored (every bound holds for any graph with at most that many edges).
 struct VDelCaps {
-    uint64_t units, hubs, pairs;
+    uint64_t hits, touched, pairs;
 };
 
 VDelCaps vdel_caps(const gv_graph* g, uint64_t edge_bound) {
     VDelCaps k;
-    // a vertex with units has more than kVSmall slots; a hub more than kVUnit
-    const uint64_t big = std::min<uint64_t>(g->v.n_cap, edge_bound / (kVSmall + 1) + 1);
-    k.units = big + edge_bound / kVUnit + 1;
-    k.hubs = std::min<uint64_t>(g->v.n_cap, edge_bound / (kVUnit + 1) + 1);
-    // sum over hubs of min(lost, kept) <= half their slots
+    k.hits = edge_bound + 1;  // a hit is a stored slot
+    k.touched = std::min<uint64_t>(g->v.n_cap, edge_bound + 1);
+    // sum over vertices of min(lost, kept) <= half their slots
     k.pairs = edge_bound / 2 + 1;
     return k;
 }
 
 void vdel_carve(Carver& cv, const VDelCaps& k, VDel& d) {
-    d.units = cv.take<uint2>(k.units);
-    d.ulost = cv.take<uint32_t>(k.units);
-    d.hv = cv.take<uint32_t>(k.hubs);
-    d.hlost = cv.take<uint32_t>(k.hubs);
-    d.hnd = cv.take<uint32_t>(k.hubs);
-    d.hholes = cv.take<uint32_t>(k.hubs);
-    d.hsurv = cv.take<uint32_t>(k.hubs);
-    d.hoff = cv.take<unsigned long long>(k.hubs);
+    d.hits = cv.take<uint2>(k.hits);
+    d.toff = cv.take<unsigned long long>(k.touched);
+    d.touched = cv.take<uint32_t>(k.touched);
+    d.tnd = cv.take<uint32_t>(k.touched);
+    d.tcap = cv.take<uint32_t>(k.touched);
+    d.tholes = cv.take<uint32_t>(k.touched);
     d.holes = cv.take<uint32_t>(k.pairs);
-    d.surv = cv.take<uint32_t>(k.pairs);
-    d.ucap = k.units;
-    d.hcap = k.hubs;
+    d.hcap = k.hits;
+    d.tcapn = k.touched;
     d.pcap = k.pairs;
 }
 
@@ -608,7 +679,7 @@ void vertex_batch_bytes(const gv_graph* g, bool del, uint64_t n, uint64_t edge_b
     carve_sort<uint32_t>(ms, ss, n);
     out[0] = ms.used;
     const uint64_t words = (g->v.n_cap + 31) / 32;
-    out[1] = (2 * n + (del ? words : 0)) * sizeof(uint32_t);
+    out[1] = (2 * n + (del ? words + kVSumWords : 0)) * sizeof(uint32_t);
     out[2] = out[3] = 0;
     if (!del) return;
     VDel d{};
@@ -626,10 +697,12 @@ void vertex_delete(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats*
     if (n >= 0xffffffffull) fail(GV_EINVAL, "batch too large");
     const uint64_t ncap = v.n_cap;
     const uint64_t words = (ncap + 31) / 32;
-    uint32_t* k0 = (uint32_t*)vbuf(g, 0, (2 * n + words) * sizeof(uint32_t));
+    uint32_t* k0 = (uint32_t*)vbuf(g, 0, (2 * n + words + kVSumWords) * sizeof(uint32_t));
     uint32_t* gone = k0 + 2 * n;
+    uint32_t* summary = gone + words;
     c.launch("vreset", k_vreset, 1, 1, v.ctr);
-    c.launch("vzero", k_vzero, div_up(words, kThreads), kThreads, gone, words);
+    c.launch("vzero", k_vzero, div_up(words + kVSumWords, kThreads), kThreads, gone,
+             words + kVSumWords);
     uint32_t* sorted = sorted_ids(g, ids, n, k0, k0 + n);
     c.launch("vdel_mark", k_vdel_mark, div_up(n, kThreads), kThreads, v, (const uint32_t*)sorted,
              n, gone);
@@ -654,11 +727,15 @@ void vertex_delete(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats*
         vdel_carve(cv, k, d);
     }
     d.gone = gone;
-    c.launch("vdel_sweep", k_vd_sweep, div_up(ncap, kThreads), kThreads, v, d);
-    const uint64_t ugrid = resident_grid(k_vd_units<0>, kThreads);
-    c.launch("vdel_units", k_vd_units<0>, ugrid, kThreads, v, d);
-    c.launch("vdel_reserve", k_vd_reserve, div_up(d.hcap, kThreads), kThreads, v, d);
-    c.launch("vdel_collect", k_vd_units<1>, ugrid, kThreads, v, d);
+    d.summary = summary;
+    d.sum_shift = v.L > 17 ? v.L - 17 : 0u;
+    d.sum_words = (uint32_t)std::max<uint64_t>(((ncap >> d.sum_shift) + 31) / 32, 1);
+    c.launch("vdel_summary", k_vd_summary, div_up(words, kThreads), kThreads, d, words);
+    c.launch("vdel_scan", k_vd_scan, resident_grid(k_vd_scan, kThreads), kThreads, v, d);
+    c.launch("vdel_sources", k_vd_sources, div_up(n, kThreads), kThreads, v,
+             (const uint32_t*)sorted, n, (const uint32_t*)gone);
+    c.launch("vdel_plan", k_vd_plan, resident_grid(k_vd_plan, kThreads), kThreads, v, d);
+    c.launch("vdel_holes", k_vd_holes, resident_grid(k_vd_holes, kThreads), kThreads, v, d);
     c.launch("vdel_fill", k_vd_fill, resident_grid(k_vd_fill, kThreads), kThreads, v, d);
     c.launch("vdel_finish", k_vdel_finish, div_up(n, kThreads), kThreads, g->v,
              (const uint32_t*)sorted, n, (const uint32_t*)gone);

@@ -104,6 +104,7 @@ def lib():
             "gv_delete_vertices": [vp, u32p, C.c_uint64, C.POINTER(gv_batch_stats)],
             "gv_edge_exists": [vp, u32p, u32p, C.c_uint64, vp],
             "gv_apply_edge_ops": [vp, vp, u32p, u32p, C.c_uint64],
+            "gv_apply_edge_ops_stats": [vp, vp, u32p, u32p, C.c_uint64, vp, C.c_uint64, vp],
             "gv_get_adjacency": [vp, C.c_uint32, u32p, C.c_uint64, u64p],
             "gv_memory_used": [vp, C.POINTER(gv_mem)],
             "gv_dump_canonical": [vp, vp, u32p, C.c_uint64, u64p, u64p],
@@ -276,6 +277,29 @@ def gv_apply_edge_ops(g, op, src, dst, device="cuda:0"):
     return o, s, d
 
 
+def gv_apply_edge_ops_stats(g, op, src, dst, req_end, device="cuda:0", stats=None):
+    """gv_apply_edge_ops with per-request statistics: request r is entries
+    [req_end[r-1], req_end[r]).  req_end: device int64 tensor or a host
+    sequence (copied through pinned memory without a host wait).  Returns
+    (tensors to keep alive until the call completes, stats: device int64
+    (n_req, 3) of applied, rejected, batch duplicates, valid after sync)."""
+    o = as_device_u8(op, device)
+    s = as_device_u32(src, device)
+    d = as_device_u32(dst, device)
+    if not (o.numel() == s.numel() == d.numel()):
+        raise ValueError("op/src/dst length mismatch")
+    if not (torch.is_tensor(req_end) and req_end.is_cuda):
+        req_end = torch.tensor(np.asarray(req_end, np.int64)).pin_memory().to(device,
+                                                                               non_blocking=True)
+    e = req_end.to(torch.int64).contiguous()
+    if stats is None:
+        stats = torch.empty((e.numel(), 3), dtype=torch.int64, device=device)
+    _check(lib().gv_apply_edge_ops_stats(C.c_void_p(g), _ptr(o), _ptr(s), _ptr(d), s.numel(),
+                                         _ptr(e), e.numel(), _ptr(stats)),
+           "gv_apply_edge_ops_stats")
+    return (o, s, d, e), stats
+
+
 def gv_get_adjacency(g, v, device="cuda:0", out=None):
     deg = C.c_uint64()
     if out is None:
@@ -439,6 +463,9 @@ class Graph:
 
     def apply_edge_ops(self, op, src, dst):
         return gv_apply_edge_ops(self.h, op, src, dst, self.device)
+
+    def apply_edge_ops_stats(self, op, src, dst, req_end):
+        return gv_apply_edge_ops_stats(self.h, op, src, dst, req_end, self.device)
 
     def get_adjacency(self, v):
         return gv_get_adjacency(self.h, v, self.device)

@@ -4,9 +4,10 @@ library's kernels).
 
 A tick takes every request that has arrived, in arrival order, up to a pair
 budget.  Its edge inserts and deletes go to the device as one mixed list
-(gv_apply_edge_ops), whose last-writer reduction gives the result of
-applying them one pair at a time in arrival order; then the tick's queries
-are answered (gv_edge_exists).  So the commit order is: a tick's writes in
+(gv_apply_edge_ops_stats), whose last-writer reduction gives the result of
+applying them one pair at a time in arrival order, with each request's
+statistics (applied, rejected, duplicates) as if it ran alone at its place
+in that order; then the tick's queries are answered (gv_edge_exists).  So the commit order is: a tick's writes in
 arrival order, then its queries.  Ticks overlap: a tick is queued as soon as
 it is formed, while earlier ones still run on the device (a few at most),
 and its answers come back by an asynchronous copy; requests that arrive
@@ -60,15 +61,20 @@ def _enqueue_tick(graph, requests, i, j, dev):
     tick's edge inserts and deletes as one mixed list, then its queries as
     one batch whose answers are copied to pinned host memory.  Returns the
     tick record (its tensors stay referenced until it completes)."""
-    ws = [r for r in requests[i:j] if r[0] in (INSERT, DELETE)]
+    ws = [(m, r) for m, r in enumerate(requests[i:j], start=i) if r[0] in (INSERT, DELETE)]
     qs = [(m, r) for m, r in enumerate(requests[i:j], start=i) if r[0] == QUERY]
     keep = []
+    wstats = None
     if ws:
         op = torch.cat([torch.full((_size(r),), r[0], dtype=torch.uint8, device=dev)
-                        for r in ws])
-        src = torch.cat([r[1] for r in ws])
-        dst = torch.cat([r[2] for r in ws])
-        keep += list(gv.gv_apply_edge_ops(graph.h, op, src, dst, dev))
+                        for _, r in ws])
+        src = torch.cat([r[1] for _, r in ws])
+        dst = torch.cat([r[2] for _, r in ws])
+        ends = np.cumsum([_size(r) for _, r in ws])
+        k, st = gv.gv_apply_edge_ops_stats(graph.h, op, src, dst, ends, dev)
+        keep += list(k) + [st]
+        wstats = torch.empty(st.shape, dtype=st.dtype, pin_memory=True)
+        wstats.copy_(st, non_blocking=True)
     host = None
     if qs:
         out = graph.edge_exists(torch.cat([r[1] for _, r in qs]),
@@ -78,11 +84,12 @@ def _enqueue_tick(graph, requests, i, j, dev):
         keep.append(out)
     ev = torch.cuda.Event()
     ev.record(torch.cuda.current_stream(dev))
-    return {"range": (i, j), "event": ev, "queries": qs, "answers": host, "keep": keep}
+    return {"range": (i, j), "event": ev, "queries": qs, "answers": host, "keep": keep,
+            "writes": [m for m, _ in ws], "stats": wstats}
 
 
 def serve(graph, requests, arrivals=None, max_tick_pairs=1 << 20, keep_answers=False,
-          clock=time.perf_counter, rejected=None, max_inflight=3):
+          clock=time.perf_counter, rejected=None, max_inflight=3, stats=None):
     """Runs `requests` [(kind, a, b)] (device id tensors; b is None for vertex
     requests) against `graph` (a graphvine.Graph).  `arrivals[i]` is request
     i's scheduled time in seconds from the start (None: all at time 0).
@@ -94,7 +101,9 @@ def serve(graph, requests, arrivals=None, max_tick_pairs=1 << 20, keep_answers=F
     Returns (completion times, ticks as (first, end) request ranges, answers
     of the query requests by index if keep_answers).  Indices of requests
     rejected by admission are appended to `rejected` (a list) if given; a
-    rejected request is not in any tick."""
+    rejected request is not in any tick.  `stats` (a dict), if given,
+    receives (applied, rejected, duplicates) for every edge insert / delete
+    request, as if the request ran alone at its place in the commit order."""
     n = len(requests)
     arr = np.zeros(n) if arrivals is None else np.asarray(arrivals, np.float64)
     if n and np.any(np.diff(arr) < 0):
@@ -117,6 +126,10 @@ def serve(graph, requests, arrivals=None, max_tick_pairs=1 << 20, keep_answers=F
             t = clock() - t0
             f, e = tk["range"]
             done[f:e] = t
+            if stats is not None and tk["writes"]:
+                st = tk["stats"].numpy()
+                for row, m in enumerate(tk["writes"]):
+                    stats[m] = tuple(int(x) for x in st[row])
             if keep_answers and tk["queries"]:
                 out = tk["answers"].numpy()
                 o = 0

@@ -54,6 +54,48 @@ def test_mixed_lists_match_oracle(n, B, seed):
     g.close()
 
 
+@pytest.mark.parametrize("n,B,seed", [(300, 4, 5), (5000, 16, 6)])
+def test_mixed_request_stats_match_oracle(n, B, seed):
+    """Per-request statistics of one mixed list equal the oracle applying each
+    request alone, in order, with the single-batch calls: pairs recurring
+    within and across requests, stored pairs, inactive and out-of-range ids,
+    an unknown op value, empty requests."""
+    gv = need_gpu()
+    rng = np.random.default_rng(seed)
+    s0 = rng.integers(0, n, 6 * n).astype(np.uint32)
+    d0 = rng.integers(0, n, 6 * n).astype(np.uint32)
+    g = gv.Graph(n, s0, d0, block_slots=B, vertex_capacity=2 * n)
+    o = O.OracleGraph(n, s0, d0, block_slots=B, vertex_capacity=2 * n)
+    dead = rng.choice(n, n // 10, replace=False).astype(np.uint32)
+    g.delete_vertices(dead)
+    o.delete_vertices(dead)
+    for rep in range(3):
+        reqs = []
+        for r in range(60):
+            size = int(rng.integers(0, 200)) if r % 17 else 0
+            op, s, d = mixed_list(rng, n, size, s0, d0, few=8)
+            kind = 2 if r % 23 == 5 else int(rng.integers(0, 2))
+            reqs.append((kind, s, d))
+        op = np.concatenate([np.full(len(x[1]), x[0], np.uint8) for x in reqs])
+        s = np.concatenate([x[1] for x in reqs])
+        d = np.concatenate([x[2] for x in reqs])
+        ends = np.cumsum([len(x[1]) for x in reqs])
+        say(f"request stats n={n} B={B} rep {rep}: {len(op)} entries, {len(reqs)} requests")
+        keep, st = g.apply_edge_ops_stats(op, s, d, ends)
+        assert g.sync() == 0
+        got = st.cpu().numpy()
+        for r, (kind, a, b) in enumerate(reqs):
+            if kind == 0:
+                want = o.insert_edges(a, b)[1]
+            elif kind == 1:
+                want = o.delete_edges(a, b)[1]
+            else:
+                want = (0, len(a), 0)
+            assert tuple(int(x) for x in got[r]) == tuple(want), f"rep {rep} request {r}"
+        assert_same(g, o, f"request stats rep {rep}")
+    g.close()
+
+
 def test_served_ticks_match_oracle_replay():
     gv = need_gpu()
     from paper_2306_08252_amd import served as S
@@ -215,8 +257,9 @@ def test_served_request_alone_equals_in_the_mix():
     each alone with the single-batch calls, in the server's commit order (a
     tick's writes in arrival order, then its queries); every query answered
     in a mixed tick equals the same query run alone on that graph at its
-    commit point, and both graphs end equal.  The ticks overlap on the
-    device (several in flight)."""
+    commit point, every insert or delete request's statistics from its
+    mixed tick equal those of the same request alone, and both graphs end
+    equal.  The ticks overlap on the device (several in flight)."""
     gv = need_gpu()
     from paper_2306_08252_amd import served as S
     scale, m, B = 16, 1 << 20, 16
@@ -226,8 +269,9 @@ def test_served_request_alone_equals_in_the_mix():
     alone = gv.Graph(n, s0, d0, block_slots=B, vertex_capacity=n)
     rng = np.random.default_rng(11)
     host, reqs = _requests(rng, n, 300, s0, d0, g.device, 10**4)
+    stats = {}
     done, ticks, answers = S.serve(g, reqs, None, max_tick_pairs=20000, keep_answers=True,
-                                   max_inflight=3)
+                                   max_inflight=3, stats=stats)
     assert g.sync() == 0
     say(f"{len(reqs)} requests in {len(ticks)} ticks")
     assert max(e - f for f, e in ticks) > 3  # ticks mix requests
@@ -238,9 +282,9 @@ def test_served_request_alone_equals_in_the_mix():
         for i in order:
             kind, a, b = host[i]
             if kind == S.INSERT:
-                alone.insert_edges(a, b)
+                assert stats[i] == tuple(alone.insert_edges(a, b)), f"insert request {i}"
             elif kind == S.DELETE:
-                alone.delete_edges(a, b)
+                assert stats[i] == tuple(alone.delete_edges(a, b)), f"delete request {i}"
             elif kind == S.VINSERT:
                 alone.insert_vertices(a)
             elif kind == S.VDELETE:
