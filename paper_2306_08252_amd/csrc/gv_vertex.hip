@@ -321,16 +321,34 @@ __global__ __launch_bounds__(kThreads) void k_vd_scan(GraphView g, VDel d) {
                 for (uint32_t i = 0; i < 4; ++i) xs[u][i] = 4 * q + i < slots ? g.pool[4 * q + i] : 0u;
             }
         }
+        // the summary in LDS clears most slots; the bitmap words of the rest
+        // are loaded together (one wait per round, not one per slot)
+        uint32_t cand = 0;
 #pragma unroll
         for (uint32_t u = 0; u < kVQuads; ++u) {
             const uint64_t q = q0 + (uint64_t)u * kThreads + threadIdx.x;
 #pragma unroll
             for (uint32_t i = 0; i < 4; ++i) {
-                uint32_t v, p;
-                if (4 * q + i < slots && (uint64_t)xs[u][i] < g.n_cap &&
-                    vd_gone(d, s_sum, xs[u][i]) && vd_hit(g, d, 4 * q + i, &v, &p))
-                    add_hit(v, p);
+                const uint32_t x = xs[u][i];
+                bool c = 4 * q + i < slots && (uint64_t)x < g.n_cap;
+                if (c) {
+                    const uint32_t b = x >> d.sum_shift;
+                    c = (s_sum[b >> 5] >> (b & 31)) & 1u;
+                }
+                cand |= (uint32_t)c << (4 * u + i);
             }
+        }
+        uint32_t word[4 * kVQuads];
+#pragma unroll
+        for (uint32_t k = 0; k < 4 * kVQuads; ++k)
+            word[k] = (cand >> k) & 1u ? d.gone[xs[k / 4][k % 4] >> 5] : 0u;
+#pragma unroll
+        for (uint32_t k = 0; k < 4 * kVQuads; ++k) {
+            const uint32_t x = xs[k / 4][k % 4];
+            if (!((word[k] >> (x & 31)) & 1u)) continue;
+            const uint64_t q = q0 + (uint64_t)(k / 4) * kThreads + threadIdx.x;
+            uint32_t v, p;
+            if (vd_hit(g, d, 4 * q + k % 4, &v, &p)) add_hit(v, p);
         }
     }
     // move the staged hits and touched vertices out
