@@ -66,6 +66,7 @@ enum {
 };
 
 #define GV_MAX_CAPACITY (1ull << 31)
+#define GV_MAX_ATTR_WORDS 8
 
 typedef struct gv_graph gv_graph;
 
@@ -84,6 +85,11 @@ typedef struct {
     /* Directory arena size in uint32 entries; 0 = default (4 entries per pool
      * block plus 2^20). */
     uint64_t directory_entries;
+    /* Attribute words (uint32) per edge entry, 0..GV_MAX_ATTR_WORDS (Sec. 4.1:
+     * an edge entry may carry attributes).  A new entry's attributes are
+     * zero; gv_set_edge_attrs / gv_get_edge_attrs write and read them. */
+    uint32_t edge_attr_words;
+    uint32_t reserved;         /* must be 0 */
 } gv_config;
 
 typedef struct {
@@ -161,6 +167,24 @@ int gv_insert_vertices(gv_graph* g, const uint32_t* d_ids, uint64_t n,
  * rejected; inactive ids are no-ops.  Synchronous. */
 int gv_delete_vertices(gv_graph* g, const uint32_t* d_ids, uint64_t n,
                        gv_batch_stats* stats_or_null);
+
+/* Edge attributes (Sec. 4.1: an edge entry may carry attributes), for
+ * graphs created with gv_config.edge_attr_words = A > 0 (else GV_EINVAL).
+ * An entry's A uint32 words live at its slot and move with it; a newly
+ * inserted edge starts with zeros, a deleted one loses them.
+ * gv_set_edge_attrs: d_attr holds n rows of A words; every pair (d_src[i],
+ * d_dst[i]) that is stored gets row i, the last row of a pair that occurs
+ * several times winning; pairs not stored, or with an invalid endpoint,
+ * change nothing.  Statistics: applied = distinct stored pairs written,
+ * rejected = pairs with an invalid endpoint, batch_duplicates = valid pairs
+ * minus distinct valid pairs.  Asynchronous without a stats pointer.
+ * gv_get_edge_attrs: d_found[i] = 1 and row i of d_attr = the pair's words
+ * if stored, else 0 and zeros.  Asynchronous.  Both take the path of a query
+ * batch (Sec. 4.6) whose probe also records the slot it finds. */
+int gv_set_edge_attrs(gv_graph* g, const uint32_t* d_src, const uint32_t* d_dst,
+                      const uint32_t* d_attr, uint64_t n, gv_batch_stats* stats_or_null);
+int gv_get_edge_attrs(gv_graph* g, const uint32_t* d_src, const uint32_t* d_dst, uint64_t n,
+                      uint8_t* d_found, uint32_t* d_attr);
 
 /* Mixed edge updates, the tick of the served form: entry i inserts
  * (d_op[i] == 0) or deletes (d_op[i] == 1) the pair (d_src[i], d_dst[i]).

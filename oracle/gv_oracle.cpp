@@ -10,6 +10,7 @@
 #include <cstring>
 #include <new>
 #include <iterator>
+#include <map>
 #include <set>
 #include <utility>
 #include <vector>
@@ -18,9 +19,26 @@ struct orc_graph {
     uint64_t capacity;    // vertex dictionary size, a power of two (Sec. 4.1)
     uint32_t B;           // edge entries per edge block (Sec. 4.3)
     uint64_t pool_blocks; // blocks the edge queue can hand out; 0 = unbounded
+    uint64_t pool_bytes;  // the pool's byte budget (0 = unbounded)
     std::vector<uint8_t> active;
     std::vector<std::set<uint32_t>> adj; // ordered adjacency set per vertex
+    // Sec. 4.1: an edge entry may carry attributes; A words per stored edge,
+    // keyed by (src << 32) | dst, present exactly for the stored edges
+    uint32_t A = 0;
+    std::map<uint64_t, std::vector<uint32_t>> attr;
 };
+
+static uint64_t pair_key(uint32_t u, uint32_t v) { return ((uint64_t)u << 32) | v; }
+
+// a stored edge appears: its attributes start at zero
+static void attr_new(orc_graph* g, uint32_t u, uint32_t v) {
+    if (g->A) g->attr[pair_key(u, v)].assign(g->A, 0u);
+}
+
+// a stored edge disappears with its attributes
+static void attr_drop(orc_graph* g, uint32_t u, uint32_t v) {
+    if (g->A) g->attr.erase(pair_key(u, v));
+}
 
 extern "C" uint64_t orc_next_pow2(uint64_t x) {
     // Sec. 4.1: a dictionary for 453 vertices has 512 entries.  Read as the
@@ -103,6 +121,7 @@ extern "C" int orc_graph_init(orc_graph** out, uint64_t num_vertices,
         nonzero += g->adj[v].empty() ? 0 : 1;
     }
     g->B = block_slots ? block_slots : orc_paper_block_slots(edges, nonzero);
+    g->pool_bytes = pool_bytes;
     g->pool_blocks = pool_bytes ? pool_bytes / (4ull * g->B) : 0;
     if (g->pool_blocks && orc_blocks_in_use(g) > g->pool_blocks) {
         delete g;
@@ -120,8 +139,11 @@ extern "C" int orc_apply_edge_ops(orc_graph* g, const uint8_t* op, const uint32_
     for (uint64_t i = 0; i < n; ++i) {
         const uint32_t u = src[i], v = dst[i];
         if (!valid_vertex(g, u) || !valid_vertex(g, v)) continue;
-        if (op[i] == 0) g->adj[u].insert(v);
-        else if (op[i] == 1) g->adj[u].erase(v);
+        if (op[i] == 0) {
+            if (g->adj[u].insert(v).second) attr_new(g, u, v);
+        } else if (op[i] == 1) {
+            if (g->adj[u].erase(v)) attr_drop(g, u, v);
+        }
     }
     return ORC_OK;
 }
@@ -170,7 +192,10 @@ extern "C" int orc_insert_edges(orc_graph* g, const uint32_t* src,
         }
         if (after > g->pool_blocks) return ORC_ENOMEM;
     }
-    for (const auto& e : fresh) g->adj[e.first].insert(e.second);
+    for (const auto& e : fresh) {
+        g->adj[e.first].insert(e.second);
+        attr_new(g, e.first, e.second);
+    }
     s.applied = fresh.size();
     if (stats) *stats = s;
     return ORC_OK;
@@ -194,7 +219,9 @@ extern "C" int orc_delete_edges(orc_graph* g, const uint32_t* src,
             continue;
         }
         // Sec. 4.5.2: a matching entry is removed; an absent one is a no-op.
-        s.applied += g->adj[u].erase(v);
+        const uint64_t e = g->adj[u].erase(v);
+        if (e) attr_drop(g, u, v);
+        s.applied += e;
     }
     if (stats) *stats = s;
     return ORC_OK;
@@ -257,11 +284,20 @@ extern "C" int orc_delete_vertices(orc_graph* g, const uint32_t* ids,
         if (g->active[x]) gone.insert(x);
     }
     // A deleted vertex loses its outgoing and its incoming edges.
-    for (uint32_t x : gone) g->adj[x].clear();
+    for (uint32_t x : gone) {
+        for (uint32_t v : g->adj[x]) attr_drop(g, x, v);
+        g->adj[x].clear();
+    }
     for (uint64_t u = 0; u < g->capacity; ++u) {
         std::set<uint32_t>& a = g->adj[u];
-        for (auto it = a.begin(); it != a.end();)
-            it = gone.count(*it) ? a.erase(it) : std::next(it);
+        for (auto it = a.begin(); it != a.end();) {
+            if (gone.count(*it)) {
+                attr_drop(g, (uint32_t)u, *it);
+                it = a.erase(it);
+            } else {
+                it = std::next(it);
+            }
+        }
     }
     for (uint32_t x : gone) g->active[x] = 0;
     s.applied = gone.size();
@@ -328,4 +364,81 @@ extern "C" int orc_is_active(const orc_graph* g, uint32_t v) {
 
 extern "C" uint64_t orc_degree(const orc_graph* g, uint32_t v) {
     return (uint64_t)v < g->capacity ? g->adj[v].size() : 0;
+}
+
+extern "C" int orc_set_attr_words(orc_graph* g, uint32_t words) {
+    if (!g || g->A != 0 || words > 8) return ORC_EINVAL;
+    g->A = words;
+    for (uint64_t u = 0; u < g->capacity; ++u)
+        for (uint32_t v : g->adj[u]) attr_new(g, (uint32_t)u, v);
+    return ORC_OK;
+}
+
+extern "C" uint32_t orc_attr_words(const orc_graph* g) { return g->A; }
+
+extern "C" int orc_set_edge_attrs(orc_graph* g, const uint32_t* src, const uint32_t* dst,
+                                  const uint32_t* vals, uint64_t n, orc_stats* stats) {
+    zero_stats(stats);
+    if (!g || g->A == 0 || (n && (!src || !dst || !vals))) return ORC_EINVAL;
+    orc_stats s = {0, 0, 0};
+    std::set<std::pair<uint32_t, uint32_t>> seen;
+    // one pair at a time in batch order: a later row of the same pair
+    // overwrites an earlier one
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint32_t u = src[i], v = dst[i];
+        if (!valid_vertex(g, u) || !valid_vertex(g, v)) {
+            s.rejected++;
+            continue;
+        }
+        const bool first = seen.insert({u, v}).second;
+        if (!first) s.batch_duplicates++;
+        if (!g->adj[u].count(v)) continue;
+        if (first) s.applied++;
+        std::vector<uint32_t>& a = g->attr[pair_key(u, v)];
+        for (uint32_t k = 0; k < g->A; ++k) a[k] = vals[i * g->A + k];
+    }
+    if (stats) *stats = s;
+    return ORC_OK;
+}
+
+extern "C" int orc_get_edge_attrs(const orc_graph* g, const uint32_t* src, const uint32_t* dst,
+                                  uint64_t n, uint8_t* found, uint32_t* vals) {
+    if (!g || g->A == 0 || (n && (!src || !dst || !found || !vals))) return ORC_EINVAL;
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint32_t u = src[i], v = dst[i];
+        const bool here = valid_vertex(g, u) && g->adj[u].count(v);
+        found[i] = here ? 1 : 0;
+        for (uint32_t k = 0; k < g->A; ++k)
+            vals[i * g->A + k] = here ? g->attr.at(pair_key(u, v))[k] : 0u;
+    }
+    return ORC_OK;
+}
+
+extern "C" int orc_set_block_slots(orc_graph* g, uint32_t block_slots) {
+    // Sec. 6 (future scope): the edge block size may change over the life of
+    // the graph; the edges stay, only the block accounting follows the new
+    // size.  The pool keeps its byte budget.
+    if (!g || block_slots == 0 || block_slots > 1024 || (block_slots & (block_slots - 1)) != 0)
+        return ORC_EINVAL;
+    const uint32_t old_b = g->B;
+    const uint64_t old_blocks = g->pool_blocks;
+    g->B = block_slots;
+    g->pool_blocks = g->pool_bytes ? g->pool_bytes / (4ull * g->B) : 0;
+    if (g->pool_blocks && orc_blocks_in_use(g) > g->pool_blocks) {
+        g->B = old_b;
+        g->pool_blocks = old_blocks;
+        return ORC_ENOMEM;
+    }
+    return ORC_OK;
+}
+
+extern "C" uint32_t orc_adapted_block_slots(const orc_graph* g) {
+    // the initialization rule of Sec. 4.3 applied to the graph as it is now
+    // (Sec. 6: the average degree changes across batches)
+    uint64_t edges = 0, nonzero = 0;
+    for (uint64_t v = 0; v < g->capacity; ++v) {
+        edges += g->adj[v].size();
+        nonzero += g->adj[v].empty() ? 0 : 1;
+    }
+    return orc_paper_block_slots(edges, nonzero);
 }

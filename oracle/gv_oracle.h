@@ -121,6 +121,32 @@ uint64_t orc_blocks_in_use(const orc_graph* g);
 int orc_is_active(const orc_graph* g, uint32_t v);
 uint64_t orc_degree(const orc_graph* g, uint32_t v);
 
+/* Edge attributes (Sec. 4.1: an edge entry may carry attributes).
+ * orc_set_attr_words gives every stored edge `words` (1..8) attribute words,
+ * all zero, once per graph.  From then on a newly stored edge starts with
+ * zeros and a removed edge loses its words.  orc_set_edge_attrs applies the
+ * rows vals[i * A ...] one pair at a time in batch order to the pairs that
+ * are stored (a later row of a pair overwrites an earlier one); stats:
+ * applied = distinct stored pairs written, rejected = invalid pairs,
+ * batch_duplicates = valid minus distinct valid.  orc_get_edge_attrs: found
+ * flag and the words of each pair (zeros when absent). */
+int orc_set_attr_words(orc_graph* g, uint32_t words);
+uint32_t orc_attr_words(const orc_graph* g);
+int orc_set_edge_attrs(orc_graph* g, const uint32_t* src, const uint32_t* dst,
+                       const uint32_t* vals, uint64_t n, orc_stats* stats);
+int orc_get_edge_attrs(const orc_graph* g, const uint32_t* src, const uint32_t* dst,
+                       uint64_t n, uint8_t* found, uint32_t* vals);
+
+/* Block size over the graph's life (Sec. 6, future scope).
+ * orc_set_block_slots: the same edges, accounted in blocks of the new size
+ * (power of two in [1, 1024]); a bounded pool keeps its byte budget, and a
+ * graph that would not fit gives ORC_ENOMEM unchanged.
+ * orc_adapted_block_slots: the rule of Sec. 4.3 applied to the current
+ * graph (average degree of the non-zero-degree vertices, power of two within
+ * [8, 64]). */
+int orc_set_block_slots(orc_graph* g, uint32_t block_slots);
+uint32_t orc_adapted_block_slots(const orc_graph* g);
+
 #ifdef __cplusplus
 }
 #endif

@@ -71,6 +71,19 @@ def lib():
         L.orc_is_active.argtypes = [C.c_void_p, C.c_uint32]
         L.orc_degree.restype = C.c_uint64
         L.orc_degree.argtypes = [C.c_void_p, C.c_uint32]
+        L.orc_set_attr_words.restype = C.c_int
+        L.orc_set_attr_words.argtypes = [C.c_void_p, C.c_uint32]
+        L.orc_attr_words.restype = C.c_uint32
+        L.orc_attr_words.argtypes = [C.c_void_p]
+        L.orc_set_edge_attrs.restype = C.c_int
+        L.orc_set_edge_attrs.argtypes = [C.c_void_p, u32p, u32p, u32p, C.c_uint64,
+                                         C.POINTER(Stats)]
+        L.orc_get_edge_attrs.restype = C.c_int
+        L.orc_get_edge_attrs.argtypes = [C.c_void_p, u32p, u32p, C.c_uint64, u8p, u32p]
+        L.orc_set_block_slots.restype = C.c_int
+        L.orc_set_block_slots.argtypes = [C.c_void_p, C.c_uint32]
+        L.orc_adapted_block_slots.restype = C.c_uint32
+        L.orc_adapted_block_slots.argtypes = [C.c_void_p]
         _lib = L
     return _lib
 
@@ -152,6 +165,44 @@ class OracleGraph:
             raise ValueError("op/src/dst length mismatch")
         return lib().orc_apply_edge_ops(self._h, o.ctypes.data_as(C.POINTER(C.c_uint8)),
                                         sp, dp, len(s))
+
+    def set_attr_words(self, words):
+        rc = lib().orc_set_attr_words(self._h, int(words))
+        if rc != OK:
+            raise OracleError(rc, "orc_set_attr_words")
+
+    @property
+    def attr_words(self):
+        return int(lib().orc_attr_words(self._h))
+
+    def set_edge_attrs(self, src, dst, vals):
+        """vals: n x A rows.  Returns (rc, (applied, rejected, batch_duplicates))."""
+        s, sp = _u32(src)
+        d, dp = _u32(dst)
+        v, vp = _u32(np.asarray(vals, np.uint32).reshape(-1))
+        st = Stats()
+        rc = lib().orc_set_edge_attrs(self._h, sp, dp, vp, len(s), C.byref(st))
+        return rc, st.as_tuple()
+
+    def get_edge_attrs(self, src, dst):
+        """Returns (found uint8[n], vals uint32[n, A])."""
+        s, sp = _u32(src)
+        d, dp = _u32(dst)
+        A = self.attr_words
+        found = np.zeros(max(len(s), 1), dtype=np.uint8)
+        vals = np.zeros((max(len(s), 1), max(A, 1)), dtype=np.uint32)
+        rc = lib().orc_get_edge_attrs(self._h, sp, dp, len(s),
+                                      found.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                      vals.ctypes.data_as(C.POINTER(C.c_uint32)))
+        if rc != OK:
+            raise OracleError(rc, "orc_get_edge_attrs")
+        return found[: len(s)], vals[: len(s), :A]
+
+    def set_block_slots(self, block_slots):
+        return int(lib().orc_set_block_slots(self._h, int(block_slots)))
+
+    def adapted_block_slots(self):
+        return int(lib().orc_adapted_block_slots(self._h))
 
     def _verts(self, fn, ids):
         a, ap = _u32(ids)

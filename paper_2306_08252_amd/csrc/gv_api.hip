@@ -51,8 +51,8 @@ void free_graph(gv_graph* g) {
     g->scratch.release();
     for (auto& v : g->vscr) v.release();
     g->cscr.release();
-    void* mem[] = {g->mem_pool, g->mem_free,   g->mem_dir, g->mem_dfree, g->mem_vt,
-                   g->mem_active, g->mem_ctr, g->mem_bown, g->mem_vlost};
+    void* mem[] = {g->mem_pool,   g->mem_free, g->mem_dir,  g->mem_dfree, g->mem_vt,
+                   g->mem_active, g->mem_ctr,  g->mem_bown, g->mem_vlost, g->mem_apool};
     for (void* p : mem)
         if (p) hipFree(p);
     if (g->hctr) hipHostFree(g->hctr);
@@ -105,7 +105,8 @@ int gv_graph_init(gv_graph** out, uint64_t num_vertices, const uint32_t* d_src,
     if (cfg) c = *cfg;
     if (num_vertices > GV_MAX_CAPACITY || c.vertex_capacity > GV_MAX_CAPACITY) return GV_EINVAL;
     if (c.block_slots != 0 && (c.block_slots > 1024 || !pow2(c.block_slots))) return GV_EINVAL;
-    if (c.flags != 0) return GV_EINVAL;
+    if (c.flags != 0 || c.reserved != 0 || c.edge_attr_words > GV_MAX_ATTR_WORDS)
+        return GV_EINVAL;
     if (num_edges && (!d_src || !d_dst)) return GV_EINVAL;
     gv_graph* g = new (std::nothrow) gv_graph();
     if (!g) return GV_ENOMEM;
@@ -118,6 +119,7 @@ int gv_graph_init(gv_graph** out, uint64_t num_vertices, const uint32_t* d_src,
         GraphView& v = g->v;
         v.n_cap = cap;
         v.L = log2_exact(cap);
+        v.A = c.edge_attr_words;
         hip_check(hipMalloc(&g->mem_vt, cap * sizeof(VRec)), "hipMalloc vertex table");
         hip_check(hipMalloc(&g->mem_active, ((cap + 31) / 32) * 4), "hipMalloc active");
         hip_check(hipMalloc(&g->mem_ctr, sizeof(DevCounters)), "hipMalloc counters");
@@ -226,6 +228,35 @@ int gv_edge_exists_noalloc(gv_graph* g, const uint32_t* d_src, const uint32_t* d
     return guarded(g, [&] { gv_noalloc_query(g, d_src, d_dst, n, d_out); });
 }
 
+int gv_set_edge_attrs(gv_graph* g, const uint32_t* d_src, const uint32_t* d_dst,
+                      const uint32_t* d_attr, uint64_t n, gv_batch_stats* st) {
+    if (st) std::memset(st, 0, sizeof(*st));
+    if (!g || !g->v.A) return GV_EINVAL;
+    if (n && (!d_src || !d_dst || !d_attr)) return GV_EINVAL;
+    if (n == 0) return GV_OK;
+    int rc = guarded(g, [&] {
+        edge_attrs(g, d_src, d_dst, n, nullptr, nullptr, d_attr);
+        if (st) {
+            read_counters(g);
+            check_sort(g);
+            const uint64_t valid = g->hctr->tot[0];  // valid pairs of the batch
+            st->applied = g->hctr->st_applied;
+            st->rejected = n - valid;
+            st->batch_duplicates = valid - g->hctr->n_uniq;
+        }
+    });
+    if (rc != GV_OK && st) std::memset(st, 0, sizeof(*st));
+    return rc;
+}
+
+int gv_get_edge_attrs(gv_graph* g, const uint32_t* d_src, const uint32_t* d_dst, uint64_t n,
+                      uint8_t* d_found, uint32_t* d_attr) {
+    if (!g || !g->v.A) return GV_EINVAL;
+    if (n && (!d_src || !d_dst || !d_found || !d_attr)) return GV_EINVAL;
+    if (n == 0) return GV_OK;
+    return guarded(g, [&] { edge_attrs(g, d_src, d_dst, n, d_found, d_attr, nullptr); });
+}
+
 int gv_apply_edge_ops(gv_graph* g, const uint8_t* d_op, const uint32_t* d_src,
                       const uint32_t* d_dst, uint64_t n) {
     if (!g) return GV_EINVAL;
@@ -275,7 +306,8 @@ int gv_memory_used(gv_graph* g, gv_mem* out) {
         m.live_bytes = m.blocks_in_use * m.block_bytes + m.vertex_table_bytes + 4ull * c.dir_live;
         m.num_edges = c.live_edges;
         m.reserved_bytes = v.cap_blocks * m.block_bytes + 4ull * v.cap_blocks +
-                           8ull * v.cap_blocks + 4ull * v.n_cap + m.directory_bytes +
+                           8ull * v.cap_blocks + 4ull * v.n_cap +
+                           4ull * v.A * v.cap_blocks * v.B + m.directory_bytes +
                            m.vertex_table_bytes + sizeof(DevCounters) + g->scratch.cap;
         *out = m;
     });

@@ -161,7 +161,9 @@ __global__ __launch_bounds__(kThreads) void k_init_scatter(GraphView g, const ui
     const uint32_t v = (uint32_t)(k >> g.L);
     const uint32_t s = (uint32_t)p - runstart[v];
     const uint64_t blk = (uint32_t)off[v] + (s >> g.log2B);
-    g.pool[(blk << g.log2B) + (s & (g.B - 1))] = (uint32_t)(k & ((1ull << g.L) - 1));
+    const uint64_t a = (blk << g.log2B) + (s & (g.B - 1));
+    g.pool[a] = (uint32_t)(k & ((1ull << g.L) - 1));
+    attr_zero(g, a);
 }
 
 __global__ __launch_bounds__(kThreads) void k_save_runstart(GraphView g, uint32_t* runstart) {
@@ -278,6 +280,8 @@ void bulk_build(gv_graph* g, uint64_t n, const uint32_t* src, const uint32_t* ds
               "hipMalloc free list");
     hip_check(hipMalloc(&g->mem_bown, std::max<uint64_t>(cap_blocks * 8ull, 8)),
               "hipMalloc block owners");
+    if (v.A)
+        hip_check(hipMalloc(&g->mem_apool, cap_blocks * B * 4ull * v.A), "hipMalloc attributes");
     hip_check(hipMalloc(&g->mem_dir, std::max<uint64_t>(dir_cap * 4ull, 4)), "hipMalloc dir");
     uint64_t dfree_total = 0;
     for (int k = 0; k < kMaxClass; ++k) {
@@ -289,6 +293,7 @@ void bulk_build(gv_graph* g, uint64_t n, const uint32_t* src, const uint32_t* ds
     v.pool = (uint32_t*)g->mem_pool;
     v.free_stack = (uint32_t*)g->mem_free;
     v.bown = (uint2*)g->mem_bown;
+    v.apool = (uint32_t*)g->mem_apool;
     v.dir = (uint32_t*)g->mem_dir;
     v.dfree = (uint32_t*)g->mem_dfree;
     v.cap_blocks = cap_blocks;

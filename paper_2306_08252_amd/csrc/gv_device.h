@@ -15,6 +15,10 @@
 //               pool has handed out, written when the block is assigned (a
 //               freed block keeps its last owner; readers check it).
 //   vlost       n_cap uint32, zero between vertex deletions (their scratch).
+//   apool       cap_blocks * B * A uint32 (graphs with A > 0 attribute words
+//               per edge entry): slot a's attributes at [a * A, a * A + A).
+//               Kept beside the pool, not inside it, so that every probe and
+//               scan reads destinations only; entries move with their slot.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -104,10 +108,11 @@ struct GraphView {
     DevCounters* ctr;
     uint2* bown;
     uint32_t* vlost;
+    uint32_t* apool;     // A attribute words per pool slot (slot a: apool[a * A, a * A + A))
     unsigned long long n_cap;
     unsigned long long cap_blocks;
     unsigned long long dir_cap;
-    uint32_t B, log2B, L, pad;
+    uint32_t B, log2B, L, A;
     unsigned long long dfree_base[kMaxClass];
 };
 
@@ -158,6 +163,16 @@ __device__ __host__ __forceinline__ uint32_t ceil_log2(uint64_t x) {
     uint32_t c = 0;
     while ((1ull << c) < x) ++c;
     return c;
+}
+
+// attributes of an entry follow it when it moves from slot `from` to `to`
+__device__ __forceinline__ void attr_move(const GraphView& g, uint64_t to, uint64_t from) {
+    for (uint32_t k = 0; k < g.A; ++k) g.apool[to * g.A + k] = g.apool[from * g.A + k];
+}
+
+// a new entry's attributes start at zero
+__device__ __forceinline__ void attr_zero(const GraphView& g, uint64_t a) {
+    for (uint32_t k = 0; k < g.A; ++k) g.apool[a * g.A + k] = 0u;
 }
 
 // SplitMix64 output function (Steele, Lea, Flood 2014): checksum mixer.

@@ -73,6 +73,9 @@ constexpr uint32_t kClassMask = 0xFFu;         // t_dreq & kClassMask: requested
 
 // scan-total slots in DevCounters::tot
 enum { kTotValid = 0, kTotSeg = 1, kTotItems = 2, kTotA = 3, kTotB = 4, kTotHash = 5 };
+// probe mode of the attribute calls: a query that also records the slot of
+// every occurrence it finds
+constexpr int kLocate = 3;
 // stripe[k][kStripeHash]: per-workgroup sums of mix64 over the sorted keys
 constexpr int kStripeHash = 1;
 
@@ -90,6 +93,12 @@ struct alignas(16) CDesc {
     uint32_t deg, dir, dcls, need;
 };
 
+// attribute call of a query batch: get (out) or set (in), n * A words
+struct AttrOp {
+    uint32_t* out;
+    const uint32_t* in;
+};
+
 struct BatchArrays {
     uint64_t* keys0;
     uint64_t* keys1;
@@ -99,7 +108,7 @@ struct BatchArrays {
     uint8_t* mark;
     uint32_t* a;        // segment index of each valid key
     uint32_t* b;        // n+1: exclusive count of kept (insert) / found (delete)
-    uint32_t* hitpos;   // delete: slot index of each hit
+    uint32_t* hitpos;   // delete, attribute calls: slot index of each hit
     uint32_t* holes;    // delete: hole slots per segment
     uint32_t* t_vtx;    // touched source per segment
     uint32_t* t_start;  // n+1: segment start; t_start[n_T] = n_valid
@@ -134,6 +143,7 @@ static void carve_batch(Carver& cv, BatchArrays& A, uint64_t n, uint64_t icap, E
     A.mark = cv.take<uint8_t>(n);
     A.a = cv.take<uint32_t>(n);
     A.b = cv.take<uint32_t>(n + 1);
+    if (mode == kQuery) A.hitpos = cv.take<uint32_t>(n);  // attribute calls
     if (mode == kDelete) {
         A.hitpos = cv.take<uint32_t>(n);
         A.holes = cv.take<uint32_t>(n);
@@ -702,7 +712,10 @@ __device__ __forceinline__ void probe_search(const GraphView& g, const Item& I, 
             g.pool[addr[u]] = kTomb;
         } else {
             const uint64_t target = vbase | x[u];
-            for (uint32_t j = pos; j < I.hi && keys[j] == target; ++j) mark[j] = 1;
+            for (uint32_t j = pos; j < I.hi && keys[j] == target; ++j) {
+                mark[j] = 1;
+                if (MODE == kLocate) hitpos[j] = si;
+            }
         }
     }
 }
@@ -748,13 +761,15 @@ __device__ __forceinline__ void probe_small(const GraphView& g, const Item& I, u
 #pragma unroll
     for (uint32_t j = 0; j < kSmallSeg; ++j) {
         if (j >= len) break;
-        if (MODE != kQuery && j > 0 && d[j] == d[j - 1]) continue;  // not a first occurrence
+        if (MODE != kQuery && MODE != kLocate && j > 0 && d[j] == d[j - 1])
+            continue;  // not a first occurrence
         uint32_t hu = kSmallDeg;
 #pragma unroll
         for (uint32_t u = 0; u < kSmallDeg; ++u)
             if (first + u < deg && x[u] == d[j]) hu = u;
         if (hu == kSmallDeg) continue;
         mark[I.lo + j] = 1;
+        if (MODE == kLocate) hitpos[I.lo + j] = first + hu;
         if (MODE == kDelete) {
             hitpos[I.lo + j] = first + hu;
             g.pool[a[hu / 4] + (hu & 3)] = kTomb;
@@ -768,7 +783,7 @@ __global__ __launch_bounds__(kThreads) void k_probe(GraphView g, const uint64_t*
                                                     uint8_t* mark, uint32_t* hitpos) {
     __shared__ uint32_t stage[kWaves * kGroupsPerWave][kStage];
     if (batch_failed(g.ctr)) return;
-    if (MODE != kQuery) {
+    if (MODE == kInsert || MODE == kDelete) {
         // the sorted keys must be the packed keys: their mix64 sums agree
         // (per-workgroup sums of the segment scan in 64 stripes; one load a lane)
         const unsigned long long sorted = wave_sum(g.ctr->stripe[lane_id()][kStripeHash]);
@@ -1073,7 +1088,9 @@ __global__ __launch_bounds__(kThreads) void k_append(GraphView g, const uint64_t
     const uint32_t sl = r.deg + (bi - b[lo]);
     const uint32_t j = sl >> g.log2B, nb0 = nblocks(g, r.deg);
     const uint32_t blk = j < nb0 ? block_of(g, r, j) : planned_block(g, c, (uint64_t)p0 + (j - nb0));
-    g.pool[((uint64_t)blk << g.log2B) + (sl & (g.B - 1))] = (uint32_t)(key & ((1ull << g.L) - 1));
+    const uint64_t sa = ((uint64_t)blk << g.log2B) + (sl & (g.B - 1));
+    g.pool[sa] = (uint32_t)(key & ((1ull << g.L) - 1));
+    attr_zero(g, sa);
 }
 
 __device__ __forceinline__ uint32_t planned_segment(const GraphView& g, const DevCounters* c,
@@ -1336,18 +1353,20 @@ __device__ __forceinline__ void compact_body(const GraphView& g, const uint8_t* 
 #pragma unroll
             for (uint32_t k = 0; k < kLaneR; ++k)
                 sm |= (k < D.r && sv[k] != kTomb) ? (1u << k) : 0u;
-            uint32_t hslot[kLaneR], hval[kLaneR];
+            uint32_t hslot[kLaneR], hval[kLaneR], hsrc[kLaneR];
             uint32_t nmove = 0;
 #pragma unroll
             for (uint32_t k = 0; k < kLaneR; ++k) {
                 hslot[k] = 0;
                 hval[k] = 0;
+                hsrc[k] = 0;
                 if (hm && sm) {
                     const uint32_t u = __builtin_ctz(hm), w = __builtin_ctz(sm);
                     hm &= hm - 1;
                     sm &= sm - 1;
                     hslot[k] = hp[u];
                     hval[k] = sv[w];
+                    hsrc[k] = w;
                     nmove = k + 1;
                 }
             }
@@ -1355,8 +1374,18 @@ __device__ __forceinline__ void compact_body(const GraphView& g, const uint8_t* 
 #pragma unroll
             for (uint32_t k = 0; k < kLaneR; ++k) hb[k] = block_of(g, rec, hslot[k] >> g.log2B);
 #pragma unroll
-            for (uint32_t k = 0; k < kLaneR; ++k)
-                if (k < nmove) g.pool[((uint64_t)hb[k] << g.log2B) + (hslot[k] & bm)] = hval[k];
+            for (uint32_t k = 0; k < kLaneR; ++k) {
+                if (k >= nmove) continue;
+                const uint64_t da = ((uint64_t)hb[k] << g.log2B) + (hslot[k] & bm);
+                g.pool[da] = hval[k];
+                if (g.A) {
+                    // the survivor sat at slot dn + w (w < r <= kLaneR)
+                    uint32_t sbw = sb[0];
+#pragma unroll
+                    for (uint32_t j = 1; j < kLaneR; ++j) sbw = hsrc[k] == j ? sb[j] : sbw;
+                    attr_move(g, da, ((uint64_t)sbw << g.log2B) + ((dn + hsrc[k]) & bm));
+                }
+            }
             moved += nmove;
             const uint32_t nb0 = nblocks(g, d), nb1 = nblocks(g, dn);
             const unsigned long long pb = fbase + D.need;
@@ -1403,7 +1432,11 @@ __device__ __forceinline__ void compact_body(const GraphView& g, const uint8_t* 
                     const uint32_t qq = ns + popc64(bal & below);
                     if (qq < nh) {
                         const uint32_t dest = holes[H.lo + qq];
-                        if (dest < dn) g.pool[slot_addr(g, rec, dest)] = x;
+                        if (dest < dn) {
+                            const uint64_t da = slot_addr(g, rec, dest);
+                            g.pool[da] = x;
+                            if (g.A) attr_move(g, da, slot_addr(g, rec, sl));
+                        }
                     }
                 }
                 ns += popc64(bal);
@@ -1466,7 +1499,11 @@ __device__ __forceinline__ void compact_big_body(const GraphView& g, const uint8
                 const uint32_t qq = ns + ex;
                 if (qq < nh) {
                     const uint32_t dest = holes[D.lo + qq];
-                    if (dest < dn) g.pool[slot_addr(g, rec, dest)] = x;
+                    if (dest < dn) {
+                        const uint64_t da = slot_addr(g, rec, dest);
+                        g.pool[da] = x;
+                        if (g.A) attr_move(g, da, slot_addr(g, rec, s));
+                    }
                 }
             }
             ns += tot;
@@ -1541,6 +1578,66 @@ __global__ __launch_bounds__(kThreads) void k_answer(GraphView g, const uint32_t
     if (i < nv && vals[i] < n) out[vals[i]] = mark[i];
 }
 
+// ------------------------------------------------------------------ attributes
+// get: a found pair's attributes (read at the slot the probe recorded) at
+// its input position; a pair not found reads zeros
+__global__ __launch_bounds__(kThreads) void k_attr_get(GraphView g, const uint64_t* keys,
+                                                       const uint32_t* vals, const uint8_t* mark,
+                                                       const uint32_t* hitpos, uint64_t n,
+                                                       uint32_t* out) {
+    const uint64_t i = thread_index();
+    if (batch_failed(g.ctr)) return;
+    const uint64_t nv = min((uint64_t)g.ctr->tot[kTotValid], n);
+    if (i >= nv || vals[i] >= n) return;
+    const uint64_t o = (uint64_t)vals[i] * g.A;
+    if (!mark[i]) {
+        for (uint32_t k = 0; k < g.A; ++k) out[o + k] = 0u;
+        return;
+    }
+    const uint64_t a = slot_addr(g, g.vt[keys[i] >> g.L], hitpos[i]);
+    for (uint32_t k = 0; k < g.A; ++k) out[o + k] = g.apool[a * g.A + k];
+}
+
+// set: the last occurrence of each found pair in input order (the sort is
+// stable, so the last of its run) writes its attributes; counts for the
+// statistics
+__global__ __launch_bounds__(kThreads) void k_attr_set(GraphView g, const uint64_t* keys,
+                                                       const uint32_t* vals, const uint8_t* mark,
+                                                       const uint32_t* hitpos, uint64_t n,
+                                                       const uint32_t* in) {
+    __shared__ unsigned long long lds[kWaves];
+    const uint64_t i = thread_index();
+    if (batch_failed(g.ctr)) return;
+    const uint64_t nv = min((uint64_t)g.ctr->tot[kTotValid], n);
+    unsigned long long distinct = 0, applied = 0;
+    if (i < nv) {
+        const bool last = i + 1 >= nv || keys[i + 1] != keys[i];
+        distinct = last;
+        if (last && mark[i] && vals[i] < n) {
+            applied = 1;
+            const uint64_t a = slot_addr(g, g.vt[keys[i] >> g.L], hitpos[i]);
+            const uint64_t o = (uint64_t)vals[i] * g.A;
+            for (uint32_t k = 0; k < g.A; ++k) g.apool[a * g.A + k] = in[o + k];
+        }
+    }
+    distinct = block_sum(distinct, lds);
+    applied = block_sum(applied, lds);
+    if (threadIdx.x == 0) {
+        if (distinct) atomicAdd(&g.ctr->n_uniq, distinct);
+        if (applied) atomicAdd(&g.ctr->st_applied, applied);
+    }
+}
+
+__global__ void k_attr_begin(DevCounters* c) {
+    c->n_uniq = 0;
+    c->st_applied = 0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_zero_attr(uint32_t* p, uint64_t n) {
+    const uint64_t i = thread_index();
+    if (i < n) p[i] = 0u;
+}
+
 __global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
 __global__ void k_set_u64(unsigned long long* p, unsigned long long v) { *p = v; }
 
@@ -1558,6 +1655,7 @@ void edge_batch_warm() {
     resident_grid(k_probe<kInsert>, kThreads);
     resident_grid(k_probe<kDelete>, kThreads);
     resident_grid(k_probe<kQuery>, kThreads);
+    resident_grid(k_probe<kLocate>, kThreads);
     resident_grid(k_grow, kThreads);
     resident_grid(k_compact, kThreads);
     resident_grid(k_os_pass<uint64_t, false>, kOsThreads);
@@ -1598,7 +1696,7 @@ __global__ __launch_bounds__(kThreads) void k_sorted_prep_b(GraphView g, const u
 static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t* dst,
                      const uint64_t* sorted, const unsigned long long* sorted_n, uint64_t n,
                      uint8_t* out, bool sticky, void* fixed, size_t fixed_bytes,
-                     uint8_t* mark_out);
+                     uint8_t* mark_out, const AttrOp* aop = nullptr);
 
 // the probe's per-key result of a sorted batch (stored before the batch, for
 // an insert; found, for a delete), out of the batch's scratch
@@ -1622,10 +1720,26 @@ void edge_batch_sorted(gv_graph* g, EdgeMode mode, const uint64_t* keys,
              mark_out);
 }
 
+void edge_attrs(gv_graph* g, const uint32_t* src, const uint32_t* dst, uint64_t n,
+                uint8_t* found, uint32_t* out, const uint32_t* in) {
+    if (n == 0) return;
+    const AttrOp op{out, in};
+    Ctx& c = g->ctx;
+    if (out) {
+        // answers of invalid pairs are written by the packing scan; their
+        // attributes read zeros
+        c.launch("attr_get", k_zero_attr, div_up(n * g->v.A, kThreads), kThreads, out,
+                 n * g->v.A);
+    } else {
+        c.launch("attr_set", k_attr_begin, 1, 1, g->v.ctr);
+    }
+    edge_run(g, kQuery, src, dst, nullptr, nullptr, n, found, true, nullptr, 0, nullptr, &op);
+}
+
 static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t* dst,
                      const uint64_t* sorted, const unsigned long long* sorted_n, uint64_t n,
                      uint8_t* out, bool sticky, void* fixed, size_t fixed_bytes,
-                     uint8_t* mark_out) {
+                     uint8_t* mark_out, const AttrOp* aop) {
     if (n == 0) return;
     if (n >= 0x3fffffffull) fail(GV_EINVAL, "batch too large");
     Ctx& c = g->ctx;
@@ -1726,6 +1840,17 @@ static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint
                  kThreads, v, (const uint8_t*)A.mark, (const uint32_t*)A.hitpos, A.holes,
                  (const CDesc*)A.cdesc, (const uint32_t*)A.heavy, (const uint32_t*)A.big, nbig);
         c.launch("final_delete", k_final_del, 1, 1, v, n);
+    } else if (aop) {
+        c.launch("probe_locate", k_probe<kLocate>, pgrid_of(k_probe<kLocate>), kThreads, v, keys,
+                 (const Item*)A.items, (const Item*)A.small, A.mark, A.hitpos);
+        if (aop->out) {
+            c.launch("answer", k_answer, grid, kThreads, v, vals, (const uint8_t*)A.mark, n, out);
+            c.launch("attr_get", k_attr_get, grid, kThreads, v, keys, vals,
+                     (const uint8_t*)A.mark, (const uint32_t*)A.hitpos, n, aop->out);
+        } else {
+            c.launch("attr_set", k_attr_set, grid, kThreads, v, keys, vals,
+                     (const uint8_t*)A.mark, (const uint32_t*)A.hitpos, n, aop->in);
+        }
     } else {
         c.launch("probe_query", k_probe<kQuery>, pgrid_of(k_probe<kQuery>), kThreads, v, keys, (const Item*)A.items, (const Item*)A.small,
                  A.mark, (uint32_t*)nullptr);

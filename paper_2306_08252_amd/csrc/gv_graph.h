@@ -27,6 +27,7 @@ struct gv_graph {
     void* mem_ctr = nullptr;
     void* mem_bown = nullptr;
     void* mem_vlost = nullptr;
+    void* mem_apool = nullptr;
     bool dead = false;            // set after a device failure
 };
 
@@ -63,6 +64,12 @@ void gv_noalloc_query(gv_graph* g, const uint32_t* d_src, const uint32_t* d_dst,
                       uint8_t* d_out);
 
 namespace gv {
+
+// attributes of pairs (a query batch that also finds their slots): get
+// (found flags to `found`, n * A words to `out`, zeros when absent) or set
+// (`in`, n * A words; for each stored pair its last occurrence writes)
+void edge_attrs(gv_graph* g, const uint32_t* src, const uint32_t* dst, uint64_t n,
+                uint8_t* found, uint32_t* out, const uint32_t* in);
 
 // a list of (op, src, dst) entries, op 0 insert / 1 delete, applied as if one
 // at a time in list order (last-writer reduction, then one delete batch and

@@ -492,7 +492,11 @@ __global__ __launch_bounds__(kThreads) void k_vd_fill(GraphView g, VDel d) {
             for (uint32_t p = nd; p < r.deg; ++p) {
                 const uint32_t x = g.pool[slot_addr(g, r, p)];
                 if (bit_of(d.gone, x)) continue;
-                if (k < nh) g.pool[slot_addr(g, r, d.holes[off + k])] = x;
+                if (k < nh) {
+                    const uint64_t da = slot_addr(g, r, d.holes[off + k]);
+                    g.pool[da] = x;
+                    if (g.A) attr_move(g, da, slot_addr(g, r, p));
+                }
                 ++k;
             }
             if (k != nh) vd_error(g);
@@ -530,7 +534,11 @@ __global__ __launch_bounds__(kThreads) void k_vd_fill(GraphView g, VDel d) {
                 }
                 const uint64_t km = ballot(keep);
                 const uint32_t kk = k + rank_below(km);
-                if (keep && kk < wnh) g.pool[slot_addr(g, w, d.holes[woff + kk])] = x;
+                if (keep && kk < wnh) {
+                    const uint64_t da = slot_addr(g, w, d.holes[woff + kk]);
+                    g.pool[da] = x;
+                    if (g.A) attr_move(g, da, slot_addr(g, w, p));
+                }
                 k += popc64(km);
             }
             if (k != wnh && lane == 0) vd_error(g);

@@ -26,7 +26,8 @@ GV_OK, GV_EINVAL, GV_ERANGE, GV_ENOMEM, GV_EDEVICE = 0, 1, 2, 3, 4
 class gv_config(C.Structure):
     _fields_ = [("block_slots", C.c_uint32), ("flags", C.c_uint32),
                 ("pool_bytes", C.c_uint64), ("vertex_capacity", C.c_uint64),
-                ("directory_entries", C.c_uint64)]
+                ("directory_entries", C.c_uint64), ("edge_attr_words", C.c_uint32),
+                ("reserved", C.c_uint32)]
 
 
 class gv_batch_stats(C.Structure):
@@ -104,6 +105,8 @@ def lib():
             "gv_delete_vertices": [vp, u32p, C.c_uint64, C.POINTER(gv_batch_stats)],
             "gv_edge_exists": [vp, u32p, u32p, C.c_uint64, vp],
             "gv_apply_edge_ops": [vp, vp, u32p, u32p, C.c_uint64],
+            "gv_set_edge_attrs": [vp, u32p, u32p, u32p, C.c_uint64, vp],
+            "gv_get_edge_attrs": [vp, u32p, u32p, C.c_uint64, vp, u32p],
             "gv_apply_edge_ops_stats": [vp, vp, u32p, u32p, C.c_uint64, vp, C.c_uint64, vp],
             "gv_get_adjacency": [vp, C.c_uint32, u32p, C.c_uint64, u64p],
             "gv_memory_used": [vp, C.POINTER(gv_mem)],
@@ -191,14 +194,14 @@ def _ptr(t):
 
 # ------------------------------------------------------------------ C names
 def gv_graph_init(num_vertices, src, dst, block_slots=0, pool_bytes=0, vertex_capacity=0,
-                  directory_entries=0, device="cuda:0"):
+                  directory_entries=0, device="cuda:0", edge_attr_words=0):
     """Returns an opaque graph handle (int).  See gv_graph_init in graphvine.h."""
     s = as_device_u32(src, device)
     d = as_device_u32(dst, device)
     if s.numel() != d.numel():
         raise ValueError("src/dst length mismatch")
     cfg = gv_config(int(block_slots), 0, int(pool_bytes), int(vertex_capacity),
-                    int(directory_entries))
+                    int(directory_entries), int(edge_attr_words), 0)
     h = C.c_void_p()
     with torch.cuda.device(torch.device(device)):
         rc = lib().gv_graph_init(C.byref(h), int(num_vertices), _ptr(s), _ptr(d), s.numel(),
@@ -298,6 +301,33 @@ def gv_apply_edge_ops_stats(g, op, src, dst, req_end, device="cuda:0", stats=Non
                                          _ptr(e), e.numel(), _ptr(stats)),
            "gv_apply_edge_ops_stats")
     return (o, s, d, e), stats
+
+
+def gv_set_edge_attrs(g, src, dst, attr, device="cuda:0", stats=True):
+    """attr: n x A uint32 (rows per pair).  Returns stats if requested."""
+    s = as_device_u32(src, device)
+    d = as_device_u32(dst, device)
+    a = as_device_u32(np.asarray(attr, np.uint32).reshape(-1) if not torch.is_tensor(attr)
+                      else attr.reshape(-1), device)
+    if s.numel() != d.numel():
+        raise ValueError("src/dst length mismatch")
+    st = gv_batch_stats()
+    _check(lib().gv_set_edge_attrs(C.c_void_p(g), _ptr(s), _ptr(d), _ptr(a), s.numel(),
+                                   C.byref(st) if stats else None), "gv_set_edge_attrs")
+    return st.as_tuple() if stats else (s, d, a)
+
+
+def gv_get_edge_attrs(g, src, dst, words, device="cuda:0"):
+    """Returns (found uint8 [n], attrs int32 [n, words]) device tensors."""
+    s = as_device_u32(src, device)
+    d = as_device_u32(dst, device)
+    if s.numel() != d.numel():
+        raise ValueError("src/dst length mismatch")
+    found = torch.empty(max(s.numel(), 1), dtype=torch.uint8, device=device)
+    out = torch.empty((max(s.numel(), 1), max(words, 1)), dtype=torch.int32, device=device)
+    _check(lib().gv_get_edge_attrs(C.c_void_p(g), _ptr(s), _ptr(d), s.numel(), _ptr(found),
+                                   _ptr(out)), "gv_get_edge_attrs")
+    return found[: s.numel()], out[: s.numel()]
 
 
 def gv_get_adjacency(g, v, device="cuda:0", out=None):
@@ -430,10 +460,11 @@ class Graph:
     """Owning wrapper over a gv_graph handle on one GPU."""
 
     def __init__(self, num_vertices, src=(), dst=(), block_slots=16, pool_bytes=0,
-                 vertex_capacity=0, directory_entries=0, device="cuda:0"):
+                 vertex_capacity=0, directory_entries=0, device="cuda:0", edge_attr_words=0):
         self.device = torch.device(device)
+        self.attr_words = int(edge_attr_words)
         self.h = gv_graph_init(num_vertices, src, dst, block_slots, pool_bytes, vertex_capacity,
-                               directory_entries, self.device)
+                               directory_entries, self.device, edge_attr_words)
 
     def close(self):
         if getattr(self, "h", None):
@@ -463,6 +494,12 @@ class Graph:
 
     def apply_edge_ops(self, op, src, dst):
         return gv_apply_edge_ops(self.h, op, src, dst, self.device)
+
+    def set_edge_attrs(self, src, dst, attr, stats=True):
+        return gv_set_edge_attrs(self.h, src, dst, attr, self.device, stats)
+
+    def get_edge_attrs(self, src, dst):
+        return gv_get_edge_attrs(self.h, src, dst, self.attr_words, self.device)
 
     def apply_edge_ops_stats(self, op, src, dst, req_end):
         return gv_apply_edge_ops_stats(self.h, op, src, dst, req_end, self.device)

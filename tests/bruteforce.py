@@ -45,7 +45,53 @@ class BruteGraph:
         self.A[src, dst] = True
         assert block_slots > 0
         self.B = block_slots
+        self.pool_bytes = pool_bytes
         self.pool_blocks = pool_bytes // (4 * block_slots) if pool_bytes else 0
+        self.W = None  # attribute words per (src, dst), when enabled
+
+    def set_attr_words(self, words):
+        self.W = np.zeros((self.cap, self.cap, words), dtype=np.uint32)
+
+    def set_block_slots(self, block_slots):
+        pool = self.pool_bytes // (4 * block_slots) if self.pool_bytes else 0
+        need = int(sum(ceil_div(int(x), block_slots) for x in self.A.sum(axis=1)))
+        if pool and need > pool:
+            return 3
+        self.B, self.pool_blocks = block_slots, pool
+        return 0
+
+    def adapted_block_slots(self):
+        deg = self.A.sum(axis=1)
+        nz = int((deg > 0).sum())
+        if nz == 0:
+            return 8
+        return max(8, min(64, pow2_at_least(ceil_div(int(deg.sum()), nz))))
+
+    def set_edge_attrs(self, src, dst, vals):
+        src = np.asarray(src, np.int64)
+        dst = np.asarray(dst, np.int64)
+        vals = np.asarray(vals, np.uint32).reshape(len(src), -1)
+        inb = (src < self.cap) & (dst < self.cap)
+        ok = np.zeros(len(src), dtype=bool)
+        ok[inb] = self.active[src[inb]] & self.active[dst[inb]]
+        idx = np.nonzero(ok)[0]
+        code = src[idx] * self.cap + dst[idx]
+        # the last row of each pair: first occurrence in the reversed order
+        _, first_rev = np.unique(code[::-1], return_index=True)
+        last = idx[::-1][first_rev]
+        stored = self.A[src[last], dst[last]]
+        keep = last[stored]
+        self.W[src[keep], dst[keep]] = vals[keep]
+        return 0, (int(stored.sum()), int((~ok).sum()), len(idx) - len(last))
+
+    def get_edge_attrs(self, src, dst):
+        found = self.edge_exists(src, dst)
+        src = np.asarray(src, np.int64)
+        dst = np.asarray(dst, np.int64)
+        out = np.zeros((len(src), self.W.shape[2]), dtype=np.uint32)
+        f = found.astype(bool)
+        out[f] = self.W[src[f], dst[f]]
+        return found, out
 
     # ---- helpers -------------------------------------------------------
     def _grow(self, cap):
@@ -53,6 +99,10 @@ class BruteGraph:
             return
         A = np.zeros((cap, cap), dtype=bool)
         A[: self.cap, : self.cap] = self.A
+        if self.W is not None:
+            W = np.zeros((cap, cap, self.W.shape[2]), dtype=np.uint32)
+            W[: self.cap, : self.cap] = self.W
+            self.W = W
         act = np.zeros(cap, dtype=bool)
         act[: self.cap] = self.active
         self.A, self.active, self.cap = A, act, cap
@@ -81,12 +131,16 @@ class BruteGraph:
             if need > self.pool_blocks:
                 return 3, (0, 0, 0)
         self.A[s[new], d[new]] = True
+        if self.W is not None:
+            self.W[s[new], d[new]] = 0
         return 0, (int(new.sum()), rej, dup)
 
     def delete_edges(self, src, dst):
         rej, dup, s, d = self._valid_pairs(src, dst)
         hit = self.A[s, d]
         self.A[s[hit], d[hit]] = False
+        if self.W is not None:
+            self.W[s[hit], d[hit]] = 0
         return 0, (int(hit.sum()), rej, dup)
 
     def insert_vertices(self, ids):
@@ -108,6 +162,9 @@ class BruteGraph:
         gone = u[self.active[u]]
         self.A[gone, :] = False
         self.A[:, gone] = False
+        if self.W is not None:
+            self.W[gone, :] = 0
+            self.W[:, gone] = 0
         self.active[gone] = False
         return 0, (len(gone), int((~ok).sum()), len(good) - len(u))
 

@@ -147,6 +147,79 @@ def test_oracle_matches_bitset_bruteforce(n, B, seed):
         np.testing.assert_array_equal(o.get_adjacency(v), b.get_adjacency(v))
 
 
+@pytest.mark.parametrize("n,B,words,seed", [(16, 1, 1, 11), (64, 4, 2, 12), (100, 16, 3, 13)])
+def test_oracle_attributes_match_bruteforce(n, B, words, seed):
+    """Edge attributes (Sec. 4.1 entries with attributes, our reading of their
+    update rules): zeros for a new edge, gone with the edge, the last row of
+    a pair in a set batch wins; pinned against the dense model."""
+    rng = np.random.default_rng(seed)
+    m = 4 * n
+    s = rng.integers(0, n, m).astype(np.uint32)
+    d = rng.integers(0, n, m).astype(np.uint32)
+    o = O.OracleGraph(n, s, d, block_slots=B)
+    b = BruteGraph(n, s, d, block_slots=B)
+    o.set_attr_words(words)
+    b.set_attr_words(words)
+    every_s = np.repeat(np.arange(o.capacity, dtype=np.uint32), o.capacity)
+    every_d = np.tile(np.arange(o.capacity, dtype=np.uint32), o.capacity)
+    for kind, x, y in _random_ops(rng, n, 40):
+        if kind == "ins":
+            assert o.insert_edges(x, y) == b.insert_edges(x, y)
+        elif kind == "del":
+            assert o.delete_edges(x, y) == b.delete_edges(x, y)
+        elif kind == "vins":
+            assert o.insert_vertices(x) == b.insert_vertices(x)
+            every_s = np.repeat(np.arange(o.capacity, dtype=np.uint32), o.capacity)
+            every_d = np.tile(np.arange(o.capacity, dtype=np.uint32), o.capacity)
+        elif kind == "vdel":
+            assert o.delete_vertices(x) == b.delete_vertices(x)
+        else:
+            # a set batch over these pairs plus some stored ones, repeats included
+            vals = rng.integers(0, 1 << 32, (len(x), words), dtype=np.uint64).astype(np.uint32)
+            assert o.set_edge_attrs(x, y, vals) == b.set_edge_attrs(x, y, vals)
+        fo, vo = o.get_edge_attrs(every_s, every_d)
+        fb, vb = b.get_edge_attrs(every_s, every_d)
+        np.testing.assert_array_equal(fo, fb)
+        np.testing.assert_array_equal(vo, vb)
+        _compare(o, b)
+
+
+def test_oracle_attribute_rules_worked_example():
+    o = O.OracleGraph(4, [0, 0, 1], [1, 2, 2], block_slots=2)
+    o.set_attr_words(1)
+    assert o.get_edge_attrs([0, 1, 3], [1, 2, 0])[1].ravel().tolist() == [0, 0, 0]
+    # the later row of a repeated pair wins; an absent pair changes nothing
+    assert o.set_edge_attrs([0, 0, 1, 3], [1, 1, 2, 3], [[5], [7], [9], [4]]) == (0, (2, 0, 1))
+    f, v = o.get_edge_attrs([0, 1, 3], [1, 2, 3])
+    assert f.tolist() == [1, 1, 0] and v.ravel().tolist() == [7, 9, 0]
+    # delete and re-insert: the words start again at zero
+    o.delete_edges([0], [1])
+    o.insert_edges([0], [1])
+    assert o.get_edge_attrs([0], [1])[1].ravel().tolist() == [0]
+    # a deleted vertex takes its in-edges' words with it
+    o.delete_vertices([2])
+    assert o.get_edge_attrs([1], [2])[0].tolist() == [0]
+
+
+@pytest.mark.parametrize("seed", [21, 22])
+def test_oracle_block_size_change_matches_bruteforce(seed):
+    """Sec. 6 future scope: a new block size over the same edges; the rule of
+    Sec. 4.3 applied to the current graph."""
+    rng = np.random.default_rng(seed)
+    n = 64
+    s = rng.integers(0, n, 300).astype(np.uint32)
+    d = rng.integers(0, n, 300).astype(np.uint32)
+    o = O.OracleGraph(n, s, d, block_slots=4, pool_bytes=4 * 4 * 120)
+    b = BruteGraph(n, s, d, block_slots=4, pool_bytes=4 * 4 * 120)
+    for B in (8, 1, 64, 2, 16):
+        assert (o.set_block_slots(B) == 0) == (b.set_block_slots(B) == 0)
+        _compare(o, b)
+        assert o.adapted_block_slots() == b.adapted_block_slots()
+    # a dense graph asks for larger blocks than a sparse one
+    dense = O.OracleGraph(32, np.repeat(np.arange(32), 31), (np.arange(32 * 31) % 32))
+    assert dense.adapted_block_slots() == 32
+
+
 def test_oracle_pool_exhaustion_matches_bruteforce():
     rng = np.random.default_rng(11)
     n, B = 32, 4
