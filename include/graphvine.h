@@ -168,6 +168,21 @@ int gv_insert_vertices(gv_graph* g, const uint32_t* d_ids, uint64_t n,
 int gv_delete_vertices(gv_graph* g, const uint32_t* d_ids, uint64_t n,
                        gv_batch_stats* stats_or_null);
 
+/* Block size over the graph's life (Sec. 6, future scope: the block size
+ * may follow the graph as its average degree changes, against internal
+ * fragmentation).  gv_set_block_slots re-lays the same edges (and their
+ * attribute words) in blocks of block_slots slots (a power of two in
+ * [1, 1024]) within the pool's byte budget; gv_adapt_block_slots first takes
+ * the rule of Sec. 4.3 on the graph as it is now (average degree of the
+ * vertices of non-zero degree, a power of two within [8, 64]) and reports
+ * the size it chose.  Synchronous; vertex capacity and activity are kept;
+ * plans recorded before become invalid (gv_plan_launch: GV_EINVAL).
+ * GV_ENOMEM, graph unchanged, when the edges do not fit the pool with the
+ * new size; a device allocation failure during the rebuild leaves the graph
+ * unusable.  Graphs of 2^30 or more edges: GV_EINVAL. */
+int gv_set_block_slots(gv_graph* g, uint32_t block_slots);
+int gv_adapt_block_slots(gv_graph* g, uint32_t* block_slots);
+
 /* Edge attributes (Sec. 4.1: an edge entry may carry attributes), for
  * graphs created with gv_config.edge_attr_words = A > 0 (else GV_EINVAL).
  * An entry's A uint32 words live at its slot and move with it; a newly

@@ -228,6 +228,20 @@ int gv_edge_exists_noalloc(gv_graph* g, const uint32_t* d_src, const uint32_t* d
     return guarded(g, [&] { gv_noalloc_query(g, d_src, d_dst, n, d_out); });
 }
 
+int gv_set_block_slots(gv_graph* g, uint32_t block_slots) {
+    if (!g || block_slots == 0 || block_slots > 1024 || !pow2(block_slots)) return GV_EINVAL;
+    return guarded(g, [&] { relayout(g, block_slots); });
+}
+
+int gv_adapt_block_slots(gv_graph* g, uint32_t* block_slots) {
+    if (!g || !block_slots) return GV_EINVAL;
+    return guarded(g, [&] {
+        const uint32_t b = adapted_block_slots(g);
+        relayout(g, b);
+        *block_slots = b;
+    });
+}
+
 int gv_set_edge_attrs(gv_graph* g, const uint32_t* d_src, const uint32_t* d_dst,
                       const uint32_t* d_attr, uint64_t n, gv_batch_stats* st) {
     if (st) std::memset(st, 0, sizeof(*st));

@@ -549,3 +549,129 @@ uint64_t audit(gv_graph* g) {
 }
 
 }  // namespace gv
+
+namespace gv {
+
+// ------------------------------------------------------------------ block size
+// blocks the adjacencies would hold with 2^lb slots per block (low half) and
+// vertices of non-zero degree (high half), one atomic per workgroup
+__global__ __launch_bounds__(kThreads) void k_layout_count(GraphView g, uint32_t lb,
+                                                           unsigned long long* out) {
+    __shared__ unsigned long long lds[kWaves];
+    const uint64_t v = tidx();
+    unsigned long long blocks = 0, nz = 0;
+    if (v < g.n_cap && is_active(g, v)) {
+        const uint32_t d = g.vt[v].deg;
+        blocks = ((uint64_t)d + (1ull << lb) - 1) >> lb;
+        nz = d > 0;
+    }
+    blocks = block_sum(blocks, lds);
+    nz = block_sum(nz, lds);
+    if (threadIdx.x == 0 && (blocks | nz)) atomicAdd(out, blocks | (nz << 32));
+}
+
+// source of every dumped edge: the vertex whose CSR range holds it
+__global__ __launch_bounds__(kThreads) void k_layout_src(const unsigned long long* offs,
+                                                         uint64_t ncap, uint64_t m,
+                                                         uint32_t* src) {
+    const uint64_t i = tidx();
+    if (i >= m) return;
+    uint64_t lo = 0, hi = ncap;  // last v with offs[v] <= i
+    while (hi - lo > 1) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (offs[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    src[i] = (uint32_t)lo;
+}
+
+namespace {
+
+// (blocks with 2^lb slots, vertices of non-zero degree)
+std::pair<uint64_t, uint64_t> layout_count(gv_graph* g, uint32_t lb) {
+    const GraphView& v = g->v;
+    set_u64(g, &v.ctr->checksum, 0);
+    g->ctx.launch("relayout", k_layout_count, div_up(v.n_cap, kThreads), kThreads, v, lb,
+                  &v.ctr->checksum);
+    read_counters(g);
+    const unsigned long long x = g->hctr->checksum;
+    return {x & 0xffffffffull, x >> 32};
+}
+
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf() {
+        if (p) hipFree(p);
+    }
+    template <typename T>
+    T* get(size_t count) {
+        hip_check(hipMalloc(&p, std::max<size_t>(count * sizeof(T), 8)), "hipMalloc relayout");
+        return (T*)p;
+    }
+};
+
+}  // namespace
+
+uint32_t adapted_block_slots(gv_graph* g) {
+    read_counters(g);
+    const uint64_t edges = g->hctr->live_edges;
+    const uint64_t nonzero = layout_count(g, 0).second;
+    return paper_block_rule(edges, nonzero);
+}
+
+// The same edges (and attribute words) in blocks of block_slots slots: dump,
+// rebuild with the pool's byte budget, restore the activity bitmap, write the
+// words back.  Checks first that the new layout fits, so that a graph that
+// would not fit stays as it is (GV_ENOMEM).
+void relayout(gv_graph* g, uint32_t block_slots) {
+    Ctx& c = g->ctx;
+    GraphView& v = g->v;
+    if (block_slots == v.B) return;
+    read_counters(g);
+    // a rebuild clears the error words: report a pending one first
+    if (g->hctr->err_sticky) fail((int)g->hctr->err_sticky, "an earlier batch failed");
+    const uint64_t m = g->hctr->live_edges;
+    if (m >= kOsMaxKeys) fail(GV_EINVAL, "2^30 or more edges");
+    const uint64_t budget = v.cap_blocks * v.B * 4ull;
+    const uint64_t cap_new = std::min<uint64_t>(budget / (4ull * block_slots), 0xfffffff0ull);
+    if (layout_count(g, log2_exact(block_slots)).first > cap_new)
+        fail(GV_ENOMEM, "the graph does not fit the pool with that block size");
+    const uint64_t words = (v.n_cap + 31) / 32;
+    DevBuf b_offs, b_dst, b_src, b_attr, b_found, b_act;
+    auto* offs = b_offs.get<uint64_t>(v.n_cap + 1);
+    auto* dst = b_dst.get<uint32_t>(m);
+    auto* src = b_src.get<uint32_t>(m);
+    auto* act = b_act.get<uint32_t>(words);
+    uint32_t* attr = v.A ? b_attr.get<uint32_t>(m * v.A) : nullptr;
+    uint64_t ck = 0, e = 0;
+    dump(g, offs, dst, m, &ck, &e);
+    if (e != m) fail(GV_EDEVICE, "edge count changed during a relayout");
+    if (m)
+        c.launch("relayout", k_layout_src, div_up(m, kThreads), kThreads,
+                 (const unsigned long long*)offs, (uint64_t)v.n_cap, m, src);
+    if (attr && m) edge_attrs(g, src, dst, m, b_found.get<uint8_t>(m), attr, nullptr);
+    hip_check(hipMemcpyAsync(act, v.active, words * 4, hipMemcpyDeviceToDevice, c.stream),
+              "hipMemcpyAsync");
+    hip_check(hipStreamSynchronize(c.stream), "hipStreamSynchronize");
+    // from here the old layout is gone: a failure leaves the graph unusable
+    g->dead = true;
+    for (void** p : {&g->mem_pool, &g->mem_free, &g->mem_dir, &g->mem_dfree, &g->mem_bown,
+                     &g->mem_apool}) {
+        if (*p) hipFree(*p);
+        *p = nullptr;
+    }
+    gv_config cfg{};
+    cfg.block_slots = block_slots;
+    cfg.pool_bytes = budget;
+    cfg.vertex_capacity = v.n_cap;
+    cfg.edge_attr_words = v.A;
+    bulk_build(g, v.n_cap, src, dst, m, cfg);
+    hip_check(hipMemcpyAsync(v.active, act, words * 4, hipMemcpyDeviceToDevice, c.stream),
+              "hipMemcpyAsync");
+    if (attr && m) edge_attrs(g, src, dst, m, nullptr, nullptr, attr);
+    hip_check(hipStreamSynchronize(c.stream), "hipStreamSynchronize");
+    g->dead = false;
+    ++g->table_gen;  // recorded plans hold the old layout
+}
+
+}  // namespace gv

@@ -14,7 +14,7 @@ struct gv_graph {
     gv::Scratch vscr[3];          // vertex-batch buffers that outlive an inner edge batch
     gv::Scratch cscr;             // a coalesced run of edge batches (batched form)
     gv_tuning tune{0u, 0u, 4096u, {0u, 0u, 0u, 0u, 0u}};
-    uint64_t table_gen = 0;       // counts vertex-table reallocations
+    uint64_t table_gen = 0;       // counts reallocations of the vertex table or the pool
     uint64_t item_slots = 0;      // bound on live adjacency slots (pool slots)
     uint32_t spin_limit = gv::kSpinLimitDefault;  // bound on each look-back wait of batch sorts
     // device allocations owned by the graph
@@ -105,6 +105,10 @@ void vertex_delete(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats*
                    uint64_t edge_bound = 0);
 
 void adjacency(gv_graph* g, uint32_t v, uint32_t* out, uint64_t cap, uint64_t* degree);
+// the block size the rule of Sec. 4.3 gives for the graph as it is now, and
+// the same graph re-laid in blocks of another size (Sec. 6), synchronous
+uint32_t adapted_block_slots(gv_graph* g);
+void relayout(gv_graph* g, uint32_t block_slots);
 void dump(gv_graph* g, uint64_t* offsets, uint32_t* dst, uint64_t cap, uint64_t* checksum,
           uint64_t* edges);
 uint64_t audit(gv_graph* g);

@@ -106,6 +106,8 @@ def lib():
             "gv_edge_exists": [vp, u32p, u32p, C.c_uint64, vp],
             "gv_apply_edge_ops": [vp, vp, u32p, u32p, C.c_uint64],
             "gv_set_edge_attrs": [vp, u32p, u32p, u32p, C.c_uint64, vp],
+            "gv_set_block_slots": [vp, C.c_uint32],
+            "gv_adapt_block_slots": [vp, C.POINTER(C.c_uint32)],
             "gv_get_edge_attrs": [vp, u32p, u32p, C.c_uint64, vp, u32p],
             "gv_apply_edge_ops_stats": [vp, vp, u32p, u32p, C.c_uint64, vp, C.c_uint64, vp],
             "gv_get_adjacency": [vp, C.c_uint32, u32p, C.c_uint64, u64p],
@@ -494,6 +496,16 @@ class Graph:
 
     def apply_edge_ops(self, op, src, dst):
         return gv_apply_edge_ops(self.h, op, src, dst, self.device)
+
+    def set_block_slots(self, block_slots):
+        _check(lib().gv_set_block_slots(C.c_void_p(self.h), int(block_slots)),
+               "gv_set_block_slots")
+
+    def adapt_block_slots(self):
+        b = C.c_uint32()
+        _check(lib().gv_adapt_block_slots(C.c_void_p(self.h), C.byref(b)),
+               "gv_adapt_block_slots")
+        return b.value
 
     def set_edge_attrs(self, src, dst, attr, stats=True):
         return gv_set_edge_attrs(self.h, src, dst, attr, self.device, stats)

@@ -138,3 +138,59 @@ def test_attributes_follow_entries_at_rmat16():
         say(f"round {r}: {int(old.sum())} moved or kept entries checked")
     assert g.sync() == 0
     g.close()
+
+
+def test_block_size_changes_keep_edges_words_and_activity():
+    """The block size re-laid over the graph's life (gv_set_block_slots,
+    gv_adapt_block_slots) against the oracle: same edges, block accounting
+    at the new size, attribute words and inactive vertices kept, plans made
+    invalid, a size that does not fit the pool refused with the graph as it
+    was."""
+    gv = need_gpu()
+    n, A = 2000, 2
+    s0, d0 = I.uniform_pairs(I.stream_seed("relayout"), 9000, n)
+    s0[:3000] = 7
+    pool = 4 * 16 * 2400
+    g = gv.Graph(n, s0, d0, block_slots=16, vertex_capacity=n, pool_bytes=pool,
+                 edge_attr_words=A)
+    o = O.OracleGraph(n, s0, d0, block_slots=16, vertex_capacity=n, pool_bytes=pool)
+    o.set_attr_words(A)
+    dead = np.arange(100, 140, dtype=np.uint32)
+    assert g.delete_vertices(dead) == o.delete_vertices(dead)[1]
+    es, ed = all_edges(g)
+    g.set_edge_attrs(es, ed, mix_words(es, ed, A))
+    o.set_edge_attrs(es, ed, mix_words(es, ed, A))
+    plan = gv.Plan(g.h, [(0, np.array([1], np.uint32), np.array([2], np.uint32))])
+    for B in (4, 1, 16):
+        say(f"relayout to B={B}")
+        g.set_block_slots(B)
+        assert o.set_block_slots(B) == 0
+        assert_same(g, o, f"B={B}")
+        assert g.info()["block_slots"] == B
+        f, v = g.get_edge_attrs(es, ed)
+        fo, vo = o.get_edge_attrs(es, ed)
+        np.testing.assert_array_equal(f.cpu().numpy(), fo)
+        np.testing.assert_array_equal(u32(v).reshape(len(es), A), vo)
+        # the deleted vertices stay inactive: their pairs are rejected
+        st = g.insert_edges(dead[:5], dead[5:10])
+        assert st == o.insert_edges(dead[:5], dead[5:10])[1] and st[1] == 5
+        s, d = I.uniform_pairs(I.stream_seed("relayout-ins", B), 3000, n)
+        assert g.insert_edges(s, d) == o.insert_edges(s, d)[1]
+        assert g.delete_edges(s[::2], d[::2]) == o.delete_edges(s[::2], d[::2])[1]
+        assert_same(g, o, f"after batches at B={B}")
+    with pytest.raises(gv.GraphVineError) as e:
+        plan.launch()
+    assert e.value.code == gv.GV_EINVAL
+    plan.close()
+    b = g.adapt_block_slots()
+    assert b == o.adapted_block_slots()
+    assert o.set_block_slots(b) == 0
+    assert_same(g, o, "adapted")
+    # blocks of 1024 slots: 2000 vertices' worth does not fit the budget
+    with pytest.raises(gv.GraphVineError) as e:
+        g.set_block_slots(1024)
+    assert e.value.code == gv.GV_ENOMEM
+    assert o.set_block_slots(1024) != 0
+    assert_same(g, o, "refused")
+    assert g.sync() == 0
+    g.close()
