@@ -456,8 +456,8 @@ def batched_form(gv, I, T, dev, scale=22, edges=1 << 26, nbatch=256, seed_name="
     else:
         best, points = stored["setting"], stored["measured_ms"]
         source = "tuning.json"
-    knobs = {k: best[k] for k in ("coalesce", "max_run_pairs", "small_sort_max")}
-    base = {"coalesce": 0, "max_run_pairs": 0, "small_sort_max": 4096}
+    knobs = {k: v for k, v in best.items() if k != "block_slots"}
+    base = dict({"coalesce": 0, "max_run_pairs": 0, "small_sort_max": 4096}, **Tu.DEFAULT_PROBE)
     el_base, want = Tu.measure(gv, w, ops, dev, 16, base, warm, "eager")
     el_eager, got_e = Tu.measure(gv, w, ops, dev, best["block_slots"], knobs, warm, "eager")
     el_plan, got_p = Tu.measure(gv, w, ops, dev, best["block_slots"], knobs, warm, "plan")
@@ -675,6 +675,14 @@ def main():
     init_s = time.perf_counter() - t0
     log(f"init {init_s * 1e3:.2f} ms")
 
+    # the step's tuning (probe shape, work-item size) stored by the tuner for
+    # this workload, if any
+    from paper_2306_08252_amd import tuner as Tu
+    step_tuning = Tu.load(Tu.steps_key(args.scale, args.edges, k, B))
+    if step_tuning:
+        gv.gv_set_tuning(g.h, **step_tuning["setting"])
+    step_setting = dict(gv.gv_get_tuning(g.h),
+                        source="tuning.json" if step_tuning else "defaults")
     h = g.h
     for j in range(args.warmup):
         gv.gv_insert_edges(h, *ins[j], dev, stats=False)
@@ -869,7 +877,8 @@ def main():
         "data": "synthetic (seeded R-MAT, drawn on the GPU)",
         "config": {"workload": f"rmat{args.scale} {args.edges} edges, B={B}, insert+delete "
                                f"batches of {k}", "vertices": n, "edges": args.edges,
-                   "batch": k, "block_slots": B},
+                   "batch": k, "block_slots": B,
+                   "tuning": step_setting},
         "pct_hbm_m1": round(pct_m1, 5),
         "m1_bytes_per_step": int(m1 / K),
         "init_edges_per_s": round(args.edges / init_s, 1),

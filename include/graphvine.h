@@ -322,7 +322,8 @@ typedef struct {
 /* Tuning of one graph's batch paths.  The batched form's autotuner
  * (paper_2306_08252_amd/tuner.py) measures the settings per workload and
  * stores them in tuning.json; the binding applies them before creating a
- * plan.  Defaults: coalesce 0, max_run_pairs 0, small_sort_max 4096.
+ * plan.  Defaults: coalesce 0, max_run_pairs 0, small_sort_max 4096,
+ * probe_group 32, probe_unroll 4, item_chunk 256.
  *   coalesce       gv_apply_ops and gv_plan_create apply every run of
  *                  consecutive edge batches (up to the next vertex batch) as
  *                  one mixed list (gv_apply_edge_ops): the same result as the
@@ -333,12 +334,21 @@ typedef struct {
  *   max_run_pairs  longest run coalesced, in pairs (0: 2^28; a batch
  *                  longer than the limit runs alone)
  *   small_sort_max insert / delete batches of at most this many pairs
- *                  (<= 4096) are packed and sorted by one workgroup */
+ *                  (<= 4096) are packed and sorted by one workgroup
+ *   probe_group    lanes that probe one work item against its batch
+ *                  segment: 16, 32 (default) or 64
+ *   probe_unroll   adjacency slots per lane per search step: 2, 4 (default)
+ *                  or 8
+ *   item_chunk     adjacency slots per work item, a power of two in
+ *                  [64, 4096] (default 256) */
 typedef struct {
     uint32_t coalesce;
     uint32_t max_run_pairs;
     uint32_t small_sort_max;
-    uint32_t reserved[5];
+    uint32_t probe_group;
+    uint32_t probe_unroll;
+    uint32_t item_chunk;
+    uint32_t reserved[2];
 } gv_tuning;
 int gv_set_tuning(gv_graph* g, const gv_tuning* t);
 int gv_get_tuning(gv_graph* g, gv_tuning* t);

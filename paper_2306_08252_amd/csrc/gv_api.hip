@@ -432,6 +432,8 @@ int gv_kernel_names(gv_graph* g, char* buf, size_t cap, size_t* needed) {
 int gv_set_tuning(gv_graph* g, const gv_tuning* t) {
     if (!g || !t) return GV_EINVAL;
     if (t->coalesce > 1 || t->small_sort_max > 4096) return GV_EINVAL;
+    if (!probe_shape_ok(t->probe_group, t->probe_unroll)) return GV_EINVAL;
+    if (t->item_chunk < 64 || t->item_chunk > 4096 || !pow2(t->item_chunk)) return GV_EINVAL;
     return guarded(g, [&] {
         hip_check(hipStreamSynchronize(g->ctx.stream), "hipStreamSynchronize");
         g->tune = *t;

@@ -249,7 +249,7 @@ int gv_plan_create(gv_graph* g, const gv_op* ops, uint64_t n_ops, gv_plan** out)
         for (int k = 0; k < 3; ++k) g->vscr[k].ensure(std::max<size_t>(vs[k], 4), c.stream);
         g->cscr.ensure(std::max<size_t>(csz, 4), c.stream);
         hip_check(hipStreamSynchronize(c.stream), "hipStreamSynchronize");
-        edge_batch_warm();
+        edge_batch_warm(g);
         vertex_batch_warm();
         // record
         hipStream_t cs = nullptr;

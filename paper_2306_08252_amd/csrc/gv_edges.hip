@@ -17,7 +17,7 @@
 //             sources T and their segment starts; first occurrences give the
 //             distinct pairs.
 //   items     scan over T: each touched adjacency is cut into work items of
-//             kChunk slots, written as self-contained 32-byte descriptors
+//             `chunk` slots, written as self-contained 32-byte descriptors
 //             (slot range, batch segment, block directory); a source with a
 //             single small block and a short segment becomes one small item.
 //   probe     small items one per lane (slots and segment loaded whole, all
@@ -40,6 +40,7 @@
 //             (reclamation, Sec. 4.2).
 //   query:    answers are scattered back to input order.
 #include <algorithm>
+#include <type_traits>
 
 #include "gv_graph.h"
 #include "gv_prim.h"
@@ -47,21 +48,12 @@
 namespace gv {
 
 constexpr uint8_t kHead = 1, kUniq = 2;
-#ifndef GV_PROBE_GROUP
-#define GV_PROBE_GROUP 32
-#endif
-#ifndef GV_PROBE_UNROLL
-#define GV_PROBE_UNROLL 4
-#endif
-constexpr int kGroup = GV_PROBE_GROUP;         // lanes per work item
-constexpr int kGroupsPerWave = 64 / kGroup;
-#ifndef GV_PROBE_STAGE_LOG
-#define GV_PROBE_STAGE_LOG 7
-#endif
-constexpr int kStageLog = GV_PROBE_STAGE_LOG;  // log2(kStage)
+// The probe's shape is picked at run time (gv_tuning) among compiled
+// variants: G lanes per work item (16, 32, 64) and U slots per lane per step
+// (2, 4, 8).
+constexpr int kStageLog = 7;                   // log2(kStage)
 constexpr int kStage = 1 << kStageLog;         // segment entries staged in LDS
 constexpr int kWinLog = 12;                    // unrolled global search steps
-constexpr int kUnroll = GV_PROBE_UNROLL;       // slots per lane per step
 constexpr uint32_t kBigR = 256;                // deletes per source handled by a workgroup
 constexpr uint32_t kBigGroups = 256;           // workgroups for those sources
 constexpr uint32_t kLaneCopy = 8;              // directory entries a lane copies or adds
@@ -520,6 +512,7 @@ struct ItemIn {
     GraphView g;
     const uint32_t* t_vtx;
     const uint32_t* t_start;
+    uint32_t chunk;  // adjacency slots per work item
     using Rec = TouchRec;
     __device__ uint64_t limit(uint64_t n) const {
         return batch_failed(g.ctr) ? 0ull : min((uint64_t)(uint32_t)g.ctr->tot[kTotSeg], n);
@@ -528,12 +521,12 @@ struct ItemIn {
     __device__ void deref(Rec& x) const { x.r = g.vt[x.v]; }
     __device__ unsigned long long value(uint64_t, const Rec& x) const {
         const unsigned long long items =
-            small_item(g.B, x.r.deg, x.hi - x.lo) ? 0ull : (x.r.deg + kChunk - 1) / kChunk;
+            small_item(g.B, x.r.deg, x.hi - x.lo) ? 0ull : (x.r.deg + chunk - 1) / chunk;
         return items | ((unsigned long long)nblocks(g, x.r.deg) << 32);
     }
 };
 
-// A source's work items: one per kChunk slots.  A lane writes up to
+// A source's work items: one per `chunk` slots.  A lane writes up to
 // kLaneItems of them; sources with more are written by all the lanes of the
 // wave that make the call, one item each per store.  The scan calls the sink
 // for elements below its size only, so in the last wave of a scan some lanes
@@ -545,12 +538,13 @@ struct ItemOut {
     Item* small;        // per touched source: its small item, or s1 = 0
     uint32_t B;
     uint64_t icap;      // capacity of items (the scan of distinct sources stays below it)
+    uint32_t chunk;     // adjacency slots per work item
     __device__ void operator()(uint64_t t, const TouchRec& x, uint64_t lim,
                                unsigned long long pre) const {
         const bool live = t < lim;
         const VRec r = x.r;
         const bool small = live && small_item(B, r.deg, x.hi - x.lo);
-        const uint32_t cnt = live && !small ? (r.deg + kChunk - 1) / kChunk : 0u;
+        const uint32_t cnt = live && !small ? (r.deg + chunk - 1) / chunk : 0u;
         const uint32_t base = (uint32_t)pre;
         Item it;
         it.lo = x.lo;
@@ -569,8 +563,8 @@ struct ItemOut {
         }
         if (cnt <= kLaneItems) {
             for (uint32_t c = 0; c < cnt; ++c) {
-                it.s0 = c * kChunk;
-                it.s1 = min(r.deg, it.s0 + kChunk);
+                it.s0 = c * chunk;
+                it.s1 = min(r.deg, it.s0 + chunk);
                 if (base + c < icap) items[base + c] = it;
             }
         }
@@ -590,8 +584,8 @@ struct ItemOut {
             const uint32_t wdeg = __shfl(r.deg, l, 64);
             const uint32_t wcnt = __shfl(cnt, l, 64), wbase = __shfl(base, l, 64);
             for (uint32_t c = me; c < wcnt; c += nact) {
-                w.s0 = c * kChunk;
-                w.s1 = min(wdeg, w.s0 + kChunk);
+                w.s0 = c * chunk;
+                w.s1 = min(wdeg, w.s0 + chunk);
                 if ((uint64_t)wbase + c < icap) items[wbase + c] = w;
             }
         }
@@ -599,72 +593,65 @@ struct ItemOut {
 };
 
 // ------------------------------------------------------------------ probe
-// Group-level helpers: a group is kGroup consecutive lanes of a wave.
-__device__ __forceinline__ uint64_t group_mask(uint64_t m, uint32_t lane) {
-    if (kGroup == 64) return m;
-    const uint32_t g0 = lane & ~(uint32_t)(kGroup - 1);
-    return (m >> g0) & ((1ull << (kGroup & 63)) - 1);
-}
-
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int MODE>
+template <int MODE, int G, int U>
 __device__ __forceinline__ void probe_load(const GraphView& g, const Item& I, const uint32_t* dp,
-                                           uint32_t s, uint32_t (&x)[kUnroll],
-                                           uint64_t (&addr)[kUnroll]) {
+                                           uint32_t s, uint32_t (&x)[U],
+                                           uint64_t (&addr)[U]) {
     // unconditional loads at clamped positions; lanes past the item are
     // masked out by the caller
-    uint32_t e[kUnroll];
+    uint32_t e[U];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-        const uint32_t si = min(s + u * kGroup, I.s1 - 1);
+    for (int u = 0; u < U; ++u) {
+        const uint32_t si = min(s + u * G, I.s1 - 1);
         e[u] = dp[si >> g.log2B];
     }
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-        const uint32_t si = min(s + u * kGroup, I.s1 - 1);
+    for (int u = 0; u < U; ++u) {
+        const uint32_t si = min(s + u * G, I.s1 - 1);
         addr[u] = ((uint64_t)e[u] << g.log2B) + (si & (g.B - 1));
     }
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) x[u] = g.pool[addr[u]];
+    for (int u = 0; u < U; ++u) x[u] = g.pool[addr[u]];
 }
 
-// Searches of the kUnroll slots of a lane run in lockstep, so that each step
-// issues kUnroll independent reads and waits once.
-template <int MODE>
+// Searches of the U slots of a lane run in lockstep, so that each step
+// issues U independent reads and waits once.
+template <int MODE, int G, int U>
 __device__ __forceinline__ void probe_search(const GraphView& g, const Item& I, uint32_t s,
-                                             const uint32_t (&x)[kUnroll],
-                                             const uint64_t (&addr)[kUnroll], const uint32_t* st,
+                                             const uint32_t (&x)[U],
+                                             const uint64_t (&addr)[U], const uint32_t* st,
                                              uint32_t steps, uint32_t shift, const uint64_t* keys,
                                              uint8_t* mark, uint32_t* hitpos) {
     const uint32_t len = I.hi - I.lo;
     const uint64_t vbase = (uint64_t)I.v << g.L;
     // rank among the LDS samples: st[0, 2^steps - 1) holds the sorted samples
     // padded with 0xFFFFFFFF (at least one pad entry, so the rank can reach ns)
-    uint32_t lo[kUnroll];
+    uint32_t lo[U];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) lo[u] = 0;
+    for (int u = 0; u < U; ++u) lo[u] = 0;
     // unrolled to the largest step count so that no loop carries outstanding
     // loads (the next step's slot loads stay in flight meanwhile)
 #pragma unroll
     for (int k = kStageLog - 1; k >= 0; --k) {
         if ((uint32_t)k >= steps) continue;
         const uint32_t half = 1u << k;
-        uint32_t sv[kUnroll];
+        uint32_t sv[U];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) sv[u] = st[lo[u] + half - 1];
+        for (int u = 0; u < U; ++u) sv[u] = st[lo[u] + half - 1];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) lo[u] += sv[u] < x[u] ? half : 0u;
+        for (int u = 0; u < U; ++u) lo[u] += sv[u] < x[u] ? half : 0u;
     }
-    uint32_t p[kUnroll];  // first segment position whose value is >= x
-    bool hit[kUnroll];
+    uint32_t p[U];  // first segment position whose value is >= x
+    bool hit[U];
     if (shift == 0) {
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < U; ++u) {
             p[u] = lo[u];
             const uint32_t v = st[lo[u]];  // lo <= ns < kStage
             hit[u] = (lo[u] < len) & (v == x[u]);
@@ -673,18 +660,18 @@ __device__ __forceinline__ void probe_search(const GraphView& g, const Item& I, 
         // the answer lies in ((lo - 1) * stride, lo * stride]: a window of
         // fewer than 2^shift entries before the sample at lo * stride (or
         // the end of the segment); branch-free lower bound in `shift` steps
-        uint32_t end[kUnroll];
+        uint32_t end[U];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < U; ++u) {
             p[u] = lo[u] ? ((lo[u] - 1) << shift) + 1 : 0;
             end[u] = min(lo[u] << shift, len);
         }
         auto step = [&](uint32_t half) {
-            uint64_t kv[kUnroll];
+            uint64_t kv[U];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) kv[u] = keys[I.lo + min(p[u] + half - 1, len - 1)];
+            for (int u = 0; u < U; ++u) kv[u] = keys[I.lo + min(p[u] + half - 1, len - 1)];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u)
+            for (int u = 0; u < U; ++u)
                 p[u] += (p[u] + half - 1 < end[u] && kv[u] < (vbase | x[u])) ? half : 0u;
         };
         // windows of up to 2^kWinLog entries take unrolled steps; longer ones
@@ -693,15 +680,15 @@ __device__ __forceinline__ void probe_search(const GraphView& g, const Item& I, 
 #pragma unroll
         for (int k = kWinLog - 1; k >= 0; --k)
             if ((uint32_t)k < shift) step(1u << k);
-        uint64_t kv[kUnroll];
+        uint64_t kv[U];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) kv[u] = keys[I.lo + min(p[u], len - 1)];
+        for (int u = 0; u < U; ++u) kv[u] = keys[I.lo + min(p[u], len - 1)];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) hit[u] = p[u] < len && kv[u] == (vbase | x[u]);
+        for (int u = 0; u < U; ++u) hit[u] = p[u] < len && kv[u] == (vbase | x[u]);
     }
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-        const uint32_t si = s + u * kGroup;
+    for (int u = 0; u < U; ++u) {
+        const uint32_t si = s + u * G;
         if (si >= I.s1 || !hit[u]) continue;
         const uint32_t pos = I.lo + p[u];
         if (MODE == kInsert) {
@@ -777,11 +764,11 @@ __device__ __forceinline__ void probe_small(const GraphView& g, const Item& I, u
     }
 }
 
-template <int MODE>
+template <int MODE, int G, int U>
 __global__ __launch_bounds__(kThreads) void k_probe(GraphView g, const uint64_t* keys,
                                                     const Item* items, const Item* small,
                                                     uint8_t* mark, uint32_t* hitpos) {
-    __shared__ uint32_t stage[kWaves * kGroupsPerWave][kStage];
+    __shared__ uint32_t stage[kWaves * (64 / G)][kStage];
     if (batch_failed(g.ctr)) return;
     if (MODE == kInsert || MODE == kDelete) {
         // the sorted keys must be the packed keys: their mix64 sums agree
@@ -804,12 +791,12 @@ __global__ __launch_bounds__(kThreads) void k_probe(GraphView g, const uint64_t*
     }
     const uint32_t nitems = (uint32_t)g.ctr->tot[kTotItems];
     const uint32_t lane = lane_id();
-    const uint32_t gl = lane & (kGroup - 1);
-    const uint32_t gid_local = (threadIdx.x >> 6) * kGroupsPerWave + (lane / kGroup);
+    const uint32_t gl = lane & (G - 1);
+    const uint32_t gid_local = (threadIdx.x >> 6) * (64 / G) + (lane / G);
     uint32_t* st = stage[gid_local];
-    const uint32_t ngroups = gridDim.x * kWaves * kGroupsPerWave;
+    const uint32_t ngroups = gridDim.x * kWaves * (64 / G);
     const uint64_t dmask = (1ull << g.L) - 1;
-    uint32_t it = global_wave() * kGroupsPerWave + lane / kGroup;
+    uint32_t it = global_wave() * (64 / G) + lane / G;
     if (it >= nitems) return;
     Item I = items[it];
     while (true) {
@@ -830,54 +817,54 @@ __global__ __launch_bounds__(kThreads) void k_probe(GraphView g, const uint64_t*
         // block ids come from the directory, or from the item itself for a
         // vertex whose only block is stored inline
         const uint32_t* dp = I.dcls != kNoDir ? g.dir + I.dirbase : &items[it].blk0;
-        uint32_t e[kUnroll];
+        uint32_t e[U];
         if (I.dcls != kNoDir) {
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const uint32_t si = min(s + u * kGroup, I.s1 - 1);
+            for (int u = 0; u < U; ++u) {
+                const uint32_t si = min(s + u * G, I.s1 - 1);
                 e[u] = dp[si >> g.log2B];
             }
         } else {
             // the only block: its id is in the descriptor, no load
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) e[u] = I.blk0;
+            for (int u = 0; u < U; ++u) e[u] = I.blk0;
         }
-        constexpr int kSv = kStage / kGroup;
+        constexpr int kSv = kStage / G;
         const uint32_t* klo = (const uint32_t*)keys;  // low words: destinations
         uint32_t sv[kSv];
 #pragma unroll
         for (int r = 0; r < kSv; ++r) {
-            const uint32_t j = min(gl + r * kGroup, ns - 1);
-            sv[r] = r * kGroup < ns ? klo[2ull * (I.lo + (j << shift))] & (uint32_t)dmask : 0u;
+            const uint32_t j = min(gl + r * G, ns - 1);
+            sv[r] = r * G < ns ? klo[2ull * (I.lo + (j << shift))] & (uint32_t)dmask : 0u;
         }
-        uint32_t x[kUnroll];
-        uint64_t addr[kUnroll];
+        uint32_t x[U];
+        uint64_t addr[U];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const uint32_t si = min(s + u * kGroup, I.s1 - 1);
+        for (int u = 0; u < U; ++u) {
+            const uint32_t si = min(s + u * G, I.s1 - 1);
             addr[u] = ((uint64_t)e[u] << g.log2B) + (si & (g.B - 1));
         }
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) x[u] = g.pool[addr[u]];
+        for (int u = 0; u < U; ++u) x[u] = g.pool[addr[u]];
 #pragma unroll
         for (int r = 0; r < kSv; ++r) {
             // the searches read st[0, 2^steps) only
-            const uint32_t j = gl + r * kGroup;
-            if (r * kGroup < (1u << steps)) st[j] = j < ns ? sv[r] : 0xFFFFFFFFu;
+            const uint32_t j = gl + r * G;
+            if (r * G < (1u << steps)) st[j] = j < ns ? sv[r] : 0xFFFFFFFFu;
         }
         wave_lds_sync();
         // the loads of step k+1 are issued before step k is searched and
         // copied over after it, so they overlap the search
         while (true) {
-            const bool more = s + kGroup * kUnroll - gl < I.s1;  // uniform in the group
-            uint32_t x2[kUnroll];
-            uint64_t a2[kUnroll];
-            if (more) probe_load<MODE>(g, I, dp, s + kGroup * kUnroll, x2, a2);
-            probe_search<MODE>(g, I, s, x, addr, st, steps, shift, keys, mark, hitpos);
+            const bool more = s + G * U - gl < I.s1;  // uniform in the group
+            uint32_t x2[U];
+            uint64_t a2[U];
+            if (more) probe_load<MODE, G, U>(g, I, dp, s + G * U, x2, a2);
+            probe_search<MODE, G, U>(g, I, s, x, addr, st, steps, shift, keys, mark, hitpos);
             if (!more) break;
-            s += kGroup * kUnroll;
+            s += G * U;
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
+            for (int u = 0; u < U; ++u) {
                 x[u] = x2[u];
                 addr[u] = a2[u];
             }
@@ -1650,12 +1637,36 @@ void set_u64(gv_graph* g, unsigned long long* p, unsigned long long value) {
 }
 
 // ------------------------------------------------------------------ driver
-// occupancy queries of the looping kernels, made before a recording
-void edge_batch_warm() {
-    resident_grid(k_probe<kInsert>, kThreads);
-    resident_grid(k_probe<kDelete>, kThreads);
-    resident_grid(k_probe<kQuery>, kThreads);
-    resident_grid(k_probe<kLocate>, kThreads);
+// Runs f on the probe variant of MODE for lanes-per-item G and slots-per-lane
+// U chosen at run time (the shapes the tuning accepts).
+template <int MODE, typename F>
+static void with_probe(uint32_t group, uint32_t unroll, F&& f) {
+#define GV_PROBE_SHAPE(G, U) \
+    if (group == G && unroll == U) return f(k_probe<MODE, G, U>);
+    GV_PROBE_SHAPE(16, 2) GV_PROBE_SHAPE(16, 4) GV_PROBE_SHAPE(16, 8)
+    GV_PROBE_SHAPE(32, 2) GV_PROBE_SHAPE(32, 4) GV_PROBE_SHAPE(32, 8)
+    GV_PROBE_SHAPE(64, 2) GV_PROBE_SHAPE(64, 4) GV_PROBE_SHAPE(64, 8)
+#undef GV_PROBE_SHAPE
+    fail(GV_EINVAL, "probe shape");
+}
+
+bool probe_shape_ok(uint32_t group, uint32_t unroll) {
+    return (group == 16 || group == 32 || group == 64) && (unroll == 2 || unroll == 4 || unroll == 8);
+}
+
+// occupancy lookups of the looping kernels, made before a recording: the
+// probe shape of the graph's tuning, or every shape when g is null
+void edge_batch_warm(const gv_graph* g) {
+    auto warm = [](auto kernel) { resident_grid(kernel, kThreads); };
+    for (uint32_t pg : {16u, 32u, 64u}) {
+        for (uint32_t pu : {2u, 4u, 8u}) {
+            if (g && (pg != g->tune.probe_group || pu != g->tune.probe_unroll)) continue;
+            with_probe<kInsert>(pg, pu, warm);
+            with_probe<kDelete>(pg, pu, warm);
+            with_probe<kQuery>(pg, pu, warm);
+            with_probe<kLocate>(pg, pu, warm);
+        }
+    }
     resident_grid(k_grow, kThreads);
     resident_grid(k_compact, kThreads);
     resident_grid(k_os_pass<uint64_t, false>, kOsThreads);
@@ -1668,7 +1679,8 @@ size_t edge_batch_bytes(const gv_graph* g, EdgeMode mode, uint64_t n) {
     if (n == 0) return 0;
     BatchArrays A;
     Carver m(nullptr);
-    carve_batch(m, A, n, n + div_up(g->item_slots, kChunk) + 1, mode, 2 * (int)g->v.L);
+    carve_batch(m, A, n, n + div_up(g->item_slots, (uint64_t)g->tune.item_chunk) + 1, mode,
+                2 * (int)g->v.L);
     return m.used;
 }
 
@@ -1744,7 +1756,7 @@ static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint
     if (n >= 0x3fffffffull) fail(GV_EINVAL, "batch too large");
     Ctx& c = g->ctx;
     const GraphView& v = g->v;
-    const uint64_t icap = n + div_up(g->item_slots, kChunk) + 1;
+    const uint64_t icap = n + div_up(g->item_slots, (uint64_t)g->tune.item_chunk) + 1;
     const int bits = 2 * (int)v.L;
     BatchArrays A;
     {
@@ -1802,15 +1814,24 @@ static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint
     scan2(c, "segments", SegIn{keys, ctr, v.L},
           SegOut{v.L, A.flags, A.a, A.t_vtx, A.t_start, ctr}, n, A.part,
           &tot[kTotSeg]);
-    scan2(c, "items", ItemIn{v, A.t_vtx, A.t_start}, ItemOut{A.items, A.small, v.B, icap}, n, A.part,
-          &tot[kTotItems]);
-    const uint64_t pwant = div_up(icap, kWaves * kGroupsPerWave);
-    auto pgrid_of = [&](auto kernel) { return std::min<uint64_t>(pwant, resident_grid(kernel, kThreads)); };
+    const uint32_t chunk = g->tune.item_chunk;
+    scan2(c, "items", ItemIn{v, A.t_vtx, A.t_start, chunk},
+          ItemOut{A.items, A.small, v.B, icap, chunk}, n, A.part, &tot[kTotItems]);
+    const uint32_t pg = g->tune.probe_group, pu = g->tune.probe_unroll;
+    const uint64_t pwant = div_up(icap, (uint64_t)kWaves * (64 / pg));
+    // launches the probe variant of the graph's tuning
+    auto probe = [&](auto mode_tag, const char* name, uint32_t* hitpos) {
+        constexpr int M = decltype(mode_tag)::value;
+        with_probe<M>(pg, pu, [&](auto kernel) {
+            c.launch(name, kernel, std::min<uint64_t>(pwant, resident_grid(kernel, kThreads)),
+                     kThreads, v, keys, (const Item*)A.items, (const Item*)A.small, A.mark,
+                     hitpos);
+        });
+    };
     const uint64_t tgrid = std::min<uint64_t>(div_up(n, kThreads), resident_grid(k_grow, kThreads));
 
     if (mode == kInsert) {
-        c.launch("probe_insert", k_probe<kInsert>, pgrid_of(k_probe<kInsert>), kThreads, v, keys, (const Item*)A.items, (const Item*)A.small,
-                 A.mark, (uint32_t*)nullptr);
+        probe(std::integral_constant<int, kInsert>{}, "probe_insert", nullptr);
         scan2(c, "keep", KeepIn{A.flags, A.mark, ctr}, U32Out{A.b}, n + 1, A.part,
               &tot[kTotA]);
         c.launch("plan_insert", k_plan_ins, grid, kThreads, v, (const uint32_t*)A.t_vtx,
@@ -1829,8 +1850,7 @@ static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint
         c.launch("final_insert", k_final_ins, std::min<uint64_t>(grid, 64), kThreads, v,
                  (const uint32_t*)A.rel, (const uint32_t*)A.t_dold, (const uint32_t*)A.t_doldc);
     } else if (mode == kDelete) {
-        c.launch("probe_delete", k_probe<kDelete>, pgrid_of(k_probe<kDelete>), kThreads, v, keys, (const Item*)A.items, (const Item*)A.small,
-                 A.mark, A.hitpos);
+        probe(std::integral_constant<int, kDelete>{}, "probe_delete", A.hitpos);
         scan2(c, "found", FoundIn{A.mark, ctr}, U32Out{A.b}, n + 1, A.part, &tot[kTotA]);
         scan2(c, "freed", FreedIn{v, A.t_vtx, A.t_start, A.b},
               FreedOut{ctr, A.cdesc, A.big, A.heavy}, n, A.part, &tot[kTotB]);
@@ -1841,8 +1861,7 @@ static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint
                  (const CDesc*)A.cdesc, (const uint32_t*)A.heavy, (const uint32_t*)A.big, nbig);
         c.launch("final_delete", k_final_del, 1, 1, v, n);
     } else if (aop) {
-        c.launch("probe_locate", k_probe<kLocate>, pgrid_of(k_probe<kLocate>), kThreads, v, keys,
-                 (const Item*)A.items, (const Item*)A.small, A.mark, A.hitpos);
+        probe(std::integral_constant<int, kLocate>{}, "probe_locate", A.hitpos);
         if (aop->out) {
             c.launch("answer", k_answer, grid, kThreads, v, vals, (const uint8_t*)A.mark, n, out);
             c.launch("attr_get", k_attr_get, grid, kThreads, v, keys, vals,
@@ -1852,8 +1871,7 @@ static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint
                      (const uint8_t*)A.mark, (const uint32_t*)A.hitpos, n, aop->in);
         }
     } else {
-        c.launch("probe_query", k_probe<kQuery>, pgrid_of(k_probe<kQuery>), kThreads, v, keys, (const Item*)A.items, (const Item*)A.small,
-                 A.mark, (uint32_t*)nullptr);
+        probe(std::integral_constant<int, kQuery>{}, "probe_query", nullptr);
         c.launch("answer", k_answer, grid, kThreads, v, vals, (const uint8_t*)A.mark, n, out);
     }
     if (mark_out && sorted)

@@ -13,7 +13,7 @@ struct gv_graph {
     gv::Scratch scratch;          // per-call temporaries
     gv::Scratch vscr[3];          // vertex-batch buffers that outlive an inner edge batch
     gv::Scratch cscr;             // a coalesced run of edge batches (batched form)
-    gv_tuning tune{0u, 0u, 4096u, {0u, 0u, 0u, 0u, 0u}};
+    gv_tuning tune{0u, 0u, 4096u, 32u, 4u, 256u, {0u, 0u}};
     uint64_t table_gen = 0;       // counts reallocations of the vertex table or the pool
     uint64_t item_slots = 0;      // bound on live adjacency slots (pool slots)
     uint32_t spin_limit = gv::kSpinLimitDefault;  // bound on each look-back wait of batch sorts
@@ -82,7 +82,8 @@ void mixed_edges(gv_graph* g, const uint8_t* op, const uint32_t* src, const uint
                  gv_batch_stats* stats = nullptr);
 
 // occupancy queries made ahead of a recording
-void edge_batch_warm();
+void edge_batch_warm(const gv_graph* g = nullptr);
+bool probe_shape_ok(uint32_t group, uint32_t unroll);
 void vertex_batch_warm();
 // bytes of g->scratch an edge batch of n pairs carves
 size_t edge_batch_bytes(const gv_graph* g, EdgeMode mode, uint64_t n);

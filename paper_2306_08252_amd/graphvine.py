@@ -67,13 +67,15 @@ class gv_counters(C.Structure):
         return out
 
 
+TUNING_FIELDS = ("coalesce", "max_run_pairs", "small_sort_max", "probe_group", "probe_unroll",
+                 "item_chunk")
+
+
 class gv_tuning(C.Structure):
-    _fields_ = [("coalesce", C.c_uint32), ("max_run_pairs", C.c_uint32),
-                ("small_sort_max", C.c_uint32), ("reserved", C.c_uint32 * 5)]
+    _fields_ = [(f, C.c_uint32) for f in TUNING_FIELDS] + [("reserved", C.c_uint32 * 2)]
 
     def as_dict(self):
-        return {"coalesce": self.coalesce, "max_run_pairs": self.max_run_pairs,
-                "small_sort_max": self.small_sort_max}
+        return {f: getattr(self, f) for f in TUNING_FIELDS}
 
 
 class gv_op(C.Structure):
@@ -429,16 +431,15 @@ def gv_sync(g):
     return lib().gv_sync(C.c_void_p(g))
 
 
-def gv_set_tuning(g, coalesce=None, max_run_pairs=None, small_sort_max=None):
+def gv_set_tuning(g, **fields):
     """Sets the given fields of the graph's gv_tuning (others unchanged)."""
     t = gv_tuning()
     _check(lib().gv_get_tuning(C.c_void_p(g), C.byref(t)), "gv_get_tuning")
-    if coalesce is not None:
-        t.coalesce = int(coalesce)
-    if max_run_pairs is not None:
-        t.max_run_pairs = int(max_run_pairs)
-    if small_sort_max is not None:
-        t.small_sort_max = int(small_sort_max)
+    for k, val in fields.items():
+        if k not in TUNING_FIELDS:
+            raise TypeError(f"unknown tuning field {k}")
+        if val is not None:
+            setattr(t, k, int(val))
     _check(lib().gv_set_tuning(C.c_void_p(g), C.byref(t)), "gv_set_tuning")
     return t.as_dict()
 

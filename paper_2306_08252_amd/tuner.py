@@ -1,16 +1,22 @@
 """Autotuner of the batched form.
 
-For a workload (a graph and a sequence of uneven batches), it measures the
-batched form with each setting it tries and keeps the fastest; the result
-goes to tuning.json beside this file, keyed by workload, with the times it
-measured.  The knobs: block size B (8, 16, 32, 64 slots), coalescing of runs
-of edge batches into mixed lists, the longest run coalesced (pairs) and the
-largest batch sorted by one workgroup.  Every setting is timed eagerly
+For a workload it measures the hot path with each setting it tries and
+keeps the fastest; the result goes to tuning.json beside this file, keyed by
+workload, with the times it measured.  Two workloads:
+  batched  a graph and a sequence of uneven batches (the batched form); knobs:
+           block size B (8, 16, 32, 64 slots), coalescing of runs of edge
+           batches into mixed lists, the longest run coalesced (pairs), the
+           largest batch sorted by one workgroup, and the probe's shape;
+  steps    insert + delete steps of equal batches on one graph (the
+           benchmark's step, block size fixed by the workload); knobs: the
+           probe's shape (lanes per work item, slots per lane per step) and
+           the adjacency slots per work item.  Every setting is timed eagerly
 (gv_apply_ops, coalescing as set) on a fresh copy of the same graph after
 the same warm-up, and every run must end in the same graph (checksum and
 edge count), so a setting cannot win by computing something else.
 
-    python -m paper_2306_08252_amd.tuner            # the batched workload
+    python -m paper_2306_08252_amd.tuner                    # the batched workload
+    python -m paper_2306_08252_amd.tuner --workload steps   # the benchmark's step
 """
 import argparse
 import json
@@ -76,19 +82,36 @@ def measure(gv, w, ops, dev, bs, tuning, warm, form="plan"):
     return el, (ck.value, e.value)
 
 
+PROBE_SPACE = [("probe_group", [16, 32, 64]), ("probe_unroll", [2, 4, 8]),
+               ("item_chunk", [64, 128, 256, 512, 1024, 2048, 4096])]
+DEFAULT_PROBE = {"probe_group": 32, "probe_unroll": 4, "item_chunk": 256}
+
+
+def descend(best, space, run):
+    """Coordinate descent: each knob in turn takes its fastest value."""
+    run(best)
+    for knob, values in space:
+        for v in values:
+            cand = dict(best, **{knob: v})
+            if run(cand) < run(best):
+                best = cand
+    return best
+
+
 def tune(gv, w, ops, dev, warm, log=print, form="plan"):
     """Coordinate descent over the knobs, starting from the defaults, timing
     `form`; returns (best setting, all measured points in ms)."""
-    best = {"block_slots": 16, "coalesce": 0, "max_run_pairs": 0, "small_sort_max": 4096}
+    best = dict({"block_slots": 16, "coalesce": 0, "max_run_pairs": 0, "small_sort_max": 4096},
+                **DEFAULT_PROBE)
     space = [("block_slots", [8, 16, 32, 64]), ("coalesce", [0, 1]),
              ("max_run_pairs", [0, 1 << 18, 1 << 20, 1 << 22]),
-             ("small_sort_max", [0, 4096]), ("block_slots", [8, 16, 32, 64])]
+             ("small_sort_max", [0, 4096])] + PROBE_SPACE + [("block_slots", [8, 16, 32, 64])]
     points, want = {}, None
 
     def run(s):
         k = json.dumps(s, sort_keys=True)
         if k not in points:
-            t = {x: s[x] for x in ("coalesce", "max_run_pairs", "small_sort_max")}
+            t = {x: s[x] for x in s if x != "block_slots"}
             el, dig = measure(gv, w, ops, dev, s["block_slots"], t, warm, form)
             nonlocal want
             if want is None:
@@ -99,20 +122,68 @@ def tune(gv, w, ops, dev, warm, log=print, form="plan"):
             log(f"tuner: {s} -> {el * 1e3:.2f} ms")
         return points[k]
 
-    run(best)
-    for knob, values in space:
-        for v in values:
-            cand = dict(best, **{knob: v})
-            if run(cand) < run(best):
-                best = cand
+    best = descend(best, space, run)
     return best, {k: round(v * 1e3, 3) for k, v in points.items()}
+
+
+def measure_steps(gv, w, ins, dels, dev, B, tuning, warmup=2, steps=4):
+    """ms per insert + delete step on a fresh graph with the given tuning
+    (the same batches for every setting), and the resulting (checksum, edges)."""
+    import torch
+    g = gv.Graph(w.num_vertices, w.src, w.dst, block_slots=B, device=dev)
+    gv.gv_set_tuning(g.h, **tuning)
+    for j in range(warmup):
+        g.insert_edges(*ins[j], stats=False)
+        g.delete_edges(*dels[j], stats=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(warmup, warmup + steps):
+        g.insert_edges(*ins[j], stats=False)
+        g.delete_edges(*dels[j], stats=False)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    rc = g.sync()
+    if rc != 0:
+        raise RuntimeError(f"tuner: {gv.gv_strerror(rc)}")
+    _, _, ck, e = g.dump(checksum_only=True)
+    g.close()
+    return el, (ck, e)
+
+
+def tune_steps(gv, w, ins, dels, dev, B, log=print):
+    """Coordinate descent over the probe's shape and the work-item size for
+    the benchmark's step; returns (best setting, measured points in ms)."""
+    points, want = {}, None
+
+    def run(s):
+        nonlocal want
+        k = json.dumps(s, sort_keys=True)
+        if k not in points:
+            el, dig = measure_steps(gv, w, ins, dels, dev, B, s)
+            if want is None:
+                want = dig
+            elif dig != want:
+                raise RuntimeError(f"tuner: setting {s} changed the result")
+            points[k] = el
+            log(f"tuner: {s} -> {el * 1e3:.3f} ms per step")
+        return points[k]
+
+    best = descend(dict(DEFAULT_PROBE), PROBE_SPACE + PROBE_SPACE[:2], run)
+    return best, {k: round(v * 1e3, 4) for k, v in points.items()}
+
+
+def steps_key(scale, edges, batch, B):
+    return f"rmat{scale}_e{edges}_steps{batch}_b{B}"
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--scale", type=int, default=22)
-    ap.add_argument("--edges", type=int, default=1 << 26)
+    ap.add_argument("--workload", choices=("batched", "steps"), default="batched")
+    ap.add_argument("--scale", type=int, default=None)
+    ap.add_argument("--edges", type=int, default=None)
     ap.add_argument("--batches", type=int, default=256)
+    ap.add_argument("--batch", type=int, default=10**6)
+    ap.add_argument("--block-slots", type=int, default=16)
     ap.add_argument("--seed-name", default="batched")
     args = ap.parse_args()
     import torch
@@ -121,6 +192,20 @@ def main():
     from . import inputs_torch as T
     from . import workloads as Wk
     dev = torch.device("cuda:0")
+    if args.workload == "steps":
+        scale = args.scale or 20
+        edges = args.edges or 1 << 24
+        w = T.RmatWorkload(scale, edges, device=dev)
+        ins = [w.insert_batch(args.batch, 1000 + j) for j in range(6)]
+        dels = [w.delete_batch(args.batch, 1000 + j) for j in range(6)]
+        best, points = tune_steps(gv, w, ins, dels, dev, args.block_slots)
+        key = steps_key(scale, edges, args.batch, args.block_slots)
+        store(key, {"setting": best, "ms": points[json.dumps(best, sort_keys=True)],
+                    "measured_ms": points})
+        print(json.dumps({"key": key, "best": best}))
+        return
+    args.scale = args.scale or 22
+    args.edges = args.edges or 1 << 26
     w = T.RmatWorkload(args.scale, args.edges, name=args.seed_name, device=dev)
     ops, pairs, vids = Wk.batched_ops(w, args.seed_name, args.batches, dev)
     warm = Wk.batched_warmup(ops)

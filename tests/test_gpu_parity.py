@@ -112,6 +112,38 @@ def test_random_mixed_ops_with_vertex_churn(n, B, seed):
     g.close()
 
 
+@pytest.mark.parametrize("group,unroll,chunk", [(16, 2, 64), (16, 8, 4096), (64, 2, 128),
+                                                 (64, 8, 256), (32, 8, 1024)])
+def test_probe_shapes_match_oracle(group, unroll, chunk):
+    """Every probe shape the tuning may pick gives the oracle's results: a
+    hub of several thousand slots (items of `chunk` slots, long segments)
+    and many small sources, through inserts, deletes, queries and vertex
+    deletes."""
+    gv = need_gpu()
+    n, B = 3000, 8
+    rng = np.random.default_rng(group * 100 + unroll)
+    s = rng.integers(0, n, 6 * n).astype(np.uint32)
+    d = rng.integers(0, n, 6 * n).astype(np.uint32)
+    s[: 4 * n // 2] = 5  # the hub
+    g = gv.Graph(n, s, d, block_slots=B, vertex_capacity=n)
+    t = gv.gv_set_tuning(g.h, probe_group=group, probe_unroll=unroll, item_chunk=chunk)
+    assert (t["probe_group"], t["probe_unroll"], t["item_chunk"]) == (group, unroll, chunk)
+    o = O.OracleGraph(n, s, d, block_slots=B, vertex_capacity=n)
+    say(f"probe shape {group}x{unroll}, chunk {chunk}")
+    for step in range(6):
+        x = rng.integers(0, n, 5000).astype(np.uint32)
+        y = rng.integers(0, n, 5000).astype(np.uint32)
+        x[:1500] = 5
+        assert g.insert_edges(x, y) == o.insert_edges(x, y)[1], step
+        same_answers(g, o, x[::3], y[::3], f"query {step}")
+        x2, y2 = x[::2], y[::2]
+        assert g.delete_edges(x2, y2) == o.delete_edges(x2, y2)[1], step
+        ids = rng.integers(6, n, 20).astype(np.uint32)
+        assert g.delete_vertices(ids) == o.delete_vertices(ids)[1], step
+        assert_same(g, o, f"shape {group}x{unroll} chunk {chunk} step {step}")
+    g.close()
+
+
 # ---------------------------------------------------------------- failures
 def test_pool_exhaustion_is_all_or_nothing():
     gv = need_gpu()
