@@ -30,6 +30,7 @@ struct gv_plan {
     uint64_t vscr_gen[3] = {0, 0, 0};
     uint64_t table_gen = 0;
     uint64_t cscr_gen = 0;
+    uint64_t insert_pairs = 0;  // pairs the plan's inserts add to the host-side edge bound
 };
 
 namespace {
@@ -262,7 +263,12 @@ int gv_plan_create(gv_graph* g, const gv_op* ops, uint64_t n_ops, gv_plan** out)
         try {
             hip_check(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal),
                       "hipStreamBeginCapture");
+            // nothing runs while recording: the inserts add to the host-side
+            // edge bound at each launch instead
+            const uint64_t bound0 = g->edge_bound_host;
             run_ops(g, ops, n_ops, true, bound);
+            p->insert_pairs = g->edge_bound_host - bound0;
+            g->edge_bound_host = bound0;
             hip_check(hipStreamEndCapture(cs, &graph), "hipStreamEndCapture");
         } catch (...) {
             hipGraph_t dropped = nullptr;
@@ -301,6 +307,7 @@ int gv_plan_launch(gv_plan* p) {
         for (int k = 0; k < 3; ++k) same = same && g->vscr[k].gen == p->vscr_gen[k];
         if (!same) fail(GV_EINVAL, "graph buffers moved since the plan was created");
         hip_check(hipGraphLaunch(p->exec, g->ctx.stream), "hipGraphLaunch");
+        g->edge_bound_host += p->insert_pairs;
     });
 }
 

@@ -25,6 +25,7 @@ void read_counters(gv_graph* g) {
                              g->ctx.stream),
               "hipMemcpyAsync counters");
     hip_check(hipStreamSynchronize(g->ctx.stream), "hipStreamSynchronize");
+    g->edge_bound_host = g->hctr->live_edges;
 }
 
 // Sort n keys of `bits` bits (n >= 2) with the one-sweep radix sort; `state`
@@ -309,6 +310,7 @@ void bulk_build(gv_graph* g, uint64_t n, const uint32_t* src, const uint32_t* ds
     c.launch("init_counters", k_init_counters, 1, 1, v, (unsigned long long)blocks,
              (unsigned long long)dents, (unsigned long long)mu);
     hip_check(hipStreamSynchronize(c.stream), "hipStreamSynchronize");
+    g->edge_bound_host = mu;
 }
 
 // ------------------------------------------------------------------ dump

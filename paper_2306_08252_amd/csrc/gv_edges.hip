@@ -1754,6 +1754,7 @@ static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint
                      uint8_t* mark_out, const AttrOp* aop) {
     if (n == 0) return;
     if (n >= 0x3fffffffull) fail(GV_EINVAL, "batch too large");
+    if (mode == kInsert) g->edge_bound_host += n;
     Ctx& c = g->ctx;
     const GraphView& v = g->v;
     const uint64_t icap = n + div_up(g->item_slots, (uint64_t)g->tune.item_chunk) + 1;

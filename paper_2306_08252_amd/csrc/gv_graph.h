@@ -16,6 +16,9 @@ struct gv_graph {
     gv_tuning tune{0u, 0u, 4096u, 32u, 4u, 256u, {0u, 0u}};
     uint64_t table_gen = 0;       // counts reallocations of the vertex table or the pool
     uint64_t item_slots = 0;      // bound on live adjacency slots (pool slots)
+    // upper bound on the edges stored, kept on the host without a read-back:
+    // exact after each counter read, plus the pairs of every insert since
+    uint64_t edge_bound_host = 0;
     uint32_t spin_limit = gv::kSpinLimitDefault;  // bound on each look-back wait of batch sorts
     // device allocations owned by the graph
     void* mem_pool = nullptr;

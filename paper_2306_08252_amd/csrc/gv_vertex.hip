@@ -715,7 +715,8 @@ void vertex_batch_bytes(const gv_graph* g, bool del, uint64_t n, uint64_t edge_b
 }
 
 // edge_bound: an upper bound on the edges stored when the call runs (0: read
-// it from the device, which synchronises)
+// it from the device when statistics are wanted, which synchronises, else
+// take the graph's host-side bound)
 void vertex_delete(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats* st,
                    uint64_t edge_bound) {
     Ctx& c = g->ctx;
@@ -732,18 +733,19 @@ void vertex_delete(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats*
     uint32_t* sorted = sorted_ids(g, ids, n, k0, k0 + n);
     c.launch("vdel_mark", k_vdel_mark, div_up(n, kThreads), kThreads, v, (const uint32_t*)sorted,
              n, gone);
-    if (!edge_bound) {
+    if (!edge_bound && st) {
+        // synchronous call: read the counts back (and stop early if no id
+        // is deleted)
         read_counters(g);
         if (!g->hctr->st_applied) {
-            if (st) {
-                st->applied = 0;
-                st->rejected = g->hctr->st_rejected;
-                st->batch_duplicates = n - g->hctr->st_rejected - g->hctr->n_uniq;
-            }
+            st->applied = 0;
+            st->rejected = g->hctr->st_rejected;
+            st->batch_duplicates = n - g->hctr->st_rejected - g->hctr->n_uniq;
             return;
         }
         edge_bound = g->hctr->live_edges;
     }
+    if (!edge_bound) edge_bound = std::max<uint64_t>(g->edge_bound_host, 1);  // no read-back
     VDel d{};
     {
         const VDelCaps k = vdel_caps(g, edge_bound);

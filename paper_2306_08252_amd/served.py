@@ -11,11 +11,13 @@ in that order; then the tick's queries are answered (gv_edge_exists).  So the co
 arrival order, then its queries.  Ticks overlap: a tick is queued as soon as
 it is formed, while earlier ones still run on the device (a few at most),
 and its answers come back by an asynchronous copy; requests that arrive
-meanwhile form the next tick.  Vertex requests are barriers: a tick ends
-before one, and it runs alone once the running ticks are done.  A request
-completes when its tick's event has passed; latency is completion time
-minus scheduled arrival time (open loop, so a late server does not lower
-the arrival rate).
+meanwhile form the next tick.  Vertex requests end a tick and run alone: a
+vertex delete is queued in stream order like a tick (it only frees blocks,
+so the host's free-block count stays a lower bound, and the library sizes
+its lists without reading the device back); a vertex insert waits for the
+running ticks (it may grow the dictionary).  A request completes when its
+tick's event has passed; latency is completion time minus scheduled arrival
+time (open loop, so a late server does not lower the arrival rate).
 
 Admission by free blocks: an edge-insert request of k pairs may need up to
 ceil(k / B) + min(k, V) new blocks (its pairs packed into full blocks, plus
@@ -97,7 +99,8 @@ def serve(graph, requests, arrivals=None, max_tick_pairs=1 << 20, keep_answers=F
     formed, while up to `max_inflight - 1` earlier ticks are still running,
     so requests that arrive meanwhile form the next tick and run right after
     (stream order keeps the commit order); a tick's requests complete when
-    its event has passed.  Vertex requests wait for every running tick.
+    its event has passed.  A vertex insert waits for every running tick; a
+    vertex delete is queued like a tick.
     Returns (completion times, ticks as (first, end) request ranges, answers
     of the query requests by index if keep_answers).  Indices of requests
     rejected by admission are appended to `rejected` (a list) if given; a
@@ -148,13 +151,19 @@ def serve(graph, requests, arrivals=None, max_tick_pairs=1 << 20, keep_answers=F
                 pass
             now = clock() - t0
         kind = requests[i][0]
-        if kind in (VINSERT, VDELETE):
+        if kind == VDELETE:
+            # queued behind the running ticks, no host wait
+            keep = gv.gv_apply_ops(graph.h, [(3, requests[i][1], None)], dev)
+            ev = torch.cuda.Event()
+            ev.record(torch.cuda.current_stream(dev))
+            flight.append({"range": (i, i + 1), "event": ev, "queries": [], "answers": None,
+                           "keep": keep, "writes": [], "stats": None})
+            ticks.append((i, i + 1))
+            i += 1
+            continue
+        if kind == VINSERT:
             retire(True)
-            ids = requests[i][1]
-            if kind == VINSERT:
-                graph.insert_vertices(ids)
-            else:
-                graph.delete_vertices(ids)
+            graph.insert_vertices(requests[i][1])
             torch.cuda.synchronize(dev)
             done[i] = clock() - t0
             ticks.append((i, i + 1))
