@@ -427,7 +427,8 @@ void scan2(Ctx& c, const char* name, In in, Out out, uint64_t n, unsigned long l
     if (n == 0) return;
     const uint64_t nt = div_up(n, (uint64_t)kThreads * scan2_items<In>::value);
     if (nt > 0xffffffffull) fail(GV_EINVAL, "scan too large");
-    c.launch(name, k_scan2_reduce<In>, nt, kThreads, in, n, part);
+    // a single tile adds no earlier partials: the apply kernel is the scan
+    if (nt > 1) c.launch(name, k_scan2_reduce<In>, nt, kThreads, in, n, part);
     const int scanned = nt > kScan2MaxTiles ? 1 : 0;
     if (scanned) c.launch(name, k_scan2_partials, 1, kThreads, part, nt);
     c.launch(name, k_scan2_apply<In, Out>, nt, kThreads, in, out, n,
