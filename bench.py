@@ -269,9 +269,9 @@ KERNEL_SYMBOLS = {
     "sort_pass": "gv::k_os_pass<unsigned long, false>",
     "sort_hist": "gv::k_os_hist_sum",
     "pack": "gv::k_pack_hist(",
-    "probe_insert": "gv::k_probe<0>",
-    "probe_delete": "gv::k_probe<1>",
-    "probe_query": "gv::k_probe<2>",
+    "probe_insert": "gv::k_probe<0,",
+    "probe_delete": "gv::k_probe<1,",
+    "probe_query": "gv::k_probe<2,",
     "compact": "gv::k_compact(",
     "append": "gv::k_append(",
 }
@@ -338,7 +338,10 @@ def summarize_traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, grid_wgs, ou
              "| HBM read B (scaled) | HBM write B (scaled) |", "|---|---|---|---|---|---|---|---|"]
     for name, sym in KERNEL_SYMBOLS.items():
         wg = grid_wgs.get(name)
-        same = lambda k, g: _short(k) == sym.rstrip("(") and (wg is None or g == wg)
+        # a symbol ending in "," names every shape of a templated kernel
+        same = lambda k, g: (_short(k) == sym.rstrip("(") or
+                             (sym.endswith(",") and _short(k).startswith(sym))) \
+            and (wg is None or g == wg)
         fk = [v for (k, g), v in kf.items() if same(k, g)]
         wk = [v for (k, g), v in kw.items() if same(k, g)]
         if not fk or not wk:
