@@ -314,11 +314,7 @@ __global__ __launch_bounds__(kOsThreads) void k_pack_sort_tile(GraphView g, cons
                                                                const uint32_t* dst, uint64_t n,
                                                                int passes, uint64_t sentinel,
                                                                uint64_t* keys, uint8_t* mark) {
-    __shared__ uint16_t cnt[kOsRounds * kOsWaves][kRadix];
-    __shared__ uint32_t part[4][kRadix];
-    __shared__ uint32_t s_start[kRadix];
-    __shared__ uint32_t s_w[kOsWaves];
-    __shared__ uint64_t skey[kOsTile];
+    __shared__ TileSortLds lds;
     __shared__ unsigned long long s_v[kOsWaves];
     const uint32_t t = threadIdx.x;
     const int w = t >> 6;
@@ -337,61 +333,7 @@ __global__ __launch_bounds__(kOsThreads) void k_pack_sort_tile(GraphView g, cons
             khash += ok ? mix64(key[j]) : 0ull;
         }
     }
-    const uint32_t d = t & (kRadix - 1), q = t >> 8;
-    constexpr int kQRows = kOsRounds * kOsWaves / 4;
-    for (int p = 0; p < passes; ++p) {
-        const int shift = p * kRadixBits;
-        {
-            uint32_t* c32 = (uint32_t*)&cnt[0][0];
-            for (int i = t; i < kOsRounds * kOsWaves * kRadix / 2; i += kOsThreads) c32[i] = 0;
-        }
-        __syncthreads();
-        uint16_t rk[kOsRounds];
-#pragma unroll
-        for (int j = 0; j < kOsRounds; ++j) {
-            const bool act = (uint64_t)j * kOsThreads + t < n;
-            const uint32_t dg = (uint32_t)(key[j] >> shift) & (kRadix - 1);
-            const uint64_t peers = digit_peers(dg, act);
-            rk[j] = (uint16_t)rank_below(peers);
-            if (act && rk[j] == 0) cnt[j * kOsWaves + w][dg] = (uint16_t)popc64(peers);
-        }
-        __syncthreads();
-        // rows in key order: exclusive prefixes per digit, 16 rows per quarter
-        uint32_t run = 0;
-#pragma unroll
-        for (int r = 0; r < kQRows; ++r) {
-            const uint32_t c = cnt[q * kQRows + r][d];
-            cnt[q * kQRows + r][d] = (uint16_t)run;
-            run += c;
-        }
-        part[q][d] = run;
-        __syncthreads();
-        uint32_t qoff = 0;
-        for (uint32_t qq = 0; qq < q; ++qq) qoff += part[qq][d];
-        if (qoff) {
-#pragma unroll
-            for (int r = 0; r < kQRows; ++r) cnt[q * kQRows + r][d] += (uint16_t)qoff;
-        }
-        const uint32_t dcount = part[0][d] + part[1][d] + part[2][d] + part[3][d];
-        uint32_t tot;
-        const uint32_t ex = os_block_scan(q == 0 ? dcount : 0u, s_w, tot);
-        if (q == 0) s_start[d] = ex;
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < kOsRounds; ++j) {
-            if ((uint64_t)j * kOsThreads + t < n) {
-                const uint32_t dg = (uint32_t)(key[j] >> shift) & (kRadix - 1);
-                skey[s_start[dg] + cnt[j * kOsWaves + w][dg] + rk[j]] = key[j];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < kOsRounds; ++j) {
-            const uint64_t i = (uint64_t)j * kOsThreads + t;
-            key[j] = i < n ? skey[i] : sentinel;
-        }
-        __syncthreads();  // skey and cnt are rewritten by the next pass
-    }
+    tile_sort(key, n, passes, sentinel, lds);
 #pragma unroll
     for (int j = 0; j < kOsRounds; ++j) {
         const uint64_t i = (uint64_t)j * kOsThreads + t;
@@ -414,6 +356,52 @@ __global__ __launch_bounds__(kOsThreads) void k_pack_sort_tile(GraphView g, cons
         g.ctr->tot[kTotValid] = x;
         g.ctr->tot[kTotHash] = y;
     }
+}
+
+// Query batches of at most kOsTile pairs: one workgroup packs each valid pair
+// as its key with its input position in the low 12 bits (an invalid pair is
+// answered 0 here and gets the all-ones key, after every valid one), sorts
+// the tile in LDS, and writes the valid keys and their positions compacted,
+// as the packing scan and the sort leave them.
+constexpr int kTilePosBits = 12;  // kOsTile = 4096 positions
+__global__ __launch_bounds__(kOsThreads) void k_query_sort_tile(GraphView g, const uint32_t* src,
+                                                                const uint32_t* dst, uint64_t n,
+                                                                int passes, uint64_t* keys,
+                                                                uint32_t* vals, uint8_t* answer,
+                                                                uint8_t* mark) {
+    __shared__ TileSortLds lds;
+    __shared__ uint32_t s_v[kOsWaves];
+    const uint32_t t = threadIdx.x;
+    clear_batch_counters(g.ctr, t);
+    uint64_t key[kOsRounds];
+    uint32_t valid = 0;
+#pragma unroll
+    for (int j = 0; j < kOsRounds; ++j) {
+        const uint64_t i = (uint64_t)j * kOsThreads + t;
+        const uint32_t su = i < n ? src[i] : 0u, du = i < n ? dst[i] : 0u;
+        const bool ok = i < n && active_bit(g, su) && active_bit(g, du);
+        key[j] = ok ? ((((uint64_t)su << g.L) | du) << kTilePosBits) | i : ~0ull;
+        if (i < n) {
+            mark[i] = 0;
+            if (!ok && answer) answer[i] = 0;
+        }
+        valid += ok ? 1u : 0u;
+    }
+    tile_sort(key, n, passes, ~0ull, lds);
+    const uint32_t vw = (uint32_t)wave_sum((unsigned long long)valid);
+    if (lane_id() == 0) s_v[t >> 6] = vw;
+    __syncthreads();
+    uint32_t nv = 0;
+    for (int k = 0; k < kOsWaves; ++k) nv += s_v[k];
+#pragma unroll
+    for (int j = 0; j < kOsRounds; ++j) {
+        const uint64_t i = (uint64_t)j * kOsThreads + t;
+        if (i < nv) {
+            keys[i] = key[j] >> kTilePosBits;
+            vals[i] = (uint32_t)(key[j] & ((1u << kTilePosBits) - 1));
+        }
+    }
+    if (t == 0) g.ctr->tot[kTotValid] = nv;
 }
 
 // ------------------------------------------------------------------ segments
@@ -1785,6 +1773,10 @@ static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint
         c.launch("pack", k_sorted_prep_a, 1, 64, v, sorted_n);
         c.launch("pack", k_sorted_prep_b, grid, kThreads, v, sorted, sorted_n, n, A.mark);
         keys_in = sorted;
+        flip = false;
+    } else if (mode == kQuery && n <= kOsTile && bits + kTilePosBits < 64) {
+        c.launch("pack", k_query_sort_tile, 1, kOsThreads, v, src, dst, n,
+                 os_passes(bits + kTilePosBits), A.keys0, A.vals0, out, A.mark);
         flip = false;
     } else if (mode == kQuery) {
         c.launch("begin", k_begin, std::min<uint64_t>(div_up(A.state_words, kThreads), 1024),

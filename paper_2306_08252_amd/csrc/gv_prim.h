@@ -517,6 +517,81 @@ __device__ __forceinline__ unsigned long long os_block_scan64(unsigned long long
     return off + inc - x;
 }
 
+// LDS of the one-tile sort below.
+struct TileSortLds {
+    uint16_t cnt[kOsRounds * kOsWaves][kRadix];
+    uint32_t part[4][kRadix];
+    uint32_t start[kRadix];
+    uint32_t w[kOsWaves];
+    uint64_t skey[kOsTile];
+};
+
+// Stable LSD sort of one tile in LDS: thread t holds key[j] = element
+// j * kOsThreads + t, the first n live; `passes` 8-bit digits (the ranking of
+// the pass kernel on a single tile, so no look-back).  key[] comes back
+// holding the sorted order in the same layout, `sentinel` past n.  Every
+// thread of the workgroup calls it (barriers inside).
+__device__ __forceinline__ void tile_sort(uint64_t (&key)[kOsRounds], uint64_t n, int passes,
+                                          uint64_t sentinel, TileSortLds& L) {
+    const uint32_t t = threadIdx.x;
+    const int w = t >> 6;
+    const uint32_t d = t & (kRadix - 1), q = t >> 8;
+    constexpr int kQRows = kOsRounds * kOsWaves / 4;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = p * kRadixBits;
+        {
+            uint32_t* c32 = (uint32_t*)&L.cnt[0][0];
+            for (int i = t; i < kOsRounds * kOsWaves * kRadix / 2; i += kOsThreads) c32[i] = 0;
+        }
+        __syncthreads();
+        uint16_t rk[kOsRounds];
+#pragma unroll
+        for (int j = 0; j < kOsRounds; ++j) {
+            const bool act = (uint64_t)j * kOsThreads + t < n;
+            const uint32_t dg = (uint32_t)(key[j] >> shift) & (kRadix - 1);
+            const uint64_t peers = digit_peers(dg, act);
+            rk[j] = (uint16_t)rank_below(peers);
+            if (act && rk[j] == 0) L.cnt[j * kOsWaves + w][dg] = (uint16_t)popc64(peers);
+        }
+        __syncthreads();
+        // rows in key order: exclusive prefixes per digit, 16 rows per quarter
+        uint32_t run = 0;
+#pragma unroll
+        for (int r = 0; r < kQRows; ++r) {
+            const uint32_t c = L.cnt[q * kQRows + r][d];
+            L.cnt[q * kQRows + r][d] = (uint16_t)run;
+            run += c;
+        }
+        L.part[q][d] = run;
+        __syncthreads();
+        uint32_t qoff = 0;
+        for (uint32_t qq = 0; qq < q; ++qq) qoff += L.part[qq][d];
+        if (qoff) {
+#pragma unroll
+            for (int r = 0; r < kQRows; ++r) L.cnt[q * kQRows + r][d] += (uint16_t)qoff;
+        }
+        const uint32_t dcount = L.part[0][d] + L.part[1][d] + L.part[2][d] + L.part[3][d];
+        uint32_t tot;
+        const uint32_t ex = os_block_scan(q == 0 ? dcount : 0u, L.w, tot);
+        if (q == 0) L.start[d] = ex;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kOsRounds; ++j) {
+            if ((uint64_t)j * kOsThreads + t < n) {
+                const uint32_t dg = (uint32_t)(key[j] >> shift) & (kRadix - 1);
+                L.skey[L.start[dg] + L.cnt[j * kOsWaves + w][dg] + rk[j]] = key[j];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kOsRounds; ++j) {
+            const uint64_t i = (uint64_t)j * kOsThreads + t;
+            key[j] = i < n ? L.skey[i] : sentinel;
+        }
+        __syncthreads();  // skey and cnt are rewritten by the next pass
+    }
+}
+
 // Histogram counting: 0 = the lowest lane of each group of equal digits adds
 // the group's size (eight ballots per digit, no conflicting LDS atomics);
 // 1 = every lane adds one to a histogram shared by a quarter of the

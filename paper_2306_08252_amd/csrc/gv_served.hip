@@ -10,7 +10,8 @@
 // valid entries as keys (src << L) | dst with their list position (an invalid
 // entry gets bit 2L, after every valid key), sort them stably, and keep the
 // last entry of every key: a scan writes the kept deletes and the kept
-// inserts, compacted and still sorted, to two key lists.  The two lists are
+// inserts, compacted and still sorted, to two key lists (a list of at most
+// one tile is packed and sorted by one workgroup).  The two lists are
 // then applied as a delete batch and an insert batch that start from their
 // sorted keys (no second sort); no key is in both, so their order does not
 // matter.
@@ -31,6 +32,41 @@ __global__ __launch_bounds__(kThreads) void k_mixed_pack(GraphView g, const uint
     const bool ok = active_bit(g, s) & active_bit(g, d) & (op[i] <= 1);
     keys[i] = ok ? ((uint64_t)s << g.L) | d : (1ull << (2 * g.L));
     pos[i] = (uint32_t)i;
+}
+
+// Lists of at most one tile: one workgroup packs each entry as its key with
+// its list position in the low 12 bits ((pair << 12) | position, an invalid
+// entry with bit 2L set above the pair) and sorts the tile in LDS, which is
+// the stable order by pair; the pair keys and positions go out separately,
+// as the general path leaves them.
+constexpr int kTilePosBits = 12;  // kOsTile = 4096 positions
+__global__ __launch_bounds__(kOsThreads) void k_mixed_sort_tile(GraphView g, const uint8_t* op,
+                                                                const uint32_t* src,
+                                                                const uint32_t* dst, uint64_t n,
+                                                                int passes, uint64_t* keys,
+                                                                uint32_t* pos) {
+    __shared__ TileSortLds lds;
+    uint64_t key[kOsRounds];
+#pragma unroll
+    for (int j = 0; j < kOsRounds; ++j) {
+        const uint64_t i = (uint64_t)j * kOsThreads + threadIdx.x;
+        uint64_t k = 0;
+        if (i < n) {
+            const uint32_t s = src[i], d = dst[i];
+            const bool ok = active_bit(g, s) & active_bit(g, d) & (op[i] <= 1);
+            k = ok ? ((uint64_t)s << g.L) | d : (1ull << (2 * g.L));
+        }
+        key[j] = (k << kTilePosBits) | (i & ((1u << kTilePosBits) - 1));
+    }
+    tile_sort(key, n, passes, ~0ull, lds);
+#pragma unroll
+    for (int j = 0; j < kOsRounds; ++j) {
+        const uint64_t i = (uint64_t)j * kOsThreads + threadIdx.x;
+        if (i < n) {
+            keys[i] = key[j] >> kTilePosBits;
+            pos[i] = (uint32_t)(key[j] & ((1u << kTilePosBits) - 1));
+        }
+    }
 }
 
 // Scan source over the sorted entries: an entry counts when it is valid and
@@ -258,11 +294,17 @@ void mixed_edges(gv_graph* g, const uint8_t* op, const uint32_t* src, const uint
         Carver cv(g->scratch.ptr);
         carve(cv);
     }
-    zero_words(c, state, os_zero_words(n, bits));
-    c.launch("mixed_pack", k_mixed_pack, div_up(n, kThreads), kThreads, v, op, src, dst, n, k0,
-             p0);
-    const bool flip = onesweep<uint64_t, true>(c, k0, k1, p0, p1, nullptr, n, bits, state,
-                                               &v.ctr->err_wait, g->spin_limit);
+    bool flip = false;
+    if (n <= kOsTile && bits + kTilePosBits <= 64) {
+        c.launch("mixed_pack", k_mixed_sort_tile, 1, kOsThreads, v, op, src, dst, n,
+                 os_passes(bits + kTilePosBits), k0, p0);
+    } else {
+        zero_words(c, state, os_zero_words(n, bits));
+        c.launch("mixed_pack", k_mixed_pack, div_up(n, kThreads), kThreads, v, op, src, dst, n,
+                 k0, p0);
+        flip = onesweep<uint64_t, true>(c, k0, k1, p0, p1, nullptr, n, bits, state,
+                                        &v.ctr->err_wait, g->spin_limit);
+    }
     const uint64_t* sk = flip ? k1 : k0;
     const uint32_t* sp = flip ? p1 : p0;
     const SplitIn in{sk, sp, op, n, v.L};

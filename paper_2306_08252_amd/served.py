@@ -58,11 +58,37 @@ def free_blocks(graph):
     return m["pool_capacity_blocks"] - m["blocks_in_use"]
 
 
-def _enqueue_tick(graph, requests, i, j, dev):
+class _PinnedRing:
+    """Pinned host buffers reused by the ticks in turn (a slot is taken again
+    only after its tick has completed: the ring has more slots than ticks in
+    flight), so that no tick waits on a pinned allocation; a slot grows by
+    doubling when a tick needs more."""
+
+    def __init__(self, slots):
+        self.slots = [{} for _ in range(slots)]
+        self.next = 0
+
+    def take(self):
+        s = self.slots[self.next]
+        self.next = (self.next + 1) % len(self.slots)
+        return s
+
+    @staticmethod
+    def buf(slot, name, count, dtype):
+        b = slot.get(name)
+        if b is None or b.numel() < count:
+            b = torch.empty(max(count, 2 * (0 if b is None else b.numel()), 64), dtype=dtype,
+                            pin_memory=True)
+            slot[name] = b
+        return b[:count]
+
+
+def _enqueue_tick(graph, requests, i, j, dev, slot):
     """Queues one tick's work on the graph's stream without waiting: the
     tick's edge inserts and deletes as one mixed list, then its queries as
-    one batch whose answers are copied to pinned host memory.  Returns the
-    tick record (its tensors stay referenced until it completes)."""
+    one batch whose answers are copied to pinned host memory (`slot` of the
+    ring).  Returns the tick record (its tensors stay referenced until it
+    completes)."""
     ws = [(m, r) for m, r in enumerate(requests[i:j], start=i) if r[0] in (INSERT, DELETE)]
     qs = [(m, r) for m, r in enumerate(requests[i:j], start=i) if r[0] == QUERY]
     keep = []
@@ -72,16 +98,18 @@ def _enqueue_tick(graph, requests, i, j, dev):
                         for _, r in ws])
         src = torch.cat([r[1] for _, r in ws])
         dst = torch.cat([r[2] for _, r in ws])
-        ends = np.cumsum([_size(r) for _, r in ws])
+        ends_h = _PinnedRing.buf(slot, "ends", len(ws), torch.int64)
+        ends_h.copy_(torch.from_numpy(np.cumsum([_size(r) for _, r in ws]).astype(np.int64)))
+        ends = ends_h.to(dev, non_blocking=True)
         k, st = gv.gv_apply_edge_ops_stats(graph.h, op, src, dst, ends, dev)
         keep += list(k) + [st]
-        wstats = torch.empty(st.shape, dtype=st.dtype, pin_memory=True)
+        wstats = _PinnedRing.buf(slot, "stats", st.numel(), st.dtype).view(st.shape)
         wstats.copy_(st, non_blocking=True)
     host = None
     if qs:
         out = graph.edge_exists(torch.cat([r[1] for _, r in qs]),
                                 torch.cat([r[2] for _, r in qs]))
-        host = torch.empty(out.shape, dtype=out.dtype, pin_memory=True)
+        host = _PinnedRing.buf(slot, "answers", out.numel(), out.dtype)
         host.copy_(out, non_blocking=True)
         keep.append(out)
     ev = torch.cuda.Event()
@@ -119,6 +147,7 @@ def serve(graph, requests, arrivals=None, max_tick_pairs=1 << 20, keep_answers=F
     ticks = []
     answers = {}
     flight = []
+    ring = _PinnedRing(max_inflight + 1)
     t0 = clock()
 
     def retire(block):
@@ -191,7 +220,7 @@ def serve(graph, requests, arrivals=None, max_tick_pairs=1 << 20, keep_answers=F
             done[i] = clock() - t0
             i += 1
             continue
-        flight.append(_enqueue_tick(graph, requests, i, j, dev))
+        flight.append(_enqueue_tick(graph, requests, i, j, dev, ring.take()))
         ticks.append((i, j))
         free -= need
         i = j
