@@ -405,10 +405,37 @@ void dump(gv_graph* g, uint64_t* offsets, uint32_t* dst, uint64_t cap, uint64_t*
 }
 
 // ------------------------------------------------------------------ adjacency
-__global__ __launch_bounds__(kThreads) void k_adj_gather(GraphView g, uint32_t u, uint32_t* out) {
+// an adjacency of at most one tile: gathered and sorted in LDS by one workgroup
+__global__ __launch_bounds__(kOsThreads) void k_adj_tile(GraphView g, uint32_t u, int passes,
+                                                         uint32_t* out) {
+    __shared__ TileSortLds lds;
+    const VRec r = g.vt[u];
+    uint64_t key[kOsRounds];
+#pragma unroll
+    for (int j = 0; j < kOsRounds; ++j) {
+        const uint64_t i = (uint64_t)j * kOsThreads + threadIdx.x;
+        key[j] = i < r.deg ? g.pool[slot_addr(g, r, (uint32_t)i)] : ~0ull;
+    }
+    tile_sort(key, r.deg, passes, ~0ull, lds);
+#pragma unroll
+    for (int j = 0; j < kOsRounds; ++j) {
+        const uint64_t i = (uint64_t)j * kOsThreads + threadIdx.x;
+        if (i < r.deg) out[i] = (uint32_t)key[j];
+    }
+}
+
+// a longer one: destinations as 64-bit keys for the one-sweep sort, and back
+__global__ __launch_bounds__(kThreads) void k_adj_gather64(GraphView g, uint32_t u,
+                                                           uint64_t* keys) {
     const VRec r = g.vt[u];
     for (uint64_t s = tidx(); s < r.deg; s += (uint64_t)gridDim.x * kThreads)
-        out[s] = g.pool[slot_addr(g, r, (uint32_t)s)];
+        keys[s] = g.pool[slot_addr(g, r, (uint32_t)s)];
+}
+
+__global__ __launch_bounds__(kThreads) void k_adj_low(const uint64_t* keys, uint64_t n,
+                                                      uint32_t* out) {
+    const uint64_t i = tidx();
+    if (i < n) out[i] = (uint32_t)keys[i];
 }
 
 __global__ __launch_bounds__(kThreads) void k_copy_u32(const uint32_t* a, uint32_t* b, uint64_t n) {
@@ -430,11 +457,19 @@ void adjacency(gv_graph* g, uint32_t u, uint32_t* out, uint64_t cap, uint64_t* d
     if (r.deg == 0) return;
     if (!out) fail(GV_EINVAL, "null output");
     const uint64_t d = r.deg;
-    uint32_t* alt = nullptr;
-    SortScratch ss{};
+    const int bits = std::max<int>((int)v.L, 1);
+    if (d <= kOsTile) {
+        // one kernel: gather and sort in LDS
+        c.launch("adj_sort", k_adj_tile, 1, kOsThreads, v, u, os_passes(bits), out);
+        hip_check(hipStreamSynchronize(c.stream), "hipStreamSynchronize");
+        return;
+    }
+    uint64_t *k0 = nullptr, *k1 = nullptr;
+    uint32_t* state = nullptr;
     auto carve = [&](Carver& cv) {
-        alt = cv.take<uint32_t>(d);
-        carve_sort<uint32_t>(cv, ss, d);
+        k0 = cv.take<uint64_t>(d);
+        k1 = cv.take<uint64_t>(d);
+        state = cv.take<uint32_t>(os_words(d, bits));
     };
     {
         Carver mz(nullptr);
@@ -443,11 +478,11 @@ void adjacency(gv_graph* g, uint32_t u, uint32_t* out, uint64_t cap, uint64_t* d
         Carver cv(g->scratch.ptr);
         carve(cv);
     }
-    c.launch("adj_gather", k_adj_gather, std::min<uint64_t>(div_up(d, kThreads), 1024), kThreads,
-             v, u, out);
-    const bool flip = radix_sort<uint32_t, false>(c, out, alt, nullptr, nullptr, d, (int)v.L, ss);
-    if (flip) c.launch("adj_copy", k_copy_u32, div_up(d, kThreads), kThreads, (const uint32_t*)alt,
-                       out, d);
+    c.launch("adj_gather", k_adj_gather64, std::min<uint64_t>(div_up(d, kThreads), 1024),
+             kThreads, v, u, k0);
+    const bool flip = sort_keys(g, k0, k1, d, bits, state);  // synchronous
+    c.launch("adj_copy", k_adj_low, div_up(d, kThreads), kThreads,
+             (const uint64_t*)(flip ? k1 : k0), d, out);
     hip_check(hipStreamSynchronize(c.stream), "hipStreamSynchronize");
 }
 

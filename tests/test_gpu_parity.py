@@ -63,6 +63,27 @@ def test_rmat_multitile_ragged(B):
     g.close()
 
 
+@pytest.mark.parametrize("B", [4, 16])
+def test_adjacency_around_one_tile(B):
+    """Adjacency reads on both sides of the one-workgroup sort (4096 slots)
+    and past it, in ascending order, against the oracle."""
+    gv = need_gpu()
+    n = 1 << 14
+    degs = {1: 1, 2: 2, 3: 4095, 4: 4096, 5: 4097, 6: 9000, 7: 0}
+    rng = np.random.default_rng(B)
+    src = np.concatenate([np.full(dg, v, np.uint32) for v, dg in degs.items()])
+    dst = np.concatenate([rng.permutation(n)[:dg].astype(np.uint32) for dg in degs.values()])
+    g = gv.Graph(n, src, dst, block_slots=B)
+    o = O.OracleGraph(n, src, dst, block_slots=B)
+    # deletes leave adjacencies out of order before the reads
+    ds, dd = src[::3], dst[::3]
+    assert g.delete_edges(ds, dd) == o.delete_edges(ds, dd)[1]
+    for v in degs:
+        np.testing.assert_array_equal(u32(g.get_adjacency(v)), o.get_adjacency(v),
+                                      err_msg=f"vertex {v}")
+    g.close()
+
+
 # ---------------------------------------------------------------- mixed ops
 def _ops(rng, n, steps):
     for _ in range(steps):
