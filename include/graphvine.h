@@ -323,7 +323,7 @@ typedef struct {
  * (paper_2306_08252_amd/tuner.py) measures the settings per workload and
  * stores them in tuning.json; the binding applies them before creating a
  * plan.  Defaults: coalesce 0, max_run_pairs 0, small_sort_max 4096,
- * probe_group 32, probe_unroll 4, item_chunk 256.
+ * probe_group 32, probe_unroll 4, item_chunk 256, overlap 0.
  *   coalesce       gv_apply_ops and gv_plan_create apply every run of
  *                  consecutive edge batches (up to the next vertex batch) as
  *                  one mixed list (gv_apply_edge_ops): the same result as the
@@ -340,7 +340,21 @@ typedef struct {
  *   probe_unroll   adjacency slots per lane per search step: 2, 4 (default)
  *                  or 8
  *   item_chunk     adjacency slots per work item, a power of two in
- *                  [64, 4096] (default 256) */
+ *                  [64, 4096] (default 256)
+ *   overlap        0 (default) or 1.  With 1, an insert or delete batch of
+ *                  more than small_sort_max pairs queued by gv_insert_edges,
+ *                  gv_delete_edges or gv_apply_ops (not while the graph's
+ *                  stream is being captured) packs and sorts its pairs on a
+ *                  second stream of the library's own, while the graph's
+ *                  stream still runs the batches queued before it; the rest
+ *                  of the batch waits for that sort on the graph's stream.
+ *                  Results are those of overlap 0.  Contract: the batch's
+ *                  d_src / d_dst must hold their pairs when the call is made
+ *                  (written by a synchronous copy, or by work the caller has
+ *                  waited for), not only once the work queued ahead of the
+ *                  batch on the graph's stream has run; they must stay
+ *                  unchanged until that stream has run the batch.
+ *   reserved       must be 0 */
 typedef struct {
     uint32_t coalesce;
     uint32_t max_run_pairs;
@@ -348,7 +362,8 @@ typedef struct {
     uint32_t probe_group;
     uint32_t probe_unroll;
     uint32_t item_chunk;
-    uint32_t reserved[2];
+    uint32_t overlap;
+    uint32_t reserved;
 } gv_tuning;
 int gv_set_tuning(gv_graph* g, const gv_tuning* t);
 int gv_get_tuning(gv_graph* g, gv_tuning* t);

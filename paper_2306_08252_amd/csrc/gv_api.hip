@@ -48,6 +48,17 @@ void free_graph(gv_graph* g) {
     if (!g) return;
     hipStreamSynchronize(g->ctx.stream);
     g->ctx.release();
+    gv_graph::Overlap& o = g->ov;
+    if (o.stream) {
+        hipStreamSynchronize(o.stream);
+        o.ctx.release();
+        hipEvent_t evs[] = {o.sorted[0], o.sorted[1], o.done[0], o.done[1], o.fence};
+        for (hipEvent_t e : evs)
+            if (e) hipEventDestroy(e);
+        hipStreamDestroy(o.stream);
+        o.stream = nullptr;
+    }
+    o.scr.release();
     g->scratch.release();
     for (auto& v : g->vscr) v.release();
     g->cscr.release();
@@ -71,6 +82,13 @@ void check_sort(gv_graph* g) {
     if (g->hctr->err_order == 2) fail(GV_EDEVICE, "a batch's sorted keys were out of order");
     if (g->hctr->err_order == 4) fail(GV_EDEVICE, "a vertex delete exceeded a device-side bound");
     if (g->hctr->err_order) fail(GV_EDEVICE, "a batch's sorted keys were not its packed keys");
+}
+
+// Timed launches of both launch contexts (the graph's stream and the sort
+// overlap's side stream) folded into their per-name sums.
+void collect_all(gv_graph* g) {
+    g->ctx.collect();
+    g->ov.ctx.collect();
 }
 
 void fill_stats(gv_graph* g, gv_batch_stats* st) {
@@ -322,7 +340,8 @@ int gv_memory_used(gv_graph* g, gv_mem* out) {
         m.reserved_bytes = v.cap_blocks * m.block_bytes + 4ull * v.cap_blocks +
                            8ull * v.cap_blocks + 4ull * v.n_cap +
                            4ull * v.A * v.cap_blocks * v.B + m.directory_bytes +
-                           m.vertex_table_bytes + sizeof(DevCounters) + g->scratch.cap;
+                           m.vertex_table_bytes + sizeof(DevCounters) + g->scratch.cap +
+                           g->ov.scr.cap;
         *out = m;
     });
 }
@@ -377,7 +396,7 @@ int gv_get_counters(gv_graph* g, gv_counters* out) {
 int gv_profile_enable(gv_graph* g, int enable) {
     if (!g) return GV_EINVAL;
     return guarded(g, [&] {
-        g->ctx.collect();
+        collect_all(g);
         g->ctx.prof = enable != 0;
     });
 }
@@ -385,7 +404,7 @@ int gv_profile_enable(gv_graph* g, int enable) {
 int gv_profile_only(gv_graph* g, const char* name) {
     if (!g) return GV_EINVAL;
     return guarded(g, [&] {
-        g->ctx.collect();
+        collect_all(g);
         g->ctx.only = name ? name : "";
     });
 }
@@ -393,8 +412,9 @@ int gv_profile_only(gv_graph* g, const char* name) {
 int gv_profile_reset(gv_graph* g) {
     if (!g) return GV_EINVAL;
     return guarded(g, [&] {
-        g->ctx.collect();
+        collect_all(g);
         g->ctx.sums.clear();
+        g->ov.ctx.sums.clear();
     });
 }
 
@@ -403,12 +423,13 @@ int gv_kernel_times(gv_graph* g, const char* name, uint64_t* launches, double* t
     *launches = 0;
     *total_ms = 0;
     return guarded(g, [&] {
-        g->ctx.collect();
-        for (auto& s : g->ctx.sums)
-            if (s.name == name) {
-                *launches = s.launches;
-                *total_ms = s.ms;
-            }
+        collect_all(g);
+        for (const Ctx* c : {&g->ctx, &g->ov.ctx})
+            for (auto& s : c->sums)
+                if (s.name == name) {
+                    *launches += s.launches;
+                    *total_ms += s.ms;
+                }
     });
 }
 
@@ -416,10 +437,15 @@ int gv_kernel_names(gv_graph* g, char* buf, size_t cap, size_t* needed) {
     if (!g || !needed) return GV_EINVAL;
     std::string all;
     const int rc = guarded(g, [&] {
-        g->ctx.collect();
-        for (auto& s : g->ctx.sums) {
+        collect_all(g);
+        std::vector<std::string> names;
+        for (const Ctx* c : {&g->ctx, &g->ov.ctx})
+            for (auto& s : c->sums)
+                if (std::find(names.begin(), names.end(), s.name) == names.end())
+                    names.push_back(s.name);
+        for (auto& nm : names) {
             if (!all.empty()) all += ',';
-            all += s.name;
+            all += nm;
         }
     });
     if (rc != GV_OK) return rc;
@@ -434,6 +460,7 @@ int gv_set_tuning(gv_graph* g, const gv_tuning* t) {
     if (t->coalesce > 1 || t->small_sort_max > 4096) return GV_EINVAL;
     if (!probe_shape_ok(t->probe_group, t->probe_unroll)) return GV_EINVAL;
     if (t->item_chunk < 64 || t->item_chunk > 4096 || !pow2(t->item_chunk)) return GV_EINVAL;
+    if (t->overlap > 1 || t->reserved != 0) return GV_EINVAL;
     return guarded(g, [&] {
         hip_check(hipStreamSynchronize(g->ctx.stream), "hipStreamSynchronize");
         g->tune = *t;
@@ -460,6 +487,7 @@ int gv_set_stream(gv_graph* g, void* hip_stream) {
         g->ctx.collect();
         hip_check(hipStreamSynchronize(g->ctx.stream), "hipStreamSynchronize");
         g->ctx.stream = (hipStream_t)hip_stream;
+        ++g->ctx.seq;
     });
 }
 

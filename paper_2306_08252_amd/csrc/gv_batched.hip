@@ -307,6 +307,7 @@ int gv_plan_launch(gv_plan* p) {
         for (int k = 0; k < 3; ++k) same = same && g->vscr[k].gen == p->vscr_gen[k];
         if (!same) fail(GV_EINVAL, "graph buffers moved since the plan was created");
         hip_check(hipGraphLaunch(p->exec, g->ctx.stream), "hipGraphLaunch");
+        ++g->ctx.seq;
         g->edge_bound_host += p->insert_pairs;
     });
 }

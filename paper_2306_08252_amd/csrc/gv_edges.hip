@@ -120,6 +120,7 @@ struct BatchArrays {
     uint64_t state_words;
     uint32_t* vpart;    // insert / delete: valid pairs per packing workgroup
     unsigned long long* hpart;  // insert / delete: mix64 sum of valid keys per packing workgroup
+    unsigned long long* stot;   // overlapped sort: valid pairs and their mix64 sum
 };
 
 static void carve_batch(Carver& cv, BatchArrays& A, uint64_t n, uint64_t icap, EdgeMode mode,
@@ -160,6 +161,7 @@ static void carve_batch(Carver& cv, BatchArrays& A, uint64_t n, uint64_t icap, E
     A.state = cv.take<uint32_t>(os_words(n, bits));
     A.vpart = cv.take<uint32_t>(kHistGroups);
     A.hpart = cv.take<unsigned long long>(kHistGroups);
+    A.stot = cv.take<unsigned long long>(2);
 }
 
 __device__ __forceinline__ uint64_t thread_index() {
@@ -230,16 +232,17 @@ struct PackOut {
 // all-ones key of the sort's bit width, which sorts after every valid key.
 // All such keys are equal, so whether or not a valid pair shares that key,
 // the first n_valid sorted keys are exactly the valid ones.  The same kernel
-// clears the batch's look-back state and counters and counts the sort's
-// digits (per workgroup, summed by the next kernel together with the valid
-// pairs).
+// clears the batch's look-back state (and, with clear_ctr, the batch
+// counters) and counts the sort's digits (per workgroup, summed by the next
+// kernel together with the valid pairs).
 __global__ __launch_bounds__(kOsThreads) void k_pack_hist(GraphView g, const uint32_t* src,
                                                           const uint32_t* dst, uint64_t n,
                                                           int passes, uint64_t sentinel,
                                                           uint64_t* keys, uint8_t* mark,
                                                           uint32_t* state, uint64_t zero_words,
                                                           uint32_t* hpart, uint32_t* vpart,
-                                                          unsigned long long* kpart) {
+                                                          unsigned long long* kpart,
+                                                          int clear_ctr) {
     __shared__ uint32_t h[kOsHistCopies][8][kRadix];
     __shared__ uint32_t s_v[kOsWaves];
     __shared__ unsigned long long s_k[kOsWaves];
@@ -247,7 +250,7 @@ __global__ __launch_bounds__(kOsThreads) void k_pack_hist(GraphView g, const uin
     for (uint64_t i = (uint64_t)blockIdx.x * kOsThreads + t; i < zero_words;
          i += (uint64_t)gridDim.x * kOsThreads)
         state[i] = 0;
-    if (blockIdx.x == 0) clear_batch_counters(g.ctr, t);
+    if (clear_ctr && blockIdx.x == 0) clear_batch_counters(g.ctr, t);
     for (int i = t; i < kOsHistCopies * 8 * kRadix; i += kOsThreads) (&h[0][0][0])[i] = 0;
     __syncthreads();
     const uint32_t copy = kOsHistCopies == 1 ? 0u : (t >> 6) & (kOsHistCopies - 1);
@@ -1736,6 +1739,34 @@ void edge_attrs(gv_graph* g, const uint32_t* src, const uint32_t* dst, uint64_t 
     edge_run(g, kQuery, src, dst, nullptr, nullptr, n, found, true, nullptr, 0, nullptr, &op);
 }
 
+// First kernel of an overlapped batch on the graph's stream: clears the
+// batch counters and takes the valid-pair count and key sum that the batch's
+// packing left in its buffer.
+__global__ void k_ov_begin(GraphView g, const unsigned long long* stot) {
+    clear_batch_counters(g.ctr, threadIdx.x);
+    if (threadIdx.x == 0) {
+        g.ctr->tot[kTotValid] = stot[0];
+        g.ctr->tot[kTotHash] = stot[1];
+    }
+}
+
+// the side stream and events of the sort overlap, made on first use
+static void ov_open(gv_graph* g) {
+    gv_graph::Overlap& o = g->ov;
+    if (o.stream) return;
+    hip_check(hipStreamCreateWithFlags(&o.stream, hipStreamNonBlocking), "hipStreamCreate");
+    o.ctx.stream = o.stream;
+    hipEvent_t* evs[] = {&o.sorted[0], &o.sorted[1], &o.done[0], &o.done[1], &o.fence};
+    for (hipEvent_t* e : evs)
+        hip_check(hipEventCreateWithFlags(e, hipEventDisableTiming), "hipEventCreate");
+}
+
+static bool capturing(hipStream_t s) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    hip_check(hipStreamIsCapturing(s, &st), "hipStreamIsCapturing");
+    return st != hipStreamCaptureStatusNone;
+}
+
 static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t* dst,
                      const uint64_t* sorted, const unsigned long long* sorted_n, uint64_t n,
                      uint8_t* out, bool sticky, void* fixed, size_t fixed_bytes,
@@ -1747,6 +1778,11 @@ static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint
     const GraphView& v = g->v;
     const uint64_t icap = n + div_up(g->item_slots, (uint64_t)g->tune.item_chunk) + 1;
     const int bits = 2 * (int)v.L;
+    // sort overlap: this batch's pack and sort go to the side stream
+    const bool ovb = g->tune.overlap && !sorted && !fixed && mode != kQuery && bits > 0 &&
+                     n > std::min<uint64_t>(g->tune.small_sort_max, kOsTile) &&
+                     !capturing(c.stream);
+    const int ob = (int)(g->ov.count & 1);  // its buffer
     BatchArrays A;
     {
         Carver m(nullptr);
@@ -1755,8 +1791,11 @@ static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint
         if (fixed) {
             if (m.used > fixed_bytes) fail(GV_ERANGE, "batch does not fit the fixed scratch");
         } else {
-            g->scratch.ensure(m.used, c.stream);
-            base = g->scratch.ptr;
+            // a buffer that grows first synchronises the graph's stream, and
+            // with it every sort queued on the side stream
+            Scratch& buf = ovb && ob ? g->ov.scr : g->scratch;
+            buf.ensure(m.used, c.stream);
+            base = buf.ptr;
         }
         Carver cv(base);
         carve_batch(cv, A, n, icap, mode, bits);
@@ -1791,11 +1830,40 @@ static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint
         c.launch("pack", k_pack_sort_tile, 1, kOsThreads, v, src, dst, n, os_passes(bits),
                  sentinel, A.keys0, A.mark);
         flip = false;
+    } else if (ovb) {
+        // The side stream reads the pairs and the activity bitmap (which no
+        // edge batch changes) and writes only this batch's buffer: it waits
+        // for the graph's stream when anything else was queued there since
+        // the last overlapped batch, and for the batch that used the buffer
+        // before.  The batch counters are cleared on the graph's stream, once
+        // the batch before has finished with them.
+        gv_graph::Overlap& o = g->ov;
+        ov_open(g);
+        Ctx& sc = o.ctx;
+        sc.prof = c.prof;
+        sc.only = c.only;
+        if (c.seq != o.seq) {
+            hip_check(hipEventRecord(o.fence, c.stream), "hipEventRecord");
+            hip_check(hipStreamWaitEvent(o.stream, o.fence, 0), "hipStreamWaitEvent");
+        }
+        if (o.used[ob]) hip_check(hipStreamWaitEvent(o.stream, o.done[ob], 0), "hipStreamWaitEvent");
+        const uint64_t sentinel = bits >= 64 ? ~0ull : (1ull << bits) - 1;
+        sc.launch("pack", k_pack_hist, os_hist_groups(n), kOsThreads, v, src, dst, n,
+                  os_passes(bits), sentinel, A.keys0, A.mark, A.state, A.state_words,
+                  os_hpart(A.state, n, bits), A.vpart, A.hpart, 0);
+        os_hist_sum(sc, A.state, n, bits, (const uint32_t*)A.vpart, &A.stot[0],
+                    (const unsigned long long*)A.hpart, &A.stot[1]);
+        flip = onesweep_passes<uint64_t, false>(sc, A.keys0, A.keys1, nullptr, nullptr, nullptr, n,
+                                                bits, A.state, err, g->spin_limit, true);
+        sc.close_run();
+        hip_check(hipEventRecord(o.sorted[ob], o.stream), "hipEventRecord");
+        hip_check(hipStreamWaitEvent(c.stream, o.sorted[ob], 0), "hipStreamWaitEvent");
+        c.launch("pack", k_ov_begin, 1, 64, v, (const unsigned long long*)A.stot);
     } else {
         const uint64_t sentinel = bits >= 64 ? ~0ull : (1ull << bits) - 1;
         c.launch("pack", k_pack_hist, os_hist_groups(n), kOsThreads, v, src, dst, n,
                  bits > 0 ? os_passes(bits) : 0, sentinel, A.keys0, A.mark, A.state,
-                 A.state_words, os_hpart(A.state, n, bits), A.vpart, A.hpart);
+                 A.state_words, os_hpart(A.state, n, bits), A.vpart, A.hpart, 1);
         os_hist_sum(c, A.state, n, bits, (const uint32_t*)A.vpart, &tot[kTotValid],
                     (const unsigned long long*)A.hpart, &tot[kTotHash]);
         flip = onesweep_passes<uint64_t, false>(c, A.keys0, A.keys1, nullptr, nullptr, nullptr, n,
@@ -1870,6 +1938,13 @@ static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint
     if (mark_out && sorted)
         c.launch("marks", k_copy_marks, grid, kThreads, (const uint8_t*)A.mark, sorted_n, n,
                  mark_out);
+    if (ovb) {
+        gv_graph::Overlap& o = g->ov;
+        hip_check(hipEventRecord(o.done[ob], c.stream), "hipEventRecord");
+        o.used[ob] = true;
+        ++o.count;
+        o.seq = c.seq;
+    }
 }
 
 }  // namespace gv

@@ -13,13 +13,30 @@ struct gv_graph {
     gv::Scratch scratch;          // per-call temporaries
     gv::Scratch vscr[3];          // vertex-batch buffers that outlive an inner edge batch
     gv::Scratch cscr;             // a coalesced run of edge batches (batched form)
-    gv_tuning tune{0u, 0u, 4096u, 32u, 4u, 256u, {0u, 0u}};
+    gv_tuning tune{0u, 0u, 4096u, 32u, 4u, 256u, 0u, 0u};
     uint64_t table_gen = 0;       // counts reallocations of the vertex table or the pool
     uint64_t item_slots = 0;      // bound on live adjacency slots (pool slots)
     // upper bound on the edges stored, kept on the host without a read-back:
     // exact after each counter read, plus the pairs of every insert since
     uint64_t edge_bound_host = 0;
     uint32_t spin_limit = gv::kSpinLimitDefault;  // bound on each look-back wait of batch sorts
+    // Sort overlap (tune.overlap): a second stream packs and sorts each large
+    // insert / delete batch while the graph's stream runs the batches before
+    // it.  Batches alternate between two buffers: buffer 0 is `scratch`,
+    // buffer 1 is ov_scr.  Every sort on the side stream is followed on the
+    // graph's stream by a wait for its event, so whatever waits for the
+    // graph's stream has also waited for the side stream.
+    struct Overlap {
+        hipStream_t stream = nullptr;
+        gv::Ctx ctx;                      // launches on `stream`
+        gv::Scratch scr;                  // buffer 1
+        hipEvent_t sorted[2] = {nullptr, nullptr};  // side: the buffer's sort is done
+        hipEvent_t done[2] = {nullptr, nullptr};    // graph's stream: done with the buffer
+        hipEvent_t fence = nullptr;       // graph's stream: all work queued before a batch
+        bool used[2] = {false, false};    // done[k] has been recorded
+        uint64_t count = 0;               // overlapped batches (next buffer = count & 1)
+        uint64_t seq = ~0ull;             // ctx.seq after the last overlapped batch
+    } ov;
     // device allocations owned by the graph
     void* mem_pool = nullptr;
     void* mem_free = nullptr;

@@ -75,6 +75,7 @@ uint64_t resident_grid(void (*kernel)(KArgs...), uint32_t block) {
 // kernels' own durations.
 struct Ctx {
     hipStream_t stream = nullptr;
+    uint64_t seq = 0;  // operations queued so far (launches, recorded graphs)
     bool prof = false;
     std::string only;  // when non-empty, only launches of this name are timed
     struct Rec {
@@ -155,6 +156,7 @@ struct Ctx {
                 Args... args) {
         if (grid == 0) return;
         if (grid > 0x7fffffffull) fail(GV_EINVAL, "grid too large");
+        ++seq;
         const bool timed = prof && (only.empty() || only == name);
         if (prof && !only.empty()) {
             // runs of the one timed kernel

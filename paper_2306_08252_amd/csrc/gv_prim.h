@@ -932,10 +932,12 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const K* kin, K* kout, c
     }
 }
 
+// concurrent: other kernels may hold compute units while the passes run
+// (work on another stream), so tiles take tickets in launch order
 template <typename K, bool HasVal>
 bool onesweep_passes(Ctx& c, K* k0, K* k1, uint32_t* v0, uint32_t* v1, const uint32_t* n_dev,
                      uint64_t n_max, int bits, uint32_t* state, uint32_t* err,
-                     uint32_t spin_limit = kSpinLimit);
+                     uint32_t spin_limit = kSpinLimit, bool concurrent = false);
 
 // Look-back counts are 30-bit fields of the status words: a sort takes fewer
 // than 2^30 keys.
@@ -989,7 +991,7 @@ inline void os_hist_sum(Ctx& c, uint32_t* state, uint64_t n_max, int bits, const
 template <typename K, bool HasVal>
 bool onesweep_passes(Ctx& c, K* k0, K* k1, uint32_t* v0, uint32_t* v1, const uint32_t* n_dev,
                      uint64_t n_max, int bits, uint32_t* state, uint32_t* err,
-                     uint32_t spin_limit) {
+                     uint32_t spin_limit, bool concurrent) {
     if (n_max <= 1 || bits <= 0) return false;
     if (n_max >= kOsMaxKeys) fail(GV_EINVAL, "sort of 2^30 or more keys");
     const int passes = os_passes(bits);
@@ -1000,7 +1002,8 @@ bool onesweep_passes(Ctx& c, K* k0, K* k1, uint32_t* v0, uint32_t* v1, const uin
     uint32_t* gstatus = status + (uint64_t)passes * nt * kRadix;  // passes * groups * 256
     const uint64_t ng = os_groups(n_max);
     uint32_t* hist = state + os_zero_words(n_max, bits);  // passes * 256 counters
-    const int block_tiles = nt <= resident_grid(k_os_pass<K, HasVal>, kOsThreads) ? 1 : 0;
+    const int block_tiles =
+        !concurrent && nt <= resident_grid(k_os_pass<K, HasVal>, kOsThreads) ? 1 : 0;
     bool flip = false;
     for (int p = 0; p < passes; ++p) {
         K* kin = flip ? k1 : k0;

@@ -68,11 +68,11 @@ class gv_counters(C.Structure):
 
 
 TUNING_FIELDS = ("coalesce", "max_run_pairs", "small_sort_max", "probe_group", "probe_unroll",
-                 "item_chunk")
+                 "item_chunk", "overlap")
 
 
 class gv_tuning(C.Structure):
-    _fields_ = [(f, C.c_uint32) for f in TUNING_FIELDS] + [("reserved", C.c_uint32 * 2)]
+    _fields_ = [(f, C.c_uint32) for f in TUNING_FIELDS] + [("reserved", C.c_uint32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f in TUNING_FIELDS}

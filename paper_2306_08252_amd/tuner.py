@@ -151,8 +151,9 @@ def measure_steps(gv, w, ins, dels, dev, B, tuning, warmup=2, steps=4):
 
 
 def tune_steps(gv, w, ins, dels, dev, B, log=print):
-    """Coordinate descent over the probe's shape and the work-item size for
-    the benchmark's step; returns (best setting, measured points in ms)."""
+    """Coordinate descent over the sort overlap, the probe's shape and the
+    work-item size for the benchmark's step; returns (best setting, measured
+    points in ms)."""
     points, want = {}, None
 
     def run(s):
@@ -168,7 +169,8 @@ def tune_steps(gv, w, ins, dels, dev, B, log=print):
             log(f"tuner: {s} -> {el * 1e3:.3f} ms per step")
         return points[k]
 
-    best = descend(dict(DEFAULT_PROBE), PROBE_SPACE + PROBE_SPACE[:2], run)
+    space = [("overlap", [0, 1])] + PROBE_SPACE + PROBE_SPACE[:2]
+    best = descend(dict(DEFAULT_PROBE, overlap=0), space, run)
     return best, {k: round(v * 1e3, 4) for k, v in points.items()}
 
 

@@ -169,11 +169,12 @@ def test_tuning_rejects_bad_values():
     with pytest.raises(gv.GraphVineError):
         gv.gv_set_tuning(g.h, small_sort_max=4097)
     for bad in ({"probe_group": 8}, {"probe_unroll": 3}, {"item_chunk": 100},
-                {"item_chunk": 8192}):
+                {"item_chunk": 8192}, {"overlap": 2}):
         with pytest.raises(gv.GraphVineError):
             gv.gv_set_tuning(g.h, **bad)
     assert gv.gv_get_tuning(g.h) == {"coalesce": 0, "max_run_pairs": 0, "small_sort_max": 4096,
-                                     "probe_group": 32, "probe_unroll": 4, "item_chunk": 256}
+                                     "probe_group": 32, "probe_unroll": 4, "item_chunk": 256,
+                                     "overlap": 0}
     g.close()
 
 

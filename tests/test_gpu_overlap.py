@@ -1,0 +1,153 @@
+"""Sort overlap (gv_tuning.overlap = 1): a large insert or delete batch packs
+and sorts its pairs on the library's second stream while the graph's stream
+still runs the batches queued before it.  The results must be the oracle's,
+element by element (bit-exact), whatever is queued between the batches:
+back-to-back edge batches (the two batch buffers alternate), buffers that
+grow, small batches and queries on the graph's stream, vertex batches that
+change the activity bitmap the packing reads, and profiling."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import assert_same, need_gpu, say
+from oracle import pyoracle as O
+from paper_2306_08252_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _host(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+@pytest.mark.parametrize("B", [4, 16])
+def test_back_to_back_batches_match_oracle(B):
+    gv = need_gpu()
+    scale, m = 14, 1 << 17
+    w = I.RmatWorkload(scale, m, name="ov")
+    g = gv.Graph(w.num_vertices, w.src, w.dst, block_slots=B)
+    assert gv.gv_set_tuning(g.h, overlap=1)["overlap"] == 1
+    o = O.OracleGraph(w.num_vertices, w.src, w.dst, block_slots=B)
+    # buffer 0 takes the inserts and buffer 1 the deletes; the 65536-pair
+    # batch and the 70000-pair batch make both buffers grow mid-sequence
+    sizes = [20000, 5000, 65536, 4097, 30001, 12000, 8000, 70000]
+    ins = [tuple(gv.as_device_u32(a, g.device) for a in w.insert_batch(k, j))
+           for j, k in enumerate(sizes)]
+    dels = [tuple(gv.as_device_u32(a, g.device) for a in w.delete_batch(k, j))
+            for j, k in enumerate(sizes)]
+    torch.cuda.synchronize()
+    say(f"overlap back-to-back B={B}")
+    for j in range(len(sizes)):  # no host synchronisation between the calls
+        g.insert_edges(*ins[j], stats=False)
+        g.delete_edges(*dels[j], stats=False)
+    assert g.sync() == 0
+    for j in range(len(sizes)):
+        o.insert_edges(*map(_host, ins[j]))
+        o.delete_edges(*map(_host, dels[j]))
+    assert_same(g, o, "after the back-to-back batches")
+    # with statistics (a read-back after each batch)
+    for j in range(3):
+        s, d = w.insert_batch(9000 + j, 50 + j)
+        assert g.insert_edges(s, d) == o.insert_edges(s, d)[1], f"insert {j}"
+        s, d = w.delete_batch(9000 + j, 50 + j)
+        assert g.delete_edges(s, d) == o.delete_edges(s, d)[1], f"delete {j}"
+    assert_same(g, o, "after batches with statistics")
+    g.close()
+
+
+def test_interleaved_work_matches_oracle():
+    """Queries, small batches and vertex batches between overlapped batches
+    (the side stream then waits for the graph's stream), all queued without
+    a host synchronisation; query answers are compared at the end with the
+    oracle's answers at the same point of the sequence."""
+    gv = need_gpu()
+    n, B = 6000, 8
+    rng = np.random.default_rng(7)
+    s0 = rng.integers(0, n, 8 * n).astype(np.uint32)
+    d0 = rng.integers(0, n, 8 * n).astype(np.uint32)
+    g = gv.Graph(n, s0, d0, block_slots=B, vertex_capacity=2 * n)
+    gv.gv_set_tuning(g.h, overlap=1)
+    o = O.OracleGraph(n, s0, d0, block_slots=B, vertex_capacity=2 * n)
+    say("overlap interleaved")
+    answers = []
+    ops = []
+    for step in range(14):
+        kind = ["ins", "del", "q", "small", "vdel", "vins", "ins", "del"][step % 8]
+        if kind in ("ins", "del", "q", "small"):
+            k = 300 if kind == "small" else int(rng.integers(5000, 40000))
+            s = rng.integers(0, 2 * n, k).astype(np.uint32)
+            d = rng.integers(0, 2 * n, k).astype(np.uint32)
+            if kind != "q":
+                rep = rng.integers(0, k, k // 4)  # duplicates within the batch
+                s = np.concatenate([s, s[rep]])
+                d = np.concatenate([d, d[rep]])
+            ops.append((kind, gv.as_device_u32(s, g.device), gv.as_device_u32(d, g.device)))
+        else:
+            ids = rng.integers(0, 2 * n, 200).astype(np.uint32)
+            ops.append((kind, gv.as_device_u32(ids, g.device), None))
+    torch.cuda.synchronize()
+    for kind, a, b in ops:
+        if kind in ("ins", "small"):
+            g.insert_edges(a, b, stats=False)
+            o.insert_edges(_host(a), _host(b))
+        elif kind == "del":
+            g.delete_edges(a, b, stats=False)
+            o.delete_edges(_host(a), _host(b))
+        elif kind == "q":
+            answers.append((g.edge_exists(a, b), o.edge_exists(_host(a), _host(b))))
+        else:
+            # vertex batches through the batched form: no read-back either
+            code = gv.OP_DELETE_VERTICES if kind == "vdel" else gv.OP_INSERT_VERTICES
+            gv.gv_apply_ops(g.h, [(code, a, None)], g.device)
+            (o.delete_vertices if kind == "vdel" else o.insert_vertices)(_host(a))
+    assert g.sync() == 0
+    for j, (got, want) in enumerate(answers):
+        np.testing.assert_array_equal(got.cpu().numpy(), want, err_msg=f"query {j}")
+    assert_same(g, o, "after the interleaved sequence")
+    g.close()
+
+
+def test_batched_form_and_profiling_with_overlap():
+    """gv_apply_ops runs its edge batches overlapped; a plan recorded with
+    overlap on records no side-stream work and gives the same graph; the
+    side stream's launches are timed with the graph's profiling."""
+    gv = need_gpu()
+    scale, m, B = 13, 1 << 16, 8
+    w = I.RmatWorkload(scale, m, name="ovb")
+    ops = []
+    for j in range(6):
+        ops.append((gv.OP_INSERT_EDGES, *w.insert_batch(6000 + 1000 * j, j)))
+        ops.append((gv.OP_DELETE_EDGES, *w.delete_batch(5000 + 1000 * j, j)))
+    ops.insert(5, (gv.OP_DELETE_VERTICES, np.arange(3, 40, 3, dtype=np.uint32), None))
+    graphs = []
+    for form in ("eager", "plan"):
+        g = gv.Graph(w.num_vertices, w.src, w.dst, block_slots=B)
+        gv.gv_set_tuning(g.h, overlap=1)
+        say(f"overlap batched form {form}")
+        if form == "eager":
+            gv.gv_profile_enable(g.h, True)
+            gv.gv_profile_only(g.h, "sort_pass")
+            keep = gv.gv_apply_ops(g.h, ops, g.device)
+            assert g.sync() == 0
+            launches, ms = gv.gv_kernel_times(g.h, "sort_pass")
+            gv.gv_profile_enable(g.h, False)
+            del keep
+            # 12 edge batches of 2 * 13 = 26-bit keys: 4 passes each
+            assert launches == 12 * 4 and ms > 0
+        else:
+            plan = gv.Plan(g.h, ops, g.device)
+            plan.launch()
+            assert g.sync() == 0
+            plan.close()
+        graphs.append(g)
+    o = O.OracleGraph(w.num_vertices, w.src, w.dst, block_slots=B)
+    for kind, a, b in ops:
+        if kind == gv.OP_INSERT_EDGES:
+            o.insert_edges(a, b)
+        elif kind == gv.OP_DELETE_EDGES:
+            o.delete_edges(a, b)
+        else:
+            o.delete_vertices(a)
+    for g, label in zip(graphs, ("eager", "plan")):
+        assert_same(g, o, label)
+        g.close()
