@@ -311,9 +311,16 @@ enum {
     GV_OP_INSERT_VERTICES = 2, /* a = ids, n ids (b unused) */
     GV_OP_DELETE_VERTICES = 3  /* a = ids, n ids (b unused) */
 };
+/* gv_op.flags: 0, or for a vertex insert run by gv_apply_ops,
+ * GV_OP_FIT_TABLE: the caller knows every id is below the vertex capacity,
+ * so the op neither grows the dictionary nor reads the device back (no host
+ * wait); an id at or past the capacity then fails the op with a sticky
+ * GV_ERANGE, as in a plan.  Any other flag, or the flag on another kind of
+ * op, is GV_EINVAL. */
+enum { GV_OP_FIT_TABLE = 1 };
 typedef struct {
     uint32_t kind;
-    uint32_t reserved;
+    uint32_t flags;
     const uint32_t* a;
     const uint32_t* b;
     uint64_t n;

@@ -122,6 +122,8 @@ int check_ops(const gv_op* ops, uint64_t n_ops) {
     for (uint64_t i = 0; i < n_ops; ++i) {
         const gv_op& op = ops[i];
         if (op.kind > GV_OP_DELETE_VERTICES) return GV_EINVAL;
+        if (op.flags & ~(uint32_t)GV_OP_FIT_TABLE) return GV_EINVAL;
+        if (op.flags && op.kind != GV_OP_INSERT_VERTICES) return GV_EINVAL;
         if (op.n && !op.a) return GV_EINVAL;
         if (op.n && op.kind <= GV_OP_DELETE_EDGES && !op.b) return GV_EINVAL;
         if (op.n >= 0x3fffffffull) return GV_EINVAL;
@@ -141,7 +143,7 @@ void run_op(gv_graph* g, const gv_op& op, bool recorded, uint64_t bound) {
             edge_batch(g, kDelete, op.a, op.b, op.n, nullptr, true);
             break;
         case GV_OP_INSERT_VERTICES:
-            vertex_insert(g, op.a, op.n, nullptr, recorded);
+            vertex_insert(g, op.a, op.n, nullptr, recorded || (op.flags & GV_OP_FIT_TABLE));
             break;
         default:
             vertex_delete(g, op.a, op.n, nullptr, recorded ? bound : 0);

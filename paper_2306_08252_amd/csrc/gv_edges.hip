@@ -1845,8 +1845,10 @@ static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint
         if (c.seq != o.seq) {
             hip_check(hipEventRecord(o.fence, c.stream), "hipEventRecord");
             hip_check(hipStreamWaitEvent(o.stream, o.fence, 0), "hipStreamWaitEvent");
+        } else if (o.used[ob]) {
+            // (with a fence, the wait for the graph's stream covers this one)
+            hip_check(hipStreamWaitEvent(o.stream, o.done[ob], 0), "hipStreamWaitEvent");
         }
-        if (o.used[ob]) hip_check(hipStreamWaitEvent(o.stream, o.done[ob], 0), "hipStreamWaitEvent");
         const uint64_t sentinel = bits >= 64 ? ~0ull : (1ull << bits) - 1;
         sc.launch("pack", k_pack_hist, os_hist_groups(n), kOsThreads, v, src, dst, n,
                   os_passes(bits), sentinel, A.keys0, A.mark, A.state, A.state_words,

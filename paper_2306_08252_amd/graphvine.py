@@ -79,11 +79,12 @@ class gv_tuning(C.Structure):
 
 
 class gv_op(C.Structure):
-    _fields_ = [("kind", C.c_uint32), ("reserved", C.c_uint32), ("a", C.c_void_p),
+    _fields_ = [("kind", C.c_uint32), ("flags", C.c_uint32), ("a", C.c_void_p),
                 ("b", C.c_void_p), ("n", C.c_uint64)]
 
 
 OP_INSERT_EDGES, OP_DELETE_EDGES, OP_INSERT_VERTICES, OP_DELETE_VERTICES = 0, 1, 2, 3
+OP_FIT_TABLE = 1  # gv_op.flags: a vertex insert whose ids fit the table (no host wait)
 
 _lib = None
 
@@ -541,13 +542,16 @@ class Graph:
 
 # ------------------------------------------------------------------ batched form
 def _ops(ops, device):
-    """[(kind, a, b or None)] -> (gv_op array, device tensors kept alive)."""
+    """[(kind, a, b or None[, flags])] -> (gv_op array, device tensors kept
+    alive)."""
     arr = (gv_op * max(len(ops), 1))()
     keep = []
-    for i, (kind, a, b) in enumerate(ops):
+    for i, op in enumerate(ops):
+        kind, a, b = op[:3]
         ta = as_device_u32(a, device)
         keep.append(ta)
         arr[i].kind = kind
+        arr[i].flags = op[3] if len(op) > 3 else 0
         arr[i].a = ta.data_ptr() if ta.numel() else None
         arr[i].n = ta.numel()
         if kind in (OP_INSERT_EDGES, OP_DELETE_EDGES):

@@ -14,8 +14,11 @@ and its answers come back by an asynchronous copy; requests that arrive
 meanwhile form the next tick.  Vertex requests end a tick and run alone: a
 vertex delete is queued in stream order like a tick (it only frees blocks,
 so the host's free-block count stays a lower bound, and the library sizes
-its lists without reading the device back); a vertex insert waits for the
-running ticks (it may grow the dictionary).  A request completes when its
+its lists without reading the device back); so is a vertex insert whose ids
+all fit the vertex table (checked on a second stream, which waits for
+nothing queued after the server started), queued with GV_OP_FIT_TABLE so
+that it never reads the device back; one with an id past the table waits
+for the running ticks (it grows the dictionary).  A request completes when its
 tick's event has passed; latency is completion time minus scheduled arrival
 time (open loop, so a late server does not lower the arrival rate).
 
@@ -42,6 +45,7 @@ import torch
 from . import graphvine as gv
 
 INSERT, DELETE, QUERY, VINSERT, VDELETE = 0, 1, 2, 3, 4
+VINSERT_OP, VDELETE_OP = 2, 3  # their gv_op kinds
 
 
 def _size(req):
@@ -127,8 +131,9 @@ def serve(graph, requests, arrivals=None, max_tick_pairs=1 << 20, keep_answers=F
     formed, while up to `max_inflight - 1` earlier ticks are still running,
     so requests that arrive meanwhile form the next tick and run right after
     (stream order keeps the commit order); a tick's requests complete when
-    its event has passed.  A vertex insert waits for every running tick; a
-    vertex delete is queued like a tick.
+    its event has passed.  A vertex insert whose ids fit the vertex table,
+    and a vertex delete, are queued like a tick; a vertex insert that grows
+    the table waits for every running tick.
     Returns (completion times, ticks as (first, end) request ranges, answers
     of the query requests by index if keep_answers).  Indices of requests
     rejected by admission are appended to `rejected` (a list) if given; a
@@ -148,6 +153,21 @@ def serve(graph, requests, arrivals=None, max_tick_pairs=1 << 20, keep_answers=F
     answers = {}
     flight = []
     ring = _PinnedRing(max_inflight + 1)
+    # the id check of vertex inserts runs on a second stream (default
+    # priority), after the work queued before the server started (which made
+    # the requests) and independent of the ticks queued since
+    side = torch.cuda.Stream(device=dev)
+    start = torch.cuda.Event()
+    start.record(torch.cuda.current_stream(dev))
+    side.wait_event(start)
+
+    def fits_table(ids):
+        if ids.numel() == 0:
+            return True
+        with torch.cuda.stream(side):
+            top = int((ids.to(torch.int64) & 0xFFFFFFFF).max())  # waits on `side` only
+        return top < vcap
+
     t0 = clock()
 
     def retire(block):
@@ -182,7 +202,17 @@ def serve(graph, requests, arrivals=None, max_tick_pairs=1 << 20, keep_answers=F
         kind = requests[i][0]
         if kind == VDELETE:
             # queued behind the running ticks, no host wait
-            keep = gv.gv_apply_ops(graph.h, [(3, requests[i][1], None)], dev)
+            keep = gv.gv_apply_ops(graph.h, [(VDELETE_OP, requests[i][1], None)], dev)
+            ev = torch.cuda.Event()
+            ev.record(torch.cuda.current_stream(dev))
+            flight.append({"range": (i, i + 1), "event": ev, "queries": [], "answers": None,
+                           "keep": keep, "writes": [], "stats": None})
+            ticks.append((i, i + 1))
+            i += 1
+            continue
+        if kind == VINSERT and fits_table(requests[i][1]):
+            keep = gv.gv_apply_ops(graph.h, [(VINSERT_OP, requests[i][1], None,
+                                              gv.OP_FIT_TABLE)], dev)
             ev = torch.cuda.Event()
             ev.record(torch.cuda.current_stream(dev))
             flight.append({"range": (i, i + 1), "event": ev, "queries": [], "answers": None,
@@ -197,6 +227,7 @@ def serve(graph, requests, arrivals=None, max_tick_pairs=1 << 20, keep_answers=F
             done[i] = clock() - t0
             ticks.append((i, i + 1))
             free = free_blocks(graph)
+            vcap = graph.info()["vertex_capacity"]  # the table may have grown
             i += 1
             continue
         j, pairs, need, fresh = i, 0, 0, False

@@ -126,7 +126,7 @@ def tune(gv, w, ops, dev, warm, log=print, form="plan"):
     return best, {k: round(v * 1e3, 3) for k, v in points.items()}
 
 
-def measure_steps(gv, w, ins, dels, dev, B, tuning, warmup=2, steps=4):
+def measure_steps(gv, w, ins, dels, dev, B, tuning, warmup=2, steps=10):
     """ms per insert + delete step on a fresh graph with the given tuning
     (the same batches for every setting), and the resulting (checksum, edges)."""
     import torch
@@ -198,8 +198,8 @@ def main():
         scale = args.scale or 20
         edges = args.edges or 1 << 24
         w = T.RmatWorkload(scale, edges, device=dev)
-        ins = [w.insert_batch(args.batch, 1000 + j) for j in range(6)]
-        dels = [w.delete_batch(args.batch, 1000 + j) for j in range(6)]
+        ins = [w.insert_batch(args.batch, 1000 + j) for j in range(12)]
+        dels = [w.delete_batch(args.batch, 1000 + j) for j in range(12)]
         best, points = tune_steps(gv, w, ins, dels, dev, args.block_slots)
         key = steps_key(scale, edges, args.batch, args.block_slots)
         store(key, {"setting": best, "ms": points[json.dumps(best, sort_keys=True)],

@@ -110,7 +110,11 @@ def test_served_ticks_match_oracle_replay():
     for j in range(120):
         kind = int(rng.choice(5, p=[0.35, 0.35, 0.2, 0.05, 0.05]))
         size = int(np.exp(rng.random() * np.log(3000))) + 1
-        if kind in (S.VINSERT, S.VDELETE):
+        if j == 90:
+            # ids past the table: this vertex insert grows it, waiting for
+            # the running ticks (the others are queued without a wait)
+            host.append((S.VINSERT, np.array([n + 1, n + 7, 3], np.uint32), None))
+        elif kind in (S.VINSERT, S.VDELETE):
             ids = rng.integers(0, n, min(size, 40)).astype(np.uint32)
             host.append((kind, ids, None))
         else:

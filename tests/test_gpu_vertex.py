@@ -82,3 +82,37 @@ def test_vertex_delete_in_a_plan_matches_eager():
     plan.close()
     ga.close()
     gb.close()
+
+
+def test_fit_table_vertex_insert_flag():
+    """GV_OP_FIT_TABLE: a vertex insert through gv_apply_ops that neither
+    grows the table nor reads the device back gives the plain insert's
+    result when its ids fit; an id past the table leaves a sticky GV_ERANGE
+    (the fitting ids are still inserted); the flag on another op kind, or an
+    unknown flag, is GV_EINVAL."""
+    gv = need_gpu()
+    n, cap = 1000, 1024
+    s0, d0 = I.uniform_pairs(I.stream_seed("fit-table", 1), 5000, n)
+    g = gv.Graph(n, s0, d0, block_slots=8, vertex_capacity=cap)
+    o = O.OracleGraph(n, s0, d0, block_slots=8, vertex_capacity=cap)
+    dels = np.arange(0, 60, 3, dtype=np.uint32)
+    g.delete_vertices(dels)
+    o.delete_vertices(dels)
+    ids = np.array([1023, 5, 3, 1001, 1023, 0xFFFFFFFF, 6], np.uint32)
+    gv.gv_apply_ops(g.h, [(gv.OP_INSERT_VERTICES, ids, None, gv.OP_FIT_TABLE)], g.device)
+    o.insert_vertices(ids)
+    assert g.sync() == 0
+    assert_same(g, o, "fitting ids")
+    gv.gv_apply_ops(g.h, [(gv.OP_INSERT_VERTICES, np.array([2000, 9], np.uint32), None,
+                           gv.OP_FIT_TABLE)], g.device)
+    o.insert_vertices(np.array([9], np.uint32))
+    assert g.sync() == gv.GV_ERANGE
+    assert g.info()["vertex_capacity"] == cap
+    assert_same(g, o, "an id past the table")
+    s, d = np.array([1, 2], np.uint32), np.array([3, 4], np.uint32)
+    for bad in ([(gv.OP_INSERT_EDGES, s, d, gv.OP_FIT_TABLE)],
+                [(gv.OP_DELETE_VERTICES, s, None, gv.OP_FIT_TABLE)],
+                [(gv.OP_INSERT_VERTICES, s, None, 2)]):
+        with pytest.raises(gv.GraphVineError):
+            gv.gv_apply_ops(g.h, bad, g.device)
+    g.close()
