@@ -184,7 +184,13 @@ __global__ __launch_bounds__(kThreads) void k_mixed_flags(
     fref[p] = ref;
 }
 
-// one workgroup per request (grid-stride): its three counts
+// Per-request counts, added into zeroed stats: each thread takes
+// kStatItems consecutive entries.  A wave whose entries all belong to one
+// request adds its sums from one lane; otherwise each lane adds its own sums
+// per request it covers.  Entries at or past the ends of every request are
+// not counted (so ends that are not ascending give wrong counts, never reads
+// out of bounds).
+constexpr uint32_t kStatItems = 8;
 __global__ __launch_bounds__(kThreads) void k_request_stats(const uint64_t* end, uint64_t n_req,
                                                             uint64_t n,
                                                             const uint8_t* flag,
@@ -192,30 +198,50 @@ __global__ __launch_bounds__(kThreads) void k_request_stats(const uint64_t* end,
                                                             const uint8_t* del_found,
                                                             const uint8_t* ins_had,
                                                             gv_batch_stats* stats) {
-    __shared__ unsigned long long lds[kWaves];
-    for (uint64_t r = blockIdx.x; r < n_req; r += gridDim.x) {
-        // ends are clamped to the list, so bad ends give bad counts, not bad reads
-        const uint64_t hi = min(end[r], n), lo = r ? min(end[r - 1], hi) : 0ull;
-        unsigned long long a = 0, d = 0, j = 0;
-        for (uint64_t p = lo + threadIdx.x; p < hi; p += kThreads) {
-            const uint8_t f = flag[p];
-            if (f == kFApplied) {
-                ++a;
-            } else if (f == kFDup) {
-                ++d;
-            } else if (f == kFRej) {
-                ++j;
-            } else if (f >= kFNeedIns) {
-                const uint32_t ref = fref[p];
-                const bool present = (ref & kRefIns) ? ins_had[ref & ~kRefIns] != 0
-                                                     : del_found[ref] != 0;
-                a += (f == kFNeedIns) != present;
-            }
+    const uint64_t p0 = ((uint64_t)blockIdx.x * kThreads + threadIdx.x) * kStatItems;
+    const bool live = p0 < n;
+    uint32_t r = live ? request_of(end, (uint32_t)n_req, p0) : (uint32_t)n_req;
+    unsigned long long a = 0, d = 0, j = 0;
+    bool moved = false;  // the lane's entries span more than one request
+    auto add = [&](uint32_t q) {
+        if (q >= n_req) return;
+        if (a) atomicAdd((unsigned long long*)&stats[q].applied, a);
+        if (j) atomicAdd((unsigned long long*)&stats[q].rejected, j);
+        if (d) atomicAdd((unsigned long long*)&stats[q].batch_duplicates, d);
+    };
+    for (uint32_t k = 0; k < kStatItems; ++k) {
+        const uint64_t p = p0 + k;
+        if (p >= n) break;
+        if (r < n_req && end[r] <= p) {
+            // the next request whose range holds p
+            add(r);
+            a = d = j = 0;
+            moved = true;
+            r = request_of(end, (uint32_t)n_req, p);
         }
-        a = block_sum(a, lds);
-        d = block_sum(d, lds);
-        j = block_sum(j, lds);
-        if (threadIdx.x == 0) stats[r] = gv_batch_stats{a, j, d};
+        const uint8_t f = flag[p];
+        if (f == kFApplied) {
+            ++a;
+        } else if (f == kFDup) {
+            ++d;
+        } else if (f == kFRej) {
+            ++j;
+        } else if (f >= kFNeedIns) {
+            const uint32_t ref = fref[p];
+            const bool present = (ref & kRefIns) ? ins_had[ref & ~kRefIns] != 0
+                                                 : del_found[ref] != 0;
+            a += (f == kFNeedIns) != present;
+        }
+    }
+    // lane 0 is live whenever any lane of its wave is (p0 grows with the lane)
+    const uint32_t r0 = (uint32_t)__shfl((int)r, 0, 64);
+    if (ballot(live && (moved || r != r0)) == 0) {
+        a = wave_sum(a);
+        d = wave_sum(d);
+        j = wave_sum(j);
+        if (lane_id() == 0 && live) add(r);
+    } else if (live) {
+        add(r);
     }
 }
 
@@ -317,10 +343,12 @@ void mixed_edges(gv_graph* g, const uint8_t* op, const uint32_t* src, const uint
                  (const uint64_t*)ins_keys, (const unsigned long long*)cnt, flag, fref);
     edge_batch_sorted(g, kDelete, del_keys, &cnt[1], n, true, del_found);
     edge_batch_sorted(g, kInsert, ins_keys, &cnt[2], n, true, ins_had);
-    if (stats)
-        c.launch("mixed_stats", k_request_stats, std::min<uint64_t>(n_req, 4096), kThreads,
-                 end, n_req, n, (const uint8_t*)flag, (const uint32_t*)fref,
+    if (stats) {
+        c.launch("mixed_stats", k_stats_zero, div_up(n_req, kThreads), kThreads, stats, n_req);
+        c.launch("mixed_stats", k_request_stats, div_up(n, (uint64_t)kThreads * kStatItems),
+                 kThreads, end, n_req, n, (const uint8_t*)flag, (const uint32_t*)fref,
                  (const uint8_t*)del_found, (const uint8_t*)ins_had, stats);
+    }
 }
 
 }  // namespace gv

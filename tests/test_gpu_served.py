@@ -69,10 +69,12 @@ def test_mixed_request_stats_match_oracle(n, B, seed):
     dead = rng.choice(n, n // 10, replace=False).astype(np.uint32)
     g.delete_vertices(dead)
     o.delete_vertices(dead)
-    for rep in range(3):
+    for rep in range(4):
         reqs = []
-        for r in range(60):
-            size = int(rng.integers(0, 200)) if r % 17 else 0
+        # the last list: a few large requests, each over many workgroups
+        big = [int(rng.integers(9000, 30000)), 0, int(rng.integers(3000, 9000)), 2049]
+        for r in range(60 if rep < 3 else len(big)):
+            size = big[r] if rep == 3 else int(rng.integers(0, 200)) if r % 17 else 0
             op, s, d = mixed_list(rng, n, size, s0, d0, few=8)
             kind = 2 if r % 23 == 5 else int(rng.integers(0, 2))
             reqs.append((kind, s, d))
