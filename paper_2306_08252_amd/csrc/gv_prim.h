@@ -526,13 +526,90 @@ struct TileSortLds {
     uint64_t skey[kOsTile];
 };
 
+// Tiles of at most kTileBitonicMax keys are sorted by a bitonic network in
+// LDS over (key, input position) pairs: the positions make the pairs
+// distinct and order equal keys as they came, so the result is the stable
+// order the radix passes give (for keys below 2^(8 * passes)), in
+// log2(m) (log2(m) + 1) / 2 barrier steps for m keys padded to a power of
+// two, instead of five barriers per radix pass.
+constexpr uint64_t kTileBitonicMax = 2048;
+
+__device__ __forceinline__ void tile_bitonic(uint64_t (&key)[kOsRounds], uint32_t n,
+                                             uint64_t sentinel, TileSortLds& L) {
+    static_assert(kTileBitonicMax <= kOsTile, "the network works in the tile's LDS");
+    static_assert(sizeof(L.cnt) >= kTileBitonicMax * sizeof(uint16_t), "room for positions");
+    const uint32_t t = threadIdx.x;
+    uint16_t* pos = &L.cnt[0][0];
+    uint32_t m = 2;
+    while (m < n) m <<= 1;
+    // pads sort after every key: the largest key and positions past n
+#pragma unroll
+    for (int j = 0; j < kOsRounds; ++j) {
+        const uint32_t i = (uint32_t)j * kOsThreads + t;
+        if (i < m) {
+            L.skey[i] = i < n ? key[j] : ~0ull;
+            pos[i] = (uint16_t)i;
+        }
+    }
+    // Thread c compares the pair (i, i + h), i being c with a zero bit
+    // inserted at h.  While h <= 64 the pairs of a wave lie in its own 128
+    // elements, so a step needs the whole workgroup's barrier only when it or
+    // the step before it has h >= 128; else the wave's own order suffices.
+    static_assert(kTileBitonicMax / 2 <= kOsThreads, "one pair per thread");
+    uint32_t hprev = m;  // the loads above cross waves
+    for (uint32_t k = 2; k <= m; k <<= 1) {
+        for (uint32_t h = k >> 1; h > 0; h >>= 1) {
+            if (h >= 128 || hprev >= 128) {
+                __syncthreads();
+            } else {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+            hprev = h;
+            if (t < m / 2) {
+                const uint32_t i = ((t & ~(h - 1)) << 1) | (t & (h - 1));
+                const uint32_t p = i + h;
+                const uint64_t a = L.skey[i], b = L.skey[p];
+                const uint16_t ia = pos[i], ib = pos[p];
+                const bool after = a > b || (a == b && ia > ib);
+                if (after == ((i & k) == 0)) {
+                    L.skey[i] = b;
+                    L.skey[p] = a;
+                    pos[i] = ib;
+                    pos[p] = ia;
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kOsRounds; ++j) {
+        const uint32_t i = (uint32_t)j * kOsThreads + t;
+        key[j] = i < n ? L.skey[i] : sentinel;
+    }
+    __syncthreads();  // the caller may reuse the LDS
+}
+
 // Stable LSD sort of one tile in LDS: thread t holds key[j] = element
 // j * kOsThreads + t, the first n live; `passes` 8-bit digits (the ranking of
 // the pass kernel on a single tile, so no look-back).  key[] comes back
 // holding the sorted order in the same layout, `sentinel` past n.  Every
-// thread of the workgroup calls it (barriers inside).
+// thread of the workgroup calls it (barriers inside).  Live keys must be
+// below 2^(8 * passes).
 __device__ __forceinline__ void tile_sort(uint64_t (&key)[kOsRounds], uint64_t n, int passes,
                                           uint64_t sentinel, TileSortLds& L) {
+    if (n <= kTileBitonicMax) {
+        if (n > 1) {
+            tile_bitonic(key, (uint32_t)n, sentinel, L);
+        } else {
+            // nothing to order: element 0 stays where it is
+            if (threadIdx.x >= n) key[0] = sentinel;
+#pragma unroll
+            for (int j = 1; j < kOsRounds; ++j) key[j] = sentinel;
+        }
+        return;
+    }
     const uint32_t t = threadIdx.x;
     const int w = t >> 6;
     const uint32_t d = t & (kRadix - 1), q = t >> 8;
