@@ -350,11 +350,12 @@ typedef struct {
  *                  [64, 4096] (default 256)
  *   overlap        0 (default) or 1.  With 1, an insert or delete batch of
  *                  more than small_sort_max pairs queued by gv_insert_edges,
- *                  gv_delete_edges or gv_apply_ops (not while the graph's
- *                  stream is being captured) packs and sorts its pairs on a
- *                  second stream of the library's own, while the graph's
- *                  stream still runs the batches queued before it; the rest
- *                  of the batch waits for that sort on the graph's stream.
+ *                  gv_delete_edges, gv_apply_ops or recorded by
+ *                  gv_plan_create packs and sorts its pairs on a second
+ *                  stream of the library's own, while the graph's stream
+ *                  still runs the batches queued before it; the rest of the
+ *                  batch waits for that sort on the graph's stream (a plan
+ *                  records the two streams as parallel branches).
  *                  Results are those of overlap 0.  Contract: the batch's
  *                  d_src / d_dst must hold their pairs when the call is made
  *                  (written by a synchronous copy, or by work the caller has

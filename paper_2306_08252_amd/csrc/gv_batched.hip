@@ -30,6 +30,7 @@ struct gv_plan {
     uint64_t vscr_gen[3] = {0, 0, 0};
     uint64_t table_gen = 0;
     uint64_t cscr_gen = 0;
+    uint64_t ovscr_gen = 0;     // the sort overlap's second batch buffer
     uint64_t insert_pairs = 0;  // pairs the plan's inserts add to the host-side edge bound
 };
 
@@ -251,6 +252,11 @@ int gv_plan_create(gv_graph* g, const gv_op* ops, uint64_t n_ops, gv_plan** out)
         g->scratch.ensure(std::max<size_t>(sc, 4), c.stream);
         for (int k = 0; k < 3; ++k) g->vscr[k].ensure(std::max<size_t>(vs[k], 4), c.stream);
         g->cscr.ensure(std::max<size_t>(csz, 4), c.stream);
+        if (g->tune.overlap) {
+            // edge batches alternate between the two batch buffers
+            g->ov.scr.ensure(std::max<size_t>(sc, 4), c.stream);
+            overlap_open(g);
+        }
         hip_check(hipStreamSynchronize(c.stream), "hipStreamSynchronize");
         edge_batch_warm(g);
         vertex_batch_warm();
@@ -291,6 +297,7 @@ int gv_plan_create(gv_graph* g, const gv_op* ops, uint64_t n_ops, gv_plan** out)
         for (int k = 0; k < 3; ++k) p->vscr_gen[k] = g->vscr[k].gen;
         p->table_gen = g->table_gen;
         p->cscr_gen = g->cscr.gen;
+        p->ovscr_gen = g->ov.scr.gen;
     });
     if (rc != GV_OK) {
         gv_plan_destroy(p);
@@ -305,7 +312,7 @@ int gv_plan_launch(gv_plan* p) {
     gv_graph* g = p->g;
     return guarded_call(g, [&] {
         bool same = g->scratch.gen == p->scratch_gen && g->table_gen == p->table_gen &&
-                    g->cscr.gen == p->cscr_gen;
+                    g->cscr.gen == p->cscr_gen && g->ov.scr.gen == p->ovscr_gen;
         for (int k = 0; k < 3; ++k) same = same && g->vscr[k].gen == p->vscr_gen[k];
         if (!same) fail(GV_EINVAL, "graph buffers moved since the plan was created");
         hip_check(hipGraphLaunch(p->exec, g->ctx.stream), "hipGraphLaunch");

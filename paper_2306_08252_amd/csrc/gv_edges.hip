@@ -1750,8 +1750,7 @@ __global__ void k_ov_begin(GraphView g, const unsigned long long* stot) {
     }
 }
 
-// the side stream and events of the sort overlap, made on first use
-static void ov_open(gv_graph* g) {
+void overlap_open(gv_graph* g) {
     gv_graph::Overlap& o = g->ov;
     if (o.stream) return;
     hip_check(hipStreamCreateWithFlags(&o.stream, hipStreamNonBlocking), "hipStreamCreate");
@@ -1761,10 +1760,12 @@ static void ov_open(gv_graph* g) {
         hip_check(hipEventCreateWithFlags(e, hipEventDisableTiming), "hipEventCreate");
 }
 
-static bool capturing(hipStream_t s) {
+// the id of the capture the stream is in, 0 when it is not being captured
+static unsigned long long capture_id(hipStream_t s) {
     hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
-    hip_check(hipStreamIsCapturing(s, &st), "hipStreamIsCapturing");
-    return st != hipStreamCaptureStatusNone;
+    unsigned long long id = 0;
+    hip_check(hipStreamGetCaptureInfo(s, &st, &id), "hipStreamGetCaptureInfo");
+    return st == hipStreamCaptureStatusActive ? id : 0ull;
 }
 
 static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t* dst,
@@ -1778,10 +1779,19 @@ static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint
     const GraphView& v = g->v;
     const uint64_t icap = n + div_up(g->item_slots, (uint64_t)g->tune.item_chunk) + 1;
     const int bits = 2 * (int)v.L;
-    // sort overlap: this batch's pack and sort go to the side stream
+    // sort overlap: this batch's pack and sort go to the side stream (also
+    // while the graph's stream is captured: the side stream then joins the
+    // capture through the first wait, and the recording keeps both branches)
     const bool ovb = g->tune.overlap && !sorted && !fixed && mode != kQuery && bits > 0 &&
-                     n > std::min<uint64_t>(g->tune.small_sort_max, kOsTile) &&
-                     !capturing(c.stream);
+                     n > std::min<uint64_t>(g->tune.small_sort_max, kOsTile);
+    if (ovb) {
+        const unsigned long long cap = capture_id(c.stream);
+        if (cap != g->ov.capture) {
+            g->ov.capture = cap;
+            g->ov.used[0] = g->ov.used[1] = false;
+            g->ov.seq = ~0ull;
+        }
+    }
     const int ob = (int)(g->ov.count & 1);  // its buffer
     BatchArrays A;
     {
@@ -1838,7 +1848,7 @@ static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint
         // before.  The batch counters are cleared on the graph's stream, once
         // the batch before has finished with them.
         gv_graph::Overlap& o = g->ov;
-        ov_open(g);
+        overlap_open(g);
         Ctx& sc = o.ctx;
         sc.prof = c.prof;
         sc.only = c.only;

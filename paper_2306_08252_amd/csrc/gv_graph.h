@@ -36,6 +36,9 @@ struct gv_graph {
         bool used[2] = {false, false};    // done[k] has been recorded
         uint64_t count = 0;               // overlapped batches (next buffer = count & 1)
         uint64_t seq = ~0ull;             // ctx.seq after the last overlapped batch
+        // id of the stream capture the state above belongs to (0: none);
+        // events of another capture, or of none, are never waited for
+        unsigned long long capture = 0;
     } ov;
     // device allocations owned by the graph
     void* mem_pool = nullptr;
@@ -103,6 +106,8 @@ void mixed_edges(gv_graph* g, const uint8_t* op, const uint32_t* src, const uint
 
 // occupancy queries made ahead of a recording
 void edge_batch_warm(const gv_graph* g = nullptr);
+// the side stream and events of the sort overlap (made once)
+void overlap_open(gv_graph* g);
 bool probe_shape_ok(uint32_t group, uint32_t unroll);
 void vertex_batch_warm();
 // bytes of g->scratch an edge batch of n pairs carves

@@ -101,9 +101,9 @@ def descend(best, space, run):
 def tune(gv, w, ops, dev, warm, log=print, form="plan"):
     """Coordinate descent over the knobs, starting from the defaults, timing
     `form`; returns (best setting, all measured points in ms)."""
-    best = dict({"block_slots": 16, "coalesce": 0, "max_run_pairs": 0, "small_sort_max": 4096},
-                **DEFAULT_PROBE)
-    space = [("block_slots", [8, 16, 32, 64]), ("coalesce", [0, 1]),
+    best = dict({"block_slots": 16, "coalesce": 0, "max_run_pairs": 0, "small_sort_max": 4096,
+                 "overlap": 0}, **DEFAULT_PROBE)
+    space = [("block_slots", [8, 16, 32, 64]), ("coalesce", [0, 1]), ("overlap", [0, 1]),
              ("max_run_pairs", [0, 1 << 18, 1 << 20, 1 << 22]),
              ("small_sort_max", [0, 4096])] + PROBE_SPACE + [("block_slots", [8, 16, 32, 64])]
     points, want = {}, None

@@ -109,8 +109,9 @@ def test_interleaved_work_matches_oracle():
 
 def test_batched_form_and_profiling_with_overlap():
     """gv_apply_ops runs its edge batches overlapped; a plan recorded with
-    overlap on records no side-stream work and gives the same graph; the
-    side stream's launches are timed with the graph's profiling."""
+    overlap on holds the side stream's work as parallel branches and gives
+    the oracle's graph, launch after launch; the side stream's launches are
+    timed with the graph's profiling."""
     gv = need_gpu()
     scale, m, B = 13, 1 << 16, 8
     w = I.RmatWorkload(scale, m, name="ovb")
@@ -135,19 +136,23 @@ def test_batched_form_and_profiling_with_overlap():
             # 12 edge batches of 2 * 13 = 26-bit keys: 4 passes each
             assert launches == 12 * 4 and ms > 0
         else:
+            # recorded with the side stream as a parallel branch; launched
+            # twice (the second launch applies the same batches again)
             plan = gv.Plan(g.h, ops, g.device)
+            plan.launch()
             plan.launch()
             assert g.sync() == 0
             plan.close()
         graphs.append(g)
-    o = O.OracleGraph(w.num_vertices, w.src, w.dst, block_slots=B)
-    for kind, a, b in ops:
-        if kind == gv.OP_INSERT_EDGES:
-            o.insert_edges(a, b)
-        elif kind == gv.OP_DELETE_EDGES:
-            o.delete_edges(a, b)
-        else:
-            o.delete_vertices(a)
-    for g, label in zip(graphs, ("eager", "plan")):
+    for g, label, times in zip(graphs, ("eager", "plan"), (1, 2)):
+        o = O.OracleGraph(w.num_vertices, w.src, w.dst, block_slots=B)
+        for _ in range(times):
+            for kind, a, b in ops:
+                if kind == gv.OP_INSERT_EDGES:
+                    o.insert_edges(a, b)
+                elif kind == gv.OP_DELETE_EDGES:
+                    o.delete_edges(a, b)
+                else:
+                    o.delete_vertices(a)
         assert_same(g, o, label)
         g.close()
