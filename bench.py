@@ -432,6 +432,57 @@ def block_size_sweep(gv, w, dev, ks=(10**4, 10**5, 10**6), block_slots=(8, 16, 3
     return out
 
 
+def batch_latency(gv, w, dev, tuning, ks=(10**3, 10**4, 10**5), nb=20):
+    """Time per batch of small insert / delete batches on the headline graph
+    (B = 16), alternating inserts and deletes: queued one call at a time
+    (eager), and recorded into one plan launched three times (no host work
+    per batch), each with the sort overlap off and on (other knobs from
+    `tuning`); a fresh graph per form."""
+    import torch
+    out = []
+    for k in ks:
+        ins = [w.insert_batch(k, 5000 + j) for j in range(2 * nb)]
+        dels = [w.delete_batch(k, 5000 + j) for j in range(2 * nb)]
+        torch.cuda.synchronize()
+        row = {"batch": k}
+        for form in ("eager", "plan"):
+            for ov in (0, 1):
+                g = gv.Graph(w.num_vertices, w.src, w.dst, block_slots=16, device=dev)
+                gv.gv_set_tuning(g.h, **dict(tuning, overlap=ov))
+                if form == "eager":
+                    for j in range(3):
+                        gv.gv_insert_edges(g.h, *ins[j], dev, stats=False)
+                        gv.gv_delete_edges(g.h, *dels[j], dev, stats=False)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for j in range(nb):
+                        gv.gv_insert_edges(g.h, *ins[j], dev, stats=False)
+                        gv.gv_delete_edges(g.h, *dels[j], dev, stats=False)
+                    torch.cuda.synchronize()
+                    el = (time.perf_counter() - t0) / (2 * nb)
+                else:
+                    ops = []
+                    for j in range(nb, 2 * nb):
+                        ops.append((gv.OP_INSERT_EDGES, *ins[j]))
+                        ops.append((gv.OP_DELETE_EDGES, *dels[j]))
+                    plan = gv.Plan(g.h, ops, dev)
+                    plan.launch()
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for _ in range(3):
+                        plan.launch()
+                    torch.cuda.synchronize()
+                    el = (time.perf_counter() - t0) / (3 * 2 * nb)
+                    plan.close()
+                rc = g.sync()
+                g.close()
+                if rc != 0:
+                    raise RuntimeError(f"batch latency: {gv.gv_strerror(rc)}")
+                row[f"{form}_overlap{ov}_us"] = round(el * 1e6, 2)
+        out.append(row)
+    return out
+
+
 def batched_form(gv, I, T, dev, scale=22, edges=1 << 26, nbatch=256, seed_name="batched"):
     """The batched form: `nbatch` batches of log-uniform size in [10^2, 10^6],
     45 % edge inserts (R-MAT pairs), 45 % edge deletes (80 % stored pairs, 20 %
@@ -599,7 +650,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-form workload (eager and recorded forms)")
     ap.add_argument("--no-sweep", action="store_true",
-                    help="skip the block-size x batch-size sweep")
+                    help="skip the block-size x batch-size sweep and the small-batch latencies")
     ap.add_argument("--no-cbt", action="store_true",
                     help="skip the paper-faithful ablation (complete binary tree, Alg. 1-3)")
     ap.add_argument("--no-config3", action="store_true",
@@ -827,6 +878,10 @@ def main():
 
     # ---- batched form on its own workload
     sweep = None if args.no_sweep else block_size_sweep(gv, w, dev)
+    knobs = {f: step_setting[f] for f in gv.TUNING_FIELDS if f in step_setting}
+    latency = None if args.no_sweep else batch_latency(gv, w, dev, knobs)
+    if latency:
+        log("batch latency:", json.dumps(latency))
     batched = None if args.no_batched else batched_form(gv, I, T, dev)
     served = None if args.no_served else served_form(gv, I, T, dev, B)
     config3 = None if args.no_config3 else config3_form(gv, I, T, dev)
@@ -897,6 +952,7 @@ def main():
         "config3": config3,
         "served_p50_p99": served,
         "block_size_sweep": sweep,
+        "batch_latency_us": latency,
         "pilot_kernels_ms": pilot,
         "roofline": roof,
         "cpu_baseline": cpu,
