@@ -19,11 +19,14 @@ follow the bytes-touched model M1 (counted once per batch): the grouping of a
 batch is 16 B per pair (one write and one read of the packed pairs) however
 many radix passes it takes, so a pass is credited 16 B per pair / passes; a
 probe is credited the touched adjacency (4 B per slot, block granular).  The
-launch time comes from HIP events on the graph's stream in a second run of
-the same steps, one event pair per run of consecutive launches of the kernel
-(the passes of one sort share a pair, so the events' own cost is spread over
-them); the committed kernel-trace summary of the same command gives the
-durations without events.
+launch time comes from HIP events on the kernel's stream in a second run of
+the same steps with the sort overlap off, so that the kernel runs alone on
+the device (under the overlap a pass shares it with the other stream's
+kernels, and its events would also time its wait for compute units), one
+event pair per run of consecutive launches of the kernel (the passes of one
+sort share a pair, so the events' own cost is spread over them); the
+committed kernel-trace summary of the same command gives the durations
+without events.
 
 cpu_baseline: the CPU oracle (ordered sets, one thread) applying the same
 batches restricted to a quarter of the sources (those whose SplitMix64 hash
@@ -743,6 +746,12 @@ def main():
         gv.gv_delete_edges(h, *dels[j], dev, stats=False)
     torch.cuda.synchronize()
 
+    # the pilot step and the roofline's event run time each kernel alone: with
+    # the sort overlap on, a pass would share the device with the other
+    # stream's kernels and its events would also count its wait for a slot
+    overlap = step_setting.get("overlap", 0)
+    gv.gv_set_tuning(h, overlap=0)
+
     # ---- pilot step (untimed): every kernel timed, to find the dominant one
     gv.gv_profile_enable(h, True)
     gv.gv_profile_only(h, None)
@@ -763,6 +772,7 @@ def main():
     # ---- timed region: steps of insert + delete, no events (an event record
     # between two kernels costs about 5 us of GPU time)
     gv.gv_profile_enable(h, False)
+    gv.gv_set_tuning(h, overlap=overlap)
     c0 = g.counters()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -774,7 +784,9 @@ def main():
     elapsed = time.perf_counter() - t0
     c1 = g.counters()
     # ---- the same number of steps again, with HIP events around every launch
-    # of the dominant kernel on the graph's stream (roofline entry)
+    # of the dominant kernel on the stream it runs on (roofline entry), the
+    # sort overlap off
+    gv.gv_set_tuning(h, overlap=0)
     gv.gv_profile_enable(h, True)
     gv.gv_profile_only(h, dominant)
     gv.gv_profile_reset(h)
@@ -787,6 +799,7 @@ def main():
     elapsed_ev = time.perf_counter() - t1
     dom_launches, dom_ms = gv.gv_kernel_times(h, dominant)
     gv.gv_profile_enable(h, False)
+    gv.gv_set_tuning(h, overlap=overlap)
     rc = g.sync()
     if rc != 0:
         raise RuntimeError(f"batch error during timed steps: {gv.gv_strerror(rc)}")
@@ -828,7 +841,8 @@ def main():
                 "avg_launch_us": round(avg_s * 1e6, 3), "launches": dom_launches,
                 "step_m1_frac": round(pct_m1, 5),
                 "timed_steps": "a second run of the same number of steps, right after the "
-                               "timed region, one HIP event pair around each run of "
+                               "timed region, with the sort overlap off (each kernel alone on "
+                               "the device), one HIP event pair around each run of "
                                "consecutive launches of the kernel (%.4f ms per step with the "
                                "events)" % (elapsed_ev / K * 1e3)}
 
