@@ -126,7 +126,7 @@ void bulk_build(gv_graph* g, uint64_t num_vertices, const uint32_t* src, const u
 // raise a sticky GV_ERANGE
 void vertex_insert(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats* st,
                    bool fixed_table = false);
-// edge_bound: upper bound on the edges stored (0: read it, synchronising)
+// edge_bound: upper bound on the edges stored (0: the host-side bound, no read-back)
 void vertex_delete(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats* st,
                    uint64_t edge_bound = 0);
 

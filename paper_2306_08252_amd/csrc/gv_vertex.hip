@@ -1,6 +1,7 @@
 // gv_vertex.hip -- batched vertex insertion and deletion (Sec. 4.4).
 //
-// Insert: ids are sorted and deduplicated; when the largest id does not fit,
+// Insert: an id's first occurrence in the batch is found with a bitmap of
+// the ids seen (no sort of the ids); when the largest id does not fit,
 // the dictionary is replaced by one of the next power-of-two capacity (copy
 // kernel, then the old one is freed); inactive ids are switched on.
 //
@@ -92,18 +93,22 @@ __global__ void k_vreset(DevCounters* c) {
     c->vd_hits = c->vd_touched = c->vd_pairs = 0;
 }
 
-// sorted ids: count rejected and distinct, activate the inactive ones
-__global__ __launch_bounds__(kThreads) void k_vins(GraphView g, const uint32_t* keys, uint64_t n) {
+// Ids in input order: an id's first occurrence is the thread whose atomicOr
+// sets its bit in `seen` (zeroed per call), so duplicates are found without
+// sorting the ids.  Counts rejected and distinct ids and activates the
+// inactive ones.
+__global__ __launch_bounds__(kThreads) void k_vins(GraphView g, const uint32_t* ids, uint64_t n,
+                                                   uint32_t* seen) {
     __shared__ unsigned long long lds[kWaves];
     const uint64_t i = vt_tidx();
     unsigned long long rej = 0, uniq = 0, app = 0;
     if (i < n) {
-        const uint32_t id = keys[i];
+        const uint32_t id = ids[i];
         const bool valid = id <= kMaxId && (uint64_t)id < g.n_cap;
         rej = !valid;
-        if (valid && (i == 0 || keys[i - 1] != id)) {
+        const uint32_t bit = 1u << (id & 31);
+        if (valid && !(atomicOr(&seen[id >> 5], bit) & bit)) {
             uniq = 1;
-            const uint32_t bit = 1u << (id & 31);
             const uint32_t old = atomicOr(&g.active[id >> 5], bit);
             if (!(old & bit)) {
                 app = 1;
@@ -121,20 +126,27 @@ __global__ __launch_bounds__(kThreads) void k_vins(GraphView g, const uint32_t* 
     }
 }
 
-// sorted ids: mark the active distinct ones in the `gone` bitmap
-__global__ __launch_bounds__(kThreads) void k_vdel_mark(GraphView g, const uint32_t* keys,
-                                                        uint64_t n, uint32_t* gone) {
+// Ids in input order: the first occurrence of each valid id (its atomicOr
+// sets the bit in `seen`) gets first[i] = 1, and marks the id in the `gone`
+// bitmap when it is active; the later kernels of the delete take an id at
+// its first occurrence only.
+__global__ __launch_bounds__(kThreads) void k_vdel_mark(GraphView g, const uint32_t* ids,
+                                                        uint64_t n, uint32_t* seen,
+                                                        uint32_t* gone, uint8_t* first) {
     __shared__ unsigned long long lds[kWaves];
     const uint64_t i = vt_tidx();
     unsigned long long rej = 0, uniq = 0, app = 0;
     if (i < n) {
-        const uint32_t id = keys[i];
+        const uint32_t id = ids[i];
         const bool valid = (uint64_t)id < g.n_cap;
         rej = !valid;
-        if (valid && (i == 0 || keys[i - 1] != id)) {
+        const uint32_t bit = 1u << (id & 31);
+        const bool head = valid && !(atomicOr(&seen[id >> 5], bit) & bit);
+        first[i] = head ? 1 : 0;
+        if (head) {
             uniq = 1;
             if (is_active(g, id)) {
-                atomicOr(&gone[id >> 5], 1u << (id & 31));
+                atomicOr(&gone[id >> 5], bit);
                 app = 1;
             }
         }
@@ -305,8 +317,9 @@ __global__ __launch_bounds__(kThreads) void k_vd_scan(GraphView g, VDel d) {
             }
         }
     };
-    for (uint64_t q0 = (uint64_t)blockIdx.x * kRound; q0 < nq; q0 += (uint64_t)gridDim.x * kRound) {
-        uint32_t xs[kVQuads][4];
+    // the slots of one round: kVQuads groups of 4 per thread (zeros past the
+    // handed-out slots)
+    auto load_round = [&](uint64_t q0, uint32_t (&xs)[kVQuads][4]) {
 #pragma unroll
         for (uint32_t u = 0; u < kVQuads; ++u) {
             const uint64_t q = q0 + (uint64_t)u * kThreads + threadIdx.x;
@@ -321,6 +334,12 @@ __global__ __launch_bounds__(kThreads) void k_vd_scan(GraphView g, VDel d) {
                 for (uint32_t i = 0; i < 4; ++i) xs[u][i] = 4 * q + i < slots ? g.pool[4 * q + i] : 0u;
             }
         }
+    };
+    const uint64_t stride = (uint64_t)gridDim.x * kRound;
+    uint32_t xs[kVQuads][4];
+    uint64_t q0 = (uint64_t)blockIdx.x * kRound;
+    if (q0 < nq) load_round(q0, xs);
+    for (; q0 < nq; q0 += stride) {
         // the summary in LDS clears most slots; the bitmap words of the rest
         // are loaded together (one wait per round, not one per slot)
         uint32_t cand = 0;
@@ -342,14 +361,29 @@ __global__ __launch_bounds__(kThreads) void k_vd_scan(GraphView g, VDel d) {
 #pragma unroll
         for (uint32_t k = 0; k < 4 * kVQuads; ++k)
             word[k] = (cand >> k) & 1u ? d.gone[xs[k / 4][k % 4] >> 5] : 0u;
+        uint32_t hm = 0;  // this thread's slots whose destination is deleted
 #pragma unroll
-        for (uint32_t k = 0; k < 4 * kVQuads; ++k) {
-            const uint32_t x = xs[k / 4][k % 4];
-            if (!((word[k] >> (x & 31)) & 1u)) continue;
+        for (uint32_t k = 0; k < 4 * kVQuads; ++k)
+            hm |= ((word[k] >> (xs[k / 4][k % 4] & 31)) & 1u) << k;
+        // the next round's slots are in flight while this round's hits are
+        // checked
+        uint32_t xn[kVQuads][4];
+        if (q0 + stride < nq) load_round(q0 + stride, xn);
+        // one hit per lane per step: a step's dependent loads (owner record,
+        // vertex record, directory) are waited for once for all lanes, so a
+        // wave waits as many times as its busiest lane has hits, not once
+        // per slot position that holds a hit in some lane
+        while (hm) {
+            const uint32_t k = (uint32_t)__ffs(hm) - 1u;
+            hm &= hm - 1u;
             const uint64_t q = q0 + (uint64_t)(k / 4) * kThreads + threadIdx.x;
             uint32_t v, p;
             if (vd_hit(g, d, 4 * q + k % 4, &v, &p)) add_hit(v, p);
         }
+#pragma unroll
+        for (uint32_t u = 0; u < kVQuads; ++u)
+#pragma unroll
+            for (uint32_t i = 0; i < 4; ++i) xs[u][i] = xn[u][i];
     }
     // move the staged hits and touched vertices out
     __syncthreads();
@@ -370,18 +404,19 @@ __global__ __launch_bounds__(kThreads) void k_vd_scan(GraphView g, VDel d) {
     vd_flush(g, lost, 0ull, lds);
 }
 
-// Deleted sources (sorted ids, one thread each): all their blocks go on the
+// Deleted sources (one thread per id, at its first occurrence): all their blocks go on the
 // free list (one reservation per workgroup), their edges off the count.
-__global__ __launch_bounds__(kThreads) void k_vd_sources(GraphView g, const uint32_t* keys,
-                                                         uint64_t n, const uint32_t* gone) {
+__global__ __launch_bounds__(kThreads) void k_vd_sources(GraphView g, const uint32_t* ids,
+                                                         uint64_t n, const uint8_t* first,
+                                                         const uint32_t* gone) {
     __shared__ unsigned long long lds[kWaves];
     __shared__ unsigned long long s_base;
     const uint64_t i = vt_tidx();
     VRec r{0u, 0u, kNoDir, 0u};
     bool mine = false;
-    if (i < n) {
-        const uint32_t id = keys[i];
-        mine = (uint64_t)id < g.n_cap && (i == 0 || keys[i - 1] != id) && bit_of(gone, id);
+    if (i < n && first[i]) {
+        const uint32_t id = ids[i];
+        mine = bit_of(gone, id);
         if (mine) r = g.vt[id];
     }
     const uint32_t nb = mine ? nblocks(g, r.deg) : 0u;
@@ -557,12 +592,13 @@ __global__ __launch_bounds__(kThreads) void k_vd_fill(GraphView g, VDel d) {
     vd_flush(g, lost_err, freed, lds);
 }
 
-__global__ __launch_bounds__(kThreads) void k_vdel_finish(GraphView g, const uint32_t* keys,
-                                                          uint64_t n, const uint32_t* gone) {
+__global__ __launch_bounds__(kThreads) void k_vdel_finish(GraphView g, const uint32_t* ids,
+                                                          uint64_t n, const uint8_t* first,
+                                                          const uint32_t* gone) {
     const uint64_t i = vt_tidx();
-    if (i >= n) return;
-    const uint32_t id = keys[i];
-    if ((uint64_t)id >= g.n_cap || (i > 0 && keys[i - 1] == id) || !bit_of(gone, id)) return;
+    if (i >= n || !first[i]) return;
+    const uint32_t id = ids[i];
+    if (!bit_of(gone, id)) return;
     atomicAnd(&g.active[id >> 5], ~(1u << (id & 31)));
     const VRec r = g.vt[id];
     if (r.dcls != kNoDir) {
@@ -573,20 +609,10 @@ __global__ __launch_bounds__(kThreads) void k_vdel_finish(GraphView g, const uin
     g.vt[id] = VRec{0u, 0u, kNoDir, 0u};
 }
 
-// sort a copy of the ids into `keys` (ascending); returns the sorted array
-static uint32_t* sorted_ids(gv_graph* g, const uint32_t* ids, uint64_t n, uint32_t* k0,
-                            uint32_t* k1) {
-    Ctx& c = g->ctx;
-    c.launch("vcopy", k_vcopy_ids, div_up(n, kThreads), kThreads, ids, n, k0);
-    SortScratch ss{};
-    {
-        Carver mz(nullptr);
-        carve_sort<uint32_t>(mz, ss, n);
-        g->scratch.ensure(mz.used, c.stream);
-        Carver cv(g->scratch.ptr);
-        carve_sort<uint32_t>(cv, ss, n);
-    }
-    return radix_sort<uint32_t, false>(c, k0, k1, nullptr, nullptr, n, 32, ss) ? k1 : k0;
+// bytes of a vertex delete's id buffer: gone, summary and seen bitmaps, then
+// one first-occurrence flag per id
+static size_t vdel_ids_bytes(uint64_t words, uint64_t n) {
+    return (2 * words + kVSumWords) * sizeof(uint32_t) + n;
 }
 
 // a vertex batch's own buffer, kept by the graph between calls
@@ -647,9 +673,10 @@ void vertex_insert(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats*
             grow_table(g, cap);
         }
     }
-    uint32_t* k0 = (uint32_t*)vbuf(g, 0, 2 * n * sizeof(uint32_t));
-    uint32_t* sorted = sorted_ids(g, ids, n, k0, k0 + n);
-    c.launch("vinsert", k_vins, div_up(n, kThreads), kThreads, g->v, (const uint32_t*)sorted, n);
+    const uint64_t words = (g->v.n_cap + 31) / 32;
+    uint32_t* seen = (uint32_t*)vbuf(g, 0, words * sizeof(uint32_t));
+    c.launch("vzero", k_vzero, div_up(words, kThreads), kThreads, seen, words);
+    c.launch("vinsert", k_vins, div_up(n, kThreads), kThreads, g->v, ids, n, seen);
     if (st) {
         read_counters(g);
         st->applied = g->hctr->st_applied;
@@ -700,12 +727,9 @@ void vdel_carve(Carver& cv, const VDelCaps& k, VDel& d) {
 // the graph-owned vertex buffers; edge_bound as in vertex_delete.
 void vertex_batch_bytes(const gv_graph* g, bool del, uint64_t n, uint64_t edge_bound,
                         size_t out[4]) {
-    SortScratch ss{};
-    Carver ms(nullptr);
-    carve_sort<uint32_t>(ms, ss, n);
-    out[0] = ms.used;
+    out[0] = 0;
     const uint64_t words = (g->v.n_cap + 31) / 32;
-    out[1] = (2 * n + (del ? words + kVSumWords : 0)) * sizeof(uint32_t);
+    out[1] = del ? vdel_ids_bytes(words, n) : words * sizeof(uint32_t);
     out[2] = out[3] = 0;
     if (!del) return;
     VDel d{};
@@ -714,9 +738,8 @@ void vertex_batch_bytes(const gv_graph* g, bool del, uint64_t n, uint64_t edge_b
     out[2] = m.used;
 }
 
-// edge_bound: an upper bound on the edges stored when the call runs (0: read
-// it from the device when statistics are wanted, which synchronises, else
-// take the graph's host-side bound)
+// edge_bound: an upper bound on the edges stored when the call runs (0: the
+// graph's host-side bound, capped by the pool's slots; no read-back)
 void vertex_delete(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats* st,
                    uint64_t edge_bound) {
     Ctx& c = g->ctx;
@@ -724,28 +747,22 @@ void vertex_delete(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats*
     if (n >= 0xffffffffull) fail(GV_EINVAL, "batch too large");
     const uint64_t ncap = v.n_cap;
     const uint64_t words = (ncap + 31) / 32;
-    uint32_t* k0 = (uint32_t*)vbuf(g, 0, (2 * n + words + kVSumWords) * sizeof(uint32_t));
-    uint32_t* gone = k0 + 2 * n;
+    // gone | summary | seen (zeroed together), then a first-occurrence flag per id
+    uint32_t* gone = (uint32_t*)vbuf(g, 0, vdel_ids_bytes(words, n));
     uint32_t* summary = gone + words;
+    uint32_t* seen = summary + kVSumWords;
+    uint8_t* first = (uint8_t*)(seen + words);
     c.launch("vreset", k_vreset, 1, 1, v.ctr);
-    c.launch("vzero", k_vzero, div_up(words + kVSumWords, kThreads), kThreads, gone,
-             words + kVSumWords);
-    uint32_t* sorted = sorted_ids(g, ids, n, k0, k0 + n);
-    c.launch("vdel_mark", k_vdel_mark, div_up(n, kThreads), kThreads, v, (const uint32_t*)sorted,
-             n, gone);
-    if (!edge_bound && st) {
-        // synchronous call: read the counts back (and stop early if no id
-        // is deleted)
-        read_counters(g);
-        if (!g->hctr->st_applied) {
-            st->applied = 0;
-            st->rejected = g->hctr->st_rejected;
-            st->batch_duplicates = n - g->hctr->st_rejected - g->hctr->n_uniq;
-            return;
-        }
-        edge_bound = g->hctr->live_edges;
+    c.launch("vzero", k_vzero, div_up(2 * words + kVSumWords, kThreads), kThreads, gone,
+             2 * words + kVSumWords);
+    c.launch("vdel_mark", k_vdel_mark, div_up(n, kThreads), kThreads, v, ids, n, seen, gone,
+             first);
+    if (!edge_bound) {
+        // no read-back: the host-side bound, capped by the pool's slots (every
+        // stored edge holds one)
+        edge_bound = std::max<uint64_t>(
+            std::min<uint64_t>(g->edge_bound_host, (uint64_t)v.cap_blocks * v.B), 1);
     }
-    if (!edge_bound) edge_bound = std::max<uint64_t>(g->edge_bound_host, 1);  // no read-back
     VDel d{};
     {
         const VDelCaps k = vdel_caps(g, edge_bound);
@@ -760,13 +777,13 @@ void vertex_delete(gv_graph* g, const uint32_t* ids, uint64_t n, gv_batch_stats*
     d.sum_words = (uint32_t)std::max<uint64_t>(((ncap >> d.sum_shift) + 31) / 32, 1);
     c.launch("vdel_summary", k_vd_summary, div_up(words, kThreads), kThreads, d, words);
     c.launch("vdel_scan", k_vd_scan, resident_grid(k_vd_scan, kThreads), kThreads, v, d);
-    c.launch("vdel_sources", k_vd_sources, div_up(n, kThreads), kThreads, v,
-             (const uint32_t*)sorted, n, (const uint32_t*)gone);
+    c.launch("vdel_sources", k_vd_sources, div_up(n, kThreads), kThreads, v, ids, n,
+             (const uint8_t*)first, (const uint32_t*)gone);
     c.launch("vdel_plan", k_vd_plan, resident_grid(k_vd_plan, kThreads), kThreads, v, d);
     c.launch("vdel_holes", k_vd_holes, resident_grid(k_vd_holes, kThreads), kThreads, v, d);
     c.launch("vdel_fill", k_vd_fill, resident_grid(k_vd_fill, kThreads), kThreads, v, d);
-    c.launch("vdel_finish", k_vdel_finish, div_up(n, kThreads), kThreads, g->v,
-             (const uint32_t*)sorted, n, (const uint32_t*)gone);
+    c.launch("vdel_finish", k_vdel_finish, div_up(n, kThreads), kThreads, g->v, ids, n,
+             (const uint8_t*)first, (const uint32_t*)gone);
     if (st) {
         read_counters(g);
         st->applied = g->hctr->st_applied;
