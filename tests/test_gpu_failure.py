@@ -24,11 +24,16 @@ def _graph(gv, B=8):
     return w, g, o
 
 
-@pytest.mark.parametrize("op", ["insert", "delete", "query", "async"])
-def test_lookback_give_up_is_reported(op):
+@pytest.mark.parametrize("op,overlap", [("insert", 0), ("delete", 0), ("query", 0),
+                                        ("async", 0), ("insert", 1), ("delete", 1),
+                                        ("async", 1)])
+def test_lookback_give_up_is_reported(op, overlap):
+    """With the sort overlap on, the passes run on the side stream and take
+    tickets; a wait that gives up there is reported the same way."""
     gv = need_gpu()
-    say(f"forced look-back give-up: {op}")
+    say(f"forced look-back give-up: {op}, overlap {overlap}")
     w, g, o = _graph(gv)
+    gv.gv_set_tuning(g.h, overlap=overlap)
     assert_same(g, o, "init")
     # a single-tile batch never waits: the setting leaves it untouched
     s, d = w.insert_batch(3000, 0)

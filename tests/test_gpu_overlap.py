@@ -156,3 +156,39 @@ def test_batched_form_and_profiling_with_overlap():
                     o.delete_vertices(a)
         assert_same(g, o, label)
         g.close()
+
+
+def test_pool_exhaustion_with_overlap_matches_oracle():
+    """Overlapped insert batches against a pool that runs out: a batch that
+    does not fit changes nothing and leaves a sticky GV_ENOMEM, later
+    batches still apply (asynchronous calls), as in the oracle."""
+    gv = need_gpu()
+    n, B = 4096, 4
+    rng = np.random.default_rng(11)
+    s0 = rng.integers(0, n, 6000).astype(np.uint32)
+    d0 = rng.integers(0, n, 6000).astype(np.uint32)
+    pool = 4 * B * 9000
+    g = gv.Graph(n, s0, d0, block_slots=B, pool_bytes=pool)
+    gv.gv_set_tuning(g.h, overlap=1)
+    o = O.OracleGraph(n, s0, d0, block_slots=B, pool_bytes=pool)
+    batches = []
+    for j in range(8):
+        k = 6000 if j != 4 else 40000  # the fifth batch cannot fit
+        x = rng.integers(0, n, k).astype(np.uint32)
+        y = rng.integers(0, n, k).astype(np.uint32)
+        batches.append((gv.as_device_u32(x, g.device), gv.as_device_u32(y, g.device), x, y))
+    torch.cuda.synchronize()
+    say("overlap pool exhaustion")
+    failed = 0
+    for j, (tx, ty, x, y) in enumerate(batches):
+        g.insert_edges(tx, ty, stats=False)
+        rc, _ = o.insert_edges(x, y)
+        failed += rc == O.ENOMEM
+        if j % 2:
+            g.delete_edges(ty[:3000], tx[:3000], stats=False)
+            o.delete_edges(y[:3000], x[:3000])
+    assert failed >= 1
+    assert g.sync() == gv.GV_ENOMEM
+    assert g.sync() == gv.GV_OK
+    assert_same(g, o, "after the overlapped batches")
+    g.close()
