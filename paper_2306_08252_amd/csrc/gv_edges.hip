@@ -530,6 +530,7 @@ struct ItemOut {
     uint32_t B;
     uint64_t icap;      // capacity of items (the scan of distinct sources stays below it)
     uint32_t chunk;     // adjacency slots per work item
+    uint32_t* shits;    // delete: small-item hits per source, zeroed here for the others
     __device__ void operator()(uint64_t t, const TouchRec& x, uint64_t lim,
                                unsigned long long pre) const {
         const bool live = t < lim;
@@ -551,6 +552,7 @@ struct ItemOut {
             this->small[t] = w;
         } else if (live) {
             *(uint4*)&this->small[t] = make_uint4(0u, 0u, 0u, 0u);
+            if (shits) shits[t] = 0u;
         }
         if (cnt <= kLaneItems) {
             for (uint32_t c = 0; c < cnt; ++c) {
@@ -614,11 +616,13 @@ __device__ __forceinline__ void probe_load(const GraphView& g, const Item& I, co
 // Searches of the U slots of a lane run in lockstep, so that each step
 // issues U independent reads and waits once.
 template <int MODE, int G, int U>
-__device__ __forceinline__ void probe_search(const GraphView& g, const Item& I, uint32_t s,
-                                             const uint32_t (&x)[U],
-                                             const uint64_t (&addr)[U], const uint32_t* st,
-                                             uint32_t steps, uint32_t shift, const uint64_t* keys,
-                                             uint8_t* mark, uint32_t* hitpos) {
+// Returns the lane's hits (delete: slots tombstoned).
+__device__ __forceinline__ uint32_t probe_search(const GraphView& g, const Item& I, uint32_t s,
+                                                 const uint32_t (&x)[U],
+                                                 const uint64_t (&addr)[U], const uint32_t* st,
+                                                 uint32_t steps, uint32_t shift,
+                                                 const uint64_t* keys, uint8_t* mark,
+                                                 uint32_t* hitpos) {
     const uint32_t len = I.hi - I.lo;
     const uint64_t vbase = (uint64_t)I.v << g.L;
     // rank among the LDS samples: st[0, 2^steps - 1) holds the sorted samples
@@ -677,6 +681,7 @@ __device__ __forceinline__ void probe_search(const GraphView& g, const Item& I, 
 #pragma unroll
         for (int u = 0; u < U; ++u) hit[u] = p[u] < len && kv[u] == (vbase | x[u]);
     }
+    uint32_t nhit = 0;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const uint32_t si = s + u * G;
@@ -688,6 +693,7 @@ __device__ __forceinline__ void probe_search(const GraphView& g, const Item& I, 
             mark[pos] = 1;
             hitpos[pos] = si;
             g.pool[addr[u]] = kTomb;
+            ++nhit;
         } else {
             const uint64_t target = vbase | x[u];
             for (uint32_t j = pos; j < I.hi && keys[j] == target; ++j) {
@@ -696,6 +702,7 @@ __device__ __forceinline__ void probe_search(const GraphView& g, const Item& I, 
             }
         }
     }
+    return nhit;
 }
 
 // Lane q of a small item's lanes probes slots [q * kSmallDeg, (q + 1) *
@@ -705,9 +712,11 @@ __device__ __forceinline__ void probe_search(const GraphView& g, const Item& I, 
 // the slot and tombstones it), query marks every occurrence.  A stored pair
 // sits in one slot, so one lane at most marks a segment entry.
 template <int MODE>
-__device__ __forceinline__ void probe_small(const GraphView& g, const Item& I, uint32_t q,
-                                            const uint64_t* keys, uint8_t* mark,
-                                            uint32_t* hitpos) {
+// Returns the lane's hits (delete).
+__device__ __forceinline__ uint32_t probe_small(const GraphView& g, const Item& I, uint32_t q,
+                                                const uint64_t* keys, uint8_t* mark,
+                                                uint32_t* hitpos) {
+    uint32_t nhit = 0;
     const uint32_t deg = I.s1;
     const uint32_t len = I.hi - I.lo;
     const uint32_t first = q * kSmallDeg;
@@ -751,15 +760,25 @@ __device__ __forceinline__ void probe_small(const GraphView& g, const Item& I, u
         if (MODE == kDelete) {
             hitpos[I.lo + j] = first + hu;
             g.pool[a[hu / 4] + (hu & 3)] = kTomb;
+            ++nhit;
         }
     }
+    return nhit;
 }
 
+// shits (delete): per touched source, the hits of its small item (written
+// for every small item; the items scan zeroes the other sources' entries)
 template <int MODE, int G, int U>
 __global__ __launch_bounds__(kThreads) void k_probe(GraphView g, const uint64_t* keys,
                                                     const Item* items, const Item* small,
-                                                    uint8_t* mark, uint32_t* hitpos) {
+                                                    uint8_t* mark, uint32_t* hitpos,
+                                                    uint32_t* shits) {
     __shared__ uint32_t stage[kWaves * (64 / G)][kStage];
+    __shared__ uint32_t s_hits[kWaves * (64 / G)];  // delete: hits of a group's item
+    if (MODE == kDelete) {
+        if (threadIdx.x < kWaves * (64 / G)) s_hits[threadIdx.x] = 0u;
+        __syncthreads();
+    }
     if (batch_failed(g.ctr)) return;
     if (MODE == kInsert || MODE == kDelete) {
         // the sorted keys must be the packed keys: their mix64 sums agree
@@ -777,7 +796,15 @@ __global__ __launch_bounds__(kThreads) void k_probe(GraphView g, const uint64_t*
         for (uint64_t k = (uint64_t)blockIdx.x * kThreads + threadIdx.x; k < nq; k += stride) {
             const Item I = small[k / kSmallLanes];
             const uint32_t q = (uint32_t)(k % kSmallLanes);
-            if (I.s1 > q * kSmallDeg) probe_small<MODE>(g, I, q, keys, mark, hitpos);
+            uint32_t h = 0;
+            if (I.s1 > q * kSmallDeg) h = probe_small<MODE>(g, I, q, keys, mark, hitpos);
+            if (MODE == kDelete) {
+                // the item's kSmallLanes lanes are consecutive and all here
+                static_assert(kSmallLanes == 4, "two exchange steps");
+                h += __shfl_xor(h, 1, 64);
+                h += __shfl_xor(h, 2, 64);
+                if (q == 0 && I.s1 > 0) shits[k / kSmallLanes] = h;
+            }
         }
     }
     const uint32_t nitems = (uint32_t)g.ctr->tot[kTotItems];
@@ -851,7 +878,9 @@ __global__ __launch_bounds__(kThreads) void k_probe(GraphView g, const uint64_t*
             uint32_t x2[U];
             uint64_t a2[U];
             if (more) probe_load<MODE, G, U>(g, I, dp, s + G * U, x2, a2);
-            probe_search<MODE, G, U>(g, I, s, x, addr, st, steps, shift, keys, mark, hitpos);
+            const uint32_t nhit = probe_search<MODE, G, U>(g, I, s, x, addr, st, steps, shift,
+                                                           keys, mark, hitpos);
+            if (MODE == kDelete && nhit) atomicAdd(&s_hits[gid_local], nhit);
             if (!more) break;
             s += G * U;
 #pragma unroll
@@ -860,7 +889,16 @@ __global__ __launch_bounds__(kThreads) void k_probe(GraphView g, const uint64_t*
                 addr[u] = a2[u];
             }
         }
+        // the item's hits (summed in LDS over its steps) go to its source's
+        // count: one add per group
         wave_lds_sync();
+        if (MODE == kDelete && gl == 0) {
+            const uint32_t h = s_hits[gid_local];
+            if (h) {
+                atomicAdd(&g.vlost[I.v], h);
+                s_hits[gid_local] = 0u;
+            }
+        }
         if (itn >= nitems) break;
         it = itn;
         I = In;
@@ -1207,19 +1245,6 @@ __global__ __launch_bounds__(kThreads) void k_final_ins(GraphView g, const uint3
 }
 
 // ------------------------------------------------------------------ delete
-struct FoundIn {
-    const uint8_t* mark;
-    const DevCounters* ctr;
-    struct Rec {
-        uint8_t m;
-    };
-    __device__ uint64_t limit(uint64_t n) const {
-        return batch_failed(ctr) ? 0ull : min((uint64_t)ctr->tot[kTotValid], n);
-    }
-    __device__ Rec load(uint64_t i, bool ok) const { return Rec{mark[ok ? i : 0]}; }
-    __device__ void deref(Rec&) const {}
-    __device__ unsigned long long value(uint64_t, const Rec& r) const { return r.m; }
-};
 
 // a source that one lane compacts by itself
 __device__ __forceinline__ bool lane_compactable(uint32_t r, uint32_t lo, uint32_t hi) {
@@ -1229,7 +1254,8 @@ __device__ __forceinline__ bool lane_compactable(uint32_t r, uint32_t lo, uint32
 // a touched source of a delete batch with its hit count r
 struct FreedRec {
     TouchRec x;
-    uint32_t r;
+    uint32_t r;   // hits
+    uint32_t rg;  // of which counted by group items (in the vertex scratch word)
 };
 
 struct FreedIn {
@@ -1237,17 +1263,20 @@ struct FreedIn {
     GraphView g;
     const uint32_t* t_vtx;
     const uint32_t* t_start;
-    const uint32_t* b;
+    const uint32_t* shits;
     using Rec = FreedRec;
     __device__ uint64_t limit(uint64_t n) const {
         return batch_failed(g.ctr) ? 0ull : min((uint64_t)(uint32_t)g.ctr->tot[kTotSeg], n);
     }
     __device__ Rec load(uint64_t t, bool ok) const {
-        return Rec{load_touched(t_vtx, t_start, t, ok), 0u};
+        return Rec{load_touched(t_vtx, t_start, t, ok), shits[ok ? t : 0], 0u};
     }
+    // the source's hits: its small item's count plus what its group items
+    // added to its vertex scratch word
     __device__ void deref(Rec& f) const {
         f.x.r = g.vt[f.x.v];
-        f.r = b[f.x.hi] - b[f.x.lo];
+        f.rg = g.vlost[f.x.v];
+        f.r += f.rg;
     }
     // freed blocks in the low half; in the high half, 1 for a source that a
     // whole wave compacts (its rank among those is its slot in the list)
@@ -1260,14 +1289,18 @@ struct FreedIn {
     }
 };
 
+// Also clears each source's hit count (the vertex scratch word is zero
+// between calls) and adds the hits of every workgroup into tot[kTotA].
 struct FreedOut {
     DevCounters* ctr;
     CDesc* cd;
     uint32_t* big;
     uint32_t* mid;  // sources for whole waves
+    uint32_t* vlost;
     __device__ void operator()(uint64_t t, const FreedRec& f, uint64_t lim,
                                unsigned long long pre) const {
         if (t >= lim) return;
+        if (f.rg) vlost[f.x.v] = 0u;
         if (f.r && f.r <= kBigR && !lane_compactable(f.r, f.x.lo, f.x.hi))
             mid[(uint32_t)(pre >> 32)] = (uint32_t)t;
         CDesc c;
@@ -1281,6 +1314,10 @@ struct FreedOut {
         c.need = (uint32_t)pre;
         cd[t] = c;
         if (c.r > kBigR) big[atomicAdd(&ctr->n_big, 1u)] = (uint32_t)t;
+    }
+    __device__ unsigned long long tally(uint64_t, const FreedRec& f) const { return f.r; }
+    __device__ void commit(unsigned long long sum) const {
+        if (sum) atomicAdd(&ctr->tot[kTotA], sum);
     }
 };
 
@@ -1889,7 +1926,8 @@ static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint
           &tot[kTotSeg]);
     const uint32_t chunk = g->tune.item_chunk;
     scan2(c, "items", ItemIn{v, A.t_vtx, A.t_start, chunk},
-          ItemOut{A.items, A.small, v.B, icap, chunk}, n, A.part, &tot[kTotItems]);
+          ItemOut{A.items, A.small, v.B, icap, chunk, mode == kDelete ? A.b : nullptr}, n,
+          A.part, &tot[kTotItems]);
     const uint32_t pg = g->tune.probe_group, pu = g->tune.probe_unroll;
     const uint64_t pwant = div_up(icap, (uint64_t)kWaves * (64 / pg));
     // launches the probe variant of the graph's tuning
@@ -1898,7 +1936,7 @@ static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint
         with_probe<M>(pg, pu, [&](auto kernel) {
             c.launch(name, kernel, std::min<uint64_t>(pwant, resident_grid(kernel, kThreads)),
                      kThreads, v, keys, (const Item*)A.items, (const Item*)A.small, A.mark,
-                     hitpos);
+                     hitpos, A.b);
         });
     };
     const uint64_t tgrid = std::min<uint64_t>(div_up(n, kThreads), resident_grid(k_grow, kThreads));
@@ -1924,9 +1962,8 @@ static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint
                  (const uint32_t*)A.rel, (const uint32_t*)A.t_dold, (const uint32_t*)A.t_doldc);
     } else if (mode == kDelete) {
         probe(std::integral_constant<int, kDelete>{}, "probe_delete", A.hitpos);
-        scan2(c, "found", FoundIn{A.mark, ctr}, U32Out{A.b}, n + 1, A.part, &tot[kTotA]);
         scan2(c, "freed", FreedIn{v, A.t_vtx, A.t_start, A.b},
-              FreedOut{ctr, A.cdesc, A.big, A.heavy}, n, A.part, &tot[kTotB]);
+              FreedOut{ctr, A.cdesc, A.big, A.heavy, v.vlost}, n, A.part, &tot[kTotB]);
         const uint32_t nbig = kBigGroups;
         c.launch("compact", k_compact,
                  nbig + std::min<uint64_t>(div_up(n, kThreads), resident_grid(k_compact, kThreads)),
