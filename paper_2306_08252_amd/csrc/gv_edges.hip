@@ -412,12 +412,26 @@ struct SegIn {
     const uint64_t* keys;
     const DevCounters* ctr;
     uint32_t L;
+    // valid pairs: tot[kTotValid], or (sort overlap) the count the packing
+    // left in the batch's buffer, with the key sum after it
+    const unsigned long long* nvalid;
+    // sort overlap: the batch counters, cleared by begin() and given the
+    // packing's count and key sum (the previous batch used them until now)
+    DevCounters* clr;
     struct Rec {
         uint64_t k, p;
     };
+    __device__ void begin() const {
+        if (!clr) return;
+        clear_batch_counters(clr, threadIdx.x);
+        if (threadIdx.x == 0) {
+            clr->tot[kTotValid] = nvalid[0];
+            clr->tot[kTotHash] = nvalid[1];
+        }
+    }
     // no segments after a look-back wait ran out (the keys are not sorted)
     __device__ uint64_t limit(uint64_t n) const {
-        return ctr->err_wait ? 0ull : min((uint64_t)ctr->tot[kTotValid], n);
+        return ctr->err_wait ? 0ull : min((uint64_t)*nvalid, n);
     }
     __device__ Rec load(uint64_t i, bool ok) const {
         const uint64_t j = ok ? i : 0;
@@ -1907,7 +1921,10 @@ static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint
         sc.close_run();
         hip_check(hipEventRecord(o.sorted[ob], o.stream), "hipEventRecord");
         hip_check(hipStreamWaitEvent(c.stream, o.sorted[ob], 0), "hipStreamWaitEvent");
-        c.launch("pack", k_ov_begin, 1, 64, v, (const unsigned long long*)A.stot);
+        // the segment scan's first kernel clears the batch counters (a batch
+        // of one scan tile has no such kernel: a kernel of its own does it)
+        if (scan2_tiles<SegIn>(n) <= 1)
+            c.launch("pack", k_ov_begin, 1, 64, v, (const unsigned long long*)A.stot);
     } else {
         const uint64_t sentinel = bits >= 64 ? ~0ull : (1ull << bits) - 1;
         c.launch("pack", k_pack_hist, os_hist_groups(n), kOsThreads, v, src, dst, n,
@@ -1921,7 +1938,10 @@ static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint
     const uint64_t* keys = keys_in ? keys_in : flip ? A.keys1 : A.keys0;
     const uint32_t* vals = flip ? A.vals1 : A.vals0;
 
-    scan2(c, "segments", SegIn{keys, ctr, v.L},
+    const bool seg_clears = ovb && scan2_tiles<SegIn>(n) > 1;
+    scan2(c, "segments",
+          SegIn{keys, ctr, v.L, ovb ? (const unsigned long long*)A.stot : n_valid,
+                seg_clears ? ctr : nullptr},
           SegOut{v.L, A.flags, A.a, A.t_vtx, A.t_start, ctr}, n, A.part,
           &tot[kTotSeg]);
     const uint32_t chunk = g->tune.item_chunk;

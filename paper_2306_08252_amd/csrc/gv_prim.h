@@ -271,6 +271,11 @@ __device__ __forceinline__ void st_status32(uint32_t* p, uint32_t v) {
 // and
 //   void finish()                       run by the first wave of the last
 //                                       workgroup once the total is written
+// and a source may define
+//   void begin()                        run by every thread of the reduce
+//                                       kernel's first workgroup (when the
+//                                       scan has more than one tile), before
+//                                       the apply kernel starts
 // Elements per thread: In::kItems when the source defines it (sources with
 // large records take fewer, to keep registers low), else kScan1Items.
 template <typename In, typename = void>
@@ -286,6 +291,11 @@ struct scan2_has_tally : std::false_type {};
 template <typename Out>
 struct scan2_has_tally<Out, std::void_t<decltype(std::declval<const Out&>().commit(0ull))>>
     : std::true_type {};
+template <typename In, typename = void>
+struct scan2_has_begin : std::false_type {};
+template <typename In>
+struct scan2_has_begin<In, std::void_t<decltype(std::declval<const In&>().begin())>>
+    : std::true_type {};
 template <typename Out, typename = void>
 struct scan2_has_finish : std::false_type {};
 template <typename Out>
@@ -298,6 +308,9 @@ __global__ __launch_bounds__(kThreads) void k_scan2_reduce(In in, uint64_t n,
                                                            unsigned long long* part) {
     constexpr int kI = scan2_items<In>::value;
     __shared__ unsigned long long s_w[kWaves];
+    if constexpr (scan2_has_begin<In>::value) {
+        if (blockIdx.x == 0) in.begin();
+    }
     const uint64_t lim = in.limit(n);
     const uint64_t base = (uint64_t)blockIdx.x * kThreads * kI + threadIdx.x;
     typename In::Rec r[kI];
@@ -417,6 +430,12 @@ inline uint64_t scan2_parts(uint64_t n) {
     return div_up(std::max<uint64_t>(n, 1), (uint64_t)kThreads * kScan2MinItems);
 }
 
+// tiles of a scan2 over n elements (one tile: no reduce kernel)
+template <typename In>
+inline uint64_t scan2_tiles(uint64_t n) {
+    return div_up(n, (uint64_t)kThreads * scan2_items<In>::value);
+}
+
 // Exclusive scan of in(i), i < n, as out(i, rec, lim, prefix); total ->
 // *total.  `part` holds scan2_parts(n) words.
 template <typename In, typename Out>
@@ -425,7 +444,7 @@ void scan2(Ctx& c, const char* name, In in, Out out, uint64_t n, unsigned long l
     static_assert(scan2_items<In>::value >= kScan2MinItems,
                   "the partials are sized for kScan2MinItems elements per thread");
     if (n == 0) return;
-    const uint64_t nt = div_up(n, (uint64_t)kThreads * scan2_items<In>::value);
+    const uint64_t nt = scan2_tiles<In>(n);
     if (nt > 0xffffffffull) fail(GV_EINVAL, "scan too large");
     // a single tile adds no earlier partials: the apply kernel is the scan
     if (nt > 1) c.launch(name, k_scan2_reduce<In>, nt, kThreads, in, n, part);
