@@ -87,21 +87,26 @@ class _PinnedRing:
         return b[:count]
 
 
-def _enqueue_tick(graph, requests, i, j, dev, slot):
+def _one_or_cat(parts):
+    return parts[0] if len(parts) == 1 else torch.cat(parts)
+
+
+def _enqueue_tick(graph, requests, i, j, dev, slot, codes):
     """Queues one tick's work on the graph's stream without waiting: the
     tick's edge inserts and deletes as one mixed list, then its queries as
     one batch whose answers are copied to pinned host memory (`slot` of the
-    ring).  Returns the tick record (its tensors stay referenced until it
-    completes)."""
+    ring).  `codes` holds a row of insert op codes and a row of delete op
+    codes, as long as the longest request, so that a request's op array is a
+    view and a tick of one request copies nothing.  Returns the tick record
+    (its tensors stay referenced until it completes)."""
     ws = [(m, r) for m, r in enumerate(requests[i:j], start=i) if r[0] in (INSERT, DELETE)]
     qs = [(m, r) for m, r in enumerate(requests[i:j], start=i) if r[0] == QUERY]
     keep = []
     wstats = None
     if ws:
-        op = torch.cat([torch.full((_size(r),), r[0], dtype=torch.uint8, device=dev)
-                        for _, r in ws])
-        src = torch.cat([r[1] for _, r in ws])
-        dst = torch.cat([r[2] for _, r in ws])
+        op = _one_or_cat([codes[r[0], :_size(r)] for _, r in ws])
+        src = _one_or_cat([r[1] for _, r in ws])
+        dst = _one_or_cat([r[2] for _, r in ws])
         ends_h = _PinnedRing.buf(slot, "ends", len(ws), torch.int64)
         ends_h.copy_(torch.from_numpy(np.cumsum([_size(r) for _, r in ws]).astype(np.int64)))
         ends = ends_h.to(dev, non_blocking=True)
@@ -111,8 +116,8 @@ def _enqueue_tick(graph, requests, i, j, dev, slot):
         wstats.copy_(st, non_blocking=True)
     host = None
     if qs:
-        out = graph.edge_exists(torch.cat([r[1] for _, r in qs]),
-                                torch.cat([r[2] for _, r in qs]))
+        out = graph.edge_exists(_one_or_cat([r[1] for _, r in qs]),
+                                _one_or_cat([r[2] for _, r in qs]))
         host = _PinnedRing.buf(slot, "answers", out.numel(), out.dtype)
         host.copy_(out, non_blocking=True)
         keep.append(out)
@@ -153,6 +158,11 @@ def serve(graph, requests, arrivals=None, max_tick_pairs=1 << 20, keep_answers=F
     answers = {}
     flight = []
     ring = _PinnedRing(max_inflight + 1)
+    # op codes of every write request as views: row INSERT of zeros, row
+    # DELETE of ones
+    longest = max([_size(r) for r in requests if r[0] in (INSERT, DELETE)], default=1)
+    codes = torch.zeros((2, max(longest, 1)), dtype=torch.uint8, device=dev)
+    codes[DELETE].fill_(1)
     # the id check of vertex inserts runs on a second stream (default
     # priority), after the work queued before the server started (which made
     # the requests) and independent of the ticks queued since
@@ -251,7 +261,7 @@ def serve(graph, requests, arrivals=None, max_tick_pairs=1 << 20, keep_answers=F
             done[i] = clock() - t0
             i += 1
             continue
-        flight.append(_enqueue_tick(graph, requests, i, j, dev, ring.take()))
+        flight.append(_enqueue_tick(graph, requests, i, j, dev, ring.take(), codes))
         ticks.append((i, j))
         free -= need
         i = j
