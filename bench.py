@@ -813,7 +813,7 @@ def main():
     pct_m1 = m1 / elapsed / (HBM_PEAK_GBS * 1e9)
 
     # per-launch quantities of the dominant kernel's batch type
-    if dominant in ("probe_delete", "found", "freed", "compact", "final_delete"):
+    if dominant in ("probe_delete", "freed", "compact", "final_delete"):
         per = {"k": k, "T": del_T / K, "S": del_S / K, "NB": del_S / K / B,
                "W": 0, "M": d["moved_slots"] / K, "FREED": d["freed_blocks"] / K}
     else:
