@@ -262,7 +262,7 @@ def summarize_counters(pmc_dir, out_md, command, title):
         vals = [f"{statistics.mean(cs[c]):.0f}" if c in cs else "" for c in names]
         lines.append(f"| `{k}` | {wg} | {nd} | " + " | ".join(vals) + " |")
     with open(out_md, "w") as f:
-        f.write(f"# {title}\n\nCommand (GPU box, repo root as $R):\n\n```\n{command}\n```\n\n"
+        f.write(f"# {title}\n\nCommand (repo root as $R):\n\n```\n{command}\n```\n\n"
                 "Average counter value per dispatch, library kernels only:\n\n" +
                 "\n".join(lines) + "\n")
 
@@ -309,7 +309,7 @@ def summarize_trace(trace_dir, out_md, command):
         lines.append(f"| `{k}` | {wg} | {len(v)} | {statistics.mean(v) / 1e3:.2f} | "
                      f"{sum(v) / 1e3:.1f} |")
     with open(out_md, "w") as f:
-        f.write(f"# Kernel trace: {os.path.basename(out_md)[:-3]}\n\nCommand (GPU box, repo root "
+        f.write(f"# Kernel trace: {os.path.basename(out_md)[:-3]}\n\nCommand (repo root "
                 f"as $R):\n\n```\n{command}\n```\n\nDurations from the kernel trace (ns -> "
                 f"us), library kernels only:\n\n" + "\n".join(lines) + "\n")
 
@@ -363,7 +363,7 @@ def summarize_traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, grid_wgs, ou
         json.dump(t, f, indent=1)
     with open(out_md, "w") as f:
         f.write("# HBM traffic per dispatch: R-MAT 2^20 / 2^24 edges, B=16, batches of 10^6\n\n"
-                "Commands (GPU box, repo root as $R):\n\n```\n" + "\n".join(commands) +
+                "Commands (repo root as $R):\n\n```\n" + "\n".join(commands) +
                 "\n```\n\nCalibration: a plain 1 GiB device copy reads "
                 f"{1 / f_factor:.3f} GiB by FETCH_SIZE and writes {1 / w_factor:.3f} GiB by "
                 f"WRITE_SIZE, so FETCH_SIZE is scaled by {f_factor:.3f} and WRITE_SIZE by "
@@ -689,7 +689,7 @@ def main():
                           args.command)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: this library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
