@@ -64,7 +64,10 @@ constexpr uint32_t kHeavy = 0x100u;            // flag bit in t_dreq: whole wave
 constexpr uint32_t kClassMask = 0xFFu;         // t_dreq & kClassMask: requested class or kNoDir
 
 // scan-total slots in DevCounters::tot
-enum { kTotValid = 0, kTotSeg = 1, kTotItems = 2, kTotA = 3, kTotB = 4, kTotHash = 5 };
+enum {
+    kTotValid = 0, kTotSeg = 1, kTotItems = 2, kTotA = 3, kTotB = 4, kTotHash = 5,
+    kTotNoHash = 6  // set for a batch whose keys arrived sorted: no multiset check
+};
 // probe mode of the attribute calls: a query that also records the slot of
 // every occurrence it finds
 constexpr int kLocate = 3;
@@ -798,7 +801,7 @@ __global__ __launch_bounds__(kThreads) void k_probe(GraphView g, const uint64_t*
         // the sorted keys must be the packed keys: their mix64 sums agree
         // (per-workgroup sums of the segment scan in 64 stripes; one load a lane)
         const unsigned long long sorted = wave_sum(g.ctr->stripe[lane_id()][kStripeHash]);
-        if (sorted != g.ctr->tot[kTotHash]) {
+        if (!g.ctr->tot[kTotNoHash] && sorted != g.ctr->tot[kTotHash]) {
             if (lane_id() == 0) g.ctr->err_order = 3;
             return;
         }
@@ -1727,39 +1730,29 @@ size_t edge_batch_bytes(const gv_graph* g, EdgeMode mode, uint64_t n) {
 }
 
 // Insert and delete batches whose keys arrive sorted (keys[0, *count), the
-// count on the device): the first kernel clears the batch counters and sets
-// the valid count, the second clears the marks and adds up the keys' mix64
-// sum (the probe's multiset check then holds the sorted keys to it).
-__global__ void k_sorted_prep_a(GraphView g, const unsigned long long* count) {
-    clear_batch_counters(g.ctr, threadIdx.x);
-    if (threadIdx.x == 0) g.ctr->tot[kTotValid] = *count;
-}
-
-__global__ __launch_bounds__(kThreads) void k_sorted_prep_b(GraphView g, const uint64_t* keys,
-                                                            const unsigned long long* count,
-                                                            uint64_t n, uint8_t* mark) {
-    __shared__ unsigned long long s_w[kWaves];
+// count on the device; they come from the library's own sort of a mixed
+// list): one kernel clears the marks, and its first workgroup clears the
+// batch counters, sets the valid count and turns the probe's multiset check
+// off (there is no packing to compare with; the segment scan still checks
+// the order).
+__global__ __launch_bounds__(kThreads) void k_sorted_prep(GraphView g,
+                                                          const unsigned long long* count,
+                                                          uint64_t n, uint8_t* mark) {
     const uint64_t i = thread_index();
-    const uint64_t nv = *count;
     if (i < n) mark[i] = 0;
-    const unsigned long long h = i < nv ? mix64(keys[i]) : 0ull;
-    const unsigned long long t = block_sum(h, s_w);
-    if (threadIdx.x == 0 && t) atomicAdd(&g.ctr->tot[kTotHash], t);
+    if (blockIdx.x == 0) {
+        clear_batch_counters(g.ctr, threadIdx.x);
+        if (threadIdx.x == 0) {
+            g.ctr->tot[kTotValid] = *count;
+            g.ctr->tot[kTotNoHash] = 1;
+        }
+    }
 }
 
 static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t* dst,
                      const uint64_t* sorted, const unsigned long long* sorted_n, uint64_t n,
                      uint8_t* out, bool sticky, void* fixed, size_t fixed_bytes,
                      uint8_t* mark_out, const AttrOp* aop = nullptr);
-
-// the probe's per-key result of a sorted batch (stored before the batch, for
-// an insert; found, for a delete), out of the batch's scratch
-__global__ __launch_bounds__(kThreads) void k_copy_marks(const uint8_t* mark,
-                                                         const unsigned long long* count,
-                                                         uint64_t n_max, uint8_t* out) {
-    const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i < min((uint64_t)*count, n_max)) out[i] = mark[i];
-}
 
 void edge_batch(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t* dst, uint64_t n,
                 uint8_t* out, bool sticky, void* fixed, size_t fixed_bytes) {
@@ -1860,6 +1853,9 @@ static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint
         }
         Carver cv(base);
         carve_batch(cv, A, n, icap, mode, bits);
+        // a sorted batch's probe writes its per-key result where the caller
+        // wants it (n_max bytes)
+        if (mark_out && sorted) A.mark = mark_out;
     }
     DevCounters* ctr = v.ctr;
     uint32_t* err = &ctr->err_wait;
@@ -1870,8 +1866,7 @@ static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint
     bool flip;
     const uint64_t* keys_in = nullptr;
     if (sorted) {
-        c.launch("pack", k_sorted_prep_a, 1, 64, v, sorted_n);
-        c.launch("pack", k_sorted_prep_b, grid, kThreads, v, sorted, sorted_n, n, A.mark);
+        c.launch("pack", k_sorted_prep, grid, kThreads, v, sorted_n, n, A.mark);
         keys_in = sorted;
         flip = false;
     } else if (mode == kQuery && n <= kOsTile && bits + kTilePosBits < 64) {
@@ -2004,9 +1999,6 @@ static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint
         probe(std::integral_constant<int, kQuery>{}, "probe_query", nullptr);
         c.launch("answer", k_answer, grid, kThreads, v, vals, (const uint8_t*)A.mark, n, out);
     }
-    if (mark_out && sorted)
-        c.launch("marks", k_copy_marks, grid, kThreads, (const uint8_t*)A.mark, sorted_n, n,
-                 mark_out);
     if (ovb) {
         gv_graph::Overlap& o = g->ov;
         hip_check(hipEventRecord(o.done[ob], c.stream), "hipEventRecord");

@@ -105,24 +105,26 @@ struct SplitIn {
     }
 };
 
+// The scan total holds both counts; finish() splits it for the two sorted
+// batches, which read one each (cnt[1] deletes, cnt[2] inserts).
 struct SplitOut {
     SplitIn in;
     uint64_t* del_keys;
     uint64_t* ins_keys;
+    unsigned long long* cnt;  // [0] the scan total
     __device__ void operator()(uint64_t, const SplitIn::Rec& r, uint64_t,
                                unsigned long long pre) const {
         const int k = in.kind(r);
         if (k == 1) del_keys[(uint32_t)pre] = r.k;
         else if (k == 2) ins_keys[(uint32_t)(pre >> 32)] = r.k;
     }
+    __device__ void finish() const {
+        if (threadIdx.x == 0) {
+            cnt[1] = cnt[0] & 0xffffffffull;
+            cnt[2] = cnt[0] >> 32;
+        }
+    }
 };
-
-// the scan total holds both counts; the two sorted batches read one each
-__global__ void k_mixed_counts(const unsigned long long* total, unsigned long long* del_n,
-                               unsigned long long* ins_n) {
-    *del_n = *total & 0xffffffffull;
-    *ins_n = *total >> 32;
-}
 
 // ---- per-request statistics
 // Request r is entries [end[r-1], end[r]).  As if each request were applied
@@ -149,11 +151,14 @@ __device__ __forceinline__ uint32_t request_of(const uint64_t* end, uint32_t n_r
 
 // one thread per sorted entry: its flag, and for a pair's first entry the
 // index of the pair in the kept delete or insert keys
+// (also zeroes the per-request statistics, one thread per request, for the
+// counts added later)
 __global__ __launch_bounds__(kThreads) void k_mixed_flags(
     GraphView g, const uint64_t* sk, const uint32_t* sp, const uint8_t* op, uint64_t n,
     const uint64_t* end, uint32_t n_req, const uint64_t* del_keys, const uint64_t* ins_keys,
-    const unsigned long long* cnt, uint8_t* flag, uint32_t* fref) {
+    const unsigned long long* cnt, uint8_t* flag, uint32_t* fref, gv_batch_stats* stats) {
     const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n_req) stats[i] = gv_batch_stats{0ull, 0ull, 0ull};
     if (i >= n) return;
     const uint64_t k = sk[i];
     const uint32_t p = sp[i];
@@ -334,17 +339,14 @@ void mixed_edges(gv_graph* g, const uint8_t* op, const uint32_t* src, const uint
     const uint64_t* sk = flip ? k1 : k0;
     const uint32_t* sp = flip ? p1 : p0;
     const SplitIn in{sk, sp, op, n, v.L};
-    scan2(c, "mixed_split", in, SplitOut{in, del_keys, ins_keys}, n, part, &cnt[0]);
-    c.launch("mixed_split", k_mixed_counts, 1, 1, (const unsigned long long*)&cnt[0], &cnt[1],
-             &cnt[2]);
+    scan2(c, "mixed_split", in, SplitOut{in, del_keys, ins_keys, cnt}, n, part, &cnt[0]);
     if (stats)  // before the batches reuse the sorted entries' scratch
-        c.launch("mixed_stats", k_mixed_flags, div_up(n, kThreads), kThreads, v, sk, sp, op, n,
-                 end, (uint32_t)n_req, (const uint64_t*)del_keys,
-                 (const uint64_t*)ins_keys, (const unsigned long long*)cnt, flag, fref);
+        c.launch("mixed_stats", k_mixed_flags, div_up(std::max<uint64_t>(n, n_req), kThreads),
+                 kThreads, v, sk, sp, op, n, end, (uint32_t)n_req, (const uint64_t*)del_keys,
+                 (const uint64_t*)ins_keys, (const unsigned long long*)cnt, flag, fref, stats);
     edge_batch_sorted(g, kDelete, del_keys, &cnt[1], n, true, del_found);
     edge_batch_sorted(g, kInsert, ins_keys, &cnt[2], n, true, ins_had);
     if (stats) {
-        c.launch("mixed_stats", k_stats_zero, div_up(n_req, kThreads), kThreads, stats, n_req);
         c.launch("mixed_stats", k_request_stats, div_up(n, (uint64_t)kThreads * kStatItems),
                  kThreads, end, n_req, n, (const uint8_t*)flag, (const uint32_t*)fref,
                  (const uint8_t*)del_found, (const uint8_t*)ins_had, stats);
