@@ -631,9 +631,9 @@ __device__ __forceinline__ void probe_load(const GraphView& g, const Item& I, co
 }
 
 // Searches of the U slots of a lane run in lockstep, so that each step
-// issues U independent reads and waits once.
+// issues U independent reads and waits once.  Returns the lane's hits
+// (delete: slots tombstoned).
 template <int MODE, int G, int U>
-// Returns the lane's hits (delete: slots tombstoned).
 __device__ __forceinline__ uint32_t probe_search(const GraphView& g, const Item& I, uint32_t s,
                                                  const uint32_t (&x)[U],
                                                  const uint64_t (&addr)[U], const uint32_t* st,
@@ -727,9 +727,9 @@ __device__ __forceinline__ uint32_t probe_search(const GraphView& g, const Item&
 // loaded whole and compared pairwise.  Same marks as the group search: insert
 // and delete mark the first occurrence of a stored pair (delete also records
 // the slot and tombstones it), query marks every occurrence.  A stored pair
-// sits in one slot, so one lane at most marks a segment entry.
+// sits in one slot, so one lane at most marks a segment entry.  Returns the
+// lane's hits (delete).
 template <int MODE>
-// Returns the lane's hits (delete).
 __device__ __forceinline__ uint32_t probe_small(const GraphView& g, const Item& I, uint32_t q,
                                                 const uint64_t* keys, uint8_t* mark,
                                                 uint32_t* hitpos) {
