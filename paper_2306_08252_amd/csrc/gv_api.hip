@@ -52,13 +52,15 @@ void free_graph(gv_graph* g) {
     if (o.stream) {
         hipStreamSynchronize(o.stream);
         o.ctx.release();
-        hipEvent_t evs[] = {o.sorted[0], o.sorted[1], o.done[0], o.done[1], o.fence};
+        hipEvent_t evs[] = {o.sorted[0],  o.sorted[1],  o.done[0],  o.done[1], o.fence,
+                            o.msorted[0], o.msorted[1], o.mdone[0], o.mdone[1]};
         for (hipEvent_t e : evs)
             if (e) hipEventDestroy(e);
         hipStreamDestroy(o.stream);
         o.stream = nullptr;
     }
     o.scr.release();
+    for (auto& m : o.mix) m.release();
     g->scratch.release();
     for (auto& v : g->vscr) v.release();
     g->cscr.release();
@@ -341,7 +343,7 @@ int gv_memory_used(gv_graph* g, gv_mem* out) {
                            8ull * v.cap_blocks + 4ull * v.n_cap +
                            4ull * v.A * v.cap_blocks * v.B + m.directory_bytes +
                            m.vertex_table_bytes + sizeof(DevCounters) + g->scratch.cap +
-                           g->ov.scr.cap;
+                           g->ov.scr.cap + g->ov.mix[0].cap + g->ov.mix[1].cap;
         *out = m;
     });
 }

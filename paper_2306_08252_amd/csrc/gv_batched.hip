@@ -17,6 +17,7 @@
 #include <new>
 
 #include "gv_graph.h"
+#include "gv_prim.h"
 
 using namespace gv;
 
@@ -31,6 +32,7 @@ struct gv_plan {
     uint64_t table_gen = 0;
     uint64_t cscr_gen = 0;
     uint64_t ovscr_gen = 0;     // the sort overlap's second batch buffer
+    uint64_t mix_gen[2] = {0, 0};  // the sort overlap's mixed-list buffers
     uint64_t insert_pairs = 0;  // pairs the plan's inserts add to the host-side edge bound
 };
 
@@ -83,13 +85,9 @@ uint64_t run_end(const gv_op* ops, uint64_t n_ops, uint64_t i, uint64_t max_pair
     return j;
 }
 
-// apply a run of edge batches as one mixed list
-void run_coalesced(gv_graph* g, const gv_op* ops, uint64_t i, uint64_t j, uint64_t pairs) {
-    Ctx& c = g->ctx;
-    g->cscr.ensure(std::max<size_t>(pairs * 9, 4), c.stream);
-    uint32_t* src = (uint32_t*)g->cscr.ptr;
-    uint32_t* dst = src + pairs;
-    uint8_t* op = (uint8_t*)(dst + pairs);
+// copies the edge batches of ops[i, j) into one list on the context's stream
+void gather_run(Ctx& c, const gv_op* ops, uint64_t i, uint64_t j, uint8_t* op, uint32_t* src,
+                uint32_t* dst) {
     CopyArgs args{};
     uint32_t cnt = 0;
     uint64_t off = 0, big = 0;
@@ -111,6 +109,30 @@ void run_coalesced(gv_graph* g, const gv_op* ops, uint64_t i, uint64_t j, uint64
         if (++cnt == kCopyDescs) flush();
     }
     flush();
+}
+
+// Lists longer than one sort tile have their gather and sort overlapped
+// (with the overlap on); a list of one tile is sorted by one kernel.
+bool side_run(const gv_graph* g, uint64_t pairs) { return g->tune.overlap && pairs > kOsTile; }
+
+// apply a run of edge batches as one mixed list; `fenced`: a list of this
+// call went to the side stream already
+void run_coalesced(gv_graph* g, const gv_op* ops, uint64_t i, uint64_t j, uint64_t pairs,
+                   bool& fenced) {
+    Ctx& c = g->ctx;
+    if (side_run(g, pairs)) {
+        mixed_edges_side(g, pairs, !fenced,
+                         [&](Ctx& sc, uint8_t* op, uint32_t* src, uint32_t* dst) {
+                             gather_run(sc, ops, i, j, op, src, dst);
+                         });
+        fenced = true;
+        return;
+    }
+    g->cscr.ensure(std::max<size_t>(pairs * 9, 4), c.stream);
+    uint32_t* src = (uint32_t*)g->cscr.ptr;
+    uint32_t* dst = src + pairs;
+    uint8_t* op = (uint8_t*)(dst + pairs);
+    gather_run(c, ops, i, j, op, src, dst);
     mixed_edges(g, op, src, dst, pairs);
 }
 
@@ -177,6 +199,7 @@ int guarded_call(gv_graph* g, F&& f) {
 
 void run_ops(gv_graph* g, const gv_op* ops, uint64_t n_ops, bool recorded, uint64_t bound) {
     uint64_t i = 0;
+    bool fenced = false;
     while (i < n_ops) {
         if (g->tune.coalesce && is_edge(ops[i])) {
             uint64_t pairs = 0;
@@ -184,7 +207,7 @@ void run_ops(gv_graph* g, const gv_op* ops, uint64_t n_ops, bool recorded, uint6
             uint64_t batches = 0;
             for (uint64_t k = i; k < j; ++k) batches += ops[k].n ? 1 : 0;
             if (batches > 1) {
-                run_coalesced(g, ops, i, j, pairs);
+                run_coalesced(g, ops, i, j, pairs, fenced);
             } else {
                 for (uint64_t k = i; k < j; ++k) run_op(g, ops[k], recorded, bound);
             }
@@ -220,7 +243,7 @@ int gv_plan_create(gv_graph* g, const gv_op* ops, uint64_t n_ops, gv_plan** out)
         // every stored edge holds a pool slot
         const uint64_t bound = std::max<uint64_t>(g->v.cap_blocks * (uint64_t)g->v.B, 1);
         // size every buffer for the largest op (and run)
-        size_t sc = 0, vs[3] = {0, 0, 0}, csz = 0;
+        size_t sc = 0, vs[3] = {0, 0, 0}, csz = 0, msz = 0;
         for (uint64_t i = 0; g->tune.coalesce && i < n_ops;) {
             if (!is_edge(ops[i])) {
                 ++i;
@@ -232,7 +255,8 @@ int gv_plan_create(gv_graph* g, const gv_op* ops, uint64_t n_ops, gv_plan** out)
             mixed_bytes(g, std::max<uint64_t>(pairs, 1), mb);
             sc = std::max(sc, mb[0]);
             vs[0] = std::max(vs[0], mb[1]);
-            csz = std::max<size_t>(csz, pairs * 9);
+            if (side_run(g, pairs)) msz = std::max(msz, mixed_side_bytes(g, pairs));
+            else csz = std::max<size_t>(csz, pairs * 9);
             i = j;
         }
         for (uint64_t i = 0; i < n_ops; ++i) {
@@ -256,6 +280,11 @@ int gv_plan_create(gv_graph* g, const gv_op* ops, uint64_t n_ops, gv_plan** out)
             // edge batches alternate between the two batch buffers
             g->ov.scr.ensure(std::max<size_t>(sc, 4), c.stream);
             overlap_open(g);
+            // and mixed lists between the two mixed-list buffers
+            if (msz) {
+                hip_check(hipStreamSynchronize(g->ov.stream), "hipStreamSynchronize");
+                for (int k = 0; k < 2; ++k) g->ov.mix[k].ensure(msz, c.stream);
+            }
         }
         hip_check(hipStreamSynchronize(c.stream), "hipStreamSynchronize");
         edge_batch_warm(g);
@@ -298,6 +327,7 @@ int gv_plan_create(gv_graph* g, const gv_op* ops, uint64_t n_ops, gv_plan** out)
         p->table_gen = g->table_gen;
         p->cscr_gen = g->cscr.gen;
         p->ovscr_gen = g->ov.scr.gen;
+        for (int k = 0; k < 2; ++k) p->mix_gen[k] = g->ov.mix[k].gen;
     });
     if (rc != GV_OK) {
         gv_plan_destroy(p);
@@ -314,6 +344,7 @@ int gv_plan_launch(gv_plan* p) {
         bool same = g->scratch.gen == p->scratch_gen && g->table_gen == p->table_gen &&
                     g->cscr.gen == p->cscr_gen && g->ov.scr.gen == p->ovscr_gen;
         for (int k = 0; k < 3; ++k) same = same && g->vscr[k].gen == p->vscr_gen[k];
+        for (int k = 0; k < 2; ++k) same = same && g->ov.mix[k].gen == p->mix_gen[k];
         if (!same) fail(GV_EINVAL, "graph buffers moved since the plan was created");
         hip_check(hipGraphLaunch(p->exec, g->ctx.stream), "hipGraphLaunch");
         ++g->ctx.seq;

@@ -1799,7 +1799,8 @@ void overlap_open(gv_graph* g) {
     if (o.stream) return;
     hip_check(hipStreamCreateWithFlags(&o.stream, hipStreamNonBlocking), "hipStreamCreate");
     o.ctx.stream = o.stream;
-    hipEvent_t* evs[] = {&o.sorted[0], &o.sorted[1], &o.done[0], &o.done[1], &o.fence};
+    hipEvent_t* evs[] = {&o.sorted[0], &o.sorted[1], &o.done[0],    &o.done[1], &o.fence,
+                         &o.msorted[0], &o.msorted[1], &o.mdone[0], &o.mdone[1]};
     for (hipEvent_t* e : evs)
         hip_check(hipEventCreateWithFlags(e, hipEventDisableTiming), "hipEventCreate");
 }
@@ -1810,6 +1811,24 @@ static unsigned long long capture_id(hipStream_t s) {
     unsigned long long id = 0;
     hip_check(hipStreamGetCaptureInfo(s, &st, &id), "hipStreamGetCaptureInfo");
     return st == hipStreamCaptureStatusActive ? id : 0ull;
+}
+
+void overlap_capture(gv_graph* g) {
+    gv_graph::Overlap& o = g->ov;
+    const unsigned long long cap = capture_id(g->ctx.stream);
+    if (cap == o.capture) return;
+    o.capture = cap;
+    o.used[0] = o.used[1] = false;
+    o.mused[0] = o.mused[1] = false;
+    o.seq = ~0ull;
+    o.joined = false;
+}
+
+void overlap_fence(gv_graph* g) {
+    gv_graph::Overlap& o = g->ov;
+    hip_check(hipEventRecord(o.fence, g->ctx.stream), "hipEventRecord");
+    hip_check(hipStreamWaitEvent(o.stream, o.fence, 0), "hipStreamWaitEvent");
+    o.joined = true;
 }
 
 static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint32_t* dst,
@@ -1828,14 +1847,7 @@ static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint
     // capture through the first wait, and the recording keeps both branches)
     const bool ovb = g->tune.overlap && !sorted && !fixed && mode != kQuery && bits > 0 &&
                      n > std::min<uint64_t>(g->tune.small_sort_max, kOsTile);
-    if (ovb) {
-        const unsigned long long cap = capture_id(c.stream);
-        if (cap != g->ov.capture) {
-            g->ov.capture = cap;
-            g->ov.used[0] = g->ov.used[1] = false;
-            g->ov.seq = ~0ull;
-        }
-    }
+    if (ovb) overlap_capture(g);
     const int ob = (int)(g->ov.count & 1);  // its buffer
     BatchArrays A;
     {
@@ -1899,8 +1911,7 @@ static void edge_run(gv_graph* g, EdgeMode mode, const uint32_t* src, const uint
         sc.prof = c.prof;
         sc.only = c.only;
         if (c.seq != o.seq) {
-            hip_check(hipEventRecord(o.fence, c.stream), "hipEventRecord");
-            hip_check(hipStreamWaitEvent(o.stream, o.fence, 0), "hipStreamWaitEvent");
+            overlap_fence(g);
         } else if (o.used[ob]) {
             // (with a fence, the wait for the graph's stream covers this one)
             hip_check(hipStreamWaitEvent(o.stream, o.done[ob], 0), "hipStreamWaitEvent");

@@ -36,6 +36,18 @@ struct gv_graph {
         bool used[2] = {false, false};    // done[k] has been recorded
         uint64_t count = 0;               // overlapped batches (next buffer = count & 1)
         uint64_t seq = ~0ull;             // ctx.seq after the last overlapped batch
+        // Coalesced runs of the batched form (mixed lists): the gather, pack
+        // and sort of a run go to the side stream with buffers of their own,
+        // which alternate; that work reads nothing the graph's stream
+        // changes, so it waits only for the buffer's previous user.
+        gv::Scratch mix[2];
+        hipEvent_t msorted[2] = {nullptr, nullptr};
+        hipEvent_t mdone[2] = {nullptr, nullptr};
+        bool mused[2] = {false, false};
+        uint64_t mcount = 0;
+        // the side stream waited for the graph's stream since the capture
+        // state last changed (its first wait joins a capture)
+        bool joined = false;
         // id of the stream capture the state above belongs to (0: none);
         // events of another capture, or of none, are never waited for
         unsigned long long capture = 0;
@@ -108,6 +120,20 @@ void mixed_edges(gv_graph* g, const uint8_t* op, const uint32_t* src, const uint
 void edge_batch_warm(const gv_graph* g = nullptr);
 // the side stream and events of the sort overlap (made once)
 void overlap_open(gv_graph* g);
+// the overlap's state for the capture the graph's stream is in: state that
+// belongs to another capture (or to none) is dropped
+void overlap_capture(gv_graph* g);
+// the side stream waits for everything queued on the graph's stream so far
+void overlap_fence(gv_graph* g);
+// a mixed list (the batched form's coalesced run) whose entries are written
+// by gather(ctx, op, src, dst) and packed and sorted on the overlap's side
+// stream; the rest of the list runs on the graph's stream.  `fence`: the
+// side stream first waits for everything queued on the graph's stream (the
+// first list of a call); otherwise only for the list that used its buffer
+void mixed_edges_side(gv_graph* g, uint64_t n, bool fence,
+                      const std::function<void(Ctx&, uint8_t*, uint32_t*, uint32_t*)>& gather);
+// bytes of each of the two buffers mixed_edges_side uses for n entries
+size_t mixed_side_bytes(const gv_graph* g, uint64_t n);
 bool probe_shape_ok(uint32_t group, uint32_t unroll);
 void vertex_batch_warm();
 // bytes of g->scratch an edge batch of n pairs carves

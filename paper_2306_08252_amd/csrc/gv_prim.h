@@ -1042,11 +1042,12 @@ constexpr uint64_t kOsMaxKeys = 1ull << 30;
 // Sorts n keys (n on the device when n_dev != null, n_max bounds it) by bits
 // [0, bits), stably, ping-ponging k0/k1 (v0/v1).  `state` must hold
 // os_words(n_max, bits) uint32 words, the first os_zero_words of them
-// zeroed.  Returns true if the result is in k1/v1.
+// zeroed; `concurrent` as for onesweep_passes.  Returns true if the result is
+// in k1/v1.
 template <typename K, bool HasVal>
 bool onesweep(Ctx& c, K* k0, K* k1, uint32_t* v0, uint32_t* v1, const uint32_t* n_dev,
               uint64_t n_max, int bits, uint32_t* state, uint32_t* err,
-              uint32_t spin_limit = kSpinLimit) {
+              uint32_t spin_limit = kSpinLimit, bool concurrent = false) {
     if (n_max <= 1 || bits <= 0) return false;
     if (n_max >= kOsMaxKeys) fail(GV_EINVAL, "sort of 2^30 or more keys");
     const int passes = os_passes(bits);
@@ -1060,7 +1061,7 @@ bool onesweep(Ctx& c, K* k0, K* k1, uint32_t* v0, uint32_t* v1, const uint32_t* 
              (uint32_t)hg, hwords, hist, (const uint32_t*)nullptr, (unsigned long long*)nullptr,
              (const unsigned long long*)nullptr, (unsigned long long*)nullptr);
     return onesweep_passes<K, HasVal>(c, k0, k1, v0, v1, n_dev, n_max, bits, state, err,
-                                      spin_limit);
+                                      spin_limit, concurrent);
 }
 
 // Per-group digit counts of a sort whose histogram kernel is fused into the

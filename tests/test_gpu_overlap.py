@@ -192,3 +192,70 @@ def test_pool_exhaustion_with_overlap_matches_oracle():
     assert g.sync() == gv.GV_OK
     assert_same(g, o, "after the overlapped batches")
     g.close()
+
+
+def test_coalesced_runs_with_overlap_match_oracle():
+    """Runs of edge batches coalesced into mixed lists with the overlap on:
+    the gather, packing and sort of a list longer than one sort tile go to
+    the side stream while the graph's stream applies the list before (and
+    the vertex batch between them).  Vertex deletes and inserts between the
+    runs change which entries count (the scan checks activity on the graph's
+    stream), and one run names ids past the vertex table.  Eager calls, a
+    plan launched around an eager call, all to the oracle's graph."""
+    gv = need_gpu()
+    scale, m, B = 13, 1 << 16, 8
+    w = I.RmatWorkload(scale, m, name="ovc")
+    n = w.num_vertices
+    rng = np.random.default_rng(5)
+    ops = []
+    for j in range(7):
+        for k in range(2 + j % 3):  # runs of 2 to 4 batches, some within one tile
+            size = int(rng.integers(1500, 9000))
+            if k % 2 == 0:
+                ops.append((gv.OP_INSERT_EDGES, *w.insert_batch(size, 10 * j + k)))
+            else:
+                ops.append((gv.OP_DELETE_EDGES, *w.delete_batch(size, 10 * j + k)))
+        ids = rng.integers(0, n, 60).astype(np.uint32)
+        ops.append((gv.OP_DELETE_VERTICES if j % 2 == 0 else gv.OP_INSERT_VERTICES, ids, None))
+    s = rng.integers(0, 2 * n, 7000).astype(np.uint32)
+    d = rng.integers(0, 2 * n, 7000).astype(np.uint32)
+    ops.append((gv.OP_INSERT_EDGES, s, d))
+    ops.append((gv.OP_DELETE_EDGES, s[:3000], d[:3000]))
+    ops.append((gv.OP_INSERT_EDGES, d[:5000], s[:5000]))
+
+    def oracle(times):
+        o = O.OracleGraph(n, w.src, w.dst, block_slots=B)
+        for _ in range(times):
+            for kind, a, b in ops:
+                if kind == gv.OP_INSERT_EDGES:
+                    o.insert_edges(a, b)
+                elif kind == gv.OP_DELETE_EDGES:
+                    o.delete_edges(a, b)
+                elif kind == gv.OP_DELETE_VERTICES:
+                    o.delete_vertices(a)
+                else:
+                    o.insert_vertices(a)
+        return o
+
+    g = gv.Graph(n, w.src, w.dst, block_slots=B)
+    gv.gv_set_tuning(g.h, coalesce=1, overlap=1)
+    say("overlap coalesced eager")
+    for _ in range(2):
+        keep = gv.gv_apply_ops(g.h, ops, g.device)
+        assert g.sync() == 0
+        del keep
+    assert_same(g, oracle(2), "eager, two calls")
+    g.close()
+
+    g = gv.Graph(n, w.src, w.dst, block_slots=B)
+    gv.gv_set_tuning(g.h, coalesce=1, overlap=1)
+    say("overlap coalesced plan")
+    plan = gv.Plan(g.h, ops, g.device)
+    plan.launch()
+    keep = gv.gv_apply_ops(g.h, ops, g.device)
+    plan.launch()
+    assert g.sync() == 0
+    del keep
+    plan.close()
+    assert_same(g, oracle(3), "plan, eager call, plan")
+    g.close()
