@@ -153,6 +153,8 @@ int gv_graph_init(gv_graph** out, uint64_t num_vertices, const uint32_t* d_src,
         v.vt = (VRec*)g->mem_vt;
         v.active = (uint32_t*)g->mem_active;
         v.ctr = (DevCounters*)g->mem_ctr;
+        g->ctx.chain = &v.ctr->chain;
+        g->ctx.chain_err = &v.ctr->err_wait;
         v.vlost = (uint32_t*)g->mem_vlost;
         noalloc_setup();
         bulk_build(g, num_vertices, d_src, d_dst, num_edges, c);

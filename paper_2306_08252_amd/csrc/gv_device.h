@@ -46,6 +46,18 @@ struct alignas(16) VRec {
     uint32_t aux;   // scratch for bulk build and vertex deletion
 };
 
+// State of the one-kernel scans of small inputs on the graph's stream (at
+// most kChainTiles tiles): a ticket per workgroup, each tile's sum with its
+// ready flag, and a count of the workgroups that finished; the last
+// workgroup of a scan returns all of it to zero, so every scan starts from
+// zeros.
+constexpr uint32_t kChainTiles = 64;
+struct ChainState {
+    uint32_t ticket, done;
+    uint32_t ready[kChainTiles];
+    unsigned long long sum[kChainTiles];
+};
+
 struct DevCounters {
     // edge-block pool (free-list stack + bump pointer)
     unsigned long long free_cnt;
@@ -87,6 +99,7 @@ struct DevCounters {
     unsigned long long live_edges;     // edges stored
     unsigned long long checksum, edges, violations;
     uint32_t vmax, vany;
+    ChainState chain;
 };
 
 // A batch sort that failed (a look-back wait ran out, or the sorted keys are

@@ -77,6 +77,10 @@ uint64_t resident_grid(void (*kernel)(KArgs...), uint32_t block) {
 struct Ctx {
     hipStream_t stream = nullptr;
     uint64_t seq = 0;  // operations queued so far (launches, recorded graphs)
+    // device state of the one-kernel small scans (a ChainState) and the word
+    // their bounded waits flag when one runs out; null: two-kernel scans only
+    void* chain = nullptr;
+    uint32_t* chain_err = nullptr;
     bool prof = false;
     std::string only;  // when non-empty, only launches of this name are timed
     struct Rec {

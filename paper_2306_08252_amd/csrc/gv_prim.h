@@ -423,6 +423,111 @@ __global__ __launch_bounds__(kThreads) void k_scan2_apply(In in, Out out, uint64
     }
 }
 
+// One-kernel form for inputs of 2 to kChainTiles tiles: a workgroup takes
+// its tile by ticket (so every tile it waits for belongs to a workgroup that
+// started before it), publishes the tile's sum (released by its flag), adds
+// the sums of the earlier tiles (one lane per tile, bounded waits), and
+// scans its tile as the apply kernel does.  The first tile runs the source's
+// begin() before it publishes, so every sink call comes after it.  The last
+// workgroup to finish returns the state to zero.
+template <typename In, typename Out>
+__global__ __launch_bounds__(kThreads) void k_scan2_chain(In in, Out out, uint64_t n,
+                                                          uint32_t nt, ChainState* st,
+                                                          uint32_t* err,
+                                                          unsigned long long* total) {
+    constexpr int kI = scan2_items<In>::value;
+    __shared__ unsigned long long s_w[kI][kWaves];
+    __shared__ unsigned long long s_p[kWaves];
+    __shared__ uint32_t s_tile;
+    if (threadIdx.x == 0) s_tile = atomicAdd(&st->ticket, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    if constexpr (scan2_has_begin<In>::value) {
+        if (tile == 0) in.begin();
+    }
+    const uint64_t lim = in.limit(n);
+    const uint64_t base = (uint64_t)tile * kThreads * kI + threadIdx.x;
+    typename In::Rec r[kI];
+#pragma unroll
+    for (int j = 0; j < kI; ++j) {
+        const uint64_t i = base + (uint64_t)j * kThreads;
+        r[j] = in.load(i < n ? i : n - 1, i < lim);
+    }
+#pragma unroll
+    for (int j = 0; j < kI; ++j) in.deref(r[j]);
+    unsigned long long x[kI], inc[kI];
+#pragma unroll
+    for (int j = 0; j < kI; ++j) {
+        const uint64_t i = base + (uint64_t)j * kThreads;
+        x[j] = i < lim ? in.value(i, r[j]) : 0ull;
+        inc[j] = wave_incl_scan(x[j]);
+    }
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 63) {
+#pragma unroll
+        for (int j = 0; j < kI; ++j) s_w[j][w] = inc[j];
+    }
+    __syncthreads();  // (also: the first tile's begin() is done)
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+#pragma unroll
+        for (int j = 0; j < kI; ++j)
+#pragma unroll
+            for (int q = 0; q < kWaves; ++q) t += s_w[j][q];
+        st->sum[tile] = t;
+        __hip_atomic_store(&st->ready[tile], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    unsigned long long p = 0;
+    if (threadIdx.x < tile) {
+        uint32_t spins = 0;
+        while (__hip_atomic_load(&st->ready[threadIdx.x], __ATOMIC_ACQUIRE,
+                                 __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+            if (++spins >= kSpinLimit) {
+                atomicOr(err, 1u);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        p = st->sum[threadIdx.x];
+    }
+    unsigned long long run = block_sum(p, s_p);
+#pragma unroll
+    for (int j = 0; j < kI; ++j) {
+        const uint64_t i = base + (uint64_t)j * kThreads;
+        unsigned long long before = 0, tot = 0;
+#pragma unroll
+        for (int q = 0; q < kWaves; ++q) {
+            const unsigned long long v = s_w[j][q];
+            before += q < w ? v : 0ull;
+            tot += v;
+        }
+        if (i < n) out(i, r[j], lim, run + before + inc[j] - x[j]);
+        run += tot;
+    }
+    const bool last = tile == nt - 1;
+    if (total && last && threadIdx.x == kThreads - 1) *total = run;
+    if constexpr (scan2_has_tally<Out>::value) {
+        unsigned long long t = 0;
+#pragma unroll
+        for (int j = 0; j < kI; ++j) {
+            const uint64_t i = base + (uint64_t)j * kThreads;
+            t += i < lim ? out.tally(i, r[j]) : 0ull;
+        }
+        t = block_sum(t, s_p);
+        if (threadIdx.x == 0) out.commit(t);
+    }
+    __syncthreads();
+    if constexpr (scan2_has_finish<Out>::value) {
+        if (last && threadIdx.x < 64) out.finish();
+    }
+    if (threadIdx.x == 0 && atomicAdd(&st->done, 1u) == nt - 1) {
+        // every workgroup has read what it waits for
+        for (uint32_t t = 0; t < nt; ++t) st->ready[t] = 0u;
+        st->ticket = 0u;
+        st->done = 0u;
+    }
+}
+
 // tiles the apply kernel adds up itself; beyond, a middle kernel scans them
 constexpr uint64_t kScan2MaxTiles = 8192;
 // partial words any scan2 over n elements needs
@@ -446,6 +551,11 @@ void scan2(Ctx& c, const char* name, In in, Out out, uint64_t n, unsigned long l
     if (n == 0) return;
     const uint64_t nt = scan2_tiles<In>(n);
     if (nt > 0xffffffffull) fail(GV_EINVAL, "scan too large");
+    if (nt > 1 && nt <= kChainTiles && c.chain) {
+        c.launch(name, k_scan2_chain<In, Out>, nt, kThreads, in, out, n, (uint32_t)nt,
+                 (ChainState*)c.chain, c.chain_err, total);
+        return;
+    }
     // a single tile adds no earlier partials: the apply kernel is the scan
     if (nt > 1) c.launch(name, k_scan2_reduce<In>, nt, kThreads, in, n, part);
     const int scanned = nt > kScan2MaxTiles ? 1 : 0;

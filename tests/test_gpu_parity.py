@@ -491,3 +491,28 @@ def test_heavy_grow_sources_are_grown_once():
         assert st[0] == len(hnew)
         have = np.setdiff1d(have, hnew)
     g.close()
+
+
+@pytest.mark.parametrize("size", [131071, 131072, 131073, 140000])
+def test_one_kernel_scan_boundary(size):
+    """Batches on both sides of the one-kernel scans (at most 64 tiles of 2048
+    elements, tiles taken by ticket) and the two-kernel scans beyond, in the
+    same sequence on one graph: inserts, deletes and queries against the
+    oracle, element by element."""
+    gv = need_gpu()
+    rng = np.random.default_rng(size)
+    n, B = 1 << 14, 8
+    s0 = rng.integers(0, n, 4 * n).astype(np.uint32)
+    d0 = rng.integers(0, n, 4 * n).astype(np.uint32)
+    g = gv.Graph(n, s0, d0, block_slots=B)
+    o = O.OracleGraph(n, s0, d0, block_slots=B)
+    for rep in range(2):
+        s = rng.integers(0, n, size).astype(np.uint32)
+        d = rng.integers(0, n, size).astype(np.uint32)
+        same_answers(g, o, s, d, f"query {size} rep {rep}")
+        assert g.insert_edges(s, d) == o.insert_edges(s, d)[1]
+        assert_same(g, o, f"insert {size} rep {rep}")
+        assert g.delete_edges(d[: size // 2], s[: size // 2]) == \
+            o.delete_edges(d[: size // 2], s[: size // 2])[1]
+        assert_same(g, o, f"delete {size} rep {rep}")
+    g.close()
