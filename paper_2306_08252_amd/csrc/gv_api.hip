@@ -65,7 +65,8 @@ void free_graph(gv_graph* g) {
     for (auto& v : g->vscr) v.release();
     g->cscr.release();
     void* mem[] = {g->mem_pool,   g->mem_free, g->mem_dir,  g->mem_dfree, g->mem_vt,
-                   g->mem_active, g->mem_ctr,  g->mem_bown, g->mem_vlost, g->mem_apool};
+                   g->mem_active, g->mem_ctr,  g->mem_bown, g->mem_vlost, g->mem_apool,
+                   g->mem_chain};
     for (void* p : mem)
         if (p) hipFree(p);
     if (g->hctr) hipHostFree(g->hctr);
@@ -143,6 +144,9 @@ int gv_graph_init(gv_graph** out, uint64_t num_vertices, const uint32_t* d_src,
         hip_check(hipMalloc(&g->mem_vt, cap * sizeof(VRec)), "hipMalloc vertex table");
         hip_check(hipMalloc(&g->mem_active, ((cap + 31) / 32) * 4), "hipMalloc active");
         hip_check(hipMalloc(&g->mem_ctr, sizeof(DevCounters)), "hipMalloc counters");
+        hip_check(hipMalloc(&g->mem_chain, sizeof(ChainState)), "hipMalloc scan state");
+        hip_check(hipMemsetAsync(g->mem_chain, 0, sizeof(ChainState), g->ctx.stream),
+                  "hipMemsetAsync");
         hip_check(hipMalloc(&g->mem_vlost, cap * sizeof(uint32_t)), "hipMalloc vertex scratch");
         hip_check(hipMemsetAsync(g->mem_vlost, 0, cap * sizeof(uint32_t), g->ctx.stream),
                   "hipMemsetAsync");
@@ -153,7 +157,7 @@ int gv_graph_init(gv_graph** out, uint64_t num_vertices, const uint32_t* d_src,
         v.vt = (VRec*)g->mem_vt;
         v.active = (uint32_t*)g->mem_active;
         v.ctr = (DevCounters*)g->mem_ctr;
-        g->ctx.chain = &v.ctr->chain;
+        g->ctx.chain = g->mem_chain;
         g->ctx.chain_err = &v.ctr->err_wait;
         v.vlost = (uint32_t*)g->mem_vlost;
         noalloc_setup();
@@ -344,7 +348,8 @@ int gv_memory_used(gv_graph* g, gv_mem* out) {
         m.reserved_bytes = v.cap_blocks * m.block_bytes + 4ull * v.cap_blocks +
                            8ull * v.cap_blocks + 4ull * v.n_cap +
                            4ull * v.A * v.cap_blocks * v.B + m.directory_bytes +
-                           m.vertex_table_bytes + sizeof(DevCounters) + g->scratch.cap +
+                           m.vertex_table_bytes + sizeof(DevCounters) + sizeof(ChainState) +
+                           g->scratch.cap +
                            g->ov.scr.cap + g->ov.mix[0].cap + g->ov.mix[1].cap;
         *out = m;
     });

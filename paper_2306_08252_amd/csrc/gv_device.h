@@ -46,15 +46,18 @@ struct alignas(16) VRec {
     uint32_t aux;   // scratch for bulk build and vertex deletion
 };
 
-// State of the one-kernel scans of small inputs on the graph's stream (at
-// most kChainTiles tiles): a ticket per workgroup, each tile's sum with its
-// ready flag, and a count of the workgroups that finished; the last
-// workgroup of a scan returns all of it to zero, so every scan starts from
-// zeros.
-constexpr uint32_t kChainTiles = 64;
+// State of the one-kernel scans on the graph's stream (at most kChainTiles
+// tiles): a ticket per workgroup, each tile's sum plus one (0: not yet
+// published; the word carries its own value, so relaxed loads suffice), and
+// a count of the workgroups that finished; the last workgroup of a scan
+// returns all of it to zero, so every scan starts from zeros.  (A buffer of
+// its own: the batch counters are copied to the host whole.)
+#ifndef GV_CHAIN_TILES
+#define GV_CHAIN_TILES 256
+#endif
+constexpr uint32_t kChainTiles = GV_CHAIN_TILES;
 struct ChainState {
     uint32_t ticket, done;
-    uint32_t ready[kChainTiles];
     unsigned long long sum[kChainTiles];
 };
 
@@ -99,7 +102,6 @@ struct DevCounters {
     unsigned long long live_edges;     // edges stored
     unsigned long long checksum, edges, violations;
     uint32_t vmax, vany;
-    ChainState chain;
 };
 
 // A batch sort that failed (a look-back wait ran out, or the sorted keys are

@@ -60,6 +60,7 @@ struct gv_graph {
     void* mem_vt = nullptr;
     void* mem_active = nullptr;
     void* mem_ctr = nullptr;
+    void* mem_chain = nullptr;  // ChainState of the graph's stream
     void* mem_bown = nullptr;
     void* mem_vlost = nullptr;
     void* mem_apool = nullptr;

@@ -425,11 +425,14 @@ __global__ __launch_bounds__(kThreads) void k_scan2_apply(In in, Out out, uint64
 
 // One-kernel form for inputs of 2 to kChainTiles tiles: a workgroup takes
 // its tile by ticket (so every tile it waits for belongs to a workgroup that
-// started before it), publishes the tile's sum (released by its flag), adds
-// the sums of the earlier tiles (one lane per tile, bounded waits), and
-// scans its tile as the apply kernel does.  The first tile runs the source's
-// begin() before it publishes, so every sink call comes after it.  The last
-// workgroup to finish returns the state to zero.
+// started before it), publishes the tile's sum (plus one: zero is unset), adds
+// the sums of all earlier tiles (each thread a strided share of them,
+// bounded waits on relaxed loads of words that carry their own value), and
+// scans its tile as the apply kernel does.  A tile waits
+// for the earlier tiles' own sums, not their prefixes, so the waits do not
+// chain.  The first tile runs the source's begin() before it publishes, so
+// every sink call comes after it.  The last workgroup to finish returns the
+// state to zero.
 template <typename In, typename Out>
 __global__ __launch_bounds__(kThreads) void k_scan2_chain(In in, Out out, uint64_t n,
                                                           uint32_t nt, ChainState* st,
@@ -438,12 +441,15 @@ __global__ __launch_bounds__(kThreads) void k_scan2_chain(In in, Out out, uint64
     constexpr int kI = scan2_items<In>::value;
     __shared__ unsigned long long s_w[kI][kWaves];
     __shared__ unsigned long long s_p[kWaves];
-    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_tile, s_last;
     if (threadIdx.x == 0) s_tile = atomicAdd(&st->ticket, 1u);
     __syncthreads();
     const uint32_t tile = s_tile;
     if constexpr (scan2_has_begin<In>::value) {
-        if (tile == 0) in.begin();
+        if (tile == 0) {
+            in.begin();
+            __threadfence();  // its writes, before the tile's sum is published
+        }
     }
     const uint64_t lim = in.limit(n);
     const uint64_t base = (uint64_t)tile * kThreads * kI + threadIdx.x;
@@ -474,23 +480,30 @@ __global__ __launch_bounds__(kThreads) void k_scan2_chain(In in, Out out, uint64
         for (int j = 0; j < kI; ++j)
 #pragma unroll
             for (int q = 0; q < kWaves; ++q) t += s_w[j][q];
-        st->sum[tile] = t;
-        __hip_atomic_store(&st->ready[tile], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&st->sum[tile], t + 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     unsigned long long p = 0;
-    if (threadIdx.x < tile) {
+    for (uint32_t k = threadIdx.x; k < tile; k += kThreads) {
         uint32_t spins = 0;
-        while (__hip_atomic_load(&st->ready[threadIdx.x], __ATOMIC_ACQUIRE,
-                                 __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+        unsigned long long x;
+        while ((x = __hip_atomic_load(&st->sum[k], __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT)) == 0ull) {
             if (++spins >= kSpinLimit) {
                 atomicOr(err, 1u);
+                x = 1ull;
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
         }
-        p = st->sum[threadIdx.x];
+        p += x - 1ull;
+    }
+    if constexpr (scan2_has_begin<In>::value) {
+        // begin()'s writes, before this tile's sink calls (thread 0 read the
+        // first tile's sum; the barrier in block_sum orders the others)
+        if (threadIdx.x == 0) __threadfence();
     }
     unsigned long long run = block_sum(p, s_p);
+    if constexpr (scan2_has_begin<In>::value) __threadfence();
 #pragma unroll
     for (int j = 0; j < kI; ++j) {
         const uint64_t i = base + (uint64_t)j * kThreads;
@@ -520,11 +533,15 @@ __global__ __launch_bounds__(kThreads) void k_scan2_chain(In in, Out out, uint64
     if constexpr (scan2_has_finish<Out>::value) {
         if (last && threadIdx.x < 64) out.finish();
     }
-    if (threadIdx.x == 0 && atomicAdd(&st->done, 1u) == nt - 1) {
+    if (threadIdx.x == 0) s_last = atomicAdd(&st->done, 1u) == nt - 1 ? 1u : 0u;
+    __syncthreads();
+    if (s_last) {
         // every workgroup has read what it waits for
-        for (uint32_t t = 0; t < nt; ++t) st->ready[t] = 0u;
-        st->ticket = 0u;
-        st->done = 0u;
+        for (uint32_t t = threadIdx.x; t < nt; t += kThreads) st->sum[t] = 0ull;
+        if (threadIdx.x == 0) {
+            st->ticket = 0u;
+            st->done = 0u;
+        }
     }
 }
 
@@ -551,7 +568,11 @@ void scan2(Ctx& c, const char* name, In in, Out out, uint64_t n, unsigned long l
     if (n == 0) return;
     const uint64_t nt = scan2_tiles<In>(n);
     if (nt > 0xffffffffull) fail(GV_EINVAL, "scan too large");
-    if (nt > 1 && nt <= kChainTiles && c.chain) {
+    // (a source with begin() costs a device-scope fence per workgroup: up to
+    // 64 tiles)
+    const uint64_t cmax = scan2_has_begin<In>::value ? std::min<uint64_t>(kChainTiles, 64)
+                                                      : kChainTiles;
+    if (nt > 1 && nt <= cmax && c.chain) {
         c.launch(name, k_scan2_chain<In, Out>, nt, kThreads, in, out, n, (uint32_t)nt,
                  (ChainState*)c.chain, c.chain_err, total);
         return;

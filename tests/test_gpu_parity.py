@@ -493,12 +493,13 @@ def test_heavy_grow_sources_are_grown_once():
     g.close()
 
 
-@pytest.mark.parametrize("size", [131071, 131072, 131073, 140000])
+@pytest.mark.parametrize("size", [131073, 262143, 262145, 524288, 524289])
 def test_one_kernel_scan_boundary(size):
-    """Batches on both sides of the one-kernel scans (at most 64 tiles of 2048
-    elements, tiles taken by ticket) and the two-kernel scans beyond, in the
-    same sequence on one graph: inserts, deletes and queries against the
-    oracle, element by element."""
+    """Batches on both sides of the one-kernel scans (at most 256 tiles, of
+    2048 elements for most scans and 1024 for the work-item scan; 64 for the
+    segment scan when it clears the batch counters) and the two-kernel
+    scans beyond: inserts, deletes and queries against the oracle, element
+    by element."""
     gv = need_gpu()
     rng = np.random.default_rng(size)
     n, B = 1 << 14, 8
