@@ -355,7 +355,11 @@ typedef struct {
  *                  stream of the library's own, while the graph's stream
  *                  still runs the batches queued before it; the rest of the
  *                  batch waits for that sort on the graph's stream (a plan
- *                  records the two streams as parallel branches).
+ *                  records the two streams as parallel branches).  With
+ *                  coalesce on, a run of more than 4096 pairs has its
+ *                  gather, pack and sort on that stream too (two buffers of
+ *                  the library's own, alternating), while the graph's
+ *                  stream applies the run before it.
  *                  Results are those of overlap 0.  Contract: the batch's
  *                  d_src / d_dst must hold their pairs when the call is made
  *                  (written by a synchronous copy, or by work the caller has
