@@ -533,6 +533,7 @@ def batched_form(gv, I, T, dev, scale=22, edges=1 << 26, nbatch=256, seed_name="
             "plan_edges_per_s": round(pairs / el_plan, 1),
             "plan_form": "the sequence recorded as one HIP graph, tuned setting",
             "plan_gain_vs_baseline": round(el_base / el_plan - 1.0, 4),
+            "plan_gain_vs_tuned_eager": round(el_eager / el_plan - 1.0, 4),
             "results_match": True, "checksum": want[0], "edges_after": want[1]}
 
 
