@@ -250,7 +250,9 @@ __device__ __forceinline__ void st_status32(uint32_t* p, uint32_t v) {
 // reduces each tile, the second recomputes its tile prefix by reducing the
 // partials of all earlier tiles (up to kScan2MaxTiles, read from L2; with
 // more tiles a one-workgroup kernel between the two scans the partials) and
-// scans its tile.  Inputs are evaluated twice, outputs written once.
+// scans its tile.  Inputs are evaluated twice, outputs written once.  On a
+// context with a scan state (the graph's stream), inputs of 2 to
+// kChainTiles tiles take a one-kernel form instead (k_scan2_chain below).
 //
 // The source is a gather: it splits each element into its memory reads and
 // the arithmetic on them, so that a thread issues the reads of all of its
