@@ -54,11 +54,20 @@ constexpr uint8_t kHead = 1, kUniq = 2;
 constexpr int kStageLog = 7;                   // log2(kStage)
 constexpr int kStage = 1 << kStageLog;         // segment entries staged in LDS
 constexpr int kWinLog = 12;                    // unrolled global search steps
-constexpr uint32_t kBigR = 256;                // deletes per source handled by a workgroup
+#ifndef GV_BIG_R
+#define GV_BIG_R 256
+#endif
+#ifndef GV_LANE_SEG
+#define GV_LANE_SEG 16
+#endif
+#ifndef GV_LANE_R
+#define GV_LANE_R 8
+#endif
+constexpr uint32_t kBigR = GV_BIG_R;           // deletes per source handled by a workgroup
 constexpr uint32_t kBigGroups = 256;           // workgroups for those sources
 constexpr uint32_t kLaneCopy = 8;              // directory entries a lane copies or adds
-constexpr uint32_t kLaneSeg = 16;              // segment entries a lane compacts
-constexpr uint32_t kLaneR = 8;                 // hits a lane compacts
+constexpr uint32_t kLaneSeg = GV_LANE_SEG;     // segment entries a lane compacts
+constexpr uint32_t kLaneR = GV_LANE_R;         // hits a lane compacts
 constexpr uint32_t kRelease = 0x80000000u;     // flag bit in the per-source demand
 constexpr uint32_t kHeavy = 0x100u;            // flag bit in t_dreq: whole waves grow this source
 constexpr uint32_t kClassMask = 0xFFu;         // t_dreq & kClassMask: requested class or kNoDir
