@@ -519,7 +519,10 @@ __device__ __forceinline__ TouchRec load_touched(const uint32_t* t_vtx, const ui
 // empty entry (s1 = 0).
 constexpr uint32_t kSmallDeg = 16;    // slots per lane (whole 16-byte groups of a block)
 constexpr uint32_t kSmallLanes = 4;   // lanes per small item
-constexpr uint32_t kSmallSeg = 8;
+#ifndef GV_SMALL_SEG
+#define GV_SMALL_SEG 8
+#endif
+constexpr uint32_t kSmallSeg = GV_SMALL_SEG;
 __device__ __forceinline__ bool small_item(uint32_t B, uint32_t deg, uint32_t len) {
     return B >= 4 && deg > 0 && deg <= kSmallLanes * kSmallDeg && len <= kSmallSeg;
 }
