@@ -679,29 +679,24 @@ struct TileSortLds {
 };
 
 // Tiles of at most kTileBitonicMax keys are sorted by a bitonic network in
-// LDS over (key, input position) pairs: the positions make the pairs
-// distinct and order equal keys as they came, so the result is the stable
-// order the radix passes give (for keys below 2^(8 * passes)), in
-// log2(m) (log2(m) + 1) / 2 barrier steps for m keys padded to a power of
-// two, instead of five barriers per radix pass.
+// LDS, in log2(m) (log2(m) + 1) / 2 compare-exchange steps for m keys padded
+// to a power of two with all-ones keys, instead of five barriers per radix
+// pass.  The network is not stable, but every caller's keys are whole
+// records (an edge key, a destination, or a key with its input position in
+// the low bits), so keys that compare equal are identical and the result is
+// the array a stable sort gives.
 constexpr uint64_t kTileBitonicMax = 2048;
 
 __device__ __forceinline__ void tile_bitonic(uint64_t (&key)[kOsRounds], uint32_t n,
                                              uint64_t sentinel, TileSortLds& L) {
     static_assert(kTileBitonicMax <= kOsTile, "the network works in the tile's LDS");
-    static_assert(sizeof(L.cnt) >= kTileBitonicMax * sizeof(uint16_t), "room for positions");
     const uint32_t t = threadIdx.x;
-    uint16_t* pos = &L.cnt[0][0];
     uint32_t m = 2;
     while (m < n) m <<= 1;
-    // pads sort after every key: the largest key and positions past n
 #pragma unroll
     for (int j = 0; j < kOsRounds; ++j) {
         const uint32_t i = (uint32_t)j * kOsThreads + t;
-        if (i < m) {
-            L.skey[i] = i < n ? key[j] : ~0ull;
-            pos[i] = (uint16_t)i;
-        }
+        if (i < m) L.skey[i] = i < n ? key[j] : ~0ull;
     }
     // Thread c compares the pair (i, i + h), i being c with a zero bit
     // inserted at h.  While h <= 64 the pairs of a wave lie in its own 128
@@ -723,13 +718,9 @@ __device__ __forceinline__ void tile_bitonic(uint64_t (&key)[kOsRounds], uint32_
                 const uint32_t i = ((t & ~(h - 1)) << 1) | (t & (h - 1));
                 const uint32_t p = i + h;
                 const uint64_t a = L.skey[i], b = L.skey[p];
-                const uint16_t ia = pos[i], ib = pos[p];
-                const bool after = a > b || (a == b && ia > ib);
-                if (after == ((i & k) == 0)) {
+                if ((a > b) == ((i & k) == 0)) {
                     L.skey[i] = b;
                     L.skey[p] = a;
-                    pos[i] = ib;
-                    pos[p] = ia;
                 }
             }
         }
