@@ -835,7 +835,8 @@ def main():
                 "bytes_model": ("M1 share: 16 B per pair per batch, over %d radix passes" % per["passes"]
                                 if dominant == "sort_pass" else
                                 "M1 share: touched adjacency, 4 B per block-granular slot"
-                                if dominant.startswith("probe") else "see DESIGN"),
+                                if dominant.startswith("probe") else
+                                "the kernel's own algorithmic bytes (bytes_model in bench.py)"),
                 "implementation_bytes_per_launch": None if ibpl is None else int(ibpl),
                 "implementation_frac": None if ibpl is None else
                 round(ibpl / avg_s / 1e9 / HBM_PEAK_GBS, 5),
